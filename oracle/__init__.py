@@ -1,0 +1,213 @@
+"""CPU oracle of the IMEX-DS hot path (ctypes binding of imexds_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: tests/, the package smoke check and the bench's
+cpu_baseline leg may import this package; the product path never does.  The
+C source is compiled here with gcc (-O2 -ffp-contract=off, OpenMP over
+independent problems) and shares no code with the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(_HERE, "imexds_oracle.c")
+LIB = os.path.join(_HERE, "liboracle_imexds.so")
+
+ST_NEWTON, ST_NONPHYS, ST_MESH, ST_OVERLAP = 1, 2, 4, 8
+FL_TINY_RIGHT, FL_MERGED, FL_REDO, FL_LMAX = 1, 2, 4, 8
+FL_CROSS_L, FL_CROSS_R, FL_FAIL, FL_INACTIVE = 16, 32, 64, 128
+
+
+def build():
+    """Compiles the oracle shared library (always recompiles)."""
+    tmp = LIB + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+                           "-shared", "-fPIC", "-o", tmp, SRC, "-lm"])
+    os.replace(tmp, LIB)
+
+
+class _Mat(ctypes.Structure):
+    _fields_ = [("a2v", ctypes.c_double), ("a2l", ctypes.c_double), ("p0", ctypes.c_double),
+                ("rhol0", ctypes.c_double), ("tau", ctypes.c_double)]
+
+
+class _Par(ctypes.Structure):
+    _fields_ = [("cfl", ctypes.c_double), ("zone_half", ctypes.c_int),
+                ("theta_nb", ctypes.c_double), ("tol_mode", ctypes.c_int),
+                ("tol_nb", ctypes.c_double), ("tol_tiny", ctypes.c_double),
+                ("tol_rel", ctypes.c_double), ("lmax", ctypes.c_int),
+                ("alpha_floor", ctypes.c_double), ("merge_safety", ctypes.c_double),
+                ("bc_left", ctypes.c_int), ("bc_right", ctypes.c_int),
+                ("newton_maxit", ctypes.c_int), ("newton_rtol", ctypes.c_double),
+                ("t_end", ctypes.c_double)]
+
+
+class _Iface(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("pl", "pr", "rl", "rr", "ul", "ur", "z", "w",
+                                               "F0", "F1")] + [("iters", ctypes.c_int),
+                                                               ("ok", ctypes.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+        L = ctypes.CDLL(LIB)
+        dp, ip, lp = (ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
+                      ctypes.POINTER(ctypes.c_longlong))
+        L.oracle_run.restype = ctypes.c_int
+        L.oracle_run.argtypes = [ctypes.POINTER(_Mat), ctypes.POINTER(_Par), ctypes.c_int, ip, dp,
+                                 ip, ip, lp, ip, dp, dp, ip, dp, dp, dp, ip, lp, ctypes.c_int, ip,
+                                 ip, ip, ctypes.c_int]
+        L.oracle_iface_solve.restype = ctypes.c_int
+        L.oracle_iface_solve.argtypes = [ctypes.POINTER(_Mat), ctypes.c_int, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                         ctypes.POINTER(_Iface)]
+        L.oracle_iface_G.restype = ctypes.c_int
+        L.oracle_iface_G.argtypes = [ctypes.POINTER(_Mat), ctypes.c_int, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
+        L.oracle_hll.restype = None
+        L.oracle_hll.argtypes = [ctypes.POINTER(_Mat), ctypes.c_int, ctypes.c_double,
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
+        L.oracle_zone_fixed_point.restype = ctypes.c_int
+        L.oracle_zone_fixed_point.argtypes = [ctypes.POINTER(_Mat), ctypes.POINTER(_Par),
+                                              ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                              ctypes.c_int, dp, dp, ip, dp, dp, ip, ctypes.c_int,
+                                              dp, dp, ip, dp]
+        _lib = L
+    return _lib
+
+
+def _mat(m):
+    return _Mat(m.a2v, m.a2l, m.p0, m.rhol0, m.tau)
+
+
+def _par(p):
+    return _Par(p.cfl, p.zone_half, p.theta_nb, p.tol_mode, p.tol_nb, p.tol_tiny, p.tol_rel,
+                p.lmax, p.alpha_floor, p.merge_safety, p.bc_left, p.bc_right, p.newton_maxit,
+                p.newton_rtol, p.t_end)
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(ctypes.POINTER(t))
+
+
+class State:
+    """Evolving state of a batch in the oracle (all host numpy arrays)."""
+
+    def __init__(self, batch):
+        self.batch = batch
+        P, nif = batch.n_problems, batch.n_iface
+        self.rho = np.ascontiguousarray(batch.rho, dtype=np.float64).copy()
+        self.mom = np.ascontiguousarray(batch.mom, dtype=np.float64).copy()
+        self.home = np.ascontiguousarray(batch.home, dtype=np.int32).copy()
+        self.hl = np.ascontiguousarray(batch.hl, dtype=np.float64).copy()
+        self.pw = np.zeros(2 * max(nif, 1), dtype=np.float64)
+        self.warm = np.zeros(max(nif, 1), dtype=np.int32)
+        self.t = np.zeros(P, dtype=np.float64)
+        self.status = np.zeros(P, dtype=np.int32)
+        self.steps = np.zeros(P, dtype=np.int64)
+
+    def x_iface(self):
+        b = self.batch
+        out = np.empty(b.n_iface)
+        for p in range(b.n_problems):
+            for k in range(int(b.iface_off[p]), int(b.iface_off[p + 1])):
+                out[k] = b.x_left[p] + self.home[k] * b.h[p] + self.hl[k]
+        return out
+
+
+def run(state, material, params, n_steps, log=False, threads=1):
+    """Advances every problem of ``state`` by ``n_steps`` steps (or until
+    t_end / failure).  Returns per-step logs (count, flags, zlo) of shape
+    [n_steps, n_iface] if ``log``."""
+    b = state.batch
+    L = lib()
+    m, p = _mat(material), _par(params)
+    n_cells = np.ascontiguousarray(b.n_cells, dtype=np.int32)
+    h = np.ascontiguousarray(b.h, dtype=np.float64)
+    pf = np.ascontiguousarray(b.phase_first, dtype=np.int32)
+    ioff = np.ascontiguousarray(b.iface_off, dtype=np.int32)
+    soff = np.ascontiguousarray(b.slot_off, dtype=np.int64)
+    nif = b.n_iface
+    if log:
+        lc = np.zeros((n_steps, max(nif, 1)), dtype=np.int32)
+        lf = np.zeros_like(lc)
+        lz = np.zeros_like(lc)
+        lcp, lfp, lzp = (_ptr(lc, ctypes.c_int), _ptr(lf, ctypes.c_int), _ptr(lz, ctypes.c_int))
+    else:
+        lcp = lfp = lzp = None
+    rc = L.oracle_run(ctypes.byref(m), ctypes.byref(p), b.n_problems, _ptr(n_cells, ctypes.c_int),
+                      _ptr(h, ctypes.c_double), _ptr(pf, ctypes.c_int), _ptr(ioff, ctypes.c_int),
+                      _ptr(soff, ctypes.c_longlong), _ptr(state.home, ctypes.c_int),
+                      _ptr(state.hl, ctypes.c_double), _ptr(state.pw, ctypes.c_double),
+                      _ptr(state.warm, ctypes.c_int), _ptr(state.rho, ctypes.c_double),
+                      _ptr(state.mom, ctypes.c_double), _ptr(state.t, ctypes.c_double),
+                      _ptr(state.status, ctypes.c_int), _ptr(state.steps, ctypes.c_longlong),
+                      int(n_steps), lcp, lfp, lzp, int(threads))
+    if rc != 0:
+        raise ValueError(f"oracle_run rejected the parameters (rc={rc})")
+    if log:
+        return lc[:, :nif], lf[:, :nif], lz[:, :nif]
+    return None
+
+
+def iface_solve(material, phl, rl, ul, phr, rr, ur, guess=None, maxit=50, rtol=1e-14):
+    """Two-phase interface Riemann problem from primitive (rho, u) states."""
+    out = _Iface()
+    g = guess if guess is not None else (0.0, 0.0)
+    ok = lib().oracle_iface_solve(ctypes.byref(_mat(material)), int(phl), float(rl),
+                                  float(rl * ul), int(phr), float(rr), float(rr * ur),
+                                  int(guess is not None), float(g[0]), float(g[1]), int(maxit),
+                                  float(rtol), ctypes.byref(out))
+    d = {n: getattr(out, n) for n, _ in _Iface._fields_}
+    d["ok"] = bool(ok)
+    return d
+
+
+def iface_G(material, phl, rl, ul, phr, rr, ur, psl, psr):
+    o = np.zeros(6)
+    ok = lib().oracle_iface_G(ctypes.byref(_mat(material)), int(phl), float(rl), float(rl * ul),
+                              int(phr), float(rr), float(rr * ur), float(psl), float(psr),
+                              _ptr(o, ctypes.c_double))
+    if not ok:
+        return None
+    return o[:2].copy(), o[2:].reshape(2, 2).copy()
+
+
+def hll(material, phase, rl, ml, rr, mr):
+    F = np.zeros(2)
+    lib().oracle_hll(ctypes.byref(_mat(material)), int(phase), float(rl), float(ml), float(rr),
+                     float(mr), _ptr(F, ctypes.c_double))
+    return F
+
+
+def zone_fixed_point(state, material, params, k=0):
+    """For a single-problem state: Algorithm 2 Part 1 iterate vs a direct
+    Newton solve of the zone's implicit system (see the C source)."""
+    b = state.batch
+    assert b.n_problems == 1
+    Wd = np.zeros(64)
+    Wn = np.zeros(64)
+    m = np.zeros(1, dtype=np.int32)
+    dt = np.zeros(1)
+    rc = lib().oracle_zone_fixed_point(
+        ctypes.byref(_mat(material)), ctypes.byref(_par(params)), int(b.n_cells[0]),
+        float(b.h[0]), int(b.phase_first[0]), int(b.n_iface), _ptr(state.rho, ctypes.c_double),
+        _ptr(state.mom, ctypes.c_double), _ptr(state.home, ctypes.c_int),
+        _ptr(state.hl, ctypes.c_double), _ptr(state.pw, ctypes.c_double),
+        _ptr(state.warm, ctypes.c_int), int(k), _ptr(Wd, ctypes.c_double),
+        _ptr(Wn, ctypes.c_double), _ptr(m, ctypes.c_int), _ptr(dt, ctypes.c_double))
+    n = 2 * int(m[0])
+    return rc, Wd[:n].reshape(-1, 2), Wn[:n].reshape(-1, 2), float(dt[0])

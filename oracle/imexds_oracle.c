@@ -1,0 +1,1098 @@
+/*
+ * imexds_oracle.c -- plain, slow, FP64 CPU oracle of the explicit-implicit
+ * domain-splitting (IMEX-DS) scheme of May & Thein (arXiv 2211.00705) for the
+ * 1D isothermal Euler equations with sharp liquid-vapour interfaces and a
+ * kinetic mass-transfer relation.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the independent CPU reference that
+ * the GPU path is checked against.  Only tests/, the package smoke check and
+ * the bench's cpu_baseline leg may load it.  It shares no code, header or
+ * constant with the HIP library; it is built on its own with
+ *   gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC
+ * so that no multiply-add is ever fused.
+ *
+ * What it computes, in the paper's order (section / equation names refer to
+ * the paper):
+ *   - phase pressure laws: ideal gas vapour (eq. eos:isoT_idgas) and linear
+ *     Tait liquid (eq. eos:isoT_lintait, read as p0 + K0 (rho/rho0 - 1),
+ *     written here as p0 + aL^2 (rho - rho0));
+ *   - Gibbs energies g_K = a_K^2 ln(rho/rho_K0), equal at saturation by the
+ *     Maxwell construction (Sec. 2.1);
+ *   - the HLL flux for same-phase faces (Sec. 5, "HLL solver as in Toro"),
+ *     Davis wave speeds;
+ *   - the two-phase interface Riemann solve: Newton-Armijo on
+ *     G(p_l*, p_r*) = 0 (Appendix A, eqs. 2p_RP:ex_sys and jacobian:ex_sys),
+ *     kinetic relation z = tau p_V [[g + e_kin]] (eq. isoT:kin_rel1) with
+ *     e_kin = z^2 v^2 / 2 relative to the interface, HLLC-type initial guess
+ *     (eq. HLLC:2p_nopt) and phase-boundary flux F_PB (eq. pb_flux:pt);
+ *   - Algorithm 1 (explicit bulk update, saved bounding fluxes) and
+ *     Algorithm 2 (dual time stepping, Part 1 and Part 2) on a zone of
+ *     2Z+1 cells around each tiny cut cell, with local pseudo steps
+ *     (eq. dual time tau diff), the residual and stopping rule of Sec. 5 and
+ *     moving cell lengths (Sec. 4.4, eq. godunov_meth:nonunif);
+ *   - CFL time step (eq. cfl_cond:unif);
+ *   - grid alignment with merging of vanishing cut pieces and re-splitting
+ *     (Sec. 2.3), by the deterministic rule stated in the design notes.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_LIQ 0
+#define OR_VAP 1
+
+#define OR_ST_NEWTON 1
+#define OR_ST_NONPHYS 2
+#define OR_ST_MESH 4
+#define OR_ST_OVERLAP 8
+
+#define OR_FL_TINY_RIGHT 1
+#define OR_FL_MERGED 2
+#define OR_FL_REDO 4
+#define OR_FL_LMAX 8
+#define OR_FL_CROSS_L 16
+#define OR_FL_CROSS_R 32
+#define OR_FL_FAIL 64
+#define OR_FL_INACTIVE 128
+
+#define OR_MAXC 32
+
+typedef struct {
+  double a2v;   /* vapour: p = a2v rho,  a2v = k T0 / m  */
+  double a2l;   /* liquid: p = p0 + a2l (rho - rhol0), a2l = K0 / rho0 */
+  double p0;    /* saturation pressure */
+  double rhol0; /* liquid saturation density */
+  double tau;   /* kinetic coefficient */
+} or_material;
+
+typedef struct {
+  double cfl;
+  int zone_half;
+  double theta_nb;
+  int tol_mode; /* 0: paper residual (tol_nb, tol_tiny); 1: relative update (tol_rel) */
+  double tol_nb, tol_tiny, tol_rel;
+  int lmax;
+  double alpha_floor;
+  double merge_safety;
+  int bc_left, bc_right; /* 0 wall, 1 transmissive */
+  int newton_maxit;
+  double newton_rtol;
+  double t_end;
+} or_params;
+
+/* ------------------------------------------------------------------ */
+/* phase laws                                                          */
+/* ------------------------------------------------------------------ */
+static double or_a2(const or_material *M, int ph) { return ph == OR_VAP ? M->a2v : M->a2l; }
+
+static double or_pres(const or_material *M, int ph, double rho) {
+  return ph == OR_VAP ? M->a2v * rho : M->p0 + M->a2l * (rho - M->rhol0);
+}
+
+static double or_rho_of_p(const or_material *M, int ph, double p) {
+  return ph == OR_VAP ? p / M->a2v : M->rhol0 + (p - M->p0) / M->a2l;
+}
+
+/* Gibbs energy up to the common constant fixed by g_L(p0) = g_V(p0). */
+static double or_gibbs(const or_material *M, int ph, double rho) {
+  if (ph == OR_VAP) return M->a2v * log(rho / (M->p0 / M->a2v));
+  return M->a2l * log(rho / M->rhol0);
+}
+
+/* ------------------------------------------------------------------ */
+/* HLL flux of the isothermal Euler system, same phase both sides      */
+/* ------------------------------------------------------------------ */
+void oracle_hll(const or_material *M, int ph, double rl, double ml, double rr, double mr,
+                double *F) {
+  double a = sqrt(or_a2(M, ph));
+  double ul = ml / rl, ur = mr / rr;
+  double pl = or_pres(M, ph, rl), pr = or_pres(M, ph, rr);
+  double sl = (ul < ur ? ul : ur) - a;
+  double sr = (ul > ur ? ul : ur) + a;
+  double fl0 = ml, fl1 = ml * ul + pl;
+  double fr0 = mr, fr1 = mr * ur + pr;
+  if (sl >= 0.0) {
+    F[0] = fl0;
+    F[1] = fl1;
+    return;
+  }
+  if (sr <= 0.0) {
+    F[0] = fr0;
+    F[1] = fr1;
+    return;
+  }
+  double d = sr - sl, ss = sl * sr;
+  F[0] = ((sr * fl0 - sl * fr0) + ss * (rr - rl)) / d;
+  F[1] = ((sr * fl1 - sl * fr1) + ss * (mr - ml)) / d;
+}
+
+/* boundary flux: ghost state (rho, -m) for a wall, (rho, m) transmissive */
+static void or_bflux(const or_material *M, int ph, int side_right, int bc, double r, double m,
+                     double *F) {
+  double mg = (bc == 0) ? -m : m;
+  if (side_right)
+    oracle_hll(M, ph, r, m, r, mg, F);
+  else
+    oracle_hll(M, ph, r, mg, r, m, F);
+}
+
+/* ------------------------------------------------------------------ */
+/* interface Riemann problem with phase transition (Appendix A)        */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  double pl, pr; /* star pressures left / right of the phase boundary */
+  double rl, rr; /* star densities */
+  double ul, ur; /* star velocities */
+  double z, w;   /* mass flux, phase-boundary speed */
+  double F0, F1; /* flux across the moving phase boundary */
+  int iters;
+  int ok;
+} or_iface;
+
+/* classical wave function f_K(p*; W_K) and df/dp*; also rho_K(p*).
+ * Both pressure laws are affine in density (p - p_K = a^2 (rho - rho_K)), so
+ * the shock branch sqrt(-[[p]][[v]]) equals a (rho* - rho_K)/sqrt(rho_K rho*),
+ * which stays accurate when the wave is vanishingly weak. */
+static int or_wave(const or_material *M, int ph, double rhoK, double pK, double ps, double *f,
+                   double *df, double *rs) {
+  double r = or_rho_of_p(M, ph, ps);
+  if (!(r > 0.0) || !isfinite(r)) return 0;
+  double a = sqrt(or_a2(M, ph));
+  *rs = r;
+  if (ps > pK) { /* shock */
+    double g = sqrt(rhoK * r);
+    *f = a * (r - rhoK) / g;
+    *df = (r + rhoK) / ((2.0 * a * r) * g);
+  } else { /* rarefaction: integral of v/a dp = a ln(rho_star / rho_K) */
+    *f = a * log(r / rhoK);
+    *df = 1.0 / (r * a);
+  }
+  return 1;
+}
+
+/* z from the kinetic relation z = tau p_V ([[g]] + z^2 [[v^2]]/2), the root
+ * continuous at [[v^2]] -> 0, and dz/dp_l*, dz/dp_r* by implicit
+ * differentiation of  A z^2 - z + C = 0. */
+static int or_kinetic(const or_material *M, int phl, int phr, double rsl, double rsr, double psl,
+                      double psr, double *z, double *dzl, double *dzr) {
+  double pV = (phl == OR_VAP) ? psl : psr;
+  double q = M->tau * pV;
+  double vl = 1.0 / rsl, vr = 1.0 / rsr;
+  double jg = or_gibbs(M, phr, rsr) - or_gibbs(M, phl, rsl);
+  double jv2 = vr * vr - vl * vl;
+  double A = 0.5 * q * jv2;
+  double C = q * jg;
+  double D = 1.0 - 4.0 * A * C;
+  if (!(D >= 0.0) || !isfinite(D)) return 0;
+  double sD = sqrt(D);
+  double zz = 2.0 * C / (1.0 + sD);
+  double a2l = or_a2(M, phl), a2r = or_a2(M, phr);
+  /* dv/dp = -v^2/a^2,  d(v^2)/dp = -2 v^3/a^2,  dg/dp = v */
+  double dAl = 0.5 * q * (2.0 * vl * vl * vl / a2l);
+  double dAr = 0.5 * q * (-2.0 * vr * vr * vr / a2r);
+  double dCl = q * (-vl);
+  double dCr = q * vr;
+  if (phl == OR_VAP) {
+    dAl += 0.5 * M->tau * jv2;
+    dCl += M->tau * jg;
+  } else {
+    dAr += 0.5 * M->tau * jv2;
+    dCr += M->tau * jg;
+  }
+  /* d/dz (A z^2 - z + C) = 2 A z - 1 = -sqrt(D) at this root */
+  *dzl = (dAl * zz * zz + dCl) / sD;
+  *dzr = (dAr * zz * zz + dCr) / sD;
+  *z = zz;
+  return 1;
+}
+
+typedef struct {
+  int phl, phr;
+  double rl, ul, pl, rr, ur, pr;
+} or_rp;
+
+typedef struct {
+  double G1, G2, J11, J12, J21, J22;
+  double rsl, rsr, fl, fr, z;
+} or_geval;
+
+static int or_eval_G(const or_material *M, const or_rp *R, double psl, double psr, or_geval *E) {
+  double dfl, dfr, dzl, dzr;
+  if (!or_wave(M, R->phl, R->rl, R->pl, psl, &E->fl, &dfl, &E->rsl)) return 0;
+  if (!or_wave(M, R->phr, R->rr, R->pr, psr, &E->fr, &dfr, &E->rsr)) return 0;
+  if (!or_kinetic(M, R->phl, R->phr, E->rsl, E->rsr, psl, psr, &E->z, &dzl, &dzr)) return 0;
+  double z = E->z;
+  double vl = 1.0 / E->rsl, vr = 1.0 / E->rsr;
+  double jv = vr - vl;
+  double el = vl * vl / or_a2(M, R->phl); /* = d[[v]]/dp_l*  */
+  double er = vr * vr / or_a2(M, R->phr); /* = -d[[v]]/dp_r* */
+  E->G1 = (psr - psl) + z * z * jv;
+  E->G2 = (E->fl + E->fr) + z * jv + (R->ur - R->ul);
+  E->J11 = -1.0 + 2.0 * z * dzl * jv + z * z * el;
+  E->J12 = 1.0 + 2.0 * z * dzr * jv - z * z * er;
+  E->J21 = dfl + dzl * jv + z * el;
+  E->J22 = dfr + dzr * jv - z * er;
+  if (!isfinite(E->G1) || !isfinite(E->G2)) return 0;
+  return 1;
+}
+
+static double or_merit(const or_geval *E, double zref) {
+  double a = E->G1 / zref, b = E->G2;
+  return sqrt(a * a + b * b);
+}
+
+/* HLLC-type starting value: contact speed and liquid star density from the
+ * left/right states (eq. HLLC:2p_nopt, mirrored for a liquid on the left),
+ * liquid pressure law for the pressure; the vapour unknown is kept above
+ * 1e-3 p_V so that it stays in the vapour state space. */
+static void or_guess(const or_material *M, const or_rp *R, double *gl, double *gr) {
+  double al = sqrt(or_a2(M, R->phl)), ar = sqrt(or_a2(M, R->phr));
+  double sl = R->ul - al, sr = R->ur + ar;
+  double num = (R->pr - R->pl) + R->rl * R->ul * (sl - R->ul) - R->rr * R->ur * (sr - R->ur);
+  double den = R->rl * (sl - R->ul) - R->rr * (sr - R->ur);
+  double ws = num / den;
+  double rLs;
+  if (R->phl == OR_LIQ)
+    rLs = R->rl * (sl - R->ul) / (sl - ws);
+  else
+    rLs = R->rr * (sr - R->ur) / (sr - ws);
+  double pg = or_pres(M, OR_LIQ, rLs);
+  double pV = (R->phl == OR_VAP) ? R->pl : R->pr;
+  double pvg = pg > 1e-3 * pV ? pg : 1e-3 * pV;
+  if (R->phl == OR_VAP) {
+    *gl = pvg;
+    *gr = pg;
+  } else {
+    *gl = pg;
+    *gr = pvg;
+  }
+}
+
+/* Newton-Armijo from one starting point; 1 on convergence. */
+static int or_newton(const or_material *M, const or_rp *R, double zref, double xl, double xr,
+                     int maxit, double rtol, double *ol, double *orr, or_geval *Eo, int *iters) {
+  or_geval E, Et;
+  if (!or_eval_G(M, R, xl, xr, &E)) return 0;
+  int it;
+  for (it = 0; it < maxit; ++it) {
+    double det = E.J11 * E.J22 - E.J12 * E.J21;
+    if (!(det != 0.0) || !isfinite(det)) return 0;
+    double dl = (-E.G1 * E.J22 + E.G2 * E.J12) / det;
+    double dr = (-E.G2 * E.J11 + E.G1 * E.J21) / det;
+    double sc = fabs(xl) > fabs(xr) ? fabs(xl) : fabs(xr);
+    if (M->p0 > sc) sc = M->p0;
+    double st = fabs(dl) > fabs(dr) ? fabs(dl) : fabs(dr);
+    if (!isfinite(st)) return 0;
+    if (st <= rtol * sc) {
+      double tl = xl + dl, tr = xr + dr;
+      if (or_eval_G(M, R, tl, tr, &Et)) {
+        xl = tl;
+        xr = tr;
+        E = Et;
+      }
+      *ol = xl;
+      *orr = xr;
+      *Eo = E;
+      *iters = it + 1;
+      return 1;
+    }
+    double m0 = or_merit(&E, zref);
+    double lam = 1.0;
+    int acc = 0, k;
+    for (k = 0; k <= 20; ++k) {
+      double tl = xl + lam * dl, tr = xr + lam * dr;
+      if (or_eval_G(M, R, tl, tr, &Et) && or_merit(&Et, zref) <= (1.0 - 1e-4 * lam) * m0) {
+        xl = tl;
+        xr = tr;
+        E = Et;
+        acc = 1;
+        break;
+      }
+      lam *= 0.5;
+    }
+    if (!acc) {
+      if (st <= 1e-8 * sc) { /* merit at its round-off floor */
+        *ol = xl;
+        *orr = xr;
+        *Eo = E;
+        *iters = it + 1;
+        return 1;
+      }
+      return 0;
+    }
+  }
+  return 0;
+}
+
+/* Starting points, tried in this order until Newton-Armijo converges:
+ * the caller's warm start (if any), the HLLC-type guess, and both unknowns
+ * at the vapour state's own pressure. */
+int oracle_iface_solve(const or_material *M, int phl, double rl, double ml, int phr, double rr,
+                       double mr, int have_guess, double gl, double gr, int maxit, double rtol,
+                       or_iface *out) {
+  or_rp R;
+  R.phl = phl;
+  R.phr = phr;
+  R.rl = rl;
+  R.rr = rr;
+  R.ul = ml / rl;
+  R.ur = mr / rr;
+  R.pl = or_pres(M, phl, rl);
+  R.pr = or_pres(M, phr, rr);
+  memset(out, 0, sizeof(*out));
+  if (!(rl > 0.0) || !(rr > 0.0) || phl == phr) return 0;
+  double zl = rl * sqrt(or_a2(M, phl)), zr = rr * sqrt(or_a2(M, phr));
+  double zref = zl > zr ? zl : zr;
+  double xl = 0.0, xr = 0.0;
+  or_geval E;
+  int iters = 0, conv = 0, tries = 0, attempt;
+  for (attempt = 0; attempt < 3 && !conv; ++attempt) {
+    double sl, sr;
+    if (attempt == 0) {
+      if (!have_guess) continue;
+      sl = gl;
+      sr = gr;
+    } else if (attempt == 1) {
+      or_guess(M, &R, &sl, &sr);
+    } else {
+      double pV = (phl == OR_VAP) ? R.pl : R.pr;
+      sl = pV;
+      sr = pV;
+    }
+    int it = 0;
+    conv = or_newton(M, &R, zref, sl, sr, maxit, rtol, &xl, &xr, &E, &it);
+    iters += it;
+    ++tries;
+  }
+  if (!conv) return 0;
+  out->iters = iters;
+  out->pl = xl;
+  out->pr = xr;
+  out->rl = E.rsl;
+  out->rr = E.rsr;
+  out->ul = R.ul - E.fl;
+  out->ur = R.ur + E.fr;
+  out->z = E.z;
+  double uV, rV, pV;
+  if (phl == OR_VAP) {
+    uV = out->ul;
+    rV = out->rl;
+    pV = xl;
+  } else {
+    uV = out->ur;
+    rV = out->rr;
+    pV = xr;
+  }
+  out->w = uV + E.z / rV;
+  out->F0 = -E.z;
+  out->F1 = -E.z * uV + pV;
+  out->ok = 1;
+  (void)tries;
+  return 1;
+}
+
+/* G and its Jacobian at a given point (test hook for the analytic Jacobian) */
+int oracle_iface_G(const or_material *M, int phl, double rl, double ml, int phr, double rr,
+                   double mr, double psl, double psr, double *out6) {
+  or_rp R;
+  or_geval E;
+  R.phl = phl;
+  R.phr = phr;
+  R.rl = rl;
+  R.rr = rr;
+  R.ul = ml / rl;
+  R.ur = mr / rr;
+  R.pl = or_pres(M, phl, rl);
+  R.pr = or_pres(M, phr, rr);
+  if (!or_eval_G(M, &R, psl, psr, &E)) return 0;
+  out6[0] = E.G1;
+  out6[1] = E.G2;
+  out6[2] = E.J11;
+  out6[3] = E.J12;
+  out6[4] = E.J21;
+  out6[5] = E.J22;
+  return 1;
+}
+
+/* ------------------------------------------------------------------ */
+/* one problem                                                         */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  int n, nif;
+  double h;
+  int phase_first;
+  double *rho, *mom; /* n + nif slots */
+  int *home;         /* background cell containing interface k */
+  double *hl;        /* offset of interface k inside its home cell */
+  double *pw;        /* 2 per interface: last converged star pressures */
+  int *warm;
+  double *t;
+  int *status;
+  long long *steps;
+} or_prob;
+
+typedef struct {
+  int m;
+  int slot[OR_MAXC];
+  int ph[OR_MAXC];
+  int mov[OR_MAXC];
+  double U0[OR_MAXC][2];
+  double hn[OR_MAXC];
+  double hh[OR_MAXC]; /* end-of-step length predicted with the explicit speed */
+  double th[OR_MAXC];
+  int ic;   /* phase boundary lies between active cells ic and ic+1 */
+  int tiny; /* active index of the tiny (or merged) cell */
+  double FL[2], FR[2];
+} or_zone;
+
+typedef struct {
+  int count;
+  int flags;
+  int zlo;
+} or_zlog;
+
+static void or_phases(const or_prob *pb, int *ph) {
+  int ns = pb->n + pb->nif, s, k = 0, cur = pb->phase_first;
+  for (s = 0; s < ns; ++s) {
+    while (k < pb->nif && pb->home[k] + k + 1 == s) {
+      cur ^= 1;
+      ++k;
+    }
+    ph[s] = cur;
+  }
+}
+
+static void or_zone_range(const or_params *P, const or_prob *pb, int k, int *zlo, int *zhi,
+                          int *tiny_right) {
+  int ns = pb->n + pb->nif;
+  int sL = pb->home[k] + k;
+  double hL = pb->hl[k], hR = pb->h - hL;
+  int tr = !(hL <= hR);
+  int c = tr ? sL + 1 : sL;
+  int lo = c - P->zone_half, hi = c + P->zone_half;
+  if (lo < 0) lo = 0;
+  if (hi > ns - 1) hi = ns - 1;
+  *zlo = lo;
+  *zhi = hi;
+  *tiny_right = tr;
+}
+
+/* zone set-up: active cells, lengths, merge, pseudo-step fractions */
+static int or_zone_build(const or_material *M, const or_params *P, const or_prob *pb, int k,
+                         const int *ph, int zlo, int zhi, int tiny_right, int merge, double w,
+                         double dt, or_zone *Z) {
+  int ns = pb->n + pb->nif;
+  int sL = pb->home[k] + k, sR = sL + 1;
+  double h = pb->h;
+  double hL = pb->hl[k], hR = h - hL;
+  int skip = -1, into = -1;
+  if (merge) {
+    if (!tiny_right) {
+      skip = sL;
+      into = sL - 1;
+    } else {
+      skip = sR;
+      into = sR + 1;
+    }
+    if (into < zlo || into > zhi || into < 0 || into >= ns) return 0;
+  }
+  int m = 0, s;
+  Z->ic = -1;
+  Z->tiny = -1;
+  for (s = zlo; s <= zhi; ++s) {
+    if (s == skip) continue;
+    if (m >= OR_MAXC) return 0;
+    Z->slot[m] = s;
+    Z->ph[m] = ph[s];
+    Z->U0[m][0] = pb->rho[s];
+    Z->U0[m][1] = pb->mom[s];
+    Z->hn[m] = h;
+    Z->mov[m] = 0;
+    if (s == sL) {
+      Z->hn[m] = hL;
+      Z->mov[m] = 1;
+    } else if (s == sR) {
+      Z->hn[m] = hR;
+      Z->mov[m] = -1;
+    }
+    if (s == into) {
+      double ht = tiny_right ? hR : hL;
+      double hm = h + ht;
+      Z->U0[m][0] = (h * pb->rho[s] + ht * pb->rho[skip]) / hm;
+      Z->U0[m][1] = (h * pb->mom[s] + ht * pb->mom[skip]) / hm;
+      Z->hn[m] = hm;
+      Z->mov[m] = tiny_right ? -1 : 1;
+    }
+    ++m;
+  }
+  Z->m = m;
+  for (s = 0; s < m; ++s) {
+    if (Z->mov[s] == 1) Z->ic = s;
+    int is_t = merge ? (Z->slot[s] == into) : (Z->slot[s] == (tiny_right ? sR : sL));
+    if (is_t) Z->tiny = s;
+  }
+  if (Z->ic < 0 || Z->ic + 1 >= m || Z->tiny < 0) return 0;
+  for (s = 0; s < m; ++s) {
+    double hh = Z->hn[s] + ((double)Z->mov[s] * w) * dt;
+    double th = hh / h;
+    if (th > P->theta_nb) th = P->theta_nb;
+    Z->hh[s] = hh;
+    Z->th[s] = th;
+    if (!(th > 0.0)) return 0;
+  }
+  /* bounding fluxes from U^n (Algorithm 1, Step 1: F_left / F_right) */
+  if (zlo == 0)
+    or_bflux(M, ph[0], 0, P->bc_left, pb->rho[0], pb->mom[0], Z->FL);
+  else
+    oracle_hll(M, ph[zlo], pb->rho[zlo - 1], pb->mom[zlo - 1], pb->rho[zlo], pb->mom[zlo], Z->FL);
+  if (zhi == ns - 1)
+    or_bflux(M, ph[ns - 1], 1, P->bc_right, pb->rho[ns - 1], pb->mom[ns - 1], Z->FR);
+  else
+    oracle_hll(M, ph[zhi], pb->rho[zhi], pb->mom[zhi], pb->rho[zhi + 1], pb->mom[zhi + 1], Z->FR);
+  return 1;
+}
+
+/* face fluxes of a zone iterate W; the phase-boundary face uses the
+ * interface Riemann solver, all other inner faces HLL. */
+static int or_zone_fluxes(const or_material *M, const or_params *P, const or_zone *Z,
+                          double W[][2], double F[][2], double *pw, double *wout) {
+  int c;
+  F[0][0] = Z->FL[0];
+  F[0][1] = Z->FL[1];
+  F[Z->m][0] = Z->FR[0];
+  F[Z->m][1] = Z->FR[1];
+  for (c = 0; c + 1 < Z->m; ++c) {
+    if (c == Z->ic) {
+      or_iface I;
+      if (!oracle_iface_solve(M, Z->ph[c], W[c][0], W[c][1], Z->ph[c + 1], W[c + 1][0],
+                              W[c + 1][1], 1, pw[0], pw[1], P->newton_maxit, P->newton_rtol, &I))
+        return 0;
+      pw[0] = I.pl;
+      pw[1] = I.pr;
+      *wout = I.w;
+      F[c + 1][0] = I.F0;
+      F[c + 1][1] = I.F1;
+    } else {
+      oracle_hll(M, Z->ph[c], W[c][0], W[c][1], W[c + 1][0], W[c + 1][1], F[c + 1]);
+    }
+  }
+  return 1;
+}
+
+static int or_state_ok(double r, double m) { return r > 0.0 && isfinite(r) && isfinite(m); }
+
+/* Algorithm 2 on one zone. Returns 0 on success, or a status bit.
+ * *shrink_cell is set when a moving cell fell below half of its predicted
+ * end-of-step length (the length its pseudo step was sized for). */
+static int or_zone_dts(const or_material *M, const or_params *P, const or_zone *Z, double dt,
+                       double *pw, double U1[][2], double *wstar, int *count, int *lmax_hit,
+                       int *shrink_cell) {
+  double W[OR_MAXC][2], Wn[OR_MAXC][2], F[OR_MAXC + 1][2], hnew[OR_MAXC];
+  int c, l, m = Z->m;
+  double w = 0.0;
+  *shrink_cell = -1;
+  *lmax_hit = 0;
+  for (c = 0; c < m; ++c) {
+    W[c][0] = Z->U0[c][0];
+    W[c][1] = Z->U0[c][1];
+  }
+  int cnt = 0, stop = 0;
+  /* Part 1: pseudo-time iterations */
+  for (l = 0; l < P->lmax; ++l) {
+    if (!or_zone_fluxes(M, P, Z, W, F, pw, &w)) return OR_ST_NEWTON;
+    for (c = 0; c < m; ++c) {
+      hnew[c] = Z->hn[c] + ((double)Z->mov[c] * w) * dt;
+      if (Z->mov[c] != 0 && !(hnew[c] >= 0.5 * Z->hh[c])) {
+        *shrink_cell = c;
+        return OR_ST_MESH;
+      }
+    }
+    double rmax_nb = 0.0, r_tiny = 0.0, rrel = 0.0;
+    for (c = 0; c < m; ++c) {
+      double th = Z->th[c];
+      double rc = 0.0, rr = 0.0;
+      int q;
+      for (q = 0; q < 2; ++q) {
+        double rhs = (Z->hn[c] * Z->U0[c][q] - dt * (F[c + 1][q] - F[c][q])) / hnew[c];
+        Wn[c][q] = (W[c][q] + th * rhs) / (1.0 + th);
+        double d = Wn[c][q] - W[c][q];
+        double sc = fabs(W[c][q]) > 1.0 ? fabs(W[c][q]) : 1.0;
+        double res = fabs((1.0 + th) * d) / ((th * dt) * sc);
+        double rel = fabs(d) / sc;
+        if (res > rc) rc = res;
+        if (rel > rr) rr = rel;
+      }
+      if (!or_state_ok(Wn[c][0], Wn[c][1])) return OR_ST_NONPHYS;
+      if (c == Z->tiny)
+        r_tiny = rc;
+      else if (rc > rmax_nb)
+        rmax_nb = rc;
+      if (rr > rrel) rrel = rr;
+    }
+    for (c = 0; c < m; ++c) {
+      W[c][0] = Wn[c][0];
+      W[c][1] = Wn[c][1];
+    }
+    cnt = l + 1;
+    if (P->tol_mode == 0)
+      stop = (rmax_nb < P->tol_nb) && (r_tiny < P->tol_tiny);
+    else
+      stop = rrel < P->tol_rel;
+    if (stop) break;
+  }
+  if (!stop) *lmax_hit = 1;
+  *count = cnt;
+  /* Part 2: fluxes from the accepted iterate, conservative update */
+  if (!or_zone_fluxes(M, P, Z, W, F, pw, &w)) return OR_ST_NEWTON;
+  for (c = 0; c < m; ++c) {
+    hnew[c] = Z->hn[c] + ((double)Z->mov[c] * w) * dt;
+    if (Z->mov[c] != 0 && !(hnew[c] >= 0.5 * Z->hh[c])) {
+      *shrink_cell = c;
+      return OR_ST_MESH;
+    }
+  }
+  for (c = 0; c < m; ++c) {
+    int q;
+    for (q = 0; q < 2; ++q)
+      U1[c][q] = (Z->hn[c] * Z->U0[c][q] - dt * (F[c + 1][q] - F[c][q])) / hnew[c];
+    if (!or_state_ok(U1[c][0], U1[c][1])) return OR_ST_NONPHYS;
+  }
+  *wstar = w;
+  return 0;
+}
+
+/* Predict, merge, solve and re-align one interface zone. Writes the zone's
+ * new cell values into (rn, mn). Returns 0 or a status bit. */
+static int or_zone_step(const or_material *M, const or_params *P, or_prob *pb, int k,
+                        const int *ph, double dt, double *rn, double *mn, or_zlog *lg) {
+  int ns = pb->n + pb->nif;
+  int sL = pb->home[k] + k, sR = sL + 1;
+  double h = pb->h;
+  int zlo, zhi, tr;
+  or_zone_range(P, pb, k, &zlo, &zhi, &tr);
+  lg->zlo = zlo;
+  lg->flags = tr ? OR_FL_TINY_RIGHT : 0;
+  lg->count = 0;
+  /* explicit prediction of the phase-boundary speed from U^n */
+  or_iface I;
+  if (!oracle_iface_solve(M, ph[sL], pb->rho[sL], pb->mom[sL], ph[sR], pb->rho[sR], pb->mom[sR],
+                          pb->warm[k], pb->pw[2 * k], pb->pw[2 * k + 1], P->newton_maxit,
+                          P->newton_rtol, &I))
+    return OR_ST_NEWTON;
+  double wp = I.w;
+  double ht = tr ? h - pb->hl[k] : pb->hl[k];
+  double rate = tr ? -wp : wp;
+  double hfl = P->alpha_floor * h;
+  int merge = (ht < hfl) || (ht + (P->merge_safety * rate) * dt < hfl);
+  int redo = 0;
+  double U1[OR_MAXC][2];
+  double wstar = 0.0;
+  int count = 0, lmax_hit = 0;
+  or_zone Z;
+  for (;;) {
+    double pw[2] = {I.pl, I.pr};
+    if (!or_zone_build(M, P, pb, k, ph, zlo, zhi, tr, merge, wp, dt, &Z)) return OR_ST_MESH;
+    int sc;
+    int st = or_zone_dts(M, P, &Z, dt, pw, U1, &wstar, &count, &lmax_hit, &sc);
+    if (st == OR_ST_MESH && !merge && sc == Z.tiny) {
+      merge = 1;
+      redo = 1;
+      continue;
+    }
+    if (st) return st;
+    pb->pw[2 * k] = pw[0];
+    pb->pw[2 * k + 1] = pw[1];
+    break;
+  }
+  int c;
+  for (c = 0; c < Z.m; ++c) {
+    rn[Z.slot[c]] = U1[c][0];
+    mn[Z.slot[c]] = U1[c][1];
+  }
+  double hln = pb->hl[k] + wstar * dt;
+  int fl = lg->flags;
+  if (merge) {
+    fl |= OR_FL_MERGED;
+    if (!tr) {
+      if (hln < 0.0) {
+        pb->home[k] -= 1;
+        pb->hl[k] = hln + h;
+        rn[sL] = rn[sR];
+        mn[sL] = mn[sR];
+        fl |= OR_FL_CROSS_L;
+      } else {
+        rn[sL] = rn[sL - 1];
+        mn[sL] = mn[sL - 1];
+        pb->hl[k] = hln;
+      }
+    } else {
+      if (hln > h) {
+        pb->home[k] += 1;
+        pb->hl[k] = hln - h;
+        rn[sR] = rn[sL];
+        mn[sR] = mn[sL];
+        fl |= OR_FL_CROSS_R;
+      } else {
+        rn[sR] = rn[sR + 1];
+        mn[sR] = mn[sR + 1];
+        pb->hl[k] = hln;
+      }
+    }
+  } else {
+    pb->hl[k] = hln;
+  }
+  (void)ns;
+  pb->warm[k] = 1;
+  if (redo) fl |= OR_FL_REDO;
+  if (lmax_hit) fl |= OR_FL_LMAX;
+  lg->flags = fl;
+  lg->count = count;
+  return 0;
+}
+
+/* one physical step of one problem (Algorithm 1 with Algorithm 2 per zone) */
+static void or_step(const or_material *M, const or_params *P, or_prob *pb, int *ph, double *F,
+                    double *rn, double *mn, int *zmark, or_zlog *lg) {
+  int ns = pb->n + pb->nif, s, k;
+  for (k = 0; k < pb->nif; ++k) {
+    lg[k].count = 0;
+    lg[k].flags = OR_FL_INACTIVE;
+    lg[k].zlo = -1;
+  }
+  if (*pb->status) return;
+  if (!(*pb->t < P->t_end)) return;
+  or_phases(pb, ph);
+  /* CFL (eq. cfl_cond:unif): maximal |u| + a over all cells */
+  double S = 0.0;
+  int bad = 0;
+  for (s = 0; s < ns; ++s) {
+    double r = pb->rho[s], m = pb->mom[s];
+    if (!or_state_ok(r, m)) {
+      bad = 1;
+      break;
+    }
+    double si = fabs(m / r) + sqrt(or_a2(M, ph[s]));
+    if (si > S) S = si;
+  }
+  if (bad || !(S > 0.0) || !isfinite(S)) {
+    *pb->status |= OR_ST_NONPHYS;
+    return;
+  }
+  double dt = (P->cfl * pb->h) / S;
+  double rem = P->t_end - *pb->t;
+  int clipped = 0;
+  if (dt >= rem) {
+    dt = rem;
+    clipped = 1;
+  }
+  /* zones: smaller cut piece +- Z slots; they must be disjoint */
+  for (s = 0; s < ns; ++s) zmark[s] = -1;
+  int prev_hi = -1;
+  for (k = 0; k < pb->nif; ++k) {
+    int zlo, zhi, tr;
+    or_zone_range(P, pb, k, &zlo, &zhi, &tr);
+    if (zlo <= prev_hi) {
+      *pb->status |= OR_ST_OVERLAP;
+      return;
+    }
+    prev_hi = zhi;
+    for (s = zlo; s <= zhi; ++s) zmark[s] = k;
+  }
+  /* Algorithm 1, Step 1: explicit update of every cell outside the zones */
+  double lam = dt / pb->h;
+  for (s = 0; s <= ns; ++s) {
+    int need = (s - 1 >= 0 && zmark[s - 1] < 0) || (s < ns && zmark[s] < 0);
+    if (!need) continue;
+    if (s == 0)
+      or_bflux(M, ph[0], 0, P->bc_left, pb->rho[0], pb->mom[0], &F[0]);
+    else if (s == ns)
+      or_bflux(M, ph[ns - 1], 1, P->bc_right, pb->rho[ns - 1], pb->mom[ns - 1], &F[2 * ns]);
+    else
+      oracle_hll(M, ph[s], pb->rho[s - 1], pb->mom[s - 1], pb->rho[s], pb->mom[s], &F[2 * s]);
+  }
+  for (s = 0; s < ns; ++s) {
+    rn[s] = pb->rho[s];
+    mn[s] = pb->mom[s];
+    if (zmark[s] >= 0) continue;
+    rn[s] = pb->rho[s] - lam * (F[2 * (s + 1)] - F[2 * s]);
+    mn[s] = pb->mom[s] - lam * (F[2 * (s + 1) + 1] - F[2 * s + 1]);
+  }
+  /* Algorithm 1, Step 2: each zone by Algorithm 2 */
+  int fail = 0;
+  for (k = 0; k < pb->nif; ++k) {
+    int homek = pb->home[k];
+    double hlk = pb->hl[k];
+    int st = or_zone_step(M, P, pb, k, ph, dt, rn, mn, &lg[k]);
+    if (st) {
+      pb->home[k] = homek;
+      pb->hl[k] = hlk;
+      int zlo, zhi, tr;
+      or_zone_range(P, pb, k, &zlo, &zhi, &tr);
+      for (s = zlo; s <= zhi; ++s) {
+        rn[s] = pb->rho[s];
+        mn[s] = pb->mom[s];
+      }
+      lg[k].flags |= OR_FL_FAIL;
+      fail |= st;
+    }
+  }
+  memcpy(pb->rho, rn, sizeof(double) * ns);
+  memcpy(pb->mom, mn, sizeof(double) * ns);
+  if (fail) {
+    *pb->status |= fail;
+    return;
+  }
+  *pb->t = clipped ? P->t_end : *pb->t + dt;
+  *pb->steps += 1;
+}
+
+/* ------------------------------------------------------------------ */
+/* batch driver                                                        */
+/* ------------------------------------------------------------------ */
+/* Runs n_steps physical steps on each of P independent problems (OpenMP
+ * over problems).  Slot arrays are flattened with slot_off[P+1]; interface
+ * arrays with iface_off[P+1].  Logs (optional) are [n_steps][n_iface]. */
+int oracle_run(const or_material *M, const or_params *Pp, int P, const int *n_cells,
+               const double *h, const int *phase_first, const int *iface_off,
+               const long long *slot_off, int *home, double *hl, double *pw, int *warm,
+               double *rho, double *mom, double *t, int *status, long long *steps, int n_steps,
+               int *log_count, int *log_flags, int *log_zlo, int n_threads) {
+  int nif_tot = iface_off[P];
+  int p;
+  if (Pp->zone_half < 1 || 2 * Pp->zone_half + 1 > OR_MAXC) return -1;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads > 0 ? n_threads : 1)
+  for (p = 0; p < P; ++p) {
+    or_prob pb;
+    int k0 = iface_off[p];
+    pb.n = n_cells[p];
+    pb.nif = iface_off[p + 1] - k0;
+    pb.h = h[p];
+    pb.phase_first = phase_first[p];
+    pb.rho = rho + slot_off[p];
+    pb.mom = mom + slot_off[p];
+    pb.home = home + k0;
+    pb.hl = hl + k0;
+    pb.pw = pw + 2 * k0;
+    pb.warm = warm + k0;
+    pb.t = t + p;
+    pb.status = status + p;
+    pb.steps = steps + p;
+    int ns = pb.n + pb.nif;
+    int *ph = (int *)malloc(sizeof(int) * ns);
+    int *zm = (int *)malloc(sizeof(int) * ns);
+    double *F = (double *)malloc(sizeof(double) * 2 * (ns + 1));
+    double *rn = (double *)malloc(sizeof(double) * ns);
+    double *mn = (double *)malloc(sizeof(double) * ns);
+    or_zlog *lg = (or_zlog *)malloc(sizeof(or_zlog) * (pb.nif > 0 ? pb.nif : 1));
+    int n, k;
+    for (n = 0; n < n_steps; ++n) {
+      or_step(M, Pp, &pb, ph, F, rn, mn, zm, lg);
+      if (log_count) {
+        for (k = 0; k < pb.nif; ++k) {
+          size_t o = (size_t)n * nif_tot + k0 + k;
+          log_count[o] = lg[k].count;
+          log_flags[o] = lg[k].flags;
+          log_zlo[o] = lg[k].zlo;
+        }
+      }
+    }
+    free(ph);
+    free(zm);
+    free(F);
+    free(rn);
+    free(mn);
+    free(lg);
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* fixed-point check: Algorithm 2 to a tight tolerance vs a direct     */
+/* Newton solve of the zone's implicit Euler system                    */
+/* ------------------------------------------------------------------ */
+/* residual R(W) = h^{n+1}(W) W - h^n U^n + dt (F_{c+1/2}(W) - F_{c-1/2}(W)) */
+static int or_zone_residual(const or_material *M, const or_params *P, const or_zone *Z,
+                            double dt, double W[][2], double *pw, double *R) {
+  double F[OR_MAXC + 1][2];
+  double w = 0.0;
+  int c, q;
+  if (!or_zone_fluxes(M, P, Z, W, F, pw, &w)) return 0;
+  for (c = 0; c < Z->m; ++c) {
+    double hnew = Z->hn[c] + ((double)Z->mov[c] * w) * dt;
+    for (q = 0; q < 2; ++q)
+      R[2 * c + q] = hnew * W[c][q] - Z->hn[c] * Z->U0[c][q] + dt * (F[c + 1][q] - F[c][q]);
+  }
+  return 1;
+}
+
+static int or_gauss(int n, double *A, double *b) {
+  int i, j, k;
+  for (k = 0; k < n; ++k) {
+    int piv = k;
+    for (i = k + 1; i < n; ++i)
+      if (fabs(A[i * n + k]) > fabs(A[piv * n + k])) piv = i;
+    if (A[piv * n + k] == 0.0) return 0;
+    if (piv != k) {
+      for (j = 0; j < n; ++j) {
+        double tmp = A[k * n + j];
+        A[k * n + j] = A[piv * n + j];
+        A[piv * n + j] = tmp;
+      }
+      double tb = b[k];
+      b[k] = b[piv];
+      b[piv] = tb;
+    }
+    for (i = k + 1; i < n; ++i) {
+      double f = A[i * n + k] / A[k * n + k];
+      for (j = k; j < n; ++j) A[i * n + j] -= f * A[k * n + j];
+      b[i] -= f * b[k];
+    }
+  }
+  for (i = n - 1; i >= 0; --i) {
+    double s = b[i];
+    for (j = i + 1; j < n; ++j) s -= A[i * n + j] * b[j];
+    b[i] = s / A[i * n + i];
+  }
+  return 1;
+}
+
+/* For interface k of a single problem at its current state, repeats the
+ * set-up of one step (CFL time step, prediction, merge decision), then
+ *   (a) runs Algorithm 2 Part 1 with the given parameters and returns the
+ *       last iterate in W_dts;
+ *   (b) solves the zone's implicit Euler system R(W) = 0 by Newton with a
+ *       central-difference Jacobian, started from U^n, into W_newton.
+ * m_out gets the number of active zone cells (2 values per cell). */
+int oracle_zone_fixed_point(const or_material *M, const or_params *Pp, int n_cells, double h,
+                            int phase_first, int nif, double *rho, double *mom, int *home,
+                            double *hl, double *pw, int *warm, int k, double *W_dts,
+                            double *W_newton, int *m_out, double *dt_out) {
+  or_prob pb;
+  double t = 0.0;
+  int status = 0;
+  long long steps = 0;
+  pb.n = n_cells;
+  pb.nif = nif;
+  pb.h = h;
+  pb.phase_first = phase_first;
+  pb.rho = rho;
+  pb.mom = mom;
+  pb.home = home;
+  pb.hl = hl;
+  pb.pw = pw;
+  pb.warm = warm;
+  pb.t = &t;
+  pb.status = &status;
+  pb.steps = &steps;
+  int ns = n_cells + nif, s, c, q;
+  int *ph = (int *)malloc(sizeof(int) * ns);
+  or_phases(&pb, ph);
+  double S = 0.0;
+  for (s = 0; s < ns; ++s) {
+    double si = fabs(mom[s] / rho[s]) + sqrt(or_a2(M, ph[s]));
+    if (si > S) S = si;
+  }
+  double dt = (Pp->cfl * h) / S;
+  *dt_out = dt;
+  int zlo, zhi, tr;
+  or_zone_range(Pp, &pb, k, &zlo, &zhi, &tr);
+  int sL = home[k] + k, sR = sL + 1;
+  or_iface I;
+  if (!oracle_iface_solve(M, ph[sL], rho[sL], mom[sL], ph[sR], rho[sR], mom[sR], warm[k],
+                          pw[2 * k], pw[2 * k + 1], Pp->newton_maxit, Pp->newton_rtol, &I)) {
+    free(ph);
+    return -1;
+  }
+  double ht = tr ? h - hl[k] : hl[k];
+  double rate = tr ? -I.w : I.w;
+  double hfl = Pp->alpha_floor * h;
+  int merge = (ht < hfl) || (ht + (Pp->merge_safety * rate) * dt < hfl);
+  or_zone Z;
+  if (!or_zone_build(M, Pp, &pb, k, ph, zlo, zhi, tr, merge, I.w, dt, &Z)) {
+    free(ph);
+    return -2;
+  }
+  free(ph);
+  *m_out = Z.m;
+  /* (a) Algorithm 2, Part 1 only */
+  double W[OR_MAXC][2], Wn[OR_MAXC][2], F[OR_MAXC + 1][2];
+  double pwz[2] = {I.pl, I.pr};
+  double w = 0.0;
+  int l;
+  for (c = 0; c < Z.m; ++c) {
+    W[c][0] = Z.U0[c][0];
+    W[c][1] = Z.U0[c][1];
+  }
+  for (l = 0; l < Pp->lmax; ++l) {
+    if (!or_zone_fluxes(M, Pp, &Z, W, F, pwz, &w)) return -3;
+    double rrel = 0.0;
+    for (c = 0; c < Z.m; ++c) {
+      double hnew = Z.hn[c] + ((double)Z.mov[c] * w) * dt;
+      for (q = 0; q < 2; ++q) {
+        double rhs = (Z.hn[c] * Z.U0[c][q] - dt * (F[c + 1][q] - F[c][q])) / hnew;
+        Wn[c][q] = (W[c][q] + Z.th[c] * rhs) / (1.0 + Z.th[c]);
+        double sc = fabs(W[c][q]) > 1.0 ? fabs(W[c][q]) : 1.0;
+        double rel = fabs(Wn[c][q] - W[c][q]) / sc;
+        if (rel > rrel) rrel = rel;
+      }
+    }
+    for (c = 0; c < Z.m; ++c) {
+      W[c][0] = Wn[c][0];
+      W[c][1] = Wn[c][1];
+    }
+    if (rrel < Pp->tol_rel) break;
+  }
+  for (c = 0; c < Z.m; ++c) {
+    W_dts[2 * c] = W[c][0];
+    W_dts[2 * c + 1] = W[c][1];
+  }
+  /* (b) Newton with a central-difference Jacobian */
+  int n = 2 * Z.m, it, j;
+  double X[2 * OR_MAXC], R0[2 * OR_MAXC], Rp[2 * OR_MAXC], Rm[2 * OR_MAXC];
+  double *J = (double *)malloc(sizeof(double) * n * n);
+  double Wt[OR_MAXC][2];
+  for (c = 0; c < Z.m; ++c) {
+    X[2 * c] = Z.U0[c][0];
+    X[2 * c + 1] = Z.U0[c][1];
+  }
+  int ok = 0;
+  for (it = 0; it < 60; ++it) {
+    double pwn[2] = {I.pl, I.pr};
+    for (c = 0; c < Z.m; ++c) {
+      Wt[c][0] = X[2 * c];
+      Wt[c][1] = X[2 * c + 1];
+    }
+    if (!or_zone_residual(M, Pp, &Z, dt, Wt, pwn, R0)) break;
+    for (j = 0; j < n; ++j) {
+      double e = 1e-6 * (fabs(X[j]) > 1e-3 ? fabs(X[j]) : 1e-3);
+      double pa[2] = {pwn[0], pwn[1]}, pb2[2] = {pwn[0], pwn[1]};
+      for (c = 0; c < Z.m; ++c) {
+        Wt[c][0] = X[2 * c];
+        Wt[c][1] = X[2 * c + 1];
+      }
+      Wt[j / 2][j % 2] = X[j] + e;
+      if (!or_zone_residual(M, Pp, &Z, dt, Wt, pa, Rp)) goto done;
+      Wt[j / 2][j % 2] = X[j] - e;
+      if (!or_zone_residual(M, Pp, &Z, dt, Wt, pb2, Rm)) goto done;
+      for (s = 0; s < n; ++s) J[s * n + j] = (Rp[s] - Rm[s]) / (2.0 * e);
+    }
+    for (s = 0; s < n; ++s) R0[s] = -R0[s];
+    if (!or_gauss(n, J, R0)) break;
+    double st = 0.0;
+    for (s = 0; s < n; ++s) {
+      double sc = fabs(X[s]) > 1.0 ? fabs(X[s]) : 1.0;
+      double d = fabs(R0[s]) / sc;
+      if (d > st) st = d;
+      X[s] += R0[s];
+    }
+    if (st < 1e-14) {
+      ok = 1;
+      break;
+    }
+  }
+done:
+  free(J);
+  for (s = 0; s < n; ++s) W_newton[s] = X[s];
+  return ok ? 0 : -4;
+}

@@ -1,0 +1,468 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test ties a part of the oracle to something outside the oracle itself:
+numbers the paper prints (tests/golden/*.json), closed forms, an exact
+self-similar solution, special cases that reduce to textbook problems, an
+independently constructed exact travelling discontinuity, and a brute-force
+Newton solve of the implicit zone system.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.integrate import quad
+from scipy.optimize import brentq
+
+import oracle
+from oracle import material as omat
+from paper_2211_00705_amd import workloads as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+def rho_of_p(M, ph, p):
+    return p / M.a2v if ph == W.VAP else M.rhol0 + (p - M.p0) / M.a2l
+
+
+def slot_lengths(b, home, hl):
+    """Cell lengths of every slot from the interface positions."""
+    out = np.empty(b.n_slots)
+    so = b.slot_off
+    for p in range(b.n_problems):
+        hp = b.h[p]
+        L = np.full(int(so[p + 1] - so[p]), hp)
+        for kk, k in enumerate(range(int(b.iface_off[p]), int(b.iface_off[p + 1]))):
+            sL = home[k] + kk
+            L[sL] = hl[k]
+            L[sL + 1] = hp - hl[k]
+        out[so[p]:so[p + 1]] = L
+    return out
+
+
+# ---------------------------------------------------------------------------
+# material constants
+# ---------------------------------------------------------------------------
+
+def test_material_literals_match_derivation(material):
+    d = omat.derive()
+    for k, v in d.items():
+        assert getattr(material, k) == pytest.approx(v, rel=1e-12), k
+
+
+def test_vapour_limit_matches_printed_table(material):
+    g = gold("eos_limits.json")
+    # rho~ = p~ / a_V^2 printed to 6 decimals
+    assert g["p_tilde_Pa"] / material.a2v == pytest.approx(g["rho_tilde"], abs=5e-7)
+    # liquid branch passes through (rho_min, p_min)
+    p = material.p0 + material.a2l * (g["rho_min"] - material.rhol0)
+    assert abs(p - g["p_min_Pa"]) < 1e-6 * material.p0
+
+
+def test_maxwell_equal_area_by_quadrature(material):
+    """The recovered liquid law makes the isotherm's equal-area integral vanish
+    (checked by adaptive quadrature, not by the closed form)."""
+    g = gold("eos_limits.json")
+    rt = g["p_tilde_Pa"] / material.a2v
+    rv0 = material.p0 / material.a2v
+    rmin = g["rho_min"]
+
+    def p_of_rho(r):
+        if r <= rt:
+            return material.a2v * r
+        if r >= rmin:
+            return material.p0 + material.a2l * (r - material.rhol0)
+        return g["p_min_Pa"] + (g["p_tilde_Pa"] - g["p_min_Pa"]) * (r - rmin) / (rt - rmin)
+
+    f = lambda r: (p_of_rho(r) - material.p0) / r**2
+    I = (quad(f, rv0, rt, epsabs=1e-15, limit=200)[0]
+         + quad(f, rt, 1.0, epsabs=1e-15, limit=200)[0]
+         + quad(f, 1.0, rmin, epsabs=1e-15, limit=400)[0]
+         + quad(f, rmin, material.rhol0, epsabs=1e-18)[0])
+    scale = quad(lambda r: abs(p_of_rho(r) - material.p0) / r**2, rv0, material.rhol0,
+                 limit=400)[0]
+    assert abs(I) < 2e-6 * scale
+
+
+def test_sound_speed_consistent_with_cavitation_time_step(material):
+    """The vapour cell created in the cavitation test has size
+    (w_r - w_l) dt; with C = 0.5 and h = 1e-2 this fixes
+    S_max = |u| + a_L = 4 m/s + a_L, an independent check on K0/rho0."""
+    g = gold("cavitation_star_states.json")
+    dt = g["h_V_created"] / (2.0 * g["w_right"])
+    S = g["cfl"] * g["h"] / dt
+    aL = math.sqrt(material.a2l)
+    assert abs(S - g["initial_liquid_speed"] - aL) / aL < 2e-4
+
+
+# ---------------------------------------------------------------------------
+# interface Riemann solver
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("orient", ["liquid_left", "vapour_left"])
+def test_iface_reproduces_cavitation_star_states(material, orient):
+    g = gold("cavitation_star_states.json")
+    rL = rho_of_p(material, W.LIQ, g["pL_star_plus_Pa"])
+    rV = rho_of_p(material, W.VAP, g["pV_star_Pa"])
+    if orient == "vapour_left":  # right phase boundary of the cavitation test
+        r = oracle.iface_solve(material, W.VAP, rV, g["uV_star"], W.LIQ, rL, g["uL_star_plus"])
+        pV, pL, w = r["pl"], r["pr"], r["w"]
+        assert w == pytest.approx(g["w_right"], abs=1e-6)
+    else:  # left phase boundary
+        r = oracle.iface_solve(material, W.LIQ, rL, g["uL_star_minus"], W.VAP, rV, g["uV_star"])
+        pL, pV, w = r["pl"], r["pr"], r["w"]
+        assert w == pytest.approx(-g["w_right"], abs=1e-6)
+    assert r["ok"]
+    assert abs(pV - g["pV_star_Pa"]) < 1e-3
+    assert abs(pL - g["pL_star_plus_Pa"]) < 1e-3
+    # the printed star states carry almost no outer waves
+    assert abs(r["z"]) == pytest.approx(rV * g["w_right"], rel=2e-7)
+
+
+def test_iface_reproduces_nucleation_star_states(material):
+    g = gold("nucleation_star_states.json")
+    rV = rho_of_p(material, W.VAP, g["pV_star_minus_Pa"])
+    rL = rho_of_p(material, W.LIQ, g["pL_star_Pa"])
+    r = oracle.iface_solve(material, W.VAP, rV, g["uV_star_minus"], W.LIQ, rL, g["uL_star"])
+    assert r["ok"]
+    assert abs(r["pl"] - g["pV_star_minus_Pa"]) < 1e-3
+    assert abs(r["pr"] - g["pL_star_Pa"]) < 1e-3
+    assert abs(r["w"]) == pytest.approx(g["w_abs"], abs=5e-7)
+    assert r["w"] < 0  # the drop grows: its left boundary (vapour | liquid) moves left
+    # mirror image: the drop's right boundary moves right
+    r2 = oracle.iface_solve(material, W.LIQ, rL, g["uL_star"], W.VAP, rV, g["uV_star_plus"])
+    assert r2["w"] == pytest.approx(-r["w"], rel=1e-9)
+
+
+@pytest.mark.parametrize("alpha_side", [0, 1])
+def test_saturation_equilibrium_is_a_fixed_point(material, alpha_side):
+    rV0 = material.p0 / material.a2v
+    if alpha_side == 0:
+        r = oracle.iface_solve(material, W.LIQ, material.rhol0, 0.0, W.VAP, rV0, 0.0)
+    else:
+        r = oracle.iface_solve(material, W.VAP, rV0, 0.0, W.LIQ, material.rhol0, 0.0)
+    assert r["ok"]
+    assert abs(r["z"]) < 1e-12
+    assert abs(r["w"]) < 1e-12
+    assert r["pl"] == pytest.approx(material.p0, rel=1e-12)
+    assert r["pr"] == pytest.approx(material.p0, rel=1e-12)
+
+
+def _textbook_wave(a, rho, rho_star):
+    """Velocity change across an isothermal wave with p = a^2 rho + const:
+    shock sqrt([[p]][[v]]) from the Rankine-Hugoniot conditions,
+    rarefaction a ln(rho*/rho) from the Riemann invariant."""
+    if rho_star > rho:
+        return math.sqrt(a * a * (rho_star - rho) * (1.0 / rho - 1.0 / rho_star))
+    return a * math.log(rho_star / rho)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_zero_kinetic_coefficient_is_the_no_transfer_problem(material, seed):
+    """tau = 0 gives z = 0, hence [[p]] = [[u]] = 0 (Appendix A, case without
+    phase transition); the common p* solves f_l + f_r + du = 0, found here by
+    bisection with the closed-form wave curves."""
+    import dataclasses
+    M0 = dataclasses.replace(material, tau=0.0)
+    rng = np.random.default_rng(seed)
+    rl, ul = rng.uniform(960, 970), rng.uniform(-1, 1)
+    rv, uv = rng.uniform(0.2, 0.6), rng.uniform(-1, 1)
+    r = oracle.iface_solve(M0, W.LIQ, rl, ul, W.VAP, rv, uv)
+    assert r["ok"]
+    assert r["z"] == 0.0
+    assert r["pl"] == pytest.approx(r["pr"], rel=1e-12)
+    assert r["ul"] == pytest.approx(r["ur"], abs=1e-9)
+    aL, aV = math.sqrt(M0.a2l), math.sqrt(M0.a2v)
+
+    def F(p):
+        return (_textbook_wave(aL, rl, rho_of_p(M0, W.LIQ, p))
+                + _textbook_wave(aV, rv, rho_of_p(M0, W.VAP, p)) + (uv - ul))
+
+    ps = brentq(F, 1.0, 1e7, xtol=1e-12, rtol=1e-15)
+    assert r["pl"] == pytest.approx(ps, rel=1e-10)
+    assert r["w"] == pytest.approx(r["ul"], abs=1e-9)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_analytic_jacobian_matches_central_differences(material, seed):
+    rng = np.random.default_rng(100 + seed)
+    rl, ul = rng.uniform(900, 1000), rng.uniform(-1, 1)
+    rv, uv = rng.uniform(0.01, 0.5), rng.uniform(-1, 1)
+    orient = seed % 2
+    args = ((W.LIQ, rl, ul, W.VAP, rv, uv) if orient == 0 else (W.VAP, rv, uv, W.LIQ, rl, ul))
+    pv = rng.uniform(5e3, 6e4)
+    pl = pv + rng.uniform(-1e4, 1e5)
+    x = (pl, pv) if orient == 0 else (pv, pl)
+    G0, J = oracle.iface_G(material, *args, *x)
+    Jfd = np.zeros((2, 2))
+    for j in range(2):
+        e = 1e-6 * abs(x[j])
+        xp, xm = list(x), list(x)
+        xp[j] += e
+        xm[j] -= e
+        Jfd[:, j] = (oracle.iface_G(material, *args, *xp)[0] - oracle.iface_G(material, *args, *xm)[0]) / (2 * e)
+    np.testing.assert_allclose(J, Jfd, rtol=1e-5, atol=1e-9 * np.abs(J).max())
+
+
+def test_iface_solves_random_configuration_states(material):
+    """Every liquid|vapour pair drawn from the configurations' ranges has a
+    converged solution that satisfies both jump conditions."""
+    rng = np.random.default_rng(7)
+    for i in range(400):
+        rl, ul = rng.uniform(900, 1000), rng.uniform(-1, 1)
+        rv, uv = rng.uniform(0.01, 0.1), rng.uniform(-1, 1)
+        r = oracle.iface_solve(material, W.LIQ, rl, ul, W.VAP, rv, uv)
+        assert r["ok"]
+        # mass: rho*(u* - w) equal on both sides
+        ml = r["rl"] * (r["ul"] - r["w"])
+        mv = r["rr"] * (r["ur"] - r["w"])
+        assert ml == pytest.approx(mv, rel=1e-9, abs=1e-12)
+        # momentum: -z u* + p* equal on both sides
+        pl_ = material.p0 + material.a2l * (r["rl"] - material.rhol0)
+        fl = -r["z"] * r["ul"] + pl_
+        fv = -r["z"] * r["ur"] + material.a2v * r["rr"]
+        assert fl == pytest.approx(fv, rel=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# bulk scheme
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("phase", [W.LIQ, W.VAP])
+def test_hll_is_consistent(material, phase):
+    rng = np.random.default_rng(3)
+    for _ in range(50):
+        r = rng.uniform(900, 1000) if phase == W.LIQ else rng.uniform(0.01, 1)
+        u = rng.uniform(-50, 50)
+        F = oracle.hll(material, phase, r, r * u, r, r * u)
+        p = material.a2v * r if phase == W.VAP else material.p0 + material.a2l * (r - material.rhol0)
+        assert F[0] == pytest.approx(r * u, rel=1e-14)
+        assert F[1] == pytest.approx(r * u * u + p, rel=1e-14)
+        # a wall ghost (rho, -m) gives exactly zero mass flux
+        Fw = oracle.hll(material, phase, r, r * u, r, -r * u)
+        assert Fw[0] == 0.0
+
+
+def test_constant_states_are_preserved(material):
+    for ph, r0 in ((W.LIQ, 970.0), (W.VAP, 0.2)):
+        b = W.single_phase_problem(64, lambda x: np.full(x.shape, r0), lambda x: np.zeros(x.shape), ph)
+        st = oracle.State(b)
+        oracle.run(st, material, W.Params(), 200)
+        assert np.array_equal(st.rho, b.rho) and np.array_equal(st.mom, b.mom)
+        b2 = W.single_phase_problem(64, lambda x: np.full(x.shape, r0), lambda x: np.full(x.shape, 3.0), ph)
+        st2 = oracle.State(b2)
+        oracle.run(st2, material, W.Params(bc_left=1, bc_right=1), 200)
+        np.testing.assert_allclose(st2.rho, b2.rho, rtol=1e-14)
+        np.testing.assert_allclose(st2.mom, b2.mom, rtol=1e-13)
+
+
+def _isothermal_exact_same_phase(a, left, right, xi):
+    """Exact same-phase isothermal Riemann solution (p = a^2 rho + const)."""
+    rl, ul = left
+    rr, ur = right
+
+    def f(rho, rk):
+        return _textbook_wave(a, rk, rho)
+
+    rs = brentq(lambda r: f(r, rl) + f(r, rr) + (ur - ul), 1e-6 * min(rl, rr), 1e3 * max(rl, rr),
+                xtol=1e-14)
+    us = ul - f(rs, rl)
+    rho, u = np.empty_like(xi), np.empty_like(xi)
+    for i, x in enumerate(xi):
+        if x < us:
+            if rs > rl:
+                s = (rs * us - rl * ul) / (rs - rl)
+                rho[i], u[i] = (rl, ul) if x < s else (rs, us)
+            else:
+                if x < ul - a:
+                    rho[i], u[i] = rl, ul
+                elif x > us - a:
+                    rho[i], u[i] = rs, us
+                else:
+                    u[i] = x + a
+                    rho[i] = rl * math.exp((ul - u[i]) / a)
+        else:
+            if rs > rr:
+                s = (rs * us - rr * ur) / (rs - rr)
+                rho[i], u[i] = (rr, ur) if x > s else (rs, us)
+            else:
+                if x > ur + a:
+                    rho[i], u[i] = rr, ur
+                elif x < us + a:
+                    rho[i], u[i] = rs, us
+                else:
+                    u[i] = x - a
+                    rho[i] = rr * math.exp((u[i] - ur) / a)
+    return rho, u
+
+
+def test_explicit_scheme_converges_to_exact_isothermal_riemann_solution(material):
+    """No interface: the oracle is the plain explicit Godunov scheme with HLL
+    fluxes; its L1 error against the exact shock-tube solution falls with h."""
+    a = math.sqrt(material.a2v)
+    left, right = (0.4, 30.0), (0.1, -10.0)
+    errs = []
+    for n in (100, 200, 400, 800):
+        b = W.single_phase_problem(n, lambda x: np.where(x < 0.5, left[0], right[0]),
+                                   lambda x: np.where(x < 0.5, left[1], right[1]), W.VAP)
+        T = 4e-4
+        st = oracle.State(b)
+        oracle.run(st, material, W.Params(bc_left=1, bc_right=1, t_end=T), 100000)
+        assert st.t[0] == T and st.status[0] == 0
+        h = 1.0 / n
+        xs = (np.arange(n)[:, None] + (np.arange(16)[None, :] + 0.5) / 16) * h
+        rex, _ = _isothermal_exact_same_phase(a, left, right, ((xs - 0.5) / T).ravel())
+        rex = rex.reshape(n, 16).mean(1)
+        errs.append(np.abs(st.rho - rex).sum() * h)
+    errs = np.array(errs)
+    assert np.all(errs[1:] < 0.8 * errs[:-1]), errs
+    assert errs[-1] < 2e-3
+
+
+# ---------------------------------------------------------------------------
+# full scheme with interfaces
+# ---------------------------------------------------------------------------
+
+def _travelling_boundary(M, rhoV, uV):
+    """Liquid|vapour states joined by a single phase boundary satisfying both
+    jump conditions and the kinetic relation (e_kin relative to the
+    boundary), built by a scalar root find on the liquid density."""
+    pV, vV = M.a2v * rhoV, 1.0 / rhoV
+    gV = M.a2v * math.log(rhoV / (M.p0 / M.a2v))
+
+    def parts(rL):
+        pL = M.p0 + M.a2l * (rL - M.rhol0)
+        vL = 1.0 / rL
+        z2 = (pL - pV) / (vV - vL)
+        return pL, vL, z2
+
+    def resid(rL):
+        pL, vL, z2 = parts(rL)
+        z = -math.sqrt(max(z2, 0.0))
+        gL = M.a2l * math.log(rL / M.rhol0)
+        return z - M.tau * pV * ((gV - gL) + 0.5 * z2 * (vV**2 - vL**2))
+
+    r_lo = M.rhol0 + (pV - M.p0) / M.a2l
+    rL = brentq(resid, r_lo * (1 + 1e-15), r_lo + 1.0, xtol=1e-14, rtol=1e-15)
+    pL, vL, z2 = parts(rL)
+    z = -math.sqrt(z2)
+    w = uV + z * vV
+    uL = w - z * vL
+    return (rL, uL), (rhoV, uV), w
+
+
+@pytest.mark.parametrize("alpha", [0.3, 1e-3, 2e-6])
+def test_travelling_phase_boundary_is_exact(material, alpha):
+    """Data equal to an exact travelling phase boundary: all cell values stay
+    put to round-off while the boundary moves through several grid cells
+    (merges and re-splits included), and x_I(t) = x0 + w t."""
+    (rL, uL), (rV, uV), w = _travelling_boundary(material, 0.38, 0.0)
+    assert w < -1.0
+    b = W.riemann_problem(40, (rL, uL), (rV, uV), j=30, alpha=alpha, length=0.4)
+    x0 = 30 * 0.01 + alpha * 0.01
+    P = W.Params(bc_left=1, bc_right=1)
+    st = oracle.State(b)
+    lc, lf, _ = oracle.run(st, material, P, 900, log=True)
+    assert st.status[0] == 0 and st.steps[0] == 900
+    assert ((lf[:, 0] & oracle.FL_CROSS_L) > 0).sum() >= 3
+    liq = np.arange(b.n_slots) <= st.home[0]
+    np.testing.assert_allclose(st.rho[liq], rL, rtol=1e-10)
+    np.testing.assert_allclose(st.mom[liq], rL * uL, rtol=1e-9)
+    np.testing.assert_allclose(st.rho[~liq], rV, rtol=1e-10)
+    # the constructed data are exact to about one ulp of rho_L (2e-7 Pa in
+    # p_L), which leaves vapour speeds of order 1e-9 |w|
+    assert np.abs(st.mom[~liq] / st.rho[~liq]).max() < 1e-9 * abs(w)
+    assert abs(st.x_iface()[0] - (x0 + w * st.t[0])) < 1e-11
+
+
+def test_mass_is_conserved_exactly_with_walls(material):
+    b = W.random_batch(seed=5, n_problems=12, nmin=64, nmax=300)
+    st = oracle.State(b)
+    L0 = slot_lengths(b, st.home, st.hl)
+    m0 = np.add.reduceat(L0 * st.rho, b.slot_off[:-1].astype(np.int64))
+    lc, lf, _ = oracle.run(st, material, W.random_batch_params(), 400, log=True)
+    assert np.all(st.status == 0)
+    assert ((lf & (oracle.FL_CROSS_L | oracle.FL_CROSS_R)) > 0).sum() > 10
+    L1 = slot_lengths(b, st.home, st.hl)
+    m1 = np.add.reduceat(L1 * st.rho, b.slot_off[:-1].astype(np.int64))
+    np.testing.assert_allclose(m1, m0, rtol=5e-14)
+
+
+def test_two_phase_riemann_problem_converges_to_exact_solution(material):
+    """Liquid|vapour Riemann problem: the IMEX-DS solution approaches the
+    exact self-similar solution (outer waves from the closed-form curves,
+    star states and boundary speed from the interface solver) as h -> 0."""
+    from exact_rp import sample, star
+    left, right = (965.6, 0.0), (0.33, 0.0)
+    st_ex = star(material, left, right, (W.LIQ, W.VAP))
+    T = 2e-4
+    errs_v, errs_l, xerr = [], [], []
+    for n in (100, 200, 400, 800):
+        b = W.riemann_problem(n, left, right, alpha=0.5)
+        st = oracle.State(b)
+        oracle.run(st, material, W.Params(bc_left=1, bc_right=1, t_end=T), 10**6)
+        assert st.t[0] == T and st.status[0] == 0
+        L = slot_lengths(b, st.home, st.hl)
+        xr = np.cumsum(L)
+        xl = xr - L
+        sub = (np.arange(32) + 0.5) / 32
+        xs = xl[:, None] + L[:, None] * sub[None, :]
+        x0 = 0.5 + 0.5 / n
+        rex, _ = sample(material, left, right, (W.LIQ, W.VAP), ((xs - x0) / T).ravel(), st_ex)
+        rex = rex.reshape(-1, 32).mean(1)
+        sL = st.home[0]
+        vap = np.arange(b.n_slots) > sL
+        errs_l.append((np.abs(st.rho - rex) * L)[~vap].sum())
+        errs_v.append((np.abs(st.rho - rex) * L)[vap].sum())
+        xerr.append(abs(st.x_iface()[0] - (x0 + st_ex["w"] * T)) * n)
+    assert errs_v[-1] < 0.6 * errs_v[0] and errs_l[-1] < 0.6 * errs_l[0], (errs_v, errs_l)
+    assert max(xerr) < 0.5, xerr  # within half a cell
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_dual_time_fixed_point_is_the_implicit_euler_step(material, seed):
+    """Algorithm 2 run to a tight relative update converges to the solution
+    of the zone's implicit Euler system found by a direct Newton solve."""
+    b = W.single_cut_problem(seed, alpha=3e-3)
+    st = oracle.State(b)
+    oracle.run(st, material, W.single_cut_params(), 3)
+    P = W.single_cut_params().replace(tol_mode=1, tol_rel=1e-15, lmax=200000)
+    rc, Wd, Wn, dt = oracle.zone_fixed_point(st, material, P)
+    assert rc == 0
+    scale = np.maximum(np.abs(Wn), 1.0)
+    assert np.max(np.abs(Wd - Wn) / scale) < 1e-9
+
+
+def test_failures_freeze_only_their_problem(material):
+    good = W.random_batch(seed=11, n_problems=3, nmin=64, nmax=128)
+    bad = good.copy()
+    so = bad.slot_off
+    bad.rho[so[1] + 5] = float("nan")
+    st = oracle.State(bad)
+    oracle.run(st, material, W.random_batch_params(), 20)
+    assert st.status[1] == oracle.ST_NONPHYS and st.steps[1] == 0
+    ref = oracle.State(good)
+    oracle.run(ref, material, W.random_batch_params(), 20)
+    for p in (0, 2):
+        sl = slice(so[p], so[p + 1])
+        assert np.array_equal(st.rho[sl], ref.rho[sl])
+    # Newton forced to fail: status NEWTON_FAIL, zone untouched, no time advance
+    st2 = oracle.State(good)
+    oracle.run(st2, material, W.random_batch_params().replace(newton_maxit=1), 5)
+    assert np.all(st2.status == oracle.ST_NEWTON) and np.all(st2.t == 0)
+
+
+def test_overlapping_zones_are_rejected(material):
+    b = W._assemble([40], [0.025], [0.0], [W.LIQ], [[10, 12]], [[0.01, 0.01]],
+                    [lambda x, q: (np.full(x.shape, 966.0 if q == W.LIQ else 0.4), np.zeros(x.shape))],
+                    name="close")
+    st = oracle.State(b)
+    oracle.run(st, material, W.Params(), 3)
+    assert st.status[0] == oracle.ST_OVERLAP
+    assert np.array_equal(st.rho, b.rho)
