@@ -1,0 +1,225 @@
+/*
+ * imexds.h -- C ABI of the MI355X (gfx950) implementation of the
+ * explicit-implicit domain-splitting (IMEX-DS) time step of May & Thein,
+ * "Explicit-Implicit Domain Splitting for Two Phase Flows with Phase
+ * Transition" (arXiv 2211.00705), for the 1D isothermal Euler equations with
+ * sharp liquid-vapour interfaces and a kinetic mass-transfer relation.
+ *
+ * The library advances a batch of independent 1D problems.  One physical
+ * step of one problem is Algorithm 1 of the paper: every cell away from the
+ * tiny cut cells is updated explicitly with HLL fluxes (Step 1, eq. "update
+ * expl time"); the cells of each implicit zone (the tiny cut cell and Z
+ * neighbours on each side) are updated by Algorithm 2, dual time stepping
+ * with local pseudo steps (eq. "dual time tau diff") followed by a
+ * conservative update from the accepted iterate (Part 2), with moving
+ * interface-adjacent cells (Sec. 4.4, eq. "godunov_meth:nonunif").  The flux
+ * across a phase boundary comes from the two-phase Riemann problem with the
+ * kinetic relation z = tau p_V [[g + e_kin]] (Sec. 2.1, eq. "isoT:kin_rel1";
+ * Appendix A, eqs. "2p_RP:ex_sys", "jacobian:ex_sys", "pb_flux:pt").  The
+ * time step follows the CFL condition (eq. "cfl_cond:unif") per problem.
+ *
+ * Units: SI.  Arithmetic: IEEE FP64 throughout, no fused multiply-add.
+ *
+ * Conventions for every function returning int:
+ *   0 on success, a negative IMEXDS_ERR_* code otherwise (imexds_strerror
+ *   names it).  Nothing aborts; no C++ exception crosses the ABI.  A failure
+ *   of one problem (Newton not converging, non-physical state, mesh failure,
+ *   overlapping zones) does not fail the call: that problem is frozen and its
+ *   IMEXDS_ST_* bits show in its status word (imexds_get_problems).
+ * Pointers: "device" pointers are HIP device memory on the context's device
+ *   (e.g. torch tensors on cuda), "host" pointers are ordinary memory.  The
+ *   caller keeps them alive for the duration of the call; the library keeps no
+ *   reference to caller memory after a call returns.
+ * Streams: all device work is enqueued on the stream given to imexds_create
+ *   (NULL = the null stream).  Functions marked "async" return before the
+ *   work is done; functions that return host data synchronize the stream.
+ */
+#ifndef IMEXDS_H
+#define IMEXDS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define IMEXDS_OK 0
+#define IMEXDS_ERR_INVALID_ARG (-1)
+#define IMEXDS_ERR_OOM (-2)
+#define IMEXDS_ERR_HIP (-3)
+#define IMEXDS_ERR_NO_STATE (-4)
+#define IMEXDS_ERR_UNSUPPORTED (-5)
+
+/* per-problem status bits (sticky; a problem with any bit set is frozen) */
+#define IMEXDS_ST_NEWTON_FAIL 1  /* interface Newton-Armijo did not converge */
+#define IMEXDS_ST_NONPHYSICAL 2  /* rho <= 0 or non-finite state */
+#define IMEXDS_ST_MESH_FAIL 4    /* a cut piece collapsed / could not merge */
+#define IMEXDS_ST_ZONE_OVERLAP 8 /* two implicit zones would overlap */
+
+/* per-step, per-interface log flags (imexds_get_log) */
+#define IMEXDS_FL_TINY_RIGHT 1 /* the smaller cut piece is right of the interface */
+#define IMEXDS_FL_MERGED 2     /* that piece was merged into its outer neighbour */
+#define IMEXDS_FL_REDO 4       /* merge forced after a collapse inside the zone solve */
+#define IMEXDS_FL_LMAX 8       /* dual time stepping stopped at lmax */
+#define IMEXDS_FL_CROSS_L 16   /* interface moved into the left neighbour cell */
+#define IMEXDS_FL_CROSS_R 32   /* interface moved into the right neighbour cell */
+#define IMEXDS_FL_FAIL 64      /* the zone failed this step (status set) */
+#define IMEXDS_FL_INACTIVE 128 /* problem frozen or finished: nothing done */
+
+/* dual-time stopping rules */
+#define IMEXDS_TOL_PAPER 0 /* Sec. 5: max(res_{k-1},res_{k+1}) < tol_nb and res_k < tol_tiny */
+#define IMEXDS_TOL_REL 1   /* max |W^{l+1}-W^l| / max(|W^l|,1) < tol_rel over the zone */
+
+#define IMEXDS_BC_WALL 0
+#define IMEXDS_BC_TRANSMISSIVE 1
+
+typedef struct imexds_ctx imexds_ctx; /* opaque; owns all of its device buffers */
+
+/* Phase pressure laws (Sec. 5): vapour ideal gas p = a2_vap rho
+ * (eq. "eos:isoT_idgas", a2_vap = k T0 / m); liquid linear Tait law
+ * p = p_sat + a2_liq (rho - rho_liq_sat) (eq. "eos:isoT_lintait" with
+ * a2_liq = K0 / rho0).  Gibbs energies g = a^2 ln(rho / rho_sat) per phase,
+ * equal at saturation (Maxwell construction, Sec. 2.1).  tau is the kinetic
+ * coefficient of eq. "isoT:kin_rel1". */
+typedef struct {
+  double a2_vap, a2_liq, p_sat, rho_liq_sat, tau;
+} imexds_material;
+
+typedef struct {
+  double cfl;         /* C_CFL of eq. "cfl_cond:unif" */
+  int32_t zone_half;  /* Z: an implicit zone is the tiny cut piece +- Z slots (1..3) */
+  double theta_nb;    /* theta for full cells (0.9 in Sec. 5) */
+  int32_t tol_mode;   /* IMEXDS_TOL_* */
+  double tol_nb;      /* 1e-3 in Sec. 5 */
+  double tol_tiny;    /* 1e-1 in Sec. 5 */
+  double tol_rel;     /* for IMEXDS_TOL_REL */
+  int32_t lmax;       /* maximal pseudo steps per zone and step (Algorithm 2) */
+  double alpha_floor; /* cut pieces shorter than alpha_floor*h are merged */
+  double merge_safety;/* factor on the predicted shrink in the merge test */
+  int32_t bc_left, bc_right; /* IMEXDS_BC_* */
+  int32_t newton_maxit;      /* per Newton-Armijo start */
+  double newton_rtol;        /* relative step for Newton convergence */
+  double t_end;              /* stop time per problem (INFINITY: step counts only) */
+} imexds_params;
+
+/* A batch of independent problems (host pointers, copied by imexds_create).
+ * Problem p has n_cells[p] background cells of width h[p] starting at
+ * x_left[p] and the interfaces iface_off[p] .. iface_off[p+1]-1, sorted left
+ * to right.  Interface k lies in background cell home[k] (0-based) at offset
+ * hl[k] in [0, h[p]] from its left face and splits it into two slots, so
+ * problem p owns n_cells[p] + (iface_off[p+1]-iface_off[p]) consecutive
+ * slots of the flat state arrays, problems in order.  phase_first[p] is the
+ * phase of the problem's first slot (0 liquid, 1 vapour); phases alternate
+ * across interfaces; home cells of one problem must increase strictly, at
+ * most 64 interfaces per problem.  Implicit zones that overlap do not fail
+ * the call: the problem gets IMEXDS_ST_ZONE_OVERLAP and stays frozen. */
+typedef struct {
+  int32_t n_problems;
+  const int32_t *n_cells;
+  const double *h;
+  const double *x_left;
+  const int32_t *phase_first;
+  const int32_t *iface_off; /* [n_problems + 1] */
+  const int32_t *home;      /* [n_iface] */
+  const double *hl;         /* [n_iface] */
+} imexds_batch;
+
+typedef struct {
+  int64_t steps;          /* physical steps completed, summed over problems */
+  int64_t cell_updates;   /* sum over problems of slots x steps completed */
+  int64_t pseudo_iters;   /* dual-time iterations, summed over zones and steps */
+  int64_t merges;         /* merge events */
+  int64_t lmax_hits;      /* zone steps that stopped at lmax */
+  int32_t n_failed;       /* problems with a nonzero status */
+  int32_t n_active;       /* problems still advancing (status 0, t < t_end) */
+} imexds_stats;
+
+/* Creates a context on the current HIP device for the given material,
+ * parameters and batch layout.  Validates the inputs (IMEXDS_ERR_INVALID_ARG
+ * on bad sizes, interfaces outside their problem or out of order, more than
+ * 64 interfaces in a problem, parameters out of range), allocates the device
+ * buffers
+ * (about 4 doubles per slot plus small per-problem/-interface records), and
+ * copies the layout to the device.  *out is NULL on failure.  An empty batch
+ * (n_problems = 0) is valid and every step on it is a no-op. */
+int imexds_create(imexds_ctx **out, const imexds_material *mat, const imexds_params *par,
+                  const imexds_batch *batch, void *hip_stream);
+
+/* Loads the cell averages (rho, rho u) of every slot (device pointers,
+ * n_slots doubles each, flat layout above), resets t = 0, statuses, step
+ * counts, interface positions (to the batch's home/hl), Newton warm starts
+ * and statistics, and computes the first time step (CFL over all slots). */
+int imexds_set_state(imexds_ctx *ctx, const double *rho, const double *mom);
+
+/* Enqueues n_steps physical steps of every problem (async).  Problems that
+ * reached t_end or failed are left unchanged. */
+int imexds_step(imexds_ctx *ctx, int32_t n_steps);
+
+/* Steps until every problem has t >= t_end or is frozen, or max_steps steps
+ * were enqueued; checks progress every check_every steps (synchronizes).
+ * *steps_done (host, may be NULL) receives the number of steps enqueued. */
+int imexds_run(imexds_ctx *ctx, int32_t max_steps, int32_t check_every, int32_t *steps_done);
+
+/* Baseline launch form: the same kernels, launched problem by problem on the
+ * context's stream (n_steps steps of every problem, async). */
+int imexds_step_per_problem(imexds_ctx *ctx, int32_t n_steps);
+
+/* Copies the current cell averages to device pointers (n_slots each, async). */
+int imexds_get_state(imexds_ctx *ctx, double *rho, double *mom);
+
+/* Host copies of the per-interface mesh state (n_iface each; any may be NULL):
+ * background cell, offset in it, and position x_left + home*h + hl.
+ * Synchronizes. */
+int imexds_get_interfaces(imexds_ctx *ctx, int32_t *home, double *hl, double *x_iface);
+
+/* Host copies of per-problem time, status bits and completed steps
+ * (n_problems each; any may be NULL).  Synchronizes. */
+int imexds_get_problems(imexds_ctx *ctx, double *t, int32_t *status, int64_t *steps);
+
+/* Enables per-step logging of the next max_steps steps (0 disables):
+ * pseudo-iteration count, IMEXDS_FL_* flags and first zone slot (local to
+ * the problem) of every interface.  Logging restarts at row 0. */
+int imexds_enable_log(imexds_ctx *ctx, int32_t max_steps);
+
+/* Host copies of the logged rows, [rows][n_iface] each (any may be NULL);
+ * *rows receives the number of rows written.  Synchronizes. */
+int imexds_get_log(imexds_ctx *ctx, int32_t *count, int32_t *flags, int32_t *zlo, int32_t *rows);
+
+/* Statistics since the last imexds_set_state.  Synchronizes. */
+int imexds_get_stats(imexds_ctx *ctx, imexds_stats *out);
+
+/* Launch configuration: cells per bulk tile (256, 512, 1024, 2048), zones
+ * per zone workgroup (1..64) and physical steps per captured HIP graph
+ * (0 = launch kernels directly, else an even number).  Rebuilds the tile
+ * table and drops captured graphs. */
+int imexds_set_launch(imexds_ctx *ctx, int32_t tile_cells, int32_t zones_per_group,
+                      int32_t graph_steps);
+
+/* Times each launch configuration on the current state for steps_per_trial
+ * steps, restores the state afterwards and keeps the fastest configuration.
+ * Results (host, may be NULL): chosen tile cells, zones per group and the
+ * measured ms per step.  Synchronizes. */
+int imexds_autotune(imexds_ctx *ctx, int32_t steps_per_trial, int32_t *tile_cells,
+                    int32_t *zones_per_group, double *ms_per_step);
+
+/* Sizes of the batch (host, any may be NULL). */
+int imexds_get_sizes(imexds_ctx *ctx, int32_t *n_problems, int32_t *n_iface, int64_t *n_slots);
+
+/* Device-time of the most recent imexds_step / imexds_step_per_problem call
+ * measured with HIP events on the context's stream, and the average
+ * duration of one bulk-sweep launch inside it (ms, host).  Synchronizes. */
+int imexds_last_timing(imexds_ctx *ctx, double *total_ms, double *bulk_ms_per_launch);
+
+/* Enables HIP-event timing of the bulk-sweep kernel inside imexds_step
+ * (adds events around each bulk launch; graphs are not used while on). */
+int imexds_time_bulk(imexds_ctx *ctx, int32_t on);
+
+void imexds_destroy(imexds_ctx *ctx);
+const char *imexds_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IMEXDS_H */

@@ -94,10 +94,58 @@ static double or_rho_of_p(const or_material *M, int ph, double p) {
   return ph == OR_VAP ? p / M->a2v : M->rhol0 + (p - M->p0) / M->a2l;
 }
 
+/* Natural logarithm of a positive finite double.  Argument reduction
+ * x = 2^e m with m in [sqrt(1/2), sqrt(2)], then ln m = 2 atanh(f) with
+ * f = (m-1)/(m+1), the atanh series 2 f (1 + f^2/3 + f^4/5 + ... + f^24/25)
+ * by Horner's rule, and e ln 2 with ln 2 split into a head with trailing
+ * zero bits and a tail (as in fdlibm).  Written as plain IEEE double
+ * operations in a fixed order, so every IEEE machine gives the same bits;
+ * accurate to a few ulp (checked against the C library in the tests). */
+double oracle_log(double x) {
+  if (!(x > 0.0)) return x == 0.0 ? -INFINITY : NAN;
+  if (!isfinite(x)) return x;
+  uint64_t b;
+  memcpy(&b, &x, 8);
+  int ex = (int)((b >> 52) & 0x7ff);
+  int e;
+  if (ex == 0) { /* subnormal: scale by 2^54 first */
+    double y = x * 18014398509481984.0;
+    memcpy(&b, &y, 8);
+    e = (int)((b >> 52) & 0x7ff) - 1023 - 54;
+  } else {
+    e = ex - 1023;
+  }
+  b = (b & 0x000fffffffffffffULL) | 0x3ff0000000000000ULL;
+  double m;
+  memcpy(&m, &b, 8);
+  if (m > 1.4142135623730951) {
+    m = 0.5 * m;
+    e += 1;
+  }
+  double f = (m - 1.0) / (m + 1.0);
+  double s = f * f;
+  double p = 1.0 / 25.0;
+  p = p * s + 1.0 / 23.0;
+  p = p * s + 1.0 / 21.0;
+  p = p * s + 1.0 / 19.0;
+  p = p * s + 1.0 / 17.0;
+  p = p * s + 1.0 / 15.0;
+  p = p * s + 1.0 / 13.0;
+  p = p * s + 1.0 / 11.0;
+  p = p * s + 1.0 / 9.0;
+  p = p * s + 1.0 / 7.0;
+  p = p * s + 1.0 / 5.0;
+  p = p * s + 1.0 / 3.0;
+  p = p * s + 1.0;
+  double r = (2.0 * f) * p;
+  double de = (double)e;
+  return de * 0x1.62e42feep-1 + (de * 0x1.a39ef35793c76p-33 + r);
+}
+
 /* Gibbs energy up to the common constant fixed by g_L(p0) = g_V(p0). */
 static double or_gibbs(const or_material *M, int ph, double rho) {
-  if (ph == OR_VAP) return M->a2v * log(rho / (M->p0 / M->a2v));
-  return M->a2l * log(rho / M->rhol0);
+  if (ph == OR_VAP) return M->a2v * oracle_log(rho / (M->p0 / M->a2v));
+  return M->a2l * oracle_log(rho / M->rhol0);
 }
 
 /* ------------------------------------------------------------------ */
@@ -165,7 +213,7 @@ static int or_wave(const or_material *M, int ph, double rhoK, double pK, double 
     *f = a * (r - rhoK) / g;
     *df = (r + rhoK) / ((2.0 * a * r) * g);
   } else { /* rarefaction: integral of v/a dp = a ln(rho_star / rho_K) */
-    *f = a * log(r / rhoK);
+    *f = a * oracle_log(r / rhoK);
     *df = 1.0 / (r * a);
   }
   return 1;

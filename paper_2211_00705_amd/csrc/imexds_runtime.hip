@@ -1,0 +1,905 @@
+// imexds_runtime.hip -- host runtime behind the C ABI of include/imexds.h.
+//
+// The context owns every device buffer: ping-pong state arrays (rho, rho u)
+// in structure-of-arrays FP64 layout over the flat slot index of all problems,
+// ping-pong interface records, per-problem scalars (t, dt, status, CFL
+// accumulator) and the tile table of the bulk sweep.  Work goes to two
+// streams owned by the context, both at the default priority: the bulk sweep
+// and the per-problem bookkeeping on the main one, the implicit zones on the
+// second, joined by events each step.  Repeated steps are captured once into
+// a HIP graph (an even number of steps, so the ping-pong parity returns) and
+// replayed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/imexds.h"
+#include "imexds_kernels.hpp"
+
+using imexds::StepArgs;
+
+namespace {
+
+template <class T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+};
+
+struct Snapshot {
+  double *rho = nullptr, *mom = nullptr;
+  int *home = nullptr, *warm = nullptr, *status = nullptr, *clipped = nullptr;
+  double *hl = nullptr, *pw = nullptr, *dt = nullptr, *t = nullptr;
+  long long* steps = nullptr;
+  unsigned long long* stats = nullptr;
+  int parity = 0;
+};
+
+}  // namespace
+
+struct imexds_ctx {
+  int device = 0;
+  hipStream_t user = nullptr;  // the caller's stream
+  hipStream_t ms = nullptr;    // main stream of the context
+  hipStream_t zs = nullptr;    // zone stream of the context
+  std::vector<hipEvent_t> fork_ev, join_ev;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
+  std::vector<hipEvent_t> bulk_ev;  // pairs around bulk launches when timing
+  imexds::Mat mat{};
+  imexds::Par par{};
+  int P = 0, NIF = 0;
+  long long S = 0;
+  std::vector<long long> h_slot_off;
+  std::vector<int> h_n_cells, h_phase_first, h_iface_off, h_home0, h_iface_prob, h_iface_local;
+  std::vector<double> h_h, h_x_left, h_hl0;
+  // static layout on the device
+  long long* d_slot_off = nullptr;
+  double* d_h = nullptr;
+  int *d_phase_first = nullptr, *d_iface_off = nullptr, *d_iface_prob = nullptr,
+      *d_iface_local = nullptr;
+  int *d_tile_prob = nullptr, *d_tile_start = nullptr, *d_tile_len = nullptr;
+  int n_tiles = 0, tile_cells = 1024, zones_per_group = 16, graph_steps = 8;
+  std::vector<int> h_tile_off;  // [P+1] tiles of each problem
+  // evolving state
+  double *d_rho[2] = {nullptr, nullptr}, *d_mom[2] = {nullptr, nullptr};
+  int* d_home[2] = {nullptr, nullptr};
+  double* d_hl[2] = {nullptr, nullptr};
+  double* d_pw[2] = {nullptr, nullptr};
+  int* d_warm[2] = {nullptr, nullptr};
+  double *d_dt = nullptr, *d_t = nullptr;
+  int *d_status = nullptr, *d_clipped = nullptr, *d_fail = nullptr;
+  long long* d_steps = nullptr;
+  unsigned long long* d_S = nullptr;
+  unsigned long long* d_stats = nullptr;  // pseudo, merges, lmax
+  int *d_log_count = nullptr, *d_log_flags = nullptr, *d_log_zlo = nullptr, *d_log_row = nullptr;
+  int log_max = 0;
+  int parity = 0;
+  bool has_state = false;
+  hipGraphExec_t gexec = nullptr;
+  bool time_bulk = false;
+  int bulk_launches = 0;
+  double last_total_ms = 0.0, last_bulk_ms = 0.0;
+  bool timed = false;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+thread_local char g_err[512];
+
+int hip_fail(hipError_t e, const char* what) {
+  snprintf(g_err, sizeof(g_err), "%s: %s", what, hipGetErrorString(e));
+  return IMEXDS_ERR_HIP;
+}
+
+#define CK(expr)                                  \
+  do {                                            \
+    hipError_t e_ = (expr);                       \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr); \
+  } while (0)
+
+template <class T>
+int dalloc(imexds_ctx* c, T** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  hipError_t e = hipMalloc((void**)p, n * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    snprintf(g_err, sizeof(g_err), "hipMalloc of %zu bytes failed", n * sizeof(T));
+    return IMEXDS_ERR_OOM;
+  }
+  c->allocs.push_back((void*)*p);
+  return 0;
+}
+
+#define AL(ptr, n)                          \
+  do {                                      \
+    int r_ = dalloc(c, &(ptr), (size_t)(n)); \
+    if (r_) return r_;                      \
+  } while (0)
+
+void drop_graph(imexds_ctx* c) {
+  if (c->gexec) {
+    (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+  }
+}
+
+StepArgs make_args(imexds_ctx* c, int parity, bool init) {
+  StepArgs A;
+  memset(&A, 0, sizeof(A));
+  A.mat = c->mat;
+  A.par = c->par;
+  A.slot_off = c->d_slot_off;
+  A.h = c->d_h;
+  A.phase_first = c->d_phase_first;
+  A.iface_off = c->d_iface_off;
+  A.iface_prob = c->d_iface_prob;
+  A.iface_local = c->d_iface_local;
+  A.tile_prob = c->d_tile_prob;
+  A.tile_start = c->d_tile_start;
+  A.tile_len = c->d_tile_len;
+  int a = parity, b = init ? parity : parity ^ 1;
+  A.rho0 = c->d_rho[a];
+  A.mom0 = c->d_mom[a];
+  A.rho1 = c->d_rho[b];
+  A.mom1 = c->d_mom[b];
+  A.rec_home0 = c->d_home[a];
+  A.rec_hl0 = c->d_hl[a];
+  A.rec_pw0 = c->d_pw[a];
+  A.rec_warm0 = c->d_warm[a];
+  A.rec_home1 = c->d_home[b];
+  A.rec_hl1 = c->d_hl[b];
+  A.rec_pw1 = c->d_pw[b];
+  A.rec_warm1 = c->d_warm[b];
+  A.dt = c->d_dt;
+  A.t = c->d_t;
+  A.status = c->d_status;
+  A.clipped = c->d_clipped;
+  A.steps = c->d_steps;
+  A.S_acc = c->d_S;
+  A.fail_acc = c->d_fail;
+  if (c->log_max > 0) {
+    A.log_count = c->d_log_count;
+    A.log_flags = c->d_log_flags;
+    A.log_zlo = c->d_log_zlo;
+    A.log_row = c->d_log_row;
+    A.log_max = c->log_max;
+  }
+  A.n_iface = c->NIF;
+  A.st_pseudo = c->d_stats;
+  A.st_merges = c->d_stats + 1;
+  A.st_lmax = c->d_stats + 2;
+  A.zones_per_group = c->zones_per_group;
+  return A;
+}
+
+int build_tiles(imexds_ctx* c, int tile_cells) {
+  std::vector<int> tp, ts, tl;
+  c->h_tile_off.assign(c->P + 1, 0);
+  for (int p = 0; p < c->P; ++p) {
+    int ns = (int)(c->h_slot_off[p + 1] - c->h_slot_off[p]);
+    for (int s = 0; s < ns; s += tile_cells) {
+      tp.push_back(p);
+      ts.push_back(s);
+      tl.push_back(std::min(tile_cells, ns - s));
+    }
+    c->h_tile_off[p + 1] = (int)tp.size();
+  }
+  int n = (int)tp.size();
+  int *np = nullptr, *nst = nullptr, *nl = nullptr;
+  if (n > 0) {
+    CK(hipMalloc((void**)&np, sizeof(int) * n));
+    CK(hipMalloc((void**)&nst, sizeof(int) * n));
+    CK(hipMalloc((void**)&nl, sizeof(int) * n));
+    CK(hipMemcpy(np, tp.data(), sizeof(int) * n, hipMemcpyHostToDevice));
+    CK(hipMemcpy(nst, ts.data(), sizeof(int) * n, hipMemcpyHostToDevice));
+    CK(hipMemcpy(nl, tl.data(), sizeof(int) * n, hipMemcpyHostToDevice));
+  }
+  if (c->d_tile_prob) {
+    (void)hipFree(c->d_tile_prob);
+    (void)hipFree(c->d_tile_start);
+    (void)hipFree(c->d_tile_len);
+  }
+  c->d_tile_prob = np;
+  c->d_tile_start = nst;
+  c->d_tile_len = nl;
+  c->n_tiles = n;
+  c->tile_cells = tile_cells;
+  return 0;
+}
+
+// One physical step of every problem, enqueued on c->ms (zones on c->zs).
+int enqueue_step(imexds_ctx* c, int ev_slot) {
+  StepArgs A = make_args(c, c->parity, false);
+  hipEvent_t ef = c->fork_ev[ev_slot], ej = c->join_ev[ev_slot];
+  if (c->NIF > 0) {
+    CK(hipEventRecord(ef, c->ms));
+    CK(hipStreamWaitEvent(c->zs, ef, 0));
+    CK(imexds::launch_zone(A, 0, c->NIF, c->zs));
+  }
+  if (c->time_bulk) {
+    size_t need = 2 * (size_t)(c->bulk_launches + 1);
+    while (c->bulk_ev.size() < need) {
+      hipEvent_t e;
+      CK(hipEventCreate(&e));
+      c->bulk_ev.push_back(e);
+    }
+    CK(hipEventRecord(c->bulk_ev[2 * c->bulk_launches], c->ms));
+  }
+  CK(imexds::launch_bulk(A, c->tile_cells, 0, c->n_tiles, c->ms));
+  if (c->time_bulk) {
+    CK(hipEventRecord(c->bulk_ev[2 * c->bulk_launches + 1], c->ms));
+    c->bulk_launches++;
+  }
+  if (c->NIF > 0) {
+    CK(hipEventRecord(ej, c->zs));
+    CK(hipStreamWaitEvent(c->ms, ej, 0));
+  }
+  CK(imexds::launch_finalize(A, 0, c->P, 0, 1, c->ms));
+  c->parity ^= 1;
+  return 0;
+}
+
+int ensure_events(imexds_ctx* c, size_t n) {
+  while (c->fork_ev.size() < n) {
+    hipEvent_t a, b;
+    CK(hipEventCreateWithFlags(&a, hipEventDisableTiming));
+    CK(hipEventCreateWithFlags(&b, hipEventDisableTiming));
+    c->fork_ev.push_back(a);
+    c->join_ev.push_back(b);
+  }
+  return 0;
+}
+
+int capture_graph(imexds_ctx* c) {
+  drop_graph(c);
+  int G = c->graph_steps;
+  int r = ensure_events(c, (size_t)G);
+  if (r) return r;
+  int par0 = c->parity;
+  CK(hipStreamBeginCapture(c->ms, hipStreamCaptureModeThreadLocal));
+  for (int i = 0; i < G; ++i) {
+    r = enqueue_step(c, i);
+    if (r) {
+      hipGraph_t g;
+      (void)hipStreamEndCapture(c->ms, &g);
+      if (g) (void)hipGraphDestroy(g);
+      c->parity = par0;
+      return r;
+    }
+  }
+  hipGraph_t g = nullptr;
+  CK(hipStreamEndCapture(c->ms, &g));
+  c->parity = par0;  // capturing does not run anything
+  hipError_t e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    c->gexec = nullptr;
+    return hip_fail(e, "hipGraphInstantiate");
+  }
+  return 0;
+}
+
+int begin_call(imexds_ctx* c) {
+  CK(hipSetDevice(c->device));
+  CK(hipEventRecord(c->ev_in, c->user));
+  CK(hipStreamWaitEvent(c->ms, c->ev_in, 0));
+  return 0;
+}
+
+int end_call(imexds_ctx* c) {
+  CK(hipEventRecord(c->ev_out, c->ms));
+  CK(hipStreamWaitEvent(c->user, c->ev_out, 0));
+  return 0;
+}
+
+int init_dt(imexds_ctx* c) {
+  StepArgs A = make_args(c, c->parity, true);
+  CK(imexds::launch_cfl(A, 0, c->n_tiles, c->ms));
+  CK(imexds::launch_finalize(A, 0, c->P, 1, 0, c->ms));
+  return 0;
+}
+
+int snap_take(imexds_ctx* c, Snapshot& s) {
+  size_t S = (size_t)std::max<long long>(c->S, 1), N = (size_t)std::max(c->NIF, 1),
+         P = (size_t)std::max(c->P, 1);
+  CK(hipMalloc((void**)&s.rho, S * 8));
+  CK(hipMalloc((void**)&s.mom, S * 8));
+  CK(hipMalloc((void**)&s.home, N * 4));
+  CK(hipMalloc((void**)&s.warm, N * 4));
+  CK(hipMalloc((void**)&s.hl, N * 8));
+  CK(hipMalloc((void**)&s.pw, 2 * N * 8));
+  CK(hipMalloc((void**)&s.dt, P * 8));
+  CK(hipMalloc((void**)&s.t, P * 8));
+  CK(hipMalloc((void**)&s.status, P * 4));
+  CK(hipMalloc((void**)&s.clipped, P * 4));
+  CK(hipMalloc((void**)&s.steps, P * 8));
+  CK(hipMalloc((void**)&s.stats, 3 * 8));
+  int a = c->parity;
+  s.parity = a;
+  hipStream_t m = c->ms;
+  CK(hipMemcpyAsync(s.rho, c->d_rho[a], S * 8, hipMemcpyDeviceToDevice, m));
+  CK(hipMemcpyAsync(s.mom, c->d_mom[a], S * 8, hipMemcpyDeviceToDevice, m));
+  CK(hipMemcpyAsync(s.home, c->d_home[a], N * 4, hipMemcpyDeviceToDevice, m));
+  CK(hipMemcpyAsync(s.warm, c->d_warm[a], N * 4, hipMemcpyDeviceToDevice, m));
+  CK(hipMemcpyAsync(s.hl, c->d_hl[a], N * 8, hipMemcpyDeviceToDevice, m));
+  CK(hipMemcpyAsync(s.pw, c->d_pw[a], 2 * N * 8, hipMemcpyDeviceToDevice, m));
+  CK(hipMemcpyAsync(s.dt, c->d_dt, P * 8, hipMemcpyDeviceToDevice, m));
+  CK(hipMemcpyAsync(s.t, c->d_t, P * 8, hipMemcpyDeviceToDevice, m));
+  CK(hipMemcpyAsync(s.status, c->d_status, P * 4, hipMemcpyDeviceToDevice, m));
+  CK(hipMemcpyAsync(s.clipped, c->d_clipped, P * 4, hipMemcpyDeviceToDevice, m));
+  CK(hipMemcpyAsync(s.steps, c->d_steps, P * 8, hipMemcpyDeviceToDevice, m));
+  CK(hipMemcpyAsync(s.stats, c->d_stats, 3 * 8, hipMemcpyDeviceToDevice, m));
+  return 0;
+}
+
+int snap_restore(imexds_ctx* c, Snapshot& s) {
+  size_t S = (size_t)std::max<long long>(c->S, 1), N = (size_t)std::max(c->NIF, 1),
+         P = (size_t)std::max(c->P, 1);
+  int a = s.parity;
+  c->parity = a;
+  hipStream_t m = c->ms;
+  CK(hipMemcpyAsync(c->d_rho[a], s.rho, S * 8, hipMemcpyDeviceToDevice, m));
+  CK(hipMemcpyAsync(c->d_mom[a], s.mom, S * 8, hipMemcpyDeviceToDevice, m));
+  CK(hipMemcpyAsync(c->d_home[a], s.home, N * 4, hipMemcpyDeviceToDevice, m));
+  CK(hipMemcpyAsync(c->d_warm[a], s.warm, N * 4, hipMemcpyDeviceToDevice, m));
+  CK(hipMemcpyAsync(c->d_hl[a], s.hl, N * 8, hipMemcpyDeviceToDevice, m));
+  CK(hipMemcpyAsync(c->d_pw[a], s.pw, 2 * N * 8, hipMemcpyDeviceToDevice, m));
+  CK(hipMemcpyAsync(c->d_dt, s.dt, P * 8, hipMemcpyDeviceToDevice, m));
+  CK(hipMemcpyAsync(c->d_t, s.t, P * 8, hipMemcpyDeviceToDevice, m));
+  CK(hipMemcpyAsync(c->d_status, s.status, P * 4, hipMemcpyDeviceToDevice, m));
+  CK(hipMemcpyAsync(c->d_clipped, s.clipped, P * 4, hipMemcpyDeviceToDevice, m));
+  CK(hipMemcpyAsync(c->d_steps, s.steps, P * 8, hipMemcpyDeviceToDevice, m));
+  CK(hipMemcpyAsync(c->d_stats, s.stats, 3 * 8, hipMemcpyDeviceToDevice, m));
+  CK(hipStreamSynchronize(m));
+  return 0;
+}
+
+void snap_free(Snapshot& s) {
+  void* ps[] = {s.rho, s.mom, s.home, s.warm, s.status, s.clipped, s.hl,
+                s.pw,  s.dt,  s.t,    s.steps, s.stats};
+  for (void* p : ps)
+    if (p) (void)hipFree(p);
+  s = Snapshot();
+}
+
+int steps_impl(imexds_ctx* c, int n) {
+  int r;
+  if (c->time_bulk || c->graph_steps <= 0) {
+    r = ensure_events(c, 1);
+    if (r) return r;
+    for (int i = 0; i < n; ++i)
+      if ((r = enqueue_step(c, 0))) return r;
+    return 0;
+  }
+  int done = 0;
+  r = ensure_events(c, 1);
+  if (r) return r;
+  if (c->parity != 0 && n > 0) {  // graphs start at parity 0
+    if ((r = enqueue_step(c, 0))) return r;
+    ++done;
+  }
+  int G = c->graph_steps;
+  if (n - done >= G) {
+    if (!c->gexec && (r = capture_graph(c))) return r;
+    while (n - done >= G) {
+      CK(hipGraphLaunch(c->gexec, c->ms));
+      done += G;
+    }
+  }
+  while (done < n) {
+    if ((r = enqueue_step(c, 0))) return r;
+    ++done;
+  }
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* imexds_strerror(int code) {
+  switch (code) {
+    case IMEXDS_OK: return "ok";
+    case IMEXDS_ERR_INVALID_ARG: return "invalid argument";
+    case IMEXDS_ERR_OOM: return "out of device memory";
+    case IMEXDS_ERR_HIP: return g_err[0] ? g_err : "HIP runtime error";
+    case IMEXDS_ERR_NO_STATE: return "no state loaded (call imexds_set_state first)";
+    case IMEXDS_ERR_UNSUPPORTED: return "unsupported configuration";
+    default: return "unknown error";
+  }
+}
+
+void imexds_destroy(imexds_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->ms) (void)hipStreamSynchronize(c->ms);
+  if (c->zs) (void)hipStreamSynchronize(c->zs);
+  drop_graph(c);
+  for (void* p : c->allocs) (void)hipFree(p);
+  if (c->d_tile_prob) (void)hipFree(c->d_tile_prob);
+  if (c->d_tile_start) (void)hipFree(c->d_tile_start);
+  if (c->d_tile_len) (void)hipFree(c->d_tile_len);
+  if (c->d_log_count) (void)hipFree(c->d_log_count);
+  if (c->d_log_flags) (void)hipFree(c->d_log_flags);
+  if (c->d_log_zlo) (void)hipFree(c->d_log_zlo);
+  for (auto e : c->fork_ev) (void)hipEventDestroy(e);
+  for (auto e : c->join_ev) (void)hipEventDestroy(e);
+  for (auto e : c->bulk_ev) (void)hipEventDestroy(e);
+  hipEvent_t es[] = {c->ev_in, c->ev_out, c->ev_t0, c->ev_t1};
+  for (auto e : es)
+    if (e) (void)hipEventDestroy(e);
+  if (c->ms) (void)hipStreamDestroy(c->ms);
+  if (c->zs) (void)hipStreamDestroy(c->zs);
+  delete c;
+}
+
+static int create_impl(imexds_ctx* c, const imexds_material* mat, const imexds_params* par,
+                       const imexds_batch* b) {
+  const int P = b->n_problems;
+  if (P < 0) return IMEXDS_ERR_INVALID_ARG;
+  if (!(par->cfl > 0.0) || par->zone_half < 1 || par->zone_half > 3 || !(par->theta_nb > 0.0) ||
+      par->lmax < 1 || par->newton_maxit < 1 || !(par->newton_rtol > 0.0) ||
+      (par->tol_mode != IMEXDS_TOL_PAPER && par->tol_mode != IMEXDS_TOL_REL) ||
+      par->bc_left < 0 || par->bc_left > 1 || par->bc_right < 0 || par->bc_right > 1 ||
+      !(par->alpha_floor >= 0.0) || !(par->merge_safety >= 0.0) || !(par->t_end > 0.0))
+    return IMEXDS_ERR_INVALID_ARG;
+  if (!(mat->a2_vap > 0.0) || !(mat->a2_liq > 0.0) || !(mat->p_sat > 0.0) ||
+      !(mat->rho_liq_sat > 0.0) || !(mat->tau >= 0.0))
+    return IMEXDS_ERR_INVALID_ARG;
+  if (P > 0 && (!b->n_cells || !b->h || !b->x_left || !b->phase_first || !b->iface_off))
+    return IMEXDS_ERR_INVALID_ARG;
+  c->P = P;
+  c->h_n_cells.assign(P, 0);
+  c->h_h.assign(P, 0.0);
+  c->h_x_left.assign(P, 0.0);
+  c->h_phase_first.assign(P, 0);
+  c->h_iface_off.assign(P + 1, 0);
+  c->h_slot_off.assign(P + 1, 0);
+  if (P > 0 && b->iface_off[0] != 0) return IMEXDS_ERR_INVALID_ARG;
+  for (int p = 0; p < P; ++p) {
+    int n = b->n_cells[p];
+    int nif = b->iface_off[p + 1] - b->iface_off[p];
+    if (n < 1 || nif < 0 || nif > imexds::MAX_IF_PER_PROB || !(b->h[p] > 0.0) ||
+        (b->phase_first[p] != 0 && b->phase_first[p] != 1))
+      return IMEXDS_ERR_INVALID_ARG;
+    c->h_n_cells[p] = n;
+    c->h_h[p] = b->h[p];
+    c->h_x_left[p] = b->x_left[p];
+    c->h_phase_first[p] = b->phase_first[p];
+    c->h_iface_off[p + 1] = b->iface_off[p + 1];
+    c->h_slot_off[p + 1] = c->h_slot_off[p] + n + nif;
+  }
+  c->NIF = P > 0 ? b->iface_off[P] : 0;
+  c->S = c->h_slot_off[P];
+  if (c->NIF > 0 && (!b->home || !b->hl)) return IMEXDS_ERR_INVALID_ARG;
+  c->h_home0.assign(b->home, b->home + c->NIF);
+  c->h_hl0.assign(b->hl, b->hl + c->NIF);
+  c->h_iface_prob.assign(c->NIF, 0);
+  c->h_iface_local.assign(c->NIF, 0);
+  for (int p = 0; p < P; ++p) {
+    int prev = -1;
+    for (int k = b->iface_off[p]; k < b->iface_off[p + 1]; ++k) {
+      int j = b->home[k];
+      double hl = b->hl[k];
+      if (j <= prev || j >= c->h_n_cells[p] || !(hl >= 0.0) || !(hl <= b->h[p]))
+        return IMEXDS_ERR_INVALID_ARG;
+      prev = j;
+      c->h_iface_prob[k] = p;
+      c->h_iface_local[k] = k - b->iface_off[p];
+    }
+  }
+  c->mat.a2v = mat->a2_vap;
+  c->mat.a2l = mat->a2_liq;
+  c->mat.p0 = mat->p_sat;
+  c->mat.rhol0 = mat->rho_liq_sat;
+  c->mat.tau = mat->tau;
+  c->mat.av = std::sqrt(mat->a2_vap);
+  c->mat.al = std::sqrt(mat->a2_liq);
+  c->mat.rhov0 = mat->p_sat / mat->a2_vap;
+  c->par.cfl = par->cfl;
+  c->par.theta_nb = par->theta_nb;
+  c->par.tol_nb = par->tol_nb;
+  c->par.tol_tiny = par->tol_tiny;
+  c->par.tol_rel = par->tol_rel;
+  c->par.alpha_floor = par->alpha_floor;
+  c->par.merge_safety = par->merge_safety;
+  c->par.newton_rtol = par->newton_rtol;
+  c->par.t_end = par->t_end;
+  c->par.zone_half = par->zone_half;
+  c->par.tol_mode = par->tol_mode;
+  c->par.lmax = par->lmax;
+  c->par.bc_left = par->bc_left;
+  c->par.bc_right = par->bc_right;
+  c->par.newton_maxit = par->newton_maxit;
+
+  CK(hipGetDevice(&c->device));
+  CK(hipStreamCreateWithFlags(&c->ms, hipStreamNonBlocking));
+  CK(hipStreamCreateWithFlags(&c->zs, hipStreamNonBlocking));
+  CK(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
+  CK(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
+  CK(hipEventCreate(&c->ev_t0));
+  CK(hipEventCreate(&c->ev_t1));
+  int r = ensure_events(c, 1);
+  if (r) return r;
+
+  size_t Pn = (size_t)P, N = (size_t)c->NIF, S = (size_t)c->S;
+  AL(c->d_slot_off, Pn + 1);
+  AL(c->d_h, Pn);
+  AL(c->d_phase_first, Pn);
+  AL(c->d_iface_off, Pn + 1);
+  AL(c->d_iface_prob, N);
+  AL(c->d_iface_local, N);
+  for (int a = 0; a < 2; ++a) {
+    AL(c->d_rho[a], S);
+    AL(c->d_mom[a], S);
+    AL(c->d_home[a], N);
+    AL(c->d_hl[a], N);
+    AL(c->d_pw[a], 2 * N);
+    AL(c->d_warm[a], N);
+  }
+  AL(c->d_dt, Pn);
+  AL(c->d_t, Pn);
+  AL(c->d_status, Pn);
+  AL(c->d_clipped, Pn);
+  AL(c->d_fail, Pn);
+  AL(c->d_steps, Pn);
+  AL(c->d_S, Pn);
+  AL(c->d_stats, 3);
+  AL(c->d_log_row, 1);
+  CK(hipMemcpy(c->d_slot_off, c->h_slot_off.data(), (Pn + 1) * 8, hipMemcpyHostToDevice));
+  if (P > 0) {
+    CK(hipMemcpy(c->d_h, c->h_h.data(), Pn * 8, hipMemcpyHostToDevice));
+    CK(hipMemcpy(c->d_phase_first, c->h_phase_first.data(), Pn * 4, hipMemcpyHostToDevice));
+  }
+  CK(hipMemcpy(c->d_iface_off, c->h_iface_off.data(), (Pn + 1) * 4, hipMemcpyHostToDevice));
+  if (N > 0) {
+    CK(hipMemcpy(c->d_iface_prob, c->h_iface_prob.data(), N * 4, hipMemcpyHostToDevice));
+    CK(hipMemcpy(c->d_iface_local, c->h_iface_local.data(), N * 4, hipMemcpyHostToDevice));
+  }
+  CK(hipMemset(c->d_log_row, 0, 4));
+  return build_tiles(c, c->tile_cells);
+}
+
+int imexds_create(imexds_ctx** out, const imexds_material* mat, const imexds_params* par,
+                  const imexds_batch* batch, void* hip_stream) {
+  if (!out) return IMEXDS_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!mat || !par || !batch) return IMEXDS_ERR_INVALID_ARG;
+  imexds_ctx* c = new (std::nothrow) imexds_ctx();
+  if (!c) return IMEXDS_ERR_OOM;
+  c->user = (hipStream_t)hip_stream;
+  int r = create_impl(c, mat, par, batch);
+  if (r) {
+    imexds_destroy(c);
+    return r;
+  }
+  *out = c;
+  return 0;
+}
+
+int imexds_set_state(imexds_ctx* c, const double* rho, const double* mom) {
+  if (!c || (c->S > 0 && (!rho || !mom))) return IMEXDS_ERR_INVALID_ARG;
+  int r = begin_call(c);
+  if (r) return r;
+  size_t S = (size_t)c->S, N = (size_t)c->NIF, P = (size_t)c->P;
+  c->parity = 0;
+  hipStream_t m = c->ms;
+  if (S) {
+    CK(hipMemcpyAsync(c->d_rho[0], rho, S * 8, hipMemcpyDeviceToDevice, m));
+    CK(hipMemcpyAsync(c->d_mom[0], mom, S * 8, hipMemcpyDeviceToDevice, m));
+  }
+  if (N) {
+    CK(hipMemcpyAsync(c->d_home[0], c->h_home0.data(), N * 4, hipMemcpyHostToDevice, m));
+    CK(hipMemcpyAsync(c->d_hl[0], c->h_hl0.data(), N * 8, hipMemcpyHostToDevice, m));
+    CK(hipMemsetAsync(c->d_pw[0], 0, 2 * N * 8, m));
+    CK(hipMemsetAsync(c->d_warm[0], 0, N * 4, m));
+  }
+  if (P) {
+    CK(hipMemsetAsync(c->d_t, 0, P * 8, m));
+    CK(hipMemsetAsync(c->d_dt, 0, P * 8, m));
+    CK(hipMemsetAsync(c->d_status, 0, P * 4, m));
+    CK(hipMemsetAsync(c->d_clipped, 0, P * 4, m));
+    CK(hipMemsetAsync(c->d_fail, 0, P * 4, m));
+    CK(hipMemsetAsync(c->d_steps, 0, P * 8, m));
+    CK(hipMemsetAsync(c->d_S, 0, P * 8, m));
+  }
+  CK(hipMemsetAsync(c->d_stats, 0, 3 * 8, m));
+  CK(hipMemsetAsync(c->d_log_row, 0, 4, m));
+  // host->device copies above read pageable host memory: finish them here
+  CK(hipStreamSynchronize(m));
+  if (P) {
+    r = init_dt(c);
+    if (r) return r;
+  }
+  c->has_state = true;
+  return end_call(c);
+}
+
+int imexds_step(imexds_ctx* c, int32_t n_steps) {
+  if (!c || n_steps < 0) return IMEXDS_ERR_INVALID_ARG;
+  if (!c->has_state) return IMEXDS_ERR_NO_STATE;
+  int r = begin_call(c);
+  if (r) return r;
+  c->bulk_launches = 0;
+  CK(hipEventRecord(c->ev_t0, c->ms));
+  if (c->P > 0 && (r = steps_impl(c, n_steps))) return r;
+  CK(hipEventRecord(c->ev_t1, c->ms));
+  c->timed = true;
+  return end_call(c);
+}
+
+int imexds_step_per_problem(imexds_ctx* c, int32_t n_steps) {
+  if (!c || n_steps < 0) return IMEXDS_ERR_INVALID_ARG;
+  if (!c->has_state) return IMEXDS_ERR_NO_STATE;
+  int r = begin_call(c);
+  if (r) return r;
+  c->bulk_launches = 0;
+  CK(hipEventRecord(c->ev_t0, c->ms));
+  for (int n = 0; n < n_steps; ++n) {
+    StepArgs A = make_args(c, c->parity, false);
+    for (int p = 0; p < c->P; ++p) {
+      int k0 = c->h_iface_off[p], k1 = c->h_iface_off[p + 1];
+      if (k1 > k0) CK(imexds::launch_zone(A, k0, k1, c->ms));
+      int t0 = c->h_tile_off[p], t1 = c->h_tile_off[p + 1];
+      CK(imexds::launch_bulk(A, c->tile_cells, t0, t1 - t0, c->ms));
+      CK(imexds::launch_finalize(A, p, p + 1, 0, p == c->P - 1, c->ms));
+    }
+    c->parity ^= 1;
+  }
+  CK(hipEventRecord(c->ev_t1, c->ms));
+  c->timed = true;
+  return end_call(c);
+}
+
+int imexds_run(imexds_ctx* c, int32_t max_steps, int32_t check_every, int32_t* steps_done) {
+  if (!c || max_steps < 0 || check_every < 1) return IMEXDS_ERR_INVALID_ARG;
+  if (!c->has_state) return IMEXDS_ERR_NO_STATE;
+  int r = begin_call(c);
+  if (r) return r;
+  int done = 0;
+  std::vector<double> dt(c->P);
+  CK(hipEventRecord(c->ev_t0, c->ms));
+  while (done < max_steps && c->P > 0) {
+    CK(hipMemcpyAsync(dt.data(), c->d_dt, sizeof(double) * c->P, hipMemcpyDeviceToHost, c->ms));
+    CK(hipStreamSynchronize(c->ms));
+    bool any = false;
+    for (double d : dt) any = any || d > 0.0;
+    if (!any) break;
+    int n = std::min(check_every, max_steps - done);
+    if ((r = steps_impl(c, n))) return r;
+    done += n;
+  }
+  CK(hipEventRecord(c->ev_t1, c->ms));
+  c->timed = true;
+  if (steps_done) *steps_done = done;
+  return end_call(c);
+}
+
+int imexds_get_state(imexds_ctx* c, double* rho, double* mom) {
+  if (!c || (c->S > 0 && (!rho || !mom))) return IMEXDS_ERR_INVALID_ARG;
+  if (!c->has_state) return IMEXDS_ERR_NO_STATE;
+  int r = begin_call(c);
+  if (r) return r;
+  size_t S = (size_t)c->S;
+  if (S) {
+    CK(hipMemcpyAsync(rho, c->d_rho[c->parity], S * 8, hipMemcpyDeviceToDevice, c->ms));
+    CK(hipMemcpyAsync(mom, c->d_mom[c->parity], S * 8, hipMemcpyDeviceToDevice, c->ms));
+  }
+  return end_call(c);
+}
+
+int imexds_get_interfaces(imexds_ctx* c, int32_t* home, double* hl, double* x_iface) {
+  if (!c) return IMEXDS_ERR_INVALID_ARG;
+  if (!c->has_state) return IMEXDS_ERR_NO_STATE;
+  CK(hipSetDevice(c->device));
+  size_t N = (size_t)c->NIF;
+  if (!N) return 0;
+  std::vector<int> hh(N);
+  std::vector<double> ll(N);
+  CK(hipMemcpyAsync(hh.data(), c->d_home[c->parity], N * 4, hipMemcpyDeviceToHost, c->ms));
+  CK(hipMemcpyAsync(ll.data(), c->d_hl[c->parity], N * 8, hipMemcpyDeviceToHost, c->ms));
+  CK(hipStreamSynchronize(c->ms));
+  for (size_t k = 0; k < N; ++k) {
+    if (home) home[k] = hh[k];
+    if (hl) hl[k] = ll[k];
+    if (x_iface) {
+      int p = c->h_iface_prob[k];
+      x_iface[k] = c->h_x_left[p] + hh[k] * c->h_h[p] + ll[k];
+    }
+  }
+  return 0;
+}
+
+int imexds_get_problems(imexds_ctx* c, double* t, int32_t* status, int64_t* steps) {
+  if (!c) return IMEXDS_ERR_INVALID_ARG;
+  if (!c->has_state) return IMEXDS_ERR_NO_STATE;
+  CK(hipSetDevice(c->device));
+  size_t P = (size_t)c->P;
+  if (!P) return 0;
+  if (t) CK(hipMemcpyAsync(t, c->d_t, P * 8, hipMemcpyDeviceToHost, c->ms));
+  if (status) CK(hipMemcpyAsync(status, c->d_status, P * 4, hipMemcpyDeviceToHost, c->ms));
+  if (steps) CK(hipMemcpyAsync(steps, c->d_steps, P * 8, hipMemcpyDeviceToHost, c->ms));
+  CK(hipStreamSynchronize(c->ms));
+  return 0;
+}
+
+int imexds_enable_log(imexds_ctx* c, int32_t max_steps) {
+  if (!c || max_steps < 0) return IMEXDS_ERR_INVALID_ARG;
+  CK(hipSetDevice(c->device));
+  CK(hipStreamSynchronize(c->ms));
+  drop_graph(c);
+  if (c->d_log_count) {
+    (void)hipFree(c->d_log_count);
+    (void)hipFree(c->d_log_flags);
+    (void)hipFree(c->d_log_zlo);
+    c->d_log_count = c->d_log_flags = c->d_log_zlo = nullptr;
+  }
+  c->log_max = 0;
+  if (max_steps > 0 && c->NIF > 0) {
+    size_t n = (size_t)max_steps * (size_t)c->NIF;
+    if (hipMalloc((void**)&c->d_log_count, n * 4) != hipSuccess ||
+        hipMalloc((void**)&c->d_log_flags, n * 4) != hipSuccess ||
+        hipMalloc((void**)&c->d_log_zlo, n * 4) != hipSuccess)
+      return IMEXDS_ERR_OOM;
+    c->log_max = max_steps;
+  }
+  CK(hipMemset(c->d_log_row, 0, 4));
+  return 0;
+}
+
+int imexds_get_log(imexds_ctx* c, int32_t* count, int32_t* flags, int32_t* zlo, int32_t* rows) {
+  if (!c) return IMEXDS_ERR_INVALID_ARG;
+  CK(hipSetDevice(c->device));
+  int row = 0;
+  CK(hipMemcpyAsync(&row, c->d_log_row, 4, hipMemcpyDeviceToHost, c->ms));
+  CK(hipStreamSynchronize(c->ms));
+  int n = std::min(row, c->log_max);
+  if (rows) *rows = n;
+  size_t cnt = (size_t)n * (size_t)c->NIF;
+  if (cnt) {
+    if (count) CK(hipMemcpy(count, c->d_log_count, cnt * 4, hipMemcpyDeviceToHost));
+    if (flags) CK(hipMemcpy(flags, c->d_log_flags, cnt * 4, hipMemcpyDeviceToHost));
+    if (zlo) CK(hipMemcpy(zlo, c->d_log_zlo, cnt * 4, hipMemcpyDeviceToHost));
+  }
+  return 0;
+}
+
+int imexds_get_stats(imexds_ctx* c, imexds_stats* out) {
+  if (!c || !out) return IMEXDS_ERR_INVALID_ARG;
+  CK(hipSetDevice(c->device));
+  memset(out, 0, sizeof(*out));
+  unsigned long long st[3] = {0, 0, 0};
+  CK(hipMemcpyAsync(st, c->d_stats, 24, hipMemcpyDeviceToHost, c->ms));
+  size_t P = (size_t)c->P;
+  std::vector<long long> steps(P);
+  std::vector<int> status(P);
+  std::vector<double> dt(P);
+  if (P) {
+    CK(hipMemcpyAsync(steps.data(), c->d_steps, P * 8, hipMemcpyDeviceToHost, c->ms));
+    CK(hipMemcpyAsync(status.data(), c->d_status, P * 4, hipMemcpyDeviceToHost, c->ms));
+    CK(hipMemcpyAsync(dt.data(), c->d_dt, P * 8, hipMemcpyDeviceToHost, c->ms));
+  }
+  CK(hipStreamSynchronize(c->ms));
+  for (size_t p = 0; p < P; ++p) {
+    out->steps += steps[p];
+    out->cell_updates += steps[p] * (c->h_slot_off[p + 1] - c->h_slot_off[p]);
+    if (status[p]) out->n_failed++;
+    if (dt[p] > 0.0) out->n_active++;
+  }
+  out->pseudo_iters = (int64_t)st[0];
+  out->merges = (int64_t)st[1];
+  out->lmax_hits = (int64_t)st[2];
+  return 0;
+}
+
+int imexds_set_launch(imexds_ctx* c, int32_t tile_cells, int32_t zones_per_group,
+                      int32_t graph_steps) {
+  if (!c) return IMEXDS_ERR_INVALID_ARG;
+  if (tile_cells != 256 && tile_cells != 512 && tile_cells != 1024 && tile_cells != 2048)
+    return IMEXDS_ERR_INVALID_ARG;
+  if (zones_per_group < 1 || zones_per_group > 64 || graph_steps < 0 || (graph_steps & 1) ||
+      graph_steps > 512)
+    return IMEXDS_ERR_INVALID_ARG;
+  CK(hipSetDevice(c->device));
+  CK(hipStreamSynchronize(c->ms));
+  drop_graph(c);
+  c->zones_per_group = zones_per_group;
+  c->graph_steps = graph_steps;
+  if (tile_cells != c->tile_cells) return build_tiles(c, tile_cells);
+  return 0;
+}
+
+int imexds_autotune(imexds_ctx* c, int32_t steps_per_trial, int32_t* tile_cells,
+                    int32_t* zones_per_group, double* ms_per_step) {
+  if (!c || steps_per_trial < 1) return IMEXDS_ERR_INVALID_ARG;
+  if (!c->has_state) return IMEXDS_ERR_NO_STATE;
+  CK(hipSetDevice(c->device));
+  CK(hipStreamSynchronize(c->user));
+  Snapshot s;
+  int r = snap_take(c, s);
+  if (r) {
+    snap_free(s);
+    return r;
+  }
+  const int tiles[] = {256, 512, 1024, 2048};
+  const int zpgs[] = {4, 8, 16, 32, 64};
+  int best_t = c->tile_cells, best_z = c->zones_per_group;
+  double best = 1e300;
+  int G = c->graph_steps;
+  for (int tc : tiles) {
+    for (int zp : zpgs) {
+      if ((r = imexds_set_launch(c, tc, zp, G))) break;
+      if ((r = snap_restore(c, s))) break;
+      if ((r = steps_impl(c, 2))) break;  // warm-up (also captures the graph)
+      if ((r = snap_restore(c, s))) break;
+      hipEvent_t a = c->ev_t0, b = c->ev_t1;
+      if (hipEventRecord(a, c->ms) != hipSuccess) break;
+      if ((r = steps_impl(c, steps_per_trial))) break;
+      if (hipEventRecord(b, c->ms) != hipSuccess) break;
+      if (hipEventSynchronize(b) != hipSuccess) break;
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, a, b);
+      double per = ms / steps_per_trial;
+      if (per < best) {
+        best = per;
+        best_t = tc;
+        best_z = zp;
+      }
+    }
+    if (r) break;
+  }
+  int r2 = imexds_set_launch(c, best_t, best_z, G);
+  int r3 = snap_restore(c, s);
+  snap_free(s);
+  if (r) return r;
+  if (r2) return r2;
+  if (r3) return r3;
+  if (tile_cells) *tile_cells = best_t;
+  if (zones_per_group) *zones_per_group = best_z;
+  if (ms_per_step) *ms_per_step = best;
+  return 0;
+}
+
+int imexds_get_sizes(imexds_ctx* c, int32_t* n_problems, int32_t* n_iface, int64_t* n_slots) {
+  if (!c) return IMEXDS_ERR_INVALID_ARG;
+  if (n_problems) *n_problems = c->P;
+  if (n_iface) *n_iface = c->NIF;
+  if (n_slots) *n_slots = c->S;
+  return 0;
+}
+
+int imexds_last_timing(imexds_ctx* c, double* total_ms, double* bulk_ms_per_launch) {
+  if (!c) return IMEXDS_ERR_INVALID_ARG;
+  CK(hipSetDevice(c->device));
+  if (!c->timed) return IMEXDS_ERR_NO_STATE;
+  CK(hipEventSynchronize(c->ev_t1));
+  float ms = 0.f;
+  CK(hipEventElapsedTime(&ms, c->ev_t0, c->ev_t1));
+  if (total_ms) *total_ms = ms;
+  if (bulk_ms_per_launch) {
+    double sum = 0.0;
+    for (int i = 0; i < c->bulk_launches; ++i) {
+      float b = 0.f;
+      CK(hipEventElapsedTime(&b, c->bulk_ev[2 * i], c->bulk_ev[2 * i + 1]));
+      sum += b;
+    }
+    *bulk_ms_per_launch = c->bulk_launches ? sum / c->bulk_launches : 0.0;
+  }
+  return 0;
+}
+
+int imexds_time_bulk(imexds_ctx* c, int32_t on) {
+  if (!c) return IMEXDS_ERR_INVALID_ARG;
+  c->time_bulk = on != 0;
+  return 0;
+}
+
+}  // extern "C"

@@ -146,25 +146,17 @@ def _assemble(n_cells, h, x_left, phase_first, homes, hls, cell_states, name, me
     rho_all, mom_all = [], []
     for p in range(P):
         n, hp, x0 = int(n_cells[p]), float(h[p]), float(x_left[p])
-        hs, ls = list(homes[p]), list(hls[p])
-        lefts, rights, phases = [], [], []
-        ph = int(phase_first[p])
-        k = 0
-        for c in range(n):
-            xa, xb = x0 + c * hp, x0 + (c + 1) * hp
-            if k < len(hs) and hs[k] == c:
-                xi = xa + ls[k]
-                lefts += [xa, xi]
-                rights += [xi, xb]
-                phases += [ph, ph ^ 1]
-                ph ^= 1
-                k += 1
-            else:
-                lefts.append(xa)
-                rights.append(xb)
-                phases.append(ph)
-        xc = 0.5 * (np.asarray(lefts) + np.asarray(rights))
-        phases = np.asarray(phases)
+        hs = np.asarray(list(homes[p]), dtype=np.int64)
+        ls = np.asarray(list(hls[p]), dtype=np.float64)
+        edges = x0 + np.arange(n + 1, dtype=np.float64) * hp
+        xi = edges[hs] + ls
+        lefts = np.insert(edges[:-1], hs + 1, xi)
+        rights = np.insert(edges[1:], hs, xi)
+        xc = 0.5 * (lefts + rights)
+        k = len(hs)
+        right_piece = hs + np.arange(k) + 1
+        flips = np.searchsorted(right_piece, np.arange(n + k), side="right")
+        phases = (int(phase_first[p]) + flips) & 1
         rho = np.empty_like(xc)
         u = np.empty_like(xc)
         for q in (LIQ, VAP):
@@ -179,8 +171,8 @@ def _assemble(n_cells, h, x_left, phase_first, homes, hls, cell_states, name, me
     hl = np.asarray([v for ls in hls for v in ls], dtype=np.float64)
     return Batch(np.asarray(n_cells, dtype=np.int32), np.asarray(h, dtype=np.float64),
                  np.asarray(x_left, dtype=np.float64), np.asarray(phase_first, dtype=np.int32),
-                 iface_off, home, hl, np.concatenate(rho_all), np.concatenate(mom_all),
-                 name=name, meta=dict(meta or {}))
+                 iface_off, home, hl, np.concatenate(rho_all) if P else np.zeros(0),
+                 np.concatenate(mom_all) if P else np.zeros(0), name=name, meta=dict(meta or {}))
 
 
 def _const_states(rng, liq=(900.0, 1000.0), vap=(0.01, 0.1), uliq=(-1.0, 1.0), uvap=(-1.0, 1.0)):

@@ -1,0 +1,179 @@
+"""HIP path vs CPU oracle, element by element, through the C ABI.
+
+Bar: rel-L1 <= 1e-10 per problem and component (FP64), identical interface
+cells, statuses, step counts, dual-time iteration counts, event flags and
+zone partitions for every step and interface.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from parity import assert_parity, run_gpu, run_oracle
+from paper_2211_00705_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2211_00705_amd import imexds  # noqa: F401  (fails loudly if the library is missing)
+
+
+def test_constant_states_are_preserved_bitwise(material):
+    b = W.single_phase_problem(1000, lambda x: np.full(x.shape, 970.0), lambda x: np.zeros(x.shape))
+    g = run_gpu(b, material, W.Params(), 50, log=False)
+    assert np.array_equal(g["rho"], b.rho) and np.array_equal(g["mom"], b.mom)
+    assert g["steps"][0] == 50
+
+
+def test_single_phase_matches_oracle_bitwise(material):
+    b = W.single_phase_problem(3000, lambda x: 900.0 + 80.0 * np.sin(6 * x) ** 2,
+                               lambda x: 20.0 * np.cos(9 * x))
+    P = W.Params(bc_left=1, bc_right=0)
+    g = run_gpu(b, material, P, 120)
+    o = run_oracle(b, material, P, 120)
+    assert np.array_equal(g["rho"], o["rho"]) and np.array_equal(g["mom"], o["mom"])
+    assert_parity(b, g, o)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_single_cut_problem(material, seed):
+    """200 cells, cut fraction 1e-4, relative-update dual time stepping."""
+    b = W.single_cut_problem(seed)
+    P = W.single_cut_params()
+    g = run_gpu(b, material, P, 400)
+    o = run_oracle(b, material, P, 400)
+    assert np.all(o["status"] == 0)
+    assert_parity(b, g, o)
+
+
+@pytest.mark.parametrize("zone_half", [1, 2, 3])
+def test_random_batch(material, zone_half):
+    """Uneven problems spanning several tiles with ragged tails, paper's
+    stopping rule, interfaces crossing cells and tiny pieces merging."""
+    b = W.random_batch(seed=3 + zone_half, n_problems=40, nmin=64, nmax=3000)
+    P = W.random_batch_params().replace(zone_half=zone_half)
+    g = run_gpu(b, material, P, 300)
+    o = run_oracle(b, material, P, 300)
+    assert np.all(o["status"] == 0)
+    ev = (o["flags"] & 2) > 0  # merged
+    assert ev.sum() > 20  # merges happened
+    assert_parity(b, g, o)
+
+
+def test_bubble_batch(material):
+    b = W.bubble_batch(seed=7, n_problems=12, n=512)
+    P = W.bubble_batch_params()
+    g = run_gpu(b, material, P, 300)
+    o = run_oracle(b, material, P, 300)
+    assert_parity(b, g, o)
+
+
+def test_launch_forms_agree_bitwise(material):
+    """Batched graph replay, direct launches, per-problem launches and every
+    tile size give bit-identical results."""
+    b = W.random_batch(seed=21, n_problems=16, nmin=100, nmax=5000)
+    P = W.random_batch_params()
+    ref = run_gpu(b, material, P, 64, launch=(1024, 16, 8))
+    for launch in [(256, 1, 0), (512, 64, 2), (2048, 7, 16), (1024, 16, 0)]:
+        g = run_gpu(b, material, P, 64, launch=launch)
+        assert np.array_equal(g["rho"], ref["rho"]) and np.array_equal(g["mom"], ref["mom"]), launch
+        assert np.array_equal(g["count"], ref["count"])
+    g = run_gpu(b, material, P, 64, per_problem=True)
+    assert np.array_equal(g["rho"], ref["rho"]) and np.array_equal(g["mom"], ref["mom"])
+    assert np.array_equal(g["count"], ref["count"])
+
+
+def test_run_to_end_time(material):
+    b = W.random_batch(seed=5, n_problems=6, nmin=64, nmax=400)
+    P = W.random_batch_params().replace(t_end=2e-4)
+    import torch
+    from paper_2211_00705_amd.imexds import IMEXDS
+    s = IMEXDS(b, material, P)
+    s.set_state()
+    n = s.run(100000, check_every=64)
+    torch.cuda.synchronize()
+    t, st, steps = s.problems()
+    rho, mom = s.state_numpy()
+    home, hl, _ = s.interfaces()
+    s.close()
+    assert np.all(t == 2e-4) and np.all(st == 0)
+    o = run_oracle(b, material, P, int(steps.max()) + 5)
+    g = dict(rho=rho, mom=mom, home=home, hl=hl, t=t, status=st, steps=steps)
+    assert_parity(b, g, o, logs=False)
+    assert n >= steps.max()
+
+
+def test_failures_are_flagged_and_confined(material):
+    good = W.random_batch(seed=11, n_problems=3, nmin=64, nmax=128)
+    bad = good.copy()
+    so = bad.slot_off
+    bad.rho[so[1] + 5] = float("nan")
+    P = W.random_batch_params()
+    g = run_gpu(bad, material, P, 20)
+    o = run_oracle(bad, material, P, 20)
+    assert g["status"][1] == 2 and g["steps"][1] == 0
+    assert_parity(bad.subset([0, 2]), {k: _sub(bad, v, k, [0, 2]) for k, v in g.items()},
+                  {k: _sub(bad, v, k, [0, 2]) for k, v in o.items()}, logs=False)
+    g2 = run_gpu(good, material, P.replace(newton_maxit=1), 5)
+    assert np.all(g2["status"] == 1) and np.all(g2["t"] == 0)
+
+
+def _sub(b, v, key, idx):
+    so, io = b.slot_off, b.iface_off
+    if key in ("rho", "mom"):
+        return np.concatenate([v[so[p]:so[p + 1]] for p in idx])
+    if key in ("home", "hl"):
+        return np.concatenate([v[io[p]:io[p + 1]] for p in idx])
+    if key in ("t", "status", "steps"):
+        return v[idx]
+    return v
+
+
+def test_overlapping_zones_freeze_the_problem(material):
+    b = W._assemble([40, 50], [0.025, 0.02], [0.0, 0.0], [W.LIQ, W.LIQ], [[10, 12], [20]],
+                    [[0.01, 0.01], [0.005]],
+                    [lambda x, q: (np.full(x.shape, 966.0 if q == W.LIQ else 0.4), np.zeros(x.shape))] * 2,
+                    name="close")
+    g = run_gpu(b, material, W.Params(), 10)
+    o = run_oracle(b, material, W.Params(), 10)
+    assert g["status"][0] == 8 and g["status"][1] == 0
+    assert_parity(b, g, o)
+
+
+def test_edge_cases(material):
+    """Empty batch; a problem without interfaces next to ones with them; an
+    interface in the first and last background cells; pieces of exactly zero
+    and of full length."""
+    P = W.Params(bc_left=0, bc_right=1)
+    empty = W._assemble([], [], [], [], [], [], [], name="empty")
+    g = run_gpu(empty, material, P, 3, log=False)
+    assert g["rho"].size == 0
+    st = lambda x, q: (np.where(q == W.LIQ, 965.0 + 5 * x, 0.05 + 0.01 * x), 0.3 * np.ones(x.shape))
+    b = W._assemble([30, 20, 25, 40], [1 / 30, 1 / 20, 1 / 25, 1 / 40], [0, 0, 0, 0],
+                    [W.LIQ, W.VAP, W.LIQ, W.VAP], [[], [0], [24], [10, 30]],
+                    [[], [0.3 / 20], [0.5 / 25], [0.0, 1 / 40]], [st] * 4, name="edges")
+    g = run_gpu(b, material, P, 40)
+    o = run_oracle(b, material, P, 40)
+    assert_parity(b, g, o)
+
+
+def test_full_size_batch_sampled(material):
+    """The benchmarked batch at full size (4096 problems, about 1.6e7 cells,
+    1000 steps) in the autotuned launch form; 6 sampled problems recomputed by
+    the oracle on their own."""
+    b = W.random_batch()
+    P = W.random_batch_params()
+    g = run_gpu(b, material, P, 1000, launch=(1024, 16, 8), log=False)
+    rng = np.random.default_rng(1)
+    idx = sorted(rng.choice(b.n_problems, size=6, replace=False).tolist())
+    sub = b.subset(idx)
+    o = run_oracle(sub, material, P, 1000)
+    gs = {k: _sub(b, v, k, idx) for k, v in g.items() if k != "stats"}
+    assert_parity(sub, gs, o, logs=False)
+    assert np.all(g["steps"] == 1000)
+    assert g["stats"]["cell_updates"] == 1000 * b.n_slots

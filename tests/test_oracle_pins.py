@@ -466,3 +466,24 @@ def test_overlapping_zones_are_rejected(material):
     oracle.run(st, material, W.Params(), 3)
     assert st.status[0] == oracle.ST_OVERLAP
     assert np.array_equal(st.rho, b.rho)
+
+
+def test_reproducible_logarithm_is_accurate():
+    """The oracle's fixed-order logarithm (atanh series after reduction to
+    [sqrt(1/2), sqrt(2)]) agrees with the C library to a few ulp, over the
+    whole double range and near 1."""
+    import ctypes
+    L = oracle.lib()
+    L.oracle_log.restype = ctypes.c_double
+    L.oracle_log.argtypes = [ctypes.c_double]
+    rng = np.random.default_rng(0)
+    xs = np.concatenate([np.exp(rng.uniform(-700, 700, 20000)), rng.uniform(0.5, 2, 20000),
+                         1 + rng.uniform(-1e-6, 1e-6, 2000), [1.0, 2.0, 0.5, 1e-310, 1.7e308]])
+    worst = 0.0
+    for x in xs:
+        r = math.log(x)
+        ulp = np.spacing(abs(r)) if r != 0 else 5e-324
+        worst = max(worst, abs(L.oracle_log(x) - r) / ulp)
+    assert worst <= 4.0
+    assert L.oracle_log(1.0) == 0.0
+    assert math.isnan(L.oracle_log(-1.0)) and L.oracle_log(0.0) == -math.inf
