@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched IMEX-DS step on one MI355X.
+
+One step = one physical time step of every problem in the batch: explicit
+HLL sweep of all bulk cells, dual time stepping on every implicit zone with
+its interface Riemann solves, CFL reduction and bookkeeping.  Inputs are
+seeded synthetic problems resident in HBM before timing starts.
+
+Prints one JSON line with the FP64 cell-update rate of the batched launch
+(HIP-graph replays), the per-problem launch form on the same state for
+comparison, the bulk kernel's HBM roofline fraction (HIP events around each
+bulk launch), and the CPU oracle timed on a bounded sample of the same
+problems (whose results are also compared with the GPU's).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FP64 cell-updates/s (batched vs per-problem) at 1e-10 rel L1; adjoint/fwd time"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+BYTES_PER_CELL_UPDATE = 32  # rho, rho u read + write, FP64
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="batch", choices=["batch", "large", "bubble"])
+    ap.add_argument("--problems", type=int, default=4096)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the cpu_baseline leg")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--per-problem-steps", type=int, default=4)
+    ap.add_argument("--roofline-steps", type=int, default=100)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one device copy of this size first (HBM counter calibration)")
+    return ap.parse_args()
+
+
+def make_workload(args):
+    from paper_2211_00705_amd import workloads as W
+    if args.workload == "batch":
+        b = W.random_batch(n_problems=args.problems)
+        P = W.random_batch_params()
+        desc = (f"random_batch: {b.n_problems} independent liquid|vapour problems, "
+                f"N ~ logU-int[256,16384] ({b.n_slots} slots), 1 interface each, "
+                "cut fraction ~ logU[1e-6,1e-1], zone = tiny +- 2, paper stop rule, lmax 100, walls")
+    elif args.workload == "bubble":
+        b = W.bubble_batch(n_problems=min(args.problems, 1024))
+        P = W.bubble_batch_params()
+        desc = (f"bubble_batch: {b.n_problems} liquid|vapour-bubble|liquid problems x 4096 cells, "
+                "2 interfaces each, vapour-side cut fraction ~ logU[1e-6,1e-2]")
+    else:
+        b = W.large_smooth_problem()
+        P = W.large_smooth_params()
+        desc = f"large_smooth: one problem of {b.n_slots} slots, piecewise-smooth states"
+    return b, P, desc
+
+
+def slot_lengths(b, home, hl):
+    out = np.empty(b.n_slots)
+    so = b.slot_off
+    for p in range(b.n_problems):
+        hp = b.h[p]
+        L = np.full(int(so[p + 1] - so[p]), hp)
+        for kk, k in enumerate(range(int(b.iface_off[p]), int(b.iface_off[p + 1]))):
+            L[home[k] + kk] = hl[k]
+            L[home[k] + kk + 1] = hp - hl[k]
+        out[so[p]:so[p + 1]] = L
+    return out
+
+
+def cpu_baseline_leg(b, P, material, steps, gpu_rho, gpu_mom, gpu_home, gpu_hl, seconds):
+    """Times the CPU oracle on chunks of the same problems for the same number
+    of steps until about `seconds` of wall time, and compares its results with
+    the GPU's for those problems (rel-L1 per problem and component)."""
+    import oracle
+    threads = max(1, min(16, os.cpu_count() or 1))
+    rng = np.random.default_rng(12345)
+    order = rng.permutation(b.n_problems)
+    done, cu, wall, worst = [], 0, 0.0, 0.0
+    so, io = b.slot_off, b.iface_off
+    chunk = 32
+    for c0 in range(0, b.n_problems, chunk):
+        idx = sorted(order[c0:c0 + chunk].tolist())
+        sub = b.subset(idx)
+        st = oracle.State(sub)
+        t0 = time.perf_counter()
+        oracle.run(st, material, P, steps, threads=threads)
+        wall += time.perf_counter() - t0
+        cu += int(np.sum(st.steps * (np.diff(sub.slot_off))))
+        L = slot_lengths(sub, st.home, st.hl)
+        sso = sub.slot_off
+        for j, p in enumerate(idx):
+            g0, g1 = int(so[p]), int(so[p + 1])
+            s0, s1 = int(sso[j]), int(sso[j + 1])
+            for gk, ok in ((gpu_rho, st.rho), (gpu_mom, st.mom)):
+                num = np.sum(np.abs(gk[g0:g1] - ok[s0:s1]) * L[s0:s1])
+                den = max(np.sum(np.abs(ok[s0:s1]) * L[s0:s1]),
+                          np.sum(np.abs(st.rho[s0:s1]) * L[s0:s1]))
+                worst = max(worst, num / den)
+            ks = range(int(io[p]), int(io[p + 1]))
+            if list(gpu_home[list(ks)]) != list(st.home[int(sub.iface_off[j]):int(sub.iface_off[j + 1])]):
+                worst = max(worst, 1.0)
+        done += idx
+        if wall >= seconds:
+            break
+    return {"value": cu / wall, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(done)} of {b.n_problems} problems ({int(np.sum(np.diff(b.slot_off)[done]))} slots) "
+                      f"x {steps} steps, OpenMP over problems, {wall:.1f} s",
+            "parity_max_rel_l1": worst}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU sharding is "
+                                   "described in DESIGN.md but not built", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    from paper_2211_00705_amd import imexds as I
+    from paper_2211_00705_amd.workloads import WATER_363K as material
+
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 8
+        xa = torch.ones(n, dtype=torch.float64, device="cuda")
+        xb = torch.empty_like(xa)
+        xb.copy_(xa)
+        torch.cuda.synchronize()
+        del xa, xb
+
+    b, P, desc = make_workload(args)
+    s = I.IMEXDS(b, material, P)
+    rho0 = torch.from_numpy(np.ascontiguousarray(b.rho)).cuda()
+    mom0 = torch.from_numpy(np.ascontiguousarray(b.mom)).cuda()
+    s.set_state(rho0, mom0)
+    tune = {"tile_cells": 1024, "zones_per_group": 16, "zone_groups": 0}
+    if not args.no_autotune:
+        tc, zp, zg, ms = s.autotune(10)
+        tune = {"tile_cells": tc, "zones_per_group": zp, "zone_groups": zg, "ms_per_step": ms}
+    s.set_launch(tune["tile_cells"], tune["zones_per_group"], tune["zone_groups"], 10)
+
+    # warm-up on the initial state, then reload it so the timed steps are the first K steps
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+    s.set_state(rho0, mom0)
+    torch.cuda.synchronize()
+    st0 = s.stats()
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms, _ = s.last_timing()
+    st1 = s.stats()
+    cell_updates = st1["cell_updates"] - st0["cell_updates"]
+    ms = ev_ms
+    value = cell_updates / (ms * 1e-3)
+
+    g_rho, g_mom = s.state_numpy()
+    g_home, g_hl, _ = s.interfaces()
+    _, g_status, g_steps = s.problems()
+
+    # bulk-kernel roofline: same state, eager launches with events around each bulk launch
+    s.time_bulk(True)
+    s.step(args.roofline_steps)
+    torch.cuda.synchronize()
+    _, bulk_ms = s.last_timing()
+    s.time_bulk(False)
+    NIF = b.n_iface
+    zone_slots = int(round(NIF * (2 * P.zone_half + 1)))
+    bulk_bytes = BYTES_PER_CELL_UPDATE * (b.n_slots - zone_slots)
+    achieved = bulk_bytes / (bulk_ms * 1e-3) / 1e9
+
+    # per-problem launch form on the same state
+    s.step_per_problem(args.per_problem_steps)
+    torch.cuda.synchronize()
+    pp_ms, _ = s.last_timing()
+    pp_value = args.per_problem_steps * b.n_slots / (pp_ms * 1e-3)
+    stats = s.stats()
+    s.close()
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded), inputs resident in HBM",
+        "config": {"workload": desc, "problems": b.n_problems, "slots": b.n_slots,
+                   "interfaces": b.n_iface, "launch": "hipGraph replay, 10 steps per graph",
+                   "launch_tuning": tune},
+        "wall_s": wall,
+        "failed_problems": int(np.sum(g_status != 0)),
+        "pseudo_iters_per_zone_step": (st1["pseudo_iters"] - st0["pseudo_iters"]) / max(1, NIF * args.steps),
+        "per_problem": {"value": pp_value, "unit": "cell-updates/s",
+                        "ms_per_step": pp_ms / args.per_problem_steps,
+                        "steps": args.per_problem_steps,
+                        "batched_speedup": value / pp_value},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_bulk", "bulk_ms_per_launch": bulk_ms,
+                     "algorithmic_bytes_per_launch": bulk_bytes},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_leg(b, P, material, args.steps, g_rho, g_mom, g_home,
+                                               g_hl, args.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

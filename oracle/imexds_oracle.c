@@ -90,8 +90,9 @@ static double or_pres(const or_material *M, int ph, double rho) {
   return ph == OR_VAP ? M->a2v * rho : M->p0 + M->a2l * (rho - M->rhol0);
 }
 
+/* inverse pressure law (used inside the interface solve), reciprocal form */
 static double or_rho_of_p(const or_material *M, int ph, double p) {
-  return ph == OR_VAP ? p / M->a2v : M->rhol0 + (p - M->p0) / M->a2l;
+  return ph == OR_VAP ? p * (1.0 / M->a2v) : M->rhol0 + (p - M->p0) * (1.0 / M->a2l);
 }
 
 /* Natural logarithm of a positive finite double.  Argument reduction
@@ -140,12 +141,6 @@ double oracle_log(double x) {
   double r = (2.0 * f) * p;
   double de = (double)e;
   return de * 0x1.62e42feep-1 + (de * 0x1.a39ef35793c76p-33 + r);
-}
-
-/* Gibbs energy up to the common constant fixed by g_L(p0) = g_V(p0). */
-static double or_gibbs(const or_material *M, int ph, double rho) {
-  if (ph == OR_VAP) return M->a2v * oracle_log(rho / (M->p0 / M->a2v));
-  return M->a2l * oracle_log(rho / M->rhol0);
 }
 
 /* ------------------------------------------------------------------ */
@@ -198,96 +193,117 @@ typedef struct {
   int ok;
 } or_iface;
 
-/* classical wave function f_K(p*; W_K) and df/dp*; also rho_K(p*).
- * Both pressure laws are affine in density (p - p_K = a^2 (rho - rho_K)), so
- * the shock branch sqrt(-[[p]][[v]]) equals a (rho* - rho_K)/sqrt(rho_K rho*),
- * which stays accurate when the wave is vanishingly weak. */
-static int or_wave(const or_material *M, int ph, double rhoK, double pK, double ps, double *f,
-                   double *df, double *rs) {
-  double r = or_rho_of_p(M, ph, ps);
+/* One side of the interface problem: its state, phase constants and
+ * L_K = ln(rho_K / rho_K,sat).  One logarithm per side and evaluation,
+ * L* = ln(rho* / rho_K,sat), then gives both the Gibbs energy a^2 L* and the
+ * rarefaction wave a ln(rho_star / rho_K) = a (L* - L_K). */
+typedef struct {
+  int ph;
+  double r, u, p, LK;
+  double a, a2, ia, ia2, hia, irs;
+} or_side;
+
+static void or_side_init(const or_material *M, int ph, double r, double m, or_side *S) {
+  S->ph = ph;
+  S->r = r;
+  S->u = m / r;
+  S->p = or_pres(M, ph, r);
+  S->a2 = or_a2(M, ph);
+  S->a = sqrt(S->a2);
+  S->ia = 1.0 / S->a;
+  S->ia2 = 1.0 / S->a2;
+  S->hia = 0.5 * S->ia;
+  S->irs = ph == OR_VAP ? 1.0 / (M->p0 / M->a2v) : 1.0 / M->rhol0;
+  S->LK = oracle_log(r * S->irs);
+}
+
+typedef struct {
+  double rs, v, g, f, df;
+} or_seval;
+
+/* Outer wave at star pressure ps (Appendix A): density, specific volume,
+ * Gibbs energy, f_K and df_K/dp*.  Shock branch sqrt(-[[p]][[v]]) written
+ * a (rho* - rho_K)/sqrt(rho_K rho*) (exact for pressure laws affine in rho);
+ * rarefaction branch: the integral of v/a, a ln(rho_star / rho_K). */
+static int or_wave(const or_material *M, const or_side *S, double ps, or_seval *E) {
+  double r = or_rho_of_p(M, S->ph, ps);
   if (!(r > 0.0) || !isfinite(r)) return 0;
-  double a = sqrt(or_a2(M, ph));
-  *rs = r;
-  if (ps > pK) { /* shock */
-    double g = sqrt(rhoK * r);
-    *f = a * (r - rhoK) / g;
-    *df = (r + rhoK) / ((2.0 * a * r) * g);
-  } else { /* rarefaction: integral of v/a dp = a ln(rho_star / rho_K) */
-    *f = a * oracle_log(r / rhoK);
-    *df = 1.0 / (r * a);
+  double v = 1.0 / r;
+  double L = oracle_log(r * S->irs);
+  E->rs = r;
+  E->v = v;
+  E->g = S->a2 * L;
+  if (ps > S->p) {
+    double ig = 1.0 / sqrt(S->r * r);
+    E->f = (S->a * (r - S->r)) * ig;
+    E->df = ((r + S->r) * ig) * (v * S->hia);
+  } else {
+    E->f = S->a * (L - S->LK);
+    E->df = v * S->ia;
   }
   return 1;
 }
 
-/* z from the kinetic relation z = tau p_V ([[g]] + z^2 [[v^2]]/2), the root
- * continuous at [[v^2]] -> 0, and dz/dp_l*, dz/dp_r* by implicit
- * differentiation of  A z^2 - z + C = 0. */
-static int or_kinetic(const or_material *M, int phl, int phr, double rsl, double rsr, double psl,
-                      double psr, double *z, double *dzl, double *dzr) {
-  double pV = (phl == OR_VAP) ? psl : psr;
+typedef struct {
+  int phl, phr;
+  or_side L, R;
+  double izref; /* 1 / max(rho_l a_l, rho_r a_r) */
+} or_rp;
+
+typedef struct {
+  double G1, G2, J11, J12, J21, J22, m2, z;
+  or_seval l, r;
+} or_geval;
+
+/* G = ([[p]] + z^2 [[v]],  f_l + f_r + z [[v]] + (u_r - u_l)) and its Jacobian
+ * (eqs. 2p_RP:ex_sys, jacobian:ex_sys).  z from the kinetic relation
+ * z = tau p_V ([[g]] + z^2 [[v^2]]/2) (eq. isoT:kin_rel1 with the kinetic
+ * energy relative to the boundary), i.e. A z^2 - z + C = 0 with
+ * A = tau p_V [[v^2]]/2 and C = tau p_V [[g]], root continuous at A -> 0;
+ * dz/dp by implicit differentiation, where 2 A z - 1 = -sqrt(1 - 4 A C). */
+static int or_eval_G(const or_material *M, const or_rp *R, double psl, double psr, or_geval *E) {
+  if (!or_wave(M, &R->L, psl, &E->l)) return 0;
+  if (!or_wave(M, &R->R, psr, &E->r)) return 0;
+  double vl = E->l.v, vr = E->r.v;
+  double pV = (R->phl == OR_VAP) ? psl : psr;
   double q = M->tau * pV;
-  double vl = 1.0 / rsl, vr = 1.0 / rsr;
-  double jg = or_gibbs(M, phr, rsr) - or_gibbs(M, phl, rsl);
+  double jg = E->r.g - E->l.g;
   double jv2 = vr * vr - vl * vl;
   double A = 0.5 * q * jv2;
   double C = q * jg;
   double D = 1.0 - 4.0 * A * C;
   if (!(D >= 0.0) || !isfinite(D)) return 0;
   double sD = sqrt(D);
-  double zz = 2.0 * C / (1.0 + sD);
-  double a2l = or_a2(M, phl), a2r = or_a2(M, phr);
-  /* dv/dp = -v^2/a^2,  d(v^2)/dp = -2 v^3/a^2,  dg/dp = v */
-  double dAl = 0.5 * q * (2.0 * vl * vl * vl / a2l);
-  double dAr = 0.5 * q * (-2.0 * vr * vr * vr / a2r);
-  double dCl = q * (-vl);
+  double isD = 1.0 / sD;
+  double z = 2.0 * C / (1.0 + sD);
+  /* d(v^2)/dp = -2 v^3 / a^2, dg/dp = v */
+  double dAl = q * ((vl * vl * vl) * R->L.ia2);
+  double dAr = -(q * ((vr * vr * vr) * R->R.ia2));
+  double dCl = -(q * vl);
   double dCr = q * vr;
-  if (phl == OR_VAP) {
-    dAl += 0.5 * M->tau * jv2;
+  if (R->phl == OR_VAP) {
+    dAl += (0.5 * M->tau) * jv2;
     dCl += M->tau * jg;
   } else {
-    dAr += 0.5 * M->tau * jv2;
+    dAr += (0.5 * M->tau) * jv2;
     dCr += M->tau * jg;
   }
-  /* d/dz (A z^2 - z + C) = 2 A z - 1 = -sqrt(D) at this root */
-  *dzl = (dAl * zz * zz + dCl) / sD;
-  *dzr = (dAr * zz * zz + dCr) / sD;
-  *z = zz;
-  return 1;
-}
-
-typedef struct {
-  int phl, phr;
-  double rl, ul, pl, rr, ur, pr;
-} or_rp;
-
-typedef struct {
-  double G1, G2, J11, J12, J21, J22;
-  double rsl, rsr, fl, fr, z;
-} or_geval;
-
-static int or_eval_G(const or_material *M, const or_rp *R, double psl, double psr, or_geval *E) {
-  double dfl, dfr, dzl, dzr;
-  if (!or_wave(M, R->phl, R->rl, R->pl, psl, &E->fl, &dfl, &E->rsl)) return 0;
-  if (!or_wave(M, R->phr, R->rr, R->pr, psr, &E->fr, &dfr, &E->rsr)) return 0;
-  if (!or_kinetic(M, R->phl, R->phr, E->rsl, E->rsr, psl, psr, &E->z, &dzl, &dzr)) return 0;
-  double z = E->z;
-  double vl = 1.0 / E->rsl, vr = 1.0 / E->rsr;
+  double dzl = (dAl * z * z + dCl) * isD;
+  double dzr = (dAr * z * z + dCr) * isD;
   double jv = vr - vl;
-  double el = vl * vl / or_a2(M, R->phl); /* = d[[v]]/dp_l*  */
-  double er = vr * vr / or_a2(M, R->phr); /* = -d[[v]]/dp_r* */
+  double el = (vl * vl) * R->L.ia2; /* = d[[v]]/dp_l* */
+  double er = (vr * vr) * R->R.ia2; /* = -d[[v]]/dp_r* */
+  E->z = z;
   E->G1 = (psr - psl) + z * z * jv;
-  E->G2 = (E->fl + E->fr) + z * jv + (R->ur - R->ul);
+  E->G2 = (E->l.f + E->r.f) + z * jv + (R->R.u - R->L.u);
   E->J11 = -1.0 + 2.0 * z * dzl * jv + z * z * el;
   E->J12 = 1.0 + 2.0 * z * dzr * jv - z * z * er;
-  E->J21 = dfl + dzl * jv + z * el;
-  E->J22 = dfr + dzr * jv - z * er;
+  E->J21 = E->l.df + dzl * jv + z * el;
+  E->J22 = E->r.df + dzr * jv - z * er;
   if (!isfinite(E->G1) || !isfinite(E->G2)) return 0;
+  double a = E->G1 * R->izref;
+  E->m2 = a * a + E->G2 * E->G2;
   return 1;
-}
-
-static double or_merit(const or_geval *E, double zref) {
-  double a = E->G1 / zref, b = E->G2;
-  return sqrt(a * a + b * b);
 }
 
 /* HLLC-type starting value: contact speed and liquid star density from the
@@ -295,18 +311,18 @@ static double or_merit(const or_geval *E, double zref) {
  * liquid pressure law for the pressure; the vapour unknown is kept above
  * 1e-3 p_V so that it stays in the vapour state space. */
 static void or_guess(const or_material *M, const or_rp *R, double *gl, double *gr) {
-  double al = sqrt(or_a2(M, R->phl)), ar = sqrt(or_a2(M, R->phr));
-  double sl = R->ul - al, sr = R->ur + ar;
-  double num = (R->pr - R->pl) + R->rl * R->ul * (sl - R->ul) - R->rr * R->ur * (sr - R->ur);
-  double den = R->rl * (sl - R->ul) - R->rr * (sr - R->ur);
+  const or_side *Ls = &R->L, *Rs = &R->R;
+  double sl = Ls->u - Ls->a, sr = Rs->u + Rs->a;
+  double num = (Rs->p - Ls->p) + Ls->r * Ls->u * (sl - Ls->u) - Rs->r * Rs->u * (sr - Rs->u);
+  double den = Ls->r * (sl - Ls->u) - Rs->r * (sr - Rs->u);
   double ws = num / den;
   double rLs;
   if (R->phl == OR_LIQ)
-    rLs = R->rl * (sl - R->ul) / (sl - ws);
+    rLs = Ls->r * (sl - Ls->u) / (sl - ws);
   else
-    rLs = R->rr * (sr - R->ur) / (sr - ws);
+    rLs = Rs->r * (sr - Rs->u) / (sr - ws);
   double pg = or_pres(M, OR_LIQ, rLs);
-  double pV = (R->phl == OR_VAP) ? R->pl : R->pr;
+  double pV = (R->phl == OR_VAP) ? Ls->p : Rs->p;
   double pvg = pg > 1e-3 * pV ? pg : 1e-3 * pV;
   if (R->phl == OR_VAP) {
     *gl = pvg;
@@ -317,17 +333,26 @@ static void or_guess(const or_material *M, const or_rp *R, double *gl, double *g
   }
 }
 
-/* Newton-Armijo from one starting point; 1 on convergence. */
-static int or_newton(const or_material *M, const or_rp *R, double zref, double xl, double xr,
-                     int maxit, double rtol, double *ol, double *orr, or_geval *Eo, int *iters) {
+/* Newton-Armijo from one starting point; 1 on convergence.  Converged when
+ * a Newton step computed at the current point is below rtol (relative;
+ * that step is then taken), or when a full step (lambda = 1) below 1e-10
+ * (relative) passed the Armijo test -- by quadratic convergence the step
+ * after it would be negligible.  Armijo: halve lambda at most 20 times
+ * until the squared merit ((G1/zref)^2 + G2^2) drops below
+ * (1 - 1e-4 lambda)^2 times its current value; if that fails the point is
+ * kept only if the step is already below 1e-8 (round-off floor). */
+static int or_newton(const or_material *M, const or_rp *R, double xl, double xr, int maxit,
+                     double rtol, double *ol, double *orr, or_geval *Eo, int *iters) {
   or_geval E, Et;
+  const double qtol = 1e-10;
   if (!or_eval_G(M, R, xl, xr, &E)) return 0;
   int it;
   for (it = 0; it < maxit; ++it) {
     double det = E.J11 * E.J22 - E.J12 * E.J21;
     if (!(det != 0.0) || !isfinite(det)) return 0;
-    double dl = (-E.G1 * E.J22 + E.G2 * E.J12) / det;
-    double dr = (-E.G2 * E.J11 + E.G1 * E.J21) / det;
+    double idet = 1.0 / det;
+    double dl = (-E.G1 * E.J22 + E.G2 * E.J12) * idet;
+    double dr = (-E.G2 * E.J11 + E.G1 * E.J21) * idet;
     double sc = fabs(xl) > fabs(xr) ? fabs(xl) : fabs(xr);
     if (M->p0 > sc) sc = M->p0;
     double st = fabs(dl) > fabs(dr) ? fabs(dl) : fabs(dr);
@@ -345,12 +370,12 @@ static int or_newton(const or_material *M, const or_rp *R, double zref, double x
       *iters = it + 1;
       return 1;
     }
-    double m0 = or_merit(&E, zref);
     double lam = 1.0;
     int acc = 0, k;
     for (k = 0; k <= 20; ++k) {
       double tl = xl + lam * dl, tr = xr + lam * dr;
-      if (or_eval_G(M, R, tl, tr, &Et) && or_merit(&Et, zref) <= (1.0 - 1e-4 * lam) * m0) {
+      double c = 1.0 - 1e-4 * lam;
+      if (or_eval_G(M, R, tl, tr, &Et) && Et.m2 <= (c * c) * E.m2) {
         xl = tl;
         xr = tr;
         E = Et;
@@ -360,7 +385,7 @@ static int or_newton(const or_material *M, const or_rp *R, double zref, double x
       lam *= 0.5;
     }
     if (!acc) {
-      if (st <= 1e-8 * sc) { /* merit at its round-off floor */
+      if (st <= 1e-8 * sc) {
         *ol = xl;
         *orr = xr;
         *Eo = E;
@@ -368,6 +393,13 @@ static int or_newton(const or_material *M, const or_rp *R, double zref, double x
         return 1;
       }
       return 0;
+    }
+    if (k == 0 && st <= qtol * sc) {
+      *ol = xl;
+      *orr = xr;
+      *Eo = E;
+      *iters = it + 1;
+      return 1;
     }
   }
   return 0;
@@ -379,22 +411,18 @@ static int or_newton(const or_material *M, const or_rp *R, double zref, double x
 int oracle_iface_solve(const or_material *M, int phl, double rl, double ml, int phr, double rr,
                        double mr, int have_guess, double gl, double gr, int maxit, double rtol,
                        or_iface *out) {
+  memset(out, 0, sizeof(*out));
+  if (!(rl > 0.0) || !(rr > 0.0) || phl == phr) return 0;
   or_rp R;
   R.phl = phl;
   R.phr = phr;
-  R.rl = rl;
-  R.rr = rr;
-  R.ul = ml / rl;
-  R.ur = mr / rr;
-  R.pl = or_pres(M, phl, rl);
-  R.pr = or_pres(M, phr, rr);
-  memset(out, 0, sizeof(*out));
-  if (!(rl > 0.0) || !(rr > 0.0) || phl == phr) return 0;
-  double zl = rl * sqrt(or_a2(M, phl)), zr = rr * sqrt(or_a2(M, phr));
-  double zref = zl > zr ? zl : zr;
+  or_side_init(M, phl, rl, ml, &R.L);
+  or_side_init(M, phr, rr, mr, &R.R);
+  double zl = rl * R.L.a, zr = rr * R.R.a;
+  R.izref = 1.0 / (zl > zr ? zl : zr);
   double xl = 0.0, xr = 0.0;
   or_geval E;
-  int iters = 0, conv = 0, tries = 0, attempt;
+  int iters = 0, conv = 0, attempt;
   for (attempt = 0; attempt < 3 && !conv; ++attempt) {
     double sl, sr;
     if (attempt == 0) {
@@ -404,39 +432,37 @@ int oracle_iface_solve(const or_material *M, int phl, double rl, double ml, int 
     } else if (attempt == 1) {
       or_guess(M, &R, &sl, &sr);
     } else {
-      double pV = (phl == OR_VAP) ? R.pl : R.pr;
+      double pV = (phl == OR_VAP) ? R.L.p : R.R.p;
       sl = pV;
       sr = pV;
     }
     int it = 0;
-    conv = or_newton(M, &R, zref, sl, sr, maxit, rtol, &xl, &xr, &E, &it);
+    conv = or_newton(M, &R, sl, sr, maxit, rtol, &xl, &xr, &E, &it);
     iters += it;
-    ++tries;
   }
   if (!conv) return 0;
   out->iters = iters;
   out->pl = xl;
   out->pr = xr;
-  out->rl = E.rsl;
-  out->rr = E.rsr;
-  out->ul = R.ul - E.fl;
-  out->ur = R.ur + E.fr;
+  out->rl = E.l.rs;
+  out->rr = E.r.rs;
+  out->ul = R.L.u - E.l.f;
+  out->ur = R.R.u + E.r.f;
   out->z = E.z;
-  double uV, rV, pV;
+  double uV, vV, pV;
   if (phl == OR_VAP) {
     uV = out->ul;
-    rV = out->rl;
+    vV = E.l.v;
     pV = xl;
   } else {
     uV = out->ur;
-    rV = out->rr;
+    vV = E.r.v;
     pV = xr;
   }
-  out->w = uV + E.z / rV;
+  out->w = uV + E.z * vV; /* from z = -rho_V (u_V - w) */
   out->F0 = -E.z;
   out->F1 = -E.z * uV + pV;
   out->ok = 1;
-  (void)tries;
   return 1;
 }
 
@@ -447,12 +473,10 @@ int oracle_iface_G(const or_material *M, int phl, double rl, double ml, int phr,
   or_geval E;
   R.phl = phl;
   R.phr = phr;
-  R.rl = rl;
-  R.rr = rr;
-  R.ul = ml / rl;
-  R.ur = mr / rr;
-  R.pl = or_pres(M, phl, rl);
-  R.pr = or_pres(M, phr, rr);
+  or_side_init(M, phl, rl, ml, &R.L);
+  or_side_init(M, phr, rr, mr, &R.R);
+  double zl = rl * R.L.a, zr = rr * R.R.a;
+  R.izref = 1.0 / (zl > zr ? zl : zr);
   if (!or_eval_G(M, &R, psl, psr, &E)) return 0;
   out6[0] = E.G1;
   out6[1] = E.G2;
@@ -489,6 +513,8 @@ typedef struct {
   double hn[OR_MAXC];
   double hh[OR_MAXC]; /* end-of-step length predicted with the explicit speed */
   double th[OR_MAXC];
+  double i1t[OR_MAXC]; /* 1 / (1 + theta) */
+  double thr[OR_MAXC]; /* tol_i * theta_i dt: stop threshold per unit max(|W|,1) */
   int ic;   /* phase boundary lies between active cells ic and ic+1 */
   int tiny; /* active index of the tiny (or merged) cell */
   double FL[2], FR[2];
@@ -587,6 +613,8 @@ static int or_zone_build(const or_material *M, const or_params *P, const or_prob
     if (th > P->theta_nb) th = P->theta_nb;
     Z->hh[s] = hh;
     Z->th[s] = th;
+    Z->i1t[s] = 1.0 / (1.0 + th);
+    Z->thr[s] = (s == Z->tiny ? P->tol_tiny : P->tol_nb) * (th * dt);
     if (!(th > 0.0)) return 0;
   }
   /* bounding fluxes from U^n (Algorithm 1, Step 1: F_left / F_right) */
@@ -632,11 +660,18 @@ static int or_state_ok(double r, double m) { return r > 0.0 && isfinite(r) && is
 
 /* Algorithm 2 on one zone. Returns 0 on success, or a status bit.
  * *shrink_cell is set when a moving cell fell below half of its predicted
- * end-of-step length (the length its pseudo step was sized for). */
+ * end-of-step length (the length its pseudo step was sized for).
+ * Pseudo step (eq. dual time tau diff with moving lengths):
+ *   W^{l+1} = (W^l + theta rhs) / (1 + theta),
+ *   rhs = (h^n U^n - dt (F_{i+1/2}(W^l) - F_{i-1/2}(W^l))) / h^{n,l+1};
+ * stop test of Sec. 5, res_i < tol_i, evaluated without dividing:
+ *   |(1 + theta_i)(W^{l+1} - W^l)| < tol_i (theta_i dt) max(|W^l|, 1)
+ * for both components of every cell (tol_tiny on the tiny cell, tol_nb on
+ * the others); in relative mode |W^{l+1} - W^l| < tol_rel max(|W^l|, 1). */
 static int or_zone_dts(const or_material *M, const or_params *P, const or_zone *Z, double dt,
                        double *pw, double U1[][2], double *wstar, int *count, int *lmax_hit,
                        int *shrink_cell) {
-  double W[OR_MAXC][2], Wn[OR_MAXC][2], F[OR_MAXC + 1][2], hnew[OR_MAXC];
+  double W[OR_MAXC][2], Wn[OR_MAXC][2], F[OR_MAXC + 1][2], hnew[OR_MAXC], ih[OR_MAXC];
   int c, l, m = Z->m;
   double w = 0.0;
   *shrink_cell = -1;
@@ -651,42 +686,32 @@ static int or_zone_dts(const or_material *M, const or_params *P, const or_zone *
     if (!or_zone_fluxes(M, P, Z, W, F, pw, &w)) return OR_ST_NEWTON;
     for (c = 0; c < m; ++c) {
       hnew[c] = Z->hn[c] + ((double)Z->mov[c] * w) * dt;
+      ih[c] = 1.0 / hnew[c];
       if (Z->mov[c] != 0 && !(hnew[c] >= 0.5 * Z->hh[c])) {
         *shrink_cell = c;
         return OR_ST_MESH;
       }
     }
-    double rmax_nb = 0.0, r_tiny = 0.0, rrel = 0.0;
+    int conv = 1;
     for (c = 0; c < m; ++c) {
-      double th = Z->th[c];
-      double rc = 0.0, rr = 0.0;
+      double th = Z->th[c], opt = 1.0 + th;
       int q;
       for (q = 0; q < 2; ++q) {
-        double rhs = (Z->hn[c] * Z->U0[c][q] - dt * (F[c + 1][q] - F[c][q])) / hnew[c];
-        Wn[c][q] = (W[c][q] + th * rhs) / (1.0 + th);
+        double rhs = (Z->hn[c] * Z->U0[c][q] - dt * (F[c + 1][q] - F[c][q])) * ih[c];
+        Wn[c][q] = (W[c][q] + th * rhs) * Z->i1t[c];
         double d = Wn[c][q] - W[c][q];
         double sc = fabs(W[c][q]) > 1.0 ? fabs(W[c][q]) : 1.0;
-        double res = fabs((1.0 + th) * d) / ((th * dt) * sc);
-        double rel = fabs(d) / sc;
-        if (res > rc) rc = res;
-        if (rel > rr) rr = rel;
+        int ok = (P->tol_mode == 0) ? (fabs(opt * d) < Z->thr[c] * sc) : (fabs(d) < P->tol_rel * sc);
+        conv = conv && ok;
       }
       if (!or_state_ok(Wn[c][0], Wn[c][1])) return OR_ST_NONPHYS;
-      if (c == Z->tiny)
-        r_tiny = rc;
-      else if (rc > rmax_nb)
-        rmax_nb = rc;
-      if (rr > rrel) rrel = rr;
     }
     for (c = 0; c < m; ++c) {
       W[c][0] = Wn[c][0];
       W[c][1] = Wn[c][1];
     }
     cnt = l + 1;
-    if (P->tol_mode == 0)
-      stop = (rmax_nb < P->tol_nb) && (r_tiny < P->tol_tiny);
-    else
-      stop = rrel < P->tol_rel;
+    stop = conv;
     if (stop) break;
   }
   if (!stop) *lmax_hit = 1;
@@ -695,6 +720,7 @@ static int or_zone_dts(const or_material *M, const or_params *P, const or_zone *
   if (!or_zone_fluxes(M, P, Z, W, F, pw, &w)) return OR_ST_NEWTON;
   for (c = 0; c < m; ++c) {
     hnew[c] = Z->hn[c] + ((double)Z->mov[c] * w) * dt;
+    ih[c] = 1.0 / hnew[c];
     if (Z->mov[c] != 0 && !(hnew[c] >= 0.5 * Z->hh[c])) {
       *shrink_cell = c;
       return OR_ST_MESH;
@@ -703,7 +729,7 @@ static int or_zone_dts(const or_material *M, const or_params *P, const or_zone *
   for (c = 0; c < m; ++c) {
     int q;
     for (q = 0; q < 2; ++q)
-      U1[c][q] = (Z->hn[c] * Z->U0[c][q] - dt * (F[c + 1][q] - F[c][q])) / hnew[c];
+      U1[c][q] = (Z->hn[c] * Z->U0[c][q] - dt * (F[c + 1][q] - F[c][q])) * ih[c];
     if (!or_state_ok(U1[c][0], U1[c][1])) return OR_ST_NONPHYS;
   }
   *wstar = w;
@@ -1078,8 +1104,8 @@ int oracle_zone_fixed_point(const or_material *M, const or_params *Pp, int n_cel
     for (c = 0; c < Z.m; ++c) {
       double hnew = Z.hn[c] + ((double)Z.mov[c] * w) * dt;
       for (q = 0; q < 2; ++q) {
-        double rhs = (Z.hn[c] * Z.U0[c][q] - dt * (F[c + 1][q] - F[c][q])) / hnew;
-        Wn[c][q] = (W[c][q] + Z.th[c] * rhs) / (1.0 + Z.th[c]);
+        double rhs = (Z.hn[c] * Z.U0[c][q] - dt * (F[c + 1][q] - F[c][q])) * (1.0 / hnew);
+        Wn[c][q] = (W[c][q] + Z.th[c] * rhs) * Z.i1t[c];
         double sc = fabs(W[c][q]) > 1.0 ? fabs(W[c][q]) : 1.0;
         double rel = fabs(Wn[c][q] - W[c][q]) / sc;
         if (rel > rrel) rrel = rel;

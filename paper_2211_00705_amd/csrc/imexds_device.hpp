@@ -34,13 +34,16 @@ constexpr int FL_CROSS_R = 32;
 constexpr int FL_FAIL = 64;
 constexpr int FL_INACTIVE = 128;
 
-// Material: the five physical constants and three derived ones (square roots
-// and the vapour saturation density), each computed once on the host with a
-// correctly rounded operation.
+// Material: the five physical constants and derived ones, each computed once
+// on the host with one correctly rounded operation (sqrt or division) from
+// the five, in the order listed.
 struct Mat {
   double a2v, a2l, p0, rhol0, tau;
-  double av, al;  // sqrt(a2v), sqrt(a2l)
-  double rhov0;   // p0 / a2v
+  double av, al;    // sqrt(a2v), sqrt(a2l)
+  double rhov0;     // p0 / a2v
+  double ia2v, ia2l;  // 1 / a2v, 1 / a2l
+  double iav, ial;    // 1 / av, 1 / al
+  double irv0, irl0;  // 1 / rhov0, 1 / rhol0
 };
 
 struct Par {
@@ -55,8 +58,9 @@ __device__ __forceinline__ double d_pres(const Mat& M, int ph, double r) {
   return ph == VAP ? M.a2v * r : M.p0 + M.a2l * (r - M.rhol0);
 }
 
+// Inverse pressure law, used inside the interface solve (reciprocal form).
 __device__ __forceinline__ double d_rho_of_p(const Mat& M, int ph, double p) {
-  return ph == VAP ? p / M.a2v : M.rhol0 + (p - M.p0) / M.a2l;
+  return ph == VAP ? p * M.ia2v : M.rhol0 + (p - M.p0) * M.ia2l;
 }
 
 // Natural logarithm of a positive finite double: x = 2^e m with m in
@@ -156,155 +160,114 @@ __device__ __forceinline__ void d_bflux(const Mat& M, int ph, bool right_end, in
 // ---------------------------------------------------------------------------
 // two-phase interface Riemann problem
 // ---------------------------------------------------------------------------
-struct RP {
-  int phl, phr;
-  double rl, ul, pl, rr, ur, pr;
+// Per-side data of one solve: the side's state and L_K = ln(rho_K / rho_K,sat),
+// so that one logarithm per side and evaluation, L* = ln(rho* / rho_K,sat),
+// yields both the Gibbs energy a^2 L* and the rarefaction wave a (L* - L_K).
+struct Side {
+  int ph;
+  double r, u, p, LK;
 };
 
+struct RP {
+  int phl;
+  Side L, Rt;
+  double izref;  // 1 / max(rho_l a_l, rho_r a_r)
+};
+
+// What one evaluation of G leaves behind: G, its Jacobian, the squared merit
+// (G1 / zref)^2 + G2^2, z, and per side rho*, v* and f_K.
 struct GEval {
-  double G1, G2, J11, J12, J21, J22;
-  double rsl, rsr, fl, fr, z;
+  double G1, G2, J11, J12, J21, J22, m2, z;
+  double rsl, vl, fl, rsr, vr, fr;
 };
 
 struct IfaceOut {
   double pl, pr, rl, rr, ul, ur, z, w, F0, F1;
-  int iters;
 };
 
-// Outer-wave function f_K(p*) and its derivative; shock branch in the form
-// a (rho* - rho_K) / sqrt(rho_K rho*), exact for pressure laws affine in rho.
-__device__ __forceinline__ bool d_wave(const Mat& M, int ph, double rhoK, double pK, double ps,
-                                       double& f, double& df, double& rs) {
-  double r = d_rho_of_p(M, ph, ps);
+__device__ __forceinline__ void d_side(const Mat& M, int ph, double r, double m, Side& S) {
+  S.ph = ph;
+  S.r = r;
+  S.u = m / r;
+  S.p = d_pres(M, ph, r);
+  S.LK = d_log(r * (ph == VAP ? M.irv0 : M.irl0));
+}
+
+// Outer wave of one side at star pressure ps: rho*, v*, Gibbs energy, f_K and
+// df_K/dp*.  Shock branch sqrt(-[[p]][[v]]) written a (rho* - rho_K) /
+// sqrt(rho_K rho*), exact for pressure laws affine in rho; rarefaction branch:
+// the integral of v/a, a ln(rho*/rho_K).
+__device__ __forceinline__ bool d_wave(const Mat& M, const Side& S, double ps, double& rs,
+                                       double& v, double& g, double& f, double& df) {
+  const bool vap = S.ph == VAP;
+  double r = d_rho_of_p(M, S.ph, ps);
   if (!(r > 0.0) || !d_finite(r)) return false;
-  double a = d_a(M, ph);
+  v = 1.0 / r;
+  double L = d_log(r * (vap ? M.irv0 : M.irl0));
   rs = r;
-  if (ps > pK) {
-    double g = sqrt(rhoK * r);
-    f = a * (r - rhoK) / g;
-    df = (r + rhoK) / ((2.0 * a * r) * g);
+  g = (vap ? M.a2v : M.a2l) * L;
+  const double a = vap ? M.av : M.al;
+  const double ia = vap ? M.iav : M.ial;
+  if (ps > S.p) {
+    double ig = 1.0 / sqrt(S.r * r);
+    f = (a * (r - S.r)) * ig;
+    df = ((r + S.r) * ig) * (v * (0.5 * ia));
   } else {
-    f = a * d_log(r / rhoK);
-    df = 1.0 / (r * a);
+    f = a * (L - S.LK);
+    df = v * ia;
   }
   return true;
 }
 
-// z(p_l*, p_r*) from A z^2 - z + C = 0 (root continuous at A = 0) and dz/dp.
-__device__ __forceinline__ bool d_kinetic(const Mat& M, int phl, int phr, double rsl, double rsr,
-                                          double psl, double psr, double& z, double& dzl,
-                                          double& dzr) {
-  double pV = (phl == VAP) ? psl : psr;
-  double q = M.tau * pV;
-  double vl = 1.0 / rsl, vr = 1.0 / rsr;
-  double jg = d_gibbs(M, phr, rsr) - d_gibbs(M, phl, rsl);
-  double jv2 = vr * vr - vl * vl;
-  double A = 0.5 * q * jv2;
-  double C = q * jg;
-  double D = 1.0 - 4.0 * A * C;
-  if (!(D >= 0.0) || !d_finite(D)) return false;
-  double sD = sqrt(D);
-  double zz = 2.0 * C / (1.0 + sD);
-  double a2l = d_a2(M, phl), a2r = d_a2(M, phr);
-  double dAl = 0.5 * q * (2.0 * vl * vl * vl / a2l);
-  double dAr = 0.5 * q * (-2.0 * vr * vr * vr / a2r);
-  double dCl = q * (-vl);
-  double dCr = q * vr;
-  if (phl == VAP) {
-    dAl += 0.5 * M.tau * jv2;
-    dCl += M.tau * jg;
-  } else {
-    dAr += 0.5 * M.tau * jv2;
-    dCr += M.tau * jg;
-  }
-  dzl = (dAl * zz * zz + dCl) / sD;
-  dzr = (dAr * zz * zz + dCr) / sD;
-  z = zz;
-  return true;
-}
-
+// G(p_l*, p_r*) and its Jacobian.  z solves A z^2 - z + C = 0 with
+// A = tau p_V [[v^2]] / 2, C = tau p_V [[g]] (root continuous at A = 0);
+// dz/dp from differentiating that relation, using 2 A z - 1 = -sqrt(D).
 __device__ __forceinline__ bool d_eval_G(const Mat& M, const RP& R, double psl, double psr,
                                          GEval& E) {
-  double dfl, dfr, dzl, dzr;
-  if (!d_wave(M, R.phl, R.rl, R.pl, psl, E.fl, dfl, E.rsl)) return false;
-  if (!d_wave(M, R.phr, R.rr, R.pr, psr, E.fr, dfr, E.rsr)) return false;
-  if (!d_kinetic(M, R.phl, R.phr, E.rsl, E.rsr, psl, psr, E.z, dzl, dzr)) return false;
-  double z = E.z;
-  double vl = 1.0 / E.rsl, vr = 1.0 / E.rsr;
-  double jv = vr - vl;
-  double el = vl * vl / d_a2(M, R.phl);
-  double er = vr * vr / d_a2(M, R.phr);
+  double gl, gr, dfl, dfr;
+  if (!d_wave(M, R.L, psl, E.rsl, E.vl, gl, E.fl, dfl)) return false;
+  if (!d_wave(M, R.Rt, psr, E.rsr, E.vr, gr, E.fr, dfr)) return false;
+  const double vl = E.vl, vr = E.vr;
+  const bool lvap = R.phl == VAP;
+  const double ia2l = lvap ? M.ia2v : M.ia2l, ia2r = lvap ? M.ia2l : M.ia2v;
+  const double pV = lvap ? psl : psr;
+  const double q = M.tau * pV;
+  const double jg = gr - gl;
+  const double jv2 = vr * vr - vl * vl;
+  const double A = 0.5 * q * jv2;
+  const double C = q * jg;
+  const double D = 1.0 - 4.0 * A * C;
+  if (!(D >= 0.0) || !d_finite(D)) return false;
+  const double sD = sqrt(D);
+  const double isD = 1.0 / sD;
+  const double z = 2.0 * C / (1.0 + sD);
+  double dAl = q * ((vl * vl * vl) * ia2l);
+  double dAr = -(q * ((vr * vr * vr) * ia2r));
+  double dCl = -(q * vl);
+  double dCr = q * vr;
+  if (lvap) {
+    dAl += (0.5 * M.tau) * jv2;
+    dCl += M.tau * jg;
+  } else {
+    dAr += (0.5 * M.tau) * jv2;
+    dCr += M.tau * jg;
+  }
+  const double dzl = (dAl * z * z + dCl) * isD;
+  const double dzr = (dAr * z * z + dCr) * isD;
+  const double jv = vr - vl;
+  const double el = (vl * vl) * ia2l;
+  const double er = (vr * vr) * ia2r;
+  E.z = z;
   E.G1 = (psr - psl) + z * z * jv;
-  E.G2 = (E.fl + E.fr) + z * jv + (R.ur - R.ul);
+  E.G2 = (E.fl + E.fr) + z * jv + (R.Rt.u - R.L.u);
   E.J11 = -1.0 + 2.0 * z * dzl * jv + z * z * el;
   E.J12 = 1.0 + 2.0 * z * dzr * jv - z * z * er;
   E.J21 = dfl + dzl * jv + z * el;
   E.J22 = dfr + dzr * jv - z * er;
-  return d_finite(E.G1) && d_finite(E.G2);
-}
-
-__device__ __forceinline__ double d_merit(const GEval& E, double zref) {
-  double a = E.G1 / zref, b = E.G2;
-  return sqrt(a * a + b * b);
-}
-
-// Newton-Armijo from one start: full step accepted once the relative step is
-// below rtol; otherwise halve the step (at most 20 times) until the merit
-// decreases by the factor (1 - 1e-4 lambda); if no halving works the point
-// is accepted only when the step is already below 1e-8 (round-off floor).
-__device__ bool d_newton(const Mat& M, const RP& R, double zref, double xl, double xr, int maxit,
-                         double rtol, double& ol, double& orr, GEval& Eo, int& iters) {
-  GEval E, Et;
-  if (!d_eval_G(M, R, xl, xr, E)) return false;
-  for (int it = 0; it < maxit; ++it) {
-    double det = E.J11 * E.J22 - E.J12 * E.J21;
-    if (!(det != 0.0) || !d_finite(det)) return false;
-    double dl = (-E.G1 * E.J22 + E.G2 * E.J12) / det;
-    double dr = (-E.G2 * E.J11 + E.G1 * E.J21) / det;
-    double sc = fabs(xl) > fabs(xr) ? fabs(xl) : fabs(xr);
-    if (M.p0 > sc) sc = M.p0;
-    double st = fabs(dl) > fabs(dr) ? fabs(dl) : fabs(dr);
-    if (!d_finite(st)) return false;
-    if (st <= rtol * sc) {
-      double tl = xl + dl, tr = xr + dr;
-      if (d_eval_G(M, R, tl, tr, Et)) {
-        xl = tl;
-        xr = tr;
-        E = Et;
-      }
-      ol = xl;
-      orr = xr;
-      Eo = E;
-      iters += it + 1;
-      return true;
-    }
-    double m0 = d_merit(E, zref);
-    double lam = 1.0;
-    bool acc = false;
-    for (int k = 0; k <= 20; ++k) {
-      double tl = xl + lam * dl, tr = xr + lam * dr;
-      if (d_eval_G(M, R, tl, tr, Et) && d_merit(Et, zref) <= (1.0 - 1e-4 * lam) * m0) {
-        xl = tl;
-        xr = tr;
-        E = Et;
-        acc = true;
-        break;
-      }
-      lam *= 0.5;
-    }
-    if (!acc) {
-      if (st <= 1e-8 * sc) {
-        ol = xl;
-        orr = xr;
-        Eo = E;
-        iters += it + 1;
-        return true;
-      }
-      return false;
-    }
-  }
-  iters += maxit;
-  return false;
+  if (!d_finite(E.G1) || !d_finite(E.G2)) return false;
+  const double a = E.G1 * R.izref;
+  E.m2 = a * a + E.G2 * E.G2;
+  return true;
 }
 
 // HLLC-type start (eq. HLLC:2p_nopt, mirrored when the liquid is on the left):
@@ -312,14 +275,14 @@ __device__ bool d_newton(const Mat& M, const RP& R, double zref, double xl, doub
 // the pressure; the vapour unknown is kept at or above 1e-3 of the vapour
 // pressure.
 __device__ __forceinline__ void d_guess(const Mat& M, const RP& R, double& gl, double& gr) {
-  double al = d_a(M, R.phl), ar = d_a(M, R.phr);
-  double sl = R.ul - al, sr = R.ur + ar;
-  double num = (R.pr - R.pl) + R.rl * R.ul * (sl - R.ul) - R.rr * R.ur * (sr - R.ur);
-  double den = R.rl * (sl - R.ul) - R.rr * (sr - R.ur);
+  const Side &Ls = R.L, &Rs = R.Rt;
+  double sl = Ls.u - d_a(M, Ls.ph), sr = Rs.u + d_a(M, Rs.ph);
+  double num = (Rs.p - Ls.p) + Ls.r * Ls.u * (sl - Ls.u) - Rs.r * Rs.u * (sr - Rs.u);
+  double den = Ls.r * (sl - Ls.u) - Rs.r * (sr - Rs.u);
   double ws = num / den;
-  double rLs = (R.phl == LIQ) ? R.rl * (sl - R.ul) / (sl - ws) : R.rr * (sr - R.ur) / (sr - ws);
+  double rLs = (R.phl == LIQ) ? Ls.r * (sl - Ls.u) / (sl - ws) : Rs.r * (sr - Rs.u) / (sr - ws);
   double pg = d_pres(M, LIQ, rLs);
-  double pV = (R.phl == VAP) ? R.pl : R.pr;
+  double pV = (R.phl == VAP) ? Ls.p : Rs.p;
   double pvg = pg > 1e-3 * pV ? pg : 1e-3 * pV;
   if (R.phl == VAP) {
     gl = pvg;
@@ -330,65 +293,148 @@ __device__ __forceinline__ void d_guess(const Mat& M, const RP& R, double& gl, d
   }
 }
 
-// Interface solve from conservative states; starts tried in order: the warm
-// start (if have_guess), the HLLC-type guess, both unknowns at the vapour
-// pressure.  Returns false if none converges.
-__device__ bool d_iface_solve(const Mat& M, int maxit, double rtol, int phl, double rl, double ml,
-                              int phr, double rr, double mr, bool have_guess, double gl,
-                              double gr, IfaceOut& out) {
+// Interface solve by Newton-Armijo from conservative states.  Starts are
+// tried in order (the warm start if have_guess, the HLLC-type guess, both
+// unknowns at the vapour pressure) until one converges.  From an accepted
+// point: a Newton step below rtol (relative) is taken and the solve ends;
+// otherwise the step is halved (at most 20 times) until the squared merit
+// falls below (1 - 1e-4 lambda)^2 times the current one; a full step
+// (lambda = 1) below 1e-10 ends the solve at the new point (by quadratic
+// convergence the next step would be negligible); if no halving passes, the point is kept when
+// the step is already below 1e-8 (round-off floor), else the start fails;
+// at most maxit steps per start.  Written as one loop with a single
+// evaluation site so that lanes at different stages share it.
+__device__ __forceinline__ bool d_iface_solve(const Mat& M, int maxit, double rtol, int phl,
+                                              double rl, double ml, int phr, double rr, double mr,
+                                              bool have_guess, double gl, double gr,
+                                              IfaceOut& out) {
   if (!(rl > 0.0) || !(rr > 0.0) || phl == phr) return false;
   RP R;
   R.phl = phl;
-  R.phr = phr;
-  R.rl = rl;
-  R.rr = rr;
-  R.ul = ml / rl;
-  R.ur = mr / rr;
-  R.pl = d_pres(M, phl, rl);
-  R.pr = d_pres(M, phr, rr);
-  double zl = rl * d_a(M, phl), zr = rr * d_a(M, phr);
-  double zref = zl > zr ? zl : zr;
-  double xl = 0.0, xr = 0.0;
-  GEval E;
-  int iters = 0;
-  bool conv = false;
-  for (int attempt = 0; attempt < 3 && !conv; ++attempt) {
-    double sl, sr;
-    if (attempt == 0) {
-      if (!have_guess) continue;
-      sl = gl;
-      sr = gr;
-    } else if (attempt == 1) {
-      d_guess(M, R, sl, sr);
-    } else {
-      double pV = (phl == VAP) ? R.pl : R.pr;
-      sl = pV;
-      sr = pV;
-    }
-    conv = d_newton(M, R, zref, sl, sr, maxit, rtol, xl, xr, E, iters);
+  d_side(M, phl, rl, ml, R.L);
+  d_side(M, phr, rr, mr, R.Rt);
+  const double zl = rl * d_a(M, phl), zr = rr * d_a(M, phr);
+  R.izref = 1.0 / (zl > zr ? zl : zr);
+  const double qtol = 1e-10;
+  int attempt = have_guess ? 0 : 1;
+  double tl, tr;  // point to evaluate next
+  if (attempt == 0) {
+    tl = gl;
+    tr = gr;
+  } else {
+    d_guess(M, R, tl, tr);
   }
-  if (!conv) return false;
-  out.iters = iters;
+  // accepted point and what survives it: squared merit and the outputs
+  double xl = 0.0, xr = 0.0, m2 = 0.0, z = 0.0, rsl = 0.0, vl = 0.0, fl = 0.0, rsr = 0.0,
+         vr = 0.0, fr = 0.0;
+  double dl = 0.0, dr = 0.0, st = 0.0, sc = 0.0, lam = 1.0;
+  int k = 0, it = 0, mode = 0;  // 0: start point, 1: Armijo trial, 2: final step
+  for (;;) {
+    GEval Et;
+    const bool valid = d_eval_G(M, R, tl, tr, Et);
+    bool done = false, take = false, next = false, acc = false;
+    if (mode == 0) {
+      if (!valid) {
+        next = true;
+      } else {
+        acc = true;
+        it = 0;
+        take = true;
+      }
+    } else if (mode == 1) {
+      const double c = 1.0 - 1e-4 * lam;
+      if (valid && Et.m2 <= (c * c) * m2) {
+        acc = true;
+        if (k == 0 && st <= qtol * sc) {
+          done = true;
+        } else {
+          ++it;
+          take = true;
+        }
+      } else {
+        lam *= 0.5;
+        ++k;
+        if (k > 20) {
+          if (st <= 1e-8 * sc)
+            done = true;
+          else
+            next = true;
+        } else {
+          tl = xl + lam * dl;
+          tr = xr + lam * dr;
+        }
+      }
+    } else {
+      acc = valid;
+      done = true;
+    }
+    if (acc) {
+      xl = tl;
+      xr = tr;
+      m2 = Et.m2;
+      z = Et.z;
+      rsl = Et.rsl;
+      vl = Et.vl;
+      fl = Et.fl;
+      rsr = Et.rsr;
+      vr = Et.vr;
+      fr = Et.fr;
+    }
+    if (take) {
+      const double det = Et.J11 * Et.J22 - Et.J12 * Et.J21;
+      if (it >= maxit || !(det != 0.0) || !d_finite(det)) {
+        next = true;
+      } else {
+        const double idet = 1.0 / det;
+        dl = (-Et.G1 * Et.J22 + Et.G2 * Et.J12) * idet;
+        dr = (-Et.G2 * Et.J11 + Et.G1 * Et.J21) * idet;
+        sc = fabs(xl) > fabs(xr) ? fabs(xl) : fabs(xr);
+        if (M.p0 > sc) sc = M.p0;
+        st = fabs(dl) > fabs(dr) ? fabs(dl) : fabs(dr);
+        if (!d_finite(st)) {
+          next = true;
+        } else {
+          mode = st <= rtol * sc ? 2 : 1;
+          lam = 1.0;
+          k = 0;
+          tl = xl + dl;
+          tr = xr + dr;
+        }
+      }
+    }
+    if (done) break;
+    if (next) {
+      ++attempt;
+      if (attempt >= 3) return false;
+      if (attempt == 1) {
+        d_guess(M, R, tl, tr);
+      } else {
+        tl = (phl == VAP) ? R.L.p : R.Rt.p;
+        tr = tl;
+      }
+      mode = 0;
+    }
+  }
   out.pl = xl;
   out.pr = xr;
-  out.rl = E.rsl;
-  out.rr = E.rsr;
-  out.ul = R.ul - E.fl;
-  out.ur = R.ur + E.fr;
-  out.z = E.z;
-  double uV, rV, pV;
+  out.rl = rsl;
+  out.rr = rsr;
+  out.ul = R.L.u - fl;
+  out.ur = R.Rt.u + fr;
+  out.z = z;
+  double uV, vV, pV;
   if (phl == VAP) {
     uV = out.ul;
-    rV = out.rl;
+    vV = vl;
     pV = xl;
   } else {
     uV = out.ur;
-    rV = out.rr;
+    vV = vr;
     pV = xr;
   }
-  out.w = uV + E.z / rV;
-  out.F0 = -E.z;
-  out.F1 = -E.z * uV + pV;
+  out.w = uV + z * vV;
+  out.F0 = -z;
+  out.F1 = -z * uV + pV;
   return true;
 }
 

@@ -1,13 +1,13 @@
 // imexds_kernels.hip -- gfx950 kernels of one IMEX-DS physical step.
 //
 // One step of every problem is three launches:
-//   k_bulk   (tiles of cells)  : Algorithm 1 Step 1 -- HLL fluxes on every face
-//                                next to a cell outside the implicit zones and
+//   k_bulk   (tiles of cells)  : Algorithm 1 Step 1 -- HLL fluxes on the faces
+//                                of every cell outside the implicit zones and
 //                                the explicit update of those cells; fused
 //                                epilogue: per-problem max(|u| + a) of the new
 //                                state (CFL, eq. cfl_cond:unif) via one 64-bit
-//                                atomicMax per workgroup.
-//   k_zone   (one lane / zone) : prediction of the boundary speed, merge test,
+//                                atomicMax per wave.
+//   k_zone   (lanes pull zones): prediction of the boundary speed, merge test,
 //                                Algorithm 2 (Part 1 dual time stepping with
 //                                local pseudo steps, Part 2 conservative update
 //                                with moving cut cells), interface advance and
@@ -57,19 +57,25 @@ __device__ __forceinline__ unsigned long long d_wave_max_u64(unsigned long long 
 // ---------------------------------------------------------------------------
 // bulk sweep
 // ---------------------------------------------------------------------------
-template <int CPT>
+// A workgroup is 4 waves; each wave handles R rows of 62 cells.  In a row,
+// lane j holds cell base-1+j (lane 0 and lane 63 are the halo), computes the
+// flux on the face to its right from its own and its right neighbour's
+// values (exchanged with a lane shuffle), takes the flux of its left face
+// from lane j-1, and lanes 1..62 update their cell.  No LDS tile, no
+// barrier in the sweep: occupancy stays high and all R rows' loads are in
+// flight together.
+template <int R>
 __global__ __launch_bounds__(256) void k_bulk(StepArgs A, int tile_begin) {
-  constexpr int T = 256 * CPT;
-  __shared__ double s_r[T + 2], s_m[T + 2], s_u[T + 2], s_p[T + 2];
-  __shared__ double s_F0[T + 1], s_F1[T + 1];
+  constexpr int OUT = 62;
   __shared__ int s_zlo[MAX_IF_PER_PROB], s_zhi[MAX_IF_PER_PROB], s_sR[MAX_IF_PER_PROB];
-  __shared__ unsigned long long s_red[4];
 
   const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = tid >> 6;
   const int tile = tile_begin + blockIdx.x;
   const int p = A.tile_prob[tile];
   const int t0 = A.tile_start[tile];
-  const int len = A.tile_len[tile];
+  const int tend = t0 + A.tile_len[tile];
   const long long so = A.slot_off[p];
   const int ns = (int)(A.slot_off[p + 1] - so);
   const double* __restrict__ r0 = A.rho0 + so;
@@ -79,9 +85,9 @@ __global__ __launch_bounds__(256) void k_bulk(StepArgs A, int tile_begin) {
   const double dt = A.dt[p];
 
   if (dt == 0.0) {  // frozen or finished: carry the state over
-    for (int c = tid; c < len; c += 256) {
-      r1[t0 + c] = r0[t0 + c];
-      m1[t0 + c] = m0[t0 + c];
+    for (int c = t0 + tid; c < tend; c += 256) {
+      r1[c] = r0[c];
+      m1[c] = m0[c];
     }
     return;
   }
@@ -91,6 +97,7 @@ __global__ __launch_bounds__(256) void k_bulk(StepArgs A, int tile_begin) {
   const int i0 = A.iface_off[p];
   const int nif = A.iface_off[p + 1] - i0;
   const int pf = A.phase_first[p];
+  const bool wallL = A.par.bc_left == 0, wallR = A.par.bc_right == 0;
   if (tid < nif) {
     int zlo, zhi;
     bool tr;
@@ -102,83 +109,60 @@ __global__ __launch_bounds__(256) void k_bulk(StepArgs A, int tile_begin) {
   }
   __syncthreads();
 
-  auto phase_of = [&](int s) {
-    int ph = pf;
-    for (int j = 0; j < nif; ++j) ph ^= (s_sR[j] <= s) ? 1 : 0;
-    return ph;
-  };
-  auto in_zone = [&](int s) {
-    bool z = false;
-    for (int j = 0; j < nif; ++j) z = z || (s >= s_zlo[j] && s <= s_zhi[j]);
-    return z;
-  };
-
-  // stage the tile and a one-cell halo (ghost states at the domain ends)
-  for (int i = tid; i < len + 2; i += 256) {
-    int s = t0 - 1 + i;
-    double r, m;
-    int ph;
-    if (s < 0) {
-      r = r0[0];
-      m = (A.par.bc_left == 0) ? -m0[0] : m0[0];
-      ph = phase_of(0);
-    } else if (s >= ns) {
-      r = r0[ns - 1];
-      m = (A.par.bc_right == 0) ? -m0[ns - 1] : m0[ns - 1];
-      ph = phase_of(ns - 1);
-    } else {
-      r = r0[s];
-      m = m0[s];
-      ph = phase_of(s);
-    }
-    s_r[i] = r;
-    s_m[i] = m;
-    s_u[i] = m / r;
-    s_p[i] = d_pres(M, ph, r);
+  // loads of all rows first
+  double rr[R], mm[R];
+  int ss[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    int s = t0 + (wv * R + r) * OUT - 1 + lane;
+    ss[r] = s;
+    int se = s < 0 ? 0 : (s > ns - 1 ? ns - 1 : s);
+    double rv = r0[se], mv = m0[se];
+    if ((s < 0 && wallL) || (s >= ns && wallR)) mv = -mv;
+    rr[r] = rv;
+    mm[r] = mv;
   }
-  __syncthreads();
-
-  // face i lies between staged entries i and i+1 (slots t0-1+i and t0+i)
-  for (int i = tid; i < len + 1; i += 256) {
-    int sl = t0 - 1 + i, sr = t0 + i;
-    bool need = (sl >= 0 && !in_zone(sl)) || (sr < ns && !in_zone(sr));
-    if (need) {
-      int ph = phase_of(sl >= 0 ? sl : sr);
-      double F0, F1;
-      d_hll_prim(d_a(M, ph), s_r[i], s_m[i], s_u[i], s_p[i], s_r[i + 1], s_m[i + 1], s_u[i + 1],
-                 s_p[i + 1], F0, F1);
-      s_F0[i] = F0;
-      s_F1[i] = F1;
-    }
-  }
-  __syncthreads();
 
   unsigned long long vmax = 0;
-  for (int c = tid; c < len; c += 256) {
-    int s = t0 + c;
-    if (in_zone(s)) continue;
-    double r = s_r[c + 1] - lam * (s_F0[c + 1] - s_F0[c]);
-    double m = s_m[c + 1] - lam * (s_F1[c + 1] - s_F1[c]);
-    r1[s] = r;
-    m1[s] = m;
-    unsigned long long b = d_speed_bits(M, phase_of(s), r, m);
-    vmax = b > vmax ? b : vmax;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int s = ss[r];
+    const int rowbase = t0 + (wv * R + r) * OUT;
+    if (rowbase >= tend) break;  // uniform over the wave
+    const int se = s < 0 ? 0 : (s > ns - 1 ? ns - 1 : s);
+    int ph = pf;
+    bool zone = false;
+    for (int j = 0; j < nif; ++j) {
+      ph ^= (s_sR[j] <= se) ? 1 : 0;
+      zone = zone || (s >= s_zlo[j] && s <= s_zhi[j]);
+    }
+    const double rho = rr[r], mom = mm[r];
+    const double u = mom / rho;
+    const double pr = d_pres(M, ph, rho);
+    const double rhoR = __shfl_down(rho, 1, 64);
+    const double momR = __shfl_down(mom, 1, 64);
+    const double uR = __shfl_down(u, 1, 64);
+    const double prR = __shfl_down(pr, 1, 64);
+    double F0, F1;  // flux on the face between s and s+1 (phase of s)
+    d_hll_prim(d_a(M, ph), rho, mom, u, pr, rhoR, momR, uR, prR, F0, F1);
+    const double G0 = __shfl_up(F0, 1, 64);
+    const double G1 = __shfl_up(F1, 1, 64);
+    if (lane >= 1 && lane <= OUT && s < tend && !zone) {
+      double rn = rho - lam * (F0 - G0);
+      double mn = mom - lam * (F1 - G1);
+      r1[s] = rn;
+      m1[s] = mn;
+      unsigned long long b = d_speed_bits(M, ph, rn, mn);
+      vmax = b > vmax ? b : vmax;
+    }
   }
   vmax = d_wave_max_u64(vmax);
-  if ((tid & 63) == 0) s_red[tid >> 6] = vmax;
-  __syncthreads();
-  if (tid == 0) {
-    unsigned long long v = s_red[0];
-    for (int w = 1; w < 4; ++w) v = s_red[w] > v ? s_red[w] : v;
-    if (v) atomicMax(A.S_acc + p, v);
-  }
+  if (lane == 0 && vmax) atomicMax(A.S_acc + p, vmax);
 }
 
 // CFL over all slots of the current state (first step after a state load).
-template <int CPT>
 __global__ __launch_bounds__(256) void k_cfl(StepArgs A, int tile_begin) {
   __shared__ int s_sR[MAX_IF_PER_PROB];
-  __shared__ unsigned long long s_red[4];
   const int tid = threadIdx.x;
   const int tile = tile_begin + blockIdx.x;
   const int p = A.tile_prob[tile];
@@ -199,479 +183,443 @@ __global__ __launch_bounds__(256) void k_cfl(StepArgs A, int tile_begin) {
     vmax = b > vmax ? b : vmax;
   }
   vmax = d_wave_max_u64(vmax);
-  if ((tid & 63) == 0) s_red[tid >> 6] = vmax;
-  __syncthreads();
-  if (tid == 0) {
-    unsigned long long v = s_red[0];
-    for (int w = 1; w < 4; ++w) v = s_red[w] > v ? s_red[w] : v;
-    if (v) atomicMax(A.S_acc + p, v);
-  }
+  if ((tid & 63) == 0 && vmax) atomicMax(A.S_acc + p, vmax);
 }
 
 // ---------------------------------------------------------------------------
 // implicit zones
 // ---------------------------------------------------------------------------
-// Interface flux of a zone iterate; warm start in/out through pw.
-__device__ __noinline__ bool d_zone_iface(const Mat& M, const Par& P, int phl, double rl, double ml,
-                                          int phr, double rr, double mr, double& pw0, double& pw1,
-                                          double& F0, double& F1, double& w) {
-  IfaceOut o;
-  if (!d_iface_solve(M, P.newton_maxit, P.newton_rtol, phl, rl, ml, phr, rr, mr, true, pw0, pw1,
-                     o))
-    return false;
-  pw0 = o.pl;
-  pw1 = o.pr;
-  F0 = o.F0;
-  F1 = o.F1;
-  w = o.w;
-  return true;
-}
-
+// Each active lane runs a state machine: fetch a zone (atomic counter), solve
+// the predicting Riemann problem, then one pseudo-time iteration per pass
+// (each pass ends with Part 2 when the stop test or lmax says so), then the
+// write-back, and fetch the next zone.  Every pass calls the interface solver
+// exactly once, so all lanes of a wave execute the same solver code together
+// whatever zone or iteration they are at.  Zone cells are addressed by their
+// position 0..nr-1 in the slot range zlo..zhi; the merged-away piece (if
+// any) is position `skip` and its content sits in position `into`.
 template <int ZH>
 __global__ __launch_bounds__(64) void k_zone(StepArgs A, int if_begin, int if_end) {
   constexpr int MC = 2 * ZH + 1;
-  const int lane = threadIdx.x;
-  if (lane >= A.zones_per_group) return;
-  const int k = if_begin + blockIdx.x * A.zones_per_group + lane;
-  if (k >= if_end) return;
+  constexpr int S_FETCH = 0, S_PRED = 1, S_ITER = 2, S_EXIT = 3;
+  if ((int)threadIdx.x >= A.zones_per_group) return;
   const Mat& M = A.mat;
   const Par& P = A.par;
-  const int p = A.iface_prob[k];
-  const int kk = A.iface_local[k];
-  const double dt = A.dt[p];
-  int home = A.rec_home0[k];
-  double hl = A.rec_hl0[k];
-  double pwa = A.rec_pw0[2 * k], pwb = A.rec_pw0[2 * k + 1];
-  int warm = A.rec_warm0[k];
-  int row = -1;
-  if (A.log_count && A.log_row) {
-    row = *A.log_row;
-    if (row >= A.log_max) row = -1;
-  }
-  if (dt == 0.0) {
-    A.rec_home1[k] = home;
-    A.rec_hl1[k] = hl;
-    A.rec_pw1[2 * k] = pwa;
-    A.rec_pw1[2 * k + 1] = pwb;
-    A.rec_warm1[k] = warm;
-    if (row >= 0) {
-      long long o = (long long)row * A.n_iface + k;
-      A.log_count[o] = 0;
-      A.log_flags[o] = FL_INACTIVE;
-      A.log_zlo[o] = -1;
-    }
-    return;
-  }
-  const long long so = A.slot_off[p];
-  const int ns = (int)(A.slot_off[p + 1] - so);
-  const double h = A.h[p];
-  const double* __restrict__ r0 = A.rho0 + so;
-  const double* __restrict__ m0 = A.mom0 + so;
-  double* __restrict__ r1 = A.rho1 + so;
-  double* __restrict__ m1 = A.mom1 + so;
-  const int sL = home + kk, sR = sL + 1;
-  if (sL < 0 || sR >= ns) {  // interface record outside its problem: freeze, touch nothing
-    atomicOr(A.fail_acc + p, ST_MESH);
-    A.rec_home1[k] = home;
-    A.rec_hl1[k] = hl;
-    A.rec_pw1[2 * k] = pwa;
-    A.rec_pw1[2 * k + 1] = pwb;
-    A.rec_warm1[k] = warm;
-    return;
-  }
-  const int phl = A.phase_first[p] ^ (kk & 1), phr = phl ^ 1;
-  int zlo, zhi;
-  bool tr;
-  d_zone_range(sL, hl, h, ZH, ns, zlo, zhi, tr);
-  const int nr = zhi - zlo + 1;
-  const int iL = sL - zlo, iR = iL + 1;
 
-  double Ur[MC], Um[MC];
-#pragma unroll
-  for (int i = 0; i < MC; ++i) {
-    if (i < nr) {
-      Ur[i] = r0[zlo + i];
-      Um[i] = m0[zlo + i];
-    } else {
-      Ur[i] = 1.0;
-      Um[i] = 0.0;
-    }
-  }
-  // bounding fluxes from U^n (Algorithm 1: F_left, F_right)
-  double FL0, FL1, FR0, FR1;
-  {
-    int phz = (zlo <= sL) ? phl : phr;
-    if (zlo == 0)
-      d_bflux(M, phz, false, P.bc_left, r0[0], m0[0], FL0, FL1);
-    else
-      d_hll(M, phz, r0[zlo - 1], m0[zlo - 1], r0[zlo], m0[zlo], FL0, FL1);
-    int phe = (zhi <= sL) ? phl : phr;
-    if (zhi == ns - 1)
-      d_bflux(M, phe, true, P.bc_right, r0[ns - 1], m0[ns - 1], FR0, FR1);
-    else
-      d_hll(M, phe, r0[zhi], m0[zhi], r0[zhi + 1], m0[zhi + 1], FR0, FR1);
-  }
-
-  int status = 0, flags = tr ? FL_TINY_RIGHT : 0, count = 0;
-  bool merge = false, redo = false, lmax_hit = false;
-  double wstar = 0.0;
-  double U1r[MC], U1m[MC];
-  int skip = -1, into = -1;
-  // prediction of the boundary speed from U^n
+  int k = 0, p = 0, kk = 0, ns = 0, sL = 0, zlo = 0, nr = 0, iL = 0, iR = 1;
+  long long so = 0;
+  double h = 0.0, dt = 0.0;
+  int phl = 0, phr = 1;
+  bool tr = false;
+  int home = 0, warm = 0;
+  double hl = 0.0, rpw0 = 0.0, rpw1 = 0.0;
+  double Ur[MC], Um[MC];  // U^n over the zone range
+  double FL0 = 0.0, FL1 = 0.0, FR0 = 0.0, FR1 = 0.0;
   double Ipl = 0.0, Ipr = 0.0, wp = 0.0;
-  {
-    double F0, F1;
-    double g0 = pwa, g1 = pwb;
+  bool merge = false, redo = false;
+  int skip = -1, into = -1, ic = 0, icr = 1, tiny = 0;
+  double Mr = 0.0, Mm = 0.0;  // U^n of the merged cell (position into)
+  // Only the two cells next to the boundary (positions ic, icr) move; every
+  // other zone cell has length h and theta = min(theta_nb, 1).
+  double hn_l = 0.0, hn_r = 0.0, th_l = 0.0, th_r = 0.0, it_l = 0.0, it_r = 0.0;
+  double hh_l = 0.0, hh_r = 0.0;  // predicted end lengths of positions ic, icr
+  double th_f = 0.0, it_f = 0.0;  // theta and 1/(1+theta) of a fixed full cell
+  double W0[MC], W1[MC];
+  double pw0 = 0.0, pw1 = 0.0;
+  int l = 0, cnt = 0;
+  bool stop = false;
+  int row = -1;
+#pragma unroll
+  for (int i = 0; i < MC; ++i) Ur[i] = Um[i] = W0[i] = W1[i] = 0.0;
+  int stage = S_FETCH;
+
+  for (;;) {
+    // ---------------- fetch a zone that needs work ----------------
+    while (stage == S_FETCH) {
+      k = if_begin + atomicAdd(A.zone_ctr, 1);
+      if (k >= if_end) {
+        stage = S_EXIT;
+        break;
+      }
+      p = A.iface_prob[k];
+      kk = A.iface_local[k];
+      dt = A.dt[p];
+      home = A.rec_home0[k];
+      hl = A.rec_hl0[k];
+      rpw0 = A.rec_pw0[2 * k];
+      rpw1 = A.rec_pw0[2 * k + 1];
+      warm = A.rec_warm0[k];
+      row = -1;
+      if (A.log_count && A.log_row) {
+        row = *A.log_row;
+        if (row >= A.log_max) row = -1;
+      }
+      so = A.slot_off[p];
+      ns = (int)(A.slot_off[p + 1] - so);
+      sL = home + kk;
+      if (dt == 0.0 || sL < 0 || sL + 1 >= ns) {
+        // frozen/finished (or a record outside its problem: freeze, touch nothing)
+        if (dt != 0.0) atomicOr(A.fail_acc + p, ST_MESH);
+        A.rec_home1[k] = home;
+        A.rec_hl1[k] = hl;
+        A.rec_pw1[2 * k] = rpw0;
+        A.rec_pw1[2 * k + 1] = rpw1;
+        A.rec_warm1[k] = warm;
+        if (row >= 0) {
+          long long o = (long long)row * A.n_iface + k;
+          A.log_count[o] = 0;
+          A.log_flags[o] = dt == 0.0 ? FL_INACTIVE : FL_FAIL;
+          A.log_zlo[o] = -1;
+        }
+        continue;
+      }
+      h = A.h[p];
+      phl = A.phase_first[p] ^ (kk & 1);
+      phr = phl ^ 1;
+      int zhi;
+      d_zone_range(sL, hl, h, ZH, ns, zlo, zhi, tr);
+      nr = zhi - zlo + 1;
+      iL = sL - zlo;
+      iR = iL + 1;
+      const double* r0 = A.rho0 + so;
+      const double* m0 = A.mom0 + so;
+#pragma unroll
+      for (int i = 0; i < MC; ++i) {
+        if (i < nr) {
+          Ur[i] = r0[zlo + i];
+          Um[i] = m0[zlo + i];
+        } else {
+          Ur[i] = 1.0;
+          Um[i] = 0.0;
+        }
+      }
+      // bounding fluxes from U^n (Algorithm 1: F_left, F_right)
+      int phz = (zlo <= sL) ? phl : phr;
+      if (zlo == 0)
+        d_bflux(M, phz, false, P.bc_left, r0[0], m0[0], FL0, FL1);
+      else
+        d_hll(M, phz, r0[zlo - 1], m0[zlo - 1], r0[zlo], m0[zlo], FL0, FL1);
+      int phe = (zhi <= sL) ? phl : phr;
+      if (zhi == ns - 1)
+        d_bflux(M, phe, true, P.bc_right, r0[ns - 1], m0[ns - 1], FR0, FR1);
+      else
+        d_hll(M, phe, r0[zhi], m0[zhi], r0[zhi + 1], m0[zhi + 1], FR0, FR1);
+      merge = false;
+      redo = false;
+      stage = S_PRED;
+    }
+    if (stage == S_EXIT) break;
+
+    // ---------------- one interface Riemann solve ----------------
+    double ql0 = 0.0, ql1 = 0.0, qr0 = 0.0, qr1 = 0.0, g0, g1;
+    bool hg;
+    {
+      const bool pred = stage == S_PRED;
+      const int a = pred ? iL : ic, b = pred ? iR : icr;
+#pragma unroll
+      for (int i = 0; i < MC; ++i) {
+        const double x0 = pred ? Ur[i] : W0[i], x1 = pred ? Um[i] : W1[i];
+        if (i == a) {
+          ql0 = x0;
+          ql1 = x1;
+        }
+        if (i == b) {
+          qr0 = x0;
+          qr1 = x1;
+        }
+      }
+      hg = pred ? warm != 0 : true;
+      g0 = pred ? rpw0 : pw0;
+      g1 = pred ? rpw1 : pw1;
+    }
     IfaceOut o;
-    if (!d_iface_solve(M, P.newton_maxit, P.newton_rtol, phl, r0[sL], m0[sL], phr, r0[sR], m0[sR],
-                       warm != 0, g0, g1, o)) {
+    const bool ok = d_iface_solve(M, P.newton_maxit, P.newton_rtol, phl, ql0, ql1, phr, qr0, qr1,
+                                  hg, g0, g1, o);
+
+    // ---------------- stage-specific work ----------------
+    int status = 0;
+    bool setup = false, finished = false;
+    double wstar = 0.0;
+    if (stage == S_PRED) {
+      if (!ok) {
+        status = ST_NEWTON;
+      } else {
+        Ipl = o.pl;
+        Ipr = o.pr;
+        wp = o.w;
+        double ht = tr ? h - hl : hl;
+        double rate = tr ? -wp : wp;
+        double hfl = P.alpha_floor * h;
+        merge = (ht < hfl) || (ht + (P.merge_safety * rate) * dt < hfl);
+        setup = true;
+      }
+    } else if (!ok) {
       status = ST_NEWTON;
     } else {
-      Ipl = o.pl;
-      Ipr = o.pr;
-      wp = o.w;
-    }
-    (void)F0;
-    (void)F1;
-  }
-  if (!status) {
-    double ht = tr ? h - hl : hl;
-    double rate = tr ? -wp : wp;
-    double hfl = P.alpha_floor * h;
-    merge = (ht < hfl) || (ht + (P.merge_safety * rate) * dt < hfl);
-  }
-
-  for (int attempt = 0; attempt < 2 && !status; ++attempt) {
-    // ---- zone set-up in range positions 0..nr-1 ----
-    skip = -1;
-    into = -1;
-    if (merge) {
-      skip = tr ? iR : iL;
-      into = tr ? iR + 1 : iL - 1;
-      if (into < 0 || into >= nr) {
-        status = ST_MESH;
-        break;
-      }
-    }
-    double U0r[MC], U0m[MC], hn[MC], hh[MC], th[MC];
-    int mov[MC];
-    bool act[MC];
-    double rskip = 0.0, mskip = 0.0;
-    if (merge) {
-      rskip = r0[zlo + skip];
-      mskip = m0[zlo + skip];
-    }
-    const double hLp = hl, hRp = h - hl;
-    bool bad = false;
-#pragma unroll
-    for (int i = 0; i < MC; ++i) {
-      act[i] = (i < nr) && (i != skip);
-      U0r[i] = Ur[i];
-      U0m[i] = Um[i];
-      hn[i] = h;
-      mov[i] = 0;
-      if (i == iL) {
-        hn[i] = hLp;
-        mov[i] = 1;
-      } else if (i == iR) {
-        hn[i] = hRp;
-        mov[i] = -1;
-      }
-      if (i == into) {
-        double ht = tr ? hRp : hLp;
-        double hm = h + ht;
-        U0r[i] = (h * Ur[i] + ht * rskip) / hm;
-        U0m[i] = (h * Um[i] + ht * mskip) / hm;
-        hn[i] = hm;
-        mov[i] = tr ? -1 : 1;
-      }
-      double hx = hn[i] + ((double)mov[i] * wp) * dt;
-      double t = hx / h;
-      if (t > P.theta_nb) t = P.theta_nb;
-      hh[i] = hx;
-      th[i] = t;
-      if (act[i] && !(t > 0.0)) bad = true;
-    }
-    if (bad) {
-      status = ST_MESH;
-      break;
-    }
-    // interface between active positions ic (left) and icr (right)
-    const int ic = (merge && !tr) ? into : iL;
-    const int icr = (merge && tr) ? into : iR;
-    const int tiny = merge ? into : (tr ? iR : iL);
-    int last = nr - 1;
-
-    double W0[MC], W1[MC];
-#pragma unroll
-    for (int i = 0; i < MC; ++i) {
-      W0[i] = U0r[i];
-      W1[i] = U0m[i];
-    }
-    double pw0 = Ipl, pw1 = Ipr;
-    int shrink = -1;
-    bool stop = false;
-    int cnt = 0;
-    double w = 0.0;
-    // ---- Part 1: pseudo-time iterations, then Part 2 with l == lmax marker ----
-    for (int l = 0; l <= P.lmax; ++l) {
-      const bool part2 = (l == P.lmax) || stop;
-      // fluxes of the iterate
-      double Wl0 = 0.0, Wl1 = 0.0, Wr0 = 0.0, Wr1 = 0.0;
+      const bool part2 = stop || (l == P.lmax);
+      pw0 = o.pl;
+      pw1 = o.pr;
+      const double w = o.w;
+      // fluxes of the iterate: right face of each active position
+      double FRa0[MC], FRa1[MC];
 #pragma unroll
       for (int i = 0; i < MC; ++i) {
-        if (i == ic) {
-          Wl0 = W0[i];
-          Wl1 = W1[i];
-        }
-        if (i == icr) {
-          Wr0 = W0[i];
-          Wr1 = W1[i];
-        }
-      }
-      double Fi0, Fi1;
-      if (!d_zone_iface(M, P, phl, Wl0, Wl1, phr, Wr0, Wr1, pw0, pw1, Fi0, Fi1, w)) {
-        status = ST_NEWTON;
-        break;
-      }
-      double FR0a[MC], FR1a[MC];  // flux on the right face of each active position
-#pragma unroll
-      for (int i = 0; i < MC; ++i) {
-        FR0a[i] = 0.0;
-        FR1a[i] = 0.0;
-        if (!act[i]) continue;
-        if (i == last) {
-          FR0a[i] = FR0;
-          FR1a[i] = FR1;
+        FRa0[i] = 0.0;
+        FRa1[i] = 0.0;
+        if (i >= nr || i == skip) continue;
+        if (i == nr - 1) {
+          FRa0[i] = FR0;
+          FRa1[i] = FR1;
         } else if (i == ic) {
-          FR0a[i] = Fi0;
-          FR1a[i] = Fi1;
+          FRa0[i] = o.F0;
+          FRa1[i] = o.F1;
         } else if (i + 1 < MC) {
           int ph = (zlo + i <= sL) ? phl : phr;
-          d_hll(M, ph, W0[i], W1[i], W0[i + 1], W1[i + 1], FR0a[i], FR1a[i]);
+          d_hll(M, ph, W0[i], W1[i], W0[i + 1], W1[i + 1], FRa0[i], FRa1[i]);
         }
       }
-      double hnew[MC];
-#pragma unroll
-      for (int i = 0; i < MC; ++i) {
-        hnew[i] = hn[i] + ((double)mov[i] * w) * dt;
-        if (shrink < 0 && act[i] && mov[i] != 0 && !(hnew[i] >= 0.5 * hh[i])) shrink = i;
+      // new lengths (only the two cells next to the boundary move); collapse check
+      const double hnew_l = hn_l + (1.0 * w) * dt;
+      const double hnew_r = hn_r + (-1.0 * w) * dt;
+      const double ih_l = 1.0 / hnew_l, ih_r = 1.0 / hnew_r;
+      const double ih_f = 1.0 / (h + (0.0 * w) * dt);
+      int shrink = -1;
+      {
+        const bool bl = !(hnew_l >= 0.5 * hh_l), br = !(hnew_r >= 0.5 * hh_r);
+        if (bl && br)
+          shrink = ic < icr ? ic : icr;
+        else if (bl)
+          shrink = ic;
+        else if (br)
+          shrink = icr;
       }
       if (shrink >= 0) {
-        status = ST_MESH;
-        break;
-      }
-      if (part2) {
-        bool okp = true;
+        if (!merge && shrink == tiny) {
+          merge = true;
+          redo = true;
+          setup = true;
+        } else {
+          status = ST_MESH;
+        }
+      } else {
+        // Part 1 pseudo step (eq. dual time tau diff, moving lengths) with the
+        // stop test of Sec. 5 written without divisions:
+        //   |(1 + theta) d| < tol_i (theta dt) max(|W|, 1)  per component;
+        // or Part 2: the conservative update from the accepted iterate.
+        const bool paper = P.tol_mode == 0;
+        bool okw = true, conv = true;
 #pragma unroll
         for (int i = 0; i < MC; ++i) {
-          if (!act[i]) continue;
+          if (i >= nr || i == skip) continue;
           double fl0, fl1;
           if (i == 0) {
             fl0 = FL0;
             fl1 = FL1;
           } else if (i >= 2 && skip == i - 1) {
-            fl0 = FR0a[i >= 2 ? i - 2 : 0];
-            fl1 = FR1a[i >= 2 ? i - 2 : 0];
+            fl0 = FRa0[i >= 2 ? i - 2 : 0];
+            fl1 = FRa1[i >= 2 ? i - 2 : 0];
           } else {
-            fl0 = FR0a[i - 1];
-            fl1 = FR1a[i - 1];
+            fl0 = FRa0[i - 1];
+            fl1 = FRa1[i - 1];
           }
-          U1r[i] = (hn[i] * U0r[i] - dt * (FR0a[i] - fl0)) / hnew[i];
-          U1m[i] = (hn[i] * U0m[i] - dt * (FR1a[i] - fl1)) / hnew[i];
-          if (!d_state_ok(U1r[i], U1m[i])) okp = false;
+          const double u0r = (i == into) ? Mr : Ur[i];
+          const double u0m = (i == into) ? Mm : Um[i];
+          const double hni = (i == ic) ? hn_l : ((i == icr) ? hn_r : h);
+          const double ihi = (i == ic) ? ih_l : ((i == icr) ? ih_r : ih_f);
+          const double rhs0 = (hni * u0r - dt * (FRa0[i] - fl0)) * ihi;
+          const double rhs1 = (hni * u0m - dt * (FRa1[i] - fl1)) * ihi;
+          double n0, n1;
+          if (part2) {
+            n0 = rhs0;
+            n1 = rhs1;
+          } else {
+            const double t = (i == ic) ? th_l : ((i == icr) ? th_r : th_f);
+            const double i1 = (i == ic) ? it_l : ((i == icr) ? it_r : it_f);
+            const double opt = 1.0 + t;
+            const double thr = (i == tiny ? P.tol_tiny : P.tol_nb) * (t * dt);
+            n0 = (W0[i] + t * rhs0) * i1;
+            n1 = (W1[i] + t * rhs1) * i1;
+            const double d0 = n0 - W0[i], d1 = n1 - W1[i];
+            const double s0 = fabs(W0[i]) > 1.0 ? fabs(W0[i]) : 1.0;
+            const double s1 = fabs(W1[i]) > 1.0 ? fabs(W1[i]) : 1.0;
+            const bool c0 = paper ? fabs(opt * d0) < thr * s0 : fabs(d0) < P.tol_rel * s0;
+            const bool c1 = paper ? fabs(opt * d1) < thr * s1 : fabs(d1) < P.tol_rel * s1;
+            conv = conv && c0 && c1;
+          }
+          if (!d_state_ok(n0, n1)) okw = false;
+          W0[i] = n0;
+          W1[i] = n1;
         }
-        if (!okp) status = ST_NONPHYS;
-        wstar = w;
-        break;
-      }
-      // Part 1 update (eq. dual time tau diff with moving lengths) and residuals
-      double N0[MC], N1[MC];
-      double rmax_nb = 0.0, r_tiny = 0.0, rrel = 0.0;
-      bool okw = true;
-#pragma unroll
-      for (int i = 0; i < MC; ++i) {
-        N0[i] = W0[i];
-        N1[i] = W1[i];
-        if (!act[i]) continue;
-        double fl0, fl1;
-        if (i == 0) {
-          fl0 = FL0;
-          fl1 = FL1;
-        } else if (i >= 2 && skip == i - 1) {
-          fl0 = FR0a[i >= 2 ? i - 2 : 0];
-          fl1 = FR1a[i >= 2 ? i - 2 : 0];
+        if (!okw) {
+          status = ST_NONPHYS;
+        } else if (part2) {
+          wstar = w;
+          finished = true;
         } else {
-          fl0 = FR0a[i - 1];
-          fl1 = FR1a[i - 1];
+          cnt = l + 1;
+          ++l;
+          stop = conv;
         }
-        const double t = th[i];
-        double rc = 0.0, rr = 0.0;
-        {
-          double rhs = (hn[i] * U0r[i] - dt * (FR0a[i] - fl0)) / hnew[i];
-          N0[i] = (W0[i] + t * rhs) / (1.0 + t);
-          double d = N0[i] - W0[i];
-          double sc = fabs(W0[i]) > 1.0 ? fabs(W0[i]) : 1.0;
-          double res = fabs((1.0 + t) * d) / ((t * dt) * sc);
-          double rel = fabs(d) / sc;
-          if (res > rc) rc = res;
-          if (rel > rr) rr = rel;
-        }
-        {
-          double rhs = (hn[i] * U0m[i] - dt * (FR1a[i] - fl1)) / hnew[i];
-          N1[i] = (W1[i] + t * rhs) / (1.0 + t);
-          double d = N1[i] - W1[i];
-          double sc = fabs(W1[i]) > 1.0 ? fabs(W1[i]) : 1.0;
-          double res = fabs((1.0 + t) * d) / ((t * dt) * sc);
-          double rel = fabs(d) / sc;
-          if (res > rc) rc = res;
-          if (rel > rr) rr = rel;
-        }
-        if (!d_state_ok(N0[i], N1[i])) okw = false;
-        if (i == tiny)
-          r_tiny = rc;
-        else if (rc > rmax_nb)
-          rmax_nb = rc;
-        if (rr > rrel) rrel = rr;
       }
-      if (!okw) {
-        status = ST_NONPHYS;
-        break;
+    }
+
+    // ---------------- (re)build the zone: merge, lengths, pseudo steps ----------------
+    if (setup && !status) {
+      skip = -1;
+      into = -1;
+      if (merge) {
+        skip = tr ? iR : iL;
+        into = tr ? iR + 1 : iL - 1;
+        if (into < 0 || into >= nr) status = ST_MESH;
       }
+      if (!status) {
+        double rskip = 0.0, mskip = 0.0, rin = 0.0, min_ = 0.0;
+#pragma unroll
+        for (int i = 0; i < MC; ++i) {
+          if (i == skip) {
+            rskip = Ur[i];
+            mskip = Um[i];
+          }
+          if (i == into) {
+            rin = Ur[i];
+            min_ = Um[i];
+          }
+        }
+        const double hLp = hl, hRp = h - hl;
+        const double ht = tr ? hRp : hLp;
+        const double hm = h + ht;
+        if (merge) {
+          Mr = (h * rin + ht * rskip) / hm;
+          Mm = (h * min_ + ht * mskip) / hm;
+        }
+        ic = (merge && !tr) ? into : iL;
+        icr = (merge && tr) ? into : iR;
+        tiny = merge ? into : (tr ? iR : iL);
+        // lengths at t^n, predicted end lengths and pseudo steps
+        // theta = min(theta_nb, h_end / h) (Sec. 5: theta_k = alpha, 0.9 otherwise)
+        hn_l = (merge && !tr) ? hm : hLp;
+        hn_r = (merge && tr) ? hm : hRp;
+        hh_l = hn_l + (1.0 * wp) * dt;
+        hh_r = hn_r + (-1.0 * wp) * dt;
+        const double hh_f = h + (0.0 * wp) * dt;
+        th_l = hh_l / h;
+        if (th_l > P.theta_nb) th_l = P.theta_nb;
+        th_r = hh_r / h;
+        if (th_r > P.theta_nb) th_r = P.theta_nb;
+        th_f = hh_f / h;
+        if (th_f > P.theta_nb) th_f = P.theta_nb;
+        it_l = 1.0 / (1.0 + th_l);
+        it_r = 1.0 / (1.0 + th_r);
+        it_f = 1.0 / (1.0 + th_f);
+        bool bad = !(th_l > 0.0) || !(th_r > 0.0) || !(th_f > 0.0);
+#pragma unroll
+        for (int i = 0; i < MC; ++i) {
+          W0[i] = (i == into) ? Mr : Ur[i];
+          W1[i] = (i == into) ? Mm : Um[i];
+        }
+        if (bad) status = ST_MESH;
+        pw0 = Ipl;
+        pw1 = Ipr;
+        l = 0;
+        cnt = 0;
+        stop = false;
+        stage = S_ITER;
+      }
+    }
+
+    if (!status && !finished) continue;
+
+    // ---------------- write-back (success or failure) ----------------
+    double* r1 = A.rho1 + so;
+    double* m1 = A.mom1 + so;
+    int flags = tr ? FL_TINY_RIGHT : 0;
+    int count = 0;
+    int nhome = home;
+    double nhl = hl;
+    if (finished) {
+      double hln = hl + wstar * dt;
+      if (merge) {
+        flags |= FL_MERGED;
+        int src;  // position whose value fills the emptied piece
+        if (!tr) {
+          if (hln < 0.0) {
+            nhome = home - 1;
+            nhl = hln + h;
+            src = iR;
+            flags |= FL_CROSS_L;
+          } else {
+            nhl = hln;
+            src = into;
+          }
+        } else {
+          if (hln > h) {
+            nhome = home + 1;
+            nhl = hln - h;
+            src = iL;
+            flags |= FL_CROSS_R;
+          } else {
+            nhl = hln;
+            src = into;
+          }
+        }
+        double cr = 0.0, cm = 0.0;
+#pragma unroll
+        for (int i = 0; i < MC; ++i)
+          if (i == src) {
+            cr = W0[i];
+            cm = W1[i];
+          }
+#pragma unroll
+        for (int i = 0; i < MC; ++i)
+          if (i == skip) {
+            W0[i] = cr;
+            W1[i] = cm;
+          }
+      } else {
+        nhl = hln;
+      }
+      if (redo) flags |= FL_REDO;
+      if (!stop) flags |= FL_LMAX;
+      count = cnt;
+      A.rec_pw1[2 * k] = pw0;
+      A.rec_pw1[2 * k + 1] = pw1;
+      A.rec_warm1[k] = 1;
+      if (A.st_pseudo) atomicAdd(A.st_pseudo, (unsigned long long)count);
+      if (merge && A.st_merges) atomicAdd(A.st_merges, 1ull);
+      if (!stop && A.st_lmax) atomicAdd(A.st_lmax, 1ull);
+    } else {
+      flags |= FL_FAIL;
 #pragma unroll
       for (int i = 0; i < MC; ++i) {
-        W0[i] = N0[i];
-        W1[i] = N1[i];
+        W0[i] = Ur[i];
+        W1[i] = Um[i];
       }
-      cnt = l + 1;
-      if (P.tol_mode == 0)
-        stop = (rmax_nb < P.tol_nb) && (r_tiny < P.tol_tiny);
-      else
-        stop = rrel < P.tol_rel;
+      A.rec_pw1[2 * k] = rpw0;
+      A.rec_pw1[2 * k + 1] = rpw1;
+      A.rec_warm1[k] = warm;
+      atomicOr(A.fail_acc + p, status);
     }
-    if (status == ST_MESH && !merge && shrink == tiny && attempt == 0) {
-      status = 0;
-      merge = true;
-      redo = true;
-      continue;
-    }
-    if (status) break;
-    lmax_hit = !stop;
-    count = cnt;
-    pwa = pw0;
-    pwb = pw1;
-    break;
-  }
-
-  // ---- write back ----
-  double Fr[MC], Fm[MC];
-#pragma unroll
-  for (int i = 0; i < MC; ++i) {
-    Fr[i] = Ur[i];
-    Fm[i] = Um[i];
-  }
-  int nhome = home;
-  double nhl = hl;
-  if (!status) {
+    A.rec_home1[k] = nhome;
+    A.rec_hl1[k] = nhl;
+    const int nsL = nhome + kk;
+    unsigned long long vmax = 0;
 #pragma unroll
     for (int i = 0; i < MC; ++i) {
-      if (i < nr && i != skip) {
-        Fr[i] = U1r[i];
-        Fm[i] = U1m[i];
+      if (i < nr) {
+        r1[zlo + i] = W0[i];
+        m1[zlo + i] = W1[i];
+        int ph = (zlo + i <= nsL) ? phl : phr;
+        unsigned long long b = d_speed_bits(M, ph, W0[i], W1[i]);
+        vmax = b > vmax ? b : vmax;
       }
     }
-    double hln = hl + wstar * dt;
-    if (merge) {
-      flags |= FL_MERGED;
-      double cr = 0.0, cm = 0.0;  // value copied into the emptied piece
-      if (!tr) {
-        if (hln < 0.0) {
-          nhome = home - 1;
-          nhl = hln + h;
-#pragma unroll
-          for (int i = 0; i < MC; ++i)
-            if (i == iR) {
-              cr = Fr[i];
-              cm = Fm[i];
-            }
-          flags |= FL_CROSS_L;
-        } else {
-#pragma unroll
-          for (int i = 0; i < MC; ++i)
-            if (i == into) {
-              cr = Fr[i];
-              cm = Fm[i];
-            }
-          nhl = hln;
-        }
-      } else {
-        if (hln > h) {
-          nhome = home + 1;
-          nhl = hln - h;
-#pragma unroll
-          for (int i = 0; i < MC; ++i)
-            if (i == iL) {
-              cr = Fr[i];
-              cm = Fm[i];
-            }
-          flags |= FL_CROSS_R;
-        } else {
-#pragma unroll
-          for (int i = 0; i < MC; ++i)
-            if (i == into) {
-              cr = Fr[i];
-              cm = Fm[i];
-            }
-          nhl = hln;
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < MC; ++i)
-        if (i == skip) {
-          Fr[i] = cr;
-          Fm[i] = cm;
-        }
-    } else {
-      nhl = hln;
+    atomicMax(A.S_acc + p, vmax);
+    if (row >= 0) {
+      long long o2 = (long long)row * A.n_iface + k;
+      A.log_count[o2] = count;
+      A.log_flags[o2] = flags;
+      A.log_zlo[o2] = zlo;
     }
-    if (redo) flags |= FL_REDO;
-    if (lmax_hit) flags |= FL_LMAX;
-    A.rec_pw1[2 * k] = pwa;
-    A.rec_pw1[2 * k + 1] = pwb;
-    A.rec_warm1[k] = 1;
-  } else {
-    flags |= FL_FAIL;
-    count = 0;
-    A.rec_pw1[2 * k] = A.rec_pw0[2 * k];
-    A.rec_pw1[2 * k + 1] = A.rec_pw0[2 * k + 1];
-    A.rec_warm1[k] = warm;
-    atomicOr(A.fail_acc + p, status);
-  }
-  A.rec_home1[k] = nhome;
-  A.rec_hl1[k] = nhl;
-  const int nsL = nhome + kk;
-  unsigned long long vmax = 0;
-#pragma unroll
-  for (int i = 0; i < MC; ++i) {
-    if (i < nr) {
-      r1[zlo + i] = Fr[i];
-      m1[zlo + i] = Fm[i];
-      int ph = (zlo + i <= nsL) ? phl : phr;
-      unsigned long long b = d_speed_bits(M, ph, Fr[i], Fm[i]);
-      vmax = b > vmax ? b : vmax;
-    }
-  }
-  atomicMax(A.S_acc + p, vmax);
-  if (!status) {
-    if (A.st_pseudo) atomicAdd(A.st_pseudo, (unsigned long long)count);
-    if (merge && A.st_merges) atomicAdd(A.st_merges, 1ull);
-    if (lmax_hit && A.st_lmax) atomicAdd(A.st_lmax, 1ull);
-  }
-  if (row >= 0) {
-    long long o = (long long)row * A.n_iface + k;
-    A.log_count[o] = count;
-    A.log_flags[o] = flags;
-    A.log_zlo[o] = zlo;
+    stage = S_FETCH;
   }
 }
 
@@ -680,7 +628,10 @@ __global__ __launch_bounds__(64) void k_zone(StepArgs A, int if_begin, int if_en
 // ---------------------------------------------------------------------------
 __global__ void k_finalize(StepArgs A, int p_begin, int p_end, int init, int bump_row) {
   const int p = p_begin + blockIdx.x * blockDim.x + threadIdx.x;
-  if (bump_row && p == p_begin && A.log_row) *A.log_row += 1;
+  if (p == p_begin) {
+    if (bump_row && A.log_row) *A.log_row += 1;
+    *A.zone_ctr = 0;
+  }
   if (p >= p_end) return;
   const Par& P = A.par;
   double dt = A.dt[p];
@@ -738,10 +689,12 @@ __global__ void k_finalize(StepArgs A, int p_begin, int p_end, int init, int bum
 // ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_bulk(const StepArgs& A, int tile_cells, int tile_begin, int n_tiles,
+int bulk_tile_cells(int tile_class) { return (tile_class / 256) * 4 * 62; }
+
+hipError_t launch_bulk(const StepArgs& A, int tile_class, int tile_begin, int n_tiles,
                        hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
-  switch (tile_cells) {
+  switch (tile_class) {
     case 256: k_bulk<1><<<n_tiles, 256, 0, s>>>(A, tile_begin); break;
     case 512: k_bulk<2><<<n_tiles, 256, 0, s>>>(A, tile_begin); break;
     case 1024: k_bulk<4><<<n_tiles, 256, 0, s>>>(A, tile_begin); break;
@@ -753,14 +706,15 @@ hipError_t launch_bulk(const StepArgs& A, int tile_cells, int tile_begin, int n_
 
 hipError_t launch_cfl(const StepArgs& A, int tile_begin, int n_tiles, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
-  k_cfl<1><<<n_tiles, 256, 0, s>>>(A, tile_begin);
+  k_cfl<<<n_tiles, 256, 0, s>>>(A, tile_begin);
   return hipGetLastError();
 }
 
-hipError_t launch_zone(const StepArgs& A, int if_begin, int if_end, hipStream_t s) {
+hipError_t launch_zone(const StepArgs& A, int if_begin, int if_end, int groups, hipStream_t s) {
   int n = if_end - if_begin;
   if (n <= 0) return hipSuccess;
-  int groups = (n + A.zones_per_group - 1) / A.zones_per_group;
+  int need = (n + A.zones_per_group - 1) / A.zones_per_group;
+  if (groups <= 0 || groups > need) groups = need;
   switch (A.par.zone_half) {
     case 1: k_zone<1><<<groups, 64, 0, s>>>(A, if_begin, if_end); break;
     case 2: k_zone<2><<<groups, 64, 0, s>>>(A, if_begin, if_end); break;

@@ -52,13 +52,19 @@ struct StepArgs {
   unsigned long long* st_pseudo;
   unsigned long long* st_merges;
   unsigned long long* st_lmax;
+  int* zone_ctr;  // zones handed out so far in this step (reset by k_finalize)
   int zones_per_group;
 };
 
-hipError_t launch_bulk(const StepArgs& A, int tile_cells, int tile_begin, int n_tiles,
+// Bulk tiles: tile_class in {256, 512, 1024, 2048} gives R = tile_class / 256
+// rows of 62 cells per wave, 4 waves per workgroup: bulk_tile_cells() cells.
+int bulk_tile_cells(int tile_class);
+hipError_t launch_bulk(const StepArgs& A, int tile_class, int tile_begin, int n_tiles,
                        hipStream_t s);
 hipError_t launch_cfl(const StepArgs& A, int tile_begin, int n_tiles, hipStream_t s);
-hipError_t launch_zone(const StepArgs& A, int if_begin, int if_end, hipStream_t s);
+// groups <= 0: one lane per zone; else that many workgroups whose lanes pull
+// zones from the shared counter until none is left.
+hipError_t launch_zone(const StepArgs& A, int if_begin, int if_end, int groups, hipStream_t s);
 hipError_t launch_finalize(const StepArgs& A, int p_begin, int p_end, int init, int bump_row,
                            hipStream_t s);
 

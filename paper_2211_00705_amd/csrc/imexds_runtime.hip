@@ -64,7 +64,7 @@ struct imexds_ctx {
   int *d_phase_first = nullptr, *d_iface_off = nullptr, *d_iface_prob = nullptr,
       *d_iface_local = nullptr;
   int *d_tile_prob = nullptr, *d_tile_start = nullptr, *d_tile_len = nullptr;
-  int n_tiles = 0, tile_cells = 1024, zones_per_group = 16, graph_steps = 8;
+  int n_tiles = 0, tile_cells = 1024, zones_per_group = 16, zone_groups = 0, graph_steps = 8;
   std::vector<int> h_tile_off;  // [P+1] tiles of each problem
   // evolving state
   double *d_rho[2] = {nullptr, nullptr}, *d_mom[2] = {nullptr, nullptr};
@@ -77,6 +77,7 @@ struct imexds_ctx {
   long long* d_steps = nullptr;
   unsigned long long* d_S = nullptr;
   unsigned long long* d_stats = nullptr;  // pseudo, merges, lmax
+  int* d_zone_ctr = nullptr;
   int *d_log_count = nullptr, *d_log_flags = nullptr, *d_log_zlo = nullptr, *d_log_row = nullptr;
   int log_max = 0;
   int parity = 0;
@@ -176,6 +177,7 @@ StepArgs make_args(imexds_ctx* c, int parity, bool init) {
   A.st_pseudo = c->d_stats;
   A.st_merges = c->d_stats + 1;
   A.st_lmax = c->d_stats + 2;
+  A.zone_ctr = c->d_zone_ctr;
   A.zones_per_group = c->zones_per_group;
   return A;
 }
@@ -183,12 +185,13 @@ StepArgs make_args(imexds_ctx* c, int parity, bool init) {
 int build_tiles(imexds_ctx* c, int tile_cells) {
   std::vector<int> tp, ts, tl;
   c->h_tile_off.assign(c->P + 1, 0);
+  const int cells = imexds::bulk_tile_cells(tile_cells);
   for (int p = 0; p < c->P; ++p) {
     int ns = (int)(c->h_slot_off[p + 1] - c->h_slot_off[p]);
-    for (int s = 0; s < ns; s += tile_cells) {
+    for (int s = 0; s < ns; s += cells) {
       tp.push_back(p);
       ts.push_back(s);
-      tl.push_back(std::min(tile_cells, ns - s));
+      tl.push_back(std::min(cells, ns - s));
     }
     c->h_tile_off[p + 1] = (int)tp.size();
   }
@@ -222,7 +225,7 @@ int enqueue_step(imexds_ctx* c, int ev_slot) {
   if (c->NIF > 0) {
     CK(hipEventRecord(ef, c->ms));
     CK(hipStreamWaitEvent(c->zs, ef, 0));
-    CK(imexds::launch_zone(A, 0, c->NIF, c->zs));
+    CK(imexds::launch_zone(A, 0, c->NIF, c->zone_groups, c->zs));
   }
   if (c->time_bulk) {
     size_t need = 2 * (size_t)(c->bulk_launches + 1);
@@ -504,6 +507,12 @@ static int create_impl(imexds_ctx* c, const imexds_material* mat, const imexds_p
   c->mat.av = std::sqrt(mat->a2_vap);
   c->mat.al = std::sqrt(mat->a2_liq);
   c->mat.rhov0 = mat->p_sat / mat->a2_vap;
+  c->mat.ia2v = 1.0 / c->mat.a2v;
+  c->mat.ia2l = 1.0 / c->mat.a2l;
+  c->mat.iav = 1.0 / c->mat.av;
+  c->mat.ial = 1.0 / c->mat.al;
+  c->mat.irv0 = 1.0 / c->mat.rhov0;
+  c->mat.irl0 = 1.0 / c->mat.rhol0;
   c->par.cfl = par->cfl;
   c->par.theta_nb = par->theta_nb;
   c->par.tol_nb = par->tol_nb;
@@ -554,6 +563,7 @@ static int create_impl(imexds_ctx* c, const imexds_material* mat, const imexds_p
   AL(c->d_S, Pn);
   AL(c->d_stats, 3);
   AL(c->d_log_row, 1);
+  AL(c->d_zone_ctr, 1);
   CK(hipMemcpy(c->d_slot_off, c->h_slot_off.data(), (Pn + 1) * 8, hipMemcpyHostToDevice));
   if (P > 0) {
     CK(hipMemcpy(c->d_h, c->h_h.data(), Pn * 8, hipMemcpyHostToDevice));
@@ -565,6 +575,7 @@ static int create_impl(imexds_ctx* c, const imexds_material* mat, const imexds_p
     CK(hipMemcpy(c->d_iface_local, c->h_iface_local.data(), N * 4, hipMemcpyHostToDevice));
   }
   CK(hipMemset(c->d_log_row, 0, 4));
+  CK(hipMemset(c->d_zone_ctr, 0, 4));
   return build_tiles(c, c->tile_cells);
 }
 
@@ -613,6 +624,7 @@ int imexds_set_state(imexds_ctx* c, const double* rho, const double* mom) {
   }
   CK(hipMemsetAsync(c->d_stats, 0, 3 * 8, m));
   CK(hipMemsetAsync(c->d_log_row, 0, 4, m));
+  CK(hipMemsetAsync(c->d_zone_ctr, 0, 4, m));
   // host->device copies above read pageable host memory: finish them here
   CK(hipStreamSynchronize(m));
   if (P) {
@@ -647,7 +659,7 @@ int imexds_step_per_problem(imexds_ctx* c, int32_t n_steps) {
     StepArgs A = make_args(c, c->parity, false);
     for (int p = 0; p < c->P; ++p) {
       int k0 = c->h_iface_off[p], k1 = c->h_iface_off[p + 1];
-      if (k1 > k0) CK(imexds::launch_zone(A, k0, k1, c->ms));
+      if (k1 > k0) CK(imexds::launch_zone(A, k0, k1, 0, c->ms));
       int t0 = c->h_tile_off[p], t1 = c->h_tile_off[p + 1];
       CK(imexds::launch_bulk(A, c->tile_cells, t0, t1 - t0, c->ms));
       CK(imexds::launch_finalize(A, p, p + 1, 0, p == c->P - 1, c->ms));
@@ -801,24 +813,25 @@ int imexds_get_stats(imexds_ctx* c, imexds_stats* out) {
 }
 
 int imexds_set_launch(imexds_ctx* c, int32_t tile_cells, int32_t zones_per_group,
-                      int32_t graph_steps) {
+                      int32_t zone_groups, int32_t graph_steps) {
   if (!c) return IMEXDS_ERR_INVALID_ARG;
   if (tile_cells != 256 && tile_cells != 512 && tile_cells != 1024 && tile_cells != 2048)
     return IMEXDS_ERR_INVALID_ARG;
-  if (zones_per_group < 1 || zones_per_group > 64 || graph_steps < 0 || (graph_steps & 1) ||
-      graph_steps > 512)
+  if (zones_per_group < 1 || zones_per_group > 64 || zone_groups < 0 || graph_steps < 0 ||
+      (graph_steps & 1) || graph_steps > 512)
     return IMEXDS_ERR_INVALID_ARG;
   CK(hipSetDevice(c->device));
   CK(hipStreamSynchronize(c->ms));
   drop_graph(c);
   c->zones_per_group = zones_per_group;
+  c->zone_groups = zone_groups;
   c->graph_steps = graph_steps;
   if (tile_cells != c->tile_cells) return build_tiles(c, tile_cells);
   return 0;
 }
 
 int imexds_autotune(imexds_ctx* c, int32_t steps_per_trial, int32_t* tile_cells,
-                    int32_t* zones_per_group, double* ms_per_step) {
+                    int32_t* zones_per_group, int32_t* zone_groups, double* ms_per_step) {
   if (!c || steps_per_trial < 1) return IMEXDS_ERR_INVALID_ARG;
   if (!c->has_state) return IMEXDS_ERR_NO_STATE;
   CK(hipSetDevice(c->device));
@@ -829,34 +842,57 @@ int imexds_autotune(imexds_ctx* c, int32_t steps_per_trial, int32_t* tile_cells,
     snap_free(s);
     return r;
   }
-  const int tiles[] = {256, 512, 1024, 2048};
-  const int zpgs[] = {4, 8, 16, 32, 64};
-  int best_t = c->tile_cells, best_z = c->zones_per_group;
+  struct Cfg {
+    int t, z, g;
+  };
+  std::vector<Cfg> cfgs;
+  // zone lanes: one zone per lane spread over many waves, or fewer lanes
+  // pulling several zones each
+  const int zl[] = {4, 8, 16, 64};
+  const int gf[] = {0, 1, 2, 4};  // 0: one zone per lane; else groups = CUs * f
+  for (int z : zl)
+    for (int f : gf) cfgs.push_back({1024, z, f == 0 ? 0 : 256 * f});
+  int best_t = c->tile_cells, best_z = c->zones_per_group, best_g = c->zone_groups;
   double best = 1e300;
   int G = c->graph_steps;
-  for (int tc : tiles) {
-    for (int zp : zpgs) {
-      if ((r = imexds_set_launch(c, tc, zp, G))) break;
-      if ((r = snap_restore(c, s))) break;
-      if ((r = steps_impl(c, 2))) break;  // warm-up (also captures the graph)
-      if ((r = snap_restore(c, s))) break;
-      hipEvent_t a = c->ev_t0, b = c->ev_t1;
-      if (hipEventRecord(a, c->ms) != hipSuccess) break;
-      if ((r = steps_impl(c, steps_per_trial))) break;
-      if (hipEventRecord(b, c->ms) != hipSuccess) break;
-      if (hipEventSynchronize(b) != hipSuccess) break;
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, a, b);
-      double per = ms / steps_per_trial;
+  auto trial = [&](const Cfg& q, double& per) -> int {
+    int rr = imexds_set_launch(c, q.t, q.z, q.g, G);
+    if (rr) return rr;
+    if ((rr = snap_restore(c, s))) return rr;
+    if ((rr = steps_impl(c, 2))) return rr;  // warm-up (also captures the graph)
+    if ((rr = snap_restore(c, s))) return rr;
+    CK(hipEventRecord(c->ev_t0, c->ms));
+    if ((rr = steps_impl(c, steps_per_trial))) return rr;
+    CK(hipEventRecord(c->ev_t1, c->ms));
+    CK(hipEventSynchronize(c->ev_t1));
+    float ms = 0.f;
+    CK(hipEventElapsedTime(&ms, c->ev_t0, c->ev_t1));
+    per = ms / steps_per_trial;
+    return 0;
+  };
+  // stage 1: zone launch shape at a mid tile size; stage 2: tile size
+  for (const Cfg& q : cfgs) {
+    double per = 0.0;
+    if ((r = trial(q, per))) break;
+    if (per < best) {
+      best = per;
+      best_z = q.z;
+      best_g = q.g;
+      best_t = q.t;
+    }
+  }
+  if (!r) {
+    const int tiles[] = {256, 512, 2048};
+    for (int t : tiles) {
+      double per = 0.0;
+      if ((r = trial({t, best_z, best_g}, per))) break;
       if (per < best) {
         best = per;
-        best_t = tc;
-        best_z = zp;
+        best_t = t;
       }
     }
-    if (r) break;
   }
-  int r2 = imexds_set_launch(c, best_t, best_z, G);
+  int r2 = imexds_set_launch(c, best_t, best_z, best_g, G);
   int r3 = snap_restore(c, s);
   snap_free(s);
   if (r) return r;
@@ -864,6 +900,7 @@ int imexds_autotune(imexds_ctx* c, int32_t steps_per_trial, int32_t* tile_cells,
   if (r3) return r3;
   if (tile_cells) *tile_cells = best_t;
   if (zones_per_group) *zones_per_group = best_z;
+  if (zone_groups) *zone_groups = best_g;
   if (ms_per_step) *ms_per_step = best;
   return 0;
 }

@@ -78,8 +78,9 @@ def test_launch_forms_agree_bitwise(material):
     tile size give bit-identical results."""
     b = W.random_batch(seed=21, n_problems=16, nmin=100, nmax=5000)
     P = W.random_batch_params()
-    ref = run_gpu(b, material, P, 64, launch=(1024, 16, 8))
-    for launch in [(256, 1, 0), (512, 64, 2), (2048, 7, 16), (1024, 16, 0)]:
+    ref = run_gpu(b, material, P, 64, launch=(1024, 16, 0, 8))
+    for launch in [(256, 1, 0, 0), (512, 64, 0, 2), (2048, 7, 1, 16), (1024, 4, 3, 0),
+                   (1024, 16, 0, 0)]:
         g = run_gpu(b, material, P, 64, launch=launch)
         assert np.array_equal(g["rho"], ref["rho"]) and np.array_equal(g["mom"], ref["mom"]), launch
         assert np.array_equal(g["count"], ref["count"])
@@ -168,7 +169,7 @@ def test_full_size_batch_sampled(material):
     the oracle on their own."""
     b = W.random_batch()
     P = W.random_batch_params()
-    g = run_gpu(b, material, P, 1000, launch=(1024, 16, 8), log=False)
+    g = run_gpu(b, material, P, 1000, launch=(1024, 16, 64, 10), log=False)
     rng = np.random.default_rng(1)
     idx = sorted(rng.choice(b.n_problems, size=6, replace=False).tolist())
     sub = b.subset(idx)
