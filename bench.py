@@ -13,6 +13,7 @@ bulk launch), and the CPU oracle timed on a bounded sample of the same
 problems (whose results are also compared with the GPU's).
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -44,6 +45,27 @@ def parse():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (HBM counter calibration)")
     return ap.parse_args()
+
+
+def measured_traffic(workload, tile_cells):
+    """HBM bytes per k_bulk launch from the committed rocprofv3 PMC summary,
+    if it was taken on this workload and launch shape and the kernel source
+    is unchanged since; else None."""
+    path = os.path.join(ROOT, "profiles", "k_bulk_random_batch_4096_hbm_traffic.txt")
+    if workload != "batch" or tile_cells != 1024 or not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if line.startswith("#") or ":" not in line:
+            continue
+        k, v = line.split(":", 1)
+        kv[k.strip()] = v.strip()
+    src = open(os.path.join(ROOT, "paper_2211_00705_amd", "csrc", "imexds_kernels.hip")).read()
+    i = src.index("template <int R>\n__global__ __launch_bounds__(256) void k_bulk")
+    j = src.index("// CFL over all slots of the current state")
+    if hashlib.sha256(src[i:j].encode()).hexdigest() != kv.get("kernel_source_sha256"):
+        return None
+    return int(kv["traffic_bytes_per_launch"])
 
 
 def make_workload(args):
@@ -171,23 +193,29 @@ def main():
     g_home, g_hl, _ = s.interfaces()
     _, g_status, g_steps = s.problems()
 
-    # bulk-kernel roofline: same state, eager launches with events around each bulk launch
-    s.time_bulk(True)
-    s.step(args.roofline_steps)
-    torch.cuda.synchronize()
-    _, bulk_ms = s.last_timing()
-    s.time_bulk(False)
+    # bulk-kernel roofline: same state, each bulk launch alone between two
+    # HIP events on its stream (zones follow it instead of overlapping it)
     NIF = b.n_iface
     zone_slots = int(round(NIF * (2 * P.zone_half + 1)))
     bulk_bytes = BYTES_PER_CELL_UPDATE * (b.n_slots - zone_slots)
-    achieved = bulk_bytes / (bulk_ms * 1e-3) / 1e9
+    bulk_ms = achieved = None
+    if args.roofline_steps > 0:
+        s.time_bulk(True)
+        s.step(args.roofline_steps)
+        torch.cuda.synchronize()
+        _, bulk_ms = s.last_timing()
+        s.time_bulk(False)
+        achieved = bulk_bytes / (bulk_ms * 1e-3) / 1e9
 
     # per-problem launch form on the same state
-    s.step_per_problem(args.per_problem_steps)
-    torch.cuda.synchronize()
-    pp_ms, _ = s.last_timing()
-    pp_value = args.per_problem_steps * b.n_slots / (pp_ms * 1e-3)
-    stats = s.stats()
+    pp = None
+    if args.per_problem_steps > 0:
+        s.step_per_problem(args.per_problem_steps)
+        torch.cuda.synchronize()
+        pp_ms, _ = s.last_timing()
+        pp_value = args.per_problem_steps * b.n_slots / (pp_ms * 1e-3)
+        pp = {"value": pp_value, "unit": "cell-updates/s", "ms_per_step": pp_ms / args.per_problem_steps,
+              "steps": args.per_problem_steps, "batched_speedup": value / pp_value}
     s.close()
 
     out = {
@@ -209,14 +237,15 @@ def main():
         "wall_s": wall,
         "failed_problems": int(np.sum(g_status != 0)),
         "pseudo_iters_per_zone_step": (st1["pseudo_iters"] - st0["pseudo_iters"]) / max(1, NIF * args.steps),
-        "per_problem": {"value": pp_value, "unit": "cell-updates/s",
-                        "ms_per_step": pp_ms / args.per_problem_steps,
-                        "steps": args.per_problem_steps,
-                        "batched_speedup": value / pp_value},
+        "per_problem": pp,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                     "traffic": measured_traffic(args.workload, tune["tile_cells"]),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "k_bulk", "bulk_ms_per_launch": bulk_ms,
+                     "bulk_launches_timed": args.roofline_steps,
                      "algorithmic_bytes_per_launch": bulk_bytes},
+        "step_roofline_frac": value / (HBM_PEAK_GBS * 1e9 / BYTES_PER_CELL_UPDATE),
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline_leg(b, P, material, args.steps, g_rho, g_mom, g_home,

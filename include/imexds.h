@@ -99,7 +99,7 @@ typedef struct {
   double merge_safety;/* factor on the predicted shrink in the merge test */
   int32_t bc_left, bc_right; /* IMEXDS_BC_* */
   int32_t newton_maxit;      /* per Newton-Armijo start */
-  double newton_rtol;        /* relative step for Newton convergence */
+  double newton_rtol;        /* Newton step below this (relative) is the last one taken */
   double t_end;              /* stop time per problem (INFINITY: step counts only) */
 } imexds_params;
 
@@ -215,8 +215,10 @@ int imexds_get_sizes(imexds_ctx *ctx, int32_t *n_problems, int32_t *n_iface, int
  * duration of one bulk-sweep launch inside it (ms, host).  Synchronizes. */
 int imexds_last_timing(imexds_ctx *ctx, double *total_ms, double *bulk_ms_per_launch);
 
-/* Enables HIP-event timing of the bulk-sweep kernel inside imexds_step
- * (adds events around each bulk launch; graphs are not used while on). */
+/* Enables HIP-event timing of the bulk-sweep kernel inside imexds_step:
+ * kernels are launched directly (no graphs), each bulk launch is bracketed by
+ * events and runs alone (the zones follow it on the same stream instead of
+ * overlapping it).  Results are unchanged. */
 int imexds_time_bulk(imexds_ctx *ctx, int32_t on);
 
 void imexds_destroy(imexds_ctx *ctx);

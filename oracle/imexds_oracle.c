@@ -98,7 +98,7 @@ static double or_rho_of_p(const or_material *M, int ph, double p) {
 /* Natural logarithm of a positive finite double.  Argument reduction
  * x = 2^e m with m in [sqrt(1/2), sqrt(2)], then ln m = 2 atanh(f) with
  * f = (m-1)/(m+1), the atanh series 2 f (1 + f^2/3 + f^4/5 + ... + f^24/25)
- * by Horner's rule, and e ln 2 with ln 2 split into a head with trailing
+ * by Estrin's scheme, and e ln 2 with ln 2 split into a head with trailing
  * zero bits and a tail (as in fdlibm).  Written as plain IEEE double
  * operations in a fixed order, so every IEEE machine gives the same bits;
  * accurate to a few ulp (checked against the C library in the tests). */
@@ -125,19 +125,14 @@ double oracle_log(double x) {
   }
   double f = (m - 1.0) / (m + 1.0);
   double s = f * f;
-  double p = 1.0 / 25.0;
-  p = p * s + 1.0 / 23.0;
-  p = p * s + 1.0 / 21.0;
-  p = p * s + 1.0 / 19.0;
-  p = p * s + 1.0 / 17.0;
-  p = p * s + 1.0 / 15.0;
-  p = p * s + 1.0 / 13.0;
-  p = p * s + 1.0 / 11.0;
-  p = p * s + 1.0 / 9.0;
-  p = p * s + 1.0 / 7.0;
-  p = p * s + 1.0 / 5.0;
-  p = p * s + 1.0 / 3.0;
-  p = p * s + 1.0;
+  /* Estrin's scheme for sum_{k=0}^{12} s^k / (2k+1) */
+  double s2 = s * s, s4 = s2 * s2, s8 = s4 * s4;
+  double q0 = 1.0 + (1.0 / 3.0) * s, q1 = (1.0 / 5.0) + (1.0 / 7.0) * s;
+  double q2 = (1.0 / 9.0) + (1.0 / 11.0) * s, q3 = (1.0 / 13.0) + (1.0 / 15.0) * s;
+  double q4 = (1.0 / 17.0) + (1.0 / 19.0) * s, q5 = (1.0 / 21.0) + (1.0 / 23.0) * s;
+  double r0 = q0 + q1 * s2, r1 = q2 + q3 * s2, r2 = q4 + q5 * s2;
+  double t0 = r0 + r1 * s4, t1 = r2 + (1.0 / 25.0) * s4;
+  double p = t0 + t1 * s8;
   double r = (2.0 * f) * p;
   double de = (double)e;
   return de * 0x1.62e42feep-1 + (de * 0x1.a39ef35793c76p-33 + r);

@@ -222,12 +222,9 @@ int build_tiles(imexds_ctx* c, int tile_cells) {
 int enqueue_step(imexds_ctx* c, int ev_slot) {
   StepArgs A = make_args(c, c->parity, false);
   hipEvent_t ef = c->fork_ev[ev_slot], ej = c->join_ev[ev_slot];
-  if (c->NIF > 0) {
-    CK(hipEventRecord(ef, c->ms));
-    CK(hipStreamWaitEvent(c->zs, ef, 0));
-    CK(imexds::launch_zone(A, 0, c->NIF, c->zone_groups, c->zs));
-  }
   if (c->time_bulk) {
+    // timing mode: the bulk sweep runs alone between its two events, then the
+    // zones on the same stream (no overlap), so the events see the kernel only
     size_t need = 2 * (size_t)(c->bulk_launches + 1);
     while (c->bulk_ev.size() < need) {
       hipEvent_t e;
@@ -235,12 +232,20 @@ int enqueue_step(imexds_ctx* c, int ev_slot) {
       c->bulk_ev.push_back(e);
     }
     CK(hipEventRecord(c->bulk_ev[2 * c->bulk_launches], c->ms));
-  }
-  CK(imexds::launch_bulk(A, c->tile_cells, 0, c->n_tiles, c->ms));
-  if (c->time_bulk) {
+    CK(imexds::launch_bulk(A, c->tile_cells, 0, c->n_tiles, c->ms));
     CK(hipEventRecord(c->bulk_ev[2 * c->bulk_launches + 1], c->ms));
     c->bulk_launches++;
+    if (c->NIF > 0) CK(imexds::launch_zone(A, 0, c->NIF, c->zone_groups, c->ms));
+    CK(imexds::launch_finalize(A, 0, c->P, 0, 1, c->ms));
+    c->parity ^= 1;
+    return 0;
   }
+  if (c->NIF > 0) {
+    CK(hipEventRecord(ef, c->ms));
+    CK(hipStreamWaitEvent(c->zs, ef, 0));
+    CK(imexds::launch_zone(A, 0, c->NIF, c->zone_groups, c->zs));
+  }
+  CK(imexds::launch_bulk(A, c->tile_cells, 0, c->n_tiles, c->ms));
   if (c->NIF > 0) {
     CK(hipEventRecord(ej, c->zs));
     CK(hipStreamWaitEvent(c->ms, ej, 0));

@@ -219,10 +219,13 @@ def test_iface_solves_random_configuration_states(material):
         rv, uv = rng.uniform(0.01, 0.1), rng.uniform(-1, 1)
         r = oracle.iface_solve(material, W.LIQ, rl, ul, W.VAP, rv, uv)
         assert r["ok"]
-        # mass: rho*(u* - w) equal on both sides
+        # mass: rho*(u* - w) equal on both sides.  u* - w is a difference of
+        # star velocities of order a_V, so round-off bounds this residual by
+        # about rho_L * 1e-12 * max|u*| (plus a relative part)
         ml = r["rl"] * (r["ul"] - r["w"])
         mv = r["rr"] * (r["ur"] - r["w"])
-        assert ml == pytest.approx(mv, rel=1e-9, abs=1e-12)
+        floor = 1e-12 * r["rl"] * max(abs(r["ul"]), abs(r["ur"]), abs(r["w"]), 1.0)
+        assert abs(ml - mv) <= 1e-10 * abs(mv) + floor
         # momentum: -z u* + p* equal on both sides
         pl_ = material.p0 + material.a2l * (r["rl"] - material.rhol0)
         fl = -r["z"] * r["ul"] + pl_
