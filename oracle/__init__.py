@@ -15,7 +15,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(_HERE, "imexds_oracle.c")
+DUAL_H = os.path.join(_HERE, "or_dual.h")
 LIB = os.path.join(_HERE, "liboracle_imexds.so")
+LIB_TAN = os.path.join(_HERE, "liboracle_imexds_tan.so")
 
 ST_NEWTON, ST_NONPHYS, ST_MESH, ST_OVERLAP = 1, 2, 4, 8
 FL_TINY_RIGHT, FL_MERGED, FL_REDO, FL_LMAX = 1, 2, 4, 8
@@ -23,11 +25,17 @@ FL_CROSS_L, FL_CROSS_R, FL_FAIL, FL_INACTIVE = 16, 32, 64, 128
 
 
 def build():
-    """Compiles the oracle shared library (always recompiles)."""
+    """Compiles the oracle shared library and its tangent (dual-number) build
+    from the same source (always recompiles)."""
     tmp = LIB + ".tmp"
     subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
                            "-shared", "-fPIC", "-o", tmp, SRC, "-lm"])
     os.replace(tmp, LIB)
+    tmp = LIB_TAN + ".tmp"
+    subprocess.check_call(["g++", "-x", "c++", "-std=c++17", "-DOR_TANGENT", "-I", _HERE, "-O2",
+                           "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-shared", "-fPIC",
+                           "-o", tmp, SRC, "-lm"])
+    os.replace(tmp, LIB_TAN)
 
 
 class _Mat(ctypes.Structure):
@@ -53,12 +61,18 @@ class _Iface(ctypes.Structure):
 
 
 _lib = None
+_lib_tan = None
+
+
+def _stale(path):
+    return (not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(SRC)
+            or os.path.getmtime(path) < os.path.getmtime(DUAL_H))
 
 
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        if _stale(LIB) or _stale(LIB_TAN):
             build()
         L = ctypes.CDLL(LIB)
         dp, ip, lp = (ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
@@ -66,7 +80,10 @@ def lib():
         L.oracle_run.restype = ctypes.c_int
         L.oracle_run.argtypes = [ctypes.POINTER(_Mat), ctypes.POINTER(_Par), ctypes.c_int, ip, dp,
                                  ip, ip, lp, ip, dp, dp, ip, dp, dp, dp, ip, lp, ctypes.c_int, ip,
-                                 ip, ip, ctypes.c_int]
+                                 ip, ip, ip, ip, ip, ip, ctypes.c_int]
+        L.oracle_objective.restype = None
+        L.oracle_objective.argtypes = [ctypes.c_int, ip, dp, dp, ip, lp, ip, dp, dp,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
         L.oracle_iface_solve.restype = ctypes.c_int
         L.oracle_iface_solve.argtypes = [ctypes.POINTER(_Mat), ctypes.c_int, ctypes.c_double,
                                          ctypes.c_double, ctypes.c_int, ctypes.c_double,
@@ -128,26 +145,41 @@ class State:
         return out
 
 
-def run(state, material, params, n_steps, log=False, threads=1):
+def _geometry(b):
+    return (np.ascontiguousarray(b.n_cells, dtype=np.int32),
+            np.ascontiguousarray(b.h, dtype=np.float64),
+            np.ascontiguousarray(b.phase_first, dtype=np.int32),
+            np.ascontiguousarray(b.iface_off, dtype=np.int32),
+            np.ascontiguousarray(b.slot_off, dtype=np.int64))
+
+
+def run(state, material, params, n_steps, log=False, threads=1, replay=None):
     """Advances every problem of ``state`` by ``n_steps`` steps (or until
     t_end / failure).  Returns per-step logs (count, flags, zlo) of shape
-    [n_steps, n_iface] if ``log``."""
+    [n_steps, n_iface] if ``log`` (with log="full": also the CFL slot,
+    [n_steps, n_problems]).  ``replay`` = a full log of an earlier run:
+    its decisions are repeated instead of taken."""
     b = state.batch
     L = lib()
     m, p = _mat(material), _par(params)
-    n_cells = np.ascontiguousarray(b.n_cells, dtype=np.int32)
-    h = np.ascontiguousarray(b.h, dtype=np.float64)
-    pf = np.ascontiguousarray(b.phase_first, dtype=np.int32)
-    ioff = np.ascontiguousarray(b.iface_off, dtype=np.int32)
-    soff = np.ascontiguousarray(b.slot_off, dtype=np.int64)
+    n_cells, h, pf, ioff, soff = _geometry(b)
     nif = b.n_iface
+    lcp = lfp = lzp = lsp = None
     if log:
         lc = np.zeros((n_steps, max(nif, 1)), dtype=np.int32)
         lf = np.zeros_like(lc)
         lz = np.zeros_like(lc)
+        ls = np.zeros((n_steps, b.n_problems), dtype=np.int32)
         lcp, lfp, lzp = (_ptr(lc, ctypes.c_int), _ptr(lf, ctypes.c_int), _ptr(lz, ctypes.c_int))
-    else:
-        lcp = lfp = lzp = None
+        lsp = _ptr(ls, ctypes.c_int)
+    rcp = rfp = rsp = None
+    if replay is not None:
+        rc_, rf_, _, rs_ = replay
+        assert rc_.shape[0] >= n_steps and rs_.shape[0] >= n_steps
+        keep = [np.ascontiguousarray(np.pad(a[:n_steps], ((0, 0), (0, max(1, a.shape[1]) - a.shape[1]))),
+                                     dtype=np.int32) for a in (rc_, rf_)]
+        keep.append(np.ascontiguousarray(rs_[:n_steps], dtype=np.int32))
+        rcp, rfp, rsp = (_ptr(a, ctypes.c_int) for a in keep)
     rc = L.oracle_run(ctypes.byref(m), ctypes.byref(p), b.n_problems, _ptr(n_cells, ctypes.c_int),
                       _ptr(h, ctypes.c_double), _ptr(pf, ctypes.c_int), _ptr(ioff, ctypes.c_int),
                       _ptr(soff, ctypes.c_longlong), _ptr(state.home, ctypes.c_int),
@@ -155,12 +187,88 @@ def run(state, material, params, n_steps, log=False, threads=1):
                       _ptr(state.warm, ctypes.c_int), _ptr(state.rho, ctypes.c_double),
                       _ptr(state.mom, ctypes.c_double), _ptr(state.t, ctypes.c_double),
                       _ptr(state.status, ctypes.c_int), _ptr(state.steps, ctypes.c_longlong),
-                      int(n_steps), lcp, lfp, lzp, int(threads))
+                      int(n_steps), lcp, lfp, lzp, lsp, rcp, rfp, rsp, int(threads))
     if rc != 0:
         raise ValueError(f"oracle_run rejected the parameters (rc={rc})")
+    if log == "full":
+        return lc[:, :nif], lf[:, :nif], lz[:, :nif], ls
     if log:
         return lc[:, :nif], lf[:, :nif], lz[:, :nif]
     return None
+
+
+# objective of the adjoint: cx * sum of interface positions + mass in [wa, wb]
+OBJ_CX, OBJ_WA, OBJ_WB = 1.0, 0.4, 0.6
+
+
+def objective(state, cx=OBJ_CX, wa=OBJ_WA, wb=OBJ_WB):
+    """Per-problem objective cx sum_k x_k + sum_s rho_s |slot_s ∩ [wa, wb]|."""
+    b = state.batch
+    n_cells, h, _, ioff, soff = _geometry(b)
+    xl = np.ascontiguousarray(b.x_left, dtype=np.float64)
+    out = np.zeros(b.n_problems)
+    lib().oracle_objective(b.n_problems, _ptr(n_cells, ctypes.c_int), _ptr(h, ctypes.c_double),
+                           _ptr(xl, ctypes.c_double), _ptr(ioff, ctypes.c_int),
+                           _ptr(soff, ctypes.c_longlong), _ptr(state.home, ctypes.c_int),
+                           _ptr(state.hl, ctypes.c_double), _ptr(state.rho, ctypes.c_double),
+                           float(cx), float(wa), float(wb), _ptr(out, ctypes.c_double))
+    return out
+
+
+def lib_tan():
+    global _lib_tan
+    if _lib_tan is None:
+        lib()
+        L = ctypes.CDLL(LIB_TAN)
+        dp, ip, lp = (ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
+                      ctypes.POINTER(ctypes.c_longlong))
+        L.oracle_tan_run.restype = ctypes.c_int
+        L.oracle_tan_run.argtypes = [dp, dp, ctypes.POINTER(_Par), ctypes.c_int, ip, dp, dp, ip, ip,
+                                     lp, ip, dp, dp, dp, dp, ip, dp, dp, dp, dp, dp, dp, ip, lp,
+                                     ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double, dp, dp, ctypes.c_int]
+        _lib_tan = L
+    return _lib_tan
+
+
+def tangent(state, material, params, n_steps, d_rho, d_mom, d_tau=0.0, d_hl=None,
+            cx=OBJ_CX, wa=OBJ_WA, wb=OBJ_WB, threads=1):
+    """Forward-mode derivative of the objective after ``n_steps`` steps along
+    the direction (d_rho, d_mom, d_tau[, d_hl]) of the initial state and the
+    kinetic coefficient (decisions frozen: those of the plain run).  Advances
+    ``state`` like run(); returns (objective per problem, derivative per
+    problem, final (d_rho, d_mom, d_hl))."""
+    b = state.batch
+    L = lib_tan()
+    n_cells, h, pf, ioff, soff = _geometry(b)
+    xl = np.ascontiguousarray(b.x_left, dtype=np.float64)
+    nif = max(b.n_iface, 1)
+    mat = np.array([material.a2v, material.a2l, material.p0, material.rhol0, material.tau])
+    dmat = np.array([0.0, 0.0, 0.0, 0.0, float(d_tau)])
+    dr = np.ascontiguousarray(d_rho, dtype=np.float64).copy()
+    dm = np.ascontiguousarray(d_mom, dtype=np.float64).copy()
+    dh = np.zeros(nif) if d_hl is None else np.ascontiguousarray(d_hl, dtype=np.float64).copy()
+    dpw = np.zeros(2 * nif)
+    dt = np.zeros(b.n_problems)
+    obj = np.zeros(b.n_problems)
+    dobj = np.zeros(b.n_problems)
+    rc = L.oracle_tan_run(_ptr(mat, ctypes.c_double), _ptr(dmat, ctypes.c_double),
+                          ctypes.byref(_par(params)), b.n_problems, _ptr(n_cells, ctypes.c_int),
+                          _ptr(h, ctypes.c_double), _ptr(xl, ctypes.c_double),
+                          _ptr(pf, ctypes.c_int), _ptr(ioff, ctypes.c_int),
+                          _ptr(soff, ctypes.c_longlong), _ptr(state.home, ctypes.c_int),
+                          _ptr(state.hl, ctypes.c_double), _ptr(dh, ctypes.c_double),
+                          _ptr(state.pw, ctypes.c_double), _ptr(dpw, ctypes.c_double),
+                          _ptr(state.warm, ctypes.c_int), _ptr(state.rho, ctypes.c_double),
+                          _ptr(dr, ctypes.c_double), _ptr(state.mom, ctypes.c_double),
+                          _ptr(dm, ctypes.c_double), _ptr(state.t, ctypes.c_double),
+                          _ptr(dt, ctypes.c_double), _ptr(state.status, ctypes.c_int),
+                          _ptr(state.steps, ctypes.c_longlong), int(n_steps), float(cx),
+                          float(wa), float(wb), _ptr(obj, ctypes.c_double),
+                          _ptr(dobj, ctypes.c_double), int(threads))
+    if rc != 0:
+        raise ValueError(f"oracle_tan_run rejected the parameters (rc={rc})")
+    return obj, dobj, (dr, dm, dh[:b.n_iface])
 
 
 def iface_solve(material, phl, rl, ul, phr, rr, ur, guess=None, maxit=50, rtol=1e-14):

@@ -33,11 +33,35 @@
  *   - CFL time step (eq. cfl_cond:unif);
  *   - grid alignment with merging of vanishing cut pieces and re-splitting
  *     (Sec. 2.3), by the deterministic rule stated in the design notes.
+ *
+ * Tangent build.  Every quantity that depends on the state or on the kinetic
+ * coefficient has the type `real`.  Compiled as C, `real` is double and this
+ * is the oracle above.  Compiled as C++ with -DOR_TANGENT, `real` is a dual
+ * number (value, derivative) from or_dual.h: the value parts go through
+ * exactly the same IEEE operations in the same order (so every branch,
+ * count and event is the same), and the derivative parts carry the exact
+ * directional derivative of the executed discrete map (forward-mode
+ * differentiation, decisions frozen).  That build is the reference the
+ * hand-written reverse-mode GPU adjoint is checked against.
+ *
+ * Replay.  oracle_run can also be told the discrete decisions of a previous
+ * run (pseudo-iteration counts, merges, crossings, CFL cell) and then
+ * repeats them instead of testing; central finite differences of the loss
+ * with decisions frozen use it.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+#ifdef OR_TANGENT
+#include "or_dual.h"
+typedef or_dual real;
+#define OR_API extern "C"
+#else
+typedef double real;
+#define OR_API
+#endif
 
 #define OR_LIQ 0
 #define OR_VAP 1
@@ -59,11 +83,11 @@
 #define OR_MAXC 32
 
 typedef struct {
-  double a2v;   /* vapour: p = a2v rho,  a2v = k T0 / m  */
-  double a2l;   /* liquid: p = p0 + a2l (rho - rhol0), a2l = K0 / rho0 */
-  double p0;    /* saturation pressure */
-  double rhol0; /* liquid saturation density */
-  double tau;   /* kinetic coefficient */
+  real a2v;   /* vapour: p = a2v rho,  a2v = k T0 / m  */
+  real a2l;   /* liquid: p = p0 + a2l (rho - rhol0), a2l = K0 / rho0 */
+  real p0;    /* saturation pressure */
+  real rhol0; /* liquid saturation density */
+  real tau;   /* kinetic coefficient */
 } or_material;
 
 typedef struct {
@@ -84,14 +108,14 @@ typedef struct {
 /* ------------------------------------------------------------------ */
 /* phase laws                                                          */
 /* ------------------------------------------------------------------ */
-static double or_a2(const or_material *M, int ph) { return ph == OR_VAP ? M->a2v : M->a2l; }
+static real or_a2(const or_material *M, int ph) { return ph == OR_VAP ? M->a2v : M->a2l; }
 
-static double or_pres(const or_material *M, int ph, double rho) {
+static real or_pres(const or_material *M, int ph, real rho) {
   return ph == OR_VAP ? M->a2v * rho : M->p0 + M->a2l * (rho - M->rhol0);
 }
 
 /* inverse pressure law (used inside the interface solve), reciprocal form */
-static double or_rho_of_p(const or_material *M, int ph, double p) {
+static real or_rho_of_p(const or_material *M, int ph, real p) {
   return ph == OR_VAP ? p * (1.0 / M->a2v) : M->rhol0 + (p - M->p0) * (1.0 / M->a2l);
 }
 
@@ -102,7 +126,7 @@ static double or_rho_of_p(const or_material *M, int ph, double p) {
  * zero bits and a tail (as in fdlibm).  Written as plain IEEE double
  * operations in a fixed order, so every IEEE machine gives the same bits;
  * accurate to a few ulp (checked against the C library in the tests). */
-double oracle_log(double x) {
+OR_API double oracle_log(double x) {
   if (!(x > 0.0)) return x == 0.0 ? -INFINITY : NAN;
   if (!isfinite(x)) return x;
   uint64_t b;
@@ -138,18 +162,24 @@ double oracle_log(double x) {
   return de * 0x1.62e42feep-1 + (de * 0x1.a39ef35793c76p-33 + r);
 }
 
+#ifdef OR_TANGENT
+static real or_log(real x) { return or_dual(oracle_log(x.v), x.d / x.v); }
+#else
+static real or_log(real x) { return oracle_log(x); }
+#endif
+
 /* ------------------------------------------------------------------ */
 /* HLL flux of the isothermal Euler system, same phase both sides      */
 /* ------------------------------------------------------------------ */
-void oracle_hll(const or_material *M, int ph, double rl, double ml, double rr, double mr,
-                double *F) {
-  double a = sqrt(or_a2(M, ph));
-  double ul = ml / rl, ur = mr / rr;
-  double pl = or_pres(M, ph, rl), pr = or_pres(M, ph, rr);
-  double sl = (ul < ur ? ul : ur) - a;
-  double sr = (ul > ur ? ul : ur) + a;
-  double fl0 = ml, fl1 = ml * ul + pl;
-  double fr0 = mr, fr1 = mr * ur + pr;
+static void or_hll(const or_material *M, int ph, real rl, real ml, real rr, real mr,
+                real *F) {
+  real a = sqrt(or_a2(M, ph));
+  real ul = ml / rl, ur = mr / rr;
+  real pl = or_pres(M, ph, rl), pr = or_pres(M, ph, rr);
+  real sl = (ul < ur ? ul : ur) - a;
+  real sr = (ul > ur ? ul : ur) + a;
+  real fl0 = ml, fl1 = ml * ul + pl;
+  real fr0 = mr, fr1 = mr * ur + pr;
   if (sl >= 0.0) {
     F[0] = fl0;
     F[1] = fl1;
@@ -160,30 +190,37 @@ void oracle_hll(const or_material *M, int ph, double rl, double ml, double rr, d
     F[1] = fr1;
     return;
   }
-  double d = sr - sl, ss = sl * sr;
+  real d = sr - sl, ss = sl * sr;
   F[0] = ((sr * fl0 - sl * fr0) + ss * (rr - rl)) / d;
   F[1] = ((sr * fl1 - sl * fr1) + ss * (mr - ml)) / d;
 }
 
+#ifndef OR_TANGENT
+void oracle_hll(const or_material *M, int ph, double rl, double ml, double rr, double mr,
+                double *F) {
+  or_hll(M, ph, rl, ml, rr, mr, F);
+}
+#endif
+
 /* boundary flux: ghost state (rho, -m) for a wall, (rho, m) transmissive */
-static void or_bflux(const or_material *M, int ph, int side_right, int bc, double r, double m,
-                     double *F) {
-  double mg = (bc == 0) ? -m : m;
+static void or_bflux(const or_material *M, int ph, int side_right, int bc, real r, real m,
+                     real *F) {
+  real mg = (bc == 0) ? -m : m;
   if (side_right)
-    oracle_hll(M, ph, r, m, r, mg, F);
+    or_hll(M, ph, r, m, r, mg, F);
   else
-    oracle_hll(M, ph, r, mg, r, m, F);
+    or_hll(M, ph, r, mg, r, m, F);
 }
 
 /* ------------------------------------------------------------------ */
 /* interface Riemann problem with phase transition (Appendix A)        */
 /* ------------------------------------------------------------------ */
 typedef struct {
-  double pl, pr; /* star pressures left / right of the phase boundary */
-  double rl, rr; /* star densities */
-  double ul, ur; /* star velocities */
-  double z, w;   /* mass flux, phase-boundary speed */
-  double F0, F1; /* flux across the moving phase boundary */
+  real pl, pr; /* star pressures left / right of the phase boundary */
+  real rl, rr; /* star densities */
+  real ul, ur; /* star velocities */
+  real z, w;   /* mass flux, phase-boundary speed */
+  real F0, F1; /* flux across the moving phase boundary */
   int iters;
   int ok;
 } or_iface;
@@ -194,11 +231,11 @@ typedef struct {
  * rarefaction wave a ln(rho_star / rho_K) = a (L* - L_K). */
 typedef struct {
   int ph;
-  double r, u, p, LK;
-  double a, a2, ia, ia2, hia, irs;
+  real r, u, p, LK;
+  real a, a2, ia, ia2, hia, irs;
 } or_side;
 
-static void or_side_init(const or_material *M, int ph, double r, double m, or_side *S) {
+static void or_side_init(const or_material *M, int ph, real r, real m, or_side *S) {
   S->ph = ph;
   S->r = r;
   S->u = m / r;
@@ -209,27 +246,27 @@ static void or_side_init(const or_material *M, int ph, double r, double m, or_si
   S->ia2 = 1.0 / S->a2;
   S->hia = 0.5 * S->ia;
   S->irs = ph == OR_VAP ? 1.0 / (M->p0 / M->a2v) : 1.0 / M->rhol0;
-  S->LK = oracle_log(r * S->irs);
+  S->LK = or_log(r * S->irs);
 }
 
 typedef struct {
-  double rs, v, g, f, df;
+  real rs, v, g, f, df;
 } or_seval;
 
 /* Outer wave at star pressure ps (Appendix A): density, specific volume,
  * Gibbs energy, f_K and df_K/dp*.  Shock branch sqrt(-[[p]][[v]]) written
  * a (rho* - rho_K)/sqrt(rho_K rho*) (exact for pressure laws affine in rho);
  * rarefaction branch: the integral of v/a, a ln(rho_star / rho_K). */
-static int or_wave(const or_material *M, const or_side *S, double ps, or_seval *E) {
-  double r = or_rho_of_p(M, S->ph, ps);
+static int or_wave(const or_material *M, const or_side *S, real ps, or_seval *E) {
+  real r = or_rho_of_p(M, S->ph, ps);
   if (!(r > 0.0) || !isfinite(r)) return 0;
-  double v = 1.0 / r;
-  double L = oracle_log(r * S->irs);
+  real v = 1.0 / r;
+  real L = or_log(r * S->irs);
   E->rs = r;
   E->v = v;
   E->g = S->a2 * L;
   if (ps > S->p) {
-    double ig = 1.0 / sqrt(S->r * r);
+    real ig = 1.0 / sqrt(S->r * r);
     E->f = (S->a * (r - S->r)) * ig;
     E->df = ((r + S->r) * ig) * (v * S->hia);
   } else {
@@ -242,11 +279,11 @@ static int or_wave(const or_material *M, const or_side *S, double ps, or_seval *
 typedef struct {
   int phl, phr;
   or_side L, R;
-  double izref; /* 1 / max(rho_l a_l, rho_r a_r) */
+  real izref; /* 1 / max(rho_l a_l, rho_r a_r) */
 } or_rp;
 
 typedef struct {
-  double G1, G2, J11, J12, J21, J22, m2, z;
+  real G1, G2, J11, J12, J21, J22, m2, z;
   or_seval l, r;
 } or_geval;
 
@@ -256,26 +293,26 @@ typedef struct {
  * energy relative to the boundary), i.e. A z^2 - z + C = 0 with
  * A = tau p_V [[v^2]]/2 and C = tau p_V [[g]], root continuous at A -> 0;
  * dz/dp by implicit differentiation, where 2 A z - 1 = -sqrt(1 - 4 A C). */
-static int or_eval_G(const or_material *M, const or_rp *R, double psl, double psr, or_geval *E) {
+static int or_eval_G(const or_material *M, const or_rp *R, real psl, real psr, or_geval *E) {
   if (!or_wave(M, &R->L, psl, &E->l)) return 0;
   if (!or_wave(M, &R->R, psr, &E->r)) return 0;
-  double vl = E->l.v, vr = E->r.v;
-  double pV = (R->phl == OR_VAP) ? psl : psr;
-  double q = M->tau * pV;
-  double jg = E->r.g - E->l.g;
-  double jv2 = vr * vr - vl * vl;
-  double A = 0.5 * q * jv2;
-  double C = q * jg;
-  double D = 1.0 - 4.0 * A * C;
+  real vl = E->l.v, vr = E->r.v;
+  real pV = (R->phl == OR_VAP) ? psl : psr;
+  real q = M->tau * pV;
+  real jg = E->r.g - E->l.g;
+  real jv2 = vr * vr - vl * vl;
+  real A = 0.5 * q * jv2;
+  real C = q * jg;
+  real D = 1.0 - 4.0 * A * C;
   if (!(D >= 0.0) || !isfinite(D)) return 0;
-  double sD = sqrt(D);
-  double isD = 1.0 / sD;
-  double z = 2.0 * C / (1.0 + sD);
+  real sD = sqrt(D);
+  real isD = 1.0 / sD;
+  real z = 2.0 * C / (1.0 + sD);
   /* d(v^2)/dp = -2 v^3 / a^2, dg/dp = v */
-  double dAl = q * ((vl * vl * vl) * R->L.ia2);
-  double dAr = -(q * ((vr * vr * vr) * R->R.ia2));
-  double dCl = -(q * vl);
-  double dCr = q * vr;
+  real dAl = q * ((vl * vl * vl) * R->L.ia2);
+  real dAr = -(q * ((vr * vr * vr) * R->R.ia2));
+  real dCl = -(q * vl);
+  real dCr = q * vr;
   if (R->phl == OR_VAP) {
     dAl += (0.5 * M->tau) * jv2;
     dCl += M->tau * jg;
@@ -283,11 +320,11 @@ static int or_eval_G(const or_material *M, const or_rp *R, double psl, double ps
     dAr += (0.5 * M->tau) * jv2;
     dCr += M->tau * jg;
   }
-  double dzl = (dAl * z * z + dCl) * isD;
-  double dzr = (dAr * z * z + dCr) * isD;
-  double jv = vr - vl;
-  double el = (vl * vl) * R->L.ia2; /* = d[[v]]/dp_l* */
-  double er = (vr * vr) * R->R.ia2; /* = -d[[v]]/dp_r* */
+  real dzl = (dAl * z * z + dCl) * isD;
+  real dzr = (dAr * z * z + dCr) * isD;
+  real jv = vr - vl;
+  real el = (vl * vl) * R->L.ia2; /* = d[[v]]/dp_l* */
+  real er = (vr * vr) * R->R.ia2; /* = -d[[v]]/dp_r* */
   E->z = z;
   E->G1 = (psr - psl) + z * z * jv;
   E->G2 = (E->l.f + E->r.f) + z * jv + (R->R.u - R->L.u);
@@ -296,7 +333,7 @@ static int or_eval_G(const or_material *M, const or_rp *R, double psl, double ps
   E->J21 = E->l.df + dzl * jv + z * el;
   E->J22 = E->r.df + dzr * jv - z * er;
   if (!isfinite(E->G1) || !isfinite(E->G2)) return 0;
-  double a = E->G1 * R->izref;
+  real a = E->G1 * R->izref;
   E->m2 = a * a + E->G2 * E->G2;
   return 1;
 }
@@ -305,20 +342,20 @@ static int or_eval_G(const or_material *M, const or_rp *R, double psl, double ps
  * left/right states (eq. HLLC:2p_nopt, mirrored for a liquid on the left),
  * liquid pressure law for the pressure; the vapour unknown is kept above
  * 1e-3 p_V so that it stays in the vapour state space. */
-static void or_guess(const or_material *M, const or_rp *R, double *gl, double *gr) {
+static void or_guess(const or_material *M, const or_rp *R, real *gl, real *gr) {
   const or_side *Ls = &R->L, *Rs = &R->R;
-  double sl = Ls->u - Ls->a, sr = Rs->u + Rs->a;
-  double num = (Rs->p - Ls->p) + Ls->r * Ls->u * (sl - Ls->u) - Rs->r * Rs->u * (sr - Rs->u);
-  double den = Ls->r * (sl - Ls->u) - Rs->r * (sr - Rs->u);
-  double ws = num / den;
-  double rLs;
+  real sl = Ls->u - Ls->a, sr = Rs->u + Rs->a;
+  real num = (Rs->p - Ls->p) + Ls->r * Ls->u * (sl - Ls->u) - Rs->r * Rs->u * (sr - Rs->u);
+  real den = Ls->r * (sl - Ls->u) - Rs->r * (sr - Rs->u);
+  real ws = num / den;
+  real rLs;
   if (R->phl == OR_LIQ)
     rLs = Ls->r * (sl - Ls->u) / (sl - ws);
   else
     rLs = Rs->r * (sr - Rs->u) / (sr - ws);
-  double pg = or_pres(M, OR_LIQ, rLs);
-  double pV = (R->phl == OR_VAP) ? Ls->p : Rs->p;
-  double pvg = pg > 1e-3 * pV ? pg : 1e-3 * pV;
+  real pg = or_pres(M, OR_LIQ, rLs);
+  real pV = (R->phl == OR_VAP) ? Ls->p : Rs->p;
+  real pvg = pg > 1e-3 * pV ? pg : 1e-3 * pV;
   if (R->phl == OR_VAP) {
     *gl = pvg;
     *gr = pg;
@@ -336,24 +373,24 @@ static void or_guess(const or_material *M, const or_rp *R, double *gl, double *g
  * until the squared merit ((G1/zref)^2 + G2^2) drops below
  * (1 - 1e-4 lambda)^2 times its current value; if that fails the point is
  * kept only if the step is already below 1e-8 (round-off floor). */
-static int or_newton(const or_material *M, const or_rp *R, double xl, double xr, int maxit,
-                     double rtol, double *ol, double *orr, or_geval *Eo, int *iters) {
+static int or_newton(const or_material *M, const or_rp *R, real xl, real xr, int maxit,
+                     real rtol, real *ol, real *orr, or_geval *Eo, int *iters) {
   or_geval E, Et;
-  const double qtol = 1e-10;
+  const real qtol = 1e-10;
   if (!or_eval_G(M, R, xl, xr, &E)) return 0;
   int it;
   for (it = 0; it < maxit; ++it) {
-    double det = E.J11 * E.J22 - E.J12 * E.J21;
+    real det = E.J11 * E.J22 - E.J12 * E.J21;
     if (!(det != 0.0) || !isfinite(det)) return 0;
-    double idet = 1.0 / det;
-    double dl = (-E.G1 * E.J22 + E.G2 * E.J12) * idet;
-    double dr = (-E.G2 * E.J11 + E.G1 * E.J21) * idet;
-    double sc = fabs(xl) > fabs(xr) ? fabs(xl) : fabs(xr);
+    real idet = 1.0 / det;
+    real dl = (-E.G1 * E.J22 + E.G2 * E.J12) * idet;
+    real dr = (-E.G2 * E.J11 + E.G1 * E.J21) * idet;
+    real sc = fabs(xl) > fabs(xr) ? fabs(xl) : fabs(xr);
     if (M->p0 > sc) sc = M->p0;
-    double st = fabs(dl) > fabs(dr) ? fabs(dl) : fabs(dr);
+    real st = fabs(dl) > fabs(dr) ? fabs(dl) : fabs(dr);
     if (!isfinite(st)) return 0;
     if (st <= rtol * sc) {
-      double tl = xl + dl, tr = xr + dr;
+      real tl = xl + dl, tr = xr + dr;
       if (or_eval_G(M, R, tl, tr, &Et)) {
         xl = tl;
         xr = tr;
@@ -365,11 +402,11 @@ static int or_newton(const or_material *M, const or_rp *R, double xl, double xr,
       *iters = it + 1;
       return 1;
     }
-    double lam = 1.0;
+    real lam = 1.0;
     int acc = 0, k;
     for (k = 0; k <= 20; ++k) {
-      double tl = xl + lam * dl, tr = xr + lam * dr;
-      double c = 1.0 - 1e-4 * lam;
+      real tl = xl + lam * dl, tr = xr + lam * dr;
+      real c = 1.0 - 1e-4 * lam;
       if (or_eval_G(M, R, tl, tr, &Et) && Et.m2 <= (c * c) * E.m2) {
         xl = tl;
         xr = tr;
@@ -403,8 +440,8 @@ static int or_newton(const or_material *M, const or_rp *R, double xl, double xr,
 /* Starting points, tried in this order until Newton-Armijo converges:
  * the caller's warm start (if any), the HLLC-type guess, and both unknowns
  * at the vapour state's own pressure. */
-int oracle_iface_solve(const or_material *M, int phl, double rl, double ml, int phr, double rr,
-                       double mr, int have_guess, double gl, double gr, int maxit, double rtol,
+static int or_iface_solve(const or_material *M, int phl, real rl, real ml, int phr, real rr,
+                       real mr, int have_guess, real gl, real gr, int maxit, real rtol,
                        or_iface *out) {
   memset(out, 0, sizeof(*out));
   if (!(rl > 0.0) || !(rr > 0.0) || phl == phr) return 0;
@@ -413,13 +450,13 @@ int oracle_iface_solve(const or_material *M, int phl, double rl, double ml, int 
   R.phr = phr;
   or_side_init(M, phl, rl, ml, &R.L);
   or_side_init(M, phr, rr, mr, &R.R);
-  double zl = rl * R.L.a, zr = rr * R.R.a;
+  real zl = rl * R.L.a, zr = rr * R.R.a;
   R.izref = 1.0 / (zl > zr ? zl : zr);
-  double xl = 0.0, xr = 0.0;
+  real xl = 0.0, xr = 0.0;
   or_geval E;
   int iters = 0, conv = 0, attempt;
   for (attempt = 0; attempt < 3 && !conv; ++attempt) {
-    double sl, sr;
+    real sl, sr;
     if (attempt == 0) {
       if (!have_guess) continue;
       sl = gl;
@@ -427,7 +464,7 @@ int oracle_iface_solve(const or_material *M, int phl, double rl, double ml, int 
     } else if (attempt == 1) {
       or_guess(M, &R, &sl, &sr);
     } else {
-      double pV = (phl == OR_VAP) ? R.L.p : R.R.p;
+      real pV = (phl == OR_VAP) ? R.L.p : R.R.p;
       sl = pV;
       sr = pV;
     }
@@ -444,7 +481,7 @@ int oracle_iface_solve(const or_material *M, int phl, double rl, double ml, int 
   out->ul = R.L.u - E.l.f;
   out->ur = R.R.u + E.r.f;
   out->z = E.z;
-  double uV, vV, pV;
+  real uV, vV, pV;
   if (phl == OR_VAP) {
     uV = out->ul;
     vV = E.l.v;
@@ -461,16 +498,23 @@ int oracle_iface_solve(const or_material *M, int phl, double rl, double ml, int 
   return 1;
 }
 
+#ifndef OR_TANGENT
+int oracle_iface_solve(const or_material *M, int phl, double rl, double ml, int phr, double rr,
+                       double mr, int have_guess, double gl, double gr, int maxit, double rtol,
+                       or_iface *out) {
+  return or_iface_solve(M, phl, rl, ml, phr, rr, mr, have_guess, gl, gr, maxit, rtol, out);
+}
+
 /* G and its Jacobian at a given point (test hook for the analytic Jacobian) */
-int oracle_iface_G(const or_material *M, int phl, double rl, double ml, int phr, double rr,
-                   double mr, double psl, double psr, double *out6) {
+int oracle_iface_G(const or_material *M, int phl, real rl, real ml, int phr, real rr,
+                   real mr, real psl, real psr, real *out6) {
   or_rp R;
   or_geval E;
   R.phl = phl;
   R.phr = phr;
   or_side_init(M, phl, rl, ml, &R.L);
   or_side_init(M, phr, rr, mr, &R.R);
-  double zl = rl * R.L.a, zr = rr * R.R.a;
+  real zl = rl * R.L.a, zr = rr * R.R.a;
   R.izref = 1.0 / (zl > zr ? zl : zr);
   if (!or_eval_G(M, &R, psl, psr, &E)) return 0;
   out6[0] = E.G1;
@@ -481,22 +525,27 @@ int oracle_iface_G(const or_material *M, int phl, double rl, double ml, int phr,
   out6[5] = E.J22;
   return 1;
 }
+#endif
 
 /* ------------------------------------------------------------------ */
 /* one problem                                                         */
 /* ------------------------------------------------------------------ */
 typedef struct {
   int n, nif;
-  double h;
+  real h;
   int phase_first;
-  double *rho, *mom; /* n + nif slots */
+  real *rho, *mom; /* n + nif slots */
   int *home;         /* background cell containing interface k */
-  double *hl;        /* offset of interface k inside its home cell */
-  double *pw;        /* 2 per interface: last converged star pressures */
+  real *hl;        /* offset of interface k inside its home cell */
+  real *pw;        /* 2 per interface: last converged star pressures */
   int *warm;
-  double *t;
+  real *t;
   int *status;
   long long *steps;
+  /* replay of a previous run's decisions at the current step (NULL: decide) */
+  const int *rp_count; /* [nif] pseudo-iteration counts */
+  const int *rp_flags; /* [nif] event flags (merge, crossings) */
+  int rp_cfl;          /* slot whose |u| + a set the time step (-1: take the max) */
 } or_prob;
 
 typedef struct {
@@ -504,15 +553,15 @@ typedef struct {
   int slot[OR_MAXC];
   int ph[OR_MAXC];
   int mov[OR_MAXC];
-  double U0[OR_MAXC][2];
-  double hn[OR_MAXC];
-  double hh[OR_MAXC]; /* end-of-step length predicted with the explicit speed */
-  double th[OR_MAXC];
-  double i1t[OR_MAXC]; /* 1 / (1 + theta) */
-  double thr[OR_MAXC]; /* tol_i * theta_i dt: stop threshold per unit max(|W|,1) */
+  real U0[OR_MAXC][2];
+  real hn[OR_MAXC];
+  real hh[OR_MAXC]; /* end-of-step length predicted with the explicit speed */
+  real th[OR_MAXC];
+  real i1t[OR_MAXC]; /* 1 / (1 + theta) */
+  real thr[OR_MAXC]; /* tol_i * theta_i dt: stop threshold per unit max(|W|,1) */
   int ic;   /* phase boundary lies between active cells ic and ic+1 */
   int tiny; /* active index of the tiny (or merged) cell */
-  double FL[2], FR[2];
+  real FL[2], FR[2];
 } or_zone;
 
 typedef struct {
@@ -536,7 +585,7 @@ static void or_zone_range(const or_params *P, const or_prob *pb, int k, int *zlo
                           int *tiny_right) {
   int ns = pb->n + pb->nif;
   int sL = pb->home[k] + k;
-  double hL = pb->hl[k], hR = pb->h - hL;
+  real hL = pb->hl[k], hR = pb->h - hL;
   int tr = !(hL <= hR);
   int c = tr ? sL + 1 : sL;
   int lo = c - P->zone_half, hi = c + P->zone_half;
@@ -549,12 +598,12 @@ static void or_zone_range(const or_params *P, const or_prob *pb, int k, int *zlo
 
 /* zone set-up: active cells, lengths, merge, pseudo-step fractions */
 static int or_zone_build(const or_material *M, const or_params *P, const or_prob *pb, int k,
-                         const int *ph, int zlo, int zhi, int tiny_right, int merge, double w,
-                         double dt, or_zone *Z) {
+                         const int *ph, int zlo, int zhi, int tiny_right, int merge, real w,
+                         real dt, or_zone *Z) {
   int ns = pb->n + pb->nif;
   int sL = pb->home[k] + k, sR = sL + 1;
-  double h = pb->h;
-  double hL = pb->hl[k], hR = h - hL;
+  real h = pb->h;
+  real hL = pb->hl[k], hR = h - hL;
   int skip = -1, into = -1;
   if (merge) {
     if (!tiny_right) {
@@ -586,8 +635,8 @@ static int or_zone_build(const or_material *M, const or_params *P, const or_prob
       Z->mov[m] = -1;
     }
     if (s == into) {
-      double ht = tiny_right ? hR : hL;
-      double hm = h + ht;
+      real ht = tiny_right ? hR : hL;
+      real hm = h + ht;
       Z->U0[m][0] = (h * pb->rho[s] + ht * pb->rho[skip]) / hm;
       Z->U0[m][1] = (h * pb->mom[s] + ht * pb->mom[skip]) / hm;
       Z->hn[m] = hm;
@@ -603,8 +652,8 @@ static int or_zone_build(const or_material *M, const or_params *P, const or_prob
   }
   if (Z->ic < 0 || Z->ic + 1 >= m || Z->tiny < 0) return 0;
   for (s = 0; s < m; ++s) {
-    double hh = Z->hn[s] + ((double)Z->mov[s] * w) * dt;
-    double th = hh / h;
+    real hh = Z->hn[s] + ((double)Z->mov[s] * w) * dt;
+    real th = hh / h;
     if (th > P->theta_nb) th = P->theta_nb;
     Z->hh[s] = hh;
     Z->th[s] = th;
@@ -616,18 +665,18 @@ static int or_zone_build(const or_material *M, const or_params *P, const or_prob
   if (zlo == 0)
     or_bflux(M, ph[0], 0, P->bc_left, pb->rho[0], pb->mom[0], Z->FL);
   else
-    oracle_hll(M, ph[zlo], pb->rho[zlo - 1], pb->mom[zlo - 1], pb->rho[zlo], pb->mom[zlo], Z->FL);
+    or_hll(M, ph[zlo], pb->rho[zlo - 1], pb->mom[zlo - 1], pb->rho[zlo], pb->mom[zlo], Z->FL);
   if (zhi == ns - 1)
     or_bflux(M, ph[ns - 1], 1, P->bc_right, pb->rho[ns - 1], pb->mom[ns - 1], Z->FR);
   else
-    oracle_hll(M, ph[zhi], pb->rho[zhi], pb->mom[zhi], pb->rho[zhi + 1], pb->mom[zhi + 1], Z->FR);
+    or_hll(M, ph[zhi], pb->rho[zhi], pb->mom[zhi], pb->rho[zhi + 1], pb->mom[zhi + 1], Z->FR);
   return 1;
 }
 
 /* face fluxes of a zone iterate W; the phase-boundary face uses the
  * interface Riemann solver, all other inner faces HLL. */
 static int or_zone_fluxes(const or_material *M, const or_params *P, const or_zone *Z,
-                          double W[][2], double F[][2], double *pw, double *wout) {
+                          real W[][2], real F[][2], real *pw, real *wout) {
   int c;
   F[0][0] = Z->FL[0];
   F[0][1] = Z->FL[1];
@@ -636,7 +685,7 @@ static int or_zone_fluxes(const or_material *M, const or_params *P, const or_zon
   for (c = 0; c + 1 < Z->m; ++c) {
     if (c == Z->ic) {
       or_iface I;
-      if (!oracle_iface_solve(M, Z->ph[c], W[c][0], W[c][1], Z->ph[c + 1], W[c + 1][0],
+      if (!or_iface_solve(M, Z->ph[c], W[c][0], W[c][1], Z->ph[c + 1], W[c + 1][0],
                               W[c + 1][1], 1, pw[0], pw[1], P->newton_maxit, P->newton_rtol, &I))
         return 0;
       pw[0] = I.pl;
@@ -645,13 +694,13 @@ static int or_zone_fluxes(const or_material *M, const or_params *P, const or_zon
       F[c + 1][0] = I.F0;
       F[c + 1][1] = I.F1;
     } else {
-      oracle_hll(M, Z->ph[c], W[c][0], W[c][1], W[c + 1][0], W[c + 1][1], F[c + 1]);
+      or_hll(M, Z->ph[c], W[c][0], W[c][1], W[c + 1][0], W[c + 1][1], F[c + 1]);
     }
   }
   return 1;
 }
 
-static int or_state_ok(double r, double m) { return r > 0.0 && isfinite(r) && isfinite(m); }
+static int or_state_ok(real r, real m) { return r > 0.0 && isfinite(r) && isfinite(m); }
 
 /* Algorithm 2 on one zone. Returns 0 on success, or a status bit.
  * *shrink_cell is set when a moving cell fell below half of its predicted
@@ -663,12 +712,12 @@ static int or_state_ok(double r, double m) { return r > 0.0 && isfinite(r) && is
  *   |(1 + theta_i)(W^{l+1} - W^l)| < tol_i (theta_i dt) max(|W^l|, 1)
  * for both components of every cell (tol_tiny on the tiny cell, tol_nb on
  * the others); in relative mode |W^{l+1} - W^l| < tol_rel max(|W^l|, 1). */
-static int or_zone_dts(const or_material *M, const or_params *P, const or_zone *Z, double dt,
-                       double *pw, double U1[][2], double *wstar, int *count, int *lmax_hit,
-                       int *shrink_cell) {
-  double W[OR_MAXC][2], Wn[OR_MAXC][2], F[OR_MAXC + 1][2], hnew[OR_MAXC], ih[OR_MAXC];
+static int or_zone_dts(const or_material *M, const or_params *P, const or_zone *Z, real dt,
+                       real *pw, real U1[][2], real *wstar, int *count, int *lmax_hit,
+                       int *shrink_cell, int force_count) {
+  real W[OR_MAXC][2], Wn[OR_MAXC][2], F[OR_MAXC + 1][2], hnew[OR_MAXC], ih[OR_MAXC];
   int c, l, m = Z->m;
-  double w = 0.0;
+  real w = 0.0;
   *shrink_cell = -1;
   *lmax_hit = 0;
   for (c = 0; c < m; ++c) {
@@ -676,8 +725,9 @@ static int or_zone_dts(const or_material *M, const or_params *P, const or_zone *
     W[c][1] = Z->U0[c][1];
   }
   int cnt = 0, stop = 0;
-  /* Part 1: pseudo-time iterations */
-  for (l = 0; l < P->lmax; ++l) {
+  /* Part 1: pseudo-time iterations (exactly force_count of them in a replay) */
+  int lmax = force_count > 0 ? force_count : P->lmax;
+  for (l = 0; l < lmax; ++l) {
     if (!or_zone_fluxes(M, P, Z, W, F, pw, &w)) return OR_ST_NEWTON;
     for (c = 0; c < m; ++c) {
       hnew[c] = Z->hn[c] + ((double)Z->mov[c] * w) * dt;
@@ -689,13 +739,13 @@ static int or_zone_dts(const or_material *M, const or_params *P, const or_zone *
     }
     int conv = 1;
     for (c = 0; c < m; ++c) {
-      double th = Z->th[c], opt = 1.0 + th;
+      real th = Z->th[c], opt = 1.0 + th;
       int q;
       for (q = 0; q < 2; ++q) {
-        double rhs = (Z->hn[c] * Z->U0[c][q] - dt * (F[c + 1][q] - F[c][q])) * ih[c];
+        real rhs = (Z->hn[c] * Z->U0[c][q] - dt * (F[c + 1][q] - F[c][q])) * ih[c];
         Wn[c][q] = (W[c][q] + th * rhs) * Z->i1t[c];
-        double d = Wn[c][q] - W[c][q];
-        double sc = fabs(W[c][q]) > 1.0 ? fabs(W[c][q]) : 1.0;
+        real d = Wn[c][q] - W[c][q];
+        real sc = fabs(W[c][q]) > 1.0 ? fabs(W[c][q]) : 1.0;
         int ok = (P->tol_mode == 0) ? (fabs(opt * d) < Z->thr[c] * sc) : (fabs(d) < P->tol_rel * sc);
         conv = conv && ok;
       }
@@ -706,7 +756,7 @@ static int or_zone_dts(const or_material *M, const or_params *P, const or_zone *
       W[c][1] = Wn[c][1];
     }
     cnt = l + 1;
-    stop = conv;
+    stop = force_count > 0 ? cnt == force_count : conv;
     if (stop) break;
   }
   if (!stop) *lmax_hit = 1;
@@ -734,10 +784,10 @@ static int or_zone_dts(const or_material *M, const or_params *P, const or_zone *
 /* Predict, merge, solve and re-align one interface zone. Writes the zone's
  * new cell values into (rn, mn). Returns 0 or a status bit. */
 static int or_zone_step(const or_material *M, const or_params *P, or_prob *pb, int k,
-                        const int *ph, double dt, double *rn, double *mn, or_zlog *lg) {
+                        const int *ph, real dt, real *rn, real *mn, or_zlog *lg) {
   int ns = pb->n + pb->nif;
   int sL = pb->home[k] + k, sR = sL + 1;
-  double h = pb->h;
+  real h = pb->h;
   int zlo, zhi, tr;
   or_zone_range(P, pb, k, &zlo, &zhi, &tr);
   lg->zlo = zlo;
@@ -745,25 +795,31 @@ static int or_zone_step(const or_material *M, const or_params *P, or_prob *pb, i
   lg->count = 0;
   /* explicit prediction of the phase-boundary speed from U^n */
   or_iface I;
-  if (!oracle_iface_solve(M, ph[sL], pb->rho[sL], pb->mom[sL], ph[sR], pb->rho[sR], pb->mom[sR],
+  if (!or_iface_solve(M, ph[sL], pb->rho[sL], pb->mom[sL], ph[sR], pb->rho[sR], pb->mom[sR],
                           pb->warm[k], pb->pw[2 * k], pb->pw[2 * k + 1], P->newton_maxit,
                           P->newton_rtol, &I))
     return OR_ST_NEWTON;
-  double wp = I.w;
-  double ht = tr ? h - pb->hl[k] : pb->hl[k];
-  double rate = tr ? -wp : wp;
-  double hfl = P->alpha_floor * h;
+  real wp = I.w;
+  real ht = tr ? h - pb->hl[k] : pb->hl[k];
+  real rate = tr ? -wp : wp;
+  real hfl = P->alpha_floor * h;
   int merge = (ht < hfl) || (ht + (P->merge_safety * rate) * dt < hfl);
+  int force = 0, rflags = 0;
+  if (pb->rp_count) {
+    force = pb->rp_count[k];
+    rflags = pb->rp_flags[k];
+    merge = (rflags & OR_FL_MERGED) != 0;
+  }
   int redo = 0;
-  double U1[OR_MAXC][2];
-  double wstar = 0.0;
+  real U1[OR_MAXC][2];
+  real wstar = 0.0;
   int count = 0, lmax_hit = 0;
   or_zone Z;
   for (;;) {
-    double pw[2] = {I.pl, I.pr};
+    real pw[2] = {I.pl, I.pr};
     if (!or_zone_build(M, P, pb, k, ph, zlo, zhi, tr, merge, wp, dt, &Z)) return OR_ST_MESH;
     int sc;
-    int st = or_zone_dts(M, P, &Z, dt, pw, U1, &wstar, &count, &lmax_hit, &sc);
+    int st = or_zone_dts(M, P, &Z, dt, pw, U1, &wstar, &count, &lmax_hit, &sc, force);
     if (st == OR_ST_MESH && !merge && sc == Z.tiny) {
       merge = 1;
       redo = 1;
@@ -779,12 +835,12 @@ static int or_zone_step(const or_material *M, const or_params *P, or_prob *pb, i
     rn[Z.slot[c]] = U1[c][0];
     mn[Z.slot[c]] = U1[c][1];
   }
-  double hln = pb->hl[k] + wstar * dt;
+  real hln = pb->hl[k] + wstar * dt;
   int fl = lg->flags;
   if (merge) {
     fl |= OR_FL_MERGED;
     if (!tr) {
-      if (hln < 0.0) {
+      if (pb->rp_count ? (rflags & OR_FL_CROSS_L) != 0 : hln < 0.0) {
         pb->home[k] -= 1;
         pb->hl[k] = hln + h;
         rn[sL] = rn[sR];
@@ -796,7 +852,7 @@ static int or_zone_step(const or_material *M, const or_params *P, or_prob *pb, i
         pb->hl[k] = hln;
       }
     } else {
-      if (hln > h) {
+      if (pb->rp_count ? (rflags & OR_FL_CROSS_R) != 0 : hln > h) {
         pb->home[k] += 1;
         pb->hl[k] = hln - h;
         rn[sR] = rn[sL];
@@ -821,35 +877,46 @@ static int or_zone_step(const or_material *M, const or_params *P, or_prob *pb, i
 }
 
 /* one physical step of one problem (Algorithm 1 with Algorithm 2 per zone) */
-static void or_step(const or_material *M, const or_params *P, or_prob *pb, int *ph, double *F,
-                    double *rn, double *mn, int *zmark, or_zlog *lg) {
+static void or_step(const or_material *M, const or_params *P, or_prob *pb, int *ph, real *F,
+                    real *rn, real *mn, int *zmark, or_zlog *lg, int *cfl_slot) {
   int ns = pb->n + pb->nif, s, k;
   for (k = 0; k < pb->nif; ++k) {
     lg[k].count = 0;
     lg[k].flags = OR_FL_INACTIVE;
     lg[k].zlo = -1;
   }
+  *cfl_slot = -1;
   if (*pb->status) return;
   if (!(*pb->t < P->t_end)) return;
   or_phases(pb, ph);
-  /* CFL (eq. cfl_cond:unif): maximal |u| + a over all cells */
-  double S = 0.0;
-  int bad = 0;
+  /* CFL (eq. cfl_cond:unif): maximal |u| + a over all cells (the first
+   * slot attaining it is reported) */
+  real S = 0.0;
+  int bad = 0, smax = -1;
   for (s = 0; s < ns; ++s) {
-    double r = pb->rho[s], m = pb->mom[s];
+    real r = pb->rho[s], m = pb->mom[s];
     if (!or_state_ok(r, m)) {
       bad = 1;
       break;
     }
-    double si = fabs(m / r) + sqrt(or_a2(M, ph[s]));
-    if (si > S) S = si;
+    real si = fabs(m / r) + sqrt(or_a2(M, ph[s]));
+    if (si > S) {
+      S = si;
+      smax = s;
+    }
   }
+  if (!bad && pb->rp_cfl >= 0) {
+    s = pb->rp_cfl;
+    S = fabs(pb->mom[s] / pb->rho[s]) + sqrt(or_a2(M, ph[s]));
+    smax = s;
+  }
+  *cfl_slot = smax;
   if (bad || !(S > 0.0) || !isfinite(S)) {
     *pb->status |= OR_ST_NONPHYS;
     return;
   }
-  double dt = (P->cfl * pb->h) / S;
-  double rem = P->t_end - *pb->t;
+  real dt = (P->cfl * pb->h) / S;
+  real rem = P->t_end - *pb->t;
   int clipped = 0;
   if (dt >= rem) {
     dt = rem;
@@ -869,7 +936,7 @@ static void or_step(const or_material *M, const or_params *P, or_prob *pb, int *
     for (s = zlo; s <= zhi; ++s) zmark[s] = k;
   }
   /* Algorithm 1, Step 1: explicit update of every cell outside the zones */
-  double lam = dt / pb->h;
+  real lam = dt / pb->h;
   for (s = 0; s <= ns; ++s) {
     int need = (s - 1 >= 0 && zmark[s - 1] < 0) || (s < ns && zmark[s] < 0);
     if (!need) continue;
@@ -878,7 +945,7 @@ static void or_step(const or_material *M, const or_params *P, or_prob *pb, int *
     else if (s == ns)
       or_bflux(M, ph[ns - 1], 1, P->bc_right, pb->rho[ns - 1], pb->mom[ns - 1], &F[2 * ns]);
     else
-      oracle_hll(M, ph[s], pb->rho[s - 1], pb->mom[s - 1], pb->rho[s], pb->mom[s], &F[2 * s]);
+      or_hll(M, ph[s], pb->rho[s - 1], pb->mom[s - 1], pb->rho[s], pb->mom[s], &F[2 * s]);
   }
   for (s = 0; s < ns; ++s) {
     rn[s] = pb->rho[s];
@@ -891,7 +958,7 @@ static void or_step(const or_material *M, const or_params *P, or_prob *pb, int *
   int fail = 0;
   for (k = 0; k < pb->nif; ++k) {
     int homek = pb->home[k];
-    double hlk = pb->hl[k];
+    real hlk = pb->hl[k];
     int st = or_zone_step(M, P, pb, k, ph, dt, rn, mn, &lg[k]);
     if (st) {
       pb->home[k] = homek;
@@ -906,8 +973,8 @@ static void or_step(const or_material *M, const or_params *P, or_prob *pb, int *
       fail |= st;
     }
   }
-  memcpy(pb->rho, rn, sizeof(double) * ns);
-  memcpy(pb->mom, mn, sizeof(double) * ns);
+  memcpy(pb->rho, rn, sizeof(real) * ns);
+  memcpy(pb->mom, mn, sizeof(real) * ns);
   if (fail) {
     *pb->status |= fail;
     return;
@@ -917,16 +984,83 @@ static void or_step(const or_material *M, const or_params *P, or_prob *pb, int *
 }
 
 /* ------------------------------------------------------------------ */
-/* batch driver                                                        */
+/* objective and batch driver                                          */
 /* ------------------------------------------------------------------ */
+/* Scalar objective of one problem: cx times the sum of its interface
+ * positions plus the mass in the window [wa, wb],
+ *   sum_k (x_left + home_k h + hl_k) cx + sum_s rho_s |slot_s ∩ [wa, wb]|,
+ * slot s spanning background cell j = s - (interfaces left of s), or the
+ * piece of it left / right of the interface that cuts it. */
+static real or_objective(const or_prob *pb, double x_left, double cx, double wa, double wb) {
+  int ns = pb->n + pb->nif, s, k = 0;
+  real h = pb->h, L = 0.0;
+  for (k = 0; k < pb->nif; ++k) L += cx * ((x_left + (double)pb->home[k] * h) + pb->hl[k]);
+  k = 0;
+  for (s = 0; s < ns; ++s) {
+    while (k < pb->nif && pb->home[k] + k + 1 < s) ++k;
+    int left_piece = k < pb->nif && pb->home[k] + k == s;
+    int right_piece = k < pb->nif && pb->home[k] + k + 1 == s;
+    int j = s - k - (right_piece ? 1 : 0);
+    real a = x_left + (double)j * h, e = x_left + (double)(j + 1) * h;
+    if (left_piece) e = a + pb->hl[k];
+    if (right_piece) a = a + pb->hl[k];
+    real lo = a > wa ? a : (real)wa, hi = e < wb ? e : (real)wb;
+    if (hi > lo) L += pb->rho[s] * (hi - lo);
+  }
+  return L;
+}
+
+/* n_steps physical steps of one problem.  Logs (optional) are rows of
+ * nif_tot (interfaces) and P (problems) entries per step; a replay reads
+ * its decisions from the same layout. */
+static void or_run_problem(const or_material *M, const or_params *Pp, or_prob *pb, int n_steps,
+                           int nif_tot, int k0, int P, int p, int *log_count, int *log_flags,
+                           int *log_zlo, int *log_cfl, const int *rp_count, const int *rp_flags,
+                           const int *rp_cfl) {
+  int ns = pb->n + pb->nif;
+  int *ph = (int *)malloc(sizeof(int) * ns);
+  int *zm = (int *)malloc(sizeof(int) * ns);
+  real *F = (real *)malloc(sizeof(real) * 2 * (ns + 1));
+  real *rn = (real *)malloc(sizeof(real) * ns);
+  real *mn = (real *)malloc(sizeof(real) * ns);
+  or_zlog *lg = (or_zlog *)malloc(sizeof(or_zlog) * (pb->nif > 0 ? pb->nif : 1));
+  int n, k;
+  for (n = 0; n < n_steps; ++n) {
+    int cs;
+    pb->rp_count = rp_count ? rp_count + (size_t)n * nif_tot + k0 : NULL;
+    pb->rp_flags = rp_count ? rp_flags + (size_t)n * nif_tot + k0 : NULL;
+    pb->rp_cfl = rp_cfl ? rp_cfl[(size_t)n * P + p] : -1;
+    or_step(M, Pp, pb, ph, F, rn, mn, zm, lg, &cs);
+    if (log_count) {
+      for (k = 0; k < pb->nif; ++k) {
+        size_t o = (size_t)n * nif_tot + k0 + k;
+        log_count[o] = lg[k].count;
+        log_flags[o] = lg[k].flags;
+        log_zlo[o] = lg[k].zlo;
+      }
+    }
+    if (log_cfl) log_cfl[(size_t)n * P + p] = cs;
+  }
+  free(ph);
+  free(zm);
+  free(F);
+  free(rn);
+  free(mn);
+  free(lg);
+}
+
+#ifndef OR_TANGENT
 /* Runs n_steps physical steps on each of P independent problems (OpenMP
  * over problems).  Slot arrays are flattened with slot_off[P+1]; interface
- * arrays with iface_off[P+1].  Logs (optional) are [n_steps][n_iface]. */
+ * arrays with iface_off[P+1].  Logs (optional) are [n_steps][n_iface]
+ * (counts, flags, zone start) and [n_steps][P] (CFL slot); rp_* (optional)
+ * replay a previous run's logs. */
 int oracle_run(const or_material *M, const or_params *Pp, int P, const int *n_cells,
                const double *h, const int *phase_first, const int *iface_off,
                const long long *slot_off, int *home, double *hl, double *pw, int *warm,
                double *rho, double *mom, double *t, int *status, long long *steps, int n_steps,
-               int *log_count, int *log_flags, int *log_zlo, int n_threads) {
+               int *log_count, int *log_flags, int *log_zlo, int *log_cfl, const int *rp_count,
+               const int *rp_flags, const int *rp_cfl, int n_threads) {
   int nif_tot = iface_off[P];
   int p;
   if (Pp->zone_half < 1 || 2 * Pp->zone_half + 1 > OR_MAXC) return -1;
@@ -947,35 +1081,108 @@ int oracle_run(const or_material *M, const or_params *Pp, int P, const int *n_ce
     pb.t = t + p;
     pb.status = status + p;
     pb.steps = steps + p;
-    int ns = pb.n + pb.nif;
-    int *ph = (int *)malloc(sizeof(int) * ns);
-    int *zm = (int *)malloc(sizeof(int) * ns);
-    double *F = (double *)malloc(sizeof(double) * 2 * (ns + 1));
-    double *rn = (double *)malloc(sizeof(double) * ns);
-    double *mn = (double *)malloc(sizeof(double) * ns);
-    or_zlog *lg = (or_zlog *)malloc(sizeof(or_zlog) * (pb.nif > 0 ? pb.nif : 1));
-    int n, k;
-    for (n = 0; n < n_steps; ++n) {
-      or_step(M, Pp, &pb, ph, F, rn, mn, zm, lg);
-      if (log_count) {
-        for (k = 0; k < pb.nif; ++k) {
-          size_t o = (size_t)n * nif_tot + k0 + k;
-          log_count[o] = lg[k].count;
-          log_flags[o] = lg[k].flags;
-          log_zlo[o] = lg[k].zlo;
-        }
-      }
-    }
-    free(ph);
-    free(zm);
-    free(F);
-    free(rn);
-    free(mn);
-    free(lg);
+    or_run_problem(M, Pp, &pb, n_steps, nif_tot, k0, P, p, log_count, log_flags, log_zlo,
+                   log_cfl, rp_count, rp_flags, rp_cfl);
   }
   return 0;
 }
 
+/* objective (see or_objective) of every problem at the given state */
+void oracle_objective(int P, const int *n_cells, const double *h, const double *x_left,
+                      const int *iface_off, const long long *slot_off, int *home, double *hl,
+                      double *rho, double cx, double wa, double wb, double *out) {
+  int p;
+  for (p = 0; p < P; ++p) {
+    or_prob pb;
+    memset(&pb, 0, sizeof(pb));
+    int k0 = iface_off[p];
+    pb.n = n_cells[p];
+    pb.nif = iface_off[p + 1] - k0;
+    pb.h = h[p];
+    pb.rho = rho + slot_off[p];
+    pb.home = home + k0;
+    pb.hl = hl + k0;
+    out[p] = or_objective(&pb, x_left[p], cx, wa, wb);
+  }
+}
+#else
+/* Tangent run: the same steps with every state value carrying a derivative
+ * along one direction (d* arrays: seeds in, derivatives out, in place), the
+ * material constants with derivative dmat (order a2v, a2l, p0, rhol0, tau).
+ * Writes each problem's objective and its directional derivative. */
+OR_API int oracle_tan_run(const double *mat, const double *dmat, const or_params *Pp, int P,
+                          const int *n_cells, const double *h, const double *x_left,
+                          const int *phase_first, const int *iface_off, const long long *slot_off,
+                          int *home, double *hl, double *dhl, double *pw, double *dpw, int *warm,
+                          double *rho, double *drho, double *mom, double *dmom, double *t,
+                          double *dtt, int *status, long long *steps, int n_steps, double cx,
+                          double wa, double wb, double *obj, double *dobj, int n_threads) {
+  or_material Md = {or_dual(mat[0], dmat[0]), or_dual(mat[1], dmat[1]), or_dual(mat[2], dmat[2]),
+                    or_dual(mat[3], dmat[3]), or_dual(mat[4], dmat[4])};
+  int nif_tot = iface_off[P];
+  int p;
+  if (Pp->zone_half < 1 || 2 * Pp->zone_half + 1 > OR_MAXC) return -1;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads > 0 ? n_threads : 1)
+  for (p = 0; p < P; ++p) {
+    or_prob pb;
+    int k0 = iface_off[p], nif = iface_off[p + 1] - k0, i;
+    long long s0 = slot_off[p];
+    int ns = (int)(slot_off[p + 1] - s0);
+    real *r = (real *)malloc(sizeof(real) * (ns + 3 * (nif > 0 ? nif : 1) + 1));
+    real *m = (real *)malloc(sizeof(real) * ns);
+    real *hlk = r + ns, *pwk = hlk + (nif > 0 ? nif : 1), *tp = pwk + 2 * (nif > 0 ? nif : 1);
+    for (i = 0; i < ns; ++i) {
+      r[i] = or_dual(rho[s0 + i], drho[s0 + i]);
+      m[i] = or_dual(mom[s0 + i], dmom[s0 + i]);
+    }
+    for (i = 0; i < nif; ++i) {
+      hlk[i] = or_dual(hl[k0 + i], dhl[k0 + i]);
+      pwk[2 * i] = or_dual(pw[2 * (k0 + i)], dpw[2 * (k0 + i)]);
+      pwk[2 * i + 1] = or_dual(pw[2 * (k0 + i) + 1], dpw[2 * (k0 + i) + 1]);
+    }
+    *tp = or_dual(t[p], dtt[p]);
+    pb.n = n_cells[p];
+    pb.nif = nif;
+    pb.h = h[p];
+    pb.phase_first = phase_first[p];
+    pb.rho = r;
+    pb.mom = m;
+    pb.home = home + k0;
+    pb.hl = hlk;
+    pb.pw = pwk;
+    pb.warm = warm + k0;
+    pb.t = tp;
+    pb.status = status + p;
+    pb.steps = steps + p;
+    or_run_problem(&Md, Pp, &pb, n_steps, nif_tot, k0, P, p, NULL, NULL, NULL, NULL, NULL, NULL,
+                   NULL);
+    real L = or_objective(&pb, x_left[p], cx, wa, wb);
+    obj[p] = L.v;
+    dobj[p] = L.d;
+    for (i = 0; i < ns; ++i) {
+      rho[s0 + i] = r[i].v;
+      drho[s0 + i] = r[i].d;
+      mom[s0 + i] = m[i].v;
+      dmom[s0 + i] = m[i].d;
+    }
+    for (i = 0; i < nif; ++i) {
+      hl[k0 + i] = hlk[i].v;
+      dhl[k0 + i] = hlk[i].d;
+      pw[2 * (k0 + i)] = pwk[2 * i].v;
+      dpw[2 * (k0 + i)] = pwk[2 * i].d;
+      pw[2 * (k0 + i) + 1] = pwk[2 * i + 1].v;
+      dpw[2 * (k0 + i) + 1] = pwk[2 * i + 1].d;
+    }
+    t[p] = tp->v;
+    dtt[p] = tp->d;
+    free(r);
+    free(m);
+  }
+  return 0;
+}
+#endif
+
+#ifndef OR_TANGENT
 /* ------------------------------------------------------------------ */
 /* fixed-point check: Algorithm 2 to a tight tolerance vs a direct     */
 /* Newton solve of the zone's implicit Euler system                    */
@@ -1068,7 +1275,7 @@ int oracle_zone_fixed_point(const or_material *M, const or_params *Pp, int n_cel
   or_zone_range(Pp, &pb, k, &zlo, &zhi, &tr);
   int sL = home[k] + k, sR = sL + 1;
   or_iface I;
-  if (!oracle_iface_solve(M, ph[sL], rho[sL], mom[sL], ph[sR], rho[sR], mom[sR], warm[k],
+  if (!or_iface_solve(M, ph[sL], rho[sL], mom[sL], ph[sR], rho[sR], mom[sR], warm[k],
                           pw[2 * k], pw[2 * k + 1], Pp->newton_maxit, Pp->newton_rtol, &I)) {
     free(ph);
     return -1;
@@ -1165,3 +1372,4 @@ done:
   for (s = 0; s < n; ++s) W_newton[s] = X[s];
   return ok ? 0 : -4;
 }
+#endif
