@@ -210,7 +210,8 @@ int imexds_autotune(imexds_ctx *ctx, int32_t steps_per_trial, int32_t *tile_cell
 /* Sizes of the batch (host, any may be NULL). */
 int imexds_get_sizes(imexds_ctx *ctx, int32_t *n_problems, int32_t *n_iface, int64_t *n_slots);
 
-/* Device-time of the most recent imexds_step / imexds_step_per_problem call
+/* Device-time of the most recent imexds_step / imexds_step_per_problem /
+ * imexds_forward_ckpt / imexds_adjoint call
  * measured with HIP events on the context's stream, and the average
  * duration of one bulk-sweep launch inside it (ms, host).  Synchronizes. */
 int imexds_last_timing(imexds_ctx *ctx, double *total_ms, double *bulk_ms_per_launch);
@@ -220,6 +221,47 @@ int imexds_last_timing(imexds_ctx *ctx, double *total_ms, double *bulk_ms_per_la
  * events and runs alone (the zones follow it on the same stream instead of
  * overlapping it).  Results are unchanged. */
 int imexds_time_bulk(imexds_ctx *ctx, int32_t on);
+
+/* Replaces the kinetic coefficient tau of the kinetic relation (Sec. 2.1,
+ * eq. "isoT:kin_rel1") for later steps (tau >= 0, finite).  Synchronizes;
+ * drops captured graphs and any recorded checkpointed forward. */
+int imexds_set_tau(imexds_ctx *ctx, double tau);
+
+/* ------------------------------------------------------------------------
+ * Adjoint (reverse-mode derivative of n steps)
+ * ------------------------------------------------------------------------
+ * The differentiated map is the discrete one the steps execute: every
+ * decision (pseudo-iteration count and stop, merges and crossings of cut
+ * pieces, HLL branches, the cell that sets each CFL time step, a clipped
+ * last step) is frozen as the forward took it.  Each interface solve is
+ * differentiated at its root by the implicit function theorem on
+ * G(p_l*, p_r*) = 0 with the Jacobian of Appendix A (eq. "jacobian:ex_sys");
+ * the pseudo iterations of Algorithm 2 are reversed one by one from stored
+ * iterates.
+ *
+ * imexds_forward_ckpt runs n_steps steps (async) from the current state like
+ * imexds_step, keeping a full copy of the state every ckpt_every steps
+ * (device memory owned by the context: about (n_steps / ckpt_every + 1) x
+ * (16 B per slot + 40 B per interface + 32 B per problem)).
+ *
+ * imexds_adjoint then returns, for a scalar objective L of the end state,
+ * the derivatives of L with respect to the state and tau at the start of
+ * that forward.  Inputs (device, [n_slots] / [n_iface]): dL/drho, dL/d(rho u)
+ * of the end state and dL/dhl of its interface offsets (gL_hl may be NULL:
+ * zero).  Outputs (device): dL/drho and dL/d(rho u) of the start state
+ * ([n_slots]), dL/dhl of the start offsets ([n_iface], may be NULL) and
+ * dL/dtau (one double).  Each segment of ckpt_every steps is run again from
+ * its checkpoint while its per-step states and zone iterates are kept
+ * (about ckpt_every x (16 B per slot + 8 B x (2 Z + 2) x (l_max + 1) per
+ * interface)), then reversed step by step.  Sums are taken in a fixed
+ * order, so results are reproducible.  Async; the end state of the forward
+ * is in place again afterwards, and the call may be repeated with other
+ * end-state derivatives.  Returns IMEXDS_ERR_NO_STATE unless the last call
+ * that changed the state was imexds_forward_ckpt. */
+int imexds_forward_ckpt(imexds_ctx *ctx, int32_t n_steps, int32_t ckpt_every);
+int imexds_adjoint(imexds_ctx *ctx, const double *gL_rho, const double *gL_mom,
+                   const double *gL_hl, double *g_rho0, double *g_mom0, double *g_hl0,
+                   double *g_tau);
 
 void imexds_destroy(imexds_ctx *ctx);
 const char *imexds_strerror(int code);

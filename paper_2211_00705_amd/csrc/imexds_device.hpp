@@ -152,6 +152,17 @@ __device__ __forceinline__ void d_bflux(const Mat& M, int ph, bool right_end, in
     d_hll(M, ph, r, mg, r, m, F0, F1);
 }
 
+// Implicit zone of an interface: the smaller cut piece (ties: left) +- Z
+// slots, clipped to the problem.  Slots are local to the problem.
+__device__ __forceinline__ void d_zone_range(int sL, double hl, double h, int Z, int ns, int& zlo,
+                                             int& zhi, bool& tiny_right) {
+  double hR = h - hl;
+  tiny_right = !(hl <= hR);
+  int c = tiny_right ? sL + 1 : sL;
+  zlo = c - Z < 0 ? 0 : c - Z;
+  zhi = c + Z > ns - 1 ? ns - 1 : c + Z;
+}
+
 // ---------------------------------------------------------------------------
 // two-phase interface Riemann problem
 // ---------------------------------------------------------------------------

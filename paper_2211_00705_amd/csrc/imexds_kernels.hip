@@ -34,17 +34,6 @@ __device__ __forceinline__ unsigned long long d_speed_bits(const Mat& M, int ph,
   return d_bits(fabs(m / r) + d_a(M, ph));
 }
 
-// Implicit zone of an interface: the smaller cut piece (ties: left) +- Z
-// slots, clipped to the problem.  Slots are local to the problem.
-__device__ __forceinline__ void d_zone_range(int sL, double hl, double h, int Z, int ns, int& zlo,
-                                             int& zhi, bool& tiny_right) {
-  double hR = h - hl;
-  tiny_right = !(hl <= hR);
-  int c = tiny_right ? sL + 1 : sL;
-  zlo = c - Z < 0 ? 0 : c - Z;
-  zhi = c + Z > ns - 1 ? ns - 1 : c + Z;
-}
-
 __device__ __forceinline__ unsigned long long d_wave_max_u64(unsigned long long v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -270,6 +259,7 @@ __global__ __launch_bounds__(64) void k_zone(StepArgs A, int if_begin, int if_en
           A.log_flags[o] = dt == 0.0 ? FL_INACTIVE : FL_FAIL;
           A.log_zlo[o] = -1;
         }
+        if (A.tape) A.tape[k * A.tape_stride + TH_FLAGS] = dt == 0.0 ? FL_INACTIVE : FL_FAIL;
         continue;
       }
       h = A.h[p];
@@ -346,6 +336,12 @@ __global__ __launch_bounds__(64) void k_zone(StepArgs A, int if_begin, int if_en
         Ipl = o.pl;
         Ipr = o.pr;
         wp = o.w;
+        if (A.tape) {
+          double* T = A.tape + k * A.tape_stride;
+          T[TH_IPL] = Ipl;
+          T[TH_IPR] = Ipr;
+          T[TH_WP] = wp;
+        }
         double ht = tr ? h - hl : hl;
         double rate = tr ? -wp : wp;
         double hfl = P.alpha_floor * h;
@@ -359,6 +355,16 @@ __global__ __launch_bounds__(64) void k_zone(StepArgs A, int if_begin, int if_en
       pw0 = o.pl;
       pw1 = o.pr;
       const double w = o.w;
+      if (A.tape) {  // W^l and its interface root
+        double* e = A.tape + k * A.tape_stride + TAPE_HDR + (long long)l * (2 * MC + 2);
+#pragma unroll
+        for (int i = 0; i < MC; ++i) {
+          e[i] = W0[i];
+          e[MC + i] = W1[i];
+        }
+        e[2 * MC] = pw0;
+        e[2 * MC + 1] = pw1;
+      }
       // fluxes of the iterate: right face of each active position
       double FRa0[MC], FRa1[MC];
 #pragma unroll
@@ -618,6 +624,13 @@ __global__ __launch_bounds__(64) void k_zone(StepArgs A, int if_begin, int if_en
       A.log_count[o2] = count;
       A.log_flags[o2] = flags;
       A.log_zlo[o2] = zlo;
+    }
+    if (A.tape) {
+      double* T = A.tape + k * A.tape_stride;
+      T[TH_COUNT] = count;
+      T[TH_FLAGS] = flags;
+      T[TH_ZLO] = zlo;
+      T[TH_WSTAR] = wstar;
     }
     stage = S_FETCH;
   }

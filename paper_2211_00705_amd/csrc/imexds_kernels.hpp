@@ -54,6 +54,41 @@ struct StepArgs {
   unsigned long long* st_lmax;
   int* zone_ctr;  // zones handed out so far in this step (reset by k_finalize)
   int zones_per_group;
+  // zone tape of this step (nullptr: none).  Per interface, tape_stride
+  // doubles: a header of TAPE_HDR values, then for l = 0..count the iterate
+  // W^l of the zone (MC densities, MC momenta, MC = 2 zone_half + 1) and the
+  // interface root (p_l*, p_r*) at W^l; entry `count` is the accepted iterate
+  // of Part 2.
+  double* tape;
+  long long tape_stride;
+};
+
+// tape header: predicting root (2), predicted speed, count, log flags, zone
+// start, accepted boundary speed w*
+constexpr int TAPE_HDR = 8;
+constexpr int TH_IPL = 0, TH_IPR = 1, TH_WP = 2, TH_COUNT = 3, TH_FLAGS = 4, TH_ZLO = 5,
+              TH_WSTAR = 6;
+inline long long tape_entry(int zone_half) { return 2 * (2 * zone_half + 1) + 2; }
+inline long long tape_stride(int zone_half, int lmax) {
+  return TAPE_HDR + (long long)(lmax + 1) * tape_entry(zone_half);
+}
+
+// Reverse sweep of one step (adjoint): arrays of adjoints ("g" = dL/d of).
+struct AdjArgs {
+  const double* gr1;  // [S] adjoint of rho^{n+1}
+  const double* gm1;  // [S] adjoint of (rho u)^{n+1}
+  double* gr0;        // [S] out: adjoint of rho^n (zone cells: partial from the zone pass)
+  double* gm0;
+  double* hl_bar;     // [NIF] in: adjoint of hl^{n+1}; out: of hl^n
+  double* tau_bar;    // [NIF] accumulated adjoint of tau per zone
+  double* zadj;       // [NIF * 5] zone pass -> bulk pass: adjoints of F_left, F_right, dt
+  double* tile_gdt;   // [tiles] bulk cells' part of the adjoint of dt
+  unsigned long long* tile_smax;  // [tiles] max |u| + a (bit pattern) over the tile
+  int* tile_sidx;     // [tiles] first slot attaining it
+  const int* tile_off;  // [P+1] tiles of each problem
+  const long long* steps0;  // [P] step counters before and after the step
+  const long long* steps1;  //     (t advanced iff they differ)
+  double* t_bar;        // [P] adjoint of t
 };
 
 // Bulk tiles: tile_class in {256, 512, 1024, 2048} gives R = tile_class / 256
@@ -67,5 +102,12 @@ hipError_t launch_cfl(const StepArgs& A, int tile_begin, int n_tiles, hipStream_
 hipError_t launch_zone(const StepArgs& A, int if_begin, int if_end, int groups, hipStream_t s);
 hipError_t launch_finalize(const StepArgs& A, int p_begin, int p_end, int init, int bump_row,
                            hipStream_t s);
+
+// adjoint of one step: zone pass, then bulk pass, then per-problem pass
+hipError_t launch_zone_adj(const StepArgs& A, const AdjArgs& B, hipStream_t s);
+hipError_t launch_bulk_adj(const StepArgs& A, const AdjArgs& B, int tile_class, int n_tiles,
+                           hipStream_t s);
+hipError_t launch_finalize_adj(const StepArgs& A, const AdjArgs& B, int P, hipStream_t s);
+hipError_t launch_sum(const double* x, int n, double* out, hipStream_t s);
 
 }  // namespace imexds

@@ -88,6 +88,28 @@ struct imexds_ctx {
   double last_total_ms = 0.0, last_bulk_ms = 0.0;
   bool timed = false;
   std::vector<void*> allocs;
+  // adjoint: checkpoints of the last checkpointed forward, one segment's tape
+  std::vector<Snapshot> ck;
+  Snapshot ck_end;
+  bool ck_end_valid = false;
+  int adj_steps = 0, adj_every = 0;
+  bool adj_ready = false;
+  int tape_steps = 0;      // segment length the tape buffers hold
+  long long tape_stride = 0;
+  double* tU = nullptr;    // [C][2][S] rho^n, (rho u)^n
+  int* tHome = nullptr;    // [C][NIF]
+  double* tHl = nullptr;   // [C][NIF]
+  double* tDt = nullptr;   // [C][P]
+  int* tClip = nullptr;    // [C][P]
+  long long* tSteps = nullptr;  // [C+1][P]
+  double* tZone = nullptr;      // [C][NIF][stride]
+  double *d_gr[2] = {nullptr, nullptr}, *d_gm[2] = {nullptr, nullptr};
+  double *d_hlbar = nullptr, *d_taubar = nullptr, *d_zadj = nullptr, *d_tbar = nullptr;
+  double* d_tgdt = nullptr;
+  unsigned long long* d_tsmax = nullptr;
+  int* d_tsidx = nullptr;
+  int adj_tiles = 0;
+  int* d_tile_off = nullptr;
 };
 
 namespace {
@@ -205,11 +227,16 @@ int build_tiles(imexds_ctx* c, int tile_cells) {
     CK(hipMemcpy(nst, ts.data(), sizeof(int) * n, hipMemcpyHostToDevice));
     CK(hipMemcpy(nl, tl.data(), sizeof(int) * n, hipMemcpyHostToDevice));
   }
+  int* toff = nullptr;
+  CK(hipMalloc((void**)&toff, sizeof(int) * (c->P + 1)));
+  CK(hipMemcpy(toff, c->h_tile_off.data(), sizeof(int) * (c->P + 1), hipMemcpyHostToDevice));
   if (c->d_tile_prob) {
     (void)hipFree(c->d_tile_prob);
     (void)hipFree(c->d_tile_start);
     (void)hipFree(c->d_tile_len);
   }
+  if (c->d_tile_off) (void)hipFree(c->d_tile_off);
+  c->d_tile_off = toff;
   c->d_tile_prob = np;
   c->d_tile_start = nst;
   c->d_tile_len = nl;
@@ -335,10 +362,12 @@ int snap_take(imexds_ctx* c, Snapshot& s) {
   hipStream_t m = c->ms;
   CK(hipMemcpyAsync(s.rho, c->d_rho[a], S * 8, hipMemcpyDeviceToDevice, m));
   CK(hipMemcpyAsync(s.mom, c->d_mom[a], S * 8, hipMemcpyDeviceToDevice, m));
-  CK(hipMemcpyAsync(s.home, c->d_home[a], N * 4, hipMemcpyDeviceToDevice, m));
-  CK(hipMemcpyAsync(s.warm, c->d_warm[a], N * 4, hipMemcpyDeviceToDevice, m));
-  CK(hipMemcpyAsync(s.hl, c->d_hl[a], N * 8, hipMemcpyDeviceToDevice, m));
-  CK(hipMemcpyAsync(s.pw, c->d_pw[a], 2 * N * 8, hipMemcpyDeviceToDevice, m));
+  if (c->NIF > 0) {
+    CK(hipMemcpyAsync(s.home, c->d_home[a], N * 4, hipMemcpyDeviceToDevice, m));
+    CK(hipMemcpyAsync(s.warm, c->d_warm[a], N * 4, hipMemcpyDeviceToDevice, m));
+    CK(hipMemcpyAsync(s.hl, c->d_hl[a], N * 8, hipMemcpyDeviceToDevice, m));
+    CK(hipMemcpyAsync(s.pw, c->d_pw[a], 2 * N * 8, hipMemcpyDeviceToDevice, m));
+  }
   CK(hipMemcpyAsync(s.dt, c->d_dt, P * 8, hipMemcpyDeviceToDevice, m));
   CK(hipMemcpyAsync(s.t, c->d_t, P * 8, hipMemcpyDeviceToDevice, m));
   CK(hipMemcpyAsync(s.status, c->d_status, P * 4, hipMemcpyDeviceToDevice, m));
@@ -356,10 +385,12 @@ int snap_restore(imexds_ctx* c, Snapshot& s) {
   hipStream_t m = c->ms;
   CK(hipMemcpyAsync(c->d_rho[a], s.rho, S * 8, hipMemcpyDeviceToDevice, m));
   CK(hipMemcpyAsync(c->d_mom[a], s.mom, S * 8, hipMemcpyDeviceToDevice, m));
-  CK(hipMemcpyAsync(c->d_home[a], s.home, N * 4, hipMemcpyDeviceToDevice, m));
-  CK(hipMemcpyAsync(c->d_warm[a], s.warm, N * 4, hipMemcpyDeviceToDevice, m));
-  CK(hipMemcpyAsync(c->d_hl[a], s.hl, N * 8, hipMemcpyDeviceToDevice, m));
-  CK(hipMemcpyAsync(c->d_pw[a], s.pw, 2 * N * 8, hipMemcpyDeviceToDevice, m));
+  if (c->NIF > 0) {
+    CK(hipMemcpyAsync(c->d_home[a], s.home, N * 4, hipMemcpyDeviceToDevice, m));
+    CK(hipMemcpyAsync(c->d_warm[a], s.warm, N * 4, hipMemcpyDeviceToDevice, m));
+    CK(hipMemcpyAsync(c->d_hl[a], s.hl, N * 8, hipMemcpyDeviceToDevice, m));
+    CK(hipMemcpyAsync(c->d_pw[a], s.pw, 2 * N * 8, hipMemcpyDeviceToDevice, m));
+  }
   CK(hipMemcpyAsync(c->d_dt, s.dt, P * 8, hipMemcpyDeviceToDevice, m));
   CK(hipMemcpyAsync(c->d_t, s.t, P * 8, hipMemcpyDeviceToDevice, m));
   CK(hipMemcpyAsync(c->d_status, s.status, P * 4, hipMemcpyDeviceToDevice, m));
@@ -409,6 +440,169 @@ int steps_impl(imexds_ctx* c, int n) {
   return 0;
 }
 
+void free_tape(imexds_ctx* c) {
+  void* ps[] = {c->tU, c->tHome, c->tHl, c->tDt, c->tClip, c->tSteps, c->tZone};
+  for (void* p : ps)
+    if (p) (void)hipFree(p);
+  c->tU = nullptr;
+  c->tHome = nullptr;
+  c->tHl = nullptr;
+  c->tDt = nullptr;
+  c->tClip = nullptr;
+  c->tSteps = nullptr;
+  c->tZone = nullptr;
+  c->tape_steps = 0;
+}
+
+void free_checkpoints(imexds_ctx* c) {
+  for (Snapshot& s : c->ck) snap_free(s);
+  c->ck.clear();
+  if (c->ck_end_valid) snap_free(c->ck_end);
+  c->ck_end_valid = false;
+  c->adj_ready = false;
+}
+
+void free_adjoint(imexds_ctx* c) {
+  free_checkpoints(c);
+  free_tape(c);
+  void* ps[] = {c->d_gr[0], c->d_gr[1], c->d_gm[0], c->d_gm[1], c->d_hlbar, c->d_taubar,
+                c->d_zadj, c->d_tbar, c->d_tgdt, c->d_tsmax, c->d_tsidx};
+  for (void* p : ps)
+    if (p) (void)hipFree(p);
+  c->d_gr[0] = c->d_gr[1] = c->d_gm[0] = c->d_gm[1] = nullptr;
+  c->d_hlbar = c->d_taubar = c->d_zadj = c->d_tbar = c->d_tgdt = nullptr;
+  c->d_tsmax = nullptr;
+  c->d_tsidx = nullptr;
+  c->adj_tiles = 0;
+}
+
+template <class T>
+int halloc(T** p, size_t n) {
+  *p = nullptr;
+  if (hipMalloc((void**)p, (n ? n : 1) * sizeof(T)) != hipSuccess) {
+    *p = nullptr;
+    snprintf(g_err, sizeof(g_err), "hipMalloc of %zu bytes failed (adjoint buffers)",
+             (n ? n : 1) * sizeof(T));
+    return IMEXDS_ERR_OOM;
+  }
+  return 0;
+}
+
+#define HA(ptr, n)                          \
+  do {                                      \
+    int r_ = halloc(&(ptr), (size_t)(n));   \
+    if (r_) return r_;                      \
+  } while (0)
+
+// Tape of one segment of C steps and the adjoint work arrays.
+int ensure_adjoint_buffers(imexds_ctx* c, int C) {
+  const size_t S = (size_t)c->S, N = (size_t)c->NIF, P = (size_t)c->P;
+  const long long stride = imexds::tape_stride(c->par.zone_half, c->par.lmax);
+  if (c->tape_steps != C || c->tape_stride != stride) {
+    free_tape(c);
+    HA(c->tU, (size_t)C * 2 * S);
+    HA(c->tHome, (size_t)C * N);
+    HA(c->tHl, (size_t)C * N);
+    HA(c->tDt, (size_t)C * P);
+    HA(c->tClip, (size_t)C * P);
+    HA(c->tSteps, (size_t)(C + 1) * P);
+    HA(c->tZone, (size_t)C * N * (size_t)stride);
+    c->tape_steps = C;
+    c->tape_stride = stride;
+  }
+  if (!c->d_gr[0]) {
+    for (int a = 0; a < 2; ++a) {
+      HA(c->d_gr[a], S);
+      HA(c->d_gm[a], S);
+    }
+    HA(c->d_hlbar, N);
+    HA(c->d_taubar, N);
+    HA(c->d_zadj, 5 * N);
+    HA(c->d_tbar, P);
+  }
+  if (c->adj_tiles != c->n_tiles) {
+    if (c->d_tgdt) (void)hipFree(c->d_tgdt);
+    if (c->d_tsmax) (void)hipFree(c->d_tsmax);
+    if (c->d_tsidx) (void)hipFree(c->d_tsidx);
+    c->d_tgdt = nullptr;
+    c->d_tsmax = nullptr;
+    c->d_tsidx = nullptr;
+    c->adj_tiles = 0;
+    HA(c->d_tgdt, (size_t)c->n_tiles);
+    HA(c->d_tsmax, (size_t)c->n_tiles);
+    HA(c->d_tsidx, (size_t)c->n_tiles);
+    c->adj_tiles = c->n_tiles;
+  }
+  return 0;
+}
+
+// Re-runs `len` steps from the restored checkpoint, keeping for each step
+// its input state, records, dt and the zone tape.
+int record_segment(imexds_ctx* c, int len) {
+  const size_t S = (size_t)c->S, N = (size_t)c->NIF, P = (size_t)c->P;
+  hipStream_t m = c->ms;
+  for (int j = 0; j < len; ++j) {
+    const int a = c->parity;
+    double* u = c->tU + (size_t)j * 2 * S;
+    if (S) {
+      CK(hipMemcpyAsync(u, c->d_rho[a], S * 8, hipMemcpyDeviceToDevice, m));
+      CK(hipMemcpyAsync(u + S, c->d_mom[a], S * 8, hipMemcpyDeviceToDevice, m));
+    }
+    if (N) {
+      CK(hipMemcpyAsync(c->tHome + j * N, c->d_home[a], N * 4, hipMemcpyDeviceToDevice, m));
+      CK(hipMemcpyAsync(c->tHl + j * N, c->d_hl[a], N * 8, hipMemcpyDeviceToDevice, m));
+    }
+    CK(hipMemcpyAsync(c->tDt + j * P, c->d_dt, P * 8, hipMemcpyDeviceToDevice, m));
+    CK(hipMemcpyAsync(c->tClip + j * P, c->d_clipped, P * 4, hipMemcpyDeviceToDevice, m));
+    CK(hipMemcpyAsync(c->tSteps + j * P, c->d_steps, P * 8, hipMemcpyDeviceToDevice, m));
+    StepArgs A = make_args(c, a, false);
+    A.log_count = A.log_flags = A.log_zlo = A.log_row = nullptr;
+    A.log_max = 0;
+    A.st_pseudo = A.st_merges = A.st_lmax = nullptr;
+    A.tape = c->tZone + (size_t)j * N * (size_t)c->tape_stride;
+    A.tape_stride = c->tape_stride;
+    if (N) CK(imexds::launch_zone(A, 0, c->NIF, c->zone_groups, m));
+    CK(imexds::launch_bulk(A, c->tile_cells, 0, c->n_tiles, m));
+    CK(imexds::launch_finalize(A, 0, c->P, 0, 0, m));
+    c->parity ^= 1;
+  }
+  CK(hipMemcpyAsync(c->tSteps + (size_t)len * P, c->d_steps, P * 8, hipMemcpyDeviceToDevice, m));
+  return 0;
+}
+
+// Reverse of step j of the recorded segment: adjoint buffers cur -> cur ^ 1.
+int reverse_step(imexds_ctx* c, int j, int cur) {
+  const size_t S = (size_t)c->S, N = (size_t)c->NIF, P = (size_t)c->P;
+  StepArgs A = make_args(c, 0, false);
+  A.rho0 = c->tU + (size_t)j * 2 * S;
+  A.mom0 = A.rho0 + S;
+  A.rec_home0 = c->tHome + (size_t)j * N;
+  A.rec_hl0 = c->tHl + (size_t)j * N;
+  A.dt = c->tDt + (size_t)j * P;
+  A.clipped = c->tClip + (size_t)j * P;
+  A.tape = c->tZone + (size_t)j * N * (size_t)c->tape_stride;
+  A.tape_stride = c->tape_stride;
+  imexds::AdjArgs B;
+  B.gr1 = c->d_gr[cur];
+  B.gm1 = c->d_gm[cur];
+  B.gr0 = c->d_gr[cur ^ 1];
+  B.gm0 = c->d_gm[cur ^ 1];
+  B.hl_bar = c->d_hlbar;
+  B.tau_bar = c->d_taubar;
+  B.zadj = c->d_zadj;
+  B.tile_gdt = c->d_tgdt;
+  B.tile_smax = c->d_tsmax;
+  B.tile_sidx = c->d_tsidx;
+  B.tile_off = c->d_tile_off;
+  B.steps0 = c->tSteps + (size_t)j * P;
+  B.steps1 = c->tSteps + (size_t)(j + 1) * P;
+  B.t_bar = c->d_tbar;
+  if (N) CK(imexds::launch_zone_adj(A, B, c->ms));
+  CK(imexds::launch_bulk_adj(A, B, c->tile_cells, c->n_tiles, c->ms));
+  CK(imexds::launch_finalize_adj(A, B, c->P, c->ms));
+  return 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -435,6 +629,8 @@ void imexds_destroy(imexds_ctx* c) {
   if (c->d_tile_prob) (void)hipFree(c->d_tile_prob);
   if (c->d_tile_start) (void)hipFree(c->d_tile_start);
   if (c->d_tile_len) (void)hipFree(c->d_tile_len);
+  if (c->d_tile_off) (void)hipFree(c->d_tile_off);
+  free_adjoint(c);
   if (c->d_log_count) (void)hipFree(c->d_log_count);
   if (c->d_log_flags) (void)hipFree(c->d_log_flags);
   if (c->d_log_zlo) (void)hipFree(c->d_log_zlo);
@@ -637,6 +833,7 @@ int imexds_set_state(imexds_ctx* c, const double* rho, const double* mom) {
     if (r) return r;
   }
   c->has_state = true;
+  free_checkpoints(c);
   return end_call(c);
 }
 
@@ -645,6 +842,7 @@ int imexds_step(imexds_ctx* c, int32_t n_steps) {
   if (!c->has_state) return IMEXDS_ERR_NO_STATE;
   int r = begin_call(c);
   if (r) return r;
+  c->adj_ready = false;
   c->bulk_launches = 0;
   CK(hipEventRecord(c->ev_t0, c->ms));
   if (c->P > 0 && (r = steps_impl(c, n_steps))) return r;
@@ -658,6 +856,7 @@ int imexds_step_per_problem(imexds_ctx* c, int32_t n_steps) {
   if (!c->has_state) return IMEXDS_ERR_NO_STATE;
   int r = begin_call(c);
   if (r) return r;
+  c->adj_ready = false;
   c->bulk_launches = 0;
   CK(hipEventRecord(c->ev_t0, c->ms));
   for (int n = 0; n < n_steps; ++n) {
@@ -681,6 +880,7 @@ int imexds_run(imexds_ctx* c, int32_t max_steps, int32_t check_every, int32_t* s
   if (!c->has_state) return IMEXDS_ERR_NO_STATE;
   int r = begin_call(c);
   if (r) return r;
+  c->adj_ready = false;
   int done = 0;
   std::vector<double> dt(c->P);
   CK(hipEventRecord(c->ev_t0, c->ms));
@@ -841,6 +1041,7 @@ int imexds_autotune(imexds_ctx* c, int32_t steps_per_trial, int32_t* tile_cells,
   if (!c->has_state) return IMEXDS_ERR_NO_STATE;
   CK(hipSetDevice(c->device));
   CK(hipStreamSynchronize(c->user));
+  c->adj_ready = false;
   Snapshot s;
   int r = snap_take(c, s);
   if (r) {
@@ -942,6 +1143,95 @@ int imexds_time_bulk(imexds_ctx* c, int32_t on) {
   if (!c) return IMEXDS_ERR_INVALID_ARG;
   c->time_bulk = on != 0;
   return 0;
+}
+
+int imexds_set_tau(imexds_ctx* c, double tau) {
+  if (!c || !(tau >= 0.0) || !std::isfinite(tau)) return IMEXDS_ERR_INVALID_ARG;
+  CK(hipSetDevice(c->device));
+  CK(hipStreamSynchronize(c->ms));
+  drop_graph(c);  // the captured launches hold the material by value
+  c->mat.tau = tau;
+  c->adj_ready = false;
+  return 0;
+}
+
+int imexds_forward_ckpt(imexds_ctx* c, int32_t n_steps, int32_t ckpt_every) {
+  if (!c || n_steps < 0 || ckpt_every < 1) return IMEXDS_ERR_INVALID_ARG;
+  if (!c->has_state) return IMEXDS_ERR_NO_STATE;
+  int r = begin_call(c);
+  if (r) return r;
+  CK(hipStreamSynchronize(c->ms));
+  free_checkpoints(c);
+  c->bulk_launches = 0;
+  CK(hipEventRecord(c->ev_t0, c->ms));
+  const int nck = (n_steps + ckpt_every - 1) / ckpt_every;
+  c->ck.resize(nck);
+  for (int j = 0; j < nck; ++j) {
+    if ((r = snap_take(c, c->ck[j]))) return r;
+    const int len = std::min(ckpt_every, n_steps - j * ckpt_every);
+    if (c->P > 0 && (r = steps_impl(c, len))) return r;
+  }
+  if ((r = snap_take(c, c->ck_end))) return r;
+  c->ck_end_valid = true;
+  CK(hipEventRecord(c->ev_t1, c->ms));
+  c->timed = true;
+  c->adj_steps = n_steps;
+  c->adj_every = ckpt_every;
+  c->adj_ready = true;
+  return end_call(c);
+}
+
+int imexds_adjoint(imexds_ctx* c, const double* gL_rho, const double* gL_mom,
+                   const double* gL_hl, double* g_rho0, double* g_mom0, double* g_hl0,
+                   double* g_tau) {
+  if (!c || (c->S > 0 && (!gL_rho || !gL_mom || !g_rho0 || !g_mom0)) || !g_tau)
+    return IMEXDS_ERR_INVALID_ARG;
+  if (!c->adj_ready) {
+    snprintf(g_err, sizeof(g_err), "imexds_adjoint needs a preceding imexds_forward_ckpt");
+    return IMEXDS_ERR_NO_STATE;
+  }
+  int r = begin_call(c);
+  if (r) return r;
+  const int n = c->adj_steps, C = c->adj_every;
+  if ((r = ensure_adjoint_buffers(c, std::max(1, std::min(C, n))))) return r;
+  const size_t S = (size_t)c->S, N = (size_t)c->NIF, P = (size_t)c->P;
+  hipStream_t m = c->ms;
+  CK(hipEventRecord(c->ev_t0, m));
+  if (S) {
+    CK(hipMemcpyAsync(c->d_gr[0], gL_rho, S * 8, hipMemcpyDeviceToDevice, m));
+    CK(hipMemcpyAsync(c->d_gm[0], gL_mom, S * 8, hipMemcpyDeviceToDevice, m));
+  }
+  if (N) {
+    if (gL_hl)
+      CK(hipMemcpyAsync(c->d_hlbar, gL_hl, N * 8, hipMemcpyDeviceToDevice, m));
+    else
+      CK(hipMemsetAsync(c->d_hlbar, 0, N * 8, m));
+    CK(hipMemsetAsync(c->d_taubar, 0, N * 8, m));
+  }
+  if (P) CK(hipMemsetAsync(c->d_tbar, 0, P * 8, m));
+  int cur = 0;
+  for (int seg = (int)c->ck.size() - 1; seg >= 0; --seg) {
+    const int len = std::min(C, n - seg * C);
+    if ((r = snap_restore(c, c->ck[seg]))) return r;
+    if ((r = record_segment(c, len))) return r;
+    for (int j = len - 1; j >= 0; --j) {
+      if ((r = reverse_step(c, j, cur))) return r;
+      cur ^= 1;
+    }
+  }
+  if (S) {
+    CK(hipMemcpyAsync(g_rho0, c->d_gr[cur], S * 8, hipMemcpyDeviceToDevice, m));
+    CK(hipMemcpyAsync(g_mom0, c->d_gm[cur], S * 8, hipMemcpyDeviceToDevice, m));
+  }
+  if (N && g_hl0) CK(hipMemcpyAsync(g_hl0, c->d_hlbar, N * 8, hipMemcpyDeviceToDevice, m));
+  if (N)
+    CK(imexds::launch_sum(c->d_taubar, c->NIF, g_tau, m));
+  else
+    CK(hipMemsetAsync(g_tau, 0, 8, m));
+  CK(hipEventRecord(c->ev_t1, m));
+  c->timed = true;
+  if ((r = snap_restore(c, c->ck_end))) return r;  // leave the end state in place
+  return end_call(c);
 }
 
 }  // extern "C"

@@ -80,6 +80,9 @@ _autotune = _sig("imexds_autotune", c_vp, c_i32, P_i32, P_i32, P_i32, P_dbl)
 _get_sizes = _sig("imexds_get_sizes", c_vp, P_i32, P_i32, P_i64)
 _last_timing = _sig("imexds_last_timing", c_vp, P_dbl, P_dbl)
 _time_bulk = _sig("imexds_time_bulk", c_vp, c_i32)
+_set_tau = _sig("imexds_set_tau", c_vp, c_dbl)
+_forward_ckpt = _sig("imexds_forward_ckpt", c_vp, c_i32, c_i32)
+_adjoint = _sig("imexds_adjoint", c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp)
 _L.imexds_destroy.restype = None
 _L.imexds_destroy.argtypes = [c_vp]
 _L.imexds_strerror.restype = ctypes.c_char_p
@@ -89,7 +92,8 @@ EXPORTED = ["imexds_create", "imexds_set_state", "imexds_step", "imexds_run",
             "imexds_step_per_problem", "imexds_get_state", "imexds_get_interfaces",
             "imexds_get_problems", "imexds_enable_log", "imexds_get_log", "imexds_get_stats",
             "imexds_set_launch", "imexds_autotune", "imexds_get_sizes", "imexds_last_timing",
-            "imexds_time_bulk", "imexds_destroy", "imexds_strerror"]
+            "imexds_time_bulk", "imexds_set_tau", "imexds_forward_ckpt", "imexds_adjoint",
+            "imexds_destroy", "imexds_strerror"]
 
 
 class IMEXDSError(RuntimeError):
@@ -242,6 +246,21 @@ def imexds_time_bulk(ctx, on):
     _check(_time_bulk(c_vp(ctx), int(bool(on))), "imexds_time_bulk")
 
 
+def imexds_set_tau(ctx, tau):
+    _check(_set_tau(c_vp(ctx), float(tau)), "imexds_set_tau")
+
+
+def imexds_forward_ckpt(ctx, n_steps, ckpt_every):
+    _check(_forward_ckpt(c_vp(ctx), int(n_steps), int(ckpt_every)), "imexds_forward_ckpt")
+
+
+def imexds_adjoint(ctx, gL_rho, gL_mom, gL_hl, g_rho0, g_mom0, g_hl0, g_tau):
+    """All arguments are FP64 cuda tensors (gL_hl and g_hl0 may be None)."""
+    opt = (lambda x: _dev_ptr(x) if x is not None else c_vp(None))
+    _check(_adjoint(c_vp(ctx), _dev_ptr(gL_rho), _dev_ptr(gL_mom), opt(gL_hl), _dev_ptr(g_rho0),
+                    _dev_ptr(g_mom0), opt(g_hl0), _dev_ptr(g_tau)), "imexds_adjoint")
+
+
 def imexds_destroy(ctx):
     if ctx:
         _L.imexds_destroy(c_vp(ctx))
@@ -314,6 +333,28 @@ class IMEXDS:
 
     def time_bulk(self, on=True):
         imexds_time_bulk(self.ctx, on)
+
+    def set_tau(self, tau):
+        imexds_set_tau(self.ctx, tau)
+
+    def forward_ckpt(self, n_steps, ckpt_every):
+        imexds_forward_ckpt(self.ctx, n_steps, ckpt_every)
+
+    def adjoint(self, g_rho, g_mom, g_hl=None):
+        """dL/d(rho0, mom0, hl0, tau) of the last forward_ckpt, given dL/d of
+        its end state (cuda FP64 tensors)."""
+        torch = self._torch
+        g_rho0 = torch.empty(self.n_slots, dtype=torch.float64, device="cuda")
+        g_mom0 = torch.empty_like(g_rho0)
+        n = max(self.batch.n_iface, 1)
+        g_hl0 = torch.empty(n, dtype=torch.float64, device="cuda")
+        g_tau = torch.empty(1, dtype=torch.float64, device="cuda")
+        if g_hl is not None and self.batch.n_iface == 0:
+            g_hl = None
+        imexds_adjoint(self.ctx, g_rho.contiguous(), g_mom.contiguous(),
+                       None if g_hl is None else g_hl.contiguous(), g_rho0, g_mom0,
+                       g_hl0 if self.batch.n_iface else None, g_tau)
+        return g_rho0, g_mom0, g_hl0[:self.batch.n_iface], g_tau
 
     def close(self):
         if self.ctx:

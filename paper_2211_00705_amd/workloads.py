@@ -286,6 +286,43 @@ def random_batch_params():
     return Params(cfl=0.9, zone_half=2, tol_mode=0, lmax=100)
 
 
+def adjoint_batch(seed=20261202, n_problems=1024, nmin=256, nmax=16384):
+    """Batch for the adjoint: per problem the large single problem's set-up
+    (piecewise-smooth states from random Fourier modes, one interface in cell
+    N/2 with cut fraction alpha ~ logU[1e-6, 1e-1]) at the uneven sizes of the
+    random batch, N_p log-uniform integer in [nmin, nmax]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    P = n_problems
+    N = np.floor(np.exp(rng.uniform(math.log(nmin), math.log(nmax + 1), size=P))).astype(np.int64)
+    N = np.clip(N, nmin, nmax)
+    homes, hls, states, hs = [], [], [], []
+    for p in range(P):
+        n = int(N[p])
+        h = 1.0 / n
+        a = float(loguniform(rng, 1e-6, 1e-1))
+        seeds = rng.integers(0, 2**62, size=4)
+
+        def st(x, q, seeds=seeds):
+            lo, hi = (900.0, 1000.0) if q == LIQ else (0.01, 0.1)
+            s_ = _fourier(np.random.Generator(np.random.PCG64(int(seeds[2 * q]))), x)
+            v = _fourier(np.random.Generator(np.random.PCG64(int(seeds[2 * q + 1]))), x)
+            xs = np.linspace(0.0, 1.0, 1025)
+            vs = _fourier(np.random.Generator(np.random.PCG64(int(seeds[2 * q + 1]))), xs)
+            rms = float(np.sqrt(np.mean(vs * vs)))
+            return lo + (hi - lo) * (0.5 + 0.5 * s_), 0.5 * v / rms
+
+        homes.append([n // 2])
+        hls.append([a * h])
+        hs.append(h)
+        states.append(st)
+    return _assemble(N, hs, np.zeros(P), np.zeros(P, dtype=np.int32), homes, hls, states,
+                     name=f"adjoint_batch_P{P}_seed{seed}")
+
+
+def adjoint_batch_params():
+    return Params(cfl=0.9, zone_half=2, tol_mode=0, lmax=100)
+
+
 def bubble_batch(seed=20261202, n_problems=1024, n=4096, gap=16, alpha_lo=1e-6, alpha_hi=1e-2):
     """Liquid | vapour bubble | liquid problems: two interfaces around `gap`
     full vapour cells in the middle of the domain; each interface's tiny piece

@@ -1,0 +1,229 @@
+"""GPU adjoint (reverse mode, checkpointed) against the oracle's tangent.
+
+For an objective L of the end state (sum of interface positions plus the
+mass in [0.4, 0.6]), the library returns dL/d(rho0, rho u 0, hl0, tau).  The
+oracle's tangent build gives the exact directional derivative of the same
+discrete map (same decisions), so for any direction d the dot product of the
+GPU gradient with d must equal the tangent, problem by problem.  The only
+differences allowed are rounding: the GPU reverses each interface solve at
+its root by the implicit function theorem where the tangent differentiates
+the Newton iterations (which agree once Newton has converged to 1e-14), and
+sums in another order.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2211_00705_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+THREADS = max(1, min(16, os.cpu_count() or 1))
+
+# |<g, d> - tangent| <= RTOL * (|tangent| + sum_i |g_i d_i|): rounding of the
+# reverse sweep relative to the size of the terms it sums
+RTOL = 1e-8
+
+
+def _gpu_gradient(b, P, M, n, C, cx=1.0, wa=0.4, wb=0.6, launch=None):
+    import torch
+    from paper_2211_00705_amd.imexds import IMEXDS
+    from paper_2211_00705_amd.autograd import window_objective
+    s = IMEXDS(b, M, P)
+    try:
+        if launch is not None:
+            s.set_launch(*launch)
+        s.set_state()
+        s.forward_ckpt(n, C)
+        rho, mom = s.state()
+        home, hl, _ = s.interfaces()
+        hl_t = torch.tensor(hl, dtype=torch.float64, device="cuda", requires_grad=True)
+        rho_t = rho.clone().requires_grad_(True)
+        L = window_objective(b, home, hl_t, rho_t, cx, wa, wb)
+        L.sum().backward()
+        g_hl = hl_t.grad if b.n_iface else None
+        g = s.adjoint(rho_t.grad.contiguous(), torch.zeros_like(rho), g_hl)
+        torch.cuda.synchronize()
+        g_rho0, g_mom0, g_hl0, g_tau = (x.cpu().numpy() for x in g)
+        rho_n, mom_n = s.state_numpy()
+        return dict(L=L.detach().cpu().numpy(), g_rho0=g_rho0, g_mom0=g_mom0, g_hl0=g_hl0,
+                    g_tau=float(g_tau[0]), rho=rho_n, mom=mom_n, home=home, hl=hl)
+    finally:
+        s.close()
+
+
+def _check_against_tangent(b, P, M, n, C, n_dirs=3, seed=0, launch=None):
+    G = _gpu_gradient(b, P, M, n, C, launch=launch)
+    # the checkpointed forward is the plain forward, bit for bit
+    ref = oracle.State(b)
+    oracle.run(ref, M, P, n, threads=THREADS)
+    assert np.array_equal(G["rho"], ref.rho) and np.array_equal(G["mom"], ref.mom)
+    assert np.array_equal(G["hl"], ref.hl[:b.n_iface])
+    L_ref = oracle.objective(ref)
+    np.testing.assert_allclose(G["L"], L_ref, rtol=1e-13)
+    so = b.slot_off
+    rng = np.random.default_rng(seed)
+    for d in range(n_dirs):
+        dr = rng.standard_normal(b.n_slots) * b.rho
+        dm = rng.standard_normal(b.n_slots) * np.maximum(np.abs(b.mom), 1e-3 * b.rho)
+        dh = rng.standard_normal(max(b.n_iface, 1))[:b.n_iface] * b.h[
+            np.repeat(np.arange(b.n_problems), np.diff(b.iface_off))] * 1e-3
+        st = oracle.State(b)
+        _, tan, _ = oracle.tangent(st, M, P, n, dr, dm, 0.0, d_hl=dh if b.n_iface else None,
+                                   threads=THREADS)
+        terms = G["g_rho0"] * dr + G["g_mom0"] * dm
+        got = np.add.reduceat(terms, so[:-1])
+        mag = np.add.reduceat(np.abs(terms), so[:-1])
+        if b.n_iface:
+            ip = np.repeat(np.arange(b.n_problems), np.diff(b.iface_off))
+            got = got + np.bincount(ip, G["g_hl0"] * dh, minlength=b.n_problems)
+            mag = mag + np.bincount(ip, np.abs(G["g_hl0"] * dh), minlength=b.n_problems)
+        err = np.abs(got - tan)
+        bad = np.nonzero(err > RTOL * (np.abs(tan) + mag))[0]
+        assert bad.size == 0, (f"direction {d}: problems {bad[:8]} got {got[bad[:4]]} "
+                               f"tangent {tan[bad[:4]]}")
+    # kinetic coefficient: one direction, summed over problems
+    z = np.zeros(b.n_slots)
+    st = oracle.State(b)
+    _, tan_tau, _ = oracle.tangent(st, M, P, n, z, z, 1.0, threads=THREADS)
+    want = float(np.sum(tan_tau))
+    assert abs(G["g_tau"] - want) <= RTOL * np.sum(np.abs(tan_tau)) + 1e-300, (G["g_tau"], want)
+    return G
+
+
+def test_adjoint_single_phase_bulk_and_cfl(material):
+    """No interface: the transposed HLL stencil, walls and the CFL cell."""
+    b = W.single_phase_problem(300, lambda x: 950.0 + 30.0 * np.sin(6.0 * x),
+                               lambda x: 2.0 * np.cos(5.0 * x) + 0.3)
+    _check_against_tangent(b, W.Params(), material, 60, 16)
+
+
+def test_adjoint_transmissive_single_phase(material):
+    b = W.single_phase_problem(200, lambda x: 0.05 + 0.02 * np.sin(4.0 * x),
+                               lambda x: 3.0 * np.sin(7.0 * x), phase=W.VAP)
+    _check_against_tangent(b, W.Params(bc_left=1, bc_right=1), material, 50, 7)
+
+
+def test_adjoint_single_cut(material):
+    b = W.single_cut_problem(seed=3)
+    P = W.single_cut_params().replace(t_end=np.inf)
+    _check_against_tangent(b, P, material, 120, 25)
+
+
+def test_adjoint_random_batch_with_merges_and_crossings(material):
+    b = W.random_batch(n_problems=16, nmax=1024)
+    P = W.random_batch_params()
+    G = _check_against_tangent(b, P, material, 83, 16)
+    assert np.all(np.isfinite(G["g_rho0"]))
+
+
+def test_adjoint_bubble_batch(material):
+    b = W.bubble_batch(n_problems=6, n=256)
+    _check_against_tangent(b, W.bubble_batch_params(), material, 100, 30)
+
+
+def test_adjoint_smooth_batch(material):
+    b = W.adjoint_batch(n_problems=12, nmax=2048)
+    _check_against_tangent(b, W.adjoint_batch_params(), material, 90, 50,
+                           launch=(512, 16, 0, 8))
+
+
+def test_adjoint_is_reproducible_and_repeatable(material):
+    import torch
+    from paper_2211_00705_amd.imexds import IMEXDS
+    b = W.random_batch(n_problems=8, nmax=700)
+    s = IMEXDS(b, material, W.random_batch_params())
+    try:
+        s.set_state()
+        s.forward_ckpt(40, 9)
+        rho, mom = s.state()
+        g = torch.rand_like(rho)
+        a = [x.cpu().numpy() for x in s.adjoint(g, g)]
+        c = [x.cpu().numpy() for x in s.adjoint(g, g)]
+        for x, y in zip(a, c):
+            assert np.array_equal(x, y)
+        # the end state is back in place after the reverse sweep
+        rho2, mom2 = s.state()
+        assert torch.equal(rho, rho2) and torch.equal(mom, mom2)
+    finally:
+        s.close()
+
+
+def test_autograd_function_gradients(material):
+    """torch.autograd through evolve(): gradients of the window objective in
+    rho0, rho u 0 and tau agree with the direct adjoint call."""
+    import torch
+    from paper_2211_00705_amd.imexds import IMEXDS
+    from paper_2211_00705_amd.autograd import evolve, window_objective
+    b = W.bubble_batch(n_problems=3, n=128)
+    P = W.bubble_batch_params()
+    s = IMEXDS(b, material, P)
+    try:
+        rho0 = torch.tensor(b.rho, dtype=torch.float64, device="cuda", requires_grad=True)
+        mom0 = torch.tensor(b.mom, dtype=torch.float64, device="cuda", requires_grad=True)
+        tau = torch.tensor([material.tau], dtype=torch.float64, device="cuda", requires_grad=True)
+        rho, mom, hl = evolve(s, rho0, mom0, tau, 40, 10)
+        home, _, _ = s.interfaces()
+        L = window_objective(b, home, hl, rho).sum()
+        L.backward()
+        st = oracle.State(b)
+        z = np.zeros(b.n_slots)
+        _, tan_tau, _ = oracle.tangent(st, material, P, 40, z, z, 1.0, threads=4)
+        assert float(tau.grad[0]) == pytest.approx(float(np.sum(tan_tau)), rel=1e-8)
+        rng = np.random.default_rng(3)
+        dr = rng.standard_normal(b.n_slots)
+        st = oracle.State(b)
+        _, tan, _ = oracle.tangent(st, material, P, 40, dr, z, 0.0, threads=4)
+        got = float(np.dot(rho0.grad.cpu().numpy(), dr))
+        assert got == pytest.approx(float(np.sum(tan)), rel=1e-8)
+    finally:
+        s.close()
+
+
+def _rel_direction(b, material, rng):
+    """Relative perturbation directions x_j -> x_j (1 + eps d_j), d ~ N(0, 1),
+    over rho0, rho u 0 and tau."""
+    dr = rng.standard_normal(b.n_slots) * b.rho
+    dm = rng.standard_normal(b.n_slots) * b.mom
+    return dr, dm, rng.standard_normal() * material.tau
+
+
+def test_adjoint_against_central_differences(material):
+    """Central differences (eps = 1e-7, 16 random relative directions) of the
+    objective, with the forward's decisions frozen (the oracle replays the
+    logged counts, events and CFL slots of the unperturbed run, which are
+    the GPU's), against the GPU gradient."""
+    b = W.adjoint_batch(n_problems=24, nmax=1024)
+    P = W.adjoint_batch_params()
+    n, C, eps = 200, 50, 1e-7
+    G = _gpu_gradient(b, P, material, n, C)
+    base = oracle.State(b)
+    lg = oracle.run(base, material, P, n, log="full", threads=THREADS)
+    rng = np.random.default_rng(2024)
+    for d in range(16):
+        dr, dm, dtau = _rel_direction(b, material, rng)
+        got = float(np.dot(G["g_rho0"], dr) + np.dot(G["g_mom0"], dm) + G["g_tau"] * dtau)
+        Ls = []
+        for sg in (1.0, -1.0):
+            bb = b.copy()
+            bb.rho = b.rho + sg * eps * dr
+            bb.mom = b.mom + sg * eps * dm
+            sp = oracle.State(bb)
+            oracle.run(sp, W.Material(tau=material.tau + sg * eps * dtau), P, n, threads=THREADS,
+                       replay=lg)
+            Ls.append(float(np.sum(oracle.objective(sp))))
+        fd = (Ls[0] - Ls[1]) / (2 * eps)
+        noise = 5e-16 * abs(Ls[0]) / eps
+        assert abs(got - fd) <= 1e-6 * abs(fd) + noise, (d, got, fd, noise)
+
+
+def test_adjoint_full_size_batch(material):
+    """The adjoint configuration at full size: 1024 problems of 256..16384
+    cells, 500 steps with a checkpoint every 50; every problem's gradient is
+    checked against the oracle tangent along one direction (and tau along
+    another)."""
+    b = W.adjoint_batch()
+    P = W.adjoint_batch_params()
+    _check_against_tangent(b, P, material, 500, 50, n_dirs=1, seed=9)
