@@ -44,6 +44,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (HBM counter calibration)")
+    ap.add_argument("--adjoint-steps", type=int, default=500,
+                    help="steps of the adjoint leg (0: skip it)")
+    ap.add_argument("--adjoint-every", type=int, default=50)
+    ap.add_argument("--adjoint-problems", type=int, default=1024)
+    ap.add_argument("--adjoint-zone-lanes", type=int, default=8, choices=[1, 8])
     return ap.parse_args()
 
 
@@ -142,6 +147,56 @@ def cpu_baseline_leg(b, P, material, steps, gpu_rho, gpu_mom, gpu_home, gpu_hl, 
             "parity_max_rel_l1": worst}
 
 
+def adjoint_leg(args, material):
+    """Adjoint workload: plain forward of n steps (HIP graphs) vs the
+    checkpointed forward and the reverse sweep, all timed with HIP events on
+    the library's stream; gradient of the window objective."""
+    import torch
+    from paper_2211_00705_amd import workloads as W
+    from paper_2211_00705_amd.imexds import IMEXDS
+    from paper_2211_00705_amd.autograd import window_objective
+    b = W.adjoint_batch(n_problems=args.adjoint_problems)
+    P = W.adjoint_batch_params()
+    n, C = args.adjoint_steps, args.adjoint_every
+    s = IMEXDS(b, material, P)
+    try:
+        s.set_launch(1024, 64, 0, 10, args.adjoint_zone_lanes)
+        s.set_state()
+        s.step(2)
+        torch.cuda.synchronize()
+        s.set_state()
+        s.step(n)
+        torch.cuda.synchronize()
+        fwd_ms, _ = s.last_timing()
+        s.set_state()
+        s.forward_ckpt(n, C)
+        torch.cuda.synchronize()
+        ck_ms, _ = s.last_timing()
+        rho, mom = s.state()
+        home, hl, _ = s.interfaces()
+        hl_t = torch.tensor(hl, dtype=torch.float64, device="cuda", requires_grad=True)
+        rho_t = rho.clone().requires_grad_(True)
+        window_objective(b, home, hl_t, rho_t).sum().backward()
+        g = (rho_t.grad.contiguous(), torch.zeros_like(rho), hl_t.grad.contiguous())
+        s.adjoint(*g)  # first call allocates the tape
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.adjoint(*g)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        adj_ms, _ = s.last_timing()
+    finally:
+        s.close()
+    return {"workload": f"adjoint_batch: {b.n_problems} problems, N ~ logU-int[256,16384] "
+                        f"({b.n_slots} slots), piecewise-smooth states, 1 interface each, "
+                        f"{n} steps, checkpoint every {C}",
+            "objective": "sum of interface positions + mass in [0.4, 0.6]",
+            "forward_ms": fwd_ms, "forward_ckpt_ms": ck_ms, "adjoint_ms": adj_ms,
+            "adjoint_wall_ms": wall * 1e3,
+            "adjoint_over_forward": adj_ms / fwd_ms,
+            "total_over_forward": (ck_ms + adj_ms) / fwd_ms}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -165,11 +220,13 @@ def main():
     rho0 = torch.from_numpy(np.ascontiguousarray(b.rho)).cuda()
     mom0 = torch.from_numpy(np.ascontiguousarray(b.mom)).cuda()
     s.set_state(rho0, mom0)
-    tune = {"tile_cells": 1024, "zones_per_group": 16, "zone_groups": 0}
+    tune = {"tile_cells": 1024, "zones_per_group": 64, "zone_groups": 0, "zone_lanes": 8}
     if not args.no_autotune:
-        tc, zp, zg, ms = s.autotune(10)
-        tune = {"tile_cells": tc, "zones_per_group": zp, "zone_groups": zg, "ms_per_step": ms}
-    s.set_launch(tune["tile_cells"], tune["zones_per_group"], tune["zone_groups"], 10)
+        tc, zp, zg, zn, ms = s.autotune(10)
+        tune = {"tile_cells": tc, "zones_per_group": zp, "zone_groups": zg, "zone_lanes": zn,
+                "ms_per_step": ms}
+    s.set_launch(tune["tile_cells"], tune["zones_per_group"], tune["zone_groups"], 10,
+                 tune["zone_lanes"])
 
     # warm-up on the initial state, then reload it so the timed steps are the first K steps
     s.step(args.warmup)
@@ -199,7 +256,10 @@ def main():
     zone_slots = int(round(NIF * (2 * P.zone_half + 1)))
     bulk_bytes = BYTES_PER_CELL_UPDATE * (b.n_slots - zone_slots)
     bulk_ms = achieved = None
+    roof_tile = 1024  # the bulk sweep's own best tile class (the step's may differ)
     if args.roofline_steps > 0:
+        s.set_launch(roof_tile, tune["zones_per_group"], tune["zone_groups"], 10,
+                     tune["zone_lanes"])
         s.time_bulk(True)
         s.step(args.roofline_steps)
         torch.cuda.synchronize()
@@ -240,13 +300,18 @@ def main():
         "per_problem": pp,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                     "traffic": measured_traffic(args.workload, tune["tile_cells"]),
+                     "traffic": measured_traffic(args.workload, roof_tile),
+                     "tile_cells": roof_tile,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "k_bulk", "bulk_ms_per_launch": bulk_ms,
                      "bulk_launches_timed": args.roofline_steps,
                      "algorithmic_bytes_per_launch": bulk_bytes},
         "step_roofline_frac": value / (HBM_PEAK_GBS * 1e9 / BYTES_PER_CELL_UPDATE),
     }
+    if args.adjoint_steps > 0:
+        adj = adjoint_leg(args, material)
+        out["adjoint"] = adj
+        out["adjoint_over_forward"] = adj["adjoint_over_forward"]
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline_leg(b, P, material, args.steps, g_rho, g_mom, g_home,
                                                g_hl, args.cpu_seconds)

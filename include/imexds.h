@@ -191,21 +191,26 @@ int imexds_get_stats(imexds_ctx *ctx, imexds_stats *out);
 
 /* Launch configuration: bulk tile class (256, 512, 1024, 2048: R = class/256
  * rows of 62 cells per wave, four waves per tile), zone lanes per 64-lane
- * workgroup (1..64), number of zone workgroups (0 = one zone per lane;
- * otherwise that many workgroups whose lanes keep taking the next unsolved
- * zone until none is left) and physical steps per captured HIP graph
- * (0 = launch kernels directly, else an even number up to 512).  Rebuilds
- * the tile table and drops captured graphs.  Results do not depend on it. */
+ * workgroup (1..64, with one lane per zone), number of zone workgroups (0 =
+ * enough for all zones at once; otherwise that many workgroups whose zone
+ * slots keep taking the next unsolved zone until none is left), physical
+ * steps per captured HIP graph (0 = launch kernels directly, else an even
+ * number up to 512) and lanes per zone (1: one lane runs a whole zone; 8: an
+ * 8-lane group runs it, one lane per zone cell, the interface solve split
+ * over the two lanes next to the phase boundary, eight zones per wave).
+ * Rebuilds the tile table and drops captured graphs.  Results do not depend
+ * on it (bit for bit). */
 int imexds_set_launch(imexds_ctx *ctx, int32_t tile_cells, int32_t zones_per_group,
-                      int32_t zone_groups, int32_t graph_steps);
+                      int32_t zone_groups, int32_t graph_steps, int32_t zone_lanes);
 
 /* Times launch configurations on the current state for steps_per_trial
- * steps each (zone lane shapes first, then tile classes), restores the state
- * afterwards and keeps the fastest configuration.  Results (host, may be
- * NULL): chosen tile class, zone lanes per group, zone groups and the
- * measured ms per step.  Synchronizes. */
+ * steps each (zone launch shapes first, then tile classes), restores the
+ * state afterwards and keeps the fastest configuration.  Results (host, may
+ * be NULL): chosen tile class, zone lanes per group, zone groups, lanes per
+ * zone and the measured ms per step.  Synchronizes. */
 int imexds_autotune(imexds_ctx *ctx, int32_t steps_per_trial, int32_t *tile_cells,
-                    int32_t *zones_per_group, int32_t *zone_groups, double *ms_per_step);
+                    int32_t *zones_per_group, int32_t *zone_groups, int32_t *zone_lanes,
+                    double *ms_per_step);
 
 /* Sizes of the batch (host, any may be NULL). */
 int imexds_get_sizes(imexds_ctx *ctx, int32_t *n_problems, int32_t *n_iface, int64_t *n_slots);

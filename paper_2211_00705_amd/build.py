@@ -5,6 +5,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libimexds.so")
 SOURCES = [os.path.join(HERE, "csrc", "imexds_kernels.hip"),
+           os.path.join(HERE, "csrc", "imexds_zone8.hip"),
            os.path.join(HERE, "csrc", "imexds_adjoint.hip"),
            os.path.join(HERE, "csrc", "imexds_runtime.hip")]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-shared", "-std=c++17",

@@ -225,14 +225,44 @@ __device__ __forceinline__ bool d_wave(const Mat& M, const Side& S, double ps, d
   return true;
 }
 
+// Exchange of one double with a partner lane (both lanes active).
+__device__ __forceinline__ double d_swap(double x, int partner) { return __shfl(x, partner, 64); }
+
 // G(p_l*, p_r*) and its Jacobian.  z solves A z^2 - z + C = 0 with
 // A = tau p_V [[v^2]] / 2, C = tau p_V [[g]] (root continuous at A = 0);
 // dz/dp from differentiating that relation, using 2 A z - 1 = -sqrt(D).
-__device__ __forceinline__ bool d_eval_G(const Mat& M, const RP& R, double psl, double psr,
-                                         GEval& E) {
+// PAIR: two lanes evaluate together, the lane with side 0 the left outer
+// wave and the one with side 1 the right one (same operations as one lane
+// doing both), then swap them; everything after is computed on both lanes
+// from identical values.
+template <bool PAIR>
+__device__ __forceinline__ bool d_eval_G_t(const Mat& M, const RP& R, double psl, double psr,
+                                           int side, int partner, GEval& E) {
   double gl, gr, dfl, dfr;
-  if (!d_wave(M, R.L, psl, E.rsl, E.vl, gl, E.fl, dfl)) return false;
-  if (!d_wave(M, R.Rt, psr, E.rsr, E.vr, gr, E.fr, dfr)) return false;
+  if (PAIR) {
+    double rs = 0.0, v = 0.0, g = 0.0, f = 0.0, df = 0.0;
+    Side me;  // field by field: a selected struct reference would go through scratch
+    me.ph = side == 0 ? R.L.ph : R.Rt.ph;
+    me.r = side == 0 ? R.L.r : R.Rt.r;
+    me.u = side == 0 ? R.L.u : R.Rt.u;
+    me.p = side == 0 ? R.L.p : R.Rt.p;
+    me.LK = side == 0 ? R.L.LK : R.Rt.LK;
+    const bool ok = d_wave(M, me, side == 0 ? psl : psr, rs, v, g, f, df);
+    const double o_rs = d_swap(rs, partner), o_v = d_swap(v, partner), o_g = d_swap(g, partner);
+    const double o_f = d_swap(f, partner), o_df = d_swap(df, partner);
+    const bool o_ok = __shfl(ok ? 1 : 0, partner, 64) != 0;
+    if (!ok || !o_ok) return false;
+    if (side == 0) {
+      E.rsl = rs; E.vl = v; gl = g; E.fl = f; dfl = df;
+      E.rsr = o_rs; E.vr = o_v; gr = o_g; E.fr = o_f; dfr = o_df;
+    } else {
+      E.rsl = o_rs; E.vl = o_v; gl = o_g; E.fl = o_f; dfl = o_df;
+      E.rsr = rs; E.vr = v; gr = g; E.fr = f; dfr = df;
+    }
+  } else {
+    if (!d_wave(M, R.L, psl, E.rsl, E.vl, gl, E.fl, dfl)) return false;
+    if (!d_wave(M, R.Rt, psr, E.rsr, E.vr, gr, E.fr, dfr)) return false;
+  }
   const double vl = E.vl, vr = E.vr;
   const bool lvap = R.phl == VAP;
   const double ia2l = lvap ? M.ia2v : M.ia2l, ia2r = lvap ? M.ia2l : M.ia2v;
@@ -276,6 +306,11 @@ __device__ __forceinline__ bool d_eval_G(const Mat& M, const RP& R, double psl, 
   return true;
 }
 
+__device__ __forceinline__ bool d_eval_G(const Mat& M, const RP& R, double psl, double psr,
+                                         GEval& E) {
+  return d_eval_G_t<false>(M, R, psl, psr, 0, 0, E);
+}
+
 // HLLC-type start (eq. HLLC:2p_nopt, mirrored when the liquid is on the left):
 // contact speed and liquid star density from the two states, liquid law for
 // the pressure; the vapour unknown is kept at or above 1e-3 of the vapour
@@ -310,15 +345,40 @@ __device__ __forceinline__ void d_guess(const Mat& M, const RP& R, double& gl, d
 // the step is already below 1e-8 (round-off floor), else the start fails;
 // at most maxit steps per start.  Written as one loop with a single
 // evaluation site so that lanes at different stages share it.
-__device__ __forceinline__ bool d_iface_solve(const Mat& M, int maxit, double rtol, int phl,
-                                              double rl, double ml, int phr, double rr, double mr,
-                                              bool have_guess, double gl, double gr,
-                                              IfaceOut& out) {
-  if (!(rl > 0.0) || !(rr > 0.0) || phl == phr) return false;
+// PAIR: two lanes solve together (see d_eval_G_t): the lane with side 0
+// passes the left state in (rl, ml), the one with side 1 the right state in
+// (rr, mr); each sets up its own side and the two swap them; both lanes
+// return the same result.
+template <bool PAIR>
+__device__ __forceinline__ bool d_iface_solve_t(const Mat& M, int maxit, double rtol, int phl,
+                                                double rl, double ml, int phr, double rr,
+                                                double mr, bool have_guess, double gl, double gr,
+                                                int side, int partner, IfaceOut& out) {
   RP R;
   R.phl = phl;
-  d_side(M, phl, rl, ml, R.L);
-  d_side(M, phr, rr, mr, R.Rt);
+  if (PAIR) {
+    Side own;
+    d_side(M, side == 0 ? phl : phr, side == 0 ? rl : rr, side == 0 ? ml : mr, own);
+    const double o_r = d_swap(own.r, partner), o_u = d_swap(own.u, partner);
+    const double o_p = d_swap(own.p, partner), o_LK = d_swap(own.LK, partner);
+    R.L.ph = phl;
+    R.Rt.ph = phr;
+    R.L.r = side == 0 ? own.r : o_r;
+    R.L.u = side == 0 ? own.u : o_u;
+    R.L.p = side == 0 ? own.p : o_p;
+    R.L.LK = side == 0 ? own.LK : o_LK;
+    R.Rt.r = side == 0 ? o_r : own.r;
+    R.Rt.u = side == 0 ? o_u : own.u;
+    R.Rt.p = side == 0 ? o_p : own.p;
+    R.Rt.LK = side == 0 ? o_LK : own.LK;
+    rl = R.L.r;
+    rr = R.Rt.r;
+    if (!(rl > 0.0) || !(rr > 0.0) || phl == phr) return false;
+  } else {
+    if (!(rl > 0.0) || !(rr > 0.0) || phl == phr) return false;
+    d_side(M, phl, rl, ml, R.L);
+    d_side(M, phr, rr, mr, R.Rt);
+  }
   const double zl = rl * d_a(M, phl), zr = rr * d_a(M, phr);
   R.izref = 1.0 / (zl > zr ? zl : zr);
   const double qtol = 1e-10;
@@ -337,7 +397,7 @@ __device__ __forceinline__ bool d_iface_solve(const Mat& M, int maxit, double rt
   int k = 0, it = 0, mode = 0;  // 0: start point, 1: Armijo trial, 2: final step
   for (;;) {
     GEval Et;
-    const bool valid = d_eval_G(M, R, tl, tr, Et);
+    const bool valid = d_eval_G_t<PAIR>(M, R, tl, tr, side, partner, Et);
     bool done = false, take = false, next = false, acc = false;
     if (mode == 0) {
       if (!valid) {
@@ -442,6 +502,14 @@ __device__ __forceinline__ bool d_iface_solve(const Mat& M, int maxit, double rt
   out.F0 = -z;
   out.F1 = -z * uV + pV;
   return true;
+}
+
+__device__ __forceinline__ bool d_iface_solve(const Mat& M, int maxit, double rtol, int phl,
+                                              double rl, double ml, int phr, double rr, double mr,
+                                              bool have_guess, double gl, double gr,
+                                              IfaceOut& out) {
+  return d_iface_solve_t<false>(M, maxit, rtol, phl, rl, ml, phr, rr, mr, have_guess, gl, gr, 0,
+                                0, out);
 }
 
 }  // namespace imexds

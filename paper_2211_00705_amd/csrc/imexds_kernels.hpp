@@ -100,6 +100,9 @@ hipError_t launch_cfl(const StepArgs& A, int tile_begin, int n_tiles, hipStream_
 // groups <= 0: one lane per zone; else that many workgroups whose lanes pull
 // zones from the shared counter until none is left.
 hipError_t launch_zone(const StepArgs& A, int if_begin, int if_end, int groups, hipStream_t s);
+// the same zones with eight lanes per zone, eight zones per wave; groups <= 0:
+// enough waves for all zones, else that many waves pulling zones
+hipError_t launch_zone8(const StepArgs& A, int if_begin, int if_end, int groups, hipStream_t s);
 hipError_t launch_finalize(const StepArgs& A, int p_begin, int p_end, int init, int bump_row,
                            hipStream_t s);
 

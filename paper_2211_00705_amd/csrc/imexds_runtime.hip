@@ -65,6 +65,7 @@ struct imexds_ctx {
       *d_iface_local = nullptr;
   int *d_tile_prob = nullptr, *d_tile_start = nullptr, *d_tile_len = nullptr;
   int n_tiles = 0, tile_cells = 1024, zones_per_group = 16, zone_groups = 0, graph_steps = 8;
+  int zone_lanes = 1;  // lanes per zone: 1 (k_zone) or 8 (k_zone8)
   std::vector<int> h_tile_off;  // [P+1] tiles of each problem
   // evolving state
   double *d_rho[2] = {nullptr, nullptr}, *d_mom[2] = {nullptr, nullptr};
@@ -245,6 +246,12 @@ int build_tiles(imexds_ctx* c, int tile_cells) {
   return 0;
 }
 
+hipError_t launch_zones(imexds_ctx* c, const StepArgs& A, int k0, int k1, int groups,
+                        hipStream_t s) {
+  if (c->zone_lanes == 8) return imexds::launch_zone8(A, k0, k1, groups, s);
+  return imexds::launch_zone(A, k0, k1, groups, s);
+}
+
 // One physical step of every problem, enqueued on c->ms (zones on c->zs).
 int enqueue_step(imexds_ctx* c, int ev_slot) {
   StepArgs A = make_args(c, c->parity, false);
@@ -262,7 +269,7 @@ int enqueue_step(imexds_ctx* c, int ev_slot) {
     CK(imexds::launch_bulk(A, c->tile_cells, 0, c->n_tiles, c->ms));
     CK(hipEventRecord(c->bulk_ev[2 * c->bulk_launches + 1], c->ms));
     c->bulk_launches++;
-    if (c->NIF > 0) CK(imexds::launch_zone(A, 0, c->NIF, c->zone_groups, c->ms));
+    if (c->NIF > 0) CK(launch_zones(c, A, 0, c->NIF, c->zone_groups, c->ms));
     CK(imexds::launch_finalize(A, 0, c->P, 0, 1, c->ms));
     c->parity ^= 1;
     return 0;
@@ -270,7 +277,7 @@ int enqueue_step(imexds_ctx* c, int ev_slot) {
   if (c->NIF > 0) {
     CK(hipEventRecord(ef, c->ms));
     CK(hipStreamWaitEvent(c->zs, ef, 0));
-    CK(imexds::launch_zone(A, 0, c->NIF, c->zone_groups, c->zs));
+    CK(launch_zones(c, A, 0, c->NIF, c->zone_groups, c->zs));
   }
   CK(imexds::launch_bulk(A, c->tile_cells, 0, c->n_tiles, c->ms));
   if (c->NIF > 0) {
@@ -561,7 +568,7 @@ int record_segment(imexds_ctx* c, int len) {
     A.st_pseudo = A.st_merges = A.st_lmax = nullptr;
     A.tape = c->tZone + (size_t)j * N * (size_t)c->tape_stride;
     A.tape_stride = c->tape_stride;
-    if (N) CK(imexds::launch_zone(A, 0, c->NIF, c->zone_groups, m));
+    if (N) CK(launch_zones(c, A, 0, c->NIF, c->zone_groups, m));
     CK(imexds::launch_bulk(A, c->tile_cells, 0, c->n_tiles, m));
     CK(imexds::launch_finalize(A, 0, c->P, 0, 0, m));
     c->parity ^= 1;
@@ -863,7 +870,7 @@ int imexds_step_per_problem(imexds_ctx* c, int32_t n_steps) {
     StepArgs A = make_args(c, c->parity, false);
     for (int p = 0; p < c->P; ++p) {
       int k0 = c->h_iface_off[p], k1 = c->h_iface_off[p + 1];
-      if (k1 > k0) CK(imexds::launch_zone(A, k0, k1, 0, c->ms));
+      if (k1 > k0) CK(launch_zones(c, A, k0, k1, 0, c->ms));
       int t0 = c->h_tile_off[p], t1 = c->h_tile_off[p + 1];
       CK(imexds::launch_bulk(A, c->tile_cells, t0, t1 - t0, c->ms));
       CK(imexds::launch_finalize(A, p, p + 1, 0, p == c->P - 1, c->ms));
@@ -1018,10 +1025,11 @@ int imexds_get_stats(imexds_ctx* c, imexds_stats* out) {
 }
 
 int imexds_set_launch(imexds_ctx* c, int32_t tile_cells, int32_t zones_per_group,
-                      int32_t zone_groups, int32_t graph_steps) {
+                      int32_t zone_groups, int32_t graph_steps, int32_t zone_lanes) {
   if (!c) return IMEXDS_ERR_INVALID_ARG;
   if (tile_cells != 256 && tile_cells != 512 && tile_cells != 1024 && tile_cells != 2048)
     return IMEXDS_ERR_INVALID_ARG;
+  if (zone_lanes != 1 && zone_lanes != 8) return IMEXDS_ERR_INVALID_ARG;
   if (zones_per_group < 1 || zones_per_group > 64 || zone_groups < 0 || graph_steps < 0 ||
       (graph_steps & 1) || graph_steps > 512)
     return IMEXDS_ERR_INVALID_ARG;
@@ -1031,12 +1039,14 @@ int imexds_set_launch(imexds_ctx* c, int32_t tile_cells, int32_t zones_per_group
   c->zones_per_group = zones_per_group;
   c->zone_groups = zone_groups;
   c->graph_steps = graph_steps;
+  c->zone_lanes = zone_lanes;
   if (tile_cells != c->tile_cells) return build_tiles(c, tile_cells);
   return 0;
 }
 
 int imexds_autotune(imexds_ctx* c, int32_t steps_per_trial, int32_t* tile_cells,
-                    int32_t* zones_per_group, int32_t* zone_groups, double* ms_per_step) {
+                    int32_t* zones_per_group, int32_t* zone_groups, int32_t* zone_lanes,
+                    double* ms_per_step) {
   if (!c || steps_per_trial < 1) return IMEXDS_ERR_INVALID_ARG;
   if (!c->has_state) return IMEXDS_ERR_NO_STATE;
   CK(hipSetDevice(c->device));
@@ -1049,20 +1059,23 @@ int imexds_autotune(imexds_ctx* c, int32_t steps_per_trial, int32_t* tile_cells,
     return r;
   }
   struct Cfg {
-    int t, z, g;
+    int t, z, g, n;
   };
   std::vector<Cfg> cfgs;
-  // zone lanes: one zone per lane spread over many waves, or fewer lanes
-  // pulling several zones each
+  // one lane per zone: zones spread one per lane over many waves, or fewer
+  // lanes pulling several zones each; eight lanes per zone: one wave per
+  // eight zones, or fewer waves pulling zones
   const int zl[] = {4, 8, 16, 64};
-  const int gf[] = {0, 1, 2, 4};  // 0: one zone per lane; else groups = CUs * f
+  const int gf[] = {0, 1, 2, 4};  // 0: all zones at once; else groups = CUs * f
   for (int z : zl)
-    for (int f : gf) cfgs.push_back({1024, z, f == 0 ? 0 : 256 * f});
-  int best_t = c->tile_cells, best_z = c->zones_per_group, best_g = c->zone_groups;
+    for (int f : gf) cfgs.push_back({1024, z, f == 0 ? 0 : 256 * f, 1});
+  for (int f : gf) cfgs.push_back({1024, 64, f == 0 ? 0 : 256 * f, 8});
+  int best_t = c->tile_cells, best_z = c->zones_per_group, best_g = c->zone_groups,
+      best_n = c->zone_lanes;
   double best = 1e300;
   int G = c->graph_steps;
   auto trial = [&](const Cfg& q, double& per) -> int {
-    int rr = imexds_set_launch(c, q.t, q.z, q.g, G);
+    int rr = imexds_set_launch(c, q.t, q.z, q.g, G, q.n);
     if (rr) return rr;
     if ((rr = snap_restore(c, s))) return rr;
     if ((rr = steps_impl(c, 2))) return rr;  // warm-up (also captures the graph)
@@ -1085,20 +1098,21 @@ int imexds_autotune(imexds_ctx* c, int32_t steps_per_trial, int32_t* tile_cells,
       best_z = q.z;
       best_g = q.g;
       best_t = q.t;
+      best_n = q.n;
     }
   }
   if (!r) {
     const int tiles[] = {256, 512, 2048};
     for (int t : tiles) {
       double per = 0.0;
-      if ((r = trial({t, best_z, best_g}, per))) break;
+      if ((r = trial({t, best_z, best_g, best_n}, per))) break;
       if (per < best) {
         best = per;
         best_t = t;
       }
     }
   }
-  int r2 = imexds_set_launch(c, best_t, best_z, best_g, G);
+  int r2 = imexds_set_launch(c, best_t, best_z, best_g, G, best_n);
   int r3 = snap_restore(c, s);
   snap_free(s);
   if (r) return r;
@@ -1107,6 +1121,7 @@ int imexds_autotune(imexds_ctx* c, int32_t steps_per_trial, int32_t* tile_cells,
   if (tile_cells) *tile_cells = best_t;
   if (zones_per_group) *zones_per_group = best_z;
   if (zone_groups) *zone_groups = best_g;
+  if (zone_lanes) *zone_lanes = best_n;
   if (ms_per_step) *ms_per_step = best;
   return 0;
 }

@@ -75,8 +75,8 @@ _get_problems = _sig("imexds_get_problems", c_vp, P_dbl, P_i32, P_i64)
 _enable_log = _sig("imexds_enable_log", c_vp, c_i32)
 _get_log = _sig("imexds_get_log", c_vp, P_i32, P_i32, P_i32, P_i32)
 _get_stats = _sig("imexds_get_stats", c_vp, ctypes.POINTER(imexds_stats))
-_set_launch = _sig("imexds_set_launch", c_vp, c_i32, c_i32, c_i32, c_i32)
-_autotune = _sig("imexds_autotune", c_vp, c_i32, P_i32, P_i32, P_i32, P_dbl)
+_set_launch = _sig("imexds_set_launch", c_vp, c_i32, c_i32, c_i32, c_i32, c_i32)
+_autotune = _sig("imexds_autotune", c_vp, c_i32, P_i32, P_i32, P_i32, P_i32, P_dbl)
 _get_sizes = _sig("imexds_get_sizes", c_vp, P_i32, P_i32, P_i64)
 _last_timing = _sig("imexds_last_timing", c_vp, P_dbl, P_dbl)
 _time_bulk = _sig("imexds_time_bulk", c_vp, c_i32)
@@ -224,16 +224,16 @@ def imexds_get_stats(ctx):
     return {n: getattr(s, n) for n, _ in imexds_stats._fields_}
 
 
-def imexds_set_launch(ctx, tile_cells, zones_per_group, zone_groups, graph_steps):
+def imexds_set_launch(ctx, tile_cells, zones_per_group, zone_groups, graph_steps, zone_lanes=1):
     _check(_set_launch(c_vp(ctx), int(tile_cells), int(zones_per_group), int(zone_groups),
-                       int(graph_steps)), "imexds_set_launch")
+                       int(graph_steps), int(zone_lanes)), "imexds_set_launch")
 
 
 def imexds_autotune(ctx, steps_per_trial):
-    t, z, g, ms = c_i32(), c_i32(), c_i32(), c_dbl()
+    t, z, g, n, ms = c_i32(), c_i32(), c_i32(), c_i32(), c_dbl()
     _check(_autotune(c_vp(ctx), int(steps_per_trial), ctypes.byref(t), ctypes.byref(z),
-                     ctypes.byref(g), ctypes.byref(ms)), "imexds_autotune")
-    return t.value, z.value, g.value, ms.value
+                     ctypes.byref(g), ctypes.byref(n), ctypes.byref(ms)), "imexds_autotune")
+    return t.value, z.value, g.value, n.value, ms.value
 
 
 def imexds_last_timing(ctx):
@@ -322,8 +322,10 @@ class IMEXDS:
     def stats(self):
         return imexds_get_stats(self.ctx)
 
-    def set_launch(self, tile_cells=1024, zones_per_group=16, zone_groups=0, graph_steps=8):
-        imexds_set_launch(self.ctx, tile_cells, zones_per_group, zone_groups, graph_steps)
+    def set_launch(self, tile_cells=1024, zones_per_group=16, zone_groups=0, graph_steps=8,
+                   zone_lanes=1):
+        imexds_set_launch(self.ctx, tile_cells, zones_per_group, zone_groups, graph_steps,
+                          zone_lanes)
 
     def autotune(self, steps_per_trial=10):
         return imexds_autotune(self.ctx, steps_per_trial)

@@ -30,13 +30,18 @@ def run_oracle(batch, material, params, n_steps, threads=8):
                 t=st.t, status=st.status, steps=st.steps, count=lc, flags=lf, zlo=lz)
 
 
-def run_gpu(batch, material, params, n_steps, launch=None, per_problem=False, log=True):
+def run_gpu(batch, material, params, n_steps, launch=None, per_problem=False, log=True,
+            lanes=None):
+    """``launch``: full set_launch tuple; ``lanes``: only the lanes per zone
+    (1 or 8) with the other launch settings at their defaults."""
     import torch
     from paper_2211_00705_amd.imexds import IMEXDS
     s = IMEXDS(batch, material, params)
     try:
         if launch is not None:
             s.set_launch(*launch)
+        elif lanes is not None:
+            s.set_launch(zone_lanes=lanes)
         s.set_state()
         if log:
             s.enable_log(n_steps)

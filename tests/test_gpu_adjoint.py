@@ -112,16 +112,18 @@ def test_adjoint_single_cut(material):
     _check_against_tangent(b, P, material, 120, 25)
 
 
-def test_adjoint_random_batch_with_merges_and_crossings(material):
+@pytest.mark.parametrize("lanes", [1, 8])
+def test_adjoint_random_batch_with_merges_and_crossings(material, lanes):
     b = W.random_batch(n_problems=16, nmax=1024)
     P = W.random_batch_params()
-    G = _check_against_tangent(b, P, material, 83, 16)
+    G = _check_against_tangent(b, P, material, 83, 16, launch=(1024, 16, 0, 8, lanes))
     assert np.all(np.isfinite(G["g_rho0"]))
 
 
 def test_adjoint_bubble_batch(material):
     b = W.bubble_batch(n_problems=6, n=256)
-    _check_against_tangent(b, W.bubble_batch_params(), material, 100, 30)
+    _check_against_tangent(b, W.bubble_batch_params(), material, 100, 30,
+                           launch=(1024, 16, 0, 8, 8))
 
 
 def test_adjoint_smooth_batch(material):

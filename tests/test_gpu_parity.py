@@ -40,24 +40,29 @@ def test_single_phase_matches_oracle_bitwise(material):
     assert_parity(b, g, o)
 
 
+LANES = [1, 8]  # lanes per zone: k_zone, k_zone8
+
+
+@pytest.mark.parametrize("lanes", LANES)
 @pytest.mark.parametrize("seed", [0, 1, 2, 3])
-def test_single_cut_problem(material, seed):
+def test_single_cut_problem(material, seed, lanes):
     """200 cells, cut fraction 1e-4, relative-update dual time stepping."""
     b = W.single_cut_problem(seed)
     P = W.single_cut_params()
-    g = run_gpu(b, material, P, 400)
+    g = run_gpu(b, material, P, 400, lanes=lanes)
     o = run_oracle(b, material, P, 400)
     assert np.all(o["status"] == 0)
     assert_parity(b, g, o)
 
 
+@pytest.mark.parametrize("lanes", LANES)
 @pytest.mark.parametrize("zone_half", [1, 2, 3])
-def test_random_batch(material, zone_half):
+def test_random_batch(material, zone_half, lanes):
     """Uneven problems spanning several tiles with ragged tails, paper's
     stopping rule, interfaces crossing cells and tiny pieces merging."""
     b = W.random_batch(seed=3 + zone_half, n_problems=40, nmin=64, nmax=3000)
     P = W.random_batch_params().replace(zone_half=zone_half)
-    g = run_gpu(b, material, P, 300)
+    g = run_gpu(b, material, P, 300, lanes=lanes)
     o = run_oracle(b, material, P, 300)
     assert np.all(o["status"] == 0)
     ev = (o["flags"] & 2) > 0  # merged
@@ -65,10 +70,11 @@ def test_random_batch(material, zone_half):
     assert_parity(b, g, o)
 
 
-def test_bubble_batch(material):
+@pytest.mark.parametrize("lanes", LANES)
+def test_bubble_batch(material, lanes):
     b = W.bubble_batch(seed=7, n_problems=12, n=512)
     P = W.bubble_batch_params()
-    g = run_gpu(b, material, P, 300)
+    g = run_gpu(b, material, P, 300, lanes=lanes)
     o = run_oracle(b, material, P, 300)
     assert_parity(b, g, o)
 
@@ -80,7 +86,7 @@ def test_launch_forms_agree_bitwise(material):
     P = W.random_batch_params()
     ref = run_gpu(b, material, P, 64, launch=(1024, 16, 0, 8))
     for launch in [(256, 1, 0, 0), (512, 64, 0, 2), (2048, 7, 1, 16), (1024, 4, 3, 0),
-                   (1024, 16, 0, 0)]:
+                   (1024, 16, 0, 0), (1024, 16, 0, 8, 8), (512, 1, 1, 0, 8), (256, 1, 3, 4, 8)]:
         g = run_gpu(b, material, P, 64, launch=launch)
         assert np.array_equal(g["rho"], ref["rho"]) and np.array_equal(g["mom"], ref["mom"]), launch
         assert np.array_equal(g["count"], ref["count"])
@@ -146,19 +152,20 @@ def test_overlapping_zones_freeze_the_problem(material):
     assert_parity(b, g, o)
 
 
-def test_edge_cases(material):
+@pytest.mark.parametrize("lanes", LANES)
+def test_edge_cases(material, lanes):
     """Empty batch; a problem without interfaces next to ones with them; an
     interface in the first and last background cells; pieces of exactly zero
     and of full length."""
     P = W.Params(bc_left=0, bc_right=1)
     empty = W._assemble([], [], [], [], [], [], [], name="empty")
-    g = run_gpu(empty, material, P, 3, log=False)
+    g = run_gpu(empty, material, P, 3, log=False, lanes=lanes)
     assert g["rho"].size == 0
     st = lambda x, q: (np.where(q == W.LIQ, 965.0 + 5 * x, 0.05 + 0.01 * x), 0.3 * np.ones(x.shape))
     b = W._assemble([30, 20, 25, 40], [1 / 30, 1 / 20, 1 / 25, 1 / 40], [0, 0, 0, 0],
                     [W.LIQ, W.VAP, W.LIQ, W.VAP], [[], [0], [24], [10, 30]],
                     [[], [0.3 / 20], [0.5 / 25], [0.0, 1 / 40]], [st] * 4, name="edges")
-    g = run_gpu(b, material, P, 40)
+    g = run_gpu(b, material, P, 40, lanes=lanes)
     o = run_oracle(b, material, P, 40)
     assert_parity(b, g, o)
 
