@@ -664,6 +664,361 @@ __global__ __launch_bounds__(64) void k_zone_adj(StepArgs A, AdjArgs B) {
 }
 
 // ---------------------------------------------------------------------------
+// zone pass with eight lanes per zone
+// ---------------------------------------------------------------------------
+// The same reverse as k_zone_adj, with the zone spread over an 8-lane group
+// as in k_zone8: lane c holds active cell c (its iterate, U0, lengths,
+// theta and their adjoints) and the face to its right; the interface solve
+// is linearised and reversed on the lane left of the phase boundary.  Sums
+// over the group run in a fixed shuffle order.
+namespace {
+
+__device__ __forceinline__ double a8_get(double x, int gb, int c) { return __shfl(x, gb + c, 64); }
+
+__device__ __forceinline__ double a8_sum(double v) {
+#pragma unroll
+  for (int off = 4; off > 0; off >>= 1) v += __shfl_xor(v, off, 8);
+  return v;
+}
+
+struct ZoneRev8 {
+  int c, gb, m, ic, zlo, sL, phl, phr;
+  double h, dt, FL0, FL1, FR0, FR1;
+  // own active cell
+  double U00, U01, hn, mv, th, it1;
+  int ph;
+  // own adjoint accumulators
+  double gU00, gU01, ghn, gth, gdt, gtau, gFL0, gFL1, gFR0, gFR1;
+};
+
+// One pass of the zone (a pseudo iteration, or Part 2) reversed: own iterate
+// (W0, W1), next iterate (N0, N1), adjoint of this lane's output (gO0, gO1);
+// gwx is the adjoint of the boundary speed from outside the pass (Part 2:
+// the interface advance; counted once).  Adds the adjoint of the own iterate
+// to (gW0, gW1).
+__device__ __forceinline__ void a8_pass_rev(const Mat& M, ZoneRev8& Z, bool part2, double W0,
+                                            double W1, double rpl, double rpr, double N0,
+                                            double N1, double gO0, double gO1, double gwx,
+                                            double& gW0, double& gW1) {
+  const int c = Z.c, gb = Z.gb;
+  const int cn = c < 7 ? c + 1 : 7;
+  const double nW0 = a8_get(W0, gb, cn), nW1 = a8_get(W1, gb, cn);
+  IfaceLin Q;
+  Q.F0 = Q.F1 = Q.w = 0.0;
+  if (c == Z.ic) d_iface_lin(M, Z.phl, W0, W1, nW0, nW1, rpl, rpr, Q);
+  const double F0pb = a8_get(Q.F0, gb, Z.ic), F1pb = a8_get(Q.F1, gb, Z.ic);
+  const double w = a8_get(Q.w, gb, Z.ic);
+  const bool act = c < Z.m;
+  double Fr0 = 0.0, Fr1 = 0.0;
+  if (act) {
+    if (c == Z.m - 1) {
+      Fr0 = Z.FR0;
+      Fr1 = Z.FR1;
+    } else if (c == Z.ic) {
+      Fr0 = F0pb;
+      Fr1 = F1pb;
+    } else {
+      d_hll(M, Z.ph, W0, W1, nW0, nW1, Fr0, Fr1);
+    }
+  }
+  const int cp = c > 0 ? c - 1 : 0;
+  double Fl0 = a8_get(Fr0, gb, cp), Fl1 = a8_get(Fr1, gb, cp);
+  if (c == 0) {
+    Fl0 = Z.FL0;
+    Fl1 = Z.FL1;
+  }
+  double gfr0 = 0.0, gfr1 = 0.0, gfl0 = 0.0, gfl1 = 0.0, gwl = 0.0;
+  if (act) {
+    const double hnew = Z.hn + (Z.mv * w) * Z.dt;
+    const double ih = 1.0 / hnew;
+    const double d0 = Fr0 - Fl0, d1 = Fr1 - Fl1;
+    const double rhs0 = (Z.hn * Z.U00 - Z.dt * d0) * ih;
+    const double rhs1 = (Z.hn * Z.U01 - Z.dt * d1) * ih;
+    double gr0, gr1;
+    if (part2) {
+      gr0 = gO0;
+      gr1 = gO1;
+    } else {
+      gW0 += Z.it1 * gO0;
+      gW1 += Z.it1 * gO1;
+      gr0 = (Z.th * Z.it1) * gO0;
+      gr1 = (Z.th * Z.it1) * gO1;
+      Z.gth += Z.it1 * ((rhs0 - N0) * gO0 + (rhs1 - N1) * gO1);
+    }
+    Z.gU00 += (Z.hn * ih) * gr0;
+    Z.gU01 += (Z.hn * ih) * gr1;
+    gfr0 = -(Z.dt * ih) * gr0;
+    gfr1 = -(Z.dt * ih) * gr1;
+    gfl0 = -gfr0;
+    gfl1 = -gfr1;
+    Z.gdt -= ih * (d0 * gr0 + d1 * gr1);
+    if (Z.mv != 0.0) {
+      const double ghnew = -ih * (rhs0 * gr0 + rhs1 * gr1);
+      Z.ghn += ih * (Z.U00 * gr0 + Z.U01 * gr1) + ghnew;
+      gwl = Z.mv * (Z.dt * ghnew);
+      Z.gdt += Z.mv * (w * ghnew);
+    }
+  }
+  // adjoint of the flux on the right face of c: own part plus the left-face
+  // part of cell c + 1
+  double gF0 = gfr0 + a8_get(gfl0, gb, cn), gF1 = gfr1 + a8_get(gfl1, gb, cn);
+  if (c == 0) {
+    Z.gFL0 += gfl0;
+    Z.gFL1 += gfl1;
+  }
+  if (act && c == Z.m - 1) {
+    Z.gFR0 += gfr0;
+    Z.gFR1 += gfr1;
+  }
+  const double gw = a8_sum(gwl) + gwx;
+  double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;  // own / right neighbour
+  if (act && c < Z.m - 1) {
+    if (c == Z.ic)
+      d_iface_adj(Q, gF0, gF1, gw, a0, a1, b0, b1, Z.gtau);
+    else
+      d_hll_adj(M, Z.ph, W0, W1, nW0, nW1, gF0, gF1, a0, a1, b0, b1);
+  }
+  gW0 += a0 + a8_get(b0, gb, cp) * (c > 0 ? 1.0 : 0.0);
+  gW1 += a1 + a8_get(b1, gb, cp) * (c > 0 ? 1.0 : 0.0);
+}
+
+}  // namespace
+
+template <int ZH>
+__global__ __launch_bounds__(64) void k_zone_adj8(StepArgs A, AdjArgs B) {
+  constexpr int MC = 2 * ZH + 1;
+  constexpr int E = 2 * MC + 2;
+  static_assert(MC <= 8, "a zone must fit an 8-lane group");
+  const int c = threadIdx.x & 7, gb = threadIdx.x & ~7;
+  const int k = (blockIdx.x * 64 + threadIdx.x) >> 3;
+  if (k >= A.n_iface) return;  // uniform over the group
+  const Mat& M = A.mat;
+  const Par& P = A.par;
+  const double theta_nb = P.theta_nb;
+  const int p = A.iface_prob[k], kk = A.iface_local[k];
+  const double dt = A.dt[p];
+  const double* T = A.tape + k * A.tape_stride;
+  const int flags = (int)T[TH_FLAGS];
+  if (c == 0) {
+    double* zo = B.zadj + 5 * (long long)k;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) zo[j] = 0.0;
+  }
+  if (dt == 0.0 || (flags & FL_INACTIVE)) return;
+  const long long so = A.slot_off[p];
+  const int ns = (int)(A.slot_off[p + 1] - so);
+  const double h = A.h[p];
+  const int home = A.rec_home0[k];
+  const double hl = A.rec_hl0[k];
+  const int sL = home + kk;
+  const int phl = A.phase_first[p] ^ (kk & 1), phr = phl ^ 1;
+  int zlo, zhi;
+  bool tr;
+  d_zone_range(sL, hl, h, ZH, ns, zlo, zhi, tr);
+  const int nr = zhi - zlo + 1, iL = sL - zlo, iR = iL + 1;
+  const double* r0 = A.rho0 + so;
+  const double* m0 = A.mom0 + so;
+  const double* g1r = B.gr1 + so;
+  const double* g1m = B.gm1 + so;
+  double* g0r = B.gr0 + so;
+  double* g0m = B.gm0 + so;
+  if ((flags & FL_FAIL) || sL < 0 || sL + 1 >= ns) {  // cells and record left at t^n
+    if (c < nr) {
+      g0r[zlo + c] = g1r[zlo + c];
+      g0m[zlo + c] = g1m[zlo + c];
+    }
+    return;
+  }
+  // U^n and the adjoint of U^{n+1} of zone position c
+  double Ur = 1.0, Um = 0.0, Br = 0.0, Bm = 0.0;
+  if (c < nr) {
+    Ur = r0[zlo + c];
+    Um = m0[zlo + c];
+    Br = g1r[zlo + c];
+    Bm = g1m[zlo + c];
+  }
+  const bool merge = (flags & FL_MERGED) != 0;
+  int cnt = (int)T[TH_COUNT];
+  cnt = cnt < 0 ? 0 : (cnt > P.lmax ? P.lmax : cnt);
+  const double wp = T[TH_WP], wstar = T[TH_WSTAR];
+  const int skip = merge ? (tr ? iR : iL) : -1;
+  const int into = merge ? (tr ? iR + 1 : iL - 1) : -1;
+  ZoneRev8 Z;
+  Z.c = c;
+  Z.gb = gb;
+  Z.m = merge ? nr - 1 : nr;
+  Z.zlo = zlo;
+  Z.sL = sL;
+  Z.phl = phl;
+  Z.phr = phr;
+  Z.h = h;
+  Z.dt = dt;
+  const int ic_pos = (merge && !tr) ? into : iL;
+  Z.ic = (skip >= 0 && ic_pos > skip) ? ic_pos - 1 : ic_pos;
+  const int pos = c < Z.m ? ((skip >= 0 && c >= skip) ? c + 1 : c) : -1;
+  const double ht = tr ? h - hl : hl;
+  const double hm = h + ht;
+  const double rpos = a8_get(Ur, gb, pos >= 0 ? pos : 0), mpos = a8_get(Um, gb, pos >= 0 ? pos : 0);
+  const double rskip = a8_get(Ur, gb, skip >= 0 ? skip : 0);
+  const double mskip = a8_get(Um, gb, skip >= 0 ? skip : 0);
+  const double Mr = merge ? (h * a8_get(Ur, gb, into >= 0 ? into : 0) + ht * rskip) / hm : 0.0;
+  const double Mm = merge ? (h * a8_get(Um, gb, into >= 0 ? into : 0) + ht * mskip) / hm : 0.0;
+  const double hn_l = (merge && !tr) ? hm : hl;
+  const double hn_r = (merge && tr) ? hm : h - hl;
+  const double hh_l = hn_l + (1.0 * wp) * dt;
+  const double hh_r = hn_r + (-1.0 * wp) * dt;
+  const bool cl_l = hh_l / h > theta_nb, cl_r = hh_r / h > theta_nb;
+  const double th_l = cl_l ? theta_nb : hh_l / h;
+  const double th_r = cl_r ? theta_nb : hh_r / h;
+  const double thf = (h + (0.0 * wp) * dt) / h;
+  const double th_f = thf > theta_nb ? theta_nb : thf;
+  const bool mvl = c == Z.ic, mvr = c == Z.ic + 1;
+  Z.U00 = pos == into ? Mr : rpos;
+  Z.U01 = pos == into ? Mm : mpos;
+  Z.hn = mvl ? hn_l : (mvr ? hn_r : h);
+  Z.mv = mvl ? 1.0 : (mvr ? -1.0 : 0.0);
+  Z.th = mvl ? th_l : (mvr ? th_r : th_f);
+  Z.it1 = 1.0 / (1.0 + Z.th);
+  Z.ph = (zlo + (pos >= 0 ? pos : 0) <= sL) ? phl : phr;
+  // bounding fluxes from U^n: F_left on lane 0, F_right on lane 1
+  {
+    double f0 = 0.0, f1 = 0.0;
+    if (c == 0) {
+      const int phz = (zlo <= sL) ? phl : phr;
+      if (zlo == 0)
+        d_bflux(M, phz, false, P.bc_left, r0[0], m0[0], f0, f1);
+      else
+        d_hll(M, phz, r0[zlo - 1], m0[zlo - 1], r0[zlo], m0[zlo], f0, f1);
+    } else if (c == 1) {
+      const int phe = (zhi <= sL) ? phl : phr;
+      if (zhi == ns - 1)
+        d_bflux(M, phe, true, P.bc_right, r0[ns - 1], m0[ns - 1], f0, f1);
+      else
+        d_hll(M, phe, r0[zhi], m0[zhi], r0[zhi + 1], m0[zhi + 1], f0, f1);
+    }
+    Z.FL0 = a8_get(f0, gb, 0);
+    Z.FL1 = a8_get(f1, gb, 0);
+    Z.FR0 = a8_get(f0, gb, 1);
+    Z.FR1 = a8_get(f1, gb, 1);
+  }
+  Z.gU00 = Z.gU01 = Z.ghn = Z.gth = Z.gdt = Z.gtau = 0.0;
+  Z.gFL0 = Z.gFL1 = Z.gFR0 = Z.gFR1 = 0.0;
+
+  // reverse of the write-back: the emptied piece copied the value of `src`.
+  // (Lane exchanges run with all eight lanes active: a lane masked off in a
+  // branch does not provide its value.)
+  const double bpos0 = a8_get(Br, gb, pos >= 0 ? pos : 0);
+  const double bpos1 = a8_get(Bm, gb, pos >= 0 ? pos : 0);
+  double gO0 = pos >= 0 ? bpos0 : 0.0, gO1 = pos >= 0 ? bpos1 : 0.0;
+  int src = -1;
+  if (merge) src = !tr ? ((flags & FL_CROSS_L) ? iR : into) : ((flags & FL_CROSS_R) ? iL : into);
+  {
+    const double sr_ = a8_get(Br, gb, skip >= 0 ? skip : 0);
+    const double sm_ = a8_get(Bm, gb, skip >= 0 ? skip : 0);
+    if (merge && pos == src) {
+      gO0 += sr_;
+      gO1 += sm_;
+    }
+  }
+  // hl^{n+1} = hl^n + w* dt (+- h after a crossing)
+  const double ghl1 = B.hl_bar[k];
+  double ghl = ghl1;
+  Z.gdt += (c == 0) ? ghl1 * wstar : 0.0;
+
+  // Part 2 at W^count, then the pseudo iterations in reverse
+  const double* e = T + TAPE_HDR + (long long)cnt * E;
+  const int ep = pos >= 0 ? pos : 0;
+  double W0 = e[ep], W1 = e[MC + ep];
+  double gW0 = 0.0, gW1 = 0.0;
+  a8_pass_rev(M, Z, true, W0, W1, e[2 * MC], e[2 * MC + 1], W0, W1, gO0, gO1,
+              (c == Z.ic) ? ghl1 * dt : 0.0, gW0, gW1);
+  for (int l = cnt - 1; l >= 0; --l) {
+    const double* el = T + TAPE_HDR + (long long)l * E;
+    const double N0 = W0, N1 = W1;
+    W0 = el[ep];
+    W1 = el[MC + ep];
+    const double o0 = gW0, o1 = gW1;
+    gW0 = gW1 = 0.0;
+    a8_pass_rev(M, Z, false, W0, W1, el[2 * MC], el[2 * MC + 1], N0, N1, o0, o1, 0.0, gW0, gW1);
+  }
+  // W^0 = U0
+  Z.gU00 += gW0;
+  Z.gU01 += gW1;
+  // theta = min(theta_nb, h_end / h), h_end = h^n +- w_pred dt (moving cells)
+  double gwp_l = 0.0;
+  if ((mvl && !cl_l) || (mvr && !cl_r)) {
+    const double g = Z.gth / h;
+    Z.ghn += g;
+    gwp_l = Z.mv * (g * dt);
+    Z.gdt += Z.mv * (g * wp);
+  }
+  const double gwp = a8_sum(gwp_l);
+  // lengths at t^n from hl (the moving cells' h^n)
+  const double ghn_l = a8_get(Z.ghn, gb, Z.ic), ghn_r = a8_get(Z.ghn, gb, Z.ic + 1);
+  // zone set-up: U0 from U^n (merge average) -> adjoint by zone position
+  const double gi_r = (pos == into) ? Z.gU00 : 0.0, gi_m = (pos == into) ? Z.gU01 : 0.0;
+  const double gir = a8_sum(gi_r), gim = a8_sum(gi_m);  // adjoint of the merged cell's U0
+  double Gown0 = (pos == into) ? (h / hm) * Z.gU00 : Z.gU00;
+  double Gown1 = (pos == into) ? (h / hm) * Z.gU01 : Z.gU01;
+  // lane j (zone position j) takes the adjoint of the active cell at j
+  const int cj = (skip >= 0 && c > skip) ? c - 1 : c;
+  double G0 = a8_get(Gown0, gb, cj), G1 = a8_get(Gown1, gb, cj);
+  if (c == skip) {
+    G0 = (ht / hm) * gir;
+    G1 = (ht / hm) * gim;
+  }
+  if (merge) {
+    double ght = ((rskip - Mr) * gir + (mskip - Mm) * gim) / hm;
+    if (!tr) {
+      ght += ghn_l;
+      ghl -= ghn_r;
+      ghl += ght;
+    } else {
+      ght += ghn_r;
+      ghl += ghn_l;
+      ghl -= ght;
+    }
+  } else {
+    ghl += ghn_l - ghn_r;
+  }
+  // predicting solve on U^n of the two cut pieces (positions iL, iR)
+  double gtau_p = 0.0;
+  {
+    const double nUr = a8_get(Ur, gb, c < 7 ? c + 1 : 7), nUm = a8_get(Um, gb, c < 7 ? c + 1 : 7);
+    double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
+    if (c == iL && gwp != 0.0) {
+      IfaceLin Q;
+      d_iface_lin(M, phl, Ur, Um, nUr, nUm, T[TH_IPL], T[TH_IPR], Q);
+      d_iface_adj(Q, 0.0, 0.0, gwp, a0, a1, b0, b1, gtau_p);
+    }
+    const double fb0 = a8_get(b0, gb, c > 0 ? c - 1 : 0), fb1 = a8_get(b1, gb, c > 0 ? c - 1 : 0);
+    G0 += a0;
+    G1 += a1;
+    if (c == iR) {
+      G0 += fb0;
+      G1 += fb1;
+    }
+  }
+  if (c < nr) {
+    g0r[zlo + c] = G0;
+    g0m[zlo + c] = G1;
+  }
+  const double sdt = a8_sum(Z.gdt), stau = a8_sum(Z.gtau + gtau_p);
+  const double sFL0 = a8_sum(Z.gFL0), sFL1 = a8_sum(Z.gFL1);
+  const double sFR0 = a8_sum(Z.gFR0), sFR1 = a8_sum(Z.gFR1);
+  if (c == 0) {
+    double* zo = B.zadj + 5 * (long long)k;
+    zo[0] = sFL0;
+    zo[1] = sFL1;
+    zo[2] = sFR0;
+    zo[3] = sFR1;
+    zo[4] = sdt;
+    B.tau_bar[k] += stau;
+    B.hl_bar[k] = ghl;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // bulk pass
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double d_wave_sum(double v) {
@@ -923,8 +1278,18 @@ __global__ __launch_bounds__(256) void k_sum(const double* x, int n, double* out
   if (threadIdx.x == 0) *out = sh[0];
 }
 
-hipError_t launch_zone_adj(const StepArgs& A, const AdjArgs& B, hipStream_t s) {
+hipError_t launch_zone_adj(const StepArgs& A, const AdjArgs& B, int lanes, hipStream_t s) {
   if (A.n_iface <= 0) return hipSuccess;
+  if (lanes == 8) {
+    const int waves = (A.n_iface + 7) / 8;
+    switch (A.par.zone_half) {
+      case 1: k_zone_adj8<1><<<waves, 64, 0, s>>>(A, B); break;
+      case 2: k_zone_adj8<2><<<waves, 64, 0, s>>>(A, B); break;
+      case 3: k_zone_adj8<3><<<waves, 64, 0, s>>>(A, B); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   const int blocks = (A.n_iface + 63) / 64;
   switch (A.par.zone_half) {
     case 1: k_zone_adj<1><<<blocks, 64, 0, s>>>(A, B); break;

@@ -107,7 +107,8 @@ hipError_t launch_finalize(const StepArgs& A, int p_begin, int p_end, int init, 
                            hipStream_t s);
 
 // adjoint of one step: zone pass, then bulk pass, then per-problem pass
-hipError_t launch_zone_adj(const StepArgs& A, const AdjArgs& B, hipStream_t s);
+// lanes: 1 (one lane per zone) or 8 (eight lanes per zone)
+hipError_t launch_zone_adj(const StepArgs& A, const AdjArgs& B, int lanes, hipStream_t s);
 hipError_t launch_bulk_adj(const StepArgs& A, const AdjArgs& B, int tile_class, int n_tiles,
                            hipStream_t s);
 hipError_t launch_finalize_adj(const StepArgs& A, const AdjArgs& B, int P, hipStream_t s);

@@ -604,7 +604,7 @@ int reverse_step(imexds_ctx* c, int j, int cur) {
   B.steps0 = c->tSteps + (size_t)j * P;
   B.steps1 = c->tSteps + (size_t)(j + 1) * P;
   B.t_bar = c->d_tbar;
-  if (N) CK(imexds::launch_zone_adj(A, B, c->ms));
+  if (N) CK(imexds::launch_zone_adj(A, B, c->zone_lanes, c->ms));
   CK(imexds::launch_bulk_adj(A, B, c->tile_cells, c->n_tiles, c->ms));
   CK(imexds::launch_finalize_adj(A, B, c->P, c->ms));
   return 0;
