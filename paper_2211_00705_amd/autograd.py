@@ -86,12 +86,11 @@ def window_objective(batch, home, hl, rho, cx=1.0, wa=0.4, wb=0.6):
     a = xp + jt * hp
     e = xp + (jt + 1.0) * hp
     if batch.n_iface:
-        klt = torch.as_tensor(kl, device=dev)
-        krt = torch.as_tensor(kr, device=dev)
-        hl_l = hl[klt.clamp(min=0)]
-        hl_r = hl[krt.clamp(min=0)]
-        e = torch.where(klt >= 0, a + hl_l, e)
-        a = torch.where(krt >= 0, a + hl_r, a)
+        # only the two pieces of each cut cell depend on hl
+        sl = torch.as_tensor(np.nonzero(kl >= 0)[0], device=dev)
+        sr = torch.as_tensor(np.nonzero(kr >= 0)[0], device=dev)
+        e = e.index_put((sl,), a[sl] + hl[torch.as_tensor(kl[kl >= 0], device=dev)])
+        a = a.index_put((sr,), a[sr] + hl[torch.as_tensor(kr[kr >= 0], device=dev)])
     ov = (torch.minimum(e, torch.full_like(e, wb)) - torch.maximum(a, torch.full_like(a, wa)))
     ov = ov.clamp(min=0.0)
     L = torch.zeros(batch.n_problems, dtype=torch.float64, device=dev)

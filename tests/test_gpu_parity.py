@@ -185,3 +185,50 @@ def test_full_size_batch_sampled(material):
     assert_parity(sub, gs, o, logs=False)
     assert np.all(g["steps"] == 1000)
     assert g["stats"]["cell_updates"] == 1000 * b.n_slots
+
+
+def test_single_cut_run_to_end_time(material):
+    """The single problem at full length: 200 cells, cut piece 1e-4 h, run to
+    t = 0.1 (about 33,000 steps, the last one clipped) with relative-update
+    dual time stepping to 1e-12 (up to 1e4 pseudo steps)."""
+    b = W.single_cut_problem(seed=0)
+    P = W.single_cut_params()
+    n = 33000
+    g = run_gpu(b, material, P, n, lanes=8)
+    o = run_oracle(b, material, P, n)
+    assert o["t"][0] == P.t_end and g["t"][0] == P.t_end
+    assert_parity(b, g, o)
+
+
+def test_large_problem_full_size(material):
+    """One problem of 2^20 cells, 2000 steps, paper stop rule, zone of 5 cells."""
+    b = W.large_smooth_problem()
+    P = W.large_smooth_params()
+    n = 2000
+    g = run_gpu(b, material, P, n, lanes=8)
+    o = run_oracle(b, material, P, n)
+    assert np.all(o["status"] == 0)
+    assert_parity(b, g, o)
+
+
+def test_bubble_batch_full_size_sampled(material):
+    """1024 bubble problems of 4096 cells (two interfaces each), 2000 steps;
+    6 sampled problems recomputed by the oracle on their own."""
+    b = W.bubble_batch()
+    P = W.bubble_batch_params()
+    n = 2000
+    g = run_gpu(b, material, P, n, log=False, lanes=8)
+    rng = np.random.default_rng(4)
+    idx = set(rng.choice(b.n_problems, size=6, replace=False).tolist())
+    # In this configuration some bubbles close (compressed liquid condenses
+    # the vapour until the two zones overlap) or reach a non-physical state
+    # and are frozen; two problems of every such status are recomputed too:
+    # the oracle must freeze them with the same status at the same step.
+    for st in np.unique(g["status"]):
+        if st != 0:
+            idx |= set(np.nonzero(g["status"] == st)[0][:2].tolist())
+    idx = sorted(idx)
+    sub = b.subset(idx)
+    o = run_oracle(sub, material, P, n)
+    gs = {k: _sub(b, v, k, idx) for k, v in g.items() if k != "stats"}
+    assert_parity(sub, gs, o, logs=False)
