@@ -197,7 +197,8 @@ int imexds_get_stats(imexds_ctx *ctx, imexds_stats *out);
  * steps per captured HIP graph (0 = launch kernels directly, else an even
  * number up to 512) and lanes per zone (1: one lane runs a whole zone; 8: an
  * 8-lane group runs it, one lane per zone cell, the interface solve split
- * over the two lanes next to the phase boundary, eight zones per wave).
+ * over the two lanes next to the phase boundary; zones_per_group then counts
+ * the zone groups per 64-lane wave, clamped to 1..8).
  * Rebuilds the tile table and drops captured graphs.  Results do not depend
  * on it (bit for bit). */
 int imexds_set_launch(imexds_ctx *ctx, int32_t tile_cells, int32_t zones_per_group,

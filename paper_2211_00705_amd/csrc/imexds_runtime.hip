@@ -1069,7 +1069,9 @@ int imexds_autotune(imexds_ctx* c, int32_t steps_per_trial, int32_t* tile_cells,
   const int gf[] = {0, 1, 2, 4};  // 0: all zones at once; else groups = CUs * f
   for (int z : zl)
     for (int f : gf) cfgs.push_back({1024, z, f == 0 ? 0 : 256 * f, 1});
-  for (int f : gf) cfgs.push_back({1024, 64, f == 0 ? 0 : 256 * f, 8});
+  const int g8[] = {2, 4, 8};  // zone groups (of eight lanes) per wave
+  for (int z : g8)
+    for (int f : gf) cfgs.push_back({1024, z, f == 0 ? 0 : 256 * f, 8});
   int best_t = c->tile_cells, best_z = c->zones_per_group, best_g = c->zone_groups,
       best_n = c->zone_lanes;
   double best = 1e300;

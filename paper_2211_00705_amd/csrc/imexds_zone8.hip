@@ -13,8 +13,9 @@
 //     broadcast to the group;
 //   * the stop test is an AND over the group.
 // Every operation is the one k_zone (and the CPU oracle) performs, in the same
-// order, so results are bit for bit those of k_zone.  A wave holds eight
-// groups; groups fetch zones from the shared counter until none is left.
+// order, so results are bit for bit those of k_zone.  A wave holds up to
+// eight groups (the launch's zones per group); groups fetch zones from the
+// shared counter until none is left.
 #include "imexds_device.hpp"
 #include "imexds_kernels.hpp"
 
@@ -68,6 +69,10 @@ __global__ __launch_bounds__(64) void k_zone8(StepArgs A, int if_begin, int if_e
   const double tol_nb = P.tol_nb, tol_tiny = P.tol_tiny;
   const int c = lane & 7;       // cell (lane) index inside the group
   const int gb = lane & ~7;     // first lane of the group
+  // zone groups per wave: A.zones_per_group clamped to 1..8 (fewer groups
+  // per wave: less divergence between zones, more waves)
+  const int gpw = A.zones_per_group < 1 ? 1 : (A.zones_per_group > 8 ? 8 : A.zones_per_group);
+  if ((lane >> 3) >= gpw) return;  // whole groups leave together
 
   // group-wide (identical on the 8 lanes)
   int k = 0, p = 0, kk = 0, ns = 0, sL = 0, zlo = 0, nr = 0, iL = 0, iR = 1, m = 0;
@@ -513,7 +518,8 @@ __global__ __launch_bounds__(64) void k_zone8(StepArgs A, int if_begin, int if_e
 hipError_t launch_zone8(const StepArgs& A, int if_begin, int if_end, int groups, hipStream_t s) {
   const int n = if_end - if_begin;
   if (n <= 0) return hipSuccess;
-  const int need = (n + 7) / 8;  // waves of eight zone groups
+  const int gpw = A.zones_per_group < 1 ? 1 : (A.zones_per_group > 8 ? 8 : A.zones_per_group);
+  const int need = (n + gpw - 1) / gpw;  // waves of gpw zone groups
   if (groups <= 0 || groups > need) groups = need;
   switch (A.par.zone_half) {
     case 1: k_zone8<1><<<groups, 64, 0, s>>>(A, if_begin, if_end); break;

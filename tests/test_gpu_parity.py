@@ -86,7 +86,8 @@ def test_launch_forms_agree_bitwise(material):
     P = W.random_batch_params()
     ref = run_gpu(b, material, P, 64, launch=(1024, 16, 0, 8))
     for launch in [(256, 1, 0, 0), (512, 64, 0, 2), (2048, 7, 1, 16), (1024, 4, 3, 0),
-                   (1024, 16, 0, 0), (1024, 16, 0, 8, 8), (512, 1, 1, 0, 8), (256, 1, 3, 4, 8)]:
+                   (1024, 16, 0, 0), (1024, 16, 0, 8, 8), (512, 1, 1, 0, 8), (256, 1, 3, 4, 8),
+                   (1024, 4, 0, 0, 8), (2048, 2, 5, 2, 8)]:
         g = run_gpu(b, material, P, 64, launch=launch)
         assert np.array_equal(g["rho"], ref["rho"]) and np.array_equal(g["mom"], ref["mom"]), launch
         assert np.array_equal(g["count"], ref["count"])
