@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--adjoint-every", type=int, default=50)
     ap.add_argument("--adjoint-problems", type=int, default=1024)
     ap.add_argument("--adjoint-zone-lanes", type=int, default=8, choices=[1, 8])
+    ap.add_argument("--adjoint-one-segment", type=int, default=1,
+                    help="also time the adjoint with a single segment (no recompute)")
     return ap.parse_args()
 
 
@@ -178,13 +180,25 @@ def adjoint_leg(args, material):
         rho_t = rho.clone().requires_grad_(True)
         window_objective(b, home, hl_t, rho_t).sum().backward()
         g = (rho_t.grad.contiguous(), torch.zeros_like(rho), hl_t.grad.contiguous())
-        s.adjoint(*g)  # first call allocates the tape
-        torch.cuda.synchronize()
         t0 = time.perf_counter()
         s.adjoint(*g)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         adj_ms, _ = s.last_timing()
+        # one segment (checkpoint interval = n): the forward records the tape
+        # of all n steps (HBM permitting) and the reverse sweep re-runs nothing
+        one = None
+        if args.adjoint_one_segment:
+            s.set_state()
+            s.forward_ckpt(n, n)
+            torch.cuda.synchronize()
+            ck1_ms, _ = s.last_timing()
+            s.adjoint(*g)
+            torch.cuda.synchronize()
+            adj1_ms, _ = s.last_timing()
+            one = {"forward_ckpt_ms": ck1_ms, "adjoint_ms": adj1_ms,
+                   "adjoint_over_forward": adj1_ms / fwd_ms,
+                   "total_over_forward": (ck1_ms + adj1_ms) / fwd_ms}
     finally:
         s.close()
     return {"workload": f"adjoint_batch: {b.n_problems} problems, N ~ logU-int[256,16384] "
@@ -194,7 +208,8 @@ def adjoint_leg(args, material):
             "forward_ms": fwd_ms, "forward_ckpt_ms": ck_ms, "adjoint_ms": adj_ms,
             "adjoint_wall_ms": wall * 1e3,
             "adjoint_over_forward": adj_ms / fwd_ms,
-            "total_over_forward": (ck_ms + adj_ms) / fwd_ms}
+            "total_over_forward": (ck_ms + adj_ms) / fwd_ms,
+            "one_segment": one}
 
 
 def main():

@@ -96,6 +96,7 @@ struct imexds_ctx {
   int adj_steps = 0, adj_every = 0;
   bool adj_ready = false;
   int tape_steps = 0;      // segment length the tape buffers hold
+  int tape_seg = -1;       // checkpoint segment whose tape is recorded (-1: none)
   long long tape_stride = 0;
   double* tU = nullptr;    // [C][2][S] rho^n, (rho u)^n
   int* tHome = nullptr;    // [C][NIF]
@@ -451,6 +452,7 @@ void free_tape(imexds_ctx* c) {
   void* ps[] = {c->tU, c->tHome, c->tHl, c->tDt, c->tClip, c->tSteps, c->tZone};
   for (void* p : ps)
     if (p) (void)hipFree(p);
+  c->tape_seg = -1;
   c->tU = nullptr;
   c->tHome = nullptr;
   c->tHl = nullptr;
@@ -462,6 +464,7 @@ void free_tape(imexds_ctx* c) {
 }
 
 void free_checkpoints(imexds_ctx* c) {
+  c->tape_seg = -1;
   for (Snapshot& s : c->ck) snap_free(s);
   c->ck.clear();
   if (c->ck_end_valid) snap_free(c->ck_end);
@@ -1183,10 +1186,21 @@ int imexds_forward_ckpt(imexds_ctx* c, int32_t n_steps, int32_t ckpt_every) {
   CK(hipEventRecord(c->ev_t0, c->ms));
   const int nck = (n_steps + ckpt_every - 1) / ckpt_every;
   c->ck.resize(nck);
+  // the last segment is run with its tape recorded: the reverse sweep starts
+  // there without re-running it
+  if (nck > 0 && (r = ensure_adjoint_buffers(c, std::max(1, std::min(ckpt_every, n_steps)))))
+    return r;
   for (int j = 0; j < nck; ++j) {
     if ((r = snap_take(c, c->ck[j]))) return r;
     const int len = std::min(ckpt_every, n_steps - j * ckpt_every);
-    if (c->P > 0 && (r = steps_impl(c, len))) return r;
+    if (c->P > 0) {
+      if (j == nck - 1) {
+        if ((r = record_segment(c, len))) return r;
+        c->tape_seg = j;
+      } else if ((r = steps_impl(c, len))) {
+        return r;
+      }
+    }
   }
   if ((r = snap_take(c, c->ck_end))) return r;
   c->ck_end_valid = true;
@@ -1229,8 +1243,11 @@ int imexds_adjoint(imexds_ctx* c, const double* gL_rho, const double* gL_mom,
   int cur = 0;
   for (int seg = (int)c->ck.size() - 1; seg >= 0; --seg) {
     const int len = std::min(C, n - seg * C);
-    if ((r = snap_restore(c, c->ck[seg]))) return r;
-    if ((r = record_segment(c, len))) return r;
+    if (c->tape_seg != seg) {
+      if ((r = snap_restore(c, c->ck[seg]))) return r;
+      if ((r = record_segment(c, len))) return r;
+      c->tape_seg = seg;
+    }
     for (int j = len - 1; j >= 0; --j) {
       if ((r = reverse_step(c, j, cur))) return r;
       cur ^= 1;
