@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--adjoint-every", type=int, default=50)
     ap.add_argument("--adjoint-problems", type=int, default=1024)
     ap.add_argument("--adjoint-zone-lanes", type=int, default=8, choices=[1, 8])
+    ap.add_argument("--other-configs", type=int, default=1,
+                    help="also time the other workloads (single cut, 2^20 cells, bubbles)")
     ap.add_argument("--adjoint-one-segment", type=int, default=1,
                     help="also time the adjoint with a single segment (no recompute)")
     return ap.parse_args()
@@ -212,6 +214,63 @@ def adjoint_leg(args, material):
             "one_segment": one}
 
 
+def other_configs_leg(material, cpu):
+    """The other configured workloads at their full size, fewer steps: GPU
+    batched (graph replay) and per-problem launches, and (cpu) the oracle on
+    one host thread and on all of them, on bounded samples."""
+    import torch
+    from paper_2211_00705_amd import workloads as W
+    from paper_2211_00705_amd.imexds import IMEXDS
+    out = {}
+    cases = [
+        ("single_cut: 1 problem, 200 cells, cut 1e-4 h, relative-update DTS to 1e-12",
+         W.single_cut_problem(seed=0), W.single_cut_params().replace(t_end=math.inf), 2000, 0, 2000),
+        ("large_smooth: 1 problem, 2^20 cells, paper stop rule, lmax 100",
+         W.large_smooth_problem(), W.large_smooth_params(), 200, 0, 10),
+        ("bubble_batch: 1024 problems x 4096 cells, 2 interfaces each",
+         W.bubble_batch(), W.bubble_batch_params(), 200, 4, 200),
+    ]
+    for desc, b, P, n, npp, ncpu in cases:
+        s = IMEXDS(b, material, P)
+        try:
+            s.set_launch(1024, 8, 0, 10, 8)
+            s.set_state()
+            s.step(4)
+            torch.cuda.synchronize()
+            s.set_state()
+            st0 = s.stats()
+            s.step(n)
+            torch.cuda.synchronize()
+            ms, _ = s.last_timing()
+            cu = s.stats()["cell_updates"] - st0["cell_updates"]
+            rec = {"steps": n, "ms_per_step": ms / n, "value": cu / (ms * 1e-3),
+                   "hbm_roofline_frac": cu / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9 / BYTES_PER_CELL_UPDATE)}
+            if npp:
+                s.set_state()
+                st0 = s.stats()
+                s.step_per_problem(npp)
+                torch.cuda.synchronize()
+                pms, _ = s.last_timing()
+                pcu = s.stats()["cell_updates"] - st0["cell_updates"]
+                rec["per_problem"] = {"steps": npp, "value": pcu / (pms * 1e-3),
+                                      "batched_speedup": rec["value"] / (pcu / (pms * 1e-3))}
+        finally:
+            s.close()
+        if cpu:
+            import oracle
+            sub = b if b.n_problems <= 8 else b.subset(list(range(0, b.n_problems, b.n_problems // 8)))
+            for threads in (1, max(1, min(16, os.cpu_count() or 1))):
+                stc = oracle.State(sub)
+                t0 = time.perf_counter()
+                oracle.run(stc, material, P, ncpu, threads=threads)
+                wall = time.perf_counter() - t0
+                key = "cpu_1_thread" if threads == 1 else "cpu_all_threads"
+                rec[key] = {"value": float(np.sum(stc.steps * np.diff(sub.slot_off))) / wall,
+                            "threads": threads, "sample": f"{sub.n_problems} problems x {ncpu} steps"}
+        out[desc] = rec
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -327,6 +386,8 @@ def main():
         adj = adjoint_leg(args, material)
         out["adjoint"] = adj
         out["adjoint_over_forward"] = adj["adjoint_over_forward"]
+    if args.other_configs:
+        out["other_configs"] = other_configs_leg(material, not args.no_cpu)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline_leg(b, P, material, args.steps, g_rho, g_mom, g_home,
                                                g_hl, args.cpu_seconds)
