@@ -229,3 +229,32 @@ def test_adjoint_full_size_batch(material):
     b = W.adjoint_batch()
     P = W.adjoint_batch_params()
     _check_against_tangent(b, P, material, 500, 50, n_dirs=1, seed=9)
+
+
+def test_adjoint_api_errors(material):
+    """The adjoint needs a checkpointed forward that is still the last thing
+    that changed the state; invalid tau is rejected."""
+    import torch
+    from paper_2211_00705_amd import imexds as I
+    b = W.random_batch(n_problems=3, nmax=300)
+    s = I.IMEXDS(b, material, W.random_batch_params())
+    try:
+        s.set_state()
+        g = torch.zeros(b.n_slots, dtype=torch.float64, device="cuda")
+        with pytest.raises(I.IMEXDSError) as e:
+            s.adjoint(g, g)
+        assert e.value.code == I.ERR_NO_STATE
+        s.forward_ckpt(6, 4)
+        s.adjoint(g, g)  # fine
+        s.step(1)
+        with pytest.raises(I.IMEXDSError) as e:
+            s.adjoint(g, g)
+        assert e.value.code == I.ERR_NO_STATE
+        for bad in (-1.0, float("nan"), float("inf")):
+            with pytest.raises(I.IMEXDSError) as e:
+                s.set_tau(bad)
+            assert e.value.code == I.ERR_INVALID_ARG
+        with pytest.raises(I.IMEXDSError):
+            s.forward_ckpt(5, 0)
+    finally:
+        s.close()

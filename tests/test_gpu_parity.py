@@ -116,19 +116,37 @@ def test_run_to_end_time(material):
     assert n >= steps.max()
 
 
-def test_failures_are_flagged_and_confined(material):
-    good = W.random_batch(seed=11, n_problems=3, nmin=64, nmax=128)
+@pytest.mark.parametrize("lanes", LANES)
+def test_failures_are_flagged_and_confined(material, lanes):
+    """Host-forced failures (a NaN density, a negative density, Newton limited
+    to one iteration) freeze exactly their problems with the oracle's status."""
+    good = W.random_batch(seed=11, n_problems=4, nmin=64, nmax=128)
     bad = good.copy()
     so = bad.slot_off
     bad.rho[so[1] + 5] = float("nan")
+    bad.rho[so[3] + 2] = -1.0
     P = W.random_batch_params()
-    g = run_gpu(bad, material, P, 20)
+    g = run_gpu(bad, material, P, 20, lanes=lanes)
     o = run_oracle(bad, material, P, 20)
     assert g["status"][1] == 2 and g["steps"][1] == 0
+    assert g["status"][3] == 2 and g["steps"][3] == 0
     assert_parity(bad.subset([0, 2]), {k: _sub(bad, v, k, [0, 2]) for k, v in g.items()},
                   {k: _sub(bad, v, k, [0, 2]) for k, v in o.items()}, logs=False)
-    g2 = run_gpu(good, material, P.replace(newton_maxit=1), 5)
+    np.testing.assert_array_equal(g["status"], o["status"])
+    g2 = run_gpu(good, material, P.replace(newton_maxit=1), 5, lanes=lanes)
     assert np.all(g2["status"] == 1) and np.all(g2["t"] == 0)
+
+
+@pytest.mark.parametrize("lanes", LANES)
+def test_forced_small_limits_match_oracle(material, lanes):
+    """l_max = 1 (every zone stops at once) and Newton limited to 3 steps per
+    start: the same results, statuses and logs as the oracle."""
+    b = W.random_batch(seed=13, n_problems=8, nmin=64, nmax=600)
+    for P in (W.random_batch_params().replace(lmax=1),
+              W.random_batch_params().replace(newton_maxit=3)):
+        g = run_gpu(b, material, P, 60, lanes=lanes)
+        o = run_oracle(b, material, P, 60)
+        assert_parity(b, g, o)
 
 
 def _sub(b, v, key, idx):
