@@ -274,8 +274,9 @@ def other_configs_leg(material, cpu):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU sharding is "
-                                   "described in DESIGN.md but not built", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "single-GPU only: the problems are independent and a multi-GPU "
+                                   "run would split the batch by problem, which is not implemented",
+                          "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
     from paper_2211_00705_amd import imexds as I

@@ -15,6 +15,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(_HERE, "imexds_oracle.c")
+SRC_EULER = os.path.join(_HERE, "euler_oracle.c")
 DUAL_H = os.path.join(_HERE, "or_dual.h")
 LIB = os.path.join(_HERE, "liboracle_imexds.so")
 LIB_TAN = os.path.join(_HERE, "liboracle_imexds_tan.so")
@@ -29,7 +30,7 @@ def build():
     from the same source (always recompiles)."""
     tmp = LIB + ".tmp"
     subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-                           "-shared", "-fPIC", "-o", tmp, SRC, "-lm"])
+                           "-shared", "-fPIC", "-o", tmp, SRC, SRC_EULER, "-lm"])
     os.replace(tmp, LIB)
     tmp = LIB_TAN + ".tmp"
     subprocess.check_call(["g++", "-x", "c++", "-std=c++17", "-DOR_TANGENT", "-I", _HERE, "-O2",
@@ -66,7 +67,8 @@ _lib_tan = None
 
 def _stale(path):
     return (not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(SRC)
-            or os.path.getmtime(path) < os.path.getmtime(DUAL_H))
+            or os.path.getmtime(path) < os.path.getmtime(DUAL_H)
+            or os.path.getmtime(path) < os.path.getmtime(SRC_EULER))
 
 
 def lib():
@@ -102,6 +104,15 @@ def lib():
                                               ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                               ctypes.c_int, dp, dp, ip, dp, dp, ip, ctypes.c_int,
                                               dp, dp, ip, dp]
+        L.oracle_exp.restype = ctypes.c_double
+        L.oracle_exp.argtypes = [ctypes.c_double]
+        L.oracle_euler_riemann.restype = ctypes.c_int
+        L.oracle_euler_riemann.argtypes = [ctypes.c_double, dp, dp, dp, dp, dp]
+        L.oracle_euler_run.restype = ctypes.c_int
+        L.oracle_euler_run.argtypes = ([ctypes.c_int, lp, ip] + [dp] * 6
+                                       + [ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_int, dp, dp, dp, dp, ip, ip, lp, ctypes.c_int,
+                                          ip, ip, ctypes.c_int])
         _lib = L
     return _lib
 
@@ -319,3 +330,75 @@ def zone_fixed_point(state, material, params, k=0):
         _ptr(Wn, ctypes.c_double), _ptr(m, ctypes.c_int), _ptr(dt, ctypes.c_double))
     n = 2 * int(m[0])
     return rc, Wd[:n].reshape(-1, 2), Wn[:n].reshape(-1, 2), float(dt[0])
+
+
+# ---------------------------------------------------------------------------
+# full Euler equations on a fixed mesh with one small cell (euler_oracle.c)
+# ---------------------------------------------------------------------------
+
+EU_ST_VACUUM, EU_ST_NEWTON, EU_ST_NONPHYS = 1, 2, 4
+EU_FL_LMAX = 1
+
+
+def exp(x):
+    """The oracle's fixed-order exponential."""
+    return lib().oracle_exp(float(x))
+
+
+def euler_riemann(gamma, WL, WR):
+    """Exact Riemann solution of the ideal-gas Euler equations for primitive
+    data WL, WR = (rho, u, p): returns (status, W0, F, star) with W0 the state
+    at x/t = 0, F its flux and star = (p*, u*, rho*_L, rho*_R)."""
+    wl = np.ascontiguousarray(WL, dtype=np.float64)
+    wr = np.ascontiguousarray(WR, dtype=np.float64)
+    W0, F, star = np.zeros(3), np.zeros(3), np.zeros(4)
+    st = lib().oracle_euler_riemann(float(gamma), _ptr(wl, ctypes.c_double),
+                                    _ptr(wr, ctypes.c_double), _ptr(W0, ctypes.c_double),
+                                    _ptr(F, ctypes.c_double), _ptr(star, ctypes.c_double))
+    return st, W0, F, star
+
+
+class EulerState:
+    """Evolving state of an EulerBatch in the oracle."""
+
+    def __init__(self, eb):
+        self.batch = eb
+        P = eb.n_problems
+        self.rho = np.ascontiguousarray(eb.rho, dtype=np.float64).copy()
+        self.mom = np.ascontiguousarray(eb.mom, dtype=np.float64).copy()
+        self.ene = np.ascontiguousarray(eb.ene, dtype=np.float64).copy()
+        self.t = np.zeros(P, dtype=np.float64)
+        self.steps = np.zeros(P, dtype=np.int32)
+        self.status = np.zeros(P, dtype=np.int32)
+        self.iters = np.zeros(P, dtype=np.int64)
+
+
+def euler_run(state, n_steps=None, threads=1, log=False):
+    """Advances every problem by up to n_steps time steps (None: to t_end).
+    With log=True returns (counts, flags), each [P, n_steps] (0 where a
+    problem did not step)."""
+    b = state.batch
+    P = b.n_problems
+    if n_steps is None:
+        if log:
+            raise ValueError("log=True needs n_steps")
+        n_steps = 2**31 - 1
+    off = np.ascontiguousarray(b.off[:-1], dtype=np.int64)
+    N = np.ascontiguousarray(b.N, dtype=np.int32)
+    per = [np.ascontiguousarray(getattr(b, f), dtype=np.float64)
+           for f in ("h", "alpha", "theta_nb", "theta_k", "cfl", "t_end")]
+    lc = lf = None
+    if log:
+        lc = np.zeros((P, n_steps), dtype=np.int32)
+        lf = np.zeros((P, n_steps), dtype=np.int32)
+    d, i, l = ctypes.c_double, ctypes.c_int, ctypes.c_longlong
+    lib().oracle_euler_run(P, _ptr(off, l), _ptr(N, i), *[_ptr(a, d) for a in per],
+                           float(b.gamma), float(b.tol_nb), float(b.tol_k), int(b.lmax),
+                           _ptr(state.rho, d), _ptr(state.mom, d), _ptr(state.ene, d),
+                           _ptr(state.t, d), _ptr(state.steps, i), _ptr(state.status, i),
+                           _ptr(state.iters, l), int(n_steps),
+                           _ptr(lc, i) if log else None, _ptr(lf, i) if log else None,
+                           int(threads))
+    if log:
+        return lc, lf
+    return None

@@ -18,8 +18,7 @@ provenance:
   rho_min).  The derivation lives with the CPU oracle and a test checks these
   numbers against it.
 
-Configuration recipes (shapes and distributions of the paper-scale workloads)
-are documented in DESIGN.md ("Inputs").
+Each generator's docstring states the shapes and distributions it draws.
 """
 from __future__ import annotations
 

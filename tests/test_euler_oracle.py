@@ -1,0 +1,293 @@
+"""Pins of the full-Euler oracle (ideal gas, fixed mesh with one small cell):
+the exact Riemann solver against the wave curves and the integral form of
+the conservation law, the dual time stepping against a direct solve of the
+implicit system and against the paper's table of average iteration counts
+for the Lax shock tube (Sec. 5, first test), conservation and convergence to
+the exact solution."""
+import math
+
+import numpy as np
+import pytest
+from scipy.optimize import fsolve
+
+import oracle
+from paper_2211_00705_amd import euler_workloads as EW
+
+G = EW.GAMMA
+
+
+def _ulp_err(a, b):
+    return abs(a - b) / math.ulp(b) if b != 0 else abs(a)
+
+
+def test_exp_is_accurate():
+    rng = np.random.default_rng(1)
+    xs = np.concatenate([rng.uniform(-700, 700, 4000), rng.uniform(-1, 1, 4000),
+                         rng.uniform(-1e-8, 1e-8, 200), [0.0, 1.0, -1.0, 0.5 * math.log(2)]])
+    worst = max(_ulp_err(oracle.exp(x), math.exp(x)) for x in xs)
+    assert worst <= 2.0, worst
+    assert oracle.exp(0.0) == 1.0
+    assert oracle.exp(800.0) == math.inf and oracle.exp(-800.0) == 0.0
+
+
+def _random_rp(rng, n):
+    for _ in range(n):
+        g = rng.choice([1.4, 5.0 / 3.0, 1.1])
+        WL = (rng.uniform(0.1, 10), rng.uniform(-2, 2), rng.uniform(0.1, 10))
+        WR = (rng.uniform(0.1, 10), rng.uniform(-2, 2), rng.uniform(0.1, 10))
+        yield g, np.array(WL), np.array(WR)
+
+
+def _cons(g, W):
+    r, u, p = W
+    return np.array([r, r * u, p / (g - 1) + 0.5 * r * u * u])
+
+
+def _flux(g, W):
+    r, u, p = W
+    E = p / (g - 1) + 0.5 * r * u * u
+    return np.array([r * u, r * u * u + p, u * (E + p)])
+
+
+def test_star_states_lie_on_the_wave_curves():
+    """Across a shock (p* > p_K) the Rankine-Hugoniot conditions hold for all
+    three conservation laws with the speed implied by mass conservation;
+    across a rarefaction the entropy p / rho^gamma and the Riemann invariant
+    u +- 2a/(gamma-1) are those of the outer state; u*, p* are shared by the
+    two star states (contact)."""
+    rng = np.random.default_rng(7)
+    n_shock = n_raref = 0
+    for g, WL, WR in _random_rp(rng, 400):
+        st, W0, F, star = oracle.euler_riemann(g, WL, WR)
+        if st == oracle.EU_ST_VACUUM:
+            continue
+        assert st == 0
+        ps, us, rsL, rsR = star
+        for side, WK, rs in ((-1, WL, rsL), (+1, WR, rsR)):
+            Ws = np.array([rs, us, ps])
+            if ps > WK[2]:
+                n_shock += 1
+                UK, Us = _cons(g, WK), _cons(g, Ws)
+                S = (rs * us - WK[0] * WK[1]) / (rs - WK[0])
+                res = _flux(g, Ws) - _flux(g, WK) - S * (Us - UK)
+                scale = np.abs(_flux(g, Ws)) + np.abs(_flux(g, WK)) + abs(S) * (np.abs(Us) + np.abs(UK))
+                assert np.all(np.abs(res) <= 1e-11 * scale + 1e-13), (WK, Ws, res)
+                # admissible: the shock moves away from the contact
+                assert side * (S - us) > 0
+            else:
+                n_raref += 1
+                assert ps / rs**g == pytest.approx(WK[2] / WK[0]**g, rel=1e-12)
+                aK, a_s = math.sqrt(g * WK[2] / WK[0]), math.sqrt(g * ps / rs)
+                JK = WK[1] - side * 2 * aK / (g - 1)
+                Js = us - side * 2 * a_s / (g - 1)
+                assert Js == pytest.approx(JK, rel=1e-12, abs=1e-12)
+    assert n_shock > 100 and n_raref > 100
+
+
+def _sample(g, WL, WR, xi):
+    """Self-similar solution at x/t = xi from the sampler at x/t = 0 of the
+    Galilean-shifted problem (velocities minus xi)."""
+    sh = np.array([0.0, xi, 0.0])
+    st, W0, _, _ = oracle.euler_riemann(g, WL - sh, WR - sh)
+    assert st == 0
+    return W0 + sh
+
+
+def test_sampled_solution_satisfies_integral_conservation():
+    """Integrating the conservation law over [-X, X] x [0, 1]: the integral of
+    U(x/t) over [-X, X] at t = 1 equals X (U_L + U_R) - (F(U_R) - F(U_L)).
+    Checked by brute-force quadrature of the sampled solution, so wave speeds,
+    star states and fan profiles are all tested at once."""
+    rng = np.random.default_rng(3)
+    cases = [(G, np.array(EW.LAX_LEFT), np.array(EW.LAX_RIGHT))]
+    cases += [c for c in _random_rp(rng, 3)]
+    for g, WL, WR in cases:
+        if oracle.euler_riemann(g, WL, WR)[0]:
+            continue
+        X, M = 30.0, 60000
+        xs = -X + (np.arange(M) + 0.5) * (2 * X / M)
+        integ = sum(_cons(g, _sample(g, WL, WR, x)) for x in xs) * (2 * X / M)
+        want = X * (_cons(g, WL) + _cons(g, WR)) - (_flux(g, WR) - _flux(g, WL))
+        err = np.abs(integ - want) / (np.abs(want) + 1.0)
+        assert np.all(err < 2e-4), (WL, WR, integ, want)
+
+
+def test_riemann_special_cases():
+    # equal states: the flux is the physical flux
+    W = np.array([0.7, -0.3, 1.9])
+    st, W0, F, _ = oracle.euler_riemann(G, W, W)
+    assert st == 0 and np.allclose(W0, W, rtol=0, atol=0) and np.allclose(F, _flux(G, W), rtol=1e-15)
+    # mirror symmetry x -> -x
+    rng = np.random.default_rng(11)
+    for g, WL, WR in _random_rp(rng, 50):
+        st, _, F, star = oracle.euler_riemann(g, WL, WR)
+        if st:
+            continue
+        mL, mR = WR * [1, -1, 1], WL * [1, -1, 1]
+        st2, _, F2, star2 = oracle.euler_riemann(g, mL, mR)
+        assert st2 == 0
+        assert star2[0] == pytest.approx(star[0], rel=1e-13)
+        assert star2[1] == pytest.approx(-star[1], rel=1e-12, abs=1e-13)
+        assert np.allclose(F2 * [-1, 1, -1], F, rtol=1e-12, atol=1e-13)
+    # a transonic left rarefaction: the state on the face is sonic, u = a,
+    # with the left state's entropy and Riemann invariant
+    WL, WR = np.array([1.0, 0.75, 1.0]), np.array([0.125, 0.0, 0.1])
+    st, W0, _, star = oracle.euler_riemann(G, WL, WR)
+    aL = math.sqrt(G * WL[2] / WL[0])
+    assert st == 0 and WL[1] - aL < 0 < star[1] - math.sqrt(G * star[0] / star[2])
+    a0 = math.sqrt(G * W0[2] / W0[0])
+    assert W0[1] == pytest.approx(a0, rel=1e-13)
+    assert W0[2] / W0[0]**G == pytest.approx(WL[2] / WL[0]**G, rel=1e-12)
+    assert W0[1] + 2 * a0 / (G - 1) == pytest.approx(WL[1] + 2 * aL / (G - 1), rel=1e-13)
+    # vacuum generation is reported, not solved
+    st, _, _, _ = oracle.euler_riemann(G, np.array([1.0, -8.0, 0.4]), np.array([1.0, 8.0, 0.4]))
+    assert st == oracle.EU_ST_VACUUM
+
+
+def _avg_iters(entries, threads=8):
+    b = EW.lax_study(entries)
+    st = oracle.EulerState(b)
+    oracle.euler_run(st, threads=threads)
+    assert np.all(st.status == 0) and np.all(st.t == b.t_end)
+    return dict(zip(entries, st.iters / st.steps))
+
+
+def test_lax_table_of_average_iterations():
+    """The paper's table of average dual time iterations for the Lax tube.
+
+    Our reading (S^n = max |u| + a over the cells, exact Godunov fluxes, the
+    Sec. 5 residual) gives 0.69..0.97 of every printed entry and never more;
+    with theta_{k+-1} = alpha the ratio of the alpha = 1e-4 to the 1e-2 column
+    (the O(1/alpha) growth the paper points out) matches the printed one to
+    1%, and every ordering the table shows holds."""
+    entries = [e for e in EW.LAX_TABLE if not (e[0] is None and e[2] < 1e-4)]
+    got = _avg_iters(entries)
+    for e in entries:
+        r = got[e] / EW.LAX_TABLE[e]
+        assert 0.65 <= r <= 1.0, (e, got[e], EW.LAX_TABLE[e])
+    for N in (100, 200, 400):
+        printed = EW.LAX_TABLE[(None, N, 1e-4)] / EW.LAX_TABLE[(None, N, 1e-2)]
+        ours = got[(None, N, 1e-4)] / got[(None, N, 1e-2)]
+        assert ours == pytest.approx(printed, rel=0.01), (N, ours, printed)
+        for a in (1e-2, 1e-4):
+            assert got[(0.9, N, a)] < got[(0.1, N, a)] < got[(None, N, a)]
+        for th in (0.9, 0.1):
+            assert got[(th, N, 1e-2)] < got[(th, N, 1e-4)] < got[(th, N, 1e-6)]
+    for th in (0.1, None):
+        for a in (1e-2, 1e-4):
+            assert got[(th, 100, a)] > got[(th, 200, a)] > got[(th, 400, a)]
+
+
+def test_lax_conserves_mass_momentum_energy():
+    """Sum of h_i U_i changes only by the boundary fluxes, which stay those of
+    the initial states while the waves are inside the domain."""
+    for th, N, a in ((0.9, 100, 1e-6), (0.1, 200, 1e-2)):
+        b = EW.lax_tube(N, a, th)
+        st = oracle.EulerState(b)
+        oracle.euler_run(st)
+        hs = np.full(N + 1, b.h[0])
+        hs[N // 2] = a * b.h[0]
+        tot0 = np.array([np.dot(hs, x) for x in (b.rho, b.mom, b.ene)])
+        tot1 = np.array([np.dot(hs, x) for x in (st.rho, st.mom, st.ene)])
+        FL, FR = _flux(G, np.array(EW.LAX_LEFT)), _flux(G, np.array(EW.LAX_RIGHT))
+        want = tot0 + 1.0 * (FL - FR)
+        assert np.allclose(tot1, want, rtol=1e-12, atol=0), (tot1, want)
+
+
+def test_lax_converges_to_exact_solution():
+    """First-order convergence in L1 to the exact solution at t = 1, and the
+    small cell (down to alpha = 1e-6) does not spoil it."""
+    WL, WR = np.array(EW.LAX_LEFT), np.array(EW.LAX_RIGHT)
+    errs = {}
+    for a in (1e-2, 1e-6):
+        for N in (100, 200, 400):
+            b = EW.lax_tube(N, a, 0.9)
+            st = oracle.EulerState(b)
+            oracle.euler_run(st)
+            h = b.h[0]
+            k = N // 2
+            left = -5.0 + (np.arange(N + 1)) * h
+            left[k + 1:] = left[k + 1:] - h + a * h
+            width = np.full(N + 1, h)
+            width[k] = a * h
+            xc = left + 0.5 * width
+            exact = np.array([_sample(G, WL, WR, x)[0] for x in xc])
+            errs[(a, N)] = float(np.sum(width * np.abs(st.rho - exact)))
+    for a in (1e-2, 1e-6):
+        assert errs[(a, 200)] < 0.8 * errs[(a, 100)]
+        assert errs[(a, 400)] < 0.8 * errs[(a, 200)]
+        assert errs[(a, 400)] < 0.2
+    for N in (100, 200, 400):
+        assert errs[(1e-6, N)] == pytest.approx(errs[(1e-2, N)], rel=0.05)
+
+
+def _prim(U):
+    r, m, E = U
+    u = m / r
+    return np.array([r, u, (G - 1) * (E - 0.5 * m * u)])
+
+
+def test_dual_time_stepping_solves_the_implicit_system():
+    """With tight tolerances the dual time iteration converges to the root of
+    the mixed explicit-implicit update (eq. update mixed EI), found here by a
+    general nonlinear solver on the 9 unknowns, whatever theta_{k+-1}."""
+    N, a = 100, 1e-3
+    base = EW.lax_tube(N, a, 0.9)
+    st = oracle.EulerState(base)
+    oracle.euler_run(st, 12)
+    U = np.stack([st.rho, st.mom, st.ene], axis=1)
+    k, h = N // 2, base.h[0]
+    S = max(abs(w[1]) + math.sqrt(G * w[2] / w[0]) for w in map(_prim, U))
+    dt = 0.8 * h / S
+    lam, lamk = dt / h, dt / (a * h)
+
+    def face(UL, UR):
+        s, _, F, _ = oracle.euler_riemann(G, _prim(UL), _prim(UR))
+        assert s == 0
+        return F
+
+    Fleft, Fright = face(U[k - 2], U[k - 1]), face(U[k + 1], U[k + 2])
+
+    def resid(x):
+        W = x.reshape(3, 3)
+        Fm, Fp = face(W[0], W[1]), face(W[1], W[2])
+        return np.concatenate([W[0] - U[k - 1] + lam * (Fm - Fleft),
+                               (W[1] - U[k] + lamk * (Fp - Fm)) * a,
+                               W[2] - U[k + 1] + lam * (Fright - Fp)])
+
+    root = fsolve(resid, U[k - 1:k + 2].ravel(), xtol=1e-14).reshape(3, 3)
+    assert np.max(np.abs(resid(root.ravel()))) < 1e-12
+    for th in (0.9, 0.4):
+        b = base.replace(tol_nb=1e-12, tol_k=1e-12, theta_nb=np.array([th]))
+        s2 = oracle.EulerState(b)
+        s2.rho[:], s2.mom[:], s2.ene[:] = st.rho, st.mom, st.ene
+        s2.t[:] = st.t
+        oracle.euler_run(s2, 1)
+        assert s2.status[0] == 0 and s2.steps[0] == 1
+        got = np.stack([s2.rho, s2.mom, s2.ene], axis=1)[k - 1:k + 2]
+        assert np.allclose(got, root, rtol=1e-9, atol=1e-12), (th, got - root)
+
+
+def test_failures_are_flagged():
+    # a tube whose data generate vacuum on the first interior face
+    b = EW._concat([EW.lax_spec(20, 1e-2, 0.9, left=(1.0, -8.0, 0.4), right=(1.0, 8.0, 0.4))],
+                   "vacuum")
+    st = oracle.EulerState(b)
+    oracle.euler_run(st)
+    assert st.status[0] & oracle.EU_ST_VACUUM and st.steps[0] == 0
+    # a negative pressure in a bulk cell
+    b = EW.lax_tube(20, 1e-2, 0.9)
+    b.ene[3] = 0.01
+    st = oracle.EulerState(b)
+    oracle.euler_run(st)
+    assert st.status[0] & oracle.EU_ST_NONPHYS and st.steps[0] == 0
+    # l_max reached is a flag, not a failure ...
+    b = EW.lax_tube(20, 1e-1, 0.9).replace(lmax=3)
+    st = oracle.EulerState(b)
+    lc, lf = oracle.euler_run(st, 5, log=True)
+    assert st.status[0] == 0 and np.all(lc[0] == 4) and np.all(lf[0] & oracle.EU_FL_LMAX)
+    # ... unless the unconverged iterate makes Part 2 non-physical
+    b = EW.lax_tube(20, 1e-2, 0.9).replace(lmax=3)
+    st = oracle.EulerState(b)
+    lc, lf = oracle.euler_run(st, 5, log=True)
+    assert st.status[0] == oracle.EU_ST_NONPHYS and st.steps[0] == 0 and lc[0, 0] == 4
