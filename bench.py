@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--adjoint-every", type=int, default=50)
     ap.add_argument("--adjoint-problems", type=int, default=1024)
     ap.add_argument("--adjoint-zone-lanes", type=int, default=8, choices=[1, 8])
+    ap.add_argument("--euler-problems", type=int, default=4096,
+                    help="tubes in the full-Euler Lax ensemble leg (0: skip)")
     ap.add_argument("--other-configs", type=int, default=1,
                     help="also time the other workloads (single cut, 2^20 cells, bubbles)")
     ap.add_argument("--adjoint-one-segment", type=int, default=1,
@@ -271,6 +273,68 @@ def other_configs_leg(material, cpu):
     return out
 
 
+def euler_leg(args, cpu):
+    """Full-Euler Lax-tube ensemble (Sec. 5 first test, batched): 4096 tubes
+    run to t_end = 1 on the GPU with per-launch HIP events, and (cpu) the
+    oracle on a bounded sample of the same tubes on 1 and on all threads."""
+    import torch
+    from paper_2211_00705_amd import euler_workloads as EW
+    from paper_2211_00705_amd.euler import EulerIMEXDS
+    b = EW.lax_batch(n_problems=args.euler_problems)
+    cells = (b.N.astype(np.int64) + 1)
+    s = EulerIMEXDS(b)
+    try:
+        best = None
+        for tile, lanes in ((256, 2), (512, 2), (256, 1)):
+            s.set_launch(tile, lanes)
+            s.set_state()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            n = s.run(1 << 20, 64)
+            torch.cuda.synchronize()
+            w = time.perf_counter() - t0
+            if best is None or w < best[0]:
+                best = (w, tile, lanes)
+        _, tile, lanes = best
+        s.set_launch(tile, lanes)
+        s.set_state()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n = s.run(1 << 20, 64)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        t, st, steps, iters = s.problems()
+        cu = float(np.sum(cells * steps))
+        s.set_state()
+        s.time_kernels(True)
+        s.run(1 << 20, 64)
+        bulk_ms, zone_ms, step_ms = s.last_timing()
+        s.time_kernels(False)
+    finally:
+        s.close()
+    rec = {"workload": f"lax_batch: {b.n_problems} Lax-type tubes, N in {{100,200,400}} "
+                       f"({b.n_cells} cells), alpha logU[1e-6,1e-2], theta_nb in {{0.9,0.1}}, "
+                       "states scaled by up to 25%, run to t_end = 1",
+           "unit": "cell-updates/s", "value": cu / wall, "wall_s": wall, "launch_steps": n,
+           "launch": {"tile_cells": tile, "zone_lanes": lanes, "check_every": 64},
+           "failed_problems": int(np.sum(st != 0)),
+           "mean_dual_time_iterations": float(np.sum(iters) / max(1, np.sum(steps))),
+           "bulk_ms_per_launch": bulk_ms, "zone_ms_per_launch": zone_ms,
+           "step_ms": step_ms}
+    if cpu:
+        import oracle
+        sub = b.subset(list(range(0, b.n_problems, max(1, b.n_problems // 64))))
+        for threads in (1, max(1, min(16, os.cpu_count() or 1))):
+            stc = oracle.EulerState(sub)
+            t0 = time.perf_counter()
+            oracle.euler_run(stc, threads=threads)
+            w = time.perf_counter() - t0
+            key = "cpu_1_thread" if threads == 1 else "cpu_all_threads"
+            rec[key] = {"value": float(np.sum((sub.N + 1) * stc.steps)) / w, "threads": threads,
+                        "kind": "oracle", "sample": f"{sub.n_problems} of the tubes to t_end"}
+    return rec
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -389,6 +453,8 @@ def main():
         out["adjoint_over_forward"] = adj["adjoint_over_forward"]
     if args.other_configs:
         out["other_configs"] = other_configs_leg(material, not args.no_cpu)
+    if args.euler_problems > 0:
+        out["euler_lax"] = euler_leg(args, not args.no_cpu)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline_leg(b, P, material, args.steps, g_rho, g_mom, g_home,
                                                g_hl, args.cpu_seconds)

@@ -27,7 +27,8 @@
  *
  * Readings where the paper is silent: the wave speed bound S^n is
  * max_i(|u_i| + a_i) over all cells at t^n, the last step is clipped to
- * t_end (t = t_end after it), both outer boundaries are transmissive (boundary flux = F(U) of the
+ * t_end (t = t_end after it) while its pseudo steps stay theta_i Delta t_ref
+ * with the unclipped CFL step Delta t_ref, both outer boundaries are transmissive (boundary flux = F(U) of the
  * boundary cell), max(U, 1) in the residual is taken as max(|U|, 1) per
  * component, and the stop test is evaluated multiplied out,
  * |(1 + theta_i) dW| < tol_i theta_i Delta t max(|W|, 1).
@@ -309,8 +310,8 @@ static int eu_cell_done(const double *Wold, const double *Wnew, double th, doubl
  * the problem is not meaningful.  *cnt = dual time iterations, *fl = EU_FL_
  * bits. */
 static int eu_step(const eu_gas *G, const eu_params *P, int N, double h, double alpha,
-                   double th_nb, double th_k, double dt, double *rho, double *mom, double *ene,
-                   double *F, int *cnt, int *fl) {
+                   double th_nb, double th_k, double dt, double dtref, int clip, double *rho,
+                   double *mom, double *ene, double *F, int *cnt, int *fl) {
   int n = N + 1, k = N / 2;
   double hk = alpha * h;
   int st = 0;
@@ -361,11 +362,16 @@ static int eu_step(const eu_gas *G, const eu_params *P, int N, double h, double 
     ene[i] = ene[i] - lam * (Fr[2] - Fl[2]);
   }
   if (stz) return st | stz;
-  /* Algorithm 2, Part 1: dual time stepping from W^0 = U^n with
-   * Delta tau_i = theta_i Delta t */
+  /* Algorithm 2, Part 1: dual time stepping from W^0 = U^n with the pseudo
+   * steps Delta tau_i = theta_i Delta t_ref of Sec. 5, Delta t_ref the CFL step;
+   * Delta t = Delta t_ref but on a step clipped to t_end, where the update
+   * takes the ratio Delta tau_i / Delta t */
   double lamk = dt / hk;
+  double tau[3] = {th_nb * dtref, th_k * dtref, th_nb * dtref};
   double th[3] = {th_nb, th_k, th_nb};
-  double thr[3] = {P->tol_nb * (th_nb * dt), P->tol_k * (th_k * dt), P->tol_nb * (th_nb * dt)};
+  if (clip)
+    for (int q = 0; q < 3; ++q) th[q] = tau[q] / dt;
+  double thr[3] = {P->tol_nb * tau[0], P->tol_k * tau[1], P->tol_nb * tau[2]};
   double W[3][3], Wn[3][3], Fkm[3], Fkp[3];
   memcpy(W, Un, sizeof(W));
   int l, done = 0;
@@ -448,7 +454,8 @@ int oracle_euler_run(int n_problems, const long long *off, const int *N, const d
         status[b] |= EU_ST_NONPHYS;
         break;
       }
-      double dt = (cfl[b] * h[b]) / S;
+      double dtref = (cfl[b] * h[b]) / S;
+      double dt = dtref;
       double rem = t_end[b] - t[b];
       int clip = 0;
       if (dt >= rem) {
@@ -456,7 +463,7 @@ int oracle_euler_run(int n_problems, const long long *off, const int *N, const d
         clip = 1;
       }
       int cnt = 0, fl = 0;
-      int st = eu_step(&G, &P, N[b], h[b], alpha[b], th_nb[b], th_k[b], dt, r, m, e, F, &cnt,
+      int st = eu_step(&G, &P, N[b], h[b], alpha[b], th_nb[b], th_k[b], dt, dtref, clip, r, m, e, F, &cnt,
                        &fl);
       if (log_cnt) log_cnt[(size_t)b * max_steps + s] = cnt;
       if (log_flags) log_flags[(size_t)b * max_steps + s] = fl;

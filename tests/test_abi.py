@@ -8,11 +8,12 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HDR = os.path.join(ROOT, "include", "imexds.h")
+HDR_EU = os.path.join(ROOT, "include", "imexds_euler.h")
 LIB = os.path.join(ROOT, "paper_2211_00705_amd", "libimexds.so")
 
 
-def declared():
-    txt = open(HDR).read()
+def declared(hdr=HDR):
+    txt = open(hdr).read()
     return sorted(set(re.findall(r"\b(imexds_[a-z_]+)\s*\(", txt)))
 
 
@@ -21,13 +22,18 @@ def test_header_declares_the_entry_points():
     for name in ("imexds_create", "imexds_set_state", "imexds_step", "imexds_run",
                  "imexds_get_state", "imexds_destroy", "imexds_strerror"):
         assert name in d
+    d = declared(HDR_EU)
+    for name in ("imexds_eu_create", "imexds_eu_set_state", "imexds_eu_step", "imexds_eu_run",
+                 "imexds_eu_get_state", "imexds_eu_get_problems", "imexds_eu_destroy"):
+        assert name in d
+    assert not set(d) & set(declared())
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
 def test_library_exports_every_declared_symbol():
     out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
     syms = set(l.split()[-1] for l in out.splitlines() if l.strip())
-    missing = [n for n in declared() if n not in syms]
+    missing = [n for n in declared() + declared(HDR_EU) if n not in syms]
     assert not missing, missing
 
 
@@ -37,6 +43,8 @@ def test_binding_loads_and_maps_every_symbol():
     assert sorted(imexds.EXPORTED) == declared()
     assert imexds.imexds_strerror(-1) == "invalid argument"
     assert imexds.imexds_strerror(0) == "ok"
+    from paper_2211_00705_amd import euler
+    assert sorted(euler.EXPORTED) == declared(HDR_EU)
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
