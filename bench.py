@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--adjoint-every", type=int, default=50)
     ap.add_argument("--adjoint-problems", type=int, default=1024)
     ap.add_argument("--adjoint-zone-lanes", type=int, default=8, choices=[1, 8])
+    ap.add_argument("--only-euler", action="store_true",
+                    help="run only the full-Euler leg (for profiling it)")
     ap.add_argument("--euler-problems", type=int, default=4096,
                     help="tubes in the full-Euler Lax ensemble leg (0: skip)")
     ap.add_argument("--other-configs", type=int, default=1,
@@ -285,8 +287,8 @@ def euler_leg(args, cpu):
     s = EulerIMEXDS(b)
     try:
         best = None
-        for tile, lanes in ((256, 2), (512, 2), (256, 1)):
-            s.set_launch(tile, lanes)
+        for tile, lanes, ppw in ((1024, 2, 32), (256, 2, 32), (1024, 2, 16)):
+            s.set_launch(tile, lanes, ppw)
             s.set_state()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -294,9 +296,9 @@ def euler_leg(args, cpu):
             torch.cuda.synchronize()
             w = time.perf_counter() - t0
             if best is None or w < best[0]:
-                best = (w, tile, lanes)
-        _, tile, lanes = best
-        s.set_launch(tile, lanes)
+                best = (w, tile, lanes, ppw)
+        _, tile, lanes, ppw = best
+        s.set_launch(tile, lanes, ppw)
         s.set_state()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -316,7 +318,8 @@ def euler_leg(args, cpu):
                        f"({b.n_cells} cells), alpha logU[1e-6,1e-2], theta_nb in {{0.9,0.1}}, "
                        "states scaled by up to 25%, run to t_end = 1",
            "unit": "cell-updates/s", "value": cu / wall, "wall_s": wall, "launch_steps": n,
-           "launch": {"tile_cells": tile, "zone_lanes": lanes, "check_every": 64},
+           "launch": {"tile_cells": tile, "zone_lanes": lanes, "zone_problems_per_wave": ppw,
+                      "check_every": 64},
            "failed_problems": int(np.sum(st != 0)),
            "mean_dual_time_iterations": float(np.sum(iters) / max(1, np.sum(steps))),
            "bulk_ms_per_launch": bulk_ms, "zone_ms_per_launch": zone_ms,
@@ -353,6 +356,10 @@ def main():
         xb.copy_(xa)
         torch.cuda.synchronize()
         del xa, xb
+
+    if args.only_euler:
+        print(json.dumps({"euler_lax": euler_leg(args, not args.no_cpu)}))
+        return
 
     b, P, desc = make_workload(args)
     s = I.IMEXDS(b, material, P)

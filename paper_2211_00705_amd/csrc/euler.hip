@@ -77,6 +77,7 @@ struct Args {
   int* log_cnt;             // [log_max][P] or null
   int* log_fl;
   int log_row;              // row of this step (or -1)
+  int zone_ppw;             // problems per wave in the dual time kernel
 };
 
 // exp of a finite double (Cody-Waite reduction by ln 2 with a head/tail split
@@ -362,10 +363,15 @@ __global__ __launch_bounds__(256) void k_eu_cfl(Args A, int tile_begin) {
 // ---------------------------------------------------------------------------
 template <int L>
 __global__ __launch_bounds__(64) void k_eu_zone(Args A) {
-  const int gid = blockIdx.x * 64 + (int)threadIdx.x;
-  const int p = gid / L;
-  const int side = L == 2 ? (gid & 1) : 0;
-  if (p >= A.P) return;  // pairs are whole: P and the pair index agree for both lanes
+  // a workgroup is one wave holding zone_ppw problems in its first lanes.
+  // Each problem is a serial chain of dual time iterations; packing 32 of
+  // them per wave (the default) leaves the other SIMDs to the sweep that runs
+  // beside this kernel, which measured faster than fewer problems per wave
+  const int lane = (int)threadIdx.x;
+  if (lane >= A.zone_ppw * L) return;
+  const int p = blockIdx.x * A.zone_ppw + lane / L;
+  const int side = L == 2 ? (lane & 1) : 0;
+  if (p >= A.P) return;  // pairs are whole: both lanes of a pair see the same p
   const long long o = A.off[p];
   const int k = A.N[p] / 2;
   const double* __restrict__ r0 = A.r0 + o;
@@ -612,7 +618,7 @@ struct imexds_eu_ctx {
   double* U[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
   int cur = 0;
   int *tile_prob = nullptr, *tile_start = nullptr, *tile_len = nullptr;
-  int n_tiles = 0, tile_class = 256, zone_lanes = 2;
+  int n_tiles = 0, tile_class = 1024, zone_lanes = 2, zone_ppw = 32;
   int *log_cnt = nullptr, *log_fl = nullptr;
   int log_max = 0, log_row = 0;
   bool have_state = false;
@@ -744,6 +750,7 @@ eu::Args make_args(const imexds_eu_ctx* c, int parity) {
   A.log_cnt = c->log_cnt;
   A.log_fl = c->log_fl;
   A.log_row = (c->log_cnt && c->log_row < c->log_max) ? c->log_row : -1;
+  A.zone_ppw = c->zone_ppw;
   return A;
 }
 
@@ -760,8 +767,7 @@ hipError_t launch_bulk(const eu::Args& A, int cls, int n_tiles, hipStream_t s) {
 
 hipError_t launch_zone(const eu::Args& A, int lanes, hipStream_t s) {
   if (A.P <= 0) return hipSuccess;
-  const long long threads = (long long)A.P * lanes;
-  const int blocks = (int)((threads + 63) / 64);
+  const int blocks = (A.P + A.zone_ppw - 1) / A.zone_ppw;
   if (lanes == 2)
     eu::k_eu_zone<2><<<blocks, 64, 0, s>>>(A);
   else
@@ -1054,15 +1060,19 @@ int imexds_eu_get_log(imexds_eu_ctx* c, int32_t* count, int32_t* flags, int32_t*
   return e;
 }
 
-int imexds_eu_set_launch(imexds_eu_ctx* c, int32_t tile_cells, int32_t zone_lanes) {
+int imexds_eu_set_launch(imexds_eu_ctx* c, int32_t tile_cells, int32_t zone_lanes,
+                         int32_t zone_problems_per_wave) {
   if (!c) return IMEXDS_ERR_INVALID_ARG;
   if (tile_cells != 256 && tile_cells != 512 && tile_cells != 1024)
     return IMEXDS_ERR_INVALID_ARG;
   if (zone_lanes != 1 && zone_lanes != 2) return IMEXDS_ERR_INVALID_ARG;
+  if (zone_problems_per_wave < 1 || zone_problems_per_wave * zone_lanes > 64)
+    return IMEXDS_ERR_INVALID_ARG;
   int e = hip_err(hipSetDevice(c->device));
   if (!e) e = hip_err(hipStreamSynchronize(c->ms));
   if (e) return e;
   c->zone_lanes = zone_lanes;
+  c->zone_ppw = zone_problems_per_wave;
   if (tile_cells != c->tile_class) {
     c->tile_class = tile_cells;
     e = build_tiles(c);

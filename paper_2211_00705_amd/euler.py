@@ -48,7 +48,7 @@ _get_state = _sig("imexds_eu_get_state", c_vp, c_vp, c_vp, c_vp)
 _get_problems = _sig("imexds_eu_get_problems", c_vp, P_dbl, P_i32, P_i32, P_i64)
 _enable_log = _sig("imexds_eu_enable_log", c_vp, c_i32)
 _get_log = _sig("imexds_eu_get_log", c_vp, P_i32, P_i32, P_i32)
-_set_launch = _sig("imexds_eu_set_launch", c_vp, c_i32, c_i32)
+_set_launch = _sig("imexds_eu_set_launch", c_vp, c_i32, c_i32, c_i32)
 _get_sizes = _sig("imexds_eu_get_sizes", c_vp, P_i32, P_i64)
 _time_kernels = _sig("imexds_eu_time_kernels", c_vp, c_i32)
 _last_timing = _sig("imexds_eu_last_timing", c_vp, P_dbl, P_dbl, P_dbl)
@@ -130,8 +130,9 @@ def imexds_eu_get_log(ctx, max_rows):
     return cnt[:r * P].reshape(r, P), fl[:r * P].reshape(r, P)
 
 
-def imexds_eu_set_launch(ctx, tile_cells, zone_lanes):
-    _check(_set_launch(c_vp(ctx), int(tile_cells), int(zone_lanes)), "imexds_eu_set_launch")
+def imexds_eu_set_launch(ctx, tile_cells, zone_lanes, zone_problems_per_wave):
+    _check(_set_launch(c_vp(ctx), int(tile_cells), int(zone_lanes), int(zone_problems_per_wave)),
+           "imexds_eu_set_launch")
 
 
 def imexds_eu_time_kernels(ctx, on):
@@ -196,8 +197,8 @@ class EulerIMEXDS:
     def log(self):
         return imexds_eu_get_log(self.ctx, self._log_max)
 
-    def set_launch(self, tile_cells=256, zone_lanes=2):
-        imexds_eu_set_launch(self.ctx, tile_cells, zone_lanes)
+    def set_launch(self, tile_cells=1024, zone_lanes=2, zone_problems_per_wave=32):
+        imexds_eu_set_launch(self.ctx, tile_cells, zone_lanes, zone_problems_per_wave)
 
     def time_kernels(self, on=True):
         imexds_eu_time_kernels(self.ctx, on)

@@ -12,12 +12,12 @@ from paper_2211_00705_amd import euler_workloads as EW
 pytestmark = pytest.mark.gpu
 
 
-def run_gpu(b, n_steps=None, tile=256, lanes=2, log_rows=None):
+def run_gpu(b, n_steps=None, tile=1024, lanes=2, log_rows=None, ppw=32):
     import torch
     from paper_2211_00705_amd.euler import EulerIMEXDS
     s = EulerIMEXDS(b)
     try:
-        s.set_launch(tile, lanes)
+        s.set_launch(tile, lanes, ppw)
         s.set_state()
         if log_rows:
             s.enable_log(log_rows)
@@ -82,13 +82,14 @@ def test_lax_study_to_end_time(lanes):
     assert avg[(0.9, 100, 1e-6)] > avg[(0.9, 100, 1e-2)]
 
 
-@pytest.mark.parametrize("tile,lanes", [(256, 2), (512, 1), (1024, 2)])
-def test_lax_batch_matches_oracle(tile, lanes):
+@pytest.mark.parametrize("tile,lanes,ppw", [(256, 2, 4), (512, 1, 64), (1024, 2, 32), (256, 1, 1),
+                                            (512, 2, 7)])
+def test_lax_batch_matches_oracle(tile, lanes, ppw):
     """A seeded ensemble of Lax-type tubes (N in 100..400, alpha log-uniform in
     [1e-6, 1e-2], theta_{k+-1} in {0.9, 0.1}, perturbed states), stepped 60
     times: ragged problem ends, tiles spanning problem boundaries."""
     b = EW.lax_batch(seed=5, n_problems=96)
-    g = run_gpu(b, 60, tile=tile, lanes=lanes, log_rows=60)
+    g = run_gpu(b, 60, tile=tile, lanes=lanes, log_rows=60, ppw=ppw)
     o = run_oracle(b, 60, log_rows=60)
     assert np.all(g["status"] == 0)
     assert_same(b, g, o, 60)
@@ -160,8 +161,7 @@ def test_api_errors():
     s = E.EulerIMEXDS(b)
     with pytest.raises(IMEXDSError):
         s.step(1)  # no state yet
-    with pytest.raises(IMEXDSError):
-        s.set_launch(300, 2)
-    with pytest.raises(IMEXDSError):
-        s.set_launch(256, 3)
+    for bad in ((300, 2, 4), (256, 3, 4), (256, 2, 0), (256, 2, 33), (256, 1, 65)):
+        with pytest.raises(IMEXDSError):
+            s.set_launch(*bad)
     s.close()
