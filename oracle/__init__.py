@@ -104,6 +104,11 @@ def lib():
                                               ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                               ctypes.c_int, dp, dp, ip, dp, dp, ip, ctypes.c_int,
                                               dp, dp, ip, dp]
+        L.oracle_creation_rp.restype = ctypes.c_int
+        L.oracle_creation_rp.argtypes = [ctypes.POINTER(_Mat), ctypes.c_int, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                         ctypes.c_double, dp]
         L.oracle_exp.restype = ctypes.c_double
         L.oracle_exp.argtypes = [ctypes.c_double]
         L.oracle_euler_riemann.restype = ctypes.c_int
@@ -303,6 +308,22 @@ def iface_G(material, phl, rl, ul, phr, rr, ur, psl, psr):
     if not ok:
         return None
     return o[:2].copy(), o[2:].reshape(2, 2).copy()
+
+
+CREATION_FIELDS = ("kind", "p1", "pa", "pb", "pc", "ra", "rb", "rc", "ua", "ub", "uc", "zl",
+                   "zr", "wl", "wr", "Fl0", "Fl1", "Fr0", "Fr1", "iters")
+
+
+def creation_rp(material, phase, rl, ml, rr, mr, p_min, p_tilde, maxit=50, rtol=1e-14):
+    """Phase creation for a Riemann problem of one phase: (status, dict).
+    status 0: no creation (dict['p1'] = star pressure without phase
+    transition), 1: a layer of the other phase is created (five states:
+    a | b (new phase) | c, boundaries at speeds wl, wr), -1: failure."""
+    out = np.zeros(len(CREATION_FIELDS))
+    st = lib().oracle_creation_rp(ctypes.byref(_mat(material)), int(phase), float(rl), float(ml),
+                                  float(rr), float(mr), float(p_min), float(p_tilde), int(maxit),
+                                  float(rtol), _ptr(out, ctypes.c_double))
+    return st, dict(zip(CREATION_FIELDS, out.tolist()))
 
 
 def hll(material, phase, rl, ml, rr, mr):

@@ -527,6 +527,254 @@ int oracle_iface_G(const or_material *M, int phl, real rl, real ml, int phr, rea
 }
 #endif
 
+#ifndef OR_TANGENT
+/* ------------------------------------------------------------------ */
+/* phase creation: cavitation and nucleation (Appendix, Sec. "Phase    */
+/* Creation", steps (i)-(iii) and (v))                                 */
+/* ------------------------------------------------------------------ */
+
+/* Step (i): the Riemann problem of two states of one phase without phase
+ * transition, f_l(p*) + f_r(p*) + (u_r - u_l) = 0 with the outer waves of
+ * or_wave, by Newton from the mean pressure (stopped when a step is below
+ * 1e-12 max(|p|, p_sat)); a step that would leave the phase's density range
+ * (rho* <= 0) is halved.  0 on success, 1 if no root with rho* > 0 was
+ * found. */
+static int or_single_rp(const or_material *M, const or_side *L, const or_side *R, real *ps) {
+  real du = R->u - L->u;
+  real p = 0.5 * (L->p + R->p);
+  or_seval El, Er;
+  for (int it = 0; it < 100; ++it) {
+    if (!or_wave(M, L, p, &El) || !or_wave(M, R, p, &Er)) return 1;
+    real dp = -(El.f + Er.f + du) / (El.df + Er.df);
+    if (!isfinite(dp)) return 1;
+    real pn = p + dp;
+    int k = 0;
+    while (!(or_rho_of_p(M, L->ph, pn) > 0.0) && k < 60) {
+      dp = 0.5 * dp;
+      pn = p + dp;
+      ++k;
+    }
+    if (k == 60) return 1;
+    real sc = fabs(p) > M->p0 ? fabs(p) : M->p0;
+    p = pn;
+    /* 1e-12: the wave functions of a stiff liquid carry round-off of about
+     * 1e-13 m/s, i.e. about 1e-7 Pa in p* */
+    if (fabs(dp) <= 1e-12 * sc) {
+      *ps = p;
+      return 0;
+    }
+  }
+  return 1;
+}
+
+/* Mass flux z through a phase boundary from the kinetic relation (as in
+ * or_eval_G) between the states l (left, phase phl) and r at pressures pl,
+ * pr, and dz/dpl, dz/dpr. */
+static int or_kinetic(const or_material *M, int phl, const or_seval *l, const or_seval *r,
+                      real pl, real pr, real ia2l, real ia2r, real *z, real *dzl, real *dzr) {
+  real vl = l->v, vr = r->v;
+  real pV = phl == OR_VAP ? pl : pr;
+  real q = M->tau * pV;
+  real jg = r->g - l->g;
+  real jv2 = vr * vr - vl * vl;
+  real A = 0.5 * q * jv2;
+  real C = q * jg;
+  real D = 1.0 - 4.0 * A * C;
+  if (!(D >= 0.0) || !isfinite(D)) return 0;
+  real sD = sqrt(D);
+  real isD = 1.0 / sD;
+  real zz = 2.0 * C / (1.0 + sD);
+  real dAl = q * ((vl * vl * vl) * ia2l);
+  real dAr = -(q * ((vr * vr * vr) * ia2r));
+  real dCl = -(q * vl);
+  real dCr = q * vr;
+  if (phl == OR_VAP) {
+    dAl += (0.5 * M->tau) * jv2;
+    dCl += M->tau * jg;
+  } else {
+    dAr += (0.5 * M->tau) * jv2;
+    dCr += M->tau * jg;
+  }
+  *z = zz;
+  *dzl = (dAl * zz * zz + dCl) * isD;
+  *dzr = (dAr * zz * zz + dCr) * isD;
+  return 1;
+}
+
+/* Step (ii): the Riemann problem of two states of phase `out` with a layer
+ * of the other phase created between them: outer wave, star state (a),
+ * phase boundary, new-phase state (b), phase boundary, star state (c),
+ * outer wave.  Each phase boundary obeys the mass and momentum jump
+ * conditions and the kinetic relation, as in the two-phase problem
+ * (eq. 2p_RP:ex_sys); eliminating the new phase's velocity leaves
+ *   E1 = (b - a) + z_l^2 (v_b - v_a),
+ *   E2 = (c - b) + z_r^2 (v_c - v_b),
+ *   E3 = f_L(a) + f_R(c) + z_l (v_b - v_a) + z_r (v_c - v_b) + (u_R - u_L). */
+typedef struct {
+  real E1, E2, E3, J[3][3], m2, zl, zr;
+  or_seval a, b, c;
+} or_ceval;
+
+static int or_creation_eval(const or_material *M, const or_side *L, const or_side *R,
+                            const or_side *S, real izref, real pa, real pb, real pc,
+                            or_ceval *E) {
+  if (!or_wave(M, L, pa, &E->a) || !or_wave(M, S, pb, &E->b) || !or_wave(M, R, pc, &E->c))
+    return 0;
+  real dla, dlb, drb, drc;
+  if (!or_kinetic(M, L->ph, &E->a, &E->b, pa, pb, L->ia2, S->ia2, &E->zl, &dla, &dlb)) return 0;
+  if (!or_kinetic(M, S->ph, &E->b, &E->c, pb, pc, S->ia2, R->ia2, &E->zr, &drb, &drc)) return 0;
+  real zl = E->zl, zr = E->zr;
+  real jl = E->b.v - E->a.v, jr = E->c.v - E->b.v;
+  real ea = (E->a.v * E->a.v) * L->ia2; /* -dv/dp of each state */
+  real eb = (E->b.v * E->b.v) * S->ia2;
+  real ec = (E->c.v * E->c.v) * R->ia2;
+  E->E1 = (pb - pa) + zl * zl * jl;
+  E->E2 = (pc - pb) + zr * zr * jr;
+  E->E3 = (E->a.f + E->c.f) + zl * jl + zr * jr + (R->u - L->u);
+  E->J[0][0] = -1.0 + 2.0 * zl * dla * jl + zl * zl * ea;
+  E->J[0][1] = 1.0 + 2.0 * zl * dlb * jl - zl * zl * eb;
+  E->J[0][2] = 0.0;
+  E->J[1][0] = 0.0;
+  E->J[1][1] = -1.0 + 2.0 * zr * drb * jr + zr * zr * eb;
+  E->J[1][2] = 1.0 + 2.0 * zr * drc * jr - zr * zr * ec;
+  E->J[2][0] = E->a.df + dla * jl + zl * ea;
+  E->J[2][1] = dlb * jl - zl * eb + drb * jr + zr * eb;
+  E->J[2][2] = E->c.df + drc * jr - zr * ec;
+  if (!isfinite(E->E1) || !isfinite(E->E2) || !isfinite(E->E3)) return 0;
+  real s1 = E->E1 * izref, s2 = E->E2 * izref;
+  E->m2 = s1 * s1 + s2 * s2 + E->E3 * E->E3;
+  return 1;
+}
+
+/* 3x3 linear solve by Cramer's rule; 0 if singular */
+static int or_solve3(const real J[3][3], const real *r, real *x) {
+  real c0 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+  real c1 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+  real c2 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+  real det = J[0][0] * c0 + J[0][1] * c1 + J[0][2] * c2;
+  if (!(det != 0.0) || !isfinite(det)) return 0;
+  real id = 1.0 / det;
+  for (int k = 0; k < 3; ++k) {
+    real A[3][3];
+    memcpy(A, J, sizeof(A));
+    for (int i = 0; i < 3; ++i) A[i][k] = r[i];
+    real d = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+             A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+             A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+    x[k] = d * id;
+  }
+  return 1;
+}
+
+typedef struct {
+  real kind;                 /* 0 none, 1 cavitation, 2 nucleation */
+  real p1;                   /* step (i) star pressure (0 if it has none) */
+  real pa, pb, pc;           /* star pressures: outer phase left, new phase, outer phase right */
+  real ra, rb, rc;           /* densities */
+  real ua, ub, uc;           /* velocities */
+  real zl, zr, wl, wr;       /* mass fluxes and speeds of the two phase boundaries */
+  real Fl0, Fl1, Fr0, Fr1;   /* fluxes across them (mass, momentum) */
+  real iters;
+} or_creation;
+
+/* Phase creation for one Riemann problem of phase ph (eqs. flux:cavitation,
+ * flux:nucleation): step (i), the test p* < p_min (liquid: cavitation) or
+ * p* > p_tilde (vapour: nucleation), a missing root counting as the test
+ * passed, then step (ii) by Newton-Armijo on (E1, E2, E3) from all three
+ * pressures at saturation, with the convergence rules of or_newton.
+ * Returns 0 (no creation; p1 set), 1 (creation solved) or -1 (invalid
+ * input or the solve failed). */
+static int or_creation_rp(const or_material *M, int ph, real rl, real ml, real rr, real mr,
+                          real p_min, real p_tilde, int maxit, real rtol, or_creation *out) {
+  memset(out, 0, sizeof(*out));
+  if (!(rl > 0.0) || !(rr > 0.0)) return -1;
+  or_side L, R, S;
+  or_side_init(M, ph, rl, ml, &L);
+  or_side_init(M, ph, rr, mr, &R);
+  real p1 = 0.0;
+  int none = or_single_rp(M, &L, &R, &p1);
+  out->p1 = none ? 0.0 : p1;
+  int create = none ? 1 : (ph == OR_LIQ ? p1 < p_min : p1 > p_tilde);
+  if (!create) return 0;
+  int nph = 1 - ph;
+  or_side_init(M, nph, nph == OR_VAP ? M->p0 / M->a2v : M->rhol0, 0.0, &S);
+  real zL = rl * L.a, zR = rr * R.a;
+  real izref = 1.0 / (zL > zR ? zL : zR);
+  real x[3] = {M->p0, M->p0, M->p0};
+  or_ceval E, Et;
+  if (!or_creation_eval(M, &L, &R, &S, izref, x[0], x[1], x[2], &E)) return -1;
+  int it, conv = 0;
+  for (it = 0; it < maxit && !conv; ++it) {
+    real rhs[3] = {-E.E1, -E.E2, -E.E3}, d[3];
+    if (!or_solve3(E.J, rhs, d)) return -1;
+    real sc = 0.0, st = 0.0;
+    for (int i = 0; i < 3; ++i) {
+      if (fabs(x[i]) > sc) sc = fabs(x[i]);
+      if (fabs(d[i]) > st) st = fabs(d[i]);
+    }
+    if (M->p0 > sc) sc = M->p0;
+    if (!isfinite(st)) return -1;
+    if (st <= rtol * sc) {
+      if (or_creation_eval(M, &L, &R, &S, izref, x[0] + d[0], x[1] + d[1], x[2] + d[2], &Et)) {
+        for (int i = 0; i < 3; ++i) x[i] = x[i] + d[i];
+        E = Et;
+      }
+      conv = 1;
+      break;
+    }
+    real lam = 1.0;
+    int acc = 0, k;
+    for (k = 0; k <= 20; ++k) {
+      real c = 1.0 - 1e-4 * lam;
+      if (or_creation_eval(M, &L, &R, &S, izref, x[0] + lam * d[0], x[1] + lam * d[1],
+                           x[2] + lam * d[2], &Et) &&
+          Et.m2 <= (c * c) * E.m2) {
+        for (int i = 0; i < 3; ++i) x[i] = x[i] + lam * d[i];
+        E = Et;
+        acc = 1;
+        break;
+      }
+      lam *= 0.5;
+    }
+    if (!acc) {
+      if (st <= 1e-8 * sc) conv = 1;
+      else return -1;
+      break;
+    }
+    if (k == 0 && st <= 1e-10 * sc) conv = 1;
+  }
+  if (!conv) return -1;
+  out->kind = ph == OR_LIQ ? 1.0 : 2.0;
+  out->pa = x[0];
+  out->pb = x[1];
+  out->pc = x[2];
+  out->ra = E.a.rs;
+  out->rb = E.b.rs;
+  out->rc = E.c.rs;
+  out->ua = L.u - E.a.f;
+  out->uc = R.u + E.c.f;
+  out->ub = out->ua - E.zl * (E.b.v - E.a.v);
+  out->zl = E.zl;
+  out->zr = E.zr;
+  out->wl = out->ub + E.zl * E.b.v; /* z = -rho (u - w) on the new phase's side */
+  out->wr = out->ub + E.zr * E.b.v;
+  out->Fl0 = -E.zl;
+  out->Fl1 = -E.zl * out->ub + x[1];
+  out->Fr0 = -E.zr;
+  out->Fr1 = -E.zr * out->ub + x[1];
+  out->iters = it + 1;
+  return 1;
+}
+
+int oracle_creation_rp(const or_material *M, int ph, double rl, double ml, double rr, double mr,
+                       double p_min, double p_tilde, int maxit, double rtol, double *out20) {
+  or_creation C;
+  int st = or_creation_rp(M, ph, rl, ml, rr, mr, p_min, p_tilde, maxit, rtol, &C);
+  memcpy(out20, &C, sizeof(C));
+  return st;
+}
+#endif
+
 /* ------------------------------------------------------------------ */
 /* one problem                                                         */
 /* ------------------------------------------------------------------ */
