@@ -49,6 +49,10 @@ def parse():
     ap.add_argument("--adjoint-every", type=int, default=50)
     ap.add_argument("--adjoint-problems", type=int, default=1024)
     ap.add_argument("--adjoint-zone-lanes", type=int, default=8, choices=[1, 8])
+    ap.add_argument("--creation-problems", type=int, default=1 << 20,
+                    help="single-phase Riemann problems in the phase-creation leg (0: skip)")
+    ap.add_argument("--only-creation", action="store_true",
+                    help="run only the phase-creation leg (for profiling it)")
     ap.add_argument("--only-euler", action="store_true",
                     help="run only the full-Euler leg (for profiling it)")
     ap.add_argument("--euler-problems", type=int, default=4096,
@@ -338,6 +342,46 @@ def euler_leg(args, cpu):
     return rec
 
 
+def creation_leg(args, cpu):
+    """Batched phase creation (cavitation / nucleation detection and the
+    five-state solve) on 2^20 single-phase Riemann problems, timed with HIP
+    events on the launching stream; the oracle on a sample on the host."""
+    import torch
+    from paper_2211_00705_amd import workloads as W
+    from paper_2211_00705_amd.creation import imexds_creation_rp
+    M = W.WATER_363K
+    b = W.creation_batch(M, n=args.creation_problems)
+    dev = lambda a, t=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to("cuda", t)
+    args_d = (dev(b.phase, torch.int32), dev(b.rho_l), dev(b.mom_l), dev(b.rho_r), dev(b.mom_r))
+    st, out = imexds_creation_rp(M, *args_d, W.P_MIN, W.P_TILDE)
+    torch.cuda.synchronize()
+    reps = 20
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        imexds_creation_rp(M, *args_d, W.P_MIN, W.P_TILDE, status=st, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    s = st.cpu().numpy()
+    rec = {"workload": f"creation_batch: {b.n} single-phase Riemann problems (half liquid "
+                       "pulled apart or compressed, half vapour compressed or expanded)",
+           "unit": "problems/s", "value": b.n / (ms * 1e-3), "ms_per_launch": ms,
+           "created": int(np.sum(s == 1)), "failed": int(np.sum(s < 0))}
+    if cpu:
+        import oracle
+        k = min(b.n, 1 << 18)
+        for threads in (1, max(1, min(16, os.cpu_count() or 1))):
+            t0 = time.perf_counter()
+            oracle.creation_batch(M, b.phase[:k], b.rho_l[:k], b.mom_l[:k], b.rho_r[:k],
+                                  b.mom_r[:k], W.P_MIN, W.P_TILDE, threads=threads)
+            w = time.perf_counter() - t0
+            key = "cpu_1_thread" if threads == 1 else "cpu_all_threads"
+            rec[key] = {"value": k / w, "threads": threads, "kind": "oracle",
+                        "sample": f"first {k} problems"}
+    return rec
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -359,6 +403,9 @@ def main():
 
     if args.only_euler:
         print(json.dumps({"euler_lax": euler_leg(args, not args.no_cpu)}))
+        return
+    if args.only_creation:
+        print(json.dumps({"phase_creation": creation_leg(args, not args.no_cpu)}))
         return
 
     b, P, desc = make_workload(args)
@@ -462,6 +509,8 @@ def main():
         out["other_configs"] = other_configs_leg(material, not args.no_cpu)
     if args.euler_problems > 0:
         out["euler_lax"] = euler_leg(args, not args.no_cpu)
+    if args.creation_problems > 0:
+        out["phase_creation"] = creation_leg(args, not args.no_cpu)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline_leg(b, P, material, args.steps, g_rho, g_mom, g_home,
                                                g_hl, args.cpu_seconds)

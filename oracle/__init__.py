@@ -109,6 +109,10 @@ def lib():
                                          ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                          ctypes.c_double, dp]
+        L.oracle_creation_batch.restype = None
+        L.oracle_creation_batch.argtypes = [ctypes.POINTER(_Mat), ctypes.c_int, ip, dp, dp, dp, dp,
+                                            ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                            ctypes.c_double, ip, dp, ctypes.c_int]
         L.oracle_exp.restype = ctypes.c_double
         L.oracle_exp.argtypes = [ctypes.c_double]
         L.oracle_euler_riemann.restype = ctypes.c_int
@@ -324,6 +328,22 @@ def creation_rp(material, phase, rl, ml, rr, mr, p_min, p_tilde, maxit=50, rtol=
                                   float(rr), float(mr), float(p_min), float(p_tilde), int(maxit),
                                   float(rtol), _ptr(out, ctypes.c_double))
     return st, dict(zip(CREATION_FIELDS, out.tolist()))
+
+
+def creation_batch(material, phase, rl, ml, rr, mr, p_min, p_tilde, maxit=50, rtol=1e-14,
+                   threads=1):
+    """Vectorised creation_rp: (status [n], out [n, 20]) in CREATION_FIELDS order."""
+    phase = np.ascontiguousarray(phase, dtype=np.int32)
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (rl, ml, rr, mr)]
+    n = phase.shape[0]
+    status = np.zeros(n, dtype=np.int32)
+    out = np.zeros((n, len(CREATION_FIELDS)))
+    lib().oracle_creation_batch(ctypes.byref(_mat(material)), n, _ptr(phase, ctypes.c_int),
+                                *[_ptr(a, ctypes.c_double) for a in arrs], float(p_min),
+                                float(p_tilde), int(maxit), float(rtol),
+                                _ptr(status, ctypes.c_int), _ptr(out, ctypes.c_double),
+                                int(threads))
+    return status, out
 
 
 def hll(material, phase, rl, ml, rr, mr):

@@ -536,8 +536,8 @@ int oracle_iface_G(const or_material *M, int phl, real rl, real ml, int phr, rea
 /* Step (i): the Riemann problem of two states of one phase without phase
  * transition, f_l(p*) + f_r(p*) + (u_r - u_l) = 0 with the outer waves of
  * or_wave, by Newton from the mean pressure (stopped when a step is below
- * 1e-12 max(|p|, p_sat)); a step that would leave the phase's density range
- * (rho* <= 0) is halved.  0 on success, 1 if no root with rho* > 0 was
+ * 1e-12 max(|p|, p_sat) or below 1e-13 a^2 rho(p)); a step that would leave
+ * the phase's density range (rho* <= 0) is halved.  0 on success, 1 if no root with rho* > 0 was
  * found. */
 static int or_single_rp(const or_material *M, const or_side *L, const or_side *R, real *ps) {
   real du = R->u - L->u;
@@ -557,9 +557,11 @@ static int or_single_rp(const or_material *M, const or_side *L, const or_side *R
     if (k == 60) return 1;
     real sc = fabs(p) > M->p0 ? fabs(p) : M->p0;
     p = pn;
-    /* 1e-12: the wave functions of a stiff liquid carry round-off of about
-     * 1e-13 m/s, i.e. about 1e-7 Pa in p* */
-    if (fabs(dp) <= 1e-12 * sc) {
+    /* converged when the step is below 1e-12 of the pressure scale or below
+     * 1e-13 of the density it implies: a stiff liquid resolves its density
+     * only to 1e-16 relative, i.e. p* to about 1e-7 Pa (a step test on p
+     * alone never passes for |p*| below about 1e5 Pa) */
+    if (fabs(dp) <= 1e-12 * sc || fabs(dp) <= 1e-13 * (or_a2(M, L->ph) * or_rho_of_p(M, L->ph, p))) {
       *ps = p;
       return 0;
     }
@@ -772,6 +774,17 @@ int oracle_creation_rp(const or_material *M, int ph, double rl, double ml, doubl
   int st = or_creation_rp(M, ph, rl, ml, rr, mr, p_min, p_tilde, maxit, rtol, &C);
   memcpy(out20, &C, sizeof(C));
   return st;
+}
+
+/* n independent problems (threads over problems); out is [n][20] */
+void oracle_creation_batch(const or_material *M, int n, const int *ph, const double *rl,
+                           const double *ml, const double *rr, const double *mr, double p_min,
+                           double p_tilde, int maxit, double rtol, int *status, double *out,
+                           int n_threads) {
+#pragma omp parallel for schedule(dynamic, 64) num_threads(n_threads > 0 ? n_threads : 1)
+  for (int j = 0; j < n; ++j)
+    status[j] = oracle_creation_rp(M, ph[j], rl[j], ml[j], rr[j], mr[j], p_min, p_tilde, maxit,
+                                   rtol, out + (size_t)j * 20);
 }
 #endif
 

@@ -1,0 +1,48 @@
+"""ctypes binding of imexds_creation_rp (include/imexds_creation.h): argument
+marshalling only.  Inputs and outputs are contiguous torch tensors on cuda;
+there is no CPU fallback."""
+from __future__ import annotations
+
+import ctypes
+
+from . import imexds as _base
+
+_L = _base._L
+c_i32, c_dbl, c_vp = _base.c_i32, _base.c_dbl, _base.c_vp
+
+FIELDS = ("kind", "p1", "pa", "pb", "pc", "ra", "rb", "rc", "ua", "ub", "uc", "zl", "zr", "wl",
+          "wr", "Fl0", "Fl1", "Fr0", "Fr1", "iters")
+
+_creation = getattr(_L, "imexds_creation_rp")
+_creation.restype = c_i32
+_creation.argtypes = [ctypes.POINTER(_base.imexds_material), c_i32, c_vp, c_vp, c_vp, c_vp, c_vp,
+                      c_dbl, c_dbl, c_i32, c_dbl, c_vp, c_vp, c_vp]
+
+EXPORTED = ["imexds_creation_rp"]
+
+
+def _dev(x, dtype):
+    import torch
+    if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype != dtype or not x.is_contiguous():
+        raise ValueError(f"expected a contiguous {dtype} tensor on the GPU")
+    return c_vp(x.data_ptr())
+
+
+def imexds_creation_rp(material, phase, rho_l, mom_l, rho_r, mom_r, p_min, p_tilde, maxit=50,
+                       rtol=1e-14, status=None, out=None, stream=None):
+    """Returns (status int32 [n], out float64 [n, 20]) as cuda tensors."""
+    import torch
+    n = int(phase.shape[0])
+    if status is None:
+        status = torch.empty(n, dtype=torch.int32, device="cuda")
+    if out is None:
+        out = torch.empty((n, len(FIELDS)), dtype=torch.float64, device="cuda")
+    m = _base.imexds_material(material.a2v, material.a2l, material.p0, material.rhol0,
+                              material.tau)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    d = torch.float64
+    _base._check(_creation(ctypes.byref(m), n, _dev(phase, torch.int32), _dev(rho_l, d),
+                           _dev(mom_l, d), _dev(rho_r, d), _dev(mom_r, d), float(p_min),
+                           float(p_tilde), int(maxit), float(rtol), _dev(status, torch.int32),
+                           _dev(out, d), c_vp(s.cuda_stream)), "imexds_creation_rp")
+    return status, out

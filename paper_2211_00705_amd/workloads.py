@@ -382,3 +382,57 @@ def single_phase_problem(n, rho_fn, u_fn, phase=LIQ, length=1.0):
         return rho_fn(x), u_fn(x)
 
     return _assemble([n], [h], [0.0], [phase], [[]], [[]], [st], name="single_phase")
+
+
+# ---------------------------------------------------------------------------
+# single-phase Riemann problems for phase creation (cavitation, nucleation)
+# ---------------------------------------------------------------------------
+
+# creation thresholds at 363.15 K (Sec. 5, table of the maximum vapour
+# pressure and the minimum liquid pressure)
+P_MIN = 0.0
+P_TILDE = 70388.660656
+
+
+@dataclass
+class CreationBatch:
+    phase: np.ndarray  # int32 [n]: 0 liquid, 1 vapour (both states)
+    rho_l: np.ndarray
+    mom_l: np.ndarray
+    rho_r: np.ndarray
+    mom_r: np.ndarray
+    name: str = "creation"
+
+    @property
+    def n(self) -> int:
+        return int(self.phase.shape[0])
+
+
+def _rho_of_p(material, ph, p):
+    p = np.asarray(p, dtype=np.float64)
+    return p / material.a2v if ph == VAP else material.rhol0 + (p - material.p0) / material.a2l
+
+
+def creation_problem(material, phase, pl, ul, pr, ur):
+    """One problem from pressures and velocities (the Sec. 5 tests: liquid
+    60000 Pa at -/+4 m/s, vapour 70000 Pa at +/-2.7 m/s)."""
+    rl, rr = _rho_of_p(material, phase, pl), _rho_of_p(material, phase, pr)
+    return CreationBatch(np.array([phase], np.int32), np.array([rl]), np.array([rl * ul]),
+                         np.array([rr]), np.array([rr * ur]), name="creation_problem")
+
+
+def creation_batch(material, seed=20261202, n=1 << 20):
+    """Single-phase Riemann problems around the paper's two creation tests:
+    half liquid (p ~ U[2e4, 1e5] Pa on each side, u_l, u_r ~ U[-3, 3] m/s:
+    pulled apart and cavitating, or compressed), half vapour
+    (p ~ U[6.9e4, 7.035e4] Pa, u_l ~ U[-2, 8], u_r ~ U[-8, 2]: compressed,
+    nucleating when hard enough, or expanding), phases interleaved."""
+    rng = np.random.default_rng(seed)
+    ph = (np.arange(n) & 1).astype(np.int32)
+    pl = np.where(ph == LIQ, rng.uniform(2e4, 1e5, n), rng.uniform(6.9e4, 7.035e4, n))
+    pr = np.where(ph == LIQ, rng.uniform(2e4, 1e5, n), rng.uniform(6.9e4, 7.035e4, n))
+    ul = np.where(ph == LIQ, rng.uniform(-3.0, 3.0, n), rng.uniform(-2.0, 8.0, n))
+    ur = np.where(ph == LIQ, rng.uniform(-3.0, 3.0, n), rng.uniform(-8.0, 2.0, n))
+    rl = np.where(ph == LIQ, _rho_of_p(material, LIQ, pl), _rho_of_p(material, VAP, pl))
+    rr = np.where(ph == LIQ, _rho_of_p(material, LIQ, pr), _rho_of_p(material, VAP, pr))
+    return CreationBatch(ph, rl, rl * ul, rr, rr * ur, name=f"creation_batch_n{n}_seed{seed}")

@@ -9,6 +9,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HDR = os.path.join(ROOT, "include", "imexds.h")
 HDR_EU = os.path.join(ROOT, "include", "imexds_euler.h")
+HDR_CR = os.path.join(ROOT, "include", "imexds_creation.h")
 LIB = os.path.join(ROOT, "paper_2211_00705_amd", "libimexds.so")
 
 
@@ -27,13 +28,14 @@ def test_header_declares_the_entry_points():
                  "imexds_eu_get_state", "imexds_eu_get_problems", "imexds_eu_destroy"):
         assert name in d
     assert not set(d) & set(declared())
+    assert declared(HDR_CR) == ["imexds_creation_rp"]
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
 def test_library_exports_every_declared_symbol():
     out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
     syms = set(l.split()[-1] for l in out.splitlines() if l.strip())
-    missing = [n for n in declared() + declared(HDR_EU) if n not in syms]
+    missing = [n for n in declared() + declared(HDR_EU) + declared(HDR_CR) if n not in syms]
     assert not missing, missing
 
 
@@ -45,6 +47,8 @@ def test_binding_loads_and_maps_every_symbol():
     assert imexds.imexds_strerror(0) == "ok"
     from paper_2211_00705_amd import euler
     assert sorted(euler.EXPORTED) == declared(HDR_EU)
+    from paper_2211_00705_amd import creation
+    assert sorted(creation.EXPORTED) == declared(HDR_CR)
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")

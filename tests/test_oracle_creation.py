@@ -90,6 +90,20 @@ def test_single_phase_problem_closed_forms():
     assert solve(W.VAP, 60000.0, 2.0, 60000.0, -2.0)[0] == 0
 
 
+@pytest.mark.parametrize("p_star", [5000.0, 1.0, -1.0, -5000.0])
+def test_step_i_decides_near_p_min(p_star):
+    """Symmetric rarefactions built to reach a given star pressure near
+    p_min = 0: the single-phase solve must converge there (the liquid
+    resolves p* only to about 1e-7 Pa) and decide by the sign."""
+    a = math.sqrt(M.a2l)
+    r = rho(W.LIQ, 60000.0)
+    r_star = rho(W.LIQ, p_star)
+    du = 2.0 * a * math.log(r / r_star)
+    st, d = solve(W.LIQ, 60000.0, -0.5 * du, 60000.0, 0.5 * du)
+    assert d["p1"] == pytest.approx(p_star, abs=1e-3)
+    assert st == (1 if p_star < P_MIN else 0)
+
+
 def _textbook_f(ph, r, r_star):
     """Velocity change across an isothermal wave of p = a^2 rho + const."""
     a = math.sqrt(M.a2v if ph == W.VAP else M.a2l)
