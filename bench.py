@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--adjoint-every", type=int, default=50)
     ap.add_argument("--adjoint-problems", type=int, default=1024)
     ap.add_argument("--adjoint-zone-lanes", type=int, default=8, choices=[1, 8])
+    ap.add_argument("--copy-bw", type=int, default=1,
+                    help="measure a plain 1 GiB device copy as the practical HBM ceiling")
     ap.add_argument("--creation-problems", type=int, default=1 << 20,
                     help="single-phase Riemann problems in the phase-creation leg (0: skip)")
     ap.add_argument("--only-creation", action="store_true",
@@ -382,6 +384,28 @@ def creation_leg(args, cpu):
     return rec
 
 
+def measure_copy_bandwidth(mib=1024, reps=20):
+    """Read+write bandwidth of a plain device-to-device copy (torch copy_) of
+    `mib` MiB: the practical HBM ceiling the sweep's roofline is read against."""
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * n * 8 / (ms * 1e-3) / 1e9
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -408,6 +432,8 @@ def main():
         print(json.dumps({"phase_creation": creation_leg(args, not args.no_cpu)}))
         return
 
+    # practical HBM ceiling (after the copy the traffic calibration counts on)
+    copy_gbs = measure_copy_bandwidth() if args.copy_bw else None
     b, P, desc = make_workload(args)
     s = I.IMEXDS(b, material, P)
     rho0 = torch.from_numpy(np.ascontiguousarray(b.rho)).cuda()
@@ -498,7 +524,9 @@ def main():
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "k_bulk", "bulk_ms_per_launch": bulk_ms,
                      "bulk_launches_timed": args.roofline_steps,
-                     "algorithmic_bytes_per_launch": bulk_bytes},
+                     "algorithmic_bytes_per_launch": bulk_bytes,
+                     "copy_GBs_measured": copy_gbs,
+                     "frac_of_copy": (achieved / copy_gbs) if (achieved and copy_gbs) else None},
         "step_roofline_frac": value / (HBM_PEAK_GBS * 1e9 / BYTES_PER_CELL_UPDATE),
     }
     if args.adjoint_steps > 0:

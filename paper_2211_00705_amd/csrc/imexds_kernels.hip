@@ -220,11 +220,16 @@ __global__ __launch_bounds__(64) void k_zone(StepArgs A, int if_begin, int if_en
 #pragma unroll
   for (int i = 0; i < MC; ++i) Ur[i] = Um[i] = W0[i] = W1[i] = 0.0;
   int stage = S_FETCH;
+  // first zone: the lane's own index in the grid; then the counter
+  const int g_self = (int)blockIdx.x * A.zones_per_group + (int)threadIdx.x;
+  const int g_all = (int)gridDim.x * A.zones_per_group;
+  bool first = true;
 
   for (;;) {
     // ---------------- fetch a zone that needs work ----------------
     while (stage == S_FETCH) {
-      k = if_begin + atomicAdd(A.zone_ctr, 1);
+      k = if_begin + (first ? g_self : g_all + atomicAdd(A.zone_ctr, 1));
+      first = false;
       if (k >= if_end) {
         stage = S_EXIT;
         break;

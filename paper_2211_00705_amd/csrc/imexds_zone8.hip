@@ -90,12 +90,19 @@ __global__ __launch_bounds__(64) void k_zone8(StepArgs A, int if_begin, int if_e
   double tol = 0.0;
   int ph = 0;
   int stage = S_FETCH;
+  // the first zone of a group is its own index in the grid, further ones come
+  // from the counter: 4096 groups pulling from one address at once would
+  // queue behind each other for tens of microseconds
+  const int g_self = (int)blockIdx.x * gpw + (lane >> 3);
+  const int g_all = (int)gridDim.x * gpw;
+  bool first = true;
 
   for (;;) {
     // ---------------- fetch a zone ----------------
     while (stage == S_FETCH) {
       int t = 0;
-      if (c == 0) t = atomicAdd(A.zone_ctr, 1);
+      if (c == 0) t = first ? g_self : g_all + atomicAdd(A.zone_ctr, 1);
+      first = false;
       k = if_begin + z8_geti(t, gb, 0);
       if (k >= if_end) {
         stage = S_EXIT;
