@@ -134,26 +134,16 @@ def lax_tube(N=100, alpha=1e-2, theta_nb=0.9, theta_k=None, **kw):
     return _concat([lax_spec(N, alpha, theta_nb, theta_k, **kw)], name=f"lax_N{N}_a{alpha:g}")
 
 
-# entries of the paper's table of average dual time iterations (Sec. 5,
-# Lax shock tube): (theta_{k+-1}, N, alpha) -> printed average; theta_{k+-1}
-# given as None means theta_{k+-1} = alpha
-LAX_TABLE = {
-    (0.9, 100, 1e-2): 16, (0.9, 100, 1e-4): 35, (0.9, 100, 1e-6): 57,
-    (0.9, 200, 1e-2): 14, (0.9, 200, 1e-4): 32, (0.9, 200, 1e-6): 51,
-    (0.9, 400, 1e-2): 13, (0.9, 400, 1e-4): 30, (0.9, 400, 1e-6): 47,
-    (0.1, 100, 1e-2): 48, (0.1, 100, 1e-4): 59, (0.1, 100, 1e-6): 97,
-    (0.1, 200, 1e-2): 38, (0.1, 200, 1e-4): 51, (0.1, 200, 1e-6): 90,
-    (0.1, 400, 1e-2): 29, (0.1, 400, 1e-4): 44, (0.1, 400, 1e-6): 81,
-    (None, 100, 1e-2): 439, (None, 100, 1e-4): 43470,
-    (None, 200, 1e-2): 347, (None, 200, 1e-4): 34356,
-    (None, 400, 1e-2): 246, (None, 400, 1e-4): 24178,
-    (None, 100, 1e-5): 434663, (None, 200, 1e-5): 343526, (None, 400, 1e-5): 241731,
-}
+# the configurations of the paper's table of average dual time iterations
+# (Sec. 5, Lax shock tube): (theta_{k+-1}, N, alpha), theta_{k+-1} = None
+# meaning theta_{k+-1} = alpha
+LAX_STUDY = ([(th, N, a) for th in (0.9, 0.1) for N in (100, 200, 400) for a in (1e-2, 1e-4, 1e-6)]
+             + [(None, N, a) for N in (100, 200, 400) for a in (1e-2, 1e-4, 1e-5)])
 
 
 def lax_study(entries=None):
-    """One problem per entry (theta_nb, N, alpha) of the table above."""
-    entries = list(LAX_TABLE) if entries is None else list(entries)
+    """One problem per configuration (theta_nb, N, alpha), LAX_STUDY by default."""
+    entries = list(LAX_STUDY) if entries is None else list(entries)
     specs = [lax_spec(N, a, a if th is None else th) for th, N, a in entries]
     return _concat(specs, name="lax_study", meta={"entries": entries})
 

@@ -70,7 +70,7 @@ def assert_same(b, g, o, rows=None):
 def test_lax_study_to_end_time(lanes):
     """The paper's Lax tube configurations (theta_{k+-1} = 0.9, 0.1 with
     alpha down to 1e-6, and theta_{k+-1} = alpha = 1e-2) run to t_end = 1."""
-    entries = [e for e in EW.LAX_TABLE if e[0] is not None] + [(None, N, 1e-2)
+    entries = [e for e in EW.LAX_STUDY if e[0] is not None] + [(None, N, 1e-2)
                                                                  for N in (100, 200, 400)]
     b = EW.lax_study(entries)
     rows = 240
