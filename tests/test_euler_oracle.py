@@ -304,3 +304,18 @@ def test_failures_are_flagged():
     st = oracle.EulerState(b)
     lc, lf = oracle.euler_run(st, 5, log=True)
     assert st.status[0] == oracle.EU_ST_NONPHYS and st.steps[0] == 0 and lc[0, 0] == 4
+
+
+def test_input_generators_are_seeded_and_shaped():
+    a, b = EW.lax_batch(seed=11, n_problems=40), EW.lax_batch(seed=11, n_problems=40)
+    assert all(np.array_equal(getattr(a, f), getattr(b, f)) for f in ("N", "alpha", "rho", "ene"))
+    assert a.n_cells == int(np.sum(a.N + 1)) and set(a.N.tolist()) <= {100, 200, 400}
+    assert np.all((a.alpha >= 1e-6) & (a.alpha <= 1e-2)) and np.all(a.theta_k == a.alpha)
+    t = EW.lax_tube(100, 1e-3, 0.9)
+    k = 50
+    assert np.all(t.rho[:k] == EW.LAX_LEFT[0]) and np.all(t.rho[k:] == EW.LAX_RIGHT[0])
+    from paper_2211_00705_amd import workloads as W
+    c1 = W.creation_batch(W.WATER_363K, seed=4, n=1000)
+    c2 = W.creation_batch(W.WATER_363K, seed=4, n=1000)
+    assert np.array_equal(c1.rho_l, c2.rho_l) and np.array_equal(c1.phase, np.arange(1000) & 1)
+    assert np.all(c1.rho_l > 0) and np.all(c1.rho_r > 0)
