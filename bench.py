@@ -281,6 +281,15 @@ def other_configs_leg(material, cpu):
     return out
 
 
+# FP64 lane operations executed per unit of work (rocprofv3 SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64,
+# FMA counted twice, x 64 lanes, so lanes idled by divergence count too), per run of the
+# profiled workloads divided by the units of that run (profiles/ and DESIGN)
+EU_ZONE_FLOP_PER_TUBE_ITER = 8989.0  # k_eu_zone: per tube and dual time iteration
+EU_BULK_FLOP_PER_FACE = 1343.0       # k_eu_bulk: per face of a tube still running
+CR_FLOP_PER_PROBLEM = 2460.0         # k_cr_detect + k_cr_solve per problem of creation_batch
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
 def euler_leg(args, cpu):
     """Full-Euler Lax-tube ensemble (Sec. 5 first test, batched): 4096 tubes
     run to t_end = 1 on the GPU with per-launch HIP events, and (cpu) the
@@ -315,11 +324,17 @@ def euler_leg(args, cpu):
         cu = float(np.sum(cells * steps))
         s.set_state()
         s.time_kernels(True)
-        s.run(1 << 20, 64)
+        n_timed = s.run(1 << 20, 64)
         bulk_ms, zone_ms, step_ms = s.last_timing()
         s.time_kernels(False)
+        _, _, steps_t, iters_t = s.problems()
     finally:
         s.close()
+    # dominant kernel: the dual time kernel, one dependent chain per tube
+    tube_iters_per_launch = float(np.sum(iters_t)) / max(1, n_timed)
+    zone_tflops = EU_ZONE_FLOP_PER_TUBE_ITER * tube_iters_per_launch / (zone_ms * 1e-3) / 1e12
+    faces_per_launch = float(np.sum((cells + 1) * steps_t)) / max(1, n_timed)
+    bulk_tflops = EU_BULK_FLOP_PER_FACE * faces_per_launch / (bulk_ms * 1e-3) / 1e12
     rec = {"workload": f"lax_batch: {b.n_problems} Lax-type tubes, N in {{100,200,400}} "
                        f"({b.n_cells} cells), alpha logU[1e-6,1e-2], theta_nb in {{0.9,0.1}}, "
                        "states scaled by up to 25%, run to t_end = 1",
@@ -329,7 +344,19 @@ def euler_leg(args, cpu):
            "failed_problems": int(np.sum(st != 0)),
            "mean_dual_time_iterations": float(np.sum(iters) / max(1, np.sum(steps))),
            "bulk_ms_per_launch": bulk_ms, "zone_ms_per_launch": zone_ms,
-           "step_ms": step_ms}
+           "step_ms": step_ms,
+           "roofline": {"bound": "alu", "kernel": "k_eu_zone", "achieved": zone_tflops,
+                        "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": zone_tflops / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                        "per_unit": f"{EU_ZONE_FLOP_PER_TUBE_ITER:.0f} FP64 ops per tube and "
+                                    "dual time iteration",
+                        "units_per_launch": tube_iters_per_launch,
+                        "note": "one dependent FP64 chain per tube: latency, not the ALU "
+                                "peak, bounds it"},
+           "bulk_roofline": {"bound": "alu", "kernel": "k_eu_bulk", "achieved": bulk_tflops,
+                             "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                             "frac": bulk_tflops / FP64_VECTOR_PEAK_TFLOPS,
+                             "per_unit": f"{EU_BULK_FLOP_PER_FACE:.0f} FP64 ops per face"}}
     if cpu:
         import oracle
         sub = b.subset(list(range(0, b.n_problems, max(1, b.n_problems // 64))))
@@ -370,6 +397,11 @@ def creation_leg(args, cpu):
                        "pulled apart or compressed, half vapour compressed or expanded)",
            "unit": "problems/s", "value": b.n / (ms * 1e-3), "ms_per_launch": ms,
            "created": int(np.sum(s == 1)), "failed": int(np.sum(s < 0))}
+    tf = CR_FLOP_PER_PROBLEM * b.n / (ms * 1e-3) / 1e12
+    rec["roofline"] = {"bound": "alu", "kernel": "k_cr_detect + k_cr_solve (one call)",
+                       "achieved": tf, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                       "frac": tf / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                       "per_unit": f"{CR_FLOP_PER_PROBLEM:.0f} FP64 ops per problem"}
     if cpu:
         import oracle
         k = min(b.n, 1 << 18)

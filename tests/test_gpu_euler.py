@@ -165,3 +165,17 @@ def test_api_errors():
         with pytest.raises(IMEXDSError):
             s.set_launch(*bad)
     s.close()
+
+
+@pytest.mark.parametrize("gamma", [5.0 / 3.0, 1.2])
+def test_other_gases_match_oracle(gamma):
+    """Other ratios of specific heats change every exponent of the exact
+    Riemann solver ((gamma-1)/(2 gamma), 1/gamma, 2/(gamma-1), ...)."""
+    rng = np.random.default_rng(17)
+    specs = [EW.lax_spec(int(rng.choice([20, 64, 100])), float(10 ** rng.uniform(-5, -2)),
+                         float(rng.choice([0.9, 0.3])), t_end=0.4) for _ in range(24)]
+    b = EW._concat(specs, f"gamma_{gamma:.3f}", gamma=gamma)
+    g = run_gpu(b, log_rows=80)
+    o = run_oracle(b, log_rows=80)
+    assert np.all(g["status"] == 0) and np.all(g["t"] == 0.4)
+    assert_same(b, g, o, 80)
