@@ -57,6 +57,7 @@ def parse():
                     help="run only the phase-creation leg (for profiling it)")
     ap.add_argument("--only-euler", action="store_true",
                     help="run only the full-Euler leg (for profiling it)")
+    ap.add_argument("--per-problem-steps-euler", type=int, default=3)
     ap.add_argument("--euler-problems", type=int, default=4096,
                     help="tubes in the full-Euler Lax ensemble leg (0: skip)")
     ap.add_argument("--other-configs", type=int, default=1,
@@ -322,6 +323,15 @@ def euler_leg(args, cpu):
         wall = time.perf_counter() - t0
         t, st, steps, iters = s.problems()
         cu = float(np.sum(cells * steps))
+        # the unbatched form on the first steps: every problem's kernels in turn
+        s.set_state()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step_per_problem(args.per_problem_steps_euler)
+        torch.cuda.synchronize()
+        pp_wall = time.perf_counter() - t0
+        _, _, steps_pp, _ = s.problems()
+        pp_value = float(np.sum(cells * steps_pp)) / pp_wall
         s.set_state()
         s.time_kernels(True)
         n_timed = s.run(1 << 20, 64)
@@ -345,6 +355,9 @@ def euler_leg(args, cpu):
            "mean_dual_time_iterations": float(np.sum(iters) / max(1, np.sum(steps))),
            "bulk_ms_per_launch": bulk_ms, "zone_ms_per_launch": zone_ms,
            "step_ms": step_ms,
+           "per_problem": {"value": pp_value, "unit": "cell-updates/s",
+                           "steps": args.per_problem_steps_euler,
+                           "batched_speedup": (cu / wall) / pp_value},
            "roofline": {"bound": "alu", "kernel": "k_eu_zone", "achieved": zone_tflops,
                         "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                         "frac": zone_tflops / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,

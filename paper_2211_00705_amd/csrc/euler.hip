@@ -607,6 +607,7 @@ struct imexds_eu_ctx {
   long long ncell = 0;
   std::vector<int> h_N;
   std::vector<long long> h_off;
+  std::vector<int> h_tile_first;  // [P + 1] first tile of each problem
   // device
   long long* off = nullptr;
   int *N = nullptr, *clipped = nullptr, *status = nullptr, *steps = nullptr, *cnt = nullptr,
@@ -690,7 +691,9 @@ int build_tiles(imexds_eu_ctx* c) {
   dfree(c->tile_len);
   const int T = tile_cells_of(c->tile_class);
   std::vector<int> tp, ts, tl;
+  c->h_tile_first.assign(c->P + 1, 0);
   for (int p = 0; p < c->P; ++p) {
+    c->h_tile_first[p] = (int)tp.size();
     const int n = c->h_N[p] + 1;
     for (int s = 0; s < n; s += T) {
       tp.push_back(p);
@@ -699,6 +702,7 @@ int build_tiles(imexds_eu_ctx* c) {
     }
   }
   c->n_tiles = (int)tp.size();
+  c->h_tile_first[c->P] = c->n_tiles;
   int e = dalloc(&c->tile_prob, tp.size());
   if (!e) e = dalloc(&c->tile_start, ts.size());
   if (!e) e = dalloc(&c->tile_len, tl.size());
@@ -754,12 +758,13 @@ eu::Args make_args(const imexds_eu_ctx* c, int parity) {
   return A;
 }
 
-hipError_t launch_bulk(const eu::Args& A, int cls, int n_tiles, hipStream_t s) {
+hipError_t launch_bulk(const eu::Args& A, int cls, int n_tiles, hipStream_t s,
+                       int tile_begin = 0) {
   if (n_tiles <= 0) return hipSuccess;
   switch (cls) {
-    case 256: eu::k_eu_bulk<1><<<n_tiles, 256, 0, s>>>(A, 0); break;
-    case 512: eu::k_eu_bulk<2><<<n_tiles, 256, 0, s>>>(A, 0); break;
-    case 1024: eu::k_eu_bulk<4><<<n_tiles, 256, 0, s>>>(A, 0); break;
+    case 256: eu::k_eu_bulk<1><<<n_tiles, 256, 0, s>>>(A, tile_begin); break;
+    case 512: eu::k_eu_bulk<2><<<n_tiles, 256, 0, s>>>(A, tile_begin); break;
+    case 1024: eu::k_eu_bulk<4><<<n_tiles, 256, 0, s>>>(A, tile_begin); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -835,6 +840,52 @@ int one_step(imexds_eu_ctx* c) {
   if (!e && tm) e = hip_err(hipEventRecord(te, c->ms));
   if (e) return e;
   if (tm) c->timed_steps += 1;
+  c->cur ^= 1;
+  c->log_row += 1;
+  return 0;
+}
+
+// The arguments of problem p alone: per-problem arrays shifted to p, one
+// problem, no log (the cell arrays and the tile table stay global).
+eu::Args problem_args(const eu::Args& A, int p) {
+  eu::Args B = A;
+  B.P = 1;
+  B.off += p;
+  B.N += p;
+  B.h += p;
+  B.alpha += p;
+  B.thnb += p;
+  B.thk += p;
+  B.cfl += p;
+  B.tend += p;
+  B.t += p;
+  B.dt += p;
+  B.dtr += p;
+  B.clipped += p;
+  B.status += p;
+  B.steps += p;
+  B.iters += p;
+  B.cnt += p;
+  B.fail += p;
+  B.S += p;
+  B.log_cnt = nullptr;
+  B.log_fl = nullptr;
+  B.log_row = -1;
+  return B;
+}
+
+// One step launched problem by problem on the main stream: the unbatched form.
+int one_step_per_problem(imexds_eu_ctx* c) {
+  eu::Args A = make_args(c, c->cur);
+  int e = 0;
+  for (int p = 0; p < c->P && !e; ++p) {
+    const eu::Args B = problem_args(A, p);
+    const int t0 = c->h_tile_first[p], nt = c->h_tile_first[p + 1] - t0;
+    e = hip_err(launch_bulk(A, c->tile_class, nt, c->ms, t0));
+    if (!e) e = hip_err(launch_zone(B, c->zone_lanes, c->ms));
+    if (!e) e = hip_err(launch_fin(B, 0, c->ms));
+  }
+  if (e) return e;
   c->cur ^= 1;
   c->log_row += 1;
   return 0;
@@ -964,6 +1015,15 @@ int imexds_eu_step(imexds_eu_ctx* c, int32_t n_steps) {
   if (!c->have_state) return IMEXDS_ERR_NO_STATE;
   int e = enter(c);
   for (int i = 0; i < n_steps && !e; ++i) e = one_step(c);
+  if (!e) e = leave(c);
+  return e;
+}
+
+int imexds_eu_step_per_problem(imexds_eu_ctx* c, int32_t n_steps) {
+  if (!c || n_steps < 0) return IMEXDS_ERR_INVALID_ARG;
+  if (!c->have_state) return IMEXDS_ERR_NO_STATE;
+  int e = enter(c);
+  for (int i = 0; i < n_steps && !e; ++i) e = one_step_per_problem(c);
   if (!e) e = leave(c);
   return e;
 }

@@ -44,6 +44,7 @@ _create = _sig("imexds_eu_create", ctypes.POINTER(c_vp), ctypes.POINTER(imexds_e
 _set_state = _sig("imexds_eu_set_state", c_vp, c_vp, c_vp, c_vp)
 _step = _sig("imexds_eu_step", c_vp, c_i32)
 _run = _sig("imexds_eu_run", c_vp, c_i32, c_i32, P_i32)
+_step_pp = _sig("imexds_eu_step_per_problem", c_vp, c_i32)
 _get_state = _sig("imexds_eu_get_state", c_vp, c_vp, c_vp, c_vp)
 _get_problems = _sig("imexds_eu_get_problems", c_vp, P_dbl, P_i32, P_i32, P_i64)
 _enable_log = _sig("imexds_eu_enable_log", c_vp, c_i32)
@@ -55,7 +56,8 @@ _last_timing = _sig("imexds_eu_last_timing", c_vp, P_dbl, P_dbl, P_dbl)
 _L.imexds_eu_destroy.restype = None
 _L.imexds_eu_destroy.argtypes = [c_vp]
 
-EXPORTED = ["imexds_eu_create", "imexds_eu_set_state", "imexds_eu_step", "imexds_eu_run",
+EXPORTED = ["imexds_eu_create", "imexds_eu_set_state", "imexds_eu_step",
+            "imexds_eu_step_per_problem", "imexds_eu_run",
             "imexds_eu_get_state", "imexds_eu_get_problems", "imexds_eu_enable_log",
             "imexds_eu_get_log", "imexds_eu_set_launch", "imexds_eu_get_sizes",
             "imexds_eu_time_kernels", "imexds_eu_last_timing", "imexds_eu_destroy"]
@@ -83,6 +85,10 @@ def imexds_eu_set_state(ctx, rho, mom, ene):
 
 def imexds_eu_step(ctx, n_steps):
     _check(_step(c_vp(ctx), int(n_steps)), "imexds_eu_step")
+
+
+def imexds_eu_step_per_problem(ctx, n_steps):
+    _check(_step_pp(c_vp(ctx), int(n_steps)), "imexds_eu_step_per_problem")
 
 
 def imexds_eu_run(ctx, max_steps, check_every=64):
@@ -172,6 +178,9 @@ class EulerIMEXDS:
 
     def step(self, n):
         imexds_eu_step(self.ctx, n)
+
+    def step_per_problem(self, n):
+        imexds_eu_step_per_problem(self.ctx, n)
 
     def run(self, max_steps=1 << 30, check_every=64):
         return imexds_eu_run(self.ctx, max_steps, check_every)

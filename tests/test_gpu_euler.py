@@ -179,3 +179,25 @@ def test_other_gases_match_oracle(gamma):
     o = run_oracle(b, log_rows=80)
     assert np.all(g["status"] == 0) and np.all(g["t"] == 0.4)
     assert_same(b, g, o, 80)
+
+
+def test_per_problem_launches_match_batched():
+    """The unbatched form (sweep, dual time kernel and bookkeeping launched
+    problem by problem) gives the batched results bit for bit."""
+    import torch
+    from paper_2211_00705_amd.euler import EulerIMEXDS
+    b = EW.lax_batch(seed=9, n_problems=24)
+    out = []
+    for per_problem in (False, True):
+        s = EulerIMEXDS(b)
+        s.set_state()
+        if per_problem:
+            s.step_per_problem(40)
+        else:
+            s.step(40)
+        torch.cuda.synchronize()
+        out.append((s.state_numpy(), s.problems()))
+        s.close()
+    (sa, pa), (sb, pb) = out
+    for x, y in zip(sa + tuple(pa), sb + tuple(pb)):
+        assert np.array_equal(x, y)
