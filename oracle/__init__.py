@@ -122,6 +122,11 @@ def lib():
                                        + [ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                           ctypes.c_int, dp, dp, dp, dp, ip, ip, lp, ctypes.c_int,
                                           ip, ip, ctypes.c_int])
+        L.oracle_ct_run.restype = ctypes.c_int
+        L.oracle_ct_run.argtypes = ([ctypes.POINTER(_Mat), ctypes.POINTER(_Par), ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_int, ip, dp, ip, lp, dp, dp, ip,
+                                     dp, dp, dp, dp, ip, ip, lp, ctypes.c_int, ip, ip,
+                                     ctypes.c_int])
         _lib = L
     return _lib
 
@@ -440,6 +445,65 @@ def euler_run(state, n_steps=None, threads=1, log=False):
                            _ptr(state.iters, l), int(n_steps),
                            _ptr(lc, i) if log else None, _ptr(lf, i) if log else None,
                            int(threads))
+    if log:
+        return lc, lf
+    return None
+
+
+CT_ST_NEWTON, CT_ST_NONPHYS, CT_ST_MESH, CT_ST_MULTI = 1, 2, 4, 8
+CT_FL_CREATED, CT_FL_LMAX, CT_FL_INACTIVE = 1, 2, 4
+
+
+class CTubeState:
+    """Evolving state of a CTubeBatch (creation tubes) in the oracle: cell
+    values, the face of the created cell (-1: none yet), its boundary
+    offsets dl, dr from that face, the boundaries' warm starts pw [P, 4],
+    time, status, steps and dual time iterations."""
+
+    def __init__(self, cb):
+        self.batch = cb
+        P = cb.n_problems
+        self.rho = np.ascontiguousarray(cb.rho, dtype=np.float64).copy()
+        self.mom = np.ascontiguousarray(cb.mom, dtype=np.float64).copy()
+        self.face = np.full(P, -1, dtype=np.int32)
+        self.dl = np.zeros(P)
+        self.dr = np.zeros(P)
+        self.pw = np.zeros((P, 4))
+        self.t = np.zeros(P)
+        self.status = np.zeros(P, dtype=np.int32)
+        self.steps = np.zeros(P, dtype=np.int32)
+        self.iters = np.zeros(P, dtype=np.int64)
+
+
+def ct_run(state, n_steps=None, threads=1, log=False):
+    """Advances every creation tube by up to n_steps steps (None: to t_end).
+    With log=True returns (counts, flags), each [n_steps, P]."""
+    b = state.batch
+    P = b.n_problems
+    if n_steps is None:
+        if log:
+            raise ValueError("log=True needs n_steps")
+        n_steps = 2**31 - 1
+    off = np.ascontiguousarray(b.off[:-1], dtype=np.int64)
+    N = np.ascontiguousarray(b.N, dtype=np.int32)
+    h = np.ascontiguousarray(b.h, dtype=np.float64)
+    ph = np.ascontiguousarray(b.phase, dtype=np.int32)
+    lc = lf = None
+    if log:
+        lc = np.zeros((n_steps, P), dtype=np.int32)
+        lf = np.zeros((n_steps, P), dtype=np.int32)
+    d, i, l = ctypes.c_double, ctypes.c_int, ctypes.c_longlong
+    m, par = _mat(b.material), _par(b.params)
+    rc = lib().oracle_ct_run(ctypes.byref(m), ctypes.byref(par), float(b.p_min),
+                             float(b.p_tilde), P, _ptr(N, i), _ptr(h, d), _ptr(ph, i),
+                             _ptr(off, l), _ptr(state.rho, d), _ptr(state.mom, d),
+                             _ptr(state.face, i), _ptr(state.dl, d), _ptr(state.dr, d),
+                             _ptr(state.pw, d), _ptr(state.t, d), _ptr(state.status, i),
+                             _ptr(state.steps, i), _ptr(state.iters, l), int(n_steps),
+                             _ptr(lc, i) if log else None, _ptr(lf, i) if log else None,
+                             int(threads))
+    if rc != 0:
+        raise ValueError("oracle_ct_run: zone_half out of range")
     if log:
         return lc, lf
     return None

@@ -1634,3 +1634,413 @@ done:
   return ok ? 0 : -4;
 }
 #endif
+
+#ifndef OR_TANGENT
+/* ------------------------------------------------------------------ */
+/* a created cell inside the mesh: appendix "Phase Creation", step     */
+/* (iv), and the two phase boundaries of the steps that follow it      */
+/* ------------------------------------------------------------------ */
+/* A creation tube has n regular cells of length h and phase ph; slot n
+ * holds the created cell once there is one.  The cell is created on the
+ * face j (between cells j-1 and j, the face the Riemann problem of step (i)
+ * failed on) and is bounded by two phase boundaries at x_j + dl and
+ * x_j + dr; the neighbours take lengths h + dl (cell j-1) and h - dr
+ * (cell j), the created cell dr - dl (the picture of the creation step in
+ * Sec. 2: the face is gone, two boundary points move apart).  Steps:
+ *   - CFL step over every cell, the created one included;
+ *   - while there is no created cell: step (i) on every inner face; one
+ *     failing face is a creation step: step (ii) there, its two
+ *     neighbours updated with the boundary fluxes of step (v) and their
+ *     new lengths, the new cell set to the middle star state of step (iv)
+ *     with length (w_r - w_l) dt; every other cell explicitly (HLL);
+ *   - with a created cell: Algorithm 1 with the zone "created cell +- Z
+ *     cells", whose inner faces are HLL faces and the two phase
+ *     boundaries (interface solver, eq. pb_flux:pt), Algorithm 2 with the
+ *     moving lengths of the three cells next to the boundaries.
+ * The created cell is never merged (its neighbours are of the other
+ * phase); a neighbour shorter than h/2, a second creation in one problem
+ * and a zone reaching past the domain are not modelled and freeze the
+ * problem with a status bit. */
+#define OR_CT_ST_NEWTON 1
+#define OR_CT_ST_NONPHYS 2
+#define OR_CT_ST_MESH 4
+#define OR_CT_ST_MULTI 8
+#define OR_CT_FL_CREATED 1
+#define OR_CT_FL_LMAX 2
+#define OR_CT_FL_INACTIVE 4
+
+typedef struct {
+  int n, ph;
+  double h;
+  double *rho, *mom; /* n + 1 slots */
+  int *face;
+  double *dl, *dr, *pw; /* pw: (p_l, p_r) of the left boundary, then of the right one */
+  double *t;
+  int *status, *steps;
+  long long *iters;
+} or_ctube;
+
+/* step (i) alone: 1 if the Riemann problem of the two states creates a
+ * layer of the other phase (as decided inside or_creation_rp) */
+static int or_creation_test(const or_material *M, int ph, double rl, double ml, double rr,
+                            double mr, double p_min, double p_tilde) {
+  or_side L, R;
+  or_side_init(M, ph, rl, ml, &L);
+  or_side_init(M, ph, rr, mr, &R);
+  double p1 = 0.0;
+  int none = or_single_rp(M, &L, &R, &p1);
+  return none ? 1 : (ph == OR_LIQ ? p1 < p_min : p1 > p_tilde);
+}
+
+/* flux on the regular face j (0 and n: the domain ends) from U */
+static void or_ct_face(const or_material *M, const or_params *P, const or_ctube *c,
+                       const double *r, const double *m, int j, double *F) {
+  if (j == 0)
+    or_bflux(M, c->ph, 0, P->bc_left, r[0], m[0], F);
+  else if (j == c->n)
+    or_bflux(M, c->ph, 1, P->bc_right, r[c->n - 1], m[c->n - 1], F);
+  else
+    or_hll(M, c->ph, r[j - 1], m[j - 1], r[j], m[j], F);
+}
+
+/* length of a zone cell when the left boundary moves with wl and the right
+ * one with wr: kind 1 left neighbour, 2 created cell, 3 right neighbour */
+static double or_ct_len(double hn, int kind, double wl, double wr, double dt) {
+  if (kind == 1) return hn + wl * dt;
+  if (kind == 2) return hn + (wr - wl) * dt;
+  if (kind == 3) return hn - wr * dt;
+  return hn;
+}
+
+typedef struct {
+  int m, zc; /* cells, index of the created cell */
+  int phn;   /* phase of the created cell */
+  int kind[OR_MAXC];
+  double U0[OR_MAXC][2], hn[OR_MAXC], hh[OR_MAXC], th[OR_MAXC], i1t[OR_MAXC], thr[OR_MAXC];
+  double FL[2], FR[2];
+} or_ctzone;
+
+/* fluxes of a zone iterate: HLL inside the outer phase, the interface
+ * solver on the two phase boundaries (warm starts pwl, pwr updated) */
+static int or_ct_fluxes(const or_material *M, const or_params *P, int ph, const or_ctzone *Z,
+                        double W[][2], double F[][2], double *pwl, double *pwr, double *wl,
+                        double *wr) {
+  int c;
+  F[0][0] = Z->FL[0];
+  F[0][1] = Z->FL[1];
+  F[Z->m][0] = Z->FR[0];
+  F[Z->m][1] = Z->FR[1];
+  for (c = 0; c + 1 < Z->m; ++c) {
+    if (c == Z->zc - 1 || c == Z->zc) {
+      int left = c == Z->zc - 1;
+      double *pw = left ? pwl : pwr;
+      or_iface I;
+      if (!or_iface_solve(M, left ? ph : Z->phn, W[c][0], W[c][1], left ? Z->phn : ph,
+                          W[c + 1][0], W[c + 1][1], 1, pw[0], pw[1], P->newton_maxit,
+                          P->newton_rtol, &I))
+        return 0;
+      pw[0] = I.pl;
+      pw[1] = I.pr;
+      if (left)
+        *wl = I.w;
+      else
+        *wr = I.w;
+      F[c + 1][0] = I.F0;
+      F[c + 1][1] = I.F1;
+    } else {
+      or_hll(M, ph, W[c][0], W[c][1], W[c + 1][0], W[c + 1][1], F[c + 1]);
+    }
+  }
+  return 1;
+}
+
+/* Algorithm 2 on the zone of the created cell (pseudo step and stop test as
+ * in or_zone_dts); returns 0 or a status bit */
+static int or_ct_dts(const or_material *M, const or_params *P, int ph, const or_ctzone *Z,
+                     double dt, double *pwl, double *pwr, double U1[][2], double *wls,
+                     double *wrs, int *count, int *lmax_hit) {
+  double W[OR_MAXC][2], Wn[OR_MAXC][2], F[OR_MAXC + 1][2], hnew[OR_MAXC], ih[OR_MAXC];
+  int c, l, m = Z->m, cnt = 0, stop = 0;
+  double wl = 0.0, wr = 0.0;
+  *lmax_hit = 0;
+  for (c = 0; c < m; ++c) {
+    W[c][0] = Z->U0[c][0];
+    W[c][1] = Z->U0[c][1];
+  }
+  for (l = 0; l < P->lmax; ++l) {
+    if (!or_ct_fluxes(M, P, ph, Z, W, F, pwl, pwr, &wl, &wr)) return OR_CT_ST_NEWTON;
+    for (c = 0; c < m; ++c) {
+      hnew[c] = or_ct_len(Z->hn[c], Z->kind[c], wl, wr, dt);
+      ih[c] = 1.0 / hnew[c];
+      if (Z->kind[c] != 0 && !(hnew[c] >= 0.5 * Z->hh[c])) return OR_CT_ST_MESH;
+    }
+    int conv = 1;
+    for (c = 0; c < m; ++c) {
+      double th = Z->th[c], opt = 1.0 + th;
+      int q;
+      for (q = 0; q < 2; ++q) {
+        double rhs = (Z->hn[c] * Z->U0[c][q] - dt * (F[c + 1][q] - F[c][q])) * ih[c];
+        Wn[c][q] = (W[c][q] + th * rhs) * Z->i1t[c];
+        double d = Wn[c][q] - W[c][q];
+        double sc = fabs(W[c][q]) > 1.0 ? fabs(W[c][q]) : 1.0;
+        int ok = (P->tol_mode == 0) ? (fabs(opt * d) < Z->thr[c] * sc) : (fabs(d) < P->tol_rel * sc);
+        conv = conv && ok;
+      }
+      if (!or_state_ok(Wn[c][0], Wn[c][1])) return OR_CT_ST_NONPHYS;
+    }
+    for (c = 0; c < m; ++c) {
+      W[c][0] = Wn[c][0];
+      W[c][1] = Wn[c][1];
+    }
+    cnt = l + 1;
+    stop = conv;
+    if (stop) break;
+  }
+  if (!stop) *lmax_hit = 1;
+  *count = cnt;
+  /* Part 2 */
+  if (!or_ct_fluxes(M, P, ph, Z, W, F, pwl, pwr, &wl, &wr)) return OR_CT_ST_NEWTON;
+  for (c = 0; c < m; ++c) {
+    hnew[c] = or_ct_len(Z->hn[c], Z->kind[c], wl, wr, dt);
+    ih[c] = 1.0 / hnew[c];
+    if (Z->kind[c] != 0 && !(hnew[c] >= 0.5 * Z->hh[c])) return OR_CT_ST_MESH;
+  }
+  for (c = 0; c < m; ++c) {
+    int q;
+    for (q = 0; q < 2; ++q)
+      U1[c][q] = (Z->hn[c] * Z->U0[c][q] - dt * (F[c + 1][q] - F[c][q])) * ih[c];
+    if (!or_state_ok(U1[c][0], U1[c][1])) return OR_CT_ST_NONPHYS;
+  }
+  *wls = wl;
+  *wrs = wr;
+  return 0;
+}
+
+/* one physical step of one creation tube; *count, *flags: its log entry */
+static void or_ct_step(const or_material *M, const or_params *P, double p_min, double p_tilde,
+                       or_ctube *c, double *rn, double *mn, double *F, int *count, int *flags) {
+  int n = c->n, s, j;
+  double h = c->h;
+  double *r = c->rho, *m = c->mom;
+  int j0 = *c->face;
+  *count = 0;
+  *flags = OR_CT_FL_INACTIVE;
+  if (*c->status || !(*c->t < P->t_end)) return;
+  *flags = 0;
+  if (j0 >= 0) {
+    double dl = *c->dl, dr = *c->dr;
+    if (!(h + dl >= 0.5 * h) || !(h - dr >= 0.5 * h) || !(dr - dl > 0.0) ||
+        j0 - P->zone_half < 0 || j0 + P->zone_half > n) {
+      *c->status |= OR_CT_ST_MESH;
+      return;
+    }
+  }
+  /* CFL (eq. cfl_cond:unif) over every cell, the created one included */
+  double S = 0.0;
+  int ns = j0 >= 0 ? n + 1 : n;
+  for (s = 0; s < ns; ++s) {
+    int phs = s < n ? c->ph : 1 - c->ph;
+    if (!or_state_ok(r[s], m[s])) {
+      *c->status |= OR_CT_ST_NONPHYS;
+      return;
+    }
+    double si = fabs(m[s] / r[s]) + sqrt(or_a2(M, phs));
+    if (si > S) S = si;
+  }
+  if (!(S > 0.0) || !isfinite(S)) {
+    *c->status |= OR_CT_ST_NONPHYS;
+    return;
+  }
+  double dt = (P->cfl * h) / S;
+  double rem = P->t_end - *c->t;
+  int clipped = 0;
+  if (dt >= rem) {
+    dt = rem;
+    clipped = 1;
+  }
+  double lam = dt / h;
+  /* cells updated by the explicit sweep: [0, a) and [b, n) */
+  int a = n, b = n, jc = -1;
+  if (j0 < 0) {
+    /* step (i) on every inner face */
+    int nc = 0;
+    for (j = 1; j < n; ++j)
+      if (or_creation_test(M, c->ph, r[j - 1], m[j - 1], r[j], m[j], p_min, p_tilde)) {
+        if (jc < 0) jc = j;
+        ++nc;
+      }
+    if (nc > 1) {
+      *c->status |= OR_CT_ST_MULTI;
+      return;
+    }
+    if (jc >= 0) {
+      a = jc - 1;
+      b = jc + 1;
+    }
+  } else {
+    a = j0 - P->zone_half;
+    b = j0 + P->zone_half;
+  }
+  for (j = 0; j <= n; ++j)
+    if (j <= a || j >= b) or_ct_face(M, P, c, r, m, j, &F[2 * j]);
+  for (s = 0; s < n; ++s) {
+    rn[s] = r[s];
+    mn[s] = m[s];
+    if (s >= a && s < b) continue;
+    rn[s] = r[s] - lam * (F[2 * (s + 1)] - F[2 * s]);
+    mn[s] = m[s] - lam * (F[2 * (s + 1) + 1] - F[2 * s + 1]);
+  }
+  rn[n] = r[n];
+  mn[n] = m[n];
+  int cnt = 0, fl = 0, st = 0;
+  double ndl = 0.0, ndr = 0.0, pw4[4] = {0.0, 0.0, 0.0, 0.0};
+  if (jc >= 0) {
+    /* creation step: steps (ii), (iii), (v) on face jc, step (iv) */
+    or_creation C;
+    if (or_creation_rp(M, c->ph, r[jc - 1], m[jc - 1], r[jc], m[jc], p_min, p_tilde,
+                       P->newton_maxit, P->newton_rtol, &C) != 1) {
+      st = OR_CT_ST_NEWTON;
+    } else {
+      double h1l = h + C.wl * dt, h1r = h - C.wr * dt;
+      ndl = C.wl * dt;
+      ndr = C.wr * dt;
+      if (!(h1l > 0.0) || !(h1r > 0.0) || !(ndr - ndl > 0.0)) {
+        st = OR_CT_ST_MESH;
+      } else {
+        double il = 1.0 / h1l, ir = 1.0 / h1r;
+        rn[jc - 1] = (h * r[jc - 1] - dt * (C.Fl0 - F[2 * (jc - 1)])) * il;
+        mn[jc - 1] = (h * m[jc - 1] - dt * (C.Fl1 - F[2 * (jc - 1) + 1])) * il;
+        rn[jc] = (h * r[jc] - dt * (F[2 * (jc + 1)] - C.Fr0)) * ir;
+        mn[jc] = (h * m[jc] - dt * (F[2 * (jc + 1) + 1] - C.Fr1)) * ir;
+        rn[n] = C.rb;
+        mn[n] = C.rb * C.ub;
+        pw4[0] = C.pa;
+        pw4[1] = C.pb;
+        pw4[2] = C.pb;
+        pw4[3] = C.pc;
+        if (!or_state_ok(rn[jc - 1], mn[jc - 1]) || !or_state_ok(rn[jc], mn[jc]) ||
+            !or_state_ok(rn[n], mn[n]))
+          st = OR_CT_ST_NONPHYS;
+        fl = OR_CT_FL_CREATED;
+      }
+    }
+  } else if (j0 >= 0) {
+    /* Algorithm 2 on cells j0-Z .. j0-1, the created cell, j0 .. j0+Z-1 */
+    int Zh = P->zone_half, k;
+    double dl = *c->dl, dr = *c->dr;
+    or_ctzone Z;
+    Z.m = 2 * Zh + 1;
+    Z.zc = Zh;
+    Z.phn = 1 - c->ph;
+    for (k = 0; k < Z.m; ++k) {
+      int sl = k < Zh ? j0 - Zh + k : (k == Zh ? n : j0 + (k - Zh - 1));
+      Z.U0[k][0] = r[sl];
+      Z.U0[k][1] = m[sl];
+      Z.kind[k] = k == Zh - 1 ? 1 : (k == Zh ? 2 : (k == Zh + 1 ? 3 : 0));
+      Z.hn[k] = k == Zh - 1 ? h + dl : (k == Zh ? dr - dl : (k == Zh + 1 ? h - dr : h));
+    }
+    or_ct_face(M, P, c, r, m, a, Z.FL);
+    or_ct_face(M, P, c, r, m, b, Z.FR);
+    /* explicit prediction of both boundary speeds from U^n */
+    or_iface Il, Ir;
+    double *pw = c->pw;
+    if (!or_iface_solve(M, c->ph, r[j0 - 1], m[j0 - 1], Z.phn, r[n], m[n], 1, pw[0], pw[1],
+                        P->newton_maxit, P->newton_rtol, &Il) ||
+        !or_iface_solve(M, Z.phn, r[n], m[n], c->ph, r[j0], m[j0], 1, pw[2], pw[3],
+                        P->newton_maxit, P->newton_rtol, &Ir)) {
+      st = OR_CT_ST_NEWTON;
+    } else {
+      for (k = 0; k < Z.m && !st; ++k) {
+        double hh = or_ct_len(Z.hn[k], Z.kind[k], Il.w, Ir.w, dt);
+        double th = hh / h;
+        if (th > P->theta_nb) th = P->theta_nb;
+        Z.hh[k] = hh;
+        Z.th[k] = th;
+        Z.i1t[k] = 1.0 / (1.0 + th);
+        Z.thr[k] = (k == Zh ? P->tol_tiny : P->tol_nb) * (th * dt);
+        if (!(th > 0.0)) st = OR_CT_ST_MESH;
+      }
+      double pwl[2] = {Il.pl, Il.pr}, pwr[2] = {Ir.pl, Ir.pr};
+      double U1[OR_MAXC][2], wl = 0.0, wr = 0.0;
+      int lh = 0;
+      if (!st) st = or_ct_dts(M, P, c->ph, &Z, dt, pwl, pwr, U1, &wl, &wr, &cnt, &lh);
+      if (!st) {
+        for (k = 0; k < Z.m; ++k) {
+          int sl = k < Zh ? j0 - Zh + k : (k == Zh ? n : j0 + (k - Zh - 1));
+          rn[sl] = U1[k][0];
+          mn[sl] = U1[k][1];
+        }
+        ndl = dl + wl * dt;
+        ndr = dr + wr * dt;
+        pw4[0] = pwl[0];
+        pw4[1] = pwl[1];
+        pw4[2] = pwr[0];
+        pw4[3] = pwr[1];
+        if (lh) fl |= OR_CT_FL_LMAX;
+      }
+    }
+  }
+  if (st) {
+    *c->status |= st;
+    *flags = fl;
+    return;
+  }
+  memcpy(r, rn, sizeof(double) * (n + 1));
+  memcpy(m, mn, sizeof(double) * (n + 1));
+  if (jc >= 0) *c->face = jc;
+  if (jc >= 0 || j0 >= 0) {
+    *c->dl = ndl;
+    *c->dr = ndr;
+    memcpy(c->pw, pw4, sizeof(pw4));
+  }
+  *c->t = clipped ? P->t_end : *c->t + dt;
+  *c->steps += 1;
+  *c->iters += cnt;
+  *count = cnt;
+  *flags = fl;
+}
+
+/* n_steps steps of P independent creation tubes (OpenMP over tubes).  Tube
+ * p has n_cells[p] regular cells and n_cells[p] + 1 slots from off[p];
+ * face, dl, dr, pw (4 per tube), t, status, steps, iters are its state.
+ * Logs (optional) are [n_steps][P]. */
+int oracle_ct_run(const or_material *M, const or_params *Pp, double p_min, double p_tilde,
+                  int P, const int *n_cells, const double *h, const int *phase,
+                  const long long *off, double *rho, double *mom, int *face, double *dl,
+                  double *dr, double *pw, double *t, int *status, int *steps, long long *iters,
+                  int n_steps, int *log_count, int *log_flags, int n_threads) {
+  int p;
+  if (Pp->zone_half < 1 || 2 * Pp->zone_half + 1 > OR_MAXC) return -1;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads > 0 ? n_threads : 1)
+  for (p = 0; p < P; ++p) {
+    or_ctube c;
+    c.n = n_cells[p];
+    c.ph = phase[p];
+    c.h = h[p];
+    c.rho = rho + off[p];
+    c.mom = mom + off[p];
+    c.face = face + p;
+    c.dl = dl + p;
+    c.dr = dr + p;
+    c.pw = pw + 4 * (size_t)p;
+    c.t = t + p;
+    c.status = status + p;
+    c.steps = steps + p;
+    c.iters = iters + p;
+    double *rn = (double *)malloc(sizeof(double) * (2 * (size_t)(c.n + 1) + 2 * (size_t)(c.n + 1)));
+    double *mn = rn + (c.n + 1), *F = mn + (c.n + 1);
+    int k;
+    for (k = 0; k < n_steps; ++k) {
+      int cnt, fl;
+      if (!log_count && (*c.status || !(*c.t < Pp->t_end))) break;
+      or_ct_step(M, Pp, p_min, p_tilde, &c, rn, mn, F, &cnt, &fl);
+      if (log_count) {
+        log_count[(size_t)k * P + p] = cnt;
+        log_flags[(size_t)k * P + p] = fl;
+      }
+    }
+    free(rn);
+  }
+  return 0;
+}
+#endif
