@@ -1823,10 +1823,11 @@ static void or_ct_step(const or_material *M, const or_params *P, double p_min, d
   double h = c->h;
   double *r = c->rho, *m = c->mom;
   int j0 = *c->face;
+  /* a tube that fails the checks at the start of its step (mesh, CFL)
+   * logs the step as inactive: nothing of it was done */
   *count = 0;
   *flags = OR_CT_FL_INACTIVE;
   if (*c->status || !(*c->t < P->t_end)) return;
-  *flags = 0;
   if (j0 >= 0) {
     double dl = *c->dl, dr = *c->dr;
     if (!(h + dl >= 0.5 * h) || !(h - dr >= 0.5 * h) || !(dr - dl > 0.0) ||
@@ -1851,6 +1852,7 @@ static void or_ct_step(const or_material *M, const or_params *P, double p_min, d
     *c->status |= OR_CT_ST_NONPHYS;
     return;
   }
+  *flags = 0;
   double dt = (P->cfl * h) / S;
   double rem = P->t_end - *c->t;
   int clipped = 0;

@@ -9,7 +9,8 @@ SOURCES = [os.path.join(HERE, "csrc", "imexds_kernels.hip"),
            os.path.join(HERE, "csrc", "imexds_adjoint.hip"),
            os.path.join(HERE, "csrc", "imexds_runtime.hip"),
            os.path.join(HERE, "csrc", "euler.hip"),
-           os.path.join(HERE, "csrc", "creation.hip")]
+           os.path.join(HERE, "csrc", "creation.hip"),
+           os.path.join(HERE, "csrc", "ctube.hip")]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-shared", "-std=c++17",
          # IEEE FP64 evaluated as written: no fused multiply-add contraction
          "-ffp-contract=off",

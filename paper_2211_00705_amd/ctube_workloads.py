@@ -133,10 +133,11 @@ def nucleation_tube(N=400, h=1e-2, **kw):
 def ctube_batch(seed=20261202, n_problems=4096, Ns=(200, 400, 800), h=1e-2, params=None):
     """Tubes around the two tests, alternating: liquid ones with p ~ U[4e4,
     9e4] Pa on each side pulled apart at u_l = -U[1, 6], u_r = U[1, 6] m/s
-    (cavitation), vapour ones with p ~ U[6.99e4, 7.025e4] Pa compressed at
-    u_l = U[3.5, 6], u_r = -U[3.5, 6] m/s (nucleation: the single-phase star
-    pressure exceeds p~); N drawn from Ns with h fixed, so every phase
-    boundary stays inside its neighbour cells up to t_end = 5e-4 s."""
+    (cavitation), vapour ones with p ~ U[6.998e4, 7.01e4] Pa compressed at
+    u_l = U[2.6, 3], u_r = -U[2.6, 3] m/s (nucleation: the single-phase star
+    pressure exceeds p~, close to the paper's test); N drawn from Ns with h
+    fixed, so every phase boundary stays inside its neighbour cells up to
+    t_end = 5e-4 s."""
     rng = np.random.default_rng(seed)
     specs = []
     for i in range(n_problems):
@@ -146,8 +147,8 @@ def ctube_batch(seed=20261202, n_problems=4096, Ns=(200, 400, 800), h=1e-2, para
             ul, ur = -rng.uniform(1.0, 6.0), rng.uniform(1.0, 6.0)
             specs.append(dict(N=N, h=h, phase=LIQ, left=(pl, ul), right=(pr, ur)))
         else:
-            pl, pr = rng.uniform(6.99e4, 7.025e4, 2)
-            ul, ur = rng.uniform(3.5, 6.0), -rng.uniform(3.5, 6.0)
+            pl, pr = rng.uniform(6.998e4, 7.01e4, 2)
+            ul, ur = rng.uniform(2.6, 3.0), -rng.uniform(2.6, 3.0)
             specs.append(dict(N=N, h=h, phase=VAP, left=(pl, ul), right=(pr, ur)))
     return concat(specs, name=f"ctube_batch_P{n_problems}_seed{seed}",
                   params=params or CT_PARAMS, meta={"seed": seed, "Ns": tuple(Ns), "h": h})

@@ -10,6 +10,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HDR = os.path.join(ROOT, "include", "imexds.h")
 HDR_EU = os.path.join(ROOT, "include", "imexds_euler.h")
 HDR_CR = os.path.join(ROOT, "include", "imexds_creation.h")
+HDR_CT = os.path.join(ROOT, "include", "imexds_ctube.h")
 LIB = os.path.join(ROOT, "paper_2211_00705_amd", "libimexds.so")
 
 
@@ -29,13 +30,19 @@ def test_header_declares_the_entry_points():
         assert name in d
     assert not set(d) & set(declared())
     assert declared(HDR_CR) == ["imexds_creation_rp"]
+    d = declared(HDR_CT)
+    for name in ("imexds_ct_create", "imexds_ct_set_state", "imexds_ct_step", "imexds_ct_run",
+                 "imexds_ct_get_state", "imexds_ct_get_problems", "imexds_ct_destroy"):
+        assert name in d
+    assert not set(d) & (set(declared()) | set(declared(HDR_EU)))
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
 def test_library_exports_every_declared_symbol():
     out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
     syms = set(l.split()[-1] for l in out.splitlines() if l.strip())
-    missing = [n for n in declared() + declared(HDR_EU) + declared(HDR_CR) if n not in syms]
+    missing = [n for n in declared() + declared(HDR_EU) + declared(HDR_CR) + declared(HDR_CT)
+               if n not in syms]
     assert not missing, missing
 
 
@@ -49,6 +56,8 @@ def test_binding_loads_and_maps_every_symbol():
     assert sorted(euler.EXPORTED) == declared(HDR_EU)
     from paper_2211_00705_amd import creation
     assert sorted(creation.EXPORTED) == declared(HDR_CR)
+    from paper_2211_00705_amd import ctube
+    assert sorted(ctube.EXPORTED) == declared(HDR_CT)
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
