@@ -60,6 +60,13 @@ def parse():
     ap.add_argument("--per-problem-steps-euler", type=int, default=3)
     ap.add_argument("--euler-problems", type=int, default=4096,
                     help="tubes in the full-Euler Lax ensemble leg (0: skip)")
+    ap.add_argument("--ctube-problems", type=int, default=4096,
+                    help="creation tubes (cavitation / nucleation inside the mesh) leg (0: skip)")
+    ap.add_argument("--only-ctube", action="store_true",
+                    help="run only the creation-tube leg (for profiling it)")
+    ap.add_argument("--ctube-steps", type=int, default=10,
+                    help="creation-tube leg: steps timed (the creation step and the heaviest "
+                         "dual time steps; 0: run to t_end, about 100 s)")
     ap.add_argument("--other-configs", type=int, default=1,
                     help="also time the other workloads (single cut, 2^20 cells, bubbles)")
     ap.add_argument("--adjoint-one-segment", type=int, default=1,
@@ -288,6 +295,10 @@ def other_configs_leg(material, cpu):
 EU_ZONE_FLOP_PER_TUBE_ITER = 8989.0  # k_eu_zone: per tube and dual time iteration
 EU_BULK_FLOP_PER_FACE = 1343.0       # k_eu_bulk: per face of a tube still running
 CR_FLOP_PER_PROBLEM = 2460.0         # k_cr_detect + k_cr_solve per problem of creation_batch
+# k_ct_zone: executed FP64 lane operations (64 per wave instruction; at 4 tubes
+# per wave 8 of the 64 lanes hold a phase boundary) per tube and dual time
+# iteration, from the rocprofv3 PMC counts of the leg's 10 steps of ctube_batch
+CT_ZONE_FLOP_PER_TUBE_ITER = 34274.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 
@@ -429,6 +440,82 @@ def creation_leg(args, cpu):
     return rec
 
 
+def ctube_leg(args, cpu):
+    """Creation tubes (Sec. 5 cavitation and nucleation runs, batched): 4096
+    tubes, half cavitating liquid, half nucleating vapour, from the creation
+    step to t_end = 5e-4 s with the paper's stop rule; HIP events around every
+    launch; the oracle on a bounded sample of the same tubes."""
+    import torch
+    from paper_2211_00705_amd import ctube_workloads as CW
+    from paper_2211_00705_amd.ctube import CreationTubes
+    b = CW.ctube_batch(n_problems=args.ctube_problems)
+    slots = b.N.astype(np.int64) + 1
+    lanes, ppw = 2, 4
+    s = CreationTubes(b)
+    try:
+        s.set_launch(lanes, ppw)
+        s.set_state()
+        s.time_kernels(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if args.ctube_steps > 0:
+            s.step(args.ctube_steps)
+            n = args.ctube_steps
+        else:
+            n = s.run(1 << 20, 64)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        bulk_ms, zone_ms, step_ms = s.last_timing()
+        s.time_kernels(False)
+        t, st, steps, iters, face, _, _ = s.problems()
+    finally:
+        s.close()
+    cu = float(np.sum(slots * steps))
+    tube_iters = float(np.sum(iters))
+    rec = {"workload": f"ctube_batch: {b.n_problems} creation tubes (half liquid pulled apart "
+                       "at 1-6 m/s, cavitating; half vapour compressed at 2.6-3 m/s, "
+                       f"nucleating), N in {{200,400,800}}, h = 1e-2 m ({b.n_slots} slots), "
+                       "C_CFL 0.5, zone +-1, paper stop rule, l_max 1e5, "
+                       + (f"first {args.ctube_steps} steps (creation step and the heaviest "
+                          "dual time steps)" if args.ctube_steps > 0 else "to t_end = 5e-4 s"),
+           "unit": "cell-updates/s", "value": cu / wall, "wall_s": wall, "launch_steps": n,
+           "launch": {"zone_lanes": lanes, "zone_problems_per_wave": ppw, "check_every": 64},
+           "failed_problems": int(np.sum(st != 0)),
+           "created": int(np.sum(face >= 0)),
+           "tube_steps_per_s": float(np.sum(steps)) / wall,
+           "tubes_to_t_end_per_s": float(b.n_problems) / wall if args.ctube_steps == 0 else None,
+           "dual_time_iterations": tube_iters,
+           "dual_time_iterations_per_s": tube_iters / wall,
+           "max_iterations_per_tube": int(np.max(iters)) if len(iters) else 0,
+           "bulk_ms_per_launch": bulk_ms, "zone_ms_per_launch": zone_ms, "step_ms": step_ms}
+    if CT_ZONE_FLOP_PER_TUBE_ITER:
+        tf = CT_ZONE_FLOP_PER_TUBE_ITER * (tube_iters / max(1, n)) / (zone_ms * 1e-3) / 1e12
+        rec["roofline"] = {"bound": "alu", "kernel": "k_ct_zone", "achieved": tf,
+                           "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                           "frac": tf / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                           "per_unit": f"{CT_ZONE_FLOP_PER_TUBE_ITER:.0f} FP64 ops per tube and "
+                                       "dual time iteration",
+                           "units_per_launch": tube_iters / max(1, n),
+                           "note": "the nucleating tubes' dependent chains (tens of thousands "
+                                   "of dual time iterations per step) bound it: latency"}
+    if cpu:
+        import oracle
+        idx = [0, 1, 2, 3]
+        sub = b.subset(idx)
+        for threads in (1, 4):
+            stc = oracle.CTubeState(sub)
+            t0 = time.perf_counter()
+            oracle.ct_run(stc, args.ctube_steps if args.ctube_steps > 0 else None,
+                          threads=threads)
+            w = time.perf_counter() - t0
+            key = "cpu_1_thread" if threads == 1 else "cpu_4_threads"
+            rec[key] = {"value": float(np.sum((sub.N + 1) * stc.steps)) / w, "threads": threads,
+                        "kind": "oracle", "sample": "tubes 0-3 of the ensemble (2 cavitating, "
+                                                    "2 nucleating), the same steps",
+                        "wall_s": w}
+    return rec
+
+
 def measure_copy_bandwidth(mib=1024, reps=20):
     """Read+write bandwidth of a plain device-to-device copy (torch copy_) of
     `mib` MiB: the practical HBM ceiling the sweep's roofline is read against."""
@@ -475,6 +562,9 @@ def main():
         return
     if args.only_creation:
         print(json.dumps({"phase_creation": creation_leg(args, not args.no_cpu)}))
+        return
+    if args.only_ctube:
+        print(json.dumps({"creation_tubes": ctube_leg(args, not args.no_cpu)}))
         return
 
     # practical HBM ceiling (after the copy the traffic calibration counts on)
@@ -584,6 +674,8 @@ def main():
         out["euler_lax"] = euler_leg(args, not args.no_cpu)
     if args.creation_problems > 0:
         out["phase_creation"] = creation_leg(args, not args.no_cpu)
+    if args.ctube_problems > 0:
+        out["creation_tubes"] = ctube_leg(args, not args.no_cpu)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline_leg(b, P, material, args.steps, g_rho, g_mom, g_home,
                                                g_hl, args.cpu_seconds)

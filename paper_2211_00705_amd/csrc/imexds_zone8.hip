@@ -63,7 +63,21 @@ __global__ __launch_bounds__(64) void k_zone8(StepArgs A, int if_begin, int if_e
   constexpr int MC = 2 * ZH + 1;
   constexpr int S_FETCH = 0, S_PRED = 1, S_ITER = 2, S_EXIT = 3;
   static_assert(MC <= 8, "a zone must fit an 8-lane group");
-  const Mat& M = A.mat;
+  // The material constants are read in every pass of the dual time loop.
+  // Uniform values live in scalar registers, which this kernel runs out of
+  // (the spills cost a v_readlane each in the loop); it has vector registers
+  // to spare at its occupancy.  OR-ing each constant's bits with a zero the
+  // compiler cannot see through (a vector register set by one v_mov) keeps
+  // every value as it is but places it in vector registers.
+  int vz;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(vz));
+  Mat Mv = A.mat;
+#define Z8_VREG(x) x = __longlong_as_double(__double_as_longlong(x) | (long long)vz)
+  Z8_VREG(Mv.a2v); Z8_VREG(Mv.a2l); Z8_VREG(Mv.p0); Z8_VREG(Mv.rhol0); Z8_VREG(Mv.tau);
+  Z8_VREG(Mv.av); Z8_VREG(Mv.al); Z8_VREG(Mv.rhov0); Z8_VREG(Mv.ia2v); Z8_VREG(Mv.ia2l);
+  Z8_VREG(Mv.iav); Z8_VREG(Mv.ial); Z8_VREG(Mv.irv0); Z8_VREG(Mv.irl0);
+#undef Z8_VREG
+  const Mat& M = Mv;
   const Par& P = A.par;
   const int lane = threadIdx.x;
   const double tol_nb = P.tol_nb, tol_tiny = P.tol_tiny;
