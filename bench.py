@@ -295,10 +295,11 @@ def other_configs_leg(material, cpu):
 EU_ZONE_FLOP_PER_TUBE_ITER = 8989.0  # k_eu_zone: per tube and dual time iteration
 EU_BULK_FLOP_PER_FACE = 1343.0       # k_eu_bulk: per face of a tube still running
 CR_FLOP_PER_PROBLEM = 2460.0         # k_cr_detect + k_cr_solve per problem of creation_batch
-# k_ct_zone: executed FP64 lane operations (64 per wave instruction; at 4 tubes
-# per wave 8 of the 64 lanes hold a phase boundary) per tube and dual time
-# iteration, from the rocprofv3 PMC counts of the leg's 10 steps of ctube_batch
-CT_ZONE_FLOP_PER_TUBE_ITER = 34274.0
+# k_ct_zone: executed FP64 lane operations (64 per wave instruction; at 2 tubes
+# per wave and 4 lanes per tube 8 of the 64 lanes are busy) per tube and dual
+# time iteration, from the rocprofv3 PMC counts of the leg's 10 steps of
+# ctube_batch
+CT_ZONE_FLOP_PER_TUBE_ITER = 47456.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 
@@ -450,7 +451,7 @@ def ctube_leg(args, cpu):
     from paper_2211_00705_amd.ctube import CreationTubes
     b = CW.ctube_batch(n_problems=args.ctube_problems)
     slots = b.N.astype(np.int64) + 1
-    lanes, ppw = 2, 4
+    lanes, ppw = 4, 2
     s = CreationTubes(b)
     try:
         s.set_launch(lanes, ppw)

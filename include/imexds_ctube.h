@@ -116,9 +116,10 @@ int imexds_ct_enable_log(imexds_ct_ctx *ctx, int32_t max_steps);
 int imexds_ct_get_log(imexds_ct_ctx *ctx, int32_t *count, int32_t *flags, int32_t *rows);
 
 /* Launch shape of the zone kernel: zone_lanes 1 (one lane per tube, the two
- * boundaries in turn) or 2 (one lane per boundary), tubes per 64-lane wave
- * (zone_problems_per_wave * zone_lanes <= 64).  Results do not depend on
- * it. */
+ * boundaries in turn), 2 (one lane per boundary) or 4 (two lanes per
+ * boundary, one per side of its Riemann problem); tubes per 64-lane wave
+ * (zone_problems_per_wave * zone_lanes <= 64).  Default 4 lanes, 2 tubes
+ * per wave.  Results do not depend on it. */
 int imexds_ct_set_launch(imexds_ct_ctx *ctx, int32_t zone_lanes, int32_t zone_problems_per_wave);
 
 int imexds_ct_get_sizes(imexds_ct_ctx *ctx, int32_t *n_problems, int64_t *n_slots);

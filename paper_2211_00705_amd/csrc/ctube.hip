@@ -14,16 +14,17 @@
 //                                 neighbours of a creating face); epilogue:
 //                                 max(|u| + a) of the new state per tube and
 //                                 failure bits, one atomic per wave each.
-//   k_ct_zone   (1 or 2 lanes per tube): the creation step (step (ii) on the
-//                                 face, the neighbours, the new cell), or
-//                                 Algorithm 2 on the created cell +- Z cells
-//                                 with both phase boundaries solved by the
-//                                 interface solver (with 2 lanes, one per
-//                                 boundary, side by side).
+//   k_ct_create (lane per tube)  : the creation step (step (ii) on the face,
+//                                 the neighbours, the new cell).
+//   k_ct_zone   (1, 2 or 4 lanes per tube): Algorithm 2 on the created
+//                                 cell +- Z cells with both phase boundaries
+//                                 solved by the interface solver (2 lanes:
+//                                 one per boundary, side by side; 4: two per
+//                                 boundary, one per side of its problem).
 //   k_ct_fin    (lane per tube)  : t, steps, status, the mesh check and the
 //                                 next dt.
-// k_ct_bulk and k_ct_zone read U^n only and write disjoint slots of U^{n+1},
-// so they run concurrently on two streams.
+// k_ct_bulk and k_ct_create + k_ct_zone read U^n only and write disjoint
+// slots of U^{n+1}, so they run concurrently on two streams.
 //
 // Every expression is evaluated in the order written (-ffp-contract=off):
 // results are bitwise those of any IEEE FP64 evaluation of the same
@@ -219,20 +220,109 @@ __global__ __launch_bounds__(TILE) void k_ct_cfl(Args A) {
 }
 
 // ---------------------------------------------------------------------------
-// the implicit part of a step: creation, or Algorithm 2 on the created cell
-// +- Z cells.  L lanes per tube; with L = 2 lane `side` solves boundary
-// `side` (0 left, 1 right) and the two swap fluxes and speeds, so both hold
-// the same iterates and take every branch together.
+// the creation step (steps (ii), (iii), (v) on the creating face, step (iv)),
+// a lane per tube; the tubes with more than one creating face fail here
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_ct_create(Args A) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= A.P) return;
+  const double dt = A.dt[p];
+  const int cc = A.ccount[p];
+  if (dt == 0.0 || A.face[p] >= 0 || cc == 0) return;  // k_ct_zone's tubes
+  const long long lrow = A.log_row >= 0 ? (long long)A.log_row * A.P + p : -1;
+  int code = 0, fl = 0;
+  if (cc > 1) {
+    code = ST_MULTI;
+  } else {
+    const Mat& M = A.M;
+    const long long o = A.off[p];
+    const int N = A.N[p];
+    const double* __restrict__ r0 = A.r0 + o;
+    const double* __restrict__ m0 = A.m0 + o;
+    double* __restrict__ r1 = A.r1 + o;
+    double* __restrict__ m1 = A.m1 + o;
+    const int ph = A.phase[p], phn = 1 - ph;
+    const double h = A.h[p];
+    const int jc = A.cface[p];
+    double C[IMEXDS_CR_FIELDS];
+#pragma unroll
+    for (int i = 0; i < IMEXDS_CR_FIELDS; ++i) C[i] = 0.0;
+    if (imexds::c_solve(M, ph, r0[jc - 1], m0[jc - 1], r0[jc], m0[jc], A.newton_maxit,
+                        A.newton_rtol, C) != 1) {
+      code = ST_NEWTON;
+    } else {
+      const double wl = C[IMEXDS_CR_WL], wr = C[IMEXDS_CR_WR];
+      const double h1l = h + wl * dt, h1r = h - wr * dt;
+      const double ndl = wl * dt, ndr = wr * dt;
+      if (!(h1l > 0.0) || !(h1r > 0.0) || !(ndr - ndl > 0.0)) {
+        code = ST_MESH;
+      } else {
+        double F0, F1, G0, G1;
+        face_flux(A, ph, N, r0, m0, jc - 1, F0, F1);
+        face_flux(A, ph, N, r0, m0, jc + 1, G0, G1);
+        const double il = 1.0 / h1l, ir = 1.0 / h1r;
+        const double ra = (h * r0[jc - 1] - dt * (C[IMEXDS_CR_FL0] - F0)) * il;
+        const double ma = (h * m0[jc - 1] - dt * (C[IMEXDS_CR_FL1] - F1)) * il;
+        const double rc = (h * r0[jc] - dt * (G0 - C[IMEXDS_CR_FR0])) * ir;
+        const double mc = (h * m0[jc] - dt * (G1 - C[IMEXDS_CR_FR1])) * ir;
+        const double rb = C[IMEXDS_CR_RB], mb = C[IMEXDS_CR_RB] * C[IMEXDS_CR_UB];
+        r1[jc - 1] = ra;
+        m1[jc - 1] = ma;
+        r1[jc] = rc;
+        m1[jc] = mc;
+        r1[N] = rb;
+        m1[N] = mb;
+        if (!d_state_ok(ra, ma) || !d_state_ok(rc, mc) || !d_state_ok(rb, mb)) {
+          code = ST_NONPHYS;
+        } else {
+          A.dl[p] = ndl;
+          A.dr[p] = ndr;
+          double* pw = A.pw + 4 * (long long)p;
+          pw[0] = C[IMEXDS_CR_PA];
+          pw[1] = C[IMEXDS_CR_PB];
+          pw[2] = C[IMEXDS_CR_PB];
+          pw[3] = C[IMEXDS_CR_PC];
+          const unsigned long long va = speed_bits(M, ph, ra, ma);
+          const unsigned long long vc = speed_bits(M, ph, rc, mc);
+          const unsigned long long vb = speed_bits(M, phn, rb, mb);
+          unsigned long long v = va > vc ? va : vc;
+          v = vb > v ? vb : v;
+          atomicMax(A.S + p, v);
+        }
+        fl = FL_CREATED;
+      }
+    }
+  }
+  if (code) atomicOr(A.fail + p, code);
+  A.cnt[p] = 0;
+  if (lrow >= 0) {
+    A.log_cnt[lrow] = 0;
+    A.log_fl[lrow] = fl;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 2 on the created cell +- Z cells (and the carry-over of frozen
+// tubes).  L lanes per tube; with L = 2 lane `side` solves boundary `side`
+// (0 left, 1 right) and the two swap fluxes and speeds, so both hold the same
+// iterates and take every branch together.  Pass -1 of the loop is the
+// explicit prediction of the boundary speeds from U^n, passes 0 .. are the
+// pseudo steps, and the pass after the last one (stopped, or l = lmax)
+// evaluates the fluxes of the accepted iterate for Part 2: one call site of
+// the interface solver.
 // ---------------------------------------------------------------------------
 template <int Z, int L>
 __global__ __launch_bounds__(64) void k_ct_zone(Args A) {
   constexpr int MC = 2 * Z + 1;
+  constexpr int XB = L == 4 ? 2 : 1;  // lane distance between the two boundaries' lanes
   const int lane = (int)threadIdx.x;
   if (lane >= A.zone_ppw * L) return;
   const int p = blockIdx.x * A.zone_ppw + lane / L;
-  const int side = L == 2 ? (lane & 1) : 0;
-  if (p >= A.P) return;  // pairs are whole
-  const bool writer = side == 0;
+  const int sub = lane & (L - 1);
+  const int side = L == 4 ? (sub >> 1) : sub;  // the boundary this lane solves (L = 1: both)
+  const int half = L == 4 ? (sub & 1) : 0;     // L = 4: the side of that boundary's problem
+  if (p >= A.P) return;  // the lanes of a tube are whole
+  const bool writer = sub == 0;
   const long long o = A.off[p];
   const int N = A.N[p];
   const double* __restrict__ r0 = A.r0 + o;
@@ -241,19 +331,25 @@ __global__ __launch_bounds__(64) void k_ct_zone(Args A) {
   double* __restrict__ m1 = A.m1 + o;
   const double dt = A.dt[p];
   const long long lrow = A.log_row >= 0 ? (long long)A.log_row * A.P + p : -1;
-  int a, b;
-  implicit_range(A, p, N, a, b);
-  if (dt == 0.0) {
+  const int j0 = A.face[p];
+  if (dt == 0.0 || j0 < 0) {
+    if (dt != 0.0 && A.ccount[p] != 0) return;  // k_ct_create's tubes
     if (writer) {
-      for (int c = a; c < b; ++c) {
-        r1[c] = r0[c];
-        m1[c] = m0[c];
+      if (dt == 0.0) {
+        int a, b;
+        implicit_range(A, p, N, a, b);
+        for (int c = a; c < b; ++c) {
+          r1[c] = r0[c];
+          m1[c] = m0[c];
+        }
       }
+      // the created slot, unused or frozen, is carried over
       r1[N] = r0[N];
       m1[N] = m0[N];
+      if (dt != 0.0) A.cnt[p] = 0;
       if (lrow >= 0) {
         A.log_cnt[lrow] = 0;
-        A.log_fl[lrow] = FL_INACTIVE;
+        A.log_fl[lrow] = dt == 0.0 ? FL_INACTIVE : 0;
       }
     }
     return;
@@ -261,118 +357,85 @@ __global__ __launch_bounds__(64) void k_ct_zone(Args A) {
   const Mat& M = A.M;
   const int ph = A.phase[p], phn = 1 - ph;
   const double h = A.h[p];
-  const int j0 = A.face[p];
-  const int cc = A.ccount[p];
   int code = 0, cnt = 0, fl = 0;
-  unsigned long long vmax = 0;
-  if (j0 < 0 && cc > 1) {
-    code = ST_MULTI;
-  } else if (j0 < 0 && cc == 1) {
-    // creation step: steps (ii), (iii), (v) on face jc, step (iv)
-    if (writer) {
-      const int jc = A.cface[p];
-      double C[IMEXDS_CR_FIELDS];
+  const double dl = A.dl[p], dr = A.dr[p];
+  double* pwp = A.pw + 4 * (long long)p;
+  double U0[MC][2], hn[MC], hh[MC], th[MC], i1t[MC], thr[MC], W[MC][2];
+  int kind[MC];
 #pragma unroll
-      for (int i = 0; i < IMEXDS_CR_FIELDS; ++i) C[i] = 0.0;
-      if (imexds::c_solve(M, ph, r0[jc - 1], m0[jc - 1], r0[jc], m0[jc], A.newton_maxit,
-                          A.newton_rtol, C) != 1) {
-        code = ST_NEWTON;
-      } else {
-        const double wl = C[IMEXDS_CR_WL], wr = C[IMEXDS_CR_WR];
-        const double h1l = h + wl * dt, h1r = h - wr * dt;
-        const double ndl = wl * dt, ndr = wr * dt;
-        if (!(h1l > 0.0) || !(h1r > 0.0) || !(ndr - ndl > 0.0)) {
-          code = ST_MESH;
-        } else {
-          double F0, F1, G0, G1;
-          face_flux(A, ph, N, r0, m0, jc - 1, F0, F1);
-          face_flux(A, ph, N, r0, m0, jc + 1, G0, G1);
-          const double il = 1.0 / h1l, ir = 1.0 / h1r;
-          const double ra = (h * r0[jc - 1] - dt * (C[IMEXDS_CR_FL0] - F0)) * il;
-          const double ma = (h * m0[jc - 1] - dt * (C[IMEXDS_CR_FL1] - F1)) * il;
-          const double rc = (h * r0[jc] - dt * (G0 - C[IMEXDS_CR_FR0])) * ir;
-          const double mc = (h * m0[jc] - dt * (G1 - C[IMEXDS_CR_FR1])) * ir;
-          const double rb = C[IMEXDS_CR_RB], mb = C[IMEXDS_CR_RB] * C[IMEXDS_CR_UB];
-          r1[jc - 1] = ra;
-          m1[jc - 1] = ma;
-          r1[jc] = rc;
-          m1[jc] = mc;
-          r1[N] = rb;
-          m1[N] = mb;
-          if (!d_state_ok(ra, ma) || !d_state_ok(rc, mc) || !d_state_ok(rb, mb)) {
-            code = ST_NONPHYS;
-          } else {
-            A.dl[p] = ndl;
-            A.dr[p] = ndr;
-            double* pw = A.pw + 4 * (long long)p;
-            pw[0] = C[IMEXDS_CR_PA];
-            pw[1] = C[IMEXDS_CR_PB];
-            pw[2] = C[IMEXDS_CR_PB];
-            pw[3] = C[IMEXDS_CR_PC];
-            const unsigned long long va = speed_bits(M, ph, ra, ma);
-            const unsigned long long vc = speed_bits(M, ph, rc, mc);
-            const unsigned long long vb = speed_bits(M, phn, rb, mb);
-            vmax = va > vc ? va : vc;
-            vmax = vb > vmax ? vb : vmax;
-          }
-          fl = FL_CREATED;
-        }
-      }
-    }
-  } else if (j0 >= 0) {
-    // Algorithm 2 on cells j0-Z .. j0-1, the created cell, j0 .. j0+Z-1
-    const double dl = A.dl[p], dr = A.dr[p];
-    double* pwp = A.pw + 4 * (long long)p;
-    double U0[MC][2], hn[MC], hh[MC], th[MC], i1t[MC], thr[MC], W[MC][2];
-    int kind[MC];
-#pragma unroll
-    for (int k = 0; k < MC; ++k) {
-      const int sl = k < Z ? j0 - Z + k : (k == Z ? N : j0 + (k - Z - 1));
-      U0[k][0] = r0[sl];
-      U0[k][1] = m0[sl];
-      kind[k] = k == Z - 1 ? 1 : (k == Z ? 2 : (k == Z + 1 ? 3 : 0));
-      hn[k] = k == Z - 1 ? h + dl : (k == Z ? dr - dl : (k == Z + 1 ? h - dr : h));
-    }
-    double FL0, FL1, FR0, FR1;
-    face_flux(A, ph, N, r0, m0, j0 - Z, FL0, FL1);
-    face_flux(A, ph, N, r0, m0, j0 + Z, FR0, FR1);
-    // explicit prediction of the boundary speeds from U^n; lane `side`
-    // solves boundary `side` (one lane: both in turn); warm starts
-    // (pl0, pl1) of the left boundary, (pr0, pr1) of the right one
-    double wl = 0.0, wr = 0.0;
-    double pl0 = pwp[0], pl1 = pwp[1], pr0 = pwp[2], pr1 = pwp[3];
-    int bad = 0;
+  for (int k = 0; k < MC; ++k) {
+    const int sl = k < Z ? j0 - Z + k : (k == Z ? N : j0 + (k - Z - 1));
+    U0[k][0] = r0[sl];
+    U0[k][1] = m0[sl];
+    W[k][0] = U0[k][0];
+    W[k][1] = U0[k][1];
+    kind[k] = k == Z - 1 ? 1 : (k == Z ? 2 : (k == Z + 1 ? 3 : 0));
+    hn[k] = k == Z - 1 ? h + dl : (k == Z ? dr - dl : (k == Z + 1 ? h - dr : h));
+    hh[k] = hn[k];
+    th[k] = 0.0;
+    i1t[k] = 1.0;
+    thr[k] = 0.0;
+  }
+  double F[MC + 1][2];
+  face_flux(A, ph, N, r0, m0, j0 - Z, F[0][0], F[0][1]);
+  face_flux(A, ph, N, r0, m0, j0 + Z, F[MC][0], F[MC][1]);
+  // boundary speeds and warm starts (pl0, pl1) of the left boundary,
+  // (pr0, pr1) of the right one
+  double wl = 0.0, wr = 0.0;
+  double pl0 = pwp[0], pl1 = pwp[1], pr0 = pwp[2], pr1 = pwp[3];
+  bool stop = false;
 #pragma unroll 1
-    for (int f = side; f < 2; f += L) {
+  for (int l = -1;; ++l) {
+    const bool part2 = l >= 0 && (stop || l == A.lmax);
+    // the two phase boundaries at the current iterate (pass -1: U^n = W)
+    int ec = 0;
+    double bl0 = 0.0, bl1 = 0.0, br0 = 0.0, br1 = 0.0;
+#pragma unroll 1
+    for (int f = side; f < 2; f += (L == 1 ? 1 : 2)) {
       const bool lf = f == 0;
       IfaceOut I;
-      if (!imexds::d_iface_solve(M, A.newton_maxit, A.newton_rtol, lf ? ph : phn,
-                                 lf ? U0[Z - 1][0] : U0[Z][0], lf ? U0[Z - 1][1] : U0[Z][1],
-                                 lf ? phn : ph, lf ? U0[Z][0] : U0[Z + 1][0],
-                                 lf ? U0[Z][1] : U0[Z + 1][1], true, lf ? pl0 : pr0,
-                                 lf ? pl1 : pr1, I)) {
-        bad = 1;
+      // L = 4: the two lanes of a boundary split its problem by side
+      if (!imexds::d_iface_solve_t<L == 4>(M, A.newton_maxit, A.newton_rtol, lf ? ph : phn,
+                                           lf ? W[Z - 1][0] : W[Z][0], lf ? W[Z - 1][1] : W[Z][1],
+                                           lf ? phn : ph, lf ? W[Z][0] : W[Z + 1][0],
+                                           lf ? W[Z][1] : W[Z + 1][1], true, lf ? pl0 : pr0,
+                                           lf ? pl1 : pr1, half, lane ^ 1, I)) {
+        ec = 1;
       } else if (lf) {
         wl = I.w;
         pl0 = I.pl;
         pl1 = I.pr;
+        bl0 = I.F0;
+        bl1 = I.F1;
       } else {
         wr = I.w;
         pr0 = I.pl;
         pr1 = I.pr;
+        br0 = I.F0;
+        br1 = I.F1;
       }
     }
-    if (L == 2) {
-      const double y = __shfl_xor(side ? wr : wl, 1, 64);
-      if (side)
-        wl = y;
-      else
-        wr = y;
-      bad |= __shfl_xor(bad, 1, 64);
+    if (L > 1) {
+      const double y0 = __shfl_xor(side ? br0 : bl0, XB, 64);
+      const double y1 = __shfl_xor(side ? br1 : bl1, XB, 64);
+      const double yw = __shfl_xor(side ? wr : wl, XB, 64);
+      ec |= __shfl_xor(ec, XB, 64);
+      if (side) {
+        bl0 = y0;
+        bl1 = y1;
+        wl = yw;
+      } else {
+        br0 = y0;
+        br1 = y1;
+        wr = yw;
+      }
     }
-    if (bad) {
+    if (ec) {
       code = ST_NEWTON;
-    } else {
+      break;
+    }
+    if (l < 0) {
+      // predicted end-of-step lengths and the pseudo step fractions
 #pragma unroll
       for (int k = 0; k < MC; ++k) {
         const double hk = cell_len(hn[k], kind[k], wl, wr, dt);
@@ -383,135 +446,78 @@ __global__ __launch_bounds__(64) void k_ct_zone(Args A) {
         i1t[k] = 1.0 / (1.0 + t);
         thr[k] = (k == Z ? A.tol_tiny : A.tol_nb) * (t * dt);
         if (!(t > 0.0)) code = ST_MESH;
-        W[k][0] = U0[k][0];
-        W[k][1] = U0[k][1];
       }
+      if (code) break;
+      continue;
     }
-    double F[MC + 1][2];
-    bool stop = false;
+    F[Z][0] = bl0;
+    F[Z][1] = bl1;
+    F[Z + 1][0] = br0;
+    F[Z + 1][1] = br1;
+#pragma unroll
+    for (int c = 0; c + 1 < MC; ++c)
+      if (c != Z - 1 && c != Z)
+        d_hll(M, ph, W[c][0], W[c][1], W[c + 1][0], W[c + 1][1], F[c + 1][0], F[c + 1][1]);
+    double ih[MC];
+    bool shrink = false;
+#pragma unroll
+    for (int k = 0; k < MC; ++k) {
+      const double hk = cell_len(hn[k], kind[k], wl, wr, dt);
+      ih[k] = 1.0 / hk;
+      if (kind[k] != 0 && !(hk >= 0.5 * hh[k])) shrink = true;
+    }
+    if (shrink) {
+      code = ST_MESH;
+      break;
+    }
+    if (part2) {
+      // Part 2: conservative update with the fluxes of the accepted iterate
+#pragma unroll
+      for (int k = 0; k < MC; ++k) {
+        const double u0 = (hn[k] * U0[k][0] - dt * (F[k + 1][0] - F[k][0])) * ih[k];
+        const double u1 = (hn[k] * U0[k][1] - dt * (F[k + 1][1] - F[k][1])) * ih[k];
+        W[k][0] = u0;
+        W[k][1] = u1;
+        if (!d_state_ok(u0, u1)) code = ST_NONPHYS;
+      }
+      break;
+    }
+    bool conv = true, okst = true;
+#pragma unroll
+    for (int k = 0; k < MC; ++k) {
+      const double opt = 1.0 + th[k];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const double rhs = (hn[k] * U0[k][q] - dt * (F[k + 1][q] - F[k][q])) * ih[k];
+        const double wn = (W[k][q] + th[k] * rhs) * i1t[k];
+        const double d = wn - W[k][q];
+        const double sc = fabs(W[k][q]) > 1.0 ? fabs(W[k][q]) : 1.0;
+        const bool ok = A.tol_mode == 0 ? (fabs(opt * d) < thr[k] * sc)
+                                        : (fabs(d) < A.tol_rel * sc);
+        conv = conv && ok;
+        W[k][q] = wn;
+      }
+      okst = okst && d_state_ok(W[k][0], W[k][1]);
+    }
+    if (!okst) {
+      code = ST_NONPHYS;
+      break;
+    }
+    cnt = l + 1;
+    stop = conv;
+  }
+  if (!code && !stop) fl |= FL_LMAX;
+  if (L > 1) {
+    // the writer takes the right boundary's warm start from its partner
+    const double q0 = __shfl_xor(pr0, XB, 64), q1 = __shfl_xor(pr1, XB, 64);
+    if (side == 0) {
+      pr0 = q0;
+      pr1 = q1;
+    }
+  }
+  if (writer) {
+    unsigned long long vmax = 0;
     if (!code) {
-      F[0][0] = FL0;
-      F[0][1] = FL1;
-      F[MC][0] = FR0;
-      F[MC][1] = FR1;
-      // pass l < lmax: pseudo step l; the pass after the last one (stopped
-      // or l = lmax) evaluates the fluxes of the accepted iterate (Part 2)
-#pragma unroll 1
-      for (int l = 0;; ++l) {
-        const bool part2 = stop || l == A.lmax;
-        // the two phase boundaries
-        int ec = 0;
-        double bl0 = 0.0, bl1 = 0.0, br0 = 0.0, br1 = 0.0;
-#pragma unroll 1
-        for (int f = side; f < 2; f += L) {
-          const bool lf = f == 0;
-          IfaceOut I;
-          if (!imexds::d_iface_solve(M, A.newton_maxit, A.newton_rtol, lf ? ph : phn,
-                                     lf ? W[Z - 1][0] : W[Z][0], lf ? W[Z - 1][1] : W[Z][1],
-                                     lf ? phn : ph, lf ? W[Z][0] : W[Z + 1][0],
-                                     lf ? W[Z][1] : W[Z + 1][1], true, lf ? pl0 : pr0,
-                                     lf ? pl1 : pr1, I)) {
-            ec = 1;
-          } else if (lf) {
-            wl = I.w;
-            pl0 = I.pl;
-            pl1 = I.pr;
-            bl0 = I.F0;
-            bl1 = I.F1;
-          } else {
-            wr = I.w;
-            pr0 = I.pl;
-            pr1 = I.pr;
-            br0 = I.F0;
-            br1 = I.F1;
-          }
-        }
-        if (L == 2) {
-          const double y0 = __shfl_xor(side ? br0 : bl0, 1, 64);
-          const double y1 = __shfl_xor(side ? br1 : bl1, 1, 64);
-          const double yw = __shfl_xor(side ? wr : wl, 1, 64);
-          ec |= __shfl_xor(ec, 1, 64);
-          if (side) {
-            bl0 = y0;
-            bl1 = y1;
-            wl = yw;
-          } else {
-            br0 = y0;
-            br1 = y1;
-            wr = yw;
-          }
-        }
-        if (ec) {
-          code = ST_NEWTON;
-          break;
-        }
-        F[Z][0] = bl0;
-        F[Z][1] = bl1;
-        F[Z + 1][0] = br0;
-        F[Z + 1][1] = br1;
-#pragma unroll
-        for (int c = 0; c + 1 < MC; ++c)
-          if (c != Z - 1 && c != Z)
-            d_hll(M, ph, W[c][0], W[c][1], W[c + 1][0], W[c + 1][1], F[c + 1][0], F[c + 1][1]);
-        double ih[MC];
-        bool shrink = false;
-#pragma unroll
-        for (int k = 0; k < MC; ++k) {
-          const double hk = cell_len(hn[k], kind[k], wl, wr, dt);
-          ih[k] = 1.0 / hk;
-          if (kind[k] != 0 && !(hk >= 0.5 * hh[k])) shrink = true;
-        }
-        if (shrink) {
-          code = ST_MESH;
-          break;
-        }
-        if (part2) {
-          // Part 2: conservative update with the fluxes of the accepted iterate
-#pragma unroll
-          for (int k = 0; k < MC; ++k) {
-            const double u0 = (hn[k] * U0[k][0] - dt * (F[k + 1][0] - F[k][0])) * ih[k];
-            const double u1 = (hn[k] * U0[k][1] - dt * (F[k + 1][1] - F[k][1])) * ih[k];
-            W[k][0] = u0;
-            W[k][1] = u1;
-            if (!d_state_ok(u0, u1)) code = ST_NONPHYS;
-          }
-          break;
-        }
-        bool conv = true, okst = true;
-#pragma unroll
-        for (int k = 0; k < MC; ++k) {
-          const double opt = 1.0 + th[k];
-#pragma unroll
-          for (int q = 0; q < 2; ++q) {
-            const double rhs = (hn[k] * U0[k][q] - dt * (F[k + 1][q] - F[k][q])) * ih[k];
-            const double wn = (W[k][q] + th[k] * rhs) * i1t[k];
-            const double d = wn - W[k][q];
-            const double sc = fabs(W[k][q]) > 1.0 ? fabs(W[k][q]) : 1.0;
-            const bool ok = A.tol_mode == 0 ? (fabs(opt * d) < thr[k] * sc)
-                                            : (fabs(d) < A.tol_rel * sc);
-            conv = conv && ok;
-            W[k][q] = wn;
-          }
-          okst = okst && d_state_ok(W[k][0], W[k][1]);
-        }
-        if (!okst) {
-          code = ST_NONPHYS;
-          break;
-        }
-        cnt = l + 1;
-        stop = conv;
-      }
-      if (!code && !stop) fl |= FL_LMAX;
-    }
-    if (L == 2) {
-      // the writer takes the right boundary's warm start from its partner
-      const double q0 = __shfl_xor(pr0, 1, 64), q1 = __shfl_xor(pr1, 1, 64);
-      if (side == 0) {
-        pr0 = q0;
-        pr1 = q1;
-      }
-    }
-    if (writer && !code) {
 #pragma unroll
       for (int k = 0; k < MC; ++k) {
         const int sl = k < Z ? j0 - Z + k : (k == Z ? N : j0 + (k - Z - 1));
@@ -526,19 +532,14 @@ __global__ __launch_bounds__(64) void k_ct_zone(Args A) {
       pwp[1] = pl1;
       pwp[2] = pr0;
       pwp[3] = pr1;
+      atomicMax(A.S + p, vmax);
+    } else {
+      atomicOr(A.fail + p, code);
     }
-  }
-  if (writer) {
-    if (j0 < 0 && cc == 0) {  // nothing created: the unused slot is carried over
-      r1[N] = r0[N];
-      m1[N] = m0[N];
-    }
-    if (vmax) atomicMax(A.S + p, vmax);
-    if (code) atomicOr(A.fail + p, code);
     A.cnt[p] = code ? 0 : cnt;
     if (lrow >= 0) {
       A.log_cnt[lrow] = code ? 0 : cnt;
-      A.log_fl[lrow] = code ? (fl & FL_CREATED) : fl;
+      A.log_fl[lrow] = code ? 0 : fl;
     }
   }
 }
@@ -624,7 +625,7 @@ struct imexds_ct_ctx {
   double* U[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   int cur = 0;
   int *tile_prob = nullptr, *tile_start = nullptr;
-  int n_tiles = 0, zone_lanes = 2, zone_ppw = 32;
+  int n_tiles = 0, zone_lanes = 4, zone_ppw = 2;
   int *log_cnt = nullptr, *log_fl = nullptr;
   int log_max = 0, log_row = 0;
   bool have_state = false;
@@ -710,14 +711,17 @@ ct::Args ct_args(const imexds_ct_ctx* c, int parity) {
 hipError_t ct_launch_zone(const ct::Args& A, int lanes, hipStream_t s) {
   if (A.P <= 0) return hipSuccess;
   const int blocks = (A.P + A.zone_ppw - 1) / A.zone_ppw;
-  const int key = A.Z * 2 + (lanes == 2 ? 1 : 0);
+  const int key = A.Z * 10 + lanes;
   switch (key) {
-    case 2: ct::k_ct_zone<1, 1><<<blocks, 64, 0, s>>>(A); break;
-    case 3: ct::k_ct_zone<1, 2><<<blocks, 64, 0, s>>>(A); break;
-    case 4: ct::k_ct_zone<2, 1><<<blocks, 64, 0, s>>>(A); break;
-    case 5: ct::k_ct_zone<2, 2><<<blocks, 64, 0, s>>>(A); break;
-    case 6: ct::k_ct_zone<3, 1><<<blocks, 64, 0, s>>>(A); break;
-    case 7: ct::k_ct_zone<3, 2><<<blocks, 64, 0, s>>>(A); break;
+    case 11: ct::k_ct_zone<1, 1><<<blocks, 64, 0, s>>>(A); break;
+    case 12: ct::k_ct_zone<1, 2><<<blocks, 64, 0, s>>>(A); break;
+    case 14: ct::k_ct_zone<1, 4><<<blocks, 64, 0, s>>>(A); break;
+    case 21: ct::k_ct_zone<2, 1><<<blocks, 64, 0, s>>>(A); break;
+    case 22: ct::k_ct_zone<2, 2><<<blocks, 64, 0, s>>>(A); break;
+    case 24: ct::k_ct_zone<2, 4><<<blocks, 64, 0, s>>>(A); break;
+    case 31: ct::k_ct_zone<3, 1><<<blocks, 64, 0, s>>>(A); break;
+    case 32: ct::k_ct_zone<3, 2><<<blocks, 64, 0, s>>>(A); break;
+    case 34: ct::k_ct_zone<3, 4><<<blocks, 64, 0, s>>>(A); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -770,6 +774,10 @@ int ct_one_step(imexds_ct_ctx* c) {
   if (!e) e = ct_err(hipEventRecord(c->ev_fork, c->ms));
   if (!e) e = ct_err(hipStreamWaitEvent(c->zs, c->ev_fork, 0));
   if (!e && tm) e = ct_err(hipEventRecord(ev[3], c->zs));
+  if (!e && A.P > 0) {
+    ct::k_ct_create<<<(A.P + 63) / 64, 64, 0, c->zs>>>(A);
+    e = ct_err(hipGetLastError());
+  }
   if (!e) e = ct_err(ct_launch_zone(A, c->zone_lanes, c->zs));
   if (!e && tm) e = ct_err(hipEventRecord(ev[4], c->zs));
   if (!e && tm) e = ct_err(hipEventRecord(ev[1], c->ms));
@@ -1031,7 +1039,7 @@ int imexds_ct_get_log(imexds_ct_ctx* c, int32_t* count, int32_t* flags, int32_t*
 
 int imexds_ct_set_launch(imexds_ct_ctx* c, int32_t zone_lanes, int32_t zone_problems_per_wave) {
   if (!c) return IMEXDS_ERR_INVALID_ARG;
-  if (zone_lanes != 1 && zone_lanes != 2) return IMEXDS_ERR_INVALID_ARG;
+  if (zone_lanes != 1 && zone_lanes != 2 && zone_lanes != 4) return IMEXDS_ERR_INVALID_ARG;
   if (zone_problems_per_wave < 1 || zone_problems_per_wave * zone_lanes > 64)
     return IMEXDS_ERR_INVALID_ARG;
   int e = ct_err(hipSetDevice(c->device));

@@ -198,7 +198,7 @@ class CreationTubes:
     def log(self):
         return imexds_ct_get_log(self.ctx, self._log_max)
 
-    def set_launch(self, zone_lanes=2, zone_problems_per_wave=4):
+    def set_launch(self, zone_lanes=4, zone_problems_per_wave=2):
         imexds_ct_set_launch(self.ctx, zone_lanes, zone_problems_per_wave)
 
     def time_kernels(self, on=True):
