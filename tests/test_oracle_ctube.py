@@ -202,3 +202,37 @@ def test_batch_generator_is_deterministic_and_creates_everywhere():
     assert np.array_equal(b1.rho, b2.rho) and np.array_equal(b1.N, b2.N)
     st = run(b1.with_params(lmax=200), 2)
     assert np.all(st.status == 0) and np.all(st.face == b1.N // 2)
+
+
+@pytest.mark.parametrize("case", [CW.CAVITATION, (LIQ, (66000.0, -5.2), (60000.0, 2.8))])
+def test_dual_time_fixed_point_is_the_implicit_step(case):
+    """Algorithm 2 run to a tight relative update (1e-15) lands on the
+    implicit step of the zone: with the separately pinned interface solver
+    and HLL flux evaluated at U^{n+1}, every zone cell satisfies
+    h^{n+1} U^{n+1} - h^n U^n + dt (F_{i+1/2} - F_{i-1/2}) = 0 (moving
+    lengths, eq. godunov_meth:nonunif; outer zone faces from U^n), and the
+    boundaries moved by w(U^{n+1}) dt."""
+    b = CW.concat([CW.spec(case, 40)], "fp").with_params(tol_mode=1, tol_rel=1e-15,
+                                                         lmax=1_000_000, t_end=1.0)
+    s0 = run(b, 3)
+    s1 = run(b, 4)
+    assert s1.status[0] == 0 and s1.steps[0] == 4 and s1.face[0] == 20
+    ph, phn, N, j0, h = case[0], 1 - case[0], 40, 20, b.h[0]
+    dt = s1.t[0] - s0.t[0]
+    h0 = [h + s0.dl[0], s0.dr[0] - s0.dl[0], h - s0.dr[0]]
+    h1 = [h + s1.dl[0], s1.dr[0] - s1.dl[0], h - s1.dr[0]]
+    u = lambda s, c: s.mom[c] / s.rho[c]
+    L = oracle.iface_solve(M, ph, s1.rho[j0 - 1], u(s1, j0 - 1), phn, s1.rho[N], u(s1, N))
+    R = oracle.iface_solve(M, phn, s1.rho[N], u(s1, N), ph, s1.rho[j0], u(s1, j0))
+    assert L["ok"] and R["ok"]
+    FL = oracle.hll(M, ph, s0.rho[j0 - 2], s0.mom[j0 - 2], s0.rho[j0 - 1], s0.mom[j0 - 1])
+    FR = oracle.hll(M, ph, s0.rho[j0], s0.mom[j0], s0.rho[j0 + 1], s0.mom[j0 + 1])
+    F = [FL, (L["F0"], L["F1"]), (R["F0"], R["F1"]), FR]
+    for k, c in enumerate((j0 - 1, N, j0)):
+        for q, (a0, a1) in enumerate(((s0.rho, s1.rho), (s0.mom, s1.mom))):
+            res = h1[k] * a1[c] - h0[k] * a0[c] + dt * (F[k + 1][q] - F[k][q])
+            scale = max(abs(h1[k] * a1[c]), abs(h0[k] * a0[c]), abs(dt * F[k][q]),
+                        abs(dt * F[k + 1][q]))
+            assert abs(res) < 1e-11 * scale, (k, q, res / scale)
+    assert abs((s1.dl[0] - s0.dl[0]) / (L["w"] * dt) - 1.0) < 1e-12
+    assert abs((s1.dr[0] - s0.dr[0]) / (R["w"] * dt) - 1.0) < 1e-12
