@@ -124,7 +124,8 @@ def lib():
                                           ip, ip, ctypes.c_int])
         L.oracle_ct_run.restype = ctypes.c_int
         L.oracle_ct_run.argtypes = ([ctypes.POINTER(_Mat), ctypes.POINTER(_Par), ctypes.c_double,
-                                     ctypes.c_double, ctypes.c_int, ip, dp, ip, lp, dp, dp, ip,
+                                     ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                     ctypes.c_int, ip, dp, ip, lp, dp, dp, ip,
                                      dp, dp, dp, dp, ip, ip, lp, ctypes.c_int, ip, ip,
                                      ctypes.c_int])
         _lib = L
@@ -475,9 +476,15 @@ class CTubeState:
         self.iters = np.zeros(P, dtype=np.int64)
 
 
-def ct_run(state, n_steps=None, threads=1, log=False):
-    """Advances every creation tube by up to n_steps steps (None: to t_end).
-    With log=True returns (counts, flags), each [n_steps, P]."""
+CT_SOLVER_DTS, CT_SOLVER_NEWTON = 0, 1
+
+
+def ct_run(state, n_steps=None, threads=1, log=False, solver=CT_SOLVER_DTS, zn_maxit=30,
+           zn_rtol=1e-10):
+    """Advances every creation tube by up to n_steps steps (None: to t_end),
+    the zone solved by Algorithm 2 (CT_SOLVER_DTS) or by Newton
+    (CT_SOLVER_NEWTON: at most zn_maxit steps, tolerance zn_rtol).  With
+    log=True returns (counts, flags), each [n_steps, P]."""
     b = state.batch
     P = b.n_problems
     if n_steps is None:
@@ -495,7 +502,8 @@ def ct_run(state, n_steps=None, threads=1, log=False):
     d, i, l = ctypes.c_double, ctypes.c_int, ctypes.c_longlong
     m, par = _mat(b.material), _par(b.params)
     rc = lib().oracle_ct_run(ctypes.byref(m), ctypes.byref(par), float(b.p_min),
-                             float(b.p_tilde), P, _ptr(N, i), _ptr(h, d), _ptr(ph, i),
+                             float(b.p_tilde), int(solver), int(zn_maxit), float(zn_rtol), P,
+                             _ptr(N, i), _ptr(h, d), _ptr(ph, i),
                              _ptr(off, l), _ptr(state.rho, d), _ptr(state.mom, d),
                              _ptr(state.face, i), _ptr(state.dl, d), _ptr(state.dr, d),
                              _ptr(state.pw, d), _ptr(state.t, d), _ptr(state.status, i),

@@ -1816,9 +1816,134 @@ static int or_ct_dts(const or_material *M, const or_params *P, int ph, const or_
   return 0;
 }
 
+/* Newton on the implicit step of the zone, the alternative to Algorithm 2
+ * that the paper's outlook names (a Newton-like solver for the small
+ * implicit systems).  Unknowns the zone iterates W (2 per cell), equations
+ *   R_c(W) = (h_c(W) / h_c^n) W_c - U_c^n + (dt / h_c^n)(F_{c+1/2}(W) - F_{c-1/2}(W))
+ * with the lengths h_c(W) from the boundary speeds at W and the outer zone
+ * faces from U^n (the fixed point of Algorithm 2).  From W = U^n: the
+ * Jacobian by forward differences (step 1e-7 max(|W_j|, 1), boundary solves
+ * warm-started from the current iterate's), Gaussian elimination with
+ * partial pivoting (first largest pivot), the full step; converged when
+ * every step component is below rtol max(|W_j|, 1) (the step is taken); at
+ * most maxit steps (then flagged like l_max).  Part 2 as in Algorithm 2.
+ * The shrink and state checks of Algorithm 2 apply to every iterate. */
+#define OR_CT_NMAX (2 * OR_MAXC)
+
+static int or_ct_resid(const or_material *M, const or_params *P, int ph, const or_ctzone *Z,
+                       double dt, double W[][2], double *pwl, double *pwr, double *R,
+                       double *wl, double *wr, int check) {
+  double F[OR_MAXC + 1][2];
+  int c, q;
+  if (!or_ct_fluxes(M, P, ph, Z, W, F, pwl, pwr, wl, wr)) return OR_CT_ST_NEWTON;
+  for (c = 0; c < Z->m; ++c) {
+    double hk = or_ct_len(Z->hn[c], Z->kind[c], *wl, *wr, dt);
+    if (check && Z->kind[c] != 0 && !(hk >= 0.5 * Z->hh[c])) return OR_CT_ST_MESH;
+    double ihn = 1.0 / Z->hn[c];
+    for (q = 0; q < 2; ++q)
+      R[2 * c + q] = (hk * ihn) * W[c][q] - Z->U0[c][q] + (dt * ihn) * (F[c + 1][q] - F[c][q]);
+  }
+  return 0;
+}
+
+/* A x = b by Gaussian elimination with partial pivoting (the first row with
+ * the largest |pivot|); A and b are overwritten; 0 if singular */
+static int or_gauss_pp(int n, double A[][OR_CT_NMAX], double *b, double *x) {
+  int k, i, j;
+  for (k = 0; k < n; ++k) {
+    int piv = k;
+    for (i = k + 1; i < n; ++i)
+      if (fabs(A[i][k]) > fabs(A[piv][k])) piv = i;
+    if (piv != k) {
+      for (j = 0; j < n; ++j) {
+        double t = A[k][j];
+        A[k][j] = A[piv][j];
+        A[piv][j] = t;
+      }
+      double t = b[k];
+      b[k] = b[piv];
+      b[piv] = t;
+    }
+    if (!(A[k][k] != 0.0) || !isfinite(A[k][k])) return 0;
+    for (i = k + 1; i < n; ++i) {
+      double f = A[i][k] / A[k][k];
+      for (j = k + 1; j < n; ++j) A[i][j] = A[i][j] - f * A[k][j];
+      b[i] = b[i] - f * b[k];
+    }
+  }
+  for (i = n - 1; i >= 0; --i) {
+    double sum = b[i];
+    for (j = i + 1; j < n; ++j) sum = sum - A[i][j] * x[j];
+    x[i] = sum / A[i][i];
+    if (!isfinite(x[i])) return 0;
+  }
+  return 1;
+}
+
+static int or_ct_newton(const or_material *M, const or_params *P, int ph, const or_ctzone *Z,
+                        double dt, double *pwl, double *pwr, int maxit, double rtol,
+                        double U1[][2], double *wls, double *wrs, int *count, int *lmax_hit) {
+  int m = Z->m, n = 2 * m, c, q, j, it, conv = 0;
+  double W[OR_MAXC][2], R[OR_CT_NMAX], Rp[OR_CT_NMAX], J[OR_CT_NMAX][OR_CT_NMAX];
+  double rhs[OR_CT_NMAX], d[OR_CT_NMAX], wl = 0.0, wr = 0.0;
+  *lmax_hit = 0;
+  *count = 0;
+  for (c = 0; c < m; ++c) {
+    W[c][0] = Z->U0[c][0];
+    W[c][1] = Z->U0[c][1];
+  }
+  for (it = 0; it < maxit && !conv; ++it) {
+    int st = or_ct_resid(M, P, ph, Z, dt, W, pwl, pwr, R, &wl, &wr, 1);
+    if (st) return st;
+    for (j = 0; j < n; ++j) {
+      int cj = j / 2, qj = j % 2;
+      double xj = W[cj][qj];
+      double e = 1e-7 * (fabs(xj) > 1.0 ? fabs(xj) : 1.0);
+      double gl[2] = {pwl[0], pwl[1]}, gr[2] = {pwr[0], pwr[1]}, a, b2;
+      W[cj][qj] = xj + e;
+      st = or_ct_resid(M, P, ph, Z, dt, W, gl, gr, Rp, &a, &b2, 0);
+      W[cj][qj] = xj;
+      if (st) return st;
+      for (q = 0; q < n; ++q) J[q][j] = (Rp[q] - R[q]) / e;
+    }
+    for (q = 0; q < n; ++q) rhs[q] = -R[q];
+    if (!or_gauss_pp(n, J, rhs, d)) return OR_CT_ST_NEWTON;
+    conv = 1;
+    for (j = 0; j < n; ++j) {
+      double xj = W[j / 2][j % 2];
+      double sc = fabs(xj) > 1.0 ? fabs(xj) : 1.0;
+      conv = conv && (fabs(d[j]) <= rtol * sc);
+    }
+    for (c = 0; c < m; ++c) {
+      W[c][0] = W[c][0] + d[2 * c];
+      W[c][1] = W[c][1] + d[2 * c + 1];
+      if (!or_state_ok(W[c][0], W[c][1])) return OR_CT_ST_NONPHYS;
+    }
+    *count = it + 1;
+  }
+  if (!conv) *lmax_hit = 1;
+  /* Part 2 */
+  double F[OR_MAXC + 1][2], ih[OR_MAXC];
+  if (!or_ct_fluxes(M, P, ph, Z, W, F, pwl, pwr, &wl, &wr)) return OR_CT_ST_NEWTON;
+  for (c = 0; c < m; ++c) {
+    double hk = or_ct_len(Z->hn[c], Z->kind[c], wl, wr, dt);
+    ih[c] = 1.0 / hk;
+    if (Z->kind[c] != 0 && !(hk >= 0.5 * Z->hh[c])) return OR_CT_ST_MESH;
+  }
+  for (c = 0; c < m; ++c) {
+    for (q = 0; q < 2; ++q)
+      U1[c][q] = (Z->hn[c] * Z->U0[c][q] - dt * (F[c + 1][q] - F[c][q])) * ih[c];
+    if (!or_state_ok(U1[c][0], U1[c][1])) return OR_CT_ST_NONPHYS;
+  }
+  *wls = wl;
+  *wrs = wr;
+  return 0;
+}
+
 /* one physical step of one creation tube; *count, *flags: its log entry */
 static void or_ct_step(const or_material *M, const or_params *P, double p_min, double p_tilde,
-                       or_ctube *c, double *rn, double *mn, double *F, int *count, int *flags) {
+                       int solver, int zn_maxit, double zn_rtol, or_ctube *c, double *rn,
+                       double *mn, double *F, int *count, int *flags) {
   int n = c->n, s, j;
   double h = c->h;
   double *r = c->rho, *m = c->mom;
@@ -1965,7 +2090,13 @@ static void or_ct_step(const or_material *M, const or_params *P, double p_min, d
       double pwl[2] = {Il.pl, Il.pr}, pwr[2] = {Ir.pl, Ir.pr};
       double U1[OR_MAXC][2], wl = 0.0, wr = 0.0;
       int lh = 0;
-      if (!st) st = or_ct_dts(M, P, c->ph, &Z, dt, pwl, pwr, U1, &wl, &wr, &cnt, &lh);
+      if (!st) {
+        if (solver == 1)
+          st = or_ct_newton(M, P, c->ph, &Z, dt, pwl, pwr, zn_maxit, zn_rtol, U1, &wl, &wr, &cnt,
+                            &lh);
+        else
+          st = or_ct_dts(M, P, c->ph, &Z, dt, pwl, pwr, U1, &wl, &wr, &cnt, &lh);
+      }
       if (!st) {
         for (k = 0; k < Z.m; ++k) {
           int sl = k < Zh ? j0 - Zh + k : (k == Zh ? n : j0 + (k - Zh - 1));
@@ -2002,11 +2133,14 @@ static void or_ct_step(const or_material *M, const or_params *P, double p_min, d
   *flags = fl;
 }
 
-/* n_steps steps of P independent creation tubes (OpenMP over tubes).  Tube
+/* n_steps steps of P independent creation tubes (OpenMP over tubes), the
+ * zone solved by Algorithm 2 (solver 0) or by Newton (solver 1, at most
+ * zn_maxit steps, tolerance zn_rtol).  Tube
  * p has n_cells[p] regular cells and n_cells[p] + 1 slots from off[p];
  * face, dl, dr, pw (4 per tube), t, status, steps, iters are its state.
  * Logs (optional) are [n_steps][P]. */
 int oracle_ct_run(const or_material *M, const or_params *Pp, double p_min, double p_tilde,
+                  int solver, int zn_maxit, double zn_rtol,
                   int P, const int *n_cells, const double *h, const int *phase,
                   const long long *off, double *rho, double *mom, int *face, double *dl,
                   double *dr, double *pw, double *t, int *status, int *steps, long long *iters,
@@ -2035,7 +2169,7 @@ int oracle_ct_run(const or_material *M, const or_params *Pp, double p_min, doubl
     for (k = 0; k < n_steps; ++k) {
       int cnt, fl;
       if (!log_count && (*c.status || !(*c.t < Pp->t_end))) break;
-      or_ct_step(M, Pp, p_min, p_tilde, &c, rn, mn, F, &cnt, &fl);
+      or_ct_step(M, Pp, p_min, p_tilde, solver, zn_maxit, zn_rtol, &c, rn, mn, F, &cnt, &fl);
       if (log_count) {
         log_count[(size_t)k * P + p] = cnt;
         log_flags[(size_t)k * P + p] = fl;

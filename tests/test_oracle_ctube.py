@@ -236,3 +236,66 @@ def test_dual_time_fixed_point_is_the_implicit_step(case):
             assert abs(res) < 1e-11 * scale, (k, q, res / scale)
     assert abs((s1.dl[0] - s0.dl[0]) / (L["w"] * dt) - 1.0) < 1e-12
     assert abs((s1.dr[0] - s0.dr[0]) / (R["w"] * dt) - 1.0) < 1e-12
+
+
+@pytest.mark.parametrize("case", [CW.CAVITATION, CW.NUCLEATION,
+                                  (LIQ, (66000.0, -5.2), (60000.0, 2.8)),
+                                  (VAP, (70020.0, 2.9), (69990.0, -2.6))])
+def test_newton_zone_solver_lands_on_the_implicit_step(case):
+    """The Newton zone solver (the paper's outlook) solves the implicit step
+    of the zone to its tolerance: at U^{n+1}, with the separately pinned
+    interface solver and HLL flux, every zone cell satisfies
+    h^{n+1} U^{n+1} - h^n U^n + dt (F_{i+1/2} - F_{i-1/2}) = 0 and the
+    boundaries moved by w(U^{n+1}) dt -- also for nucleated cells, where
+    Algorithm 2's update-size rule stops early; a handful of Newton steps
+    per time step."""
+    b = CW.concat([CW.spec(case, 40)], "nz").with_params(t_end=1.0)
+    kw = dict(solver=oracle.CT_SOLVER_NEWTON, zn_rtol=1e-10)
+    s0 = oracle.CTubeState(b)
+    oracle.ct_run(s0, 3, **kw)
+    s1 = oracle.CTubeState(b)
+    cnt, fl = oracle.ct_run(s1, 4, log=True, **kw)
+    assert s1.status[0] == 0 and s1.steps[0] == 4 and s1.face[0] == 20
+    assert np.all(cnt[1:, 0] <= 6) and not np.any(fl & oracle.CT_FL_LMAX)
+    ph, phn, N, j0, h = case[0], 1 - case[0], 40, 20, b.h[0]
+    dt = s1.t[0] - s0.t[0]
+    h0 = [h + s0.dl[0], s0.dr[0] - s0.dl[0], h - s0.dr[0]]
+    h1 = [h + s1.dl[0], s1.dr[0] - s1.dl[0], h - s1.dr[0]]
+    u = lambda s, c: s.mom[c] / s.rho[c]
+    L = oracle.iface_solve(M, ph, s1.rho[j0 - 1], u(s1, j0 - 1), phn, s1.rho[N], u(s1, N))
+    R = oracle.iface_solve(M, phn, s1.rho[N], u(s1, N), ph, s1.rho[j0], u(s1, j0))
+    FL = oracle.hll(M, ph, s0.rho[j0 - 2], s0.mom[j0 - 2], s0.rho[j0 - 1], s0.mom[j0 - 1])
+    FR = oracle.hll(M, ph, s0.rho[j0], s0.mom[j0], s0.rho[j0 + 1], s0.mom[j0 + 1])
+    F = [FL, (L["F0"], L["F1"]), (R["F0"], R["F1"]), FR]
+    for k, c in enumerate((j0 - 1, N, j0)):
+        for q, (a0, a1) in enumerate(((s0.rho, s1.rho), (s0.mom, s1.mom))):
+            res = h1[k] * a1[c] - h0[k] * a0[c] + dt * (F[k + 1][q] - F[k][q])
+            scale = max(abs(h1[k] * a1[c]), abs(h0[k] * a0[c]), abs(dt * F[k][q]),
+                        abs(dt * F[k + 1][q]))
+            # the check's interface solves start cold, the scheme's warm: both
+            # stop at the solver's own tolerance, which a 1e-8 cell sees
+            assert abs(res) < 1e-8 * scale, (k, q, res / scale)
+    # a nucleated liquid layer is stiff: its boundary speed (about 2e-4 m/s)
+    # moves by 1e-4 of itself when its density moves by 1e-13 of itself
+    wtol = 1e-7 if ph == LIQ else 1e-3
+    assert abs((s1.dl[0] - s0.dl[0]) / (L["w"] * dt) - 1.0) < wtol
+    assert abs((s1.dr[0] - s0.dr[0]) / (R["w"] * dt) - 1.0) < wtol
+
+
+def test_newton_zone_solver_on_the_paper_runs():
+    """With the Newton zone solver the Sec. 5 runs reach t_end in the same
+    large steps, the star cells within 0.02 Pa of the printed implicit rows
+    (the liquid layer's pressure, p0 + a_L^2 (rho - rho0), moves 0.02 Pa per
+    1e-8 kg/m^3), with about 3 Newton steps per time step instead of up to
+    tens of thousands of dual time iterations."""
+    for mk, rows in ((CW.cavitation_tube, (68483.740426, 68477.181783, 68483.740588)),
+                     (CW.nucleation_tube, (70382.992468, 70383.072633, 70382.992468))):
+        b = mk()
+        sd = run(b)
+        sn = oracle.CTubeState(b)
+        oracle.ct_run(sn, solver=oracle.CT_SOLVER_NEWTON)
+        assert sn.status[0] == 0 and sn.t[0] == 5e-4 and sn.steps[0] == sd.steps[0]
+        assert sn.iters[0] < 4 * sn.steps[0]
+        for (p, _), printed in zip(star_cells(sn, b), rows):
+            assert abs(p - printed) < 0.02, (p, printed)
+        assert abs((sn.dr[0] - sn.dl[0]) / (sd.dr[0] - sd.dl[0]) - 1.0) < 1e-6
