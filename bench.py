@@ -499,6 +499,44 @@ def ctube_leg(args, cpu):
                            "units_per_launch": tube_iters / max(1, n),
                            "note": "the nucleating tubes' dependent chains (tens of thousands "
                                    "of dual time iterations per step) bound it: latency"}
+    # the Newton zone solver (zone +- 1) on the whole run to t_end
+    s = CreationTubes(b)
+    try:
+        s.set_launch(lanes, ppw)
+        s.set_solver(1)
+        s.set_state()
+        s.time_kernels(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nn = s.run(1 << 20, 64)
+        torch.cuda.synchronize()
+        nwall = time.perf_counter() - t0
+        nb_ms, nz_ms, ns_ms = s.last_timing()
+        s.time_kernels(False)
+        _, nst, nsteps, niters, nface, _, _ = s.problems()
+    finally:
+        s.close()
+    rec["newton_zone_solver"] = {
+        "what": "the zone's implicit step by Newton (forward-difference Jacobian, tolerance "
+                "1e-10) instead of dual time stepping, the whole run to t_end = 5e-4 s",
+        "unit": "cell-updates/s", "value": float(np.sum(slots * nsteps)) / nwall,
+        "wall_s": nwall, "launch_steps": nn, "failed_problems": int(np.sum(nst != 0)),
+        "tubes_to_t_end_per_s": float(b.n_problems) / nwall,
+        "newton_steps": int(np.sum(niters)), "max_newton_steps_per_tube": int(np.max(niters)),
+        "bulk_ms_per_launch": nb_ms, "zone_ms_per_launch": nz_ms, "step_ms": ns_ms}
+    if cpu:
+        import oracle
+        sub = b.subset(list(range(0, b.n_problems, 16)))
+        for threads in (1, max(1, min(16, os.cpu_count() or 1))):
+            stc = oracle.CTubeState(sub)
+            t0 = time.perf_counter()
+            oracle.ct_run(stc, threads=threads, solver=oracle.CT_SOLVER_NEWTON)
+            w = time.perf_counter() - t0
+            key = "cpu_1_thread" if threads == 1 else "cpu_all_threads"
+            rec["newton_zone_solver"][key] = {
+                "value": float(np.sum((sub.N + 1) * stc.steps)) / w, "threads": threads,
+                "kind": "oracle", "sample": f"every 16th tube ({sub.n_problems}) to t_end",
+                "wall_s": w}
     if cpu:
         import oracle
         idx = [0, 1, 2, 3]

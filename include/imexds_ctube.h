@@ -122,6 +122,22 @@ int imexds_ct_get_log(imexds_ct_ctx *ctx, int32_t *count, int32_t *flags, int32_
  * per wave.  Results do not depend on it. */
 int imexds_ct_set_launch(imexds_ct_ctx *ctx, int32_t zone_lanes, int32_t zone_problems_per_wave);
 
+/* The solver of the zone's implicit step.  IMEXDS_CT_SOLVER_DTS (default):
+ * Algorithm 2 as described above.  IMEXDS_CT_SOLVER_NEWTON: Newton on the
+ * same implicit step (the Newton-like solver of the paper's outlook), zone
+ * +- 1 only (IMEXDS_ERR_UNSUPPORTED otherwise): unknowns the zone's 6
+ * values, residual
+ *   R_c(W) = (h_c(W) / h_c^n) W_c - U_c^n + (dt / h_c^n)(F_{c+1/2}(W) - F_{c-1/2}(W))
+ * (lengths from the boundary speeds at W, outer zone faces from U^n),
+ * Jacobian by forward differences with step 1e-7 max(|W_j|, 1), Gaussian
+ * elimination with partial pivoting, full steps from W = U^n; converged when
+ * every step component is below rtol max(|W_j|, 1) (e.g. 1e-10), at most
+ * maxit steps (e.g. 30; then IMEXDS_CT_FL_LMAX); Part 2 as in Algorithm 2.
+ * The log's count is the number of Newton steps. */
+#define IMEXDS_CT_SOLVER_DTS 0
+#define IMEXDS_CT_SOLVER_NEWTON 1
+int imexds_ct_set_solver(imexds_ct_ctx *ctx, int32_t solver, int32_t maxit, double rtol);
+
 int imexds_ct_get_sizes(imexds_ct_ctx *ctx, int32_t *n_problems, int64_t *n_slots);
 
 /* HIP-event timing of the sweep, the zone kernel and the whole step, averaged

@@ -21,6 +21,8 @@
 //                                 solved by the interface solver (2 lanes:
 //                                 one per boundary, side by side; 4: two per
 //                                 boundary, one per side of its problem).
+//   k_ct_newton (1, 2 or 4 lanes per tube): instead of k_ct_zone when
+//                                 the zone is solved by Newton (zone +- 1).
 //   k_ct_fin    (lane per tube)  : t, steps, status, the mesh check and the
 //                                 next dt.
 // k_ct_bulk and k_ct_create + k_ct_zone read U^n only and write disjoint
@@ -45,6 +47,7 @@ namespace ct {
 
 using imexds::d_a;
 using imexds::d_bflux;
+using imexds::d_finite;
 using imexds::d_hll;
 using imexds::d_state_ok;
 using imexds::IfaceOut;
@@ -88,6 +91,8 @@ struct Args {
   int* log_fl;
   int log_row;
   int zone_ppw;
+  int zn_maxit;     // Newton zone solver: at most this many steps
+  double zn_rtol;   // and this relative step tolerance
 };
 
 __device__ __forceinline__ unsigned long long speed_bits(const Mat& M, int ph, double r,
@@ -545,6 +550,350 @@ __global__ __launch_bounds__(64) void k_ct_zone(Args A) {
 }
 
 // ---------------------------------------------------------------------------
+// Newton on the implicit step of the zone (created cell +- 1), the
+// alternative to Algorithm 2 (the paper's outlook: a Newton-like solver for
+// the small implicit systems).  Unknowns: the 6 values of the zone's 3
+// cells; residual
+//   R_c(W) = (h_c(W) / h_c^n) W_c - U_c^n + (dt / h_c^n)(F_{c+1/2}(W) - F_{c-1/2}(W)),
+// Jacobian by forward differences (step 1e-7 max(|W_j|, 1), boundary solves
+// warm-started from the current iterate's), Gaussian elimination with
+// partial pivoting, full steps from W = U^n, converged when every step
+// component is below zn_rtol max(|W_j|, 1); at most zn_maxit steps.
+// Evaluation sequence, one call site of the interface solver: the
+// prediction from U^n, then per Newton step the residual at W and at the six
+// perturbed points; after the last step the evaluation at W feeds Part 2.
+// Lanes as in k_ct_zone (L = 1, 2, 4).
+// ---------------------------------------------------------------------------
+template <int L>
+__global__ __launch_bounds__(64) void k_ct_newton(Args A) {
+  constexpr int Z = 1, MC = 3, NV = 6;
+  constexpr int XB = L == 4 ? 2 : 1;
+  const int lane = (int)threadIdx.x;
+  if (lane >= A.zone_ppw * L) return;
+  const int p = blockIdx.x * A.zone_ppw + lane / L;
+  const int sub = lane & (L - 1);
+  const int side = L == 4 ? (sub >> 1) : sub;
+  const int half = L == 4 ? (sub & 1) : 0;
+  if (p >= A.P) return;
+  const bool writer = sub == 0;
+  const long long o = A.off[p];
+  const int N = A.N[p];
+  const double* __restrict__ r0 = A.r0 + o;
+  const double* __restrict__ m0 = A.m0 + o;
+  double* __restrict__ r1 = A.r1 + o;
+  double* __restrict__ m1 = A.m1 + o;
+  const double dt = A.dt[p];
+  const long long lrow = A.log_row >= 0 ? (long long)A.log_row * A.P + p : -1;
+  const int j0 = A.face[p];
+  if (dt == 0.0 || j0 < 0) {
+    if (dt != 0.0 && A.ccount[p] != 0) return;  // k_ct_create's tubes
+    if (writer) {
+      if (dt == 0.0) {
+        int a, b;
+        implicit_range(A, p, N, a, b);
+        for (int c = a; c < b; ++c) {
+          r1[c] = r0[c];
+          m1[c] = m0[c];
+        }
+      }
+      r1[N] = r0[N];
+      m1[N] = m0[N];
+      if (dt != 0.0) A.cnt[p] = 0;
+      if (lrow >= 0) {
+        A.log_cnt[lrow] = 0;
+        A.log_fl[lrow] = dt == 0.0 ? FL_INACTIVE : 0;
+      }
+    }
+    return;
+  }
+  const Mat& M = A.M;
+  const int ph = A.phase[p], phn = 1 - ph;
+  const double h = A.h[p];
+  const double dl = A.dl[p], dr = A.dr[p];
+  double* pwp = A.pw + 4 * (long long)p;
+  // zone cells: 0 = j0 - 1 (kind 1), 1 = created (kind 2), 2 = j0 (kind 3)
+  double U0[MC][2], W[MC][2], hn[MC], ihn[MC], hh[MC];
+  const int slot[MC] = {j0 - 1, N, j0};
+  hn[0] = h + dl;
+  hn[1] = dr - dl;
+  hn[2] = h - dr;
+#pragma unroll
+  for (int k = 0; k < MC; ++k) {
+    U0[k][0] = r0[slot[k]];
+    U0[k][1] = m0[slot[k]];
+    W[k][0] = U0[k][0];
+    W[k][1] = U0[k][1];
+    ihn[k] = 1.0 / hn[k];
+    hh[k] = hn[k];
+  }
+  double FL0, FL1, FR0, FR1;
+  face_flux(A, ph, N, r0, m0, j0 - Z, FL0, FL1);
+  face_flux(A, ph, N, r0, m0, j0 + Z, FR0, FR1);
+  double wl = 0.0, wr = 0.0;
+  double pl0 = pwp[0], pl1 = pwp[1], pr0 = pwp[2], pr1 = pwp[3];  // current warm starts
+  double gl0 = 0.0, gl1 = 0.0, gr0 = 0.0, gr1 = 0.0;              // the base point's, for columns
+  double R[NV], J[NV][NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    R[i] = 0.0;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) J[i][j] = 0.0;
+  }
+  int code = 0, it = 0, col = -2;  // -2: prediction, -1: base point, 0..5: column
+  double ecol = 0.0;
+  bool final_pass = false, conv = false;
+#pragma unroll 1
+  for (;;) {
+    const bool fd = col >= 0;
+    // the point: W, or W with entry col moved by ecol
+    double X[MC][2];
+#pragma unroll
+    for (int k = 0; k < MC; ++k)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) X[k][q] = (fd && col == 2 * k + q) ? W[k][q] + ecol : W[k][q];
+    int ec = 0;
+    double bl0 = 0.0, bl1 = 0.0, br0 = 0.0, br1 = 0.0, ewl = 0.0, ewr = 0.0;
+    double npl0 = 0.0, npl1 = 0.0, npr0 = 0.0, npr1 = 0.0;
+#pragma unroll 1
+    for (int f = side; f < 2; f += (L == 1 ? 1 : 2)) {
+      const bool lf = f == 0;
+      IfaceOut I;
+      const double g0 = fd ? (lf ? gl0 : gr0) : (lf ? pl0 : pr0);
+      const double g1 = fd ? (lf ? gl1 : gr1) : (lf ? pl1 : pr1);
+      if (!imexds::d_iface_solve_t<L == 4>(M, A.newton_maxit, A.newton_rtol, lf ? ph : phn,
+                                           lf ? X[0][0] : X[1][0], lf ? X[0][1] : X[1][1],
+                                           lf ? phn : ph, lf ? X[1][0] : X[2][0],
+                                           lf ? X[1][1] : X[2][1], true, g0, g1, half, lane ^ 1, I)) {
+        ec = 1;
+      } else if (lf) {
+        ewl = I.w;
+        npl0 = I.pl;
+        npl1 = I.pr;
+        bl0 = I.F0;
+        bl1 = I.F1;
+      } else {
+        ewr = I.w;
+        npr0 = I.pl;
+        npr1 = I.pr;
+        br0 = I.F0;
+        br1 = I.F1;
+      }
+    }
+    if (L > 1) {
+      const double y0 = __shfl_xor(side ? br0 : bl0, XB, 64);
+      const double y1 = __shfl_xor(side ? br1 : bl1, XB, 64);
+      const double yw = __shfl_xor(side ? ewr : ewl, XB, 64);
+      const double q0 = __shfl_xor(side ? npr0 : npl0, XB, 64);
+      const double q1 = __shfl_xor(side ? npr1 : npl1, XB, 64);
+      ec |= __shfl_xor(ec, XB, 64);
+      if (side) {
+        bl0 = y0;
+        bl1 = y1;
+        ewl = yw;
+        npl0 = q0;
+        npl1 = q1;
+      } else {
+        br0 = y0;
+        br1 = y1;
+        ewr = yw;
+        npr0 = q0;
+        npr1 = q1;
+      }
+    }
+    if (ec) {
+      code = ST_NEWTON;
+      break;
+    }
+    if (!fd) {  // prediction and base points carry the warm starts on
+      wl = ewl;
+      wr = ewr;
+      pl0 = npl0;
+      pl1 = npl1;
+      pr0 = npr0;
+      pr1 = npr1;
+    }
+    if (col == -2) {
+      bool bad = false;
+#pragma unroll
+      for (int k = 0; k < MC; ++k) {
+        hh[k] = cell_len(hn[k], k + 1, wl, wr, dt);
+        if (!(hh[k] / h > 0.0)) bad = true;  // a predicted length that vanishes
+      }
+      if (bad) {
+        code = ST_MESH;
+        break;
+      }
+      col = -1;
+      continue;
+    }
+    const double F[MC + 1][2] = {{FL0, FL1}, {bl0, bl1}, {br0, br1}, {FR0, FR1}};
+    double hk[MC];
+    bool shrink = false;
+#pragma unroll
+    for (int k = 0; k < MC; ++k) {
+      hk[k] = cell_len(hn[k], k + 1, ewl, ewr, dt);
+      if (!fd && !(hk[k] >= 0.5 * hh[k])) shrink = true;
+    }
+    if (shrink) {
+      code = ST_MESH;
+      break;
+    }
+    if (final_pass) {
+      // Part 2: conservative update with the fluxes of the accepted iterate
+#pragma unroll
+      for (int k = 0; k < MC; ++k) {
+        const double ih = 1.0 / hk[k];
+        const double u0 = (hn[k] * U0[k][0] - dt * (F[k + 1][0] - F[k][0])) * ih;
+        const double u1 = (hn[k] * U0[k][1] - dt * (F[k + 1][1] - F[k][1])) * ih;
+        W[k][0] = u0;
+        W[k][1] = u1;
+        if (!d_state_ok(u0, u1)) code = ST_NONPHYS;
+      }
+      break;
+    }
+    double RX[NV];
+#pragma unroll
+    for (int k = 0; k < MC; ++k)
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+        RX[2 * k + q] = (hk[k] * ihn[k]) * X[k][q] - U0[k][q] + (dt * ihn[k]) * (F[k + 1][q] - F[k][q]);
+    if (!fd) {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) R[i] = RX[i];
+      gl0 = pl0;
+      gl1 = pl1;
+      gr0 = pr0;
+      gr1 = pr1;
+    } else {
+#pragma unroll
+      for (int i = 0; i < NV; ++i)
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+          if (j == col) J[i][j] = (RX[i] - R[i]) / ecol;
+    }
+    const int next = col + 1;
+    if (next < NV) {
+      // the next column's step
+      double xj = 0.0;
+#pragma unroll
+      for (int k = 0; k < MC; ++k)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+          if (2 * k + q == next) xj = W[k][q];
+      ecol = 1e-7 * (fabs(xj) > 1.0 ? fabs(xj) : 1.0);
+      col = next;
+      continue;
+    }
+    // J d = -R by Gaussian elimination with partial pivoting
+    double Am[NV][NV], b[NV], d[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      b[i] = -R[i];
+#pragma unroll
+      for (int j = 0; j < NV; ++j) Am[i][j] = J[i][j];
+    }
+    bool sing = false;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      int piv = k;
+      double pv = fabs(Am[k][k]);
+#pragma unroll
+      for (int i = k + 1; i < NV; ++i)
+        if (fabs(Am[i][k]) > pv) {
+          piv = i;
+          pv = fabs(Am[i][k]);
+        }
+      // swap rows k and piv by selects (register arrays need fixed indices)
+      double rk[NV], bk = b[k];
+#pragma unroll
+      for (int j = 0; j < NV; ++j) rk[j] = Am[k][j];
+#pragma unroll
+      for (int i = k + 1; i < NV; ++i) {
+        const bool sw = piv == i;
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+          const double t = Am[i][j];
+          Am[i][j] = sw ? rk[j] : t;
+          Am[k][j] = sw ? t : Am[k][j];
+        }
+        const double tb = b[i];
+        b[i] = sw ? bk : tb;
+        b[k] = sw ? tb : b[k];
+      }
+      if (!(Am[k][k] != 0.0) || !d_finite(Am[k][k])) sing = true;
+#pragma unroll
+      for (int i = k + 1; i < NV; ++i) {
+        const double fct = Am[i][k] / Am[k][k];
+#pragma unroll
+        for (int j = k + 1; j < NV; ++j) Am[i][j] = Am[i][j] - fct * Am[k][j];
+        b[i] = b[i] - fct * b[k];
+      }
+    }
+#pragma unroll
+    for (int i = NV - 1; i >= 0; --i) {
+      double sum = b[i];
+#pragma unroll
+      for (int j = i + 1; j < NV; ++j) sum = sum - Am[i][j] * d[j];
+      d[i] = sum / Am[i][i];
+      if (!d_finite(d[i])) sing = true;
+    }
+    if (sing) {
+      code = ST_NEWTON;
+      break;
+    }
+    conv = true;
+#pragma unroll
+    for (int k = 0; k < MC; ++k)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const double sc = fabs(W[k][q]) > 1.0 ? fabs(W[k][q]) : 1.0;
+        conv = conv && (fabs(d[2 * k + q]) <= A.zn_rtol * sc);
+      }
+    bool okst = true;
+#pragma unroll
+    for (int k = 0; k < MC; ++k) {
+      W[k][0] = W[k][0] + d[2 * k];
+      W[k][1] = W[k][1] + d[2 * k + 1];
+      okst = okst && d_state_ok(W[k][0], W[k][1]);
+    }
+    if (!okst) {
+      code = ST_NONPHYS;
+      break;
+    }
+    it += 1;
+    final_pass = conv || it == A.zn_maxit;
+    col = -1;
+  }
+  int fl = (!code && !conv) ? FL_LMAX : 0;
+  if (writer) {
+    if (!code) {
+      unsigned long long vmax = 0;
+#pragma unroll
+      for (int k = 0; k < MC; ++k) {
+        r1[slot[k]] = W[k][0];
+        m1[slot[k]] = W[k][1];
+        const unsigned long long v = speed_bits(M, k == Z ? phn : ph, W[k][0], W[k][1]);
+        vmax = v > vmax ? v : vmax;
+      }
+      A.dl[p] = dl + wl * dt;
+      A.dr[p] = dr + wr * dt;
+      pwp[0] = pl0;
+      pwp[1] = pl1;
+      pwp[2] = pr0;
+      pwp[3] = pr1;
+      atomicMax(A.S + p, vmax);
+    } else {
+      atomicOr(A.fail + p, code);
+    }
+    A.cnt[p] = code ? 0 : it;
+    if (lrow >= 0) {
+      A.log_cnt[lrow] = code ? 0 : it;
+      A.log_fl[lrow] = code ? 0 : fl;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // per-tube bookkeeping between steps
 // ---------------------------------------------------------------------------
 __global__ void k_ct_fin(Args A, int init) {
@@ -626,6 +975,8 @@ struct imexds_ct_ctx {
   int cur = 0;
   int *tile_prob = nullptr, *tile_start = nullptr;
   int n_tiles = 0, zone_lanes = 4, zone_ppw = 2;
+  int zone_solver = IMEXDS_CT_SOLVER_DTS, zn_maxit = 30;
+  double zn_rtol = 1e-10;
   int *log_cnt = nullptr, *log_fl = nullptr;
   int log_max = 0, log_row = 0;
   bool have_state = false;
@@ -705,6 +1056,8 @@ ct::Args ct_args(const imexds_ct_ctx* c, int parity) {
   A.log_fl = c->log_fl;
   A.log_row = (c->log_cnt && c->log_row < c->log_max) ? c->log_row : -1;
   A.zone_ppw = c->zone_ppw;
+  A.zn_maxit = c->zn_maxit;
+  A.zn_rtol = c->zn_rtol;
   return A;
 }
 
@@ -722,6 +1075,18 @@ hipError_t ct_launch_zone(const ct::Args& A, int lanes, hipStream_t s) {
     case 31: ct::k_ct_zone<3, 1><<<blocks, 64, 0, s>>>(A); break;
     case 32: ct::k_ct_zone<3, 2><<<blocks, 64, 0, s>>>(A); break;
     case 34: ct::k_ct_zone<3, 4><<<blocks, 64, 0, s>>>(A); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t ct_launch_newton(const ct::Args& A, int lanes, hipStream_t s) {
+  if (A.P <= 0) return hipSuccess;
+  const int blocks = (A.P + A.zone_ppw - 1) / A.zone_ppw;
+  switch (lanes) {
+    case 1: ct::k_ct_newton<1><<<blocks, 64, 0, s>>>(A); break;
+    case 2: ct::k_ct_newton<2><<<blocks, 64, 0, s>>>(A); break;
+    case 4: ct::k_ct_newton<4><<<blocks, 64, 0, s>>>(A); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -778,7 +1143,9 @@ int ct_one_step(imexds_ct_ctx* c) {
     ct::k_ct_create<<<(A.P + 63) / 64, 64, 0, c->zs>>>(A);
     e = ct_err(hipGetLastError());
   }
-  if (!e) e = ct_err(ct_launch_zone(A, c->zone_lanes, c->zs));
+  if (!e)
+    e = ct_err(c->zone_solver == IMEXDS_CT_SOLVER_NEWTON ? ct_launch_newton(A, c->zone_lanes, c->zs)
+                                                         : ct_launch_zone(A, c->zone_lanes, c->zs));
   if (!e && tm) e = ct_err(hipEventRecord(ev[4], c->zs));
   if (!e && tm) e = ct_err(hipEventRecord(ev[1], c->ms));
   if (!e && c->n_tiles) {
@@ -1047,6 +1414,22 @@ int imexds_ct_set_launch(imexds_ct_ctx* c, int32_t zone_lanes, int32_t zone_prob
   if (e) return e;
   c->zone_lanes = zone_lanes;
   c->zone_ppw = zone_problems_per_wave;
+  return 0;
+}
+
+int imexds_ct_set_solver(imexds_ct_ctx* c, int32_t solver, int32_t maxit, double rtol) {
+  if (!c) return IMEXDS_ERR_INVALID_ARG;
+  if (solver != IMEXDS_CT_SOLVER_DTS && solver != IMEXDS_CT_SOLVER_NEWTON)
+    return IMEXDS_ERR_INVALID_ARG;
+  if (solver == IMEXDS_CT_SOLVER_NEWTON && c->base.Z != 1) return IMEXDS_ERR_UNSUPPORTED;
+  if (maxit < 1 || !ct_pos(rtol)) return IMEXDS_ERR_INVALID_ARG;
+  int e = ct_err(hipSetDevice(c->device));
+  if (!e) e = ct_err(hipStreamSynchronize(c->ms));
+  if (!e) e = ct_err(hipStreamSynchronize(c->zs));
+  if (e) return e;
+  c->zone_solver = solver;
+  c->zn_maxit = maxit;
+  c->zn_rtol = rtol;
   return 0;
 }
 

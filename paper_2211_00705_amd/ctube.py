@@ -21,6 +21,7 @@ P_i32, P_i64, P_dbl = _base.P_i32, _base.P_i64, _base.P_dbl
 
 ST_NEWTON, ST_NONPHYS, ST_MESH, ST_MULTI = 1, 2, 4, 8
 FL_CREATED, FL_LMAX, FL_INACTIVE = 1, 2, 4
+SOLVER_DTS, SOLVER_NEWTON = 0, 1
 
 
 class imexds_ct_batch(ctypes.Structure):
@@ -46,6 +47,7 @@ _get_problems = _sig("imexds_ct_get_problems", c_vp, P_dbl, P_i32, P_i32, P_i64,
 _enable_log = _sig("imexds_ct_enable_log", c_vp, c_i32)
 _get_log = _sig("imexds_ct_get_log", c_vp, P_i32, P_i32, P_i32)
 _set_launch = _sig("imexds_ct_set_launch", c_vp, c_i32, c_i32)
+_set_solver = _sig("imexds_ct_set_solver", c_vp, c_i32, c_i32, c_dbl)
 _get_sizes = _sig("imexds_ct_get_sizes", c_vp, P_i32, P_i64)
 _time_kernels = _sig("imexds_ct_time_kernels", c_vp, c_i32)
 _last_timing = _sig("imexds_ct_last_timing", c_vp, P_dbl, P_dbl, P_dbl)
@@ -54,7 +56,8 @@ _L.imexds_ct_destroy.argtypes = [c_vp]
 
 EXPORTED = ["imexds_ct_create", "imexds_ct_set_state", "imexds_ct_step", "imexds_ct_run",
             "imexds_ct_get_state", "imexds_ct_get_problems", "imexds_ct_enable_log",
-            "imexds_ct_get_log", "imexds_ct_set_launch", "imexds_ct_get_sizes",
+            "imexds_ct_get_log", "imexds_ct_set_launch", "imexds_ct_set_solver",
+            "imexds_ct_get_sizes",
             "imexds_ct_time_kernels", "imexds_ct_last_timing", "imexds_ct_destroy"]
 
 
@@ -136,6 +139,10 @@ def imexds_ct_set_launch(ctx, zone_lanes, zone_problems_per_wave):
            "imexds_ct_set_launch")
 
 
+def imexds_ct_set_solver(ctx, solver, maxit=30, rtol=1e-10):
+    _check(_set_solver(c_vp(ctx), int(solver), int(maxit), float(rtol)), "imexds_ct_set_solver")
+
+
 def imexds_ct_time_kernels(ctx, on):
     _check(_time_kernels(c_vp(ctx), int(bool(on))), "imexds_ct_time_kernels")
 
@@ -200,6 +207,9 @@ class CreationTubes:
 
     def set_launch(self, zone_lanes=4, zone_problems_per_wave=2):
         imexds_ct_set_launch(self.ctx, zone_lanes, zone_problems_per_wave)
+
+    def set_solver(self, solver, maxit=30, rtol=1e-10):
+        imexds_ct_set_solver(self.ctx, solver, maxit, rtol)
 
     def time_kernels(self, on=True):
         imexds_ct_time_kernels(self.ctx, on)

@@ -12,12 +12,14 @@ from paper_2211_00705_amd import ctube_workloads as CW
 pytestmark = pytest.mark.gpu
 
 
-def run_gpu(b, n_steps=None, lanes=4, ppw=2, log_rows=None):
+def run_gpu(b, n_steps=None, lanes=4, ppw=2, log_rows=None, solver=0):
     import torch
     from paper_2211_00705_amd.ctube import CreationTubes
     s = CreationTubes(b)
     try:
         s.set_launch(lanes, ppw)
+        if solver:
+            s.set_solver(solver)
         s.set_state()
         if log_rows:
             s.enable_log(log_rows)
@@ -37,13 +39,14 @@ def run_gpu(b, n_steps=None, lanes=4, ppw=2, log_rows=None):
         s.close()
 
 
-def run_oracle(b, n_steps=None, log_rows=None, threads=8):
+def run_oracle(b, n_steps=None, log_rows=None, threads=8, solver=0):
     st = oracle.CTubeState(b)
     out = {}
     if log_rows:
-        out["count"], out["flags"] = oracle.ct_run(st, log_rows, threads=threads, log=True)
+        out["count"], out["flags"] = oracle.ct_run(st, log_rows, threads=threads, log=True,
+                                                   solver=solver)
     else:
-        oracle.ct_run(st, n_steps, threads=threads)
+        oracle.ct_run(st, n_steps, threads=threads, solver=solver)
     out.update(rho=st.rho, mom=st.mom, t=st.t, status=st.status, steps=st.steps, iters=st.iters,
                face=st.face, dl=st.dl, dr=st.dr)
     return out
@@ -176,4 +179,56 @@ def test_api_errors():
     for bad in ((3, 4), (2, 0), (2, 33), (1, 65), (4, 17)):
         with pytest.raises(IMEXDSError):
             s.set_launch(*bad)
+    s.close()
+
+
+NEWTON = oracle.CT_SOLVER_NEWTON
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 4])
+def test_newton_paper_tests_to_end_time(lanes):
+    """The Sec. 5 cavitation and nucleation tubes to t_end with the Newton
+    zone solver: about 3 Newton steps per time step."""
+    b = CW.concat([CW.spec(CW.CAVITATION), CW.spec(CW.NUCLEATION)], "paper")
+    rows = 160
+    g = run_gpu(b, lanes=lanes, log_rows=rows, solver=NEWTON)
+    o = run_oracle(b, rows + 10, log_rows=rows + 10, solver=NEWTON)
+    assert np.all(g["status"] == 0) and np.all(g["t"] == 5e-4) and np.all(g["face"] == 200)
+    assert np.all(g["iters"] < 4 * g["steps"])
+    assert_same(b, g, o, rows=rows)
+
+
+@pytest.mark.parametrize("lanes,ppw", [(4, 2), (2, 32), (1, 3)])
+def test_newton_batch_to_end_time(lanes, ppw):
+    """A seeded ensemble to t_end with the Newton zone solver, under three
+    launch shapes."""
+    b = CW.ctube_batch(seed=7, n_problems=64)
+    g = run_gpu(b, lanes=lanes, ppw=ppw, log_rows=160, solver=NEWTON)
+    o = run_oracle(b, 170, log_rows=170, solver=NEWTON)
+    assert np.all(g["status"] == 0) and np.all(g["t"] == 5e-4)
+    assert_same(b, g, o, rows=160)
+
+
+def test_newton_full_batch_to_end_time_sampled():
+    """The benchmark ensemble (4096 tubes) to t_end with the Newton zone
+    solver; 64 tubes of it against the oracle run on them alone."""
+    b = CW.ctube_batch()
+    g = run_gpu(b, solver=NEWTON)
+    assert np.all(g["status"] == 0) and np.all(g["t"] == 5e-4)
+    idx = np.concatenate([np.arange(0, 32), np.arange(b.n_problems - 32, b.n_problems)])
+    o = run_oracle(b.subset(idx), threads=16, solver=NEWTON)
+    assert_same(b, g, o, idx=idx)
+
+
+def test_newton_solver_errors():
+    from paper_2211_00705_amd import ctube as C
+    from paper_2211_00705_amd.imexds import IMEXDSError
+    s = C.CreationTubes(CW.cavitation_tube(20))
+    for bad in ((2, 30, 1e-10), (1, 0, 1e-10), (1, 30, 0.0), (1, 30, np.nan)):
+        with pytest.raises(IMEXDSError):
+            s.set_solver(*bad)
+    s.close()
+    s = C.CreationTubes(CW.cavitation_tube(20).with_params(zone_half=2))
+    with pytest.raises(IMEXDSError):
+        s.set_solver(NEWTON)  # the Newton zone solver covers zones +- 1 only
     s.close()
