@@ -21,8 +21,9 @@
 //                                 solved by the interface solver (2 lanes:
 //                                 one per boundary, side by side; 4: two per
 //                                 boundary, one per side of its problem).
-//   k_ct_newton (1, 2 or 4 lanes per tube): instead of k_ct_zone when
-//                                 the zone is solved by Newton (zone +- 1).
+//   k_ct_newton (7 groups of 1, 2 or 4 lanes per tube): instead of
+//                                 k_ct_zone when the zone is solved by
+//                                 Newton (zone +- 1).
 //   k_ct_fin    (lane per tube)  : t, steps, status, the mesh check and the
 //                                 next dt.
 // k_ct_bulk and k_ct_create + k_ct_zone read U^n only and write disjoint
@@ -556,26 +557,39 @@ __global__ __launch_bounds__(64) void k_ct_zone(Args A) {
 // cells; residual
 //   R_c(W) = (h_c(W) / h_c^n) W_c - U_c^n + (dt / h_c^n)(F_{c+1/2}(W) - F_{c-1/2}(W)),
 // Jacobian by forward differences (step 1e-7 max(|W_j|, 1), boundary solves
-// warm-started from the current iterate's), Gaussian elimination with
-// partial pivoting, full steps from W = U^n, converged when every step
-// component is below zn_rtol max(|W_j|, 1); at most zn_maxit steps.
-// Evaluation sequence, one call site of the interface solver: the
-// prediction from U^n, then per Newton step the residual at W and at the six
-// perturbed points; after the last step the evaluation at W feeds Part 2.
-// Lanes as in k_ct_zone (L = 1, 2, 4).
+// warm-started from the base point's), Gaussian elimination with partial
+// pivoting, full steps from W = U^n, converged when every step component is
+// below zn_rtol max(|W_j|, 1); at most zn_maxit steps.
+// A tube has 7 groups of L lanes (L = 1, 2, 4 as in k_ct_zone).  Every group
+// evaluates the prediction and each base point (identical inputs and warm
+// starts, so identical results without any exchange); then group g >= 1
+// evaluates the point moved along unknown g - 1 -- the six difference
+// columns side by side -- and every lane gathers the columns and runs the
+// same 6x6 elimination.  Per Newton step two evaluations in sequence
+// instead of seven.
 // ---------------------------------------------------------------------------
 template <int L>
+__device__ __forceinline__ int newton_tubes_per_wave(int ppw) {
+  const int cap = 64 / (7 * L);
+  return ppw < cap ? ppw : cap;
+}
+
+template <int L>
 __global__ __launch_bounds__(64) void k_ct_newton(Args A) {
-  constexpr int Z = 1, MC = 3, NV = 6;
+  constexpr int Z = 1, MC = 3, NV = 6, G = 7, TL = G * L;
   constexpr int XB = L == 4 ? 2 : 1;
+  const int tpw = newton_tubes_per_wave<L>(A.zone_ppw);
   const int lane = (int)threadIdx.x;
-  if (lane >= A.zone_ppw * L) return;
-  const int p = blockIdx.x * A.zone_ppw + lane / L;
-  const int sub = lane & (L - 1);
+  if (lane >= tpw * TL) return;
+  const int p = blockIdx.x * tpw + lane / TL;
+  const int tl = lane % TL;      // lane within the tube
+  const int grp = tl / L;        // 0: base points only; g >= 1: column g - 1
+  const int sub = tl % L;
   const int side = L == 4 ? (sub >> 1) : sub;
   const int half = L == 4 ? (sub & 1) : 0;
-  if (p >= A.P) return;
-  const bool writer = sub == 0;
+  const int lane0 = lane - tl;   // the tube's first lane
+  if (p >= A.P) return;          // the lanes of a tube are whole
+  const bool writer = tl == 0;
   const long long o = A.off[p];
   const int N = A.N[p];
   const double* __restrict__ r0 = A.r0 + o;
@@ -631,26 +645,27 @@ __global__ __launch_bounds__(64) void k_ct_newton(Args A) {
   face_flux(A, ph, N, r0, m0, j0 + Z, FR0, FR1);
   double wl = 0.0, wr = 0.0;
   double pl0 = pwp[0], pl1 = pwp[1], pr0 = pwp[2], pr1 = pwp[3];  // current warm starts
-  double gl0 = 0.0, gl1 = 0.0, gr0 = 0.0, gr1 = 0.0;              // the base point's, for columns
-  double R[NV], J[NV][NV];
+  double gl0 = 0.0, gl1 = 0.0, gr0 = 0.0, gr1 = 0.0;              // the base point's
+  double R[NV], Jc[NV];  // residual at the base point; this group's column
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
     R[i] = 0.0;
-#pragma unroll
-    for (int j = 0; j < NV; ++j) J[i][j] = 0.0;
+    Jc[i] = 0.0;
   }
-  int code = 0, it = 0, col = -2;  // -2: prediction, -1: base point, 0..5: column
+  const int colj = grp - 1;  // this group's unknown (groups >= 1)
+  int code = 0, it = 0, phase = -2;  // -2: prediction, -1: base point, 0: columns
   double ecol = 0.0;
   bool final_pass = false, conv = false;
 #pragma unroll 1
   for (;;) {
-    const bool fd = col >= 0;
-    // the point: W, or W with entry col moved by ecol
+    const bool fd = phase == 0;
+    const bool moved = fd && grp > 0;
+    // the point: W, or (groups >= 1 in the column pass) W moved along colj
     double X[MC][2];
 #pragma unroll
     for (int k = 0; k < MC; ++k)
 #pragma unroll
-      for (int q = 0; q < 2; ++q) X[k][q] = (fd && col == 2 * k + q) ? W[k][q] + ecol : W[k][q];
+      for (int q = 0; q < 2; ++q) X[k][q] = (moved && colj == 2 * k + q) ? W[k][q] + ecol : W[k][q];
     int ec = 0;
     double bl0 = 0.0, bl1 = 0.0, br0 = 0.0, br1 = 0.0, ewl = 0.0, ewr = 0.0;
     double npl0 = 0.0, npl1 = 0.0, npr0 = 0.0, npr1 = 0.0;
@@ -663,7 +678,8 @@ __global__ __launch_bounds__(64) void k_ct_newton(Args A) {
       if (!imexds::d_iface_solve_t<L == 4>(M, A.newton_maxit, A.newton_rtol, lf ? ph : phn,
                                            lf ? X[0][0] : X[1][0], lf ? X[0][1] : X[1][1],
                                            lf ? phn : ph, lf ? X[1][0] : X[2][0],
-                                           lf ? X[1][1] : X[2][1], true, g0, g1, half, lane ^ 1, I)) {
+                                           lf ? X[1][1] : X[2][1], true, g0, g1, half, lane ^ 1,
+                                           I)) {
         ec = 1;
       } else if (lf) {
         ewl = I.w;
@@ -700,7 +716,11 @@ __global__ __launch_bounds__(64) void k_ct_newton(Args A) {
         npr1 = q1;
       }
     }
-    if (ec) {
+    // a failed solve in any group of the tube fails the zone (group 0's
+    // column-pass evaluation repeats the base point and cannot fail)
+    const unsigned long long failm = __ballot(ec != 0);
+    const unsigned long long tm = ((1ull << TL) - 1ull) << lane0;
+    if (failm & tm) {
       code = ST_NEWTON;
       break;
     }
@@ -712,7 +732,7 @@ __global__ __launch_bounds__(64) void k_ct_newton(Args A) {
       pr0 = npr0;
       pr1 = npr1;
     }
-    if (col == -2) {
+    if (phase == -2) {
       bool bad = false;
 #pragma unroll
       for (int k = 0; k < MC; ++k) {
@@ -723,7 +743,7 @@ __global__ __launch_bounds__(64) void k_ct_newton(Args A) {
         code = ST_MESH;
         break;
       }
-      col = -1;
+      phase = -1;
       continue;
     }
     const double F[MC + 1][2] = {{FL0, FL1}, {bl0, bl1}, {br0, br1}, {FR0, FR1}};
@@ -764,34 +784,28 @@ __global__ __launch_bounds__(64) void k_ct_newton(Args A) {
       gl1 = pl1;
       gr0 = pr0;
       gr1 = pr1;
-    } else {
-#pragma unroll
-      for (int i = 0; i < NV; ++i)
-#pragma unroll
-        for (int j = 0; j < NV; ++j)
-          if (j == col) J[i][j] = (RX[i] - R[i]) / ecol;
-    }
-    const int next = col + 1;
-    if (next < NV) {
-      // the next column's step
+      // this group's column step
       double xj = 0.0;
 #pragma unroll
       for (int k = 0; k < MC; ++k)
 #pragma unroll
         for (int q = 0; q < 2; ++q)
-          if (2 * k + q == next) xj = W[k][q];
+          if (2 * k + q == colj) xj = W[k][q];
       ecol = 1e-7 * (fabs(xj) > 1.0 ? fabs(xj) : 1.0);
-      col = next;
+      phase = 0;
       continue;
     }
-    // J d = -R by Gaussian elimination with partial pivoting
+#pragma unroll
+    for (int i = 0; i < NV; ++i) Jc[i] = (RX[i] - R[i]) / ecol;
+    // every lane gathers the six columns (group j + 1 holds column j)
     double Am[NV][NV], b[NV], d[NV];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      b[i] = -R[i];
+    for (int j = 0; j < NV; ++j)
 #pragma unroll
-      for (int j = 0; j < NV; ++j) Am[i][j] = J[i][j];
-    }
+      for (int i = 0; i < NV; ++i) Am[i][j] = __shfl(Jc[i], lane0 + (j + 1) * L, 64);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) b[i] = -R[i];
+    // J d = -R by Gaussian elimination with partial pivoting
     bool sing = false;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
@@ -862,9 +876,9 @@ __global__ __launch_bounds__(64) void k_ct_newton(Args A) {
     }
     it += 1;
     final_pass = conv || it == A.zn_maxit;
-    col = -1;
+    phase = -1;
   }
-  int fl = (!code && !conv) ? FL_LMAX : 0;
+  const int fl = (!code && !conv) ? FL_LMAX : 0;
   if (writer) {
     if (!code) {
       unsigned long long vmax = 0;
@@ -1082,7 +1096,10 @@ hipError_t ct_launch_zone(const ct::Args& A, int lanes, hipStream_t s) {
 
 hipError_t ct_launch_newton(const ct::Args& A, int lanes, hipStream_t s) {
   if (A.P <= 0) return hipSuccess;
-  const int blocks = (A.P + A.zone_ppw - 1) / A.zone_ppw;
+  // tubes per wave as in ct::newton_tubes_per_wave: 7 lane groups per tube
+  const int cap = 64 / (7 * lanes);
+  const int tpw = A.zone_ppw < cap ? A.zone_ppw : cap;
+  const int blocks = (A.P + tpw - 1) / tpw;
   switch (lanes) {
     case 1: ct::k_ct_newton<1><<<blocks, 64, 0, s>>>(A); break;
     case 2: ct::k_ct_newton<2><<<blocks, 64, 0, s>>>(A); break;
