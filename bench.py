@@ -501,8 +501,9 @@ def ctube_leg(args, cpu):
                                    "of dual time iterations per step) bound it: latency"}
     # the Newton zone solver (zone +- 1) on the whole run to t_end
     s = CreationTubes(b)
+    nlanes, nppw = 2, 4  # the Newton kernel's fastest shape (7 groups of 2 lanes, 4 tubes a wave)
     try:
-        s.set_launch(lanes, ppw)
+        s.set_launch(nlanes, nppw)
         s.set_solver(1)
         s.set_state()
         s.time_kernels(True)
@@ -521,6 +522,7 @@ def ctube_leg(args, cpu):
                 "1e-10) instead of dual time stepping, the whole run to t_end = 5e-4 s",
         "unit": "cell-updates/s", "value": float(np.sum(slots * nsteps)) / nwall,
         "wall_s": nwall, "launch_steps": nn, "failed_problems": int(np.sum(nst != 0)),
+        "launch": {"zone_lanes": nlanes, "zone_problems_per_wave": nppw},
         "tubes_to_t_end_per_s": float(b.n_problems) / nwall,
         "newton_steps": int(np.sum(niters)), "max_newton_steps_per_tube": int(np.max(niters)),
         "bulk_ms_per_launch": nb_ms, "zone_ms_per_launch": nz_ms, "step_ms": ns_ms}
