@@ -111,12 +111,6 @@ __device__ __forceinline__ unsigned long long wave_max(unsigned long long v) {
   return v;
 }
 
-__device__ __forceinline__ int wave_or(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
-  return v;
-}
-
 // flux on the regular face j of a tube (0 and N: the domain ends)
 __device__ __forceinline__ void face_flux(const Args& A, int ph, int N, const double* r,
                                           const double* m, int j, double& F0, double& F1) {
