@@ -299,3 +299,14 @@ def test_newton_zone_solver_on_the_paper_runs():
         for (p, _), printed in zip(star_cells(sn, b), rows):
             assert abs(p - printed) < 0.02, (p, printed)
         assert abs((sn.dr[0] - sn.dl[0]) / (sd.dr[0] - sd.dl[0]) - 1.0) < 1e-6
+
+
+@pytest.mark.parametrize("ph,p", [(LIQ, 60000.0), (VAP, 50000.0)])
+def test_constant_state_is_preserved(ph, p):
+    """A tube at rest in one uniform state creates nothing and stays exactly
+    uniform (HLL fluxes of equal states cancel, walls reflect rest)."""
+    b = CW.concat([dict(N=30, h=1e-2, phase=ph, left=(p, 0.0), right=(p, 0.0))],
+                  "rest").with_params(bc_left=0, bc_right=0, t_end=1e-4)
+    st = run(b)
+    assert st.status[0] == 0 and st.face[0] == -1 and st.t[0] == 1e-4
+    assert np.all(st.rho[:30] == b.rho[:30]) and np.all(st.mom[:30] == 0.0)
