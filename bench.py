@@ -67,6 +67,8 @@ def parse():
     ap.add_argument("--ctube-steps", type=int, default=10,
                     help="creation-tube leg: steps timed (the creation step and the heaviest "
                          "dual time steps; 0: run to t_end, about 100 s)")
+    ap.add_argument("--per-problem-steps-ctube", type=int, default=3,
+                    help="steps of the creation tubes' Newton run launched tube by tube")
     ap.add_argument("--other-configs", type=int, default=1,
                     help="also time the other workloads (single cut, 2^20 cells, bubbles)")
     ap.add_argument("--adjoint-one-segment", type=int, default=1,
@@ -515,6 +517,20 @@ def ctube_leg(args, cpu):
         nb_ms, nz_ms, ns_ms = s.last_timing()
         s.time_kernels(False)
         _, nst, nsteps, niters, nface, _, _ = s.problems()
+        # the unbatched form on the first steps: every tube's kernels in turn
+        npp = None
+        if args.per_problem_steps_ctube > 0:
+            s.set_state()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.step_per_problem(args.per_problem_steps_ctube)
+            torch.cuda.synchronize()
+            ppw_s = time.perf_counter() - t0
+            _, _, pp_steps, _, _, _, _ = s.problems()
+            pp_value = float(np.sum(slots * pp_steps)) / ppw_s
+            npp = {"value": pp_value, "unit": "cell-updates/s",
+                   "steps": args.per_problem_steps_ctube,
+                   "batched_speedup": (float(np.sum(slots * nsteps)) / nwall) / pp_value}
     finally:
         s.close()
     rec["newton_zone_solver"] = {
@@ -525,6 +541,7 @@ def ctube_leg(args, cpu):
         "launch": {"zone_lanes": nlanes, "zone_problems_per_wave": nppw},
         "tubes_to_t_end_per_s": float(b.n_problems) / nwall,
         "newton_steps": int(np.sum(niters)), "max_newton_steps_per_tube": int(np.max(niters)),
+        "per_problem": npp,
         "bulk_ms_per_launch": nb_ms, "zone_ms_per_launch": nz_ms, "step_ms": ns_ms}
     if cpu:
         import oracle

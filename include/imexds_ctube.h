@@ -95,6 +95,11 @@ int imexds_ct_set_state(imexds_ct_ctx *ctx, const double *rho, const double *mom
  * nothing).  IMEXDS_ERR_NO_STATE before imexds_ct_set_state. */
 int imexds_ct_step(imexds_ct_ctx *ctx, int32_t n_steps);
 
+/* The same steps launched tube by tube (every kernel of a step once per tube,
+ * in turn, on one stream; no log): the unbatched form, results bitwise those
+ * of imexds_ct_step. */
+int imexds_ct_step_per_problem(imexds_ct_ctx *ctx, int32_t n_steps);
+
 /* Steps in chunks of check_every until no tube is active or max_steps are
  * done (synchronises between chunks); *steps_done gets the steps issued. */
 int imexds_ct_run(imexds_ct_ctx *ctx, int32_t max_steps, int32_t check_every,

@@ -150,8 +150,8 @@ __device__ __forceinline__ double cell_len(double hn, int kind, double wl, doubl
 // ---------------------------------------------------------------------------
 // step (i) on the inner faces of tubes without a created cell
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(TILE) void k_ct_detect(Args A) {
-  const int tile = blockIdx.x;
+__global__ __launch_bounds__(TILE) void k_ct_detect(Args A, int tile_begin) {
+  const int tile = tile_begin + (int)blockIdx.x;
   const int p = A.tile_prob[tile];
   if (A.dt[p] == 0.0 || A.face[p] >= 0) return;  // uniform over the workgroup
   const int j = A.tile_start[tile] + (int)threadIdx.x;  // face between cells j-1 and j
@@ -169,8 +169,8 @@ __global__ __launch_bounds__(TILE) void k_ct_detect(Args A) {
 // ---------------------------------------------------------------------------
 // explicit sweep: one lane per cell, both faces by HLL
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(TILE) void k_ct_bulk(Args A) {
-  const int tile = blockIdx.x;
+__global__ __launch_bounds__(TILE) void k_ct_bulk(Args A, int tile_begin) {
+  const int tile = tile_begin + (int)blockIdx.x;
   const int p = A.tile_prob[tile];
   const int N = A.N[p];
   const int s = A.tile_start[tile] + (int)threadIdx.x;
@@ -972,6 +972,7 @@ struct imexds_ct_ctx {
   int P = 0;
   long long nslot = 0;
   std::vector<int> h_N;
+  std::vector<int> h_tile_first;  // [P + 1] first tile of each tube
   // device
   long long* off = nullptr;
   int *N = nullptr, *phase = nullptr, *face = nullptr, *clipped = nullptr, *status = nullptr,
@@ -1144,7 +1145,7 @@ int ct_one_step(imexds_ct_ctx* c) {
   }
   int e = 0;
   if (c->n_tiles) {
-    ct::k_ct_detect<<<c->n_tiles, ct::TILE, 0, c->ms>>>(A);
+    ct::k_ct_detect<<<c->n_tiles, ct::TILE, 0, c->ms>>>(A, 0);
     e = ct_err(hipGetLastError());
   }
   if (!e) e = ct_err(hipEventRecord(c->ev_fork, c->ms));
@@ -1160,7 +1161,7 @@ int ct_one_step(imexds_ct_ctx* c) {
   if (!e && tm) e = ct_err(hipEventRecord(ev[4], c->zs));
   if (!e && tm) e = ct_err(hipEventRecord(ev[1], c->ms));
   if (!e && c->n_tiles) {
-    ct::k_ct_bulk<<<c->n_tiles, ct::TILE, 0, c->ms>>>(A);
+    ct::k_ct_bulk<<<c->n_tiles, ct::TILE, 0, c->ms>>>(A, 0);
     e = ct_err(hipGetLastError());
   }
   if (!e && tm) e = ct_err(hipEventRecord(ev[2], c->ms));
@@ -1170,6 +1171,69 @@ int ct_one_step(imexds_ct_ctx* c) {
   if (!e && tm) e = ct_err(hipEventRecord(ev[5], c->ms));
   if (e) return e;
   if (tm) c->timed_steps += 1;
+  c->cur ^= 1;
+  c->log_row += 1;
+  return 0;
+}
+
+// The arguments of tube p alone: per-tube arrays shifted to p, one tube, no
+// log (the cell arrays and the tile table stay global).
+ct::Args ct_problem_args(const ct::Args& A, int p) {
+  ct::Args B = A;
+  B.P = 1;
+  B.off += p;
+  B.N += p;
+  B.h += p;
+  B.phase += p;
+  B.face += p;
+  B.dl += p;
+  B.dr += p;
+  B.pw += 4 * (long long)p;
+  B.t += p;
+  B.dt += p;
+  B.clipped += p;
+  B.status += p;
+  B.steps += p;
+  B.iters += p;
+  B.cnt += p;
+  B.fail += p;
+  B.S += p;
+  B.cface += p;
+  B.ccount += p;
+  B.log_cnt = nullptr;
+  B.log_fl = nullptr;
+  B.log_row = -1;
+  return B;
+}
+
+// One step launched tube by tube on the main stream: the unbatched form.
+int ct_one_step_per_problem(imexds_ct_ctx* c) {
+  ct::Args A = ct_args(c, c->cur);
+  A.log_cnt = nullptr;
+  A.log_fl = nullptr;
+  A.log_row = -1;
+  int e = 0;
+  for (int p = 0; p < c->P && !e; ++p) {
+    const ct::Args B = ct_problem_args(A, p);
+    const int t0 = c->h_tile_first[p], nt = c->h_tile_first[p + 1] - t0;
+    if (nt > 0) {
+      ct::k_ct_detect<<<nt, ct::TILE, 0, c->ms>>>(A, t0);
+      e = ct_err(hipGetLastError());
+      if (!e) {
+        ct::k_ct_bulk<<<nt, ct::TILE, 0, c->ms>>>(A, t0);
+        e = ct_err(hipGetLastError());
+      }
+    }
+    if (!e) {
+      ct::k_ct_create<<<1, 64, 0, c->ms>>>(B);
+      e = ct_err(hipGetLastError());
+    }
+    if (!e)
+      e = ct_err(c->zone_solver == IMEXDS_CT_SOLVER_NEWTON ? ct_launch_newton(B, c->zone_lanes, c->ms)
+                                                           : ct_launch_zone(B, c->zone_lanes, c->ms));
+    if (!e) e = ct_err(ct_launch_fin(B, 0, c->ms));
+  }
+  if (e) return e;
   c->cur ^= 1;
   c->log_row += 1;
   return 0;
@@ -1248,12 +1312,16 @@ int imexds_ct_create(imexds_ct_ctx** out, const imexds_material* mat, const imex
   c->h_N.assign(b->n_cells, b->n_cells + P);
   // tiles of TILE regular cells, problem by problem
   std::vector<int> tp, ts;
-  for (int p = 0; p < P; ++p)
+  c->h_tile_first.assign(P + 1, 0);
+  for (int p = 0; p < P; ++p) {
+    c->h_tile_first[p] = (int)tp.size();
     for (int s = 0; s < b->n_cells[p]; s += ct::TILE) {
       tp.push_back(p);
       ts.push_back(s);
     }
+  }
   c->n_tiles = (int)tp.size();
+  c->h_tile_first[P] = c->n_tiles;
   if (!e) e = ct_alloc(&c->off, P + 1);
   for (int** q : {&c->N, &c->phase, &c->face, &c->clipped, &c->status, &c->steps, &c->cnt,
                   &c->fail, &c->cface, &c->ccount})
@@ -1319,6 +1387,15 @@ int imexds_ct_step(imexds_ct_ctx* c, int32_t n_steps) {
   if (!c->have_state) return IMEXDS_ERR_NO_STATE;
   int e = ct_enter(c);
   for (int i = 0; i < n_steps && !e; ++i) e = ct_one_step(c);
+  if (!e) e = ct_leave(c);
+  return e;
+}
+
+int imexds_ct_step_per_problem(imexds_ct_ctx* c, int32_t n_steps) {
+  if (!c || n_steps < 0) return IMEXDS_ERR_INVALID_ARG;
+  if (!c->have_state) return IMEXDS_ERR_NO_STATE;
+  int e = ct_enter(c);
+  for (int i = 0; i < n_steps && !e; ++i) e = ct_one_step_per_problem(c);
   if (!e) e = ct_leave(c);
   return e;
 }

@@ -40,6 +40,7 @@ _create = _sig("imexds_ct_create", ctypes.POINTER(c_vp), ctypes.POINTER(_base.im
                ctypes.POINTER(imexds_ct_batch), c_vp)
 _set_state = _sig("imexds_ct_set_state", c_vp, c_vp, c_vp)
 _step = _sig("imexds_ct_step", c_vp, c_i32)
+_step_pp = _sig("imexds_ct_step_per_problem", c_vp, c_i32)
 _run = _sig("imexds_ct_run", c_vp, c_i32, c_i32, P_i32)
 _get_state = _sig("imexds_ct_get_state", c_vp, c_vp, c_vp)
 _get_problems = _sig("imexds_ct_get_problems", c_vp, P_dbl, P_i32, P_i32, P_i64, P_i32, P_dbl,
@@ -54,7 +55,8 @@ _last_timing = _sig("imexds_ct_last_timing", c_vp, P_dbl, P_dbl, P_dbl)
 _L.imexds_ct_destroy.restype = None
 _L.imexds_ct_destroy.argtypes = [c_vp]
 
-EXPORTED = ["imexds_ct_create", "imexds_ct_set_state", "imexds_ct_step", "imexds_ct_run",
+EXPORTED = ["imexds_ct_create", "imexds_ct_set_state", "imexds_ct_step",
+            "imexds_ct_step_per_problem", "imexds_ct_run",
             "imexds_ct_get_state", "imexds_ct_get_problems", "imexds_ct_enable_log",
             "imexds_ct_get_log", "imexds_ct_set_launch", "imexds_ct_set_solver",
             "imexds_ct_get_sizes",
@@ -86,6 +88,10 @@ def imexds_ct_set_state(ctx, rho, mom):
 
 def imexds_ct_step(ctx, n_steps):
     _check(_step(c_vp(ctx), int(n_steps)), "imexds_ct_step")
+
+
+def imexds_ct_step_per_problem(ctx, n_steps):
+    _check(_step_pp(c_vp(ctx), int(n_steps)), "imexds_ct_step_per_problem")
 
 
 def imexds_ct_run(ctx, max_steps, check_every=64):
@@ -180,6 +186,9 @@ class CreationTubes:
 
     def step(self, n):
         imexds_ct_step(self.ctx, n)
+
+    def step_per_problem(self, n):
+        imexds_ct_step_per_problem(self.ctx, n)
 
     def run(self, max_steps=1 << 30, check_every=64):
         return imexds_ct_run(self.ctx, max_steps, check_every)
