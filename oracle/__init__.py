@@ -52,7 +52,8 @@ class _Par(ctypes.Structure):
                 ("alpha_floor", ctypes.c_double), ("merge_safety", ctypes.c_double),
                 ("bc_left", ctypes.c_int), ("bc_right", ctypes.c_int),
                 ("newton_maxit", ctypes.c_int), ("newton_rtol", ctypes.c_double),
-                ("t_end", ctypes.c_double)]
+                ("t_end", ctypes.c_double), ("zone_solver", ctypes.c_int),
+                ("zn_maxit", ctypes.c_int), ("zn_rtol", ctypes.c_double)]
 
 
 class _Iface(ctypes.Structure):
@@ -139,7 +140,8 @@ def _mat(m):
 def _par(p):
     return _Par(p.cfl, p.zone_half, p.theta_nb, p.tol_mode, p.tol_nb, p.tol_tiny, p.tol_rel,
                 p.lmax, p.alpha_floor, p.merge_safety, p.bc_left, p.bc_right, p.newton_maxit,
-                p.newton_rtol, p.t_end)
+                p.newton_rtol, p.t_end, int(getattr(p, "zone_solver", 0)),
+                int(getattr(p, "zn_maxit", 30)), float(getattr(p, "zn_rtol", 1e-10)))
 
 
 def _ptr(a, t):

@@ -103,6 +103,9 @@ typedef struct {
   int newton_maxit;
   double newton_rtol;
   double t_end;
+  int zone_solver; /* 0: Algorithm 2 (dual time stepping), 1: Newton on the implicit step */
+  int zn_maxit;    /* Newton: at most this many steps */
+  double zn_rtol;  /* Newton: relative step tolerance */
 } or_params;
 
 /* ------------------------------------------------------------------ */
@@ -1042,6 +1045,103 @@ static int or_zone_dts(const or_material *M, const or_params *P, const or_zone *
   return 0;
 }
 
+#ifndef OR_TANGENT
+/* Newton on the implicit step of a zone (the Newton-like solver of the
+ * paper's outlook), the alternative to or_zone_dts: unknowns the zone
+ * iterates W, equations
+ *   R_c(W) = (h_c(W) / h_c^n) W_c - U_c^n + (dt / h_c^n)(F_{c+1/2}(W) - F_{c-1/2}(W)),
+ * h_c(W) = h_c^n + mov_c w(W) dt, the zone's outer faces from U^n; from
+ * W = U^n a forward-difference Jacobian (step 1e-7 max(|W_j|, 1), the
+ * interface solve warm-started from the base point's), Gaussian elimination
+ * with partial pivoting (first largest pivot), full steps; converged when
+ * every step component is below zn_rtol max(|W_j|, 1); at most zn_maxit
+ * steps.  Shrink and state checks, Part 2 and the return codes as in
+ * or_zone_dts (the shrink check on every base point). */
+static int or_gauss_pp(int n, double A[][2 * OR_MAXC], double *b, double *x);
+
+static int or_zone_resid(const or_material *M, const or_params *P, const or_zone *Z, double dt,
+                         double W[][2], double *pw, double *R, double *w, int check,
+                         int *shrink_cell) {
+  double F[OR_MAXC + 1][2];
+  int c, q;
+  if (!or_zone_fluxes(M, P, Z, W, F, pw, w)) return OR_ST_NEWTON;
+  for (c = 0; c < Z->m; ++c) {
+    double hk = Z->hn[c] + ((double)Z->mov[c] * *w) * dt;
+    if (check && Z->mov[c] != 0 && !(hk >= 0.5 * Z->hh[c])) {
+      *shrink_cell = c;
+      return OR_ST_MESH;
+    }
+    double ihn = 1.0 / Z->hn[c];
+    for (q = 0; q < 2; ++q)
+      R[2 * c + q] = (hk * ihn) * W[c][q] - Z->U0[c][q] + (dt * ihn) * (F[c + 1][q] - F[c][q]);
+  }
+  return 0;
+}
+
+static int or_zone_newton(const or_material *M, const or_params *P, const or_zone *Z, double dt,
+                          double *pw, double U1[][2], double *wstar, int *count, int *lmax_hit,
+                          int *shrink_cell) {
+  int m = Z->m, n = 2 * m, c, q, j, it, conv = 0;
+  double W[OR_MAXC][2], R[2 * OR_MAXC], Rp[2 * OR_MAXC], J[2 * OR_MAXC][2 * OR_MAXC];
+  double rhs[2 * OR_MAXC], d[2 * OR_MAXC], w = 0.0;
+  *shrink_cell = -1;
+  *lmax_hit = 0;
+  *count = 0;
+  for (c = 0; c < m; ++c) {
+    W[c][0] = Z->U0[c][0];
+    W[c][1] = Z->U0[c][1];
+  }
+  for (it = 0; it < P->zn_maxit && !conv; ++it) {
+    int st = or_zone_resid(M, P, Z, dt, W, pw, R, &w, 1, shrink_cell);
+    if (st) return st;
+    for (j = 0; j < n; ++j) {
+      int cj = j / 2, qj = j % 2, dummy;
+      double xj = W[cj][qj];
+      double e = 1e-7 * (fabs(xj) > 1.0 ? fabs(xj) : 1.0);
+      double g[2] = {pw[0], pw[1]}, a;
+      W[cj][qj] = xj + e;
+      st = or_zone_resid(M, P, Z, dt, W, g, Rp, &a, 0, &dummy);
+      W[cj][qj] = xj;
+      if (st) return st;
+      for (q = 0; q < n; ++q) J[q][j] = (Rp[q] - R[q]) / e;
+    }
+    for (q = 0; q < n; ++q) rhs[q] = -R[q];
+    if (!or_gauss_pp(n, J, rhs, d)) return OR_ST_NEWTON;
+    conv = 1;
+    for (j = 0; j < n; ++j) {
+      double xj = W[j / 2][j % 2];
+      double sc = fabs(xj) > 1.0 ? fabs(xj) : 1.0;
+      conv = conv && (fabs(d[j]) <= P->zn_rtol * sc);
+    }
+    for (c = 0; c < m; ++c) {
+      W[c][0] = W[c][0] + d[2 * c];
+      W[c][1] = W[c][1] + d[2 * c + 1];
+      if (!or_state_ok(W[c][0], W[c][1])) return OR_ST_NONPHYS;
+    }
+    *count = it + 1;
+  }
+  if (!conv) *lmax_hit = 1;
+  /* Part 2 */
+  double F[OR_MAXC + 1][2], ih[OR_MAXC];
+  if (!or_zone_fluxes(M, P, Z, W, F, pw, &w)) return OR_ST_NEWTON;
+  for (c = 0; c < m; ++c) {
+    double hk = Z->hn[c] + ((double)Z->mov[c] * w) * dt;
+    ih[c] = 1.0 / hk;
+    if (Z->mov[c] != 0 && !(hk >= 0.5 * Z->hh[c])) {
+      *shrink_cell = c;
+      return OR_ST_MESH;
+    }
+  }
+  for (c = 0; c < m; ++c) {
+    for (q = 0; q < 2; ++q)
+      U1[c][q] = (Z->hn[c] * Z->U0[c][q] - dt * (F[c + 1][q] - F[c][q])) * ih[c];
+    if (!or_state_ok(U1[c][0], U1[c][1])) return OR_ST_NONPHYS;
+  }
+  *wstar = w;
+  return 0;
+}
+#endif
+
 /* Predict, merge, solve and re-align one interface zone. Writes the zone's
  * new cell values into (rn, mn). Returns 0 or a status bit. */
 static int or_zone_step(const or_material *M, const or_params *P, or_prob *pb, int k,
@@ -1080,7 +1180,13 @@ static int or_zone_step(const or_material *M, const or_params *P, or_prob *pb, i
     real pw[2] = {I.pl, I.pr};
     if (!or_zone_build(M, P, pb, k, ph, zlo, zhi, tr, merge, wp, dt, &Z)) return OR_ST_MESH;
     int sc;
+#ifndef OR_TANGENT
+    int st = P->zone_solver == 1
+                 ? or_zone_newton(M, P, &Z, dt, pw, U1, &wstar, &count, &lmax_hit, &sc)
+                 : or_zone_dts(M, P, &Z, dt, pw, U1, &wstar, &count, &lmax_hit, &sc, force);
+#else
     int st = or_zone_dts(M, P, &Z, dt, pw, U1, &wstar, &count, &lmax_hit, &sc, force);
+#endif
     if (st == OR_ST_MESH && !merge && sc == Z.tiny) {
       merge = 1;
       redo = 1;
@@ -1848,7 +1954,7 @@ static int or_ct_resid(const or_material *M, const or_params *P, int ph, const o
 
 /* A x = b by Gaussian elimination with partial pivoting (the first row with
  * the largest |pivot|); A and b are overwritten; 0 if singular */
-static int or_gauss_pp(int n, double A[][OR_CT_NMAX], double *b, double *x) {
+static int or_gauss_pp(int n, double A[][2 * OR_MAXC], double *b, double *x) {
   int k, i, j;
   for (k = 0; k < n; ++k) {
     int piv = k;

@@ -61,6 +61,9 @@ class Params:
     newton_maxit: int = 50
     newton_rtol: float = 1e-14
     t_end: float = math.inf
+    zone_solver: int = 0  # 0: Algorithm 2 (dual time stepping); 1: Newton on the implicit step
+    zn_maxit: int = 30    # Newton zone solver: at most this many steps
+    zn_rtol: float = 1e-10  # Newton zone solver: relative step tolerance
 
     def replace(self, **kw) -> "Params":
         return dataclasses.replace(self, **kw)

@@ -490,3 +490,46 @@ def test_reproducible_logarithm_is_accurate():
     assert worst <= 4.0
     assert L.oracle_log(1.0) == 0.0
     assert math.isnan(L.oracle_log(-1.0)) and L.oracle_log(0.0) == -math.inf
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_newton_zone_solver_lands_on_the_direct_newton_solution(material, seed):
+    """The Newton zone solver (forward differences, the alternative to
+    Algorithm 2 that the paper's outlook names) ends its step on the solution
+    of the zone's implicit Euler system that the independent central-
+    difference Newton solve finds (Part 2 then reproduces that iterate)."""
+    import copy
+    b = W.single_cut_problem(seed, alpha=3e-3)
+    st = oracle.State(b)
+    oracle.run(st, material, W.single_cut_params(), 3)
+    P = W.single_cut_params()
+    rc, Wd, Wn, dt = oracle.zone_fixed_point(st, material,
+                                             P.replace(tol_mode=1, tol_rel=1e-15, lmax=200000))
+    assert rc == 0
+    st2 = copy.deepcopy(st)
+    lc, lf, lz = oracle.run(st2, material, P.replace(zone_solver=1), 1, log=True)
+    assert st2.status[0] == 0 and 1 <= lc.ravel()[0] <= 8
+    zlo, m = int(lz.ravel()[0]), Wn.shape[0]
+    got = np.stack([st2.rho[zlo:zlo + m], st2.mom[zlo:zlo + m]], 1)
+    scale = np.maximum(np.abs(Wn), 1.0)
+    assert np.max(np.abs(got - Wn) / scale) < 1e-8
+
+
+def test_newton_zone_solver_on_a_batch(material):
+    """On a seeded batch with merges the Newton zone solver takes the same
+    mesh decisions as Algorithm 2, a few steps per zone and time step, and
+    ends within Algorithm 2's own tolerance of its states."""
+    b = W.random_batch(seed=7, n_problems=32, nmin=256, nmax=1024)
+    P = W.random_batch_params()
+    out = []
+    for solver in (0, 1):
+        st = oracle.State(b)
+        lc, lf, lz = oracle.run(st, material, P.replace(zone_solver=solver), 100, log=True,
+                                threads=4)
+        out.append((st, lc, lf, lz))
+    (s0, c0, f0, z0), (s1, c1, f1, z1) = out
+    assert np.all(s0.status == 0) and np.all(s1.status == 0)
+    assert np.array_equal(f0 & ~oracle.FL_LMAX, f1) and np.array_equal(z0, z1)
+    assert np.array_equal(s0.home, s1.home)
+    assert c1.max() <= 8 and c1.mean() < 4 < c0.mean()
+    assert np.max(np.abs(s1.rho - s0.rho) / np.abs(s0.rho)) < 1e-6
