@@ -204,6 +204,25 @@ int imexds_get_stats(imexds_ctx *ctx, imexds_stats *out);
 int imexds_set_launch(imexds_ctx *ctx, int32_t tile_cells, int32_t zones_per_group,
                       int32_t zone_groups, int32_t graph_steps, int32_t zone_lanes);
 
+/* The solver of the zones' implicit step.  IMEXDS_ZONE_DTS (default):
+ * Algorithm 2, dual time stepping with the stop rule of the parameters.
+ * IMEXDS_ZONE_NEWTON: Newton on the same implicit step (the Newton-like
+ * solver of the paper's outlook), zone_half 1 or 2 only
+ * (IMEXDS_ERR_UNSUPPORTED otherwise): unknowns the zone's values W,
+ * residual R_i(W) = (h_i(W)/h_i^n) W_i - U_i^n + (dt/h_i^n)(F_{i+1/2}(W) -
+ * F_{i-1/2}(W)) with h_i(W) = h_i^n + mov_i w(W) dt and the zone's outer
+ * faces from U^n; from W = U^n a forward-difference Jacobian (step
+ * 1e-7 max(|W_j|, 1)), Gaussian elimination with partial pivoting, full
+ * steps; converged when every step component is below rtol max(|W_j|, 1)
+ * (e.g. 1e-10), at most maxit steps (e.g. 30; then IMEXDS_FL_LMAX).  The
+ * prediction, merges, redo, Part 2 and re-split are those of Algorithm 2's
+ * path; the logs count Newton steps.  Not differentiated:
+ * imexds_forward_ckpt returns IMEXDS_ERR_UNSUPPORTED while it is set.
+ * Drops captured graphs; synchronizes. */
+#define IMEXDS_ZONE_DTS 0
+#define IMEXDS_ZONE_NEWTON 1
+int imexds_set_zone_solver(imexds_ctx *ctx, int32_t solver, int32_t maxit, double rtol);
+
 /* Times launch configurations on the current state for steps_per_trial
  * steps each (zone launch shapes first, then tile classes), restores the
  * state afterwards and keeps the fastest configuration.  Results (host, may

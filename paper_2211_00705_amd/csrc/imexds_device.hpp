@@ -49,6 +49,8 @@ struct Mat {
 struct Par {
   double cfl, theta_nb, tol_nb, tol_tiny, tol_rel, alpha_floor, merge_safety, newton_rtol, t_end;
   int zone_half, tol_mode, lmax, bc_left, bc_right, newton_maxit;
+  int zone_solver, zn_maxit;  // zone solver: 0 Algorithm 2, 1 Newton (at most zn_maxit steps)
+  double zn_rtol;             // Newton: relative step tolerance
 };
 
 __device__ __forceinline__ double d_a2(const Mat& M, int ph) { return ph == VAP ? M.a2v : M.a2l; }

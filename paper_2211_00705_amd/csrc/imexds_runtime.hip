@@ -249,6 +249,7 @@ int build_tiles(imexds_ctx* c, int tile_cells) {
 
 hipError_t launch_zones(imexds_ctx* c, const StepArgs& A, int k0, int k1, int groups,
                         hipStream_t s) {
+  if (c->par.zone_solver == IMEXDS_ZONE_NEWTON) return imexds::launch_zone_newton(A, k0, k1, s);
   if (c->zone_lanes == 8) return imexds::launch_zone8(A, k0, k1, groups, s);
   return imexds::launch_zone(A, k0, k1, groups, s);
 }
@@ -739,6 +740,9 @@ static int create_impl(imexds_ctx* c, const imexds_material* mat, const imexds_p
   c->par.bc_left = par->bc_left;
   c->par.bc_right = par->bc_right;
   c->par.newton_maxit = par->newton_maxit;
+  c->par.zone_solver = IMEXDS_ZONE_DTS;
+  c->par.zn_maxit = 30;
+  c->par.zn_rtol = 1e-10;
 
   CK(hipGetDevice(&c->device));
   CK(hipStreamCreateWithFlags(&c->ms, hipStreamNonBlocking));
@@ -1047,6 +1051,25 @@ int imexds_set_launch(imexds_ctx* c, int32_t tile_cells, int32_t zones_per_group
   return 0;
 }
 
+int imexds_set_zone_solver(imexds_ctx* c, int32_t solver, int32_t maxit, double rtol) {
+  if (!c) return IMEXDS_ERR_INVALID_ARG;
+  if (solver != IMEXDS_ZONE_DTS && solver != IMEXDS_ZONE_NEWTON) return IMEXDS_ERR_INVALID_ARG;
+  if (maxit < 1 || !(rtol > 0.0) || !std::isfinite(rtol)) return IMEXDS_ERR_INVALID_ARG;
+  if (solver == IMEXDS_ZONE_NEWTON && c->par.zone_half > 2) {
+    snprintf(g_err, sizeof(g_err), "the Newton zone solver covers zone_half 1 and 2");
+    return IMEXDS_ERR_UNSUPPORTED;
+  }
+  CK(hipSetDevice(c->device));
+  CK(hipStreamSynchronize(c->ms));
+  CK(hipStreamSynchronize(c->zs));
+  c->par.zone_solver = solver;
+  c->par.zn_maxit = maxit;
+  c->par.zn_rtol = rtol;
+  c->adj_ready = false;
+  drop_graph(c);
+  return 0;
+}
+
 int imexds_autotune(imexds_ctx* c, int32_t steps_per_trial, int32_t* tile_cells,
                     int32_t* zones_per_group, int32_t* zone_groups, int32_t* zone_lanes,
                     double* ms_per_step) {
@@ -1178,6 +1201,10 @@ int imexds_set_tau(imexds_ctx* c, double tau) {
 int imexds_forward_ckpt(imexds_ctx* c, int32_t n_steps, int32_t ckpt_every) {
   if (!c || n_steps < 0 || ckpt_every < 1) return IMEXDS_ERR_INVALID_ARG;
   if (!c->has_state) return IMEXDS_ERR_NO_STATE;
+  if (c->par.zone_solver != IMEXDS_ZONE_DTS) {
+    snprintf(g_err, sizeof(g_err), "the adjoint covers the dual time zone solver only");
+    return IMEXDS_ERR_UNSUPPORTED;
+  }
   int r = begin_call(c);
   if (r) return r;
   CK(hipStreamSynchronize(c->ms));

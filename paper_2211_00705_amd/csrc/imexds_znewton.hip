@@ -1,0 +1,559 @@
+// imexds_znewton.hip -- the interface zones of one step solved by Newton on
+// their implicit step instead of Algorithm 2 (the Newton-like solver for the
+// small implicit systems that the paper's outlook names).  Everything around
+// the solve is the zone step of k_zone: the prediction of the boundary speed
+// from U^n, the merge test, the zone (tiny cut piece +- Z slots, a merged
+// piece folded into its neighbour), the redo with a merge when the tiny cell
+// collapses, Part 2, the interface advance and re-split, the records, logs
+// and the CFL contribution.
+//
+// The solve: unknowns the zone's values W (2 per position, positions that
+// are not zone cells padded with identity rows), residual
+//   R_i(W) = (h_i(W) / h_i^n) W_i - U_i^n + (dt / h_i^n)(F_{i+1/2}(W) - F_{i-1/2}(W)),
+// h_i(W) = h_i^n + mov_i w(W) dt, the zone's outer faces from U^n; a
+// forward-difference Jacobian (step 1e-7 max(|W_j|, 1), the interface solve
+// warm-started from the base point's), Gaussian elimination with partial
+// pivoting, full steps from W = U^n, converged when every step component is
+// below zn_rtol max(|W_j|, 1), at most zn_maxit steps (then flagged like
+// l_max).  The padded identity rows never change the elimination of the
+// zone's rows (their entries in the zone's columns are zero), so the result
+// is the compact system's.
+//
+// A zone has G = 1 + 2 MC groups of two lanes (the pair form of the
+// interface solver: one lane per side of the interface problem).  Every
+// group evaluates the prediction and each base point with identical inputs
+// (identical results, no exchange); group g >= 1 then evaluates the point
+// moved along unknown g - 1, so the difference columns run side by side;
+// every lane gathers the columns and runs the same elimination.
+#include "imexds_device.hpp"
+#include "imexds_kernels.hpp"
+
+namespace imexds {
+namespace {
+
+constexpr unsigned long long NT_NAN_BITS = 0x7FF8000000000000ull;
+
+__device__ __forceinline__ unsigned long long nt_speed_bits(const Mat& M, int ph, double r,
+                                                            double m) {
+  if (!d_state_ok(r, m)) return NT_NAN_BITS;
+  return (unsigned long long)__double_as_longlong(fabs(m / r) + d_a(M, ph));
+}
+
+template <int ZH>
+__global__ __launch_bounds__(64) void k_zone_nt(StepArgs A, int if_begin, int if_end) {
+  constexpr int MC = 2 * ZH + 1, NV = 2 * MC, G = NV + 1, TL = 2 * G, ZPW = 64 / TL;
+  const Mat& M = A.mat;
+  const Par& P = A.par;
+  const int lane = (int)threadIdx.x;
+  if (lane >= ZPW * TL) return;
+  const int tl = lane % TL;
+  const int grp = tl >> 1, half = tl & 1;
+  const int lane0 = lane - tl;
+  const int k = if_begin + (int)blockIdx.x * ZPW + lane / TL;
+  if (k >= if_end) return;  // the lanes of a zone are whole
+  const bool writer = tl == 0;
+  const int p = A.iface_prob[k];
+  const int kk = A.iface_local[k];
+  const double dt = A.dt[p];
+  const int home = A.rec_home0[k];
+  const double hl = A.rec_hl0[k];
+  const double rpw0 = A.rec_pw0[2 * k], rpw1 = A.rec_pw0[2 * k + 1];
+  const int warm = A.rec_warm0[k];
+  int row = -1;
+  if (A.log_count && A.log_row) {
+    row = *A.log_row;
+    if (row >= A.log_max) row = -1;
+  }
+  const long long so = A.slot_off[p];
+  const int ns = (int)(A.slot_off[p + 1] - so);
+  const int sL = home + kk;
+  if (dt == 0.0 || sL < 0 || sL + 1 >= ns) {
+    if (writer) {
+      if (dt != 0.0) atomicOr(A.fail_acc + p, ST_MESH);
+      A.rec_home1[k] = home;
+      A.rec_hl1[k] = hl;
+      A.rec_pw1[2 * k] = rpw0;
+      A.rec_pw1[2 * k + 1] = rpw1;
+      A.rec_warm1[k] = warm;
+      if (row >= 0) {
+        const long long o = (long long)row * A.n_iface + k;
+        A.log_count[o] = 0;
+        A.log_flags[o] = dt == 0.0 ? FL_INACTIVE : FL_FAIL;
+        A.log_zlo[o] = -1;
+      }
+    }
+    return;
+  }
+  const double h = A.h[p];
+  const int phl = A.phase_first[p] ^ (kk & 1), phr = phl ^ 1;
+  int zlo, zhi;
+  bool tr;
+  d_zone_range(sL, hl, h, ZH, ns, zlo, zhi, tr);
+  const int nr = zhi - zlo + 1, iL = sL - zlo, iR = iL + 1;
+  const double* r0 = A.rho0 + so;
+  const double* m0 = A.mom0 + so;
+  double Ur[MC], Um[MC];
+#pragma unroll
+  for (int i = 0; i < MC; ++i) {
+    Ur[i] = i < nr ? r0[zlo + i] : 1.0;
+    Um[i] = i < nr ? m0[zlo + i] : 0.0;
+  }
+  double FL0, FL1, FR0, FR1;
+  {
+    const int phz = (zlo <= sL) ? phl : phr;
+    if (zlo == 0)
+      d_bflux(M, phz, false, P.bc_left, r0[0], m0[0], FL0, FL1);
+    else
+      d_hll(M, phz, r0[zlo - 1], m0[zlo - 1], r0[zlo], m0[zlo], FL0, FL1);
+    const int phe = (zhi <= sL) ? phl : phr;
+    if (zhi == ns - 1)
+      d_bflux(M, phe, true, P.bc_right, r0[ns - 1], m0[ns - 1], FR0, FR1);
+    else
+      d_hll(M, phe, r0[zhi], m0[zhi], r0[zhi + 1], m0[zhi + 1], FR0, FR1);
+  }
+  // zone state
+  bool merge = false, redo = false;
+  int skip = -1, into = -1, ic = 0, icr = 1, tiny = 0;
+  double Mr = 0.0, Mm = 0.0, hn_l = 0.0, hn_r = 0.0, hh_l = 0.0, hh_r = 0.0;
+  double Ipl = 0.0, Ipr = 0.0, wp = 0.0;
+  double W0[MC], W1[MC];
+#pragma unroll
+  for (int i = 0; i < MC; ++i) {
+    W0[i] = Ur[i];
+    W1[i] = Um[i];
+  }
+  double pw0 = 0.0, pw1 = 0.0, gw0 = 0.0, gw1 = 0.0, w = 0.0;
+  double R[NV], Jc[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    R[i] = 0.0;
+    Jc[i] = 0.0;
+  }
+  const int colj = grp - 1;
+  int status = 0, it = 0, phase = -2;  // -2: prediction, -1: base point, 0: columns
+  double ecol = 0.0;
+  bool final_pass = false, conv = false, finished = false, setup = false;
+  double wstar = 0.0;
+#pragma unroll 1
+  for (;;) {
+    // ---------------- (re)build the zone after the prediction or a redo ----------------
+    if (setup) {
+      setup = false;
+      skip = -1;
+      into = -1;
+      if (merge) {
+        skip = tr ? iR : iL;
+        into = tr ? iR + 1 : iL - 1;
+        if (into < 0 || into >= nr) status = ST_MESH;
+      }
+      if (status) break;
+      double rskip = 0.0, mskip = 0.0, rin = 0.0, min_ = 0.0;
+#pragma unroll
+      for (int i = 0; i < MC; ++i) {
+        if (i == skip) {
+          rskip = Ur[i];
+          mskip = Um[i];
+        }
+        if (i == into) {
+          rin = Ur[i];
+          min_ = Um[i];
+        }
+      }
+      const double hLp = hl, hRp = h - hl;
+      const double ht = tr ? hRp : hLp;
+      const double hm = h + ht;
+      if (merge) {
+        Mr = (h * rin + ht * rskip) / hm;
+        Mm = (h * min_ + ht * mskip) / hm;
+      }
+      ic = (merge && !tr) ? into : iL;
+      icr = (merge && tr) ? into : iR;
+      tiny = merge ? into : (tr ? iR : iL);
+      hn_l = (merge && !tr) ? hm : hLp;
+      hn_r = (merge && tr) ? hm : hRp;
+      hh_l = hn_l + (1.0 * wp) * dt;
+      hh_r = hn_r + (-1.0 * wp) * dt;
+      const double hh_f = h + (0.0 * wp) * dt;
+      double th_l = hh_l / h, th_r = hh_r / h, th_f = hh_f / h;
+      if (th_l > P.theta_nb) th_l = P.theta_nb;
+      if (th_r > P.theta_nb) th_r = P.theta_nb;
+      if (th_f > P.theta_nb) th_f = P.theta_nb;
+      if (!(th_l > 0.0) || !(th_r > 0.0) || !(th_f > 0.0)) {
+        status = ST_MESH;
+        break;
+      }
+#pragma unroll
+      for (int i = 0; i < MC; ++i) {
+        W0[i] = (i == into) ? Mr : Ur[i];
+        W1[i] = (i == into) ? Mm : Um[i];
+      }
+      pw0 = Ipl;
+      pw1 = Ipr;
+      it = 0;
+      conv = false;
+      final_pass = false;
+      phase = -1;
+    }
+    const bool pred = phase == -2;
+    const bool fd = phase == 0;
+    // the point: W (or U^n for the prediction), moved along colj by groups
+    // >= 1 in the column pass when that unknown belongs to the zone
+    const int cpos = colj >> 1, ccmp = colj & 1;
+    const bool cact = colj >= 0 && cpos < nr && cpos != skip;
+    const bool moved = fd && cact;
+    double X0[MC], X1[MC];
+#pragma unroll
+    for (int i = 0; i < MC; ++i) {
+      const double a0 = pred ? Ur[i] : W0[i], a1 = pred ? Um[i] : W1[i];
+      X0[i] = (moved && cpos == i && ccmp == 0) ? a0 + ecol : a0;
+      X1[i] = (moved && cpos == i && ccmp == 1) ? a1 + ecol : a1;
+    }
+    // the interface problem: positions iL, iR (prediction) or ic, icr
+    const int a = pred ? iL : ic, b = pred ? iR : icr;
+    double ql0 = 0.0, ql1 = 0.0, qr0 = 0.0, qr1 = 0.0;
+#pragma unroll
+    for (int i = 0; i < MC; ++i) {
+      if (i == a) {
+        ql0 = X0[i];
+        ql1 = X1[i];
+      }
+      if (i == b) {
+        qr0 = X0[i];
+        qr1 = X1[i];
+      }
+    }
+    const bool hg = pred ? warm != 0 : true;
+    const double g0 = pred ? rpw0 : (fd ? gw0 : pw0);
+    const double g1 = pred ? rpw1 : (fd ? gw1 : pw1);
+    IfaceOut o;
+    const bool okl = d_iface_solve_t<true>(M, P.newton_maxit, P.newton_rtol, phl, ql0, ql1, phr,
+                                           qr0, qr1, hg, g0, g1, half, lane ^ 1, o);
+    const unsigned long long failm = __ballot(!okl);
+    const unsigned long long zm = ((1ull << TL) - 1ull) << lane0;
+    if (failm & zm) {
+      status = ST_NEWTON;
+      break;
+    }
+    if (pred) {
+      Ipl = o.pl;
+      Ipr = o.pr;
+      wp = o.w;
+      const double ht = tr ? h - hl : hl;
+      const double rate = tr ? -wp : wp;
+      const double hfl = P.alpha_floor * h;
+      merge = (ht < hfl) || (ht + (P.merge_safety * rate) * dt < hfl);
+      setup = true;
+      continue;
+    }
+    if (!fd) {
+      pw0 = o.pl;
+      pw1 = o.pr;
+      w = o.w;
+    }
+    const double we = o.w;
+    // right face of each zone position at the point
+    double FR_0[MC], FR_1[MC];
+#pragma unroll
+    for (int i = 0; i < MC; ++i) {
+      FR_0[i] = 0.0;
+      FR_1[i] = 0.0;
+      if (i >= nr || i == skip) continue;
+      if (i == nr - 1) {
+        FR_0[i] = FR0;
+        FR_1[i] = FR1;
+      } else if (i == ic) {
+        FR_0[i] = o.F0;
+        FR_1[i] = o.F1;
+      } else if (i + 1 < MC) {
+        const int ph = (zlo + i <= sL) ? phl : phr;
+        d_hll(M, ph, X0[i], X1[i], X0[i + 1], X1[i + 1], FR_0[i], FR_1[i]);
+      }
+    }
+    const double hk_l = hn_l + (1.0 * we) * dt;
+    const double hk_r = hn_r + (-1.0 * we) * dt;
+    const double hk_f = h + (0.0 * we) * dt;
+    if (!fd) {
+      const bool bl = !(hk_l >= 0.5 * hh_l), br = !(hk_r >= 0.5 * hh_r);
+      int shrink = -1;
+      if (bl && br)
+        shrink = ic < icr ? ic : icr;
+      else if (bl)
+        shrink = ic;
+      else if (br)
+        shrink = icr;
+      if (shrink >= 0) {
+        if (!merge && shrink == tiny) {
+          merge = true;
+          redo = true;
+          setup = true;
+          continue;
+        }
+        status = ST_MESH;
+        break;
+      }
+    }
+    // residual (or Part 2) of every zone position
+    double RX[NV];
+    bool okw = true;
+#pragma unroll
+    for (int i = 0; i < MC; ++i) {
+      RX[2 * i] = 0.0;
+      RX[2 * i + 1] = 0.0;
+      if (i >= nr || i == skip) continue;
+      double fl0, fl1;
+      if (i == 0) {
+        fl0 = FL0;
+        fl1 = FL1;
+      } else if (i >= 2 && skip == i - 1) {
+        fl0 = FR_0[i >= 2 ? i - 2 : 0];
+        fl1 = FR_1[i >= 2 ? i - 2 : 0];
+      } else {
+        fl0 = FR_0[i - 1];
+        fl1 = FR_1[i - 1];
+      }
+      const double u0r = (i == into) ? Mr : Ur[i];
+      const double u0m = (i == into) ? Mm : Um[i];
+      const double hni = (i == ic) ? hn_l : ((i == icr) ? hn_r : h);
+      const double hki = (i == ic) ? hk_l : ((i == icr) ? hk_r : hk_f);
+      if (final_pass) {
+        const double ih = 1.0 / hki;
+        const double n0 = (hni * u0r - dt * (FR_0[i] - fl0)) * ih;
+        const double n1 = (hni * u0m - dt * (FR_1[i] - fl1)) * ih;
+        if (!d_state_ok(n0, n1)) okw = false;
+        W0[i] = n0;
+        W1[i] = n1;
+      } else {
+        const double ihn = 1.0 / hni;
+        RX[2 * i] = (hki * ihn) * X0[i] - u0r + (dt * ihn) * (FR_0[i] - fl0);
+        RX[2 * i + 1] = (hki * ihn) * X1[i] - u0m + (dt * ihn) * (FR_1[i] - fl1);
+      }
+    }
+    if (final_pass) {
+      if (!okw) {
+        status = ST_NONPHYS;
+      } else {
+        wstar = w;
+        finished = true;
+      }
+      break;
+    }
+    if (!fd) {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) R[i] = RX[i];
+      gw0 = pw0;
+      gw1 = pw1;
+      double xj = 0.0;
+#pragma unroll
+      for (int i = 0; i < MC; ++i) {
+        if (cpos == i && ccmp == 0) xj = W0[i];
+        if (cpos == i && ccmp == 1) xj = W1[i];
+      }
+      ecol = 1e-7 * (fabs(xj) > 1.0 ? fabs(xj) : 1.0);
+      phase = 0;
+      continue;
+    }
+#pragma unroll
+    for (int i = 0; i < NV; ++i) Jc[i] = (RX[i] - R[i]) / ecol;
+    // gather the columns (group j + 1 holds column j); columns of positions
+    // outside the zone are unit columns, their right-hand sides zero
+    double Am[NV][NV], bb[NV], d[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      const bool act = (j >> 1) < nr && (j >> 1) != skip;
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        const double v = __shfl(Jc[i], lane0 + 2 * (j + 1), 64);
+        Am[i][j] = act ? v : (i == j ? 1.0 : 0.0);
+      }
+      bb[j] = act ? -R[j] : 0.0;
+    }
+    bool sing = false;
+#pragma unroll
+    for (int kq = 0; kq < NV; ++kq) {
+      int piv = kq;
+      double pv = fabs(Am[kq][kq]);
+#pragma unroll
+      for (int i = kq + 1; i < NV; ++i)
+        if (fabs(Am[i][kq]) > pv) {
+          piv = i;
+          pv = fabs(Am[i][kq]);
+        }
+      double rk[NV], bk = bb[kq];
+#pragma unroll
+      for (int j = 0; j < NV; ++j) rk[j] = Am[kq][j];
+#pragma unroll
+      for (int i = kq + 1; i < NV; ++i) {
+        const bool sw = piv == i;
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+          const double t = Am[i][j];
+          Am[i][j] = sw ? rk[j] : t;
+          Am[kq][j] = sw ? t : Am[kq][j];
+        }
+        const double tb = bb[i];
+        bb[i] = sw ? bk : tb;
+        bb[kq] = sw ? tb : bb[kq];
+      }
+      if (!(Am[kq][kq] != 0.0) || !d_finite(Am[kq][kq])) sing = true;
+#pragma unroll
+      for (int i = kq + 1; i < NV; ++i) {
+        const double fct = Am[i][kq] / Am[kq][kq];
+#pragma unroll
+        for (int j = kq + 1; j < NV; ++j) Am[i][j] = Am[i][j] - fct * Am[kq][j];
+        bb[i] = bb[i] - fct * bb[kq];
+      }
+    }
+#pragma unroll
+    for (int i = NV - 1; i >= 0; --i) {
+      double sum = bb[i];
+#pragma unroll
+      for (int j = i + 1; j < NV; ++j) sum = sum - Am[i][j] * d[j];
+      d[i] = sum / Am[i][i];
+      if (!d_finite(d[i])) sing = true;
+    }
+    if (sing) {
+      status = ST_NEWTON;
+      break;
+    }
+    conv = true;
+#pragma unroll
+    for (int i = 0; i < MC; ++i) {
+      if (i >= nr || i == skip) continue;
+      const double s0 = fabs(W0[i]) > 1.0 ? fabs(W0[i]) : 1.0;
+      const double s1 = fabs(W1[i]) > 1.0 ? fabs(W1[i]) : 1.0;
+      conv = conv && (fabs(d[2 * i]) <= P.zn_rtol * s0) && (fabs(d[2 * i + 1]) <= P.zn_rtol * s1);
+    }
+    bool okst = true;
+#pragma unroll
+    for (int i = 0; i < MC; ++i) {
+      if (i >= nr || i == skip) continue;
+      W0[i] = W0[i] + d[2 * i];
+      W1[i] = W1[i] + d[2 * i + 1];
+      okst = okst && d_state_ok(W0[i], W1[i]);
+    }
+    if (!okst) {
+      status = ST_NONPHYS;
+      break;
+    }
+    it += 1;
+    final_pass = conv || it == P.zn_maxit;
+    phase = -1;
+  }
+  if (!writer) return;
+
+  // ---------------- write-back (success or failure), as k_zone ----------------
+  double* r1 = A.rho1 + so;
+  double* m1 = A.mom1 + so;
+  int flags = tr ? FL_TINY_RIGHT : 0;
+  int count = 0;
+  int nhome = home;
+  double nhl = hl;
+  if (finished) {
+    const double hln = hl + wstar * dt;
+    if (merge) {
+      flags |= FL_MERGED;
+      int src;
+      if (!tr) {
+        if (hln < 0.0) {
+          nhome = home - 1;
+          nhl = hln + h;
+          src = iR;
+          flags |= FL_CROSS_L;
+        } else {
+          nhl = hln;
+          src = into;
+        }
+      } else {
+        if (hln > h) {
+          nhome = home + 1;
+          nhl = hln - h;
+          src = iL;
+          flags |= FL_CROSS_R;
+        } else {
+          nhl = hln;
+          src = into;
+        }
+      }
+      double cr = 0.0, cm = 0.0;
+#pragma unroll
+      for (int i = 0; i < MC; ++i)
+        if (i == src) {
+          cr = W0[i];
+          cm = W1[i];
+        }
+#pragma unroll
+      for (int i = 0; i < MC; ++i)
+        if (i == skip) {
+          W0[i] = cr;
+          W1[i] = cm;
+        }
+    } else {
+      nhl = hln;
+    }
+    if (redo) flags |= FL_REDO;
+    if (!conv) flags |= FL_LMAX;
+    count = it;
+    A.rec_pw1[2 * k] = pw0;
+    A.rec_pw1[2 * k + 1] = pw1;
+    A.rec_warm1[k] = 1;
+    if (A.st_pseudo) atomicAdd(A.st_pseudo, (unsigned long long)count);
+    if (merge && A.st_merges) atomicAdd(A.st_merges, 1ull);
+    if (!conv && A.st_lmax) atomicAdd(A.st_lmax, 1ull);
+  } else {
+    flags |= FL_FAIL;
+#pragma unroll
+    for (int i = 0; i < MC; ++i) {
+      W0[i] = Ur[i];
+      W1[i] = Um[i];
+    }
+    A.rec_pw1[2 * k] = rpw0;
+    A.rec_pw1[2 * k + 1] = rpw1;
+    A.rec_warm1[k] = warm;
+    atomicOr(A.fail_acc + p, status);
+  }
+  A.rec_home1[k] = nhome;
+  A.rec_hl1[k] = nhl;
+  const int nsL = nhome + kk;
+  unsigned long long vmax = 0;
+#pragma unroll
+  for (int i = 0; i < MC; ++i) {
+    if (i < nr) {
+      r1[zlo + i] = W0[i];
+      m1[zlo + i] = W1[i];
+      const int ph = (zlo + i <= nsL) ? phl : phr;
+      const unsigned long long bt = nt_speed_bits(M, ph, W0[i], W1[i]);
+      vmax = bt > vmax ? bt : vmax;
+    }
+  }
+  atomicMax(A.S_acc + p, vmax);
+  if (row >= 0) {
+    const long long o2 = (long long)row * A.n_iface + k;
+    A.log_count[o2] = count;
+    A.log_flags[o2] = flags;
+    A.log_zlo[o2] = zlo;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_zone_newton(const StepArgs& A, int if_begin, int if_end, hipStream_t s) {
+  const int n = if_end - if_begin;
+  if (n <= 0) return hipSuccess;
+  switch (A.par.zone_half) {
+    case 1: {
+      constexpr int zpw = 64 / (2 * (2 * 3 + 1));
+      k_zone_nt<1><<<(n + zpw - 1) / zpw, 64, 0, s>>>(A, if_begin, if_end);
+      break;
+    }
+    case 2: {
+      constexpr int zpw = 64 / (2 * (2 * 5 + 1));
+      k_zone_nt<2><<<(n + zpw - 1) / zpw, 64, 0, s>>>(A, if_begin, if_end);
+      break;
+    }
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace imexds

@@ -76,6 +76,7 @@ _enable_log = _sig("imexds_enable_log", c_vp, c_i32)
 _get_log = _sig("imexds_get_log", c_vp, P_i32, P_i32, P_i32, P_i32)
 _get_stats = _sig("imexds_get_stats", c_vp, ctypes.POINTER(imexds_stats))
 _set_launch = _sig("imexds_set_launch", c_vp, c_i32, c_i32, c_i32, c_i32, c_i32)
+_set_zone_solver = _sig("imexds_set_zone_solver", c_vp, c_i32, c_i32, c_dbl)
 _autotune = _sig("imexds_autotune", c_vp, c_i32, P_i32, P_i32, P_i32, P_i32, P_dbl)
 _get_sizes = _sig("imexds_get_sizes", c_vp, P_i32, P_i32, P_i64)
 _last_timing = _sig("imexds_last_timing", c_vp, P_dbl, P_dbl)
@@ -91,7 +92,8 @@ _L.imexds_strerror.argtypes = [c_i32]
 EXPORTED = ["imexds_create", "imexds_set_state", "imexds_step", "imexds_run",
             "imexds_step_per_problem", "imexds_get_state", "imexds_get_interfaces",
             "imexds_get_problems", "imexds_enable_log", "imexds_get_log", "imexds_get_stats",
-            "imexds_set_launch", "imexds_autotune", "imexds_get_sizes", "imexds_last_timing",
+            "imexds_set_launch", "imexds_set_zone_solver", "imexds_autotune", "imexds_get_sizes",
+            "imexds_last_timing",
             "imexds_time_bulk", "imexds_set_tau", "imexds_forward_ckpt", "imexds_adjoint",
             "imexds_destroy", "imexds_strerror"]
 
@@ -229,6 +231,14 @@ def imexds_set_launch(ctx, tile_cells, zones_per_group, zone_groups, graph_steps
                        int(graph_steps), int(zone_lanes)), "imexds_set_launch")
 
 
+ZONE_DTS, ZONE_NEWTON = 0, 1
+
+
+def imexds_set_zone_solver(ctx, solver, maxit=30, rtol=1e-10):
+    _check(_set_zone_solver(c_vp(ctx), int(solver), int(maxit), float(rtol)),
+           "imexds_set_zone_solver")
+
+
 def imexds_autotune(ctx, steps_per_trial):
     t, z, g, n, ms = c_i32(), c_i32(), c_i32(), c_i32(), c_dbl()
     _check(_autotune(c_vp(ctx), int(steps_per_trial), ctypes.byref(t), ctypes.byref(z),
@@ -326,6 +336,9 @@ class IMEXDS:
                    zone_lanes=1):
         imexds_set_launch(self.ctx, tile_cells, zones_per_group, zone_groups, graph_steps,
                           zone_lanes)
+
+    def set_zone_solver(self, solver, maxit=30, rtol=1e-10):
+        imexds_set_zone_solver(self.ctx, solver, maxit, rtol)
 
     def autotune(self, steps_per_trial=10):
         return imexds_autotune(self.ctx, steps_per_trial)

@@ -32,6 +32,7 @@ def run_oracle(batch, material, params, n_steps, threads=8):
 
 def run_gpu(batch, material, params, n_steps, launch=None, per_problem=False, log=True,
             lanes=None):
+    """``params.zone_solver`` 1 selects the Newton zone solver."""
     """``launch``: full set_launch tuple; ``lanes``: only the lanes per zone
     (1 or 8) with the other launch settings at their defaults."""
     import torch
@@ -42,6 +43,8 @@ def run_gpu(batch, material, params, n_steps, launch=None, per_problem=False, lo
             s.set_launch(*launch)
         elif lanes is not None:
             s.set_launch(zone_lanes=lanes)
+        if getattr(params, "zone_solver", 0):
+            s.set_zone_solver(params.zone_solver, params.zn_maxit, params.zn_rtol)
         s.set_state()
         if log:
             s.enable_log(n_steps)
