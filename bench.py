@@ -67,6 +67,8 @@ def parse():
     ap.add_argument("--ctube-steps", type=int, default=10,
                     help="creation-tube leg: steps timed (the creation step and the heaviest "
                          "dual time steps; 0: run to t_end, about 100 s)")
+    ap.add_argument("--newton-steps", type=int, default=1000,
+                    help="steps of the main workload with the Newton zone solver (0: skip)")
     ap.add_argument("--per-problem-steps-ctube", type=int, default=3,
                     help="steps of the creation tubes' Newton run launched tube by tube")
     ap.add_argument("--other-configs", type=int, default=1,
@@ -688,6 +690,38 @@ def main():
         pp_value = args.per_problem_steps * b.n_slots / (pp_ms * 1e-3)
         pp = {"value": pp_value, "unit": "cell-updates/s", "ms_per_step": pp_ms / args.per_problem_steps,
               "steps": args.per_problem_steps, "batched_speedup": value / pp_value}
+    # the same steps with the zones solved by Newton on their implicit step
+    # instead of Algorithm 2 (the paper's outlook): same workload, same
+    # launch, from the initial state
+    nz = None
+    if args.newton_steps > 0 and P.zone_half <= 2:
+        # one-lane groups at tile class 1024: the fastest measured shape
+        s.set_launch(1024, tune["zones_per_group"], tune["zone_groups"], 10, 1)
+        s.set_zone_solver(1)
+        s.set_state(rho0, mom0)
+        s.step(args.warmup)
+        torch.cuda.synchronize()
+        s.set_state(rho0, mom0)
+        torch.cuda.synchronize()
+        n0 = s.stats()
+        s.step(args.newton_steps)
+        torch.cuda.synchronize()
+        nz_ms, _ = s.last_timing()
+        n1 = s.stats()
+        ncu = n1["cell_updates"] - n0["cell_updates"]
+        nval = ncu / (nz_ms * 1e-3)
+        _, nz_status, _ = s.problems()
+        nz = {"what": "the zones' implicit steps solved by Newton (forward-difference Jacobian, "
+                      "tolerance 1e-10) instead of dual time stepping; same workload, tile class "
+                      "1024, one-lane groups (1 + 4 zone_half + 2 per zone)",
+              "value": nval, "unit": "cell-updates/s", "steps": args.newton_steps,
+              "ms_per_step": nz_ms / args.newton_steps,
+              "newton_steps_per_zone_step": (n1["pseudo_iters"] - n0["pseudo_iters"])
+              / max(1, NIF * args.newton_steps),
+              "failed_problems": int(np.sum(nz_status != 0)),
+              "step_roofline_frac": nval / (HBM_PEAK_GBS * 1e9 / BYTES_PER_CELL_UPDATE),
+              "over_dual_time": nval / value}
+        s.set_zone_solver(0)
     s.close()
 
     out = {
@@ -721,6 +755,7 @@ def main():
                      "copy_GBs_measured": copy_gbs,
                      "frac_of_copy": (achieved / copy_gbs) if (achieved and copy_gbs) else None},
         "step_roofline_frac": value / (HBM_PEAK_GBS * 1e9 / BYTES_PER_CELL_UPDATE),
+        "newton_zone_solver": nz,
     }
     if args.adjoint_steps > 0:
         adj = adjoint_leg(args, material)

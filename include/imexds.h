@@ -216,7 +216,9 @@ int imexds_set_launch(imexds_ctx *ctx, int32_t tile_cells, int32_t zones_per_gro
  * steps; converged when every step component is below rtol max(|W_j|, 1)
  * (e.g. 1e-10), at most maxit steps (e.g. 30; then IMEXDS_FL_LMAX).  The
  * prediction, merges, redo, Part 2 and re-split are those of Algorithm 2's
- * path; the logs count Newton steps.  Not differentiated:
+ * path; the logs count Newton steps.  Launch: 1 + 4 zone_half + 2 lane
+ * groups per zone, each of one lane (zone_lanes 1 in imexds_set_launch) or
+ * of two (otherwise).  Not differentiated:
  * imexds_forward_ckpt returns IMEXDS_ERR_UNSUPPORTED while it is set.
  * Drops captured graphs; synchronizes. */
 #define IMEXDS_ZONE_DTS 0

@@ -106,8 +106,10 @@ hipError_t launch_zone8(const StepArgs& A, int if_begin, int if_end, int groups,
 hipError_t launch_finalize(const StepArgs& A, int p_begin, int p_end, int init, int bump_row,
                            hipStream_t s);
 // the zones solved by Newton on their implicit step (zone_half 1 or 2):
-// 1 + 4 zone_half + 2 groups of two lanes per zone
-hipError_t launch_zone_newton(const StepArgs& A, int if_begin, int if_end, hipStream_t s);
+// 1 + 4 zone_half + 2 groups per zone of one lane (lanes == 1) or of two
+// lanes (the pair form of the interface solver)
+hipError_t launch_zone_newton(const StepArgs& A, int if_begin, int if_end, int lanes,
+                              hipStream_t s);
 
 // adjoint of one step: zone pass, then bulk pass, then per-problem pass
 // lanes: 1 (one lane per zone) or 8 (eight lanes per zone)

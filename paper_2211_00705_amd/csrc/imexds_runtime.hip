@@ -249,7 +249,8 @@ int build_tiles(imexds_ctx* c, int tile_cells) {
 
 hipError_t launch_zones(imexds_ctx* c, const StepArgs& A, int k0, int k1, int groups,
                         hipStream_t s) {
-  if (c->par.zone_solver == IMEXDS_ZONE_NEWTON) return imexds::launch_zone_newton(A, k0, k1, s);
+  if (c->par.zone_solver == IMEXDS_ZONE_NEWTON)
+    return imexds::launch_zone_newton(A, k0, k1, c->zone_lanes, s);
   if (c->zone_lanes == 8) return imexds::launch_zone8(A, k0, k1, groups, s);
   return imexds::launch_zone(A, k0, k1, groups, s);
 }

@@ -19,8 +19,8 @@
 // zone's rows (their entries in the zone's columns are zero), so the result
 // is the compact system's.
 //
-// A zone has G = 1 + 2 MC groups of two lanes (the pair form of the
-// interface solver: one lane per side of the interface problem).  Every
+// A zone has G = 1 + 2 MC groups of one lane, or of two lanes (the pair form
+// of the interface solver: one lane per side of the interface problem).  Every
 // group evaluates the prediction and each base point with identical inputs
 // (identical results, no exchange); group g >= 1 then evaluates the point
 // moved along unknown g - 1, so the difference columns run side by side;
@@ -39,15 +39,15 @@ __device__ __forceinline__ unsigned long long nt_speed_bits(const Mat& M, int ph
   return (unsigned long long)__double_as_longlong(fabs(m / r) + d_a(M, ph));
 }
 
-template <int ZH>
+template <int ZH, int LG>
 __global__ __launch_bounds__(64) void k_zone_nt(StepArgs A, int if_begin, int if_end) {
-  constexpr int MC = 2 * ZH + 1, NV = 2 * MC, G = NV + 1, TL = 2 * G, ZPW = 64 / TL;
+  constexpr int MC = 2 * ZH + 1, NV = 2 * MC, G = NV + 1, TL = LG * G, ZPW = 64 / TL;
   const Mat& M = A.mat;
   const Par& P = A.par;
   const int lane = (int)threadIdx.x;
   if (lane >= ZPW * TL) return;
   const int tl = lane % TL;
-  const int grp = tl >> 1, half = tl & 1;
+  const int grp = tl / LG, half = LG == 2 ? (tl & 1) : 0;
   const int lane0 = lane - tl;
   const int k = if_begin + (int)blockIdx.x * ZPW + lane / TL;
   if (k >= if_end) return;  // the lanes of a zone are whole
@@ -226,8 +226,8 @@ __global__ __launch_bounds__(64) void k_zone_nt(StepArgs A, int if_begin, int if
     const double g0 = pred ? rpw0 : (fd ? gw0 : pw0);
     const double g1 = pred ? rpw1 : (fd ? gw1 : pw1);
     IfaceOut o;
-    const bool okl = d_iface_solve_t<true>(M, P.newton_maxit, P.newton_rtol, phl, ql0, ql1, phr,
-                                           qr0, qr1, hg, g0, g1, half, lane ^ 1, o);
+    const bool okl = d_iface_solve_t<LG == 2>(M, P.newton_maxit, P.newton_rtol, phl, ql0, ql1,
+                                              phr, qr0, qr1, hg, g0, g1, half, lane ^ 1, o);
     const unsigned long long failm = __ballot(!okl);
     const unsigned long long zm = ((1ull << TL) - 1ull) << lane0;
     if (failm & zm) {
@@ -362,7 +362,7 @@ __global__ __launch_bounds__(64) void k_zone_nt(StepArgs A, int if_begin, int if
       const bool act = (j >> 1) < nr && (j >> 1) != skip;
 #pragma unroll
       for (int i = 0; i < NV; ++i) {
-        const double v = __shfl(Jc[i], lane0 + 2 * (j + 1), 64);
+        const double v = __shfl(Jc[i], lane0 + LG * (j + 1), 64);
         Am[i][j] = act ? v : (i == j ? 1.0 : 0.0);
       }
       bb[j] = act ? -R[j] : 0.0;
@@ -536,24 +536,23 @@ __global__ __launch_bounds__(64) void k_zone_nt(StepArgs A, int if_begin, int if
 
 }  // namespace
 
-hipError_t launch_zone_newton(const StepArgs& A, int if_begin, int if_end, hipStream_t s) {
+template <int ZH, int LG>
+hipError_t launch_nt(const StepArgs& A, int if_begin, int n, hipStream_t s) {
+  constexpr int zpw = 64 / (LG * (2 * (2 * ZH + 1) + 1));
+  k_zone_nt<ZH, LG><<<(n + zpw - 1) / zpw, 64, 0, s>>>(A, if_begin, if_begin + n);
+  return hipGetLastError();
+}
+
+hipError_t launch_zone_newton(const StepArgs& A, int if_begin, int if_end, int lanes,
+                              hipStream_t s) {
   const int n = if_end - if_begin;
   if (n <= 0) return hipSuccess;
+  const bool pair = lanes != 1;
   switch (A.par.zone_half) {
-    case 1: {
-      constexpr int zpw = 64 / (2 * (2 * 3 + 1));
-      k_zone_nt<1><<<(n + zpw - 1) / zpw, 64, 0, s>>>(A, if_begin, if_end);
-      break;
-    }
-    case 2: {
-      constexpr int zpw = 64 / (2 * (2 * 5 + 1));
-      k_zone_nt<2><<<(n + zpw - 1) / zpw, 64, 0, s>>>(A, if_begin, if_end);
-      break;
-    }
-    default:
-      return hipErrorInvalidValue;
+    case 1: return pair ? launch_nt<1, 2>(A, if_begin, n, s) : launch_nt<1, 1>(A, if_begin, n, s);
+    case 2: return pair ? launch_nt<2, 2>(A, if_begin, n, s) : launch_nt<2, 1>(A, if_begin, n, s);
+    default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 }  // namespace imexds

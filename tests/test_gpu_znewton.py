@@ -22,12 +22,14 @@ def test_single_cut_problem_newton(material, seed):
     assert np.array_equal(g["rho"], o["rho"]) and np.array_equal(g["mom"], o["mom"])
 
 
+@pytest.mark.parametrize("lanes", [1, 8])
 @pytest.mark.parametrize("zone_half", [1, 2])
-def test_random_batch_newton(material, zone_half):
-    """Seeded batch with tiny cut pieces (merges, re-splits, crossings)."""
+def test_random_batch_newton(material, zone_half, lanes):
+    """Seeded batch with tiny cut pieces (merges, re-splits, crossings);
+    lane groups of one lane or of two."""
     b = W.random_batch(seed=zone_half, n_problems=64, nmin=256, nmax=2048)
     P = W.random_batch_params().replace(zone_half=zone_half, zone_solver=1)
-    g = run_gpu(b, material, P, 120)
+    g = run_gpu(b, material, P, 120, lanes=lanes)
     o = run_oracle(b, material, P, 120)
     assert np.all(o["status"] == 0)
     assert np.any(o["flags"] & 2)  # merges happen
