@@ -13,6 +13,7 @@ bulk launch), and the CPU oracle timed on a bounded sample of the same
 problems (whose results are also compared with the GPU's).
 """
 import argparse
+import dataclasses
 import hashlib
 import json
 import math
@@ -42,6 +43,8 @@ def parse():
     ap.add_argument("--per-problem-steps", type=int, default=4)
     ap.add_argument("--roofline-steps", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--newton-cpu-seconds", type=float, default=8.0,
+                    help="oracle time for the Newton zone solver's CPU baseline (0: skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (HBM counter calibration)")
     ap.add_argument("--adjoint-steps", type=int, default=500,
@@ -711,6 +714,8 @@ def main():
         ncu = n1["cell_updates"] - n0["cell_updates"]
         nval = ncu / (nz_ms * 1e-3)
         _, nz_status, _ = s.problems()
+        nz_rho, nz_mom = s.state_numpy()
+        nz_home, nz_hl, _ = s.interfaces()
         nz = {"what": "the zones' implicit steps solved by Newton (forward-difference Jacobian, "
                       "tolerance 1e-10) instead of dual time stepping; same workload, tile class "
                       "1024, one-lane groups (1 + 4 zone_half + 2 per zone)",
@@ -722,6 +727,10 @@ def main():
               "step_roofline_frac": nval / (HBM_PEAK_GBS * 1e9 / BYTES_PER_CELL_UPDATE),
               "over_dual_time": nval / value}
         s.set_zone_solver(0)
+        if not args.no_cpu and args.newton_cpu_seconds > 0:
+            nz["cpu_baseline"] = cpu_baseline_leg(b, dataclasses.replace(P, zone_solver=1),
+                                                  material, args.newton_steps, nz_rho, nz_mom,
+                                                  nz_home, nz_hl, args.newton_cpu_seconds)
     s.close()
 
     out = {

@@ -212,8 +212,11 @@ int imexds_set_launch(imexds_ctx *ctx, int32_t tile_cells, int32_t zones_per_gro
  * residual R_i(W) = (h_i(W)/h_i^n) W_i - U_i^n + (dt/h_i^n)(F_{i+1/2}(W) -
  * F_{i-1/2}(W)) with h_i(W) = h_i^n + mov_i w(W) dt and the zone's outer
  * faces from U^n; from W = U^n a forward-difference Jacobian (step
- * 1e-7 max(|W_j|, 1)), Gaussian elimination with partial pivoting, full
- * steps; converged when every step component is below rtol max(|W_j|, 1)
+ * 1e-7 max(|W_j|, 1)) of which the 2x2 blocks beside the diagonal are kept
+ * (R_i depends on W_{i-1}, W_i and W_{i+1} only), the block Thomas
+ * algorithm (no pivoting; a 2x2 pivot block without a finite inverse fails
+ * the problem with IMEXDS_ST_NEWTON), full steps; converged when every step
+ * component is below rtol max(|W_j|, 1)
  * (e.g. 1e-10), at most maxit steps (e.g. 30; then IMEXDS_FL_LMAX).  The
  * prediction, merges, redo, Part 2 and re-split are those of Algorithm 2's
  * path; the logs count Newton steps.  Launch: 1 + 4 zone_half + 2 lane

@@ -1052,12 +1052,68 @@ static int or_zone_dts(const or_material *M, const or_params *P, const or_zone *
  *   R_c(W) = (h_c(W) / h_c^n) W_c - U_c^n + (dt / h_c^n)(F_{c+1/2}(W) - F_{c-1/2}(W)),
  * h_c(W) = h_c^n + mov_c w(W) dt, the zone's outer faces from U^n; from
  * W = U^n a forward-difference Jacobian (step 1e-7 max(|W_j|, 1), the
- * interface solve warm-started from the base point's), Gaussian elimination
- * with partial pivoting (first largest pivot), full steps; converged when
- * every step component is below zn_rtol max(|W_j|, 1); at most zn_maxit
- * steps.  Shrink and state checks, Part 2 and the return codes as in
- * or_zone_dts (the shrink check on every base point). */
-static int or_gauss_pp(int n, double A[][2 * OR_MAXC], double *b, double *x);
+ * interface solve warm-started from the base point's), full steps;
+ * converged when every step component is below zn_rtol max(|W_j|, 1); at
+ * most zn_maxit steps.  R_c depends on W_{c-1}, W_c and W_{c+1} only (each
+ * face flux on the two cells beside it, the moving lengths on the interface
+ * face, whose cells are neighbours), so the Jacobian is block tridiagonal in
+ * 2x2 blocks: the Newton system takes the difference quotients of those
+ * blocks and is solved by or_block_tri.  Shrink and state checks, Part 2 and
+ * the return codes as in or_zone_dts (the shrink check on every base point). */
+
+/* inverse of a 2x2 matrix by its adjugate; 0 if 1/det is not finite */
+static int or_inv2(const double A[2][2], double I[2][2]) {
+  double det = A[0][0] * A[1][1] - A[0][1] * A[1][0];
+  double id = 1.0 / det;
+  if (!isfinite(id)) return 0;
+  I[0][0] = A[1][1] * id;
+  I[0][1] = -A[0][1] * id;
+  I[1][0] = -A[1][0] * id;
+  I[1][1] = A[0][0] * id;
+  return 1;
+}
+
+/* block tridiagonal system (block Thomas algorithm, no pivoting):
+ *   L_c x_{c-1} + D_c x_c + U_c x_{c+1} = r_c,  c = 0 .. m-1
+ * (L_0, U_{m-1} unused).  Forward: D'_0 = D_0, r'_0 = r_0,
+ *   D'_c = D_c - (L_c D'_{c-1}^{-1}) U_{c-1},  r'_c = r_c - (L_c D'_{c-1}^{-1}) r'_{c-1};
+ * back: x_{m-1} = D'_{m-1}^{-1} r'_{m-1},  x_c = D'_c^{-1} (r'_c - U_c x_{c+1}).
+ * 2x2 products summed in index order.  0 if a D'_c has no finite inverse or
+ * a result is not finite. */
+static int or_block_tri(int m, double D[][2][2], double L[][2][2], double U[][2][2],
+                        double r[][2], double x[][2]) {
+  double I[OR_MAXC][2][2], rp[OR_MAXC][2];
+  int c, i, j;
+  for (c = 0; c < m; ++c) {
+    double Dp[2][2];
+    if (c == 0) {
+      for (i = 0; i < 2; ++i) {
+        rp[0][i] = r[0][i];
+        for (j = 0; j < 2; ++j) Dp[i][j] = D[0][i][j];
+      }
+    } else {
+      double Lf[2][2];
+      for (i = 0; i < 2; ++i)
+        for (j = 0; j < 2; ++j) Lf[i][j] = L[c][i][0] * I[c - 1][0][j] + L[c][i][1] * I[c - 1][1][j];
+      for (i = 0; i < 2; ++i) {
+        for (j = 0; j < 2; ++j)
+          Dp[i][j] = D[c][i][j] - (Lf[i][0] * U[c - 1][0][j] + Lf[i][1] * U[c - 1][1][j]);
+        rp[c][i] = r[c][i] - (Lf[i][0] * rp[c - 1][0] + Lf[i][1] * rp[c - 1][1]);
+      }
+    }
+    if (!or_inv2(Dp, I[c])) return 0;
+  }
+  for (c = m - 1; c >= 0; --c) {
+    double y[2];
+    for (i = 0; i < 2; ++i)
+      y[i] = c == m - 1 ? rp[c][i] : rp[c][i] - (U[c][i][0] * x[c + 1][0] + U[c][i][1] * x[c + 1][1]);
+    for (i = 0; i < 2; ++i) {
+      x[c][i] = I[c][i][0] * y[0] + I[c][i][1] * y[1];
+      if (!isfinite(x[c][i])) return 0;
+    }
+  }
+  return 1;
+}
 
 static int or_zone_resid(const or_material *M, const or_params *P, const or_zone *Z, double dt,
                          double W[][2], double *pw, double *R, double *w, int check,
@@ -1083,7 +1139,8 @@ static int or_zone_newton(const or_material *M, const or_params *P, const or_zon
                           int *shrink_cell) {
   int m = Z->m, n = 2 * m, c, q, j, it, conv = 0;
   double W[OR_MAXC][2], R[2 * OR_MAXC], Rp[2 * OR_MAXC], J[2 * OR_MAXC][2 * OR_MAXC];
-  double rhs[2 * OR_MAXC], d[2 * OR_MAXC], w = 0.0;
+  double Db[OR_MAXC][2][2], Lb[OR_MAXC][2][2], Ub[OR_MAXC][2][2], rb[OR_MAXC][2], d[OR_MAXC][2];
+  double w = 0.0;
   *shrink_cell = -1;
   *lmax_hit = 0;
   *count = 0;
@@ -1105,17 +1162,27 @@ static int or_zone_newton(const or_material *M, const or_params *P, const or_zon
       if (st) return st;
       for (q = 0; q < n; ++q) J[q][j] = (Rp[q] - R[q]) / e;
     }
-    for (q = 0; q < n; ++q) rhs[q] = -R[q];
-    if (!or_gauss_pp(n, J, rhs, d)) return OR_ST_NEWTON;
+    for (c = 0; c < m; ++c) {
+      int a, b;
+      for (a = 0; a < 2; ++a) {
+        rb[c][a] = -R[2 * c + a];
+        for (b = 0; b < 2; ++b) {
+          Db[c][a][b] = J[2 * c + a][2 * c + b];
+          Lb[c][a][b] = c > 0 ? J[2 * c + a][2 * (c - 1) + b] : 0.0;
+          Ub[c][a][b] = c + 1 < m ? J[2 * c + a][2 * (c + 1) + b] : 0.0;
+        }
+      }
+    }
+    if (!or_block_tri(m, Db, Lb, Ub, rb, d)) return OR_ST_NEWTON;
     conv = 1;
     for (j = 0; j < n; ++j) {
       double xj = W[j / 2][j % 2];
       double sc = fabs(xj) > 1.0 ? fabs(xj) : 1.0;
-      conv = conv && (fabs(d[j]) <= P->zn_rtol * sc);
+      conv = conv && (fabs(d[j / 2][j % 2]) <= P->zn_rtol * sc);
     }
     for (c = 0; c < m; ++c) {
-      W[c][0] = W[c][0] + d[2 * c];
-      W[c][1] = W[c][1] + d[2 * c + 1];
+      W[c][0] = W[c][0] + d[c][0];
+      W[c][1] = W[c][1] + d[c][1];
       if (!or_state_ok(W[c][0], W[c][1])) return OR_ST_NONPHYS;
     }
     *count = it + 1;

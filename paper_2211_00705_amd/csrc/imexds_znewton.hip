@@ -7,24 +7,26 @@
 // collapses, Part 2, the interface advance and re-split, the records, logs
 // and the CFL contribution.
 //
-// The solve: unknowns the zone's values W (2 per position, positions that
-// are not zone cells padded with identity rows), residual
+// The solve: unknowns the zone cells' values W (2 per cell), residual
 //   R_i(W) = (h_i(W) / h_i^n) W_i - U_i^n + (dt / h_i^n)(F_{i+1/2}(W) - F_{i-1/2}(W)),
 // h_i(W) = h_i^n + mov_i w(W) dt, the zone's outer faces from U^n; a
 // forward-difference Jacobian (step 1e-7 max(|W_j|, 1), the interface solve
-// warm-started from the base point's), Gaussian elimination with partial
-// pivoting, full steps from W = U^n, converged when every step component is
-// below zn_rtol max(|W_j|, 1), at most zn_maxit steps (then flagged like
-// l_max).  The padded identity rows never change the elimination of the
-// zone's rows (their entries in the zone's columns are zero), so the result
-// is the compact system's.
+// warm-started from the base point's) of which the 2x2 blocks next to the
+// diagonal are kept (R_i depends on W_{i-1}, W_i, W_{i+1} only), solved by
+// the block Thomas algorithm; full steps from W = U^n, converged when every
+// step component is below zn_rtol max(|W_j|, 1), at most zn_maxit steps (then
+// flagged like l_max).  The kernel works on 2 Z + 1 cells; cells past the
+// zone (the folded piece's position is left out) are identity rows with
+// zero right-hand sides, which leave the zone cells' results as in the
+// compact system.
 //
 // A zone has G = 1 + 2 MC groups of one lane, or of two lanes (the pair form
 // of the interface solver: one lane per side of the interface problem).  Every
 // group evaluates the prediction and each base point with identical inputs
 // (identical results, no exchange); group g >= 1 then evaluates the point
 // moved along unknown g - 1, so the difference columns run side by side;
-// every lane gathers the columns and runs the same elimination.
+// every lane gathers the three blocks of each cell's row and runs the same
+// block solve.
 #include "imexds_device.hpp"
 #include "imexds_kernels.hpp"
 
@@ -198,8 +200,12 @@ __global__ __launch_bounds__(64) void k_zone_nt(StepArgs A, int if_begin, int if
     const bool fd = phase == 0;
     // the point: W (or U^n for the prediction), moved along colj by groups
     // >= 1 in the column pass when that unknown belongs to the zone
-    const int cpos = colj >> 1, ccmp = colj & 1;
-    const bool cact = colj >= 0 && cpos < nr && cpos != skip;
+    // unknown colj is component ccmp of zone cell ccell (zone cells in slot
+    // order, the folded piece left out), at position cpos
+    const int mm = skip >= 0 ? nr - 1 : nr;
+    const int ccell = colj >> 1, ccmp = colj & 1;
+    const int cpos = ccell + ((skip >= 0 && ccell >= skip) ? 1 : 0);
+    const bool cact = colj >= 0 && ccell < mm;
     const bool moved = fd && cact;
     double X0[MC], X1[MC];
 #pragma unroll
@@ -354,66 +360,98 @@ __global__ __launch_bounds__(64) void k_zone_nt(StepArgs A, int if_begin, int if
     }
 #pragma unroll
     for (int i = 0; i < NV; ++i) Jc[i] = (RX[i] - R[i]) / ecol;
-    // gather the columns (group j + 1 holds column j); columns of positions
-    // outside the zone are unit columns, their right-hand sides zero
-    double Am[NV][NV], bb[NV], d[NV];
+    // rows in zone-cell order (the folded piece's position left out)
+    double Jk[NV], Rk[NV];
 #pragma unroll
-    for (int j = 0; j < NV; ++j) {
-      const bool act = (j >> 1) < nr && (j >> 1) != skip;
+    for (int c = 0; c < MC; ++c) {
+      const bool sh = skip >= 0 && c >= skip;
 #pragma unroll
-      for (int i = 0; i < NV; ++i) {
-        const double v = __shfl(Jc[i], lane0 + LG * (j + 1), 64);
-        Am[i][j] = act ? v : (i == j ? 1.0 : 0.0);
+      for (int a = 0; a < 2; ++a) {
+        const double j1 = c + 1 < MC ? Jc[2 * (c + 1) + a] : 0.0;
+        const double r1 = c + 1 < MC ? R[2 * (c + 1) + a] : 0.0;
+        Jk[2 * c + a] = sh ? j1 : Jc[2 * c + a];
+        Rk[2 * c + a] = sh ? r1 : R[2 * c + a];
       }
-      bb[j] = act ? -R[j] : 0.0;
     }
+    // block tridiagonal solve (block Thomas, the oracle's order of
+    // operations): group j + 1 holds column j; cell c's blocks D_c, L_c and
+    // U_{c-1} are gathered from the groups of cells c, c - 1 and c.  Cells
+    // c >= mm are identity rows with zero right-hand sides: their L, U blocks
+    // are zero, so they leave the zone cells' forward sweep untouched and
+    // give x_c = +-0, which subtracts nothing from the last zone cell.
+    double Ib[MC][2][2], rp[MC][2], Ub[MC][2][2], dx[MC][2];
     bool sing = false;
 #pragma unroll
-    for (int kq = 0; kq < NV; ++kq) {
-      int piv = kq;
-      double pv = fabs(Am[kq][kq]);
+    for (int c = 0; c < MC; ++c) {
+      const bool ac = c < mm;
+      double Dp[2][2], rc[2];
 #pragma unroll
-      for (int i = kq + 1; i < NV; ++i)
-        if (fabs(Am[i][kq]) > pv) {
-          piv = i;
-          pv = fabs(Am[i][kq]);
+      for (int a = 0; a < 2; ++a) {
+        rc[a] = ac ? -Rk[2 * c + a] : 0.0;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const double v = __shfl(Jk[2 * c + a], lane0 + LG * (2 * c + b + 1), 64);
+          Dp[a][b] = ac ? v : (a == b ? 1.0 : 0.0);
         }
-      double rk[NV], bk = bb[kq];
+      }
+      if (c > 0) {
+        double Lc[2][2], Lf[2][2];
 #pragma unroll
-      for (int j = 0; j < NV; ++j) rk[j] = Am[kq][j];
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int i = kq + 1; i < NV; ++i) {
-        const bool sw = piv == i;
+          for (int b = 0; b < 2; ++b) {
+            const double lv = __shfl(Jk[2 * c + a], lane0 + LG * (2 * (c - 1) + b + 1), 64);
+            const double uv = __shfl(Jk[2 * (c - 1) + a], lane0 + LG * (2 * c + b + 1), 64);
+            Lc[a][b] = ac ? lv : 0.0;
+            Ub[c - 1][a][b] = ac ? uv : 0.0;
+          }
 #pragma unroll
-        for (int j = 0; j < NV; ++j) {
-          const double t = Am[i][j];
-          Am[i][j] = sw ? rk[j] : t;
-          Am[kq][j] = sw ? t : Am[kq][j];
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            Lf[a][b] = Lc[a][0] * Ib[c - 1][0][b] + Lc[a][1] * Ib[c - 1][1][b];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            Dp[a][b] = Dp[a][b] - (Lf[a][0] * Ub[c - 1][0][b] + Lf[a][1] * Ub[c - 1][1][b]);
+          rc[a] = rc[a] - (Lf[a][0] * rp[c - 1][0] + Lf[a][1] * rp[c - 1][1]);
         }
-        const double tb = bb[i];
-        bb[i] = sw ? bk : tb;
-        bb[kq] = sw ? tb : bb[kq];
       }
-      if (!(Am[kq][kq] != 0.0) || !d_finite(Am[kq][kq])) sing = true;
-#pragma unroll
-      for (int i = kq + 1; i < NV; ++i) {
-        const double fct = Am[i][kq] / Am[kq][kq];
-#pragma unroll
-        for (int j = kq + 1; j < NV; ++j) Am[i][j] = Am[i][j] - fct * Am[kq][j];
-        bb[i] = bb[i] - fct * bb[kq];
-      }
+      rp[c][0] = rc[0];
+      rp[c][1] = rc[1];
+      const double det = Dp[0][0] * Dp[1][1] - Dp[0][1] * Dp[1][0];
+      const double id = 1.0 / det;
+      if (ac && !d_finite(id)) sing = true;
+      Ib[c][0][0] = Dp[1][1] * id;
+      Ib[c][0][1] = -Dp[0][1] * id;
+      Ib[c][1][0] = -Dp[1][0] * id;
+      Ib[c][1][1] = Dp[0][0] * id;
     }
 #pragma unroll
-    for (int i = NV - 1; i >= 0; --i) {
-      double sum = bb[i];
+    for (int c = MC - 1; c >= 0; --c) {
+      double y[2];
 #pragma unroll
-      for (int j = i + 1; j < NV; ++j) sum = sum - Am[i][j] * d[j];
-      d[i] = sum / Am[i][i];
-      if (!d_finite(d[i])) sing = true;
+      for (int a = 0; a < 2; ++a)
+        y[a] = c == MC - 1 ? rp[c][a]
+                           : rp[c][a] - (Ub[c][a][0] * dx[c + 1][0] + Ub[c][a][1] * dx[c + 1][1]);
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        dx[c][a] = Ib[c][a][0] * y[0] + Ib[c][a][1] * y[1];
+        if (c < mm && !d_finite(dx[c][a])) sing = true;
+      }
     }
     if (sing) {
       status = ST_NEWTON;
       break;
+    }
+    // the step of each zone position's values
+    double e0[MC], e1[MC];
+#pragma unroll
+    for (int i = 0; i < MC; ++i) {
+      const bool sh = skip >= 0 && i > skip;
+      e0[i] = (sh && i > 0) ? dx[i > 0 ? i - 1 : 0][0] : dx[i][0];
+      e1[i] = (sh && i > 0) ? dx[i > 0 ? i - 1 : 0][1] : dx[i][1];
     }
     conv = true;
 #pragma unroll
@@ -421,14 +459,14 @@ __global__ __launch_bounds__(64) void k_zone_nt(StepArgs A, int if_begin, int if
       if (i >= nr || i == skip) continue;
       const double s0 = fabs(W0[i]) > 1.0 ? fabs(W0[i]) : 1.0;
       const double s1 = fabs(W1[i]) > 1.0 ? fabs(W1[i]) : 1.0;
-      conv = conv && (fabs(d[2 * i]) <= P.zn_rtol * s0) && (fabs(d[2 * i + 1]) <= P.zn_rtol * s1);
+      conv = conv && (fabs(e0[i]) <= P.zn_rtol * s0) && (fabs(e1[i]) <= P.zn_rtol * s1);
     }
     bool okst = true;
 #pragma unroll
     for (int i = 0; i < MC; ++i) {
       if (i >= nr || i == skip) continue;
-      W0[i] = W0[i] + d[2 * i];
-      W1[i] = W1[i] + d[2 * i + 1];
+      W0[i] = W0[i] + e0[i];
+      W1[i] = W1[i] + e1[i];
       okst = okst && d_state_ok(W0[i], W1[i]);
     }
     if (!okst) {
