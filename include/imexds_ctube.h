@@ -134,9 +134,11 @@ int imexds_ct_set_launch(imexds_ct_ctx *ctx, int32_t zone_lanes, int32_t zone_pr
  * values, residual
  *   R_c(W) = (h_c(W) / h_c^n) W_c - U_c^n + (dt / h_c^n)(F_{c+1/2}(W) - F_{c-1/2}(W))
  * (lengths from the boundary speeds at W, outer zone faces from U^n),
- * Jacobian by forward differences with step 1e-7 max(|W_j|, 1), Gaussian
- * elimination with partial pivoting, full steps from W = U^n; converged when
- * every step component is below rtol max(|W_j|, 1) (e.g. 1e-10), at most
+ * Jacobian by forward differences with step 1e-7 max(|W_j|, 1), the block
+ * Thomas algorithm on its 2x2 blocks beside the diagonal (the created cell
+ * couples its two neighbours only; no pivoting, a pivot block without a
+ * finite inverse fails the tube with IMEXDS_CT_ST_NEWTON), full steps from
+ * W = U^n; converged when every step component is below rtol max(|W_j|, 1) (e.g. 1e-10), at most
  * maxit steps (e.g. 30; then IMEXDS_CT_FL_LMAX); Part 2 as in Algorithm 2.
  * The log's count is the number of Newton steps. */
 #define IMEXDS_CT_SOLVER_DTS 0

@@ -1996,11 +1996,14 @@ static int or_ct_dts(const or_material *M, const or_params *P, int ph, const or_
  * with the lengths h_c(W) from the boundary speeds at W and the outer zone
  * faces from U^n (the fixed point of Algorithm 2).  From W = U^n: the
  * Jacobian by forward differences (step 1e-7 max(|W_j|, 1), boundary solves
- * warm-started from the current iterate's), Gaussian elimination with
- * partial pivoting (first largest pivot), the full step; converged when
+ * warm-started from the current iterate's), the full step; converged when
  * every step component is below rtol max(|W_j|, 1) (the step is taken); at
  * most maxit steps (then flagged like l_max).  Part 2 as in Algorithm 2.
- * The shrink and state checks of Algorithm 2 apply to every iterate. */
+ * The shrink and state checks of Algorithm 2 apply to every iterate.  R_c
+ * depends on W_{c-1}, W_c, W_{c+1} only (the created cell's length on both
+ * boundary speeds, each neighbour's on its own boundary), so the 2x2 blocks
+ * beside the diagonal of the difference Jacobian are kept and the system is
+ * solved by or_block_tri, as for the batch path's zones. */
 #define OR_CT_NMAX (2 * OR_MAXC)
 
 static int or_ct_resid(const or_material *M, const or_params *P, int ph, const or_ctzone *Z,
@@ -2019,46 +2022,13 @@ static int or_ct_resid(const or_material *M, const or_params *P, int ph, const o
   return 0;
 }
 
-/* A x = b by Gaussian elimination with partial pivoting (the first row with
- * the largest |pivot|); A and b are overwritten; 0 if singular */
-static int or_gauss_pp(int n, double A[][2 * OR_MAXC], double *b, double *x) {
-  int k, i, j;
-  for (k = 0; k < n; ++k) {
-    int piv = k;
-    for (i = k + 1; i < n; ++i)
-      if (fabs(A[i][k]) > fabs(A[piv][k])) piv = i;
-    if (piv != k) {
-      for (j = 0; j < n; ++j) {
-        double t = A[k][j];
-        A[k][j] = A[piv][j];
-        A[piv][j] = t;
-      }
-      double t = b[k];
-      b[k] = b[piv];
-      b[piv] = t;
-    }
-    if (!(A[k][k] != 0.0) || !isfinite(A[k][k])) return 0;
-    for (i = k + 1; i < n; ++i) {
-      double f = A[i][k] / A[k][k];
-      for (j = k + 1; j < n; ++j) A[i][j] = A[i][j] - f * A[k][j];
-      b[i] = b[i] - f * b[k];
-    }
-  }
-  for (i = n - 1; i >= 0; --i) {
-    double sum = b[i];
-    for (j = i + 1; j < n; ++j) sum = sum - A[i][j] * x[j];
-    x[i] = sum / A[i][i];
-    if (!isfinite(x[i])) return 0;
-  }
-  return 1;
-}
-
 static int or_ct_newton(const or_material *M, const or_params *P, int ph, const or_ctzone *Z,
                         double dt, double *pwl, double *pwr, int maxit, double rtol,
                         double U1[][2], double *wls, double *wrs, int *count, int *lmax_hit) {
   int m = Z->m, n = 2 * m, c, q, j, it, conv = 0;
   double W[OR_MAXC][2], R[OR_CT_NMAX], Rp[OR_CT_NMAX], J[OR_CT_NMAX][OR_CT_NMAX];
-  double rhs[OR_CT_NMAX], d[OR_CT_NMAX], wl = 0.0, wr = 0.0;
+  double Db[OR_MAXC][2][2], Lb[OR_MAXC][2][2], Ub[OR_MAXC][2][2], rb[OR_MAXC][2], d[OR_MAXC][2];
+  double wl = 0.0, wr = 0.0;
   *lmax_hit = 0;
   *count = 0;
   for (c = 0; c < m; ++c) {
@@ -2079,17 +2049,27 @@ static int or_ct_newton(const or_material *M, const or_params *P, int ph, const 
       if (st) return st;
       for (q = 0; q < n; ++q) J[q][j] = (Rp[q] - R[q]) / e;
     }
-    for (q = 0; q < n; ++q) rhs[q] = -R[q];
-    if (!or_gauss_pp(n, J, rhs, d)) return OR_CT_ST_NEWTON;
+    for (c = 0; c < m; ++c) {
+      int a, b;
+      for (a = 0; a < 2; ++a) {
+        rb[c][a] = -R[2 * c + a];
+        for (b = 0; b < 2; ++b) {
+          Db[c][a][b] = J[2 * c + a][2 * c + b];
+          Lb[c][a][b] = c > 0 ? J[2 * c + a][2 * (c - 1) + b] : 0.0;
+          Ub[c][a][b] = c + 1 < m ? J[2 * c + a][2 * (c + 1) + b] : 0.0;
+        }
+      }
+    }
+    if (!or_block_tri(m, Db, Lb, Ub, rb, d)) return OR_CT_ST_NEWTON;
     conv = 1;
     for (j = 0; j < n; ++j) {
       double xj = W[j / 2][j % 2];
       double sc = fabs(xj) > 1.0 ? fabs(xj) : 1.0;
-      conv = conv && (fabs(d[j]) <= rtol * sc);
+      conv = conv && (fabs(d[j / 2][j % 2]) <= rtol * sc);
     }
     for (c = 0; c < m; ++c) {
-      W[c][0] = W[c][0] + d[2 * c];
-      W[c][1] = W[c][1] + d[2 * c + 1];
+      W[c][0] = W[c][0] + d[c][0];
+      W[c][1] = W[c][1] + d[c][1];
       if (!or_state_ok(W[c][0], W[c][1])) return OR_CT_ST_NONPHYS;
     }
     *count = it + 1;

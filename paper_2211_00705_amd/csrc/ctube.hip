@@ -551,15 +551,17 @@ __global__ __launch_bounds__(64) void k_ct_zone(Args A) {
 // cells; residual
 //   R_c(W) = (h_c(W) / h_c^n) W_c - U_c^n + (dt / h_c^n)(F_{c+1/2}(W) - F_{c-1/2}(W)),
 // Jacobian by forward differences (step 1e-7 max(|W_j|, 1), boundary solves
-// warm-started from the base point's), Gaussian elimination with partial
-// pivoting, full steps from W = U^n, converged when every step component is
-// below zn_rtol max(|W_j|, 1); at most zn_maxit steps.
+// warm-started from the base point's) of which the 2x2 blocks beside the
+// diagonal are kept (the created cell's row couples its two neighbours, each
+// neighbour's row the created cell), the block Thomas algorithm, full steps
+// from W = U^n, converged when every step component is below
+// zn_rtol max(|W_j|, 1); at most zn_maxit steps.
 // A tube has 7 groups of L lanes (L = 1, 2, 4 as in k_ct_zone).  Every group
 // evaluates the prediction and each base point (identical inputs and warm
 // starts, so identical results without any exchange); then group g >= 1
 // evaluates the point moved along unknown g - 1 -- the six difference
-// columns side by side -- and every lane gathers the columns and runs the
-// same 6x6 elimination.  Per Newton step two evaluations in sequence
+// columns side by side -- and every lane gathers the blocks and runs the
+// same block solve.  Per Newton step two evaluations in sequence
 // instead of seven.
 // ---------------------------------------------------------------------------
 template <int L>
@@ -791,59 +793,65 @@ __global__ __launch_bounds__(64) void k_ct_newton(Args A) {
     }
 #pragma unroll
     for (int i = 0; i < NV; ++i) Jc[i] = (RX[i] - R[i]) / ecol;
-    // every lane gathers the six columns (group j + 1 holds column j)
-    double Am[NV][NV], b[NV], d[NV];
-#pragma unroll
-    for (int j = 0; j < NV; ++j)
-#pragma unroll
-      for (int i = 0; i < NV; ++i) Am[i][j] = __shfl(Jc[i], lane0 + (j + 1) * L, 64);
-#pragma unroll
-    for (int i = 0; i < NV; ++i) b[i] = -R[i];
-    // J d = -R by Gaussian elimination with partial pivoting
+    // block tridiagonal solve (block Thomas, the oracle's order of
+    // operations): group j + 1 holds column j; cell k's blocks D_k, L_k and
+    // U_{k-1} come from the groups of cells k, k - 1 and k
+    double Ib[MC][2][2], rp[MC][2], Ub[MC][2][2], dx[MC][2], d[NV];
     bool sing = false;
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      int piv = k;
-      double pv = fabs(Am[k][k]);
+    for (int k = 0; k < MC; ++k) {
+      double Dp[2][2], rc[2];
 #pragma unroll
-      for (int i = k + 1; i < NV; ++i)
-        if (fabs(Am[i][k]) > pv) {
-          piv = i;
-          pv = fabs(Am[i][k]);
-        }
-      // swap rows k and piv by selects (register arrays need fixed indices)
-      double rk[NV], bk = b[k];
+      for (int a = 0; a < 2; ++a) {
+        rc[a] = -R[2 * k + a];
 #pragma unroll
-      for (int j = 0; j < NV; ++j) rk[j] = Am[k][j];
-#pragma unroll
-      for (int i = k + 1; i < NV; ++i) {
-        const bool sw = piv == i;
-#pragma unroll
-        for (int j = 0; j < NV; ++j) {
-          const double t = Am[i][j];
-          Am[i][j] = sw ? rk[j] : t;
-          Am[k][j] = sw ? t : Am[k][j];
-        }
-        const double tb = b[i];
-        b[i] = sw ? bk : tb;
-        b[k] = sw ? tb : b[k];
+        for (int c = 0; c < 2; ++c) Dp[a][c] = __shfl(Jc[2 * k + a], lane0 + (2 * k + c + 1) * L, 64);
       }
-      if (!(Am[k][k] != 0.0) || !d_finite(Am[k][k])) sing = true;
+      if (k > 0) {
+        double Lc[2][2], Lf[2][2];
 #pragma unroll
-      for (int i = k + 1; i < NV; ++i) {
-        const double fct = Am[i][k] / Am[k][k];
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int j = k + 1; j < NV; ++j) Am[i][j] = Am[i][j] - fct * Am[k][j];
-        b[i] = b[i] - fct * b[k];
+          for (int c = 0; c < 2; ++c) {
+            Lc[a][c] = __shfl(Jc[2 * k + a], lane0 + (2 * (k - 1) + c + 1) * L, 64);
+            Ub[k - 1][a][c] = __shfl(Jc[2 * (k - 1) + a], lane0 + (2 * k + c + 1) * L, 64);
+          }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int c = 0; c < 2; ++c)
+            Lf[a][c] = Lc[a][0] * Ib[k - 1][0][c] + Lc[a][1] * Ib[k - 1][1][c];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+#pragma unroll
+          for (int c = 0; c < 2; ++c)
+            Dp[a][c] = Dp[a][c] - (Lf[a][0] * Ub[k - 1][0][c] + Lf[a][1] * Ub[k - 1][1][c]);
+          rc[a] = rc[a] - (Lf[a][0] * rp[k - 1][0] + Lf[a][1] * rp[k - 1][1]);
+        }
       }
+      rp[k][0] = rc[0];
+      rp[k][1] = rc[1];
+      const double det = Dp[0][0] * Dp[1][1] - Dp[0][1] * Dp[1][0];
+      const double id = 1.0 / det;
+      if (!d_finite(id)) sing = true;
+      Ib[k][0][0] = Dp[1][1] * id;
+      Ib[k][0][1] = -Dp[0][1] * id;
+      Ib[k][1][0] = -Dp[1][0] * id;
+      Ib[k][1][1] = Dp[0][0] * id;
     }
 #pragma unroll
-    for (int i = NV - 1; i >= 0; --i) {
-      double sum = b[i];
+    for (int k = MC - 1; k >= 0; --k) {
+      double y[2];
 #pragma unroll
-      for (int j = i + 1; j < NV; ++j) sum = sum - Am[i][j] * d[j];
-      d[i] = sum / Am[i][i];
-      if (!d_finite(d[i])) sing = true;
+      for (int a = 0; a < 2; ++a)
+        y[a] = k == MC - 1 ? rp[k][a]
+                           : rp[k][a] - (Ub[k][a][0] * dx[k + 1][0] + Ub[k][a][1] * dx[k + 1][1]);
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        dx[k][a] = Ib[k][a][0] * y[0] + Ib[k][a][1] * y[1];
+        if (!d_finite(dx[k][a])) sing = true;
+        d[2 * k + a] = dx[k][a];
+      }
     }
     if (sing) {
       code = ST_NEWTON;

