@@ -97,6 +97,8 @@ def lib():
         L.oracle_iface_G.argtypes = [ctypes.POINTER(_Mat), ctypes.c_int, ctypes.c_double,
                                      ctypes.c_double, ctypes.c_int, ctypes.c_double,
                                      ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
+        L.oracle_block_tri.restype = ctypes.c_int
+        L.oracle_block_tri.argtypes = [ctypes.c_int, dp, dp, dp, dp, dp]
         L.oracle_hll.restype = None
         L.oracle_hll.argtypes = [ctypes.POINTER(_Mat), ctypes.c_int, ctypes.c_double,
                                  ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
@@ -352,6 +354,19 @@ def creation_batch(material, phase, rl, ml, rr, mr, p_min, p_tilde, maxit=50, rt
                                 _ptr(status, ctypes.c_int), _ptr(out, ctypes.c_double),
                                 int(threads))
     return status, out
+
+
+def block_tri(D, L, U, r):
+    """Block tridiagonal solve of the Newton zone solvers (block Thomas):
+    D, L, U of shape [m, 2, 2] (L[0], U[m-1] unused), r of shape [m, 2];
+    returns x of shape [m, 2], or None if a pivot block has no finite
+    inverse or a result is not finite."""
+    m = len(D)
+    args = [np.ascontiguousarray(a, dtype=np.float64).ravel() for a in (D, L, U, r)]
+    x = np.zeros(2 * m)
+    ok = lib().oracle_block_tri(int(m), *[_ptr(a, ctypes.c_double) for a in args],
+                                _ptr(x, ctypes.c_double))
+    return x.reshape(m, 2) if ok else None
 
 
 def hll(material, phase, rl, ml, rr, mr):

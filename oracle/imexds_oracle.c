@@ -1115,6 +1115,28 @@ static int or_block_tri(int m, double D[][2][2], double L[][2][2], double U[][2]
   return 1;
 }
 
+/* exported for the tests: blocks as flat arrays of m * 4 (row-major 2x2)
+ * and m * 2 doubles */
+int oracle_block_tri(int m, const double *D, const double *L, const double *U, const double *r,
+                     double *x) {
+  double Db[OR_MAXC][2][2], Lb[OR_MAXC][2][2], Ub[OR_MAXC][2][2], rb[OR_MAXC][2], xb[OR_MAXC][2];
+  int c, i, j;
+  if (m < 1 || m > OR_MAXC) return 0;
+  for (c = 0; c < m; ++c)
+    for (i = 0; i < 2; ++i) {
+      rb[c][i] = r[2 * c + i];
+      for (j = 0; j < 2; ++j) {
+        Db[c][i][j] = D[4 * c + 2 * i + j];
+        Lb[c][i][j] = L[4 * c + 2 * i + j];
+        Ub[c][i][j] = U[4 * c + 2 * i + j];
+      }
+    }
+  if (!or_block_tri(m, Db, Lb, Ub, rb, xb)) return 0;
+  for (c = 0; c < m; ++c)
+    for (i = 0; i < 2; ++i) x[2 * c + i] = xb[c][i];
+  return 1;
+}
+
 static int or_zone_resid(const or_material *M, const or_params *P, const or_zone *Z, double dt,
                          double W[][2], double *pw, double *R, double *w, int check,
                          int *shrink_cell) {

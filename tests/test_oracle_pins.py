@@ -533,3 +533,42 @@ def test_newton_zone_solver_on_a_batch(material):
     assert np.array_equal(s0.home, s1.home)
     assert c1.max() <= 8 and c1.mean() < 4 < c0.mean()
     assert np.max(np.abs(s1.rho - s0.rho) / np.abs(s0.rho)) < 1e-6
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 5, 7])
+def test_block_tridiagonal_solver_against_dense_solve(m):
+    """The Newton zone solvers' block Thomas algorithm equals a dense LU
+    solve (numpy) of the assembled block tridiagonal matrix on
+    well-conditioned random systems, including a zone-like one whose middle
+    row is scaled by 1/alpha (a tiny cell), and refuses a singular pivot
+    block."""
+    rng = np.random.default_rng(100 + m)
+    for scale_mid in (1.0, 1e6):
+        D = rng.normal(size=(m, 2, 2)) + 4.0 * np.eye(2)
+        L = rng.normal(size=(m, 2, 2))
+        U = rng.normal(size=(m, 2, 2))
+        r = rng.normal(size=(m, 2))
+        c = m // 2
+        D[c] *= scale_mid
+        L[c] *= scale_mid
+        U[c] *= scale_mid
+        r[c] *= scale_mid
+        A = np.zeros((2 * m, 2 * m))
+        for k in range(m):
+            A[2 * k:2 * k + 2, 2 * k:2 * k + 2] = D[k]
+            if k > 0:
+                A[2 * k:2 * k + 2, 2 * k - 2:2 * k] = L[k]
+            if k + 1 < m:
+                A[2 * k:2 * k + 2, 2 * k + 2:2 * k + 4] = U[k]
+        x = oracle.block_tri(D, L, U, r)
+        xd = np.linalg.solve(A, r.ravel()).reshape(m, 2)
+        assert x is not None
+        np.testing.assert_allclose(x, xd, rtol=1e-12, atol=1e-12 * np.abs(xd).max())
+        # the unused corner blocks play no part
+        L2, U2 = L.copy(), U.copy()
+        L2[0] = 7.0
+        U2[m - 1] = -3.0
+        assert np.array_equal(oracle.block_tri(D, L2, U2, r), x)
+    Ds = np.tile(np.eye(2), (m, 1, 1))
+    Ds[m - 1] = [[1.0, 2.0], [2.0, 4.0]]  # singular last pivot block
+    assert oracle.block_tri(Ds, np.zeros((m, 2, 2)), np.zeros((m, 2, 2)), np.ones((m, 2))) is None
