@@ -673,6 +673,10 @@ def main():
     zone_slots = int(round(NIF * (2 * P.zone_half + 1)))
     bulk_bytes = BYTES_PER_CELL_UPDATE * (b.n_slots - zone_slots)
     bulk_ms = achieved = None
+    # a plain copy moving the same bytes per launch (read + write), the
+    # practical ceiling at this transfer size
+    copy_same_gbs = (measure_copy_bandwidth(mib=max(1, int(round(bulk_bytes / 2 / (1 << 20)))))
+                     if args.copy_bw else None)
     roof_tile = 1024  # the bulk sweep's own best tile class (the step's may differ)
     if args.roofline_steps > 0:
         s.set_launch(roof_tile, tune["zones_per_group"], tune["zone_groups"], 10,
@@ -697,7 +701,7 @@ def main():
     # instead of Algorithm 2 (the paper's outlook): same workload, same
     # launch, from the initial state
     nz = None
-    if args.newton_steps > 0 and P.zone_half <= 2:
+    if args.newton_steps > 0:
         # one-lane groups at tile class 1024: the fastest measured shape
         s.set_launch(1024, tune["zones_per_group"], tune["zone_groups"], 10, 1)
         s.set_zone_solver(1)
@@ -762,7 +766,10 @@ def main():
                      "bulk_launches_timed": args.roofline_steps,
                      "algorithmic_bytes_per_launch": bulk_bytes,
                      "copy_GBs_measured": copy_gbs,
-                     "frac_of_copy": (achieved / copy_gbs) if (achieved and copy_gbs) else None},
+                     "frac_of_copy": (achieved / copy_gbs) if (achieved and copy_gbs) else None,
+                     "copy_same_bytes_GBs": copy_same_gbs,
+                     "frac_of_same_bytes_copy": (achieved / copy_same_gbs)
+                     if (achieved and copy_same_gbs) else None},
         "step_roofline_frac": value / (HBM_PEAK_GBS * 1e9 / BYTES_PER_CELL_UPDATE),
         "newton_zone_solver": nz,
     }

@@ -207,8 +207,8 @@ int imexds_set_launch(imexds_ctx *ctx, int32_t tile_cells, int32_t zones_per_gro
 /* The solver of the zones' implicit step.  IMEXDS_ZONE_DTS (default):
  * Algorithm 2, dual time stepping with the stop rule of the parameters.
  * IMEXDS_ZONE_NEWTON: Newton on the same implicit step (the Newton-like
- * solver of the paper's outlook), zone_half 1 or 2 only
- * (IMEXDS_ERR_UNSUPPORTED otherwise): unknowns the zone's values W,
+ * solver of the paper's outlook), any zone_half (1..3): unknowns the
+ * zone's values W,
  * residual R_i(W) = (h_i(W)/h_i^n) W_i - U_i^n + (dt/h_i^n)(F_{i+1/2}(W) -
  * F_{i-1/2}(W)) with h_i(W) = h_i^n + mov_i w(W) dt and the zone's outer
  * faces from U^n; from W = U^n a forward-difference Jacobian (step

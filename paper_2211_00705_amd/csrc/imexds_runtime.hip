@@ -1056,10 +1056,6 @@ int imexds_set_zone_solver(imexds_ctx* c, int32_t solver, int32_t maxit, double 
   if (!c) return IMEXDS_ERR_INVALID_ARG;
   if (solver != IMEXDS_ZONE_DTS && solver != IMEXDS_ZONE_NEWTON) return IMEXDS_ERR_INVALID_ARG;
   if (maxit < 1 || !(rtol > 0.0) || !std::isfinite(rtol)) return IMEXDS_ERR_INVALID_ARG;
-  if (solver == IMEXDS_ZONE_NEWTON && c->par.zone_half > 2) {
-    snprintf(g_err, sizeof(g_err), "the Newton zone solver covers zone_half 1 and 2");
-    return IMEXDS_ERR_UNSUPPORTED;
-  }
   CK(hipSetDevice(c->device));
   CK(hipStreamSynchronize(c->ms));
   CK(hipStreamSynchronize(c->zs));

@@ -589,6 +589,7 @@ hipError_t launch_zone_newton(const StepArgs& A, int if_begin, int if_end, int l
   switch (A.par.zone_half) {
     case 1: return pair ? launch_nt<1, 2>(A, if_begin, n, s) : launch_nt<1, 1>(A, if_begin, n, s);
     case 2: return pair ? launch_nt<2, 2>(A, if_begin, n, s) : launch_nt<2, 1>(A, if_begin, n, s);
+    case 3: return pair ? launch_nt<3, 2>(A, if_begin, n, s) : launch_nt<3, 1>(A, if_begin, n, s);
     default: return hipErrorInvalidValue;
   }
 }

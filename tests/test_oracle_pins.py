@@ -492,17 +492,17 @@ def test_reproducible_logarithm_is_accurate():
     assert math.isnan(L.oracle_log(-1.0)) and L.oracle_log(0.0) == -math.inf
 
 
-@pytest.mark.parametrize("seed", [0, 1, 2])
-def test_newton_zone_solver_lands_on_the_direct_newton_solution(material, seed):
+@pytest.mark.parametrize("seed,zone_half", [(0, 2), (1, 2), (2, 2), (0, 3), (1, 1)])
+def test_newton_zone_solver_lands_on_the_direct_newton_solution(material, seed, zone_half):
     """The Newton zone solver (forward differences, the alternative to
     Algorithm 2 that the paper's outlook names) ends its step on the solution
     of the zone's implicit Euler system that the independent central-
     difference Newton solve finds (Part 2 then reproduces that iterate)."""
     import copy
     b = W.single_cut_problem(seed, alpha=3e-3)
+    P = W.single_cut_params().replace(zone_half=zone_half)
     st = oracle.State(b)
-    oracle.run(st, material, W.single_cut_params(), 3)
-    P = W.single_cut_params()
+    oracle.run(st, material, P, 3)
     rc, Wd, Wn, dt = oracle.zone_fixed_point(st, material,
                                              P.replace(tol_mode=1, tol_rel=1e-15, lmax=200000))
     assert rc == 0
@@ -515,12 +515,13 @@ def test_newton_zone_solver_lands_on_the_direct_newton_solution(material, seed):
     assert np.max(np.abs(got - Wn) / scale) < 1e-8
 
 
-def test_newton_zone_solver_on_a_batch(material):
+@pytest.mark.parametrize("zone_half", [2, 3])
+def test_newton_zone_solver_on_a_batch(material, zone_half):
     """On a seeded batch with merges the Newton zone solver takes the same
     mesh decisions as Algorithm 2, a few steps per zone and time step, and
     ends within Algorithm 2's own tolerance of its states."""
     b = W.random_batch(seed=7, n_problems=32, nmin=256, nmax=1024)
-    P = W.random_batch_params()
+    P = W.random_batch_params().replace(zone_half=zone_half)
     out = []
     for solver in (0, 1):
         st = oracle.State(b)
