@@ -539,8 +539,9 @@ def ctube_leg(args, cpu):
     finally:
         s.close()
     rec["newton_zone_solver"] = {
-        "what": "the zone's implicit step by Newton (forward-difference Jacobian, tolerance "
-                "1e-10) instead of dual time stepping, the whole run to t_end = 5e-4 s",
+        "what": "the zone's implicit step by Newton (forward-difference Jacobian, block "
+                "tridiagonal solve, tolerance 1e-10) instead of dual time stepping, the whole "
+                "run to t_end = 5e-4 s",
         "unit": "cell-updates/s", "value": float(np.sum(slots * nsteps)) / nwall,
         "wall_s": nwall, "launch_steps": nn, "failed_problems": int(np.sum(nst != 0)),
         "launch": {"zone_lanes": nlanes, "zone_problems_per_wave": nppw},
@@ -721,7 +722,7 @@ def main():
         nz_rho, nz_mom = s.state_numpy()
         nz_home, nz_hl, _ = s.interfaces()
         nz = {"what": "the zones' implicit steps solved by Newton (forward-difference Jacobian, "
-                      "tolerance 1e-10) instead of dual time stepping; same workload, tile class "
+                      "block tridiagonal solve, tolerance 1e-10) instead of dual time stepping; same workload, tile class "
                       "1024, one-lane groups (1 + 4 zone_half + 2 per zone)",
               "value": nval, "unit": "cell-updates/s", "steps": args.newton_steps,
               "ms_per_step": nz_ms / args.newton_steps,
