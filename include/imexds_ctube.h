@@ -129,9 +129,8 @@ int imexds_ct_set_launch(imexds_ct_ctx *ctx, int32_t zone_lanes, int32_t zone_pr
 
 /* The solver of the zone's implicit step.  IMEXDS_CT_SOLVER_DTS (default):
  * Algorithm 2 as described above.  IMEXDS_CT_SOLVER_NEWTON: Newton on the
- * same implicit step (the Newton-like solver of the paper's outlook), zone
- * +- 1 only (IMEXDS_ERR_UNSUPPORTED otherwise): unknowns the zone's 6
- * values, residual
+ * same implicit step (the Newton-like solver of the paper's outlook), any
+ * zone_half: unknowns the zone's 2 (2 zone_half + 1) values, residual
  *   R_c(W) = (h_c(W) / h_c^n) W_c - U_c^n + (dt / h_c^n)(F_{c+1/2}(W) - F_{c-1/2}(W))
  * (lengths from the boundary speeds at W, outer zone faces from U^n),
  * Jacobian by forward differences with step 1e-7 max(|W_j|, 1), the block

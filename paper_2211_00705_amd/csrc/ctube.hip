@@ -545,36 +545,37 @@ __global__ __launch_bounds__(64) void k_ct_zone(Args A) {
 }
 
 // ---------------------------------------------------------------------------
-// Newton on the implicit step of the zone (created cell +- 1), the
+// Newton on the implicit step of the zone (created cell +- Z), the
 // alternative to Algorithm 2 (the paper's outlook: a Newton-like solver for
-// the small implicit systems).  Unknowns: the 6 values of the zone's 3
-// cells; residual
+// the small implicit systems).  Unknowns: the 2 (2 Z + 1) values of the
+// zone's cells; residual
 //   R_c(W) = (h_c(W) / h_c^n) W_c - U_c^n + (dt / h_c^n)(F_{c+1/2}(W) - F_{c-1/2}(W)),
-// Jacobian by forward differences (step 1e-7 max(|W_j|, 1), boundary solves
-// warm-started from the base point's) of which the 2x2 blocks beside the
-// diagonal are kept (the created cell's row couples its two neighbours, each
-// neighbour's row the created cell), the block Thomas algorithm, full steps
-// from W = U^n, converged when every step component is below
-// zn_rtol max(|W_j|, 1); at most zn_maxit steps.
-// A tube has 7 groups of L lanes (L = 1, 2, 4 as in k_ct_zone).  Every group
-// evaluates the prediction and each base point (identical inputs and warm
-// starts, so identical results without any exchange); then group g >= 1
-// evaluates the point moved along unknown g - 1 -- the six difference
-// columns side by side -- and every lane gathers the blocks and runs the
-// same block solve.  Per Newton step two evaluations in sequence
-// instead of seven.
+// (the lengths of the created cell and its two neighbours from the boundary
+// speeds at W, HLL on the other inner faces, the zone's outer faces from
+// U^n); Jacobian by forward differences (step 1e-7 max(|W_j|, 1), boundary
+// solves warm-started from the base point's) of which the 2x2 blocks beside
+// the diagonal are kept (each row couples its two neighbours only), the
+// block Thomas algorithm, full steps from W = U^n, converged when every step
+// component is below zn_rtol max(|W_j|, 1); at most zn_maxit steps.
+// A tube has 1 + 2 (2 Z + 1) groups of L lanes (L = 1, 2, 4 as in
+// k_ct_zone).  Every group evaluates the prediction and each base point
+// (identical inputs and warm starts, so identical results without any
+// exchange); then group g >= 1 evaluates the point moved along unknown
+// g - 1 -- the difference columns side by side -- and every lane gathers the
+// blocks and runs the same block solve.  Per Newton step two evaluations in
+// sequence instead of 1 + 2 (2 Z + 1).
 // ---------------------------------------------------------------------------
-template <int L>
+template <int Z, int L>
 __device__ __forceinline__ int newton_tubes_per_wave(int ppw) {
-  const int cap = 64 / (7 * L);
+  const int cap = 64 / ((2 * (2 * Z + 1) + 1) * L);
   return ppw < cap ? ppw : cap;
 }
 
-template <int L>
+template <int Z, int L>
 __global__ __launch_bounds__(64) void k_ct_newton(Args A) {
-  constexpr int Z = 1, MC = 3, NV = 6, G = 7, TL = G * L;
+  constexpr int MC = 2 * Z + 1, NV = 2 * MC, G = NV + 1, TL = G * L;
   constexpr int XB = L == 4 ? 2 : 1;
-  const int tpw = newton_tubes_per_wave<L>(A.zone_ppw);
+  const int tpw = newton_tubes_per_wave<Z, L>(A.zone_ppw);
   const int lane = (int)threadIdx.x;
   if (lane >= tpw * TL) return;
   const int p = blockIdx.x * tpw + lane / TL;
@@ -621,12 +622,16 @@ __global__ __launch_bounds__(64) void k_ct_newton(Args A) {
   const double h = A.h[p];
   const double dl = A.dl[p], dr = A.dr[p];
   double* pwp = A.pw + 4 * (long long)p;
-  // zone cells: 0 = j0 - 1 (kind 1), 1 = created (kind 2), 2 = j0 (kind 3)
+  // zone cells: j0 - Z .. j0 - 2 (kind 0), j0 - 1 (kind 1), the created cell
+  // (kind 2), j0 (kind 3), j0 + 1 .. j0 + Z - 1 (kind 0)
   double U0[MC][2], W[MC][2], hn[MC], ihn[MC], hh[MC];
-  const int slot[MC] = {j0 - 1, N, j0};
-  hn[0] = h + dl;
-  hn[1] = dr - dl;
-  hn[2] = h - dr;
+  int slot[MC], kind[MC];
+#pragma unroll
+  for (int k = 0; k < MC; ++k) {
+    slot[k] = k < Z ? j0 - Z + k : (k == Z ? N : j0 + (k - Z - 1));
+    kind[k] = k == Z - 1 ? 1 : (k == Z ? 2 : (k == Z + 1 ? 3 : 0));
+    hn[k] = k == Z - 1 ? h + dl : (k == Z ? dr - dl : (k == Z + 1 ? h - dr : h));
+  }
 #pragma unroll
   for (int k = 0; k < MC; ++k) {
     U0[k][0] = r0[slot[k]];
@@ -672,10 +677,10 @@ __global__ __launch_bounds__(64) void k_ct_newton(Args A) {
       const double g0 = fd ? (lf ? gl0 : gr0) : (lf ? pl0 : pr0);
       const double g1 = fd ? (lf ? gl1 : gr1) : (lf ? pl1 : pr1);
       if (!imexds::d_iface_solve_t<L == 4>(M, A.newton_maxit, A.newton_rtol, lf ? ph : phn,
-                                           lf ? X[0][0] : X[1][0], lf ? X[0][1] : X[1][1],
-                                           lf ? phn : ph, lf ? X[1][0] : X[2][0],
-                                           lf ? X[1][1] : X[2][1], true, g0, g1, half, lane ^ 1,
-                                           I)) {
+                                           lf ? X[Z - 1][0] : X[Z][0], lf ? X[Z - 1][1] : X[Z][1],
+                                           lf ? phn : ph, lf ? X[Z][0] : X[Z + 1][0],
+                                           lf ? X[Z][1] : X[Z + 1][1], true, g0, g1, half,
+                                           lane ^ 1, I)) {
         ec = 1;
       } else if (lf) {
         ewl = I.w;
@@ -732,7 +737,7 @@ __global__ __launch_bounds__(64) void k_ct_newton(Args A) {
       bool bad = false;
 #pragma unroll
       for (int k = 0; k < MC; ++k) {
-        hh[k] = cell_len(hn[k], k + 1, wl, wr, dt);
+        hh[k] = cell_len(hn[k], kind[k], wl, wr, dt);
         if (!(hh[k] / h > 0.0)) bad = true;  // a predicted length that vanishes
       }
       if (bad) {
@@ -742,12 +747,26 @@ __global__ __launch_bounds__(64) void k_ct_newton(Args A) {
       phase = -1;
       continue;
     }
-    const double F[MC + 1][2] = {{FL0, FL1}, {bl0, bl1}, {br0, br1}, {FR0, FR1}};
+    // faces of the point: the zone's outer faces from U^n, the two phase
+    // boundaries, HLL on the other inner faces
+    double F[MC + 1][2];
+    F[0][0] = FL0;
+    F[0][1] = FL1;
+    F[MC][0] = FR0;
+    F[MC][1] = FR1;
+    F[Z][0] = bl0;
+    F[Z][1] = bl1;
+    F[Z + 1][0] = br0;
+    F[Z + 1][1] = br1;
+#pragma unroll
+    for (int c = 0; c + 1 < MC; ++c)
+      if (c != Z - 1 && c != Z)
+        d_hll(M, ph, X[c][0], X[c][1], X[c + 1][0], X[c + 1][1], F[c + 1][0], F[c + 1][1]);
     double hk[MC];
     bool shrink = false;
 #pragma unroll
     for (int k = 0; k < MC; ++k) {
-      hk[k] = cell_len(hn[k], k + 1, ewl, ewr, dt);
+      hk[k] = cell_len(hn[k], kind[k], ewl, ewr, dt);
       if (!fd && !(hk[k] >= 0.5 * hh[k])) shrink = true;
     }
     if (shrink) {
@@ -1099,14 +1118,21 @@ hipError_t ct_launch_zone(const ct::Args& A, int lanes, hipStream_t s) {
 
 hipError_t ct_launch_newton(const ct::Args& A, int lanes, hipStream_t s) {
   if (A.P <= 0) return hipSuccess;
-  // tubes per wave as in ct::newton_tubes_per_wave: 7 lane groups per tube
-  const int cap = 64 / (7 * lanes);
+  // tubes per wave as in ct::newton_tubes_per_wave: 1 + 2 (2 Z + 1) lane
+  // groups per tube
+  const int cap = 64 / ((2 * (2 * A.Z + 1) + 1) * lanes);
   const int tpw = A.zone_ppw < cap ? A.zone_ppw : cap;
   const int blocks = (A.P + tpw - 1) / tpw;
-  switch (lanes) {
-    case 1: ct::k_ct_newton<1><<<blocks, 64, 0, s>>>(A); break;
-    case 2: ct::k_ct_newton<2><<<blocks, 64, 0, s>>>(A); break;
-    case 4: ct::k_ct_newton<4><<<blocks, 64, 0, s>>>(A); break;
+  switch (A.Z * 10 + lanes) {
+    case 11: ct::k_ct_newton<1, 1><<<blocks, 64, 0, s>>>(A); break;
+    case 12: ct::k_ct_newton<1, 2><<<blocks, 64, 0, s>>>(A); break;
+    case 14: ct::k_ct_newton<1, 4><<<blocks, 64, 0, s>>>(A); break;
+    case 21: ct::k_ct_newton<2, 1><<<blocks, 64, 0, s>>>(A); break;
+    case 22: ct::k_ct_newton<2, 2><<<blocks, 64, 0, s>>>(A); break;
+    case 24: ct::k_ct_newton<2, 4><<<blocks, 64, 0, s>>>(A); break;
+    case 31: ct::k_ct_newton<3, 1><<<blocks, 64, 0, s>>>(A); break;
+    case 32: ct::k_ct_newton<3, 2><<<blocks, 64, 0, s>>>(A); break;
+    case 34: ct::k_ct_newton<3, 4><<<blocks, 64, 0, s>>>(A); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1517,7 +1543,6 @@ int imexds_ct_set_solver(imexds_ct_ctx* c, int32_t solver, int32_t maxit, double
   if (!c) return IMEXDS_ERR_INVALID_ARG;
   if (solver != IMEXDS_CT_SOLVER_DTS && solver != IMEXDS_CT_SOLVER_NEWTON)
     return IMEXDS_ERR_INVALID_ARG;
-  if (solver == IMEXDS_CT_SOLVER_NEWTON && c->base.Z != 1) return IMEXDS_ERR_UNSUPPORTED;
   if (maxit < 1 || !ct_pos(rtol)) return IMEXDS_ERR_INVALID_ARG;
   int e = ct_err(hipSetDevice(c->device));
   if (!e) e = ct_err(hipStreamSynchronize(c->ms));

@@ -228,10 +228,22 @@ def test_newton_solver_errors():
         with pytest.raises(IMEXDSError):
             s.set_solver(*bad)
     s.close()
-    s = C.CreationTubes(CW.cavitation_tube(20).with_params(zone_half=2))
-    with pytest.raises(IMEXDSError):
-        s.set_solver(NEWTON)  # the Newton zone solver covers zones +- 1 only
-    s.close()
+
+
+@pytest.mark.parametrize("Z", [2, 3])
+def test_newton_wider_zones_and_walls(Z):
+    """The Newton zone solver on zones of the created cell +- 2 and 3 cells
+    (HLL faces inside the zone, the three moving cells in the middle),
+    walls at both ends, the smallest tube for each zone, three lane forms."""
+    specs = [CW.spec(CW.CAVITATION, 40), CW.spec(CW.NUCLEATION, 40),
+             dict(N=2 * Z + 2, h=1e-2, phase=0, left=(50000.0, -3.0), right=(70000.0, 2.0))]
+    b = CW.concat(specs, f"nzone{Z}").with_params(zone_half=Z, bc_left=0, bc_right=0, t_end=1e-4)
+    o = run_oracle(b, 40, log_rows=40, solver=NEWTON)
+    # the paper's tubes run through; the smallest tube may stop on a mesh event
+    assert np.all(o["face"] >= 0) and np.all(o["status"][:2] == 0)
+    for lanes in (1, 2, 4):
+        g = run_gpu(b, 40, lanes=lanes, log_rows=40, solver=NEWTON)
+        assert_same(b, g, o, rows=40)
 
 
 @pytest.mark.parametrize("solver,steps", [(0, 8), (NEWTON, 40)])

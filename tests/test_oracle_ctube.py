@@ -304,6 +304,27 @@ def test_newton_zone_solver_on_the_paper_runs():
         assert abs((sn.dr[0] - sn.dl[0]) / (sd.dr[0] - sd.dl[0]) - 1.0) < 1e-6
 
 
+@pytest.mark.parametrize("Z", [2, 3])
+def test_newton_zone_solver_on_wider_zones(Z):
+    """Zones of the created cell +- 2 and 3 cells (HLL faces inside the
+    zone): the Newton zone solver creates on the same face in the same step,
+    takes the same steps to t_end as Algorithm 2 (tightened to a relative
+    update of 1e-12 so that it converges as far as Newton does) and ends on
+    its states to 1e-8; a handful of Newton steps per time step."""
+    b = CW.concat([CW.spec(CW.CAVITATION, 40)], f"nz{Z}").with_params(
+        zone_half=Z, t_end=1e-4, tol_mode=1, tol_rel=1e-12, lmax=100000)
+    sd = run(b)
+    sn = oracle.CTubeState(b)
+    oracle.ct_run(sn, solver=oracle.CT_SOLVER_NEWTON)
+    assert sd.status[0] == 0 and sn.status[0] == 0
+    assert sn.face[0] == sd.face[0] == 20 and sn.steps[0] == sd.steps[0]
+    assert sn.iters[0] <= 6 * sn.steps[0] < sd.iters[0]
+    zone = np.r_[20 - Z:20 + Z, 40]  # the zone's regular cells and the created one
+    for x, y in ((sn.rho, sd.rho), (sn.mom, sd.mom)):
+        assert np.max(np.abs(x[zone] - y[zone]) / np.maximum(np.abs(y[zone]), 1.0)) < 1e-8
+    assert abs(sn.dr[0] - sd.dr[0]) < 1e-8 * abs(sd.dr[0] - sd.dl[0]) + 1e-15
+
+
 @pytest.mark.parametrize("ph,p", [(LIQ, 60000.0), (VAP, 50000.0)])
 def test_constant_state_is_preserved(ph, p):
     """A tube at rest in one uniform state creates nothing and stays exactly
