@@ -32,9 +32,9 @@ def run_oracle(batch, material, params, n_steps, threads=8):
 
 def run_gpu(batch, material, params, n_steps, launch=None, per_problem=False, log=True,
             lanes=None):
-    """``params.zone_solver`` 1 selects the Newton zone solver."""
-    """``launch``: full set_launch tuple; ``lanes``: only the lanes per zone
-    (1 or 8) with the other launch settings at their defaults."""
+    """``params.zone_solver`` 1 selects the Newton zone solver; ``launch``:
+    full set_launch tuple; ``lanes``: only the lanes per zone (1 or 8) with
+    the other launch settings at their defaults."""
     import torch
     from paper_2211_00705_amd.imexds import IMEXDS
     s = IMEXDS(batch, material, params)
@@ -98,3 +98,15 @@ def assert_parity(batch, g, o, rtol=RTOL_L1, logs=True):
             assert abs(g["hl"][k] - o["hl"][k]) <= rtol * hp, (p, k, g["hl"][k], o["hl"][k])
     np.testing.assert_allclose(g["t"], o["t"], rtol=1e-13, atol=0)
     return worst
+
+
+def take_problems(b, v, key, idx):
+    """The entries of problems ``idx`` (in order) of a run_gpu output field."""
+    so, io = b.slot_off, b.iface_off
+    if key in ("rho", "mom"):
+        return np.concatenate([v[so[p]:so[p + 1]] for p in idx])
+    if key in ("home", "hl"):
+        return np.concatenate([v[io[p]:io[p + 1]] for p in idx])
+    if key in ("t", "status", "steps"):
+        return v[idx]
+    return v

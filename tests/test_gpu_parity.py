@@ -9,7 +9,7 @@ import math
 import numpy as np
 import pytest
 
-from parity import assert_parity, run_gpu, run_oracle
+from parity import assert_parity, run_gpu, run_oracle, take_problems
 from paper_2211_00705_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -130,8 +130,8 @@ def test_failures_are_flagged_and_confined(material, lanes):
     o = run_oracle(bad, material, P, 20)
     assert g["status"][1] == 2 and g["steps"][1] == 0
     assert g["status"][3] == 2 and g["steps"][3] == 0
-    assert_parity(bad.subset([0, 2]), {k: _sub(bad, v, k, [0, 2]) for k, v in g.items()},
-                  {k: _sub(bad, v, k, [0, 2]) for k, v in o.items()}, logs=False)
+    assert_parity(bad.subset([0, 2]), {k: take_problems(bad, v, k, [0, 2]) for k, v in g.items()},
+                  {k: take_problems(bad, v, k, [0, 2]) for k, v in o.items()}, logs=False)
     np.testing.assert_array_equal(g["status"], o["status"])
     g2 = run_gpu(good, material, P.replace(newton_maxit=1), 5, lanes=lanes)
     assert np.all(g2["status"] == 1) and np.all(g2["t"] == 0)
@@ -147,17 +147,6 @@ def test_forced_small_limits_match_oracle(material, lanes):
         g = run_gpu(b, material, P, 60, lanes=lanes)
         o = run_oracle(b, material, P, 60)
         assert_parity(b, g, o)
-
-
-def _sub(b, v, key, idx):
-    so, io = b.slot_off, b.iface_off
-    if key in ("rho", "mom"):
-        return np.concatenate([v[so[p]:so[p + 1]] for p in idx])
-    if key in ("home", "hl"):
-        return np.concatenate([v[io[p]:io[p + 1]] for p in idx])
-    if key in ("t", "status", "steps"):
-        return v[idx]
-    return v
 
 
 def test_overlapping_zones_freeze_the_problem(material):
@@ -200,7 +189,7 @@ def test_full_size_batch_sampled(material):
     idx = sorted(rng.choice(b.n_problems, size=6, replace=False).tolist())
     sub = b.subset(idx)
     o = run_oracle(sub, material, P, 1000)
-    gs = {k: _sub(b, v, k, idx) for k, v in g.items() if k != "stats"}
+    gs = {k: take_problems(b, v, k, idx) for k, v in g.items() if k != "stats"}
     assert_parity(sub, gs, o, logs=False)
     assert np.all(g["steps"] == 1000)
     assert g["stats"]["cell_updates"] == 1000 * b.n_slots
@@ -249,5 +238,5 @@ def test_bubble_batch_full_size_sampled(material):
     idx = sorted(idx)
     sub = b.subset(idx)
     o = run_oracle(sub, material, P, n)
-    gs = {k: _sub(b, v, k, idx) for k, v in g.items() if k != "stats"}
+    gs = {k: take_problems(b, v, k, idx) for k, v in g.items() if k != "stats"}
     assert_parity(sub, gs, o, logs=False)

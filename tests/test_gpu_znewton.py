@@ -5,7 +5,7 @@ counts, Newton step counts, event flags and zone partitions."""
 import numpy as np
 import pytest
 
-from parity import assert_parity, run_gpu, run_oracle
+from parity import assert_parity, run_gpu, run_oracle, take_problems
 from paper_2211_00705_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -69,3 +69,39 @@ def test_per_problem_and_errors_newton(material):
         s.forward_ckpt(4, 2)  # the adjoint covers the dual time solver only
     torch.cuda.synchronize()
     s.close()
+
+
+@pytest.mark.parametrize("lanes", [1, 8])
+def test_edge_cases_newton(material, lanes):
+    """Empty batch; a problem without interfaces next to ones with them; an
+    interface in the first and last background cells; pieces of exactly zero
+    and of full length -- with the Newton zone solver."""
+    P = W.Params(bc_left=0, bc_right=1, zone_solver=1)
+    empty = W._assemble([], [], [], [], [], [], [], name="empty")
+    g = run_gpu(empty, material, P, 3, log=False, lanes=lanes)
+    assert g["rho"].size == 0
+    st = lambda x, q: (np.where(q == W.LIQ, 965.0 + 5 * x, 0.05 + 0.01 * x), 0.3 * np.ones(x.shape))
+    b = W._assemble([30, 20, 25, 40], [1 / 30, 1 / 20, 1 / 25, 1 / 40], [0, 0, 0, 0],
+                    [W.LIQ, W.VAP, W.LIQ, W.VAP], [[], [0], [24], [10, 30]],
+                    [[], [0.3 / 20], [0.5 / 25], [0.0, 1 / 40]], [st] * 4, name="edges")
+    g = run_gpu(b, material, P, 40, lanes=lanes)
+    o = run_oracle(b, material, P, 40)
+    assert_parity(b, g, o)
+
+
+def test_full_size_batch_sampled_newton(material):
+    """The benchmarked batch at full size (4096 problems, about 1.6e7 cells,
+    1000 steps) in the launch form the bench times for the Newton record
+    (tile class 1024, one-lane groups); 6 sampled problems recomputed by the
+    oracle on their own."""
+    b = W.random_batch()
+    P = W.random_batch_params().replace(zone_solver=1)
+    g = run_gpu(b, material, P, 1000, launch=(1024, 64, 0, 10, 1), log=False)
+    rng = np.random.default_rng(2)
+    idx = sorted(rng.choice(b.n_problems, size=6, replace=False).tolist())
+    sub = b.subset(idx)
+    o = run_oracle(sub, material, P, 1000)
+    gs = {k: take_problems(b, v, k, idx) for k, v in g.items() if k != "stats"}
+    assert_parity(sub, gs, o, logs=False)
+    assert np.all(g["status"] == 0) and np.all(g["steps"] == 1000)
+    assert np.array_equal(gs["rho"], o["rho"]) and np.array_equal(gs["mom"], o["mom"])
