@@ -199,6 +199,10 @@ __global__ __launch_bounds__(64) void k_zone8(StepArgs A, int if_begin, int if_e
       stage = S_PRED;
     }
     if (stage == S_EXIT) break;
+    // the right neighbour's iterate for this pass's HLL flux, read ahead of the
+    // interface solve (which leaves it unchanged) so the exchange overlaps it
+    const double nW0 = z8_get(W0, gb, c < 7 ? c + 1 : 7);
+    const double nW1 = z8_get(W1, gb, c < 7 ? c + 1 : 7);
 
     // ---------------- one interface solve (two lanes of the group) ----------------
     const bool pred = stage == S_PRED;
@@ -268,8 +272,6 @@ __global__ __launch_bounds__(64) void k_zone8(StepArgs A, int if_begin, int if_e
         }
       }
       // flux on the right face of cell c, left face from lane c - 1
-      const double nW0 = z8_get(W0, gb, c < 7 ? c + 1 : 7);
-      const double nW1 = z8_get(W1, gb, c < 7 ? c + 1 : 7);
       double Fr0 = 0.0, Fr1 = 0.0;
       if (c < m) {
         if (c == m - 1) {
@@ -296,8 +298,10 @@ __global__ __launch_bounds__(64) void k_zone8(StepArgs A, int if_begin, int if_e
       if (c == ic + 1) shr = !(hnew >= 0.5 * hh_r);
       const bool bl = z8_any(shr && c == ic, gb), br = z8_any(shr && c == ic + 1, gb);
       int shrink = -1;  // zone position
+      // zone position of active cell q: the set-up's pos of lane q
+      auto pos_of = [&](int q) { return q < m ? ((skip >= 0 && q >= skip) ? q + 1 : q) : -1; };
       {
-        const int pic = z8_geti(pos, gb, ic), pir = z8_geti(pos, gb, ic + 1);
+        const int pic = pos_of(ic), pir = pos_of(ic + 1);
         if (bl && br)
           shrink = pic < pir ? pic : pir;
         else if (bl)
@@ -306,7 +310,7 @@ __global__ __launch_bounds__(64) void k_zone8(StepArgs A, int if_begin, int if_e
           shrink = pir;
       }
       if (shrink >= 0) {
-        const int ptiny = z8_geti(pos, gb, tiny);
+        const int ptiny = pos_of(tiny);
         if (!merge && shrink == ptiny) {
           merge = true;
           redo = true;
