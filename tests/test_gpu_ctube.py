@@ -246,13 +246,15 @@ def test_newton_wider_zones_and_walls(Z):
         assert_same(b, g, o, rows=40)
 
 
-@pytest.mark.parametrize("solver,steps", [(0, 8), (NEWTON, 40)])
-def test_per_problem_launches_match_batched(solver, steps):
+@pytest.mark.parametrize("solver,steps,Z", [(0, 8, 1), (NEWTON, 40, 1), (NEWTON, 40, 2)])
+def test_per_problem_launches_match_batched(solver, steps, Z):
     """The unbatched form (every kernel of a step launched tube by tube)
     gives the batched results bit for bit."""
     import torch
     from paper_2211_00705_amd.ctube import CreationTubes
     b = CW.ctube_batch(seed=9, n_problems=24)
+    if Z != 1:
+        b = b.with_params(zone_half=Z)
     out = []
     for per_problem in (False, True):
         s = CreationTubes(b)
