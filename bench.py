@@ -311,7 +311,7 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 
 def euler_leg(args, cpu):
-    """Full-Euler Lax-tube ensemble (Sec. 5 first test, batched): 4096 tubes
+    """Full-Euler Lax-tube ensemble (Sec. 4 first test, batched): 4096 tubes
     run to t_end = 1 on the GPU with per-launch HIP events, and (cpu) the
     oracle on a bounded sample of the same tubes on 1 and on all threads."""
     import torch
@@ -449,7 +449,7 @@ def creation_leg(args, cpu):
 
 
 def ctube_leg(args, cpu):
-    """Creation tubes (Sec. 5 cavitation and nucleation runs, batched): 4096
+    """Creation tubes (Sec. 4 cavitation and nucleation runs, batched): 4096
     tubes, half cavitating liquid, half nucleating vapour, from the creation
     step to t_end = 5e-4 s with the paper's stop rule; HIP events around every
     launch; the oracle on a bounded sample of the same tubes."""

@@ -12,7 +12,7 @@
  * neighbours on each side) are updated by Algorithm 2, dual time stepping
  * with local pseudo steps (eq. "dual time tau diff") followed by a
  * conservative update from the accepted iterate (Part 2), with moving
- * interface-adjacent cells (Sec. 4.4, eq. "godunov_meth:nonunif").  The flux
+ * interface-adjacent cells (Sec. 3.4, eq. "godunov_meth:nonunif").  The flux
  * across a phase boundary comes from the two-phase Riemann problem with the
  * kinetic relation z = tau p_V [[g + e_kin]] (Sec. 2.1, eq. "isoT:kin_rel1";
  * Appendix A, eqs. "2p_RP:ex_sys", "jacobian:ex_sys", "pb_flux:pt").  The
@@ -68,7 +68,7 @@ extern "C" {
 #define IMEXDS_FL_INACTIVE 128 /* problem frozen or finished: nothing done */
 
 /* dual-time stopping rules */
-#define IMEXDS_TOL_PAPER 0 /* Sec. 5: max(res_{k-1},res_{k+1}) < tol_nb and res_k < tol_tiny */
+#define IMEXDS_TOL_PAPER 0 /* Sec. 4: max(res_{k-1},res_{k+1}) < tol_nb and res_k < tol_tiny */
 #define IMEXDS_TOL_REL 1   /* max |W^{l+1}-W^l| / max(|W^l|,1) < tol_rel over the zone */
 
 #define IMEXDS_BC_WALL 0
@@ -76,7 +76,7 @@ extern "C" {
 
 typedef struct imexds_ctx imexds_ctx; /* opaque; owns all of its device buffers */
 
-/* Phase pressure laws (Sec. 5): vapour ideal gas p = a2_vap rho
+/* Phase pressure laws (Sec. 4): vapour ideal gas p = a2_vap rho
  * (eq. "eos:isoT_idgas", a2_vap = k T0 / m); liquid linear Tait law
  * p = p_sat + a2_liq (rho - rho_liq_sat) (eq. "eos:isoT_lintait" with
  * a2_liq = K0 / rho0).  Gibbs energies g = a^2 ln(rho / rho_sat) per phase,
@@ -89,10 +89,10 @@ typedef struct {
 typedef struct {
   double cfl;         /* C_CFL of eq. "cfl_cond:unif" */
   int32_t zone_half;  /* Z: an implicit zone is the tiny cut piece +- Z slots (1..3) */
-  double theta_nb;    /* theta for full cells (0.9 in Sec. 5) */
+  double theta_nb;    /* theta for full cells (0.9 in Sec. 4) */
   int32_t tol_mode;   /* IMEXDS_TOL_* */
-  double tol_nb;      /* 1e-3 in Sec. 5 */
-  double tol_tiny;    /* 1e-1 in Sec. 5 */
+  double tol_nb;      /* 1e-3 in Sec. 4 */
+  double tol_tiny;    /* 1e-1 in Sec. 4 */
   double tol_rel;     /* for IMEXDS_TOL_REL */
   int32_t lmax;       /* maximal pseudo steps per zone and step (Algorithm 2) */
   double alpha_floor; /* cut pieces shorter than alpha_floor*h are merged */

@@ -73,7 +73,7 @@ extern "C" {
  *   rho_l, mom_l   device [n]: left state (rho, rho u)
  *   rho_r, mom_r   device [n]: right state
  *   p_min, p_tilde the creation thresholds (0 Pa and 70388.660656 Pa at
- *                  363.15 K, Sec. 5)
+ *                  363.15 K, Sec. 4)
  *   maxit, rtol    Newton-Armijo limits of step (ii) (e.g. 50, 1e-14)
  *   status         device [n] out: 0 no creation, 1 created, -1 invalid
  *                  input (rho <= 0, unknown phase) or step (ii) failed

@@ -2,7 +2,7 @@
  * imexds_ctube.h -- creation tubes: phase creation inside the mesh of the
  * isothermal two-phase scheme of imexds.h (May & Thein, arXiv 2211.00705:
  * appendix "Phase Creation", step (iv) and the sentence after the step lists
- * -- the next step has two phase boundaries treated as before; Sec. 5,
+ * -- the next step has two phase boundaries treated as before; Sec. 4,
  * cavitation and nucleation tests).
  *
  * A tube has N regular cells of length h, all of one phase, on a fixed
@@ -20,7 +20,7 @@
  * x_j + dl and x_j + dr; Algorithm 1 treats every cell but "created cell
  * +- Z cells" explicitly, and Algorithm 2 (dual time stepping with Delta
  * tau_i = theta_i dt, theta_i = min(theta_nb, h_i^pred / h), the stop rule
- * of Sec. 5 with tol_tiny on the created cell) solves that zone: HLL on its
+ * of Sec. 4 with tol_tiny on the created cell) solves that zone: HLL on its
  * inner faces of the outer phase, the interface solver on the two phase
  * boundaries (their speeds move the lengths of the created cell and its two
  * neighbours), the zone's outer faces from U^n, Part 2 conservative.  CFL
@@ -78,7 +78,7 @@ typedef struct {
 /* Creates a context on the current HIP device; work is ordered after
  * hip_stream (NULL: the null stream) on entry and before it on return.
  * p_min, p_tilde: the creation thresholds (0 Pa and 70388.660656 Pa at
- * 363.15 K, Sec. 5).  Returns IMEXDS_ERR_INVALID_ARG for invalid material,
+ * 363.15 K, Sec. 4).  Returns IMEXDS_ERR_INVALID_ARG for invalid material,
  * parameters (zone_half outside 1..3, lmax < 1, ...) or tubes,
  * IMEXDS_ERR_OOM, IMEXDS_ERR_HIP. */
 int imexds_ct_create(imexds_ct_ctx **out, const imexds_material *mat, const imexds_params *par,

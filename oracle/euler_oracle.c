@@ -1,7 +1,7 @@
 /*
  * euler_oracle.c -- plain, slow, FP64 CPU oracle of the mixed explicit-implicit
  * scheme with dual time stepping applied to the full 1D Euler equations of an
- * ideal gas on a fixed mesh with one small cell (the first test of Sec. 5,
+ * ideal gas on a fixed mesh with one small cell (the first test of Sec. 4,
  * "stationary phase boundary without phase transition": the Lax shock tube
  * and its study of the local pseudo time step factors theta_i).
  *
@@ -21,7 +21,7 @@
  *     (dual time stepping on the three cells with Delta tau_i = theta_i Delta t,
  *     then Part 2, the conservative update with fluxes of the accepted
  *     iterate);
- *   - the residual and stopping rule of Sec. 5: res_{k-1}, res_{k+1} < tol_nb
+ *   - the residual and stopping rule of Sec. 4: res_{k-1}, res_{k+1} < tol_nb
  *     and res_k < tol_k;
  *   - the time step of eq. cfl_cond:unif with the regular length h.
  *
@@ -291,7 +291,7 @@ typedef struct {
   int lmax;
 } eu_params;
 
-/* stop test of Sec. 5 for one cell */
+/* stop test of Sec. 4 for one cell */
 static int eu_cell_done(const double *Wold, const double *Wnew, double th, double thr) {
   for (int c = 0; c < 3; ++c) {
     double d = (1.0 + th) * (Wnew[c] - Wold[c]);
@@ -363,7 +363,7 @@ static int eu_step(const eu_gas *G, const eu_params *P, int N, double h, double 
   }
   if (stz) return st | stz;
   /* Algorithm 2, Part 1: dual time stepping from W^0 = U^n with the pseudo
-   * steps Delta tau_i = theta_i Delta t_ref of Sec. 5, Delta t_ref the CFL step;
+   * steps Delta tau_i = theta_i Delta t_ref of Sec. 4, Delta t_ref the CFL step;
    * Delta t = Delta t_ref but on a step clipped to t_end, where the update
    * takes the ratio Delta tau_i / Delta t */
   double lamk = dt / hk;

@@ -18,7 +18,7 @@
  *     written here as p0 + aL^2 (rho - rho0));
  *   - Gibbs energies g_K = a_K^2 ln(rho/rho_K0), equal at saturation by the
  *     Maxwell construction (Sec. 2.1);
- *   - the HLL flux for same-phase faces (Sec. 5, "HLL solver as in Toro"),
+ *   - the HLL flux for same-phase faces (Sec. 4, "HLL solver as in Toro"),
  *     Davis wave speeds;
  *   - the two-phase interface Riemann solve: Newton-Armijo on
  *     G(p_l*, p_r*) = 0 (Appendix A, eqs. 2p_RP:ex_sys and jacobian:ex_sys),
@@ -28,8 +28,8 @@
  *   - Algorithm 1 (explicit bulk update, saved bounding fluxes) and
  *     Algorithm 2 (dual time stepping, Part 1 and Part 2) on a zone of
  *     2Z+1 cells around each tiny cut cell, with local pseudo steps
- *     (eq. dual time tau diff), the residual and stopping rule of Sec. 5 and
- *     moving cell lengths (Sec. 4.4, eq. godunov_meth:nonunif);
+ *     (eq. dual time tau diff), the residual and stopping rule of Sec. 4 and
+ *     moving cell lengths (Sec. 3.4, eq. godunov_meth:nonunif);
  *   - CFL time step (eq. cfl_cond:unif);
  *   - grid alignment with merging of vanishing cut pieces and re-splitting
  *     (Sec. 2.3), by the deterministic rule stated in the design notes.
@@ -972,7 +972,7 @@ static int or_state_ok(real r, real m) { return r > 0.0 && isfinite(r) && isfini
  * Pseudo step (eq. dual time tau diff with moving lengths):
  *   W^{l+1} = (W^l + theta rhs) / (1 + theta),
  *   rhs = (h^n U^n - dt (F_{i+1/2}(W^l) - F_{i-1/2}(W^l))) / h^{n,l+1};
- * stop test of Sec. 5, res_i < tol_i, evaluated without dividing:
+ * stop test of Sec. 4, res_i < tol_i, evaluated without dividing:
  *   |(1 + theta_i)(W^{l+1} - W^l)| < tol_i (theta_i dt) max(|W^l|, 1)
  * for both components of every cell (tol_tiny on the tiny cell, tol_nb on
  * the others); in relative mode |W^{l+1} - W^l| < tol_rel max(|W^l|, 1). */

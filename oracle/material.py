@@ -3,8 +3,8 @@
 TEST INFRASTRUCTURE ONLY (part of the CPU oracle).
 
 * Vapour: ideal gas p = (k T0 / m) rho with the printed Boltzmann constant and
-  molecule mass (Sec. 5, eq. eos:isoT_idgas).
-* Kinetic coefficient tau = (2 pi)^(-1/2) (m / (k T0))^(3/2) (Sec. 5).
+  molecule mass (Sec. 4, eq. eos:isoT_idgas).
+* Kinetic coefficient tau = (2 pi)^(-1/2) (m / (k T0))^(3/2) (Sec. 4).
 * Liquid: linear Tait law, read as p = p0 + K0 (rho/rho0 - 1) (the printed
   "- p0" inside the bracket is dimensionally inconsistent).  rho0 and K0 come
   from steam tables in the paper and are not printed; they are recovered

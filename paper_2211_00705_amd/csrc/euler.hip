@@ -1,6 +1,6 @@
 // euler.hip -- the explicit-implicit scheme with dual time stepping for the
 // full 1D Euler equations of an ideal gas on a fixed mesh with one small cell
-// per problem (Sec. 5, first test; Algorithms 1 and 2), kernels and the host
+// per problem (Sec. 4, first test; Algorithms 1 and 2), kernels and the host
 // runtime behind include/imexds_euler.h.
 //
 // Kernels, one step of every problem:
@@ -400,7 +400,7 @@ __global__ __launch_bounds__(64) void k_eu_zone(Args A) {
   const double h = A.h[p];
   const double hk = A.alpha[p] * h;
   const double lam = dt / h, lamk = dt / hk;
-  // pseudo steps Delta tau_i = theta_i Delta t_ref (Sec. 5); the update uses
+  // pseudo steps Delta tau_i = theta_i Delta t_ref (Sec. 4); the update uses
   // Delta tau_i / Delta t, which is theta_i unless the step was clipped
   const double dtr = A.dtr[p];
   const double tau0 = A.thnb[p] * dtr, tau1 = A.thk[p] * dtr;
@@ -495,7 +495,7 @@ __global__ __launch_bounds__(64) void k_eu_zone(Args A) {
       const double nc0 = (Wc0 + th0 * (rc - lam * (Fr0 - Kp0))) / (1.0 + th0);
       const double nc1 = (Wc1 + th0 * (mc - lam * (Fr1 - Kp1))) / (1.0 + th0);
       const double nc2 = (Wc2 + th0 * (Ec - lam * (Fr2 - Kp2))) / (1.0 + th0);
-      // stop test of Sec. 5, multiplied out
+      // stop test of Sec. 4, multiplied out
       bool ok = true;
 #define EU_TEST(Wo, Wn, th, thr)                                   \
   {                                                                \

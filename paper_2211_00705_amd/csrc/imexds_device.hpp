@@ -1,6 +1,6 @@
 // imexds_device.hpp -- device-side physics of the IMEX-DS step (gfx950).
 //
-// Phase laws and Gibbs energies (Sec. 5 eqs. eos:isoT_idgas, eos:isoT_lintait;
+// Phase laws and Gibbs energies (Sec. 4 eqs. eos:isoT_idgas, eos:isoT_lintait;
 // Sec. 2.1 Maxwell construction), the HLL flux for same-phase faces, and the
 // two-phase interface Riemann solve of Appendix A: Newton-Armijo on
 // G(p_l*, p_r*) = ([[p]] + z^2 [[v]],  f_l + f_r + z [[v]] + (u_r - u_l)) with

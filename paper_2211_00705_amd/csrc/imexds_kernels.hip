@@ -413,7 +413,7 @@ __global__ __launch_bounds__(64) void k_zone(StepArgs A, int if_begin, int if_en
         }
       } else {
         // Part 1 pseudo step (eq. dual time tau diff, moving lengths) with the
-        // stop test of Sec. 5 written without divisions:
+        // stop test of Sec. 4 written without divisions:
         //   |(1 + theta) d| < tol_i (theta dt) max(|W|, 1)  per component;
         // or Part 2: the conservative update from the accepted iterate.
         const bool paper = P.tol_mode == 0;
@@ -506,7 +506,7 @@ __global__ __launch_bounds__(64) void k_zone(StepArgs A, int if_begin, int if_en
         icr = (merge && tr) ? into : iR;
         tiny = merge ? into : (tr ? iR : iL);
         // lengths at t^n, predicted end lengths and pseudo steps
-        // theta = min(theta_nb, h_end / h) (Sec. 5: theta_k = alpha, 0.9 otherwise)
+        // theta = min(theta_nb, h_end / h) (Sec. 4: theta_k = alpha, 0.9 otherwise)
         hn_l = (merge && !tr) ? hm : hLp;
         hn_r = (merge && tr) ? hm : hRp;
         hh_l = hn_l + (1.0 * wp) * dt;

@@ -320,7 +320,7 @@ __global__ __launch_bounds__(64) void k_zone8(StepArgs A, int if_begin, int if_e
         }
       } else {
         // Part 1 pseudo step (eq. dual time tau diff, moving lengths) with the
-        // stop test of Sec. 5; or Part 2, the conservative update
+        // stop test of Sec. 4; or Part 2, the conservative update
         const bool paper = P.tol_mode == 0;
         bool okw = true, conv = true;
         if (c < m) {

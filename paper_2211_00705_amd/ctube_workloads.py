@@ -1,5 +1,5 @@
 """Seeded synthetic inputs for creation tubes: the cavitation and nucleation
-tests of Sec. 5 run through the whole scheme (phase creation on a face, then
+tests of Sec. 4 run through the whole scheme (phase creation on a face, then
 a created cell between two phase boundaries), and ensembles around them.
 
 Like ``workloads``, this module only lays out grids, initial data and run
@@ -21,7 +21,7 @@ import numpy as np
 
 from .workloads import LIQ, P_MIN, P_TILDE, VAP, WATER_363K, Params, _rho_of_p
 
-# the Sec. 5 runs: C_CFL = 0.5, h = 1e-2 m on [-2, 2] m, t_end = 5e-4 s;
+# the Sec. 4 runs: C_CFL = 0.5, h = 1e-2 m on [-2, 2] m, t_end = 5e-4 s;
 # zone of the created cell +- 1 cell, the paper's stop rule
 CT_PARAMS = Params(cfl=0.5, zone_half=1, theta_nb=0.9, tol_mode=0, tol_nb=1e-3, tol_tiny=1e-1,
                    lmax=100_000, bc_left=1, bc_right=1, t_end=5e-4)
@@ -119,13 +119,13 @@ def spec(case, N=400, h=1e-2):
 
 
 def cavitation_tube(N=400, h=1e-2, **kw):
-    """The cavitation test of Sec. 5: liquid at 60000 Pa pulled apart at
+    """The cavitation test of Sec. 4: liquid at 60000 Pa pulled apart at
     -/+4 m/s, [-2, 2] m with h = 1e-2 m for N = 400."""
     return concat([spec(CAVITATION, N, h)], name=f"cavitation_N{N}", **kw)
 
 
 def nucleation_tube(N=400, h=1e-2, **kw):
-    """The nucleation test of Sec. 5: vapour at 70000 Pa compressed at
+    """The nucleation test of Sec. 4: vapour at 70000 Pa compressed at
     +/-2.7 m/s."""
     return concat([spec(NUCLEATION, N, h)], name=f"nucleation_N{N}", **kw)
 

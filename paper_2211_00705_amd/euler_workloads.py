@@ -1,5 +1,5 @@
 """Seeded synthetic inputs for the full-Euler instance of the method: ideal gas
-on a fixed mesh with one small cell (the first test of Sec. 5, the Lax shock
+on a fixed mesh with one small cell (the first test of Sec. 4, the Lax shock
 tube with the local pseudo time step factors theta_i).
 
 Like ``workloads``, this module only lays out grids, initial data and run
@@ -129,13 +129,13 @@ def lax_spec(N=100, alpha=1e-2, theta_nb=0.9, theta_k=None, cfl=0.8, t_end=1.0,
 
 
 def lax_tube(N=100, alpha=1e-2, theta_nb=0.9, theta_k=None, **kw):
-    """The Lax shock tube of Sec. 5 on [-5, 5 + alpha h], C_CFL = 0.8,
+    """The Lax shock tube of Sec. 4 on [-5, 5 + alpha h], C_CFL = 0.8,
     t_end = 1, theta_k = alpha unless given."""
     return _concat([lax_spec(N, alpha, theta_nb, theta_k, **kw)], name=f"lax_N{N}_a{alpha:g}")
 
 
 # the configurations of the paper's table of average dual time iterations
-# (Sec. 5, Lax shock tube): (theta_{k+-1}, N, alpha), theta_{k+-1} = None
+# (Sec. 4, Lax shock tube): (theta_{k+-1}, N, alpha), theta_{k+-1} = None
 # meaning theta_{k+-1} = alpha
 LAX_STUDY = ([(th, N, a) for th in (0.9, 0.1) for N in (100, 200, 400) for a in (1e-2, 1e-4, 1e-6)]
              + [(None, N, a) for N in (100, 200, 400) for a in (1e-2, 1e-4, 1e-5)])

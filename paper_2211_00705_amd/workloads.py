@@ -8,13 +8,13 @@ Material constants (water at T0 = 363.15 K) are stored as numbers with their
 provenance:
 
 * ``a2v = k T0 / m`` with Boltzmann's constant and the molecule mass printed
-  with the ideal-gas law (Sec. 5, eq. eos:isoT_idgas);
+  with the ideal-gas law (Sec. 4, eq. eos:isoT_idgas);
 * ``p0`` is the printed saturation pressure (cavitation initial-data table);
-* ``tau = (2 pi)^(-1/2) (m / k T0)^(3/2)`` (Sec. 5, kinetic coefficient);
+* ``tau = (2 pi)^(-1/2) (m / k T0)^(3/2)`` (Sec. 4, kinetic coefficient);
 * ``rhol0`` and ``a2l = K0 / rho0`` of the linear Tait law are not printed (the
   paper takes them from steam tables); they are recovered from the printed
   p_min = 0 Pa at rho_min = 965.289008 kg/m^3 and the Maxwell equal-area rule
-  with a connector linear in density (Sec. 5, table of p~, rho~, p_min,
+  with a connector linear in density (Sec. 4, table of p~, rho~, p_min,
   rho_min).  The derivation lives with the CPU oracle and a test checks these
   numbers against it.
 
@@ -391,7 +391,7 @@ def single_phase_problem(n, rho_fn, u_fn, phase=LIQ, length=1.0):
 # single-phase Riemann problems for phase creation (cavitation, nucleation)
 # ---------------------------------------------------------------------------
 
-# creation thresholds at 363.15 K (Sec. 5, table of the maximum vapour
+# creation thresholds at 363.15 K (Sec. 4, table of the maximum vapour
 # pressure and the minimum liquid pressure)
 P_MIN = 0.0
 P_TILDE = 70388.660656
@@ -417,7 +417,7 @@ def _rho_of_p(material, ph, p):
 
 
 def creation_problem(material, phase, pl, ul, pr, ur):
-    """One problem from pressures and velocities (the Sec. 5 tests: liquid
+    """One problem from pressures and velocities (the Sec. 4 tests: liquid
     60000 Pa at -/+4 m/s, vapour 70000 Pa at +/-2.7 m/s)."""
     rl, rr = _rho_of_p(material, phase, pl), _rho_of_p(material, phase, pr)
     return CreationBatch(np.array([phase], np.int32), np.array([rl]), np.array([rl * ul]),

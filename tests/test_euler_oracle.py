@@ -2,7 +2,7 @@
 the exact Riemann solver against the wave curves and the integral form of
 the conservation law, the dual time stepping against a direct solve of the
 implicit system and against the paper's table of average iteration counts
-for the Lax shock tube (Sec. 5, first test), conservation and convergence to
+for the Lax shock tube (Sec. 4, first test), conservation and convergence to
 the exact solution."""
 import json
 import math
@@ -167,7 +167,7 @@ def test_lax_table_of_average_iterations():
     """The paper's table of average dual time iterations for the Lax tube.
 
     Our reading (S^n = max |u| + a over the cells, exact Godunov fluxes, the
-    Sec. 5 residual) gives 0.69..0.97 of every printed entry and never more;
+    Sec. 4 residual) gives 0.69..0.97 of every printed entry and never more;
     with theta_{k+-1} = alpha the ratio of the alpha = 1e-4 to the 1e-2 column
     (the O(1/alpha) growth the paper points out) matches the printed one to
     1%, and every ordering the table shows holds."""

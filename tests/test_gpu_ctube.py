@@ -74,7 +74,7 @@ def assert_same(b, g, o, idx=None, rows=None):
 
 
 def test_paper_tests_to_end_time():
-    """The cavitation and nucleation tests of Sec. 5 (N = 400, h = 1e-2 m,
+    """The cavitation and nucleation tests of Sec. 4 (N = 400, h = 1e-2 m,
     C_CFL = 0.5) to t_end = 5e-4 s with the paper's stop rule: about 3.2
     million dual time iterations for the nucleation tube (two lanes per phase
     boundary; the other forms are compared on the ensembles)."""
@@ -187,7 +187,7 @@ NEWTON = oracle.CT_SOLVER_NEWTON
 
 @pytest.mark.parametrize("lanes", [1, 2, 4])
 def test_newton_paper_tests_to_end_time(lanes):
-    """The Sec. 5 cavitation and nucleation tubes to t_end with the Newton
+    """The Sec. 4 cavitation and nucleation tubes to t_end with the Newton
     zone solver: about 3 Newton steps per time step."""
     b = CW.concat([CW.spec(CW.CAVITATION), CW.spec(CW.NUCLEATION)], "paper")
     rows = 160

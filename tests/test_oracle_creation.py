@@ -27,7 +27,7 @@ P_MIN, P_TILDE = LIM["p_min_Pa"], LIM["p_tilde_Pa"]
 
 
 def rho(ph, p):
-    # the phase pressure laws of Sec. 5, inverted
+    # the phase pressure laws of Sec. 4, inverted
     return p / M.a2v if ph == W.VAP else M.rhol0 + (p - M.p0) / M.a2l
 
 
@@ -37,7 +37,7 @@ def solve(ph, pl, ul, pr, ur):
 
 
 def test_cavitation_exact_row():
-    """Sec. 5 cavitation test: liquid at 60000 Pa pulled apart at -/+4 m/s."""
+    """Sec. 4 cavitation test: liquid at 60000 Pa pulled apart at -/+4 m/s."""
     g = gold("cavitation_star_states.json")
     st, d = solve(W.LIQ, 60000.0, -4.0, 60000.0, 4.0)
     assert st == 1 and d["kind"] == 1.0 and d["p1"] < P_MIN
@@ -56,7 +56,7 @@ def test_cavitation_exact_row():
 
 
 def test_nucleation_exact_row():
-    """Sec. 5 nucleation test: vapour at 70000 Pa compressed at +/-2.7 m/s."""
+    """Sec. 4 nucleation test: vapour at 70000 Pa compressed at +/-2.7 m/s."""
     g = gold("nucleation_star_states.json")
     st, d = solve(W.VAP, 70000.0, 2.7, 70000.0, -2.7)
     assert st == 1 and d["kind"] == 2.0 and d["p1"] > P_TILDE

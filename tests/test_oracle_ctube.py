@@ -1,5 +1,5 @@
 """The creation-tube oracle (a created cell inside the mesh: appendix "Phase
-Creation" step (iv), then two phase boundaries, Sec. 4 with Algorithm 2)
+Creation" step (iv), then two phase boundaries, Sec. 3 with Algorithm 2)
 pinned on what the paper prints for its cavitation and nucleation tests and
 on what the mathematics fixes: conservation, mirror symmetry, the plain
 explicit HLL scheme where nothing is created, and the status paths."""
@@ -47,7 +47,7 @@ def cell_mass(st, b, p):
 
 
 def test_cavitation_test_reproduces_printed_rows():
-    """Cavitation test (Sec. 5): liquid 60000 Pa at -/+4 m/s, h = 1e-2 m,
+    """Cavitation test (Sec. 4): liquid 60000 Pa at -/+4 m/s, h = 1e-2 m,
     C_CFL = 0.5, t_end = 5e-4 s.  The star cells at t_end carry the printed
     rows (pressure table: implicit 68483.740426 / 68477.181783 /
     68483.740588 Pa, exact 68483.741137 / 68477.181783; velocity table
@@ -69,7 +69,7 @@ def test_cavitation_test_reproduces_printed_rows():
 
 
 def test_nucleation_test_reproduces_printed_implicit_row():
-    """Nucleation test (Sec. 5): vapour 70000 Pa at +/-2.7 m/s.  The computed
+    """Nucleation test (Sec. 4): vapour 70000 Pa at +/-2.7 m/s.  The computed
     star cells sit where the printed implicit row does (70382.992468 /
     70383.072633 / 70382.992468 Pa, 0.465933 / ~1e-10 / -0.465933 m/s),
     about 0.03 Pa below the exact solution (70383.024449 / 70383.115685):
@@ -286,7 +286,7 @@ def test_newton_zone_solver_lands_on_the_implicit_step(case):
 
 
 def test_newton_zone_solver_on_the_paper_runs():
-    """With the Newton zone solver the Sec. 5 runs reach t_end in the same
+    """With the Newton zone solver the Sec. 4 runs reach t_end in the same
     large steps, the star cells within 0.02 Pa of the printed implicit rows
     (the liquid layer's pressure, p0 + a_L^2 (rho - rho0), moves 0.02 Pa per
     1e-8 kg/m^3), with about 3 Newton steps per time step instead of up to

@@ -6,7 +6,7 @@ decision (pseudo-iteration count, merge, crossing, CFL cell, HLL branch)
 that of the plain run.  These tests pin it to things other than itself:
 
 * its value parts are the plain oracle's, bit for bit;
-* the scheme conserves mass exactly with walls (Sec. 4.4: the moving cut
+* the scheme conserves mass exactly with walls (Sec. 3.4: the moving cut
   cells update h U conservatively, eq. godunov_meth:nonunif), so the
   derivative of the total mass after any number of steps along any
   direction is the initial slot lengths dotted with the density direction;
