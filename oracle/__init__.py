@@ -19,6 +19,9 @@ SRC_EULER = os.path.join(_HERE, "euler_oracle.c")
 DUAL_H = os.path.join(_HERE, "or_dual.h")
 LIB = os.path.join(_HERE, "liboracle_imexds.so")
 LIB_TAN = os.path.join(_HERE, "liboracle_imexds_tan.so")
+# the same source with every formula as the paper prints it and the C
+# library's log (OR_PLAIN; see the source's header)
+LIB_PLAIN = os.path.join(_HERE, "liboracle_imexds_plain.so")
 
 ST_NEWTON, ST_NONPHYS, ST_MESH, ST_OVERLAP = 1, 2, 4, 8
 FL_TINY_RIGHT, FL_MERGED, FL_REDO, FL_LMAX = 1, 2, 4, 8
@@ -26,12 +29,17 @@ FL_CROSS_L, FL_CROSS_R, FL_FAIL, FL_INACTIVE = 16, 32, 64, 128
 
 
 def build():
-    """Compiles the oracle shared library and its tangent (dual-number) build
-    from the same source (always recompiles)."""
+    """Compiles the oracle shared library, its tangent (dual-number) build
+    and its plain-arithmetic build from the same source (always
+    recompiles)."""
     tmp = LIB + ".tmp"
     subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
                            "-shared", "-fPIC", "-o", tmp, SRC, SRC_EULER, "-lm"])
     os.replace(tmp, LIB)
+    tmp = LIB_PLAIN + ".tmp"
+    subprocess.check_call(["gcc", "-DOR_PLAIN", "-O2", "-ffp-contract=off", "-fno-fast-math",
+                           "-fopenmp", "-shared", "-fPIC", "-o", tmp, SRC, "-lm"])
+    os.replace(tmp, LIB_PLAIN)
     tmp = LIB_TAN + ".tmp"
     subprocess.check_call(["g++", "-x", "c++", "-std=c++17", "-DOR_TANGENT", "-I", _HERE, "-O2",
                            "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-shared", "-fPIC",
@@ -64,6 +72,7 @@ class _Iface(ctypes.Structure):
 
 _lib = None
 _lib_tan = None
+_lib_plain = None
 
 
 def _stale(path):
@@ -72,18 +81,28 @@ def _stale(path):
             or os.path.getmtime(path) < os.path.getmtime(SRC_EULER))
 
 
+def _run_argtypes(L):
+    dp, ip, lp = (ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
+                  ctypes.POINTER(ctypes.c_longlong))
+    run_args = [ctypes.POINTER(_Mat), ctypes.POINTER(_Par), ctypes.c_int, ip, dp, ip, ip, lp, ip,
+                dp, dp, ip, dp, dp, dp, ip, lp, ctypes.c_int, ip, ip, ip, ip, ip, ip, ip,
+                ctypes.c_int]
+    L.oracle_run.restype = ctypes.c_int
+    L.oracle_run.argtypes = run_args
+    L.oracle_run_trace.restype = ctypes.c_int
+    L.oracle_run_trace.argtypes = run_args + [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp,
+                                              ctypes.c_int, ip]
+
+
 def lib():
     global _lib
     if _lib is None:
-        if _stale(LIB) or _stale(LIB_TAN):
+        if _stale(LIB) or _stale(LIB_TAN) or _stale(LIB_PLAIN):
             build()
         L = ctypes.CDLL(LIB)
         dp, ip, lp = (ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
                       ctypes.POINTER(ctypes.c_longlong))
-        L.oracle_run.restype = ctypes.c_int
-        L.oracle_run.argtypes = [ctypes.POINTER(_Mat), ctypes.POINTER(_Par), ctypes.c_int, ip, dp,
-                                 ip, ip, lp, ip, dp, dp, ip, dp, dp, dp, ip, lp, ctypes.c_int, ip,
-                                 ip, ip, ip, ip, ip, ip, ctypes.c_int]
+        _run_argtypes(L)
         L.oracle_objective.restype = None
         L.oracle_objective.argtypes = [ctypes.c_int, ip, dp, dp, ip, lp, ip, dp, dp,
                                        ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
@@ -135,6 +154,20 @@ def lib():
     return _lib
 
 
+def lib_plain():
+    """The plain-arithmetic build (oracle_run, oracle_run_trace and the
+    interface solve only)."""
+    global _lib_plain
+    if _lib_plain is None:
+        lib()
+        L = ctypes.CDLL(LIB_PLAIN)
+        _run_argtypes(L)
+        L.oracle_iface_solve.restype = ctypes.c_int
+        L.oracle_iface_solve.argtypes = lib().oracle_iface_solve.argtypes
+        _lib_plain = L
+    return _lib_plain
+
+
 def _mat(m):
     return _Mat(m.a2v, m.a2l, m.p0, m.rhol0, m.tau)
 
@@ -183,14 +216,18 @@ def _geometry(b):
             np.ascontiguousarray(b.slot_off, dtype=np.int64))
 
 
-def run(state, material, params, n_steps, log=False, threads=1, replay=None):
+def run(state, material, params, n_steps, log=False, threads=1, replay=None, plain=False,
+        trace=None):
     """Advances every problem of ``state`` by ``n_steps`` steps (or until
     t_end / failure).  Returns per-step logs (count, flags, zlo) of shape
     [n_steps, n_iface] if ``log`` (with log="full": also the CFL slot,
     [n_steps, n_problems]).  ``replay`` = a full log of an earlier run:
-    its decisions are repeated instead of taken."""
+    its decisions are repeated instead of taken.  ``plain``: run the
+    plain-arithmetic build.  ``trace`` = (problem, step, local interface):
+    the dual time iterates of that zone solve are recorded and returned
+    (see trace_record) as the last element of the result."""
     b = state.batch
-    L = lib()
+    L = lib_plain() if plain else lib()
     m, p = _mat(material), _par(params)
     n_cells, h, pf, ioff, soff = _geometry(b)
     nif = b.n_iface
@@ -210,21 +247,55 @@ def run(state, material, params, n_steps, log=False, threads=1, replay=None):
                                      dtype=np.int32) for a in (rc_, rf_)]
         keep.append(np.ascontiguousarray(rs_[:n_steps], dtype=np.int32))
         rcp, rfp, rsp = (_ptr(a, ctypes.c_int) for a in keep)
-    rc = L.oracle_run(ctypes.byref(m), ctypes.byref(p), b.n_problems, _ptr(n_cells, ctypes.c_int),
-                      _ptr(h, ctypes.c_double), _ptr(pf, ctypes.c_int), _ptr(ioff, ctypes.c_int),
-                      _ptr(soff, ctypes.c_longlong), _ptr(state.home, ctypes.c_int),
-                      _ptr(state.hl, ctypes.c_double), _ptr(state.pw, ctypes.c_double),
-                      _ptr(state.warm, ctypes.c_int), _ptr(state.rho, ctypes.c_double),
-                      _ptr(state.mom, ctypes.c_double), _ptr(state.t, ctypes.c_double),
-                      _ptr(state.status, ctypes.c_int), _ptr(state.steps, ctypes.c_longlong),
-                      int(n_steps), lcp, lfp, lzp, lsp, rcp, rfp, rsp, int(threads))
+    args = (ctypes.byref(m), ctypes.byref(p), b.n_problems, _ptr(n_cells, ctypes.c_int),
+            _ptr(h, ctypes.c_double), _ptr(pf, ctypes.c_int), _ptr(ioff, ctypes.c_int),
+            _ptr(soff, ctypes.c_longlong), _ptr(state.home, ctypes.c_int),
+            _ptr(state.hl, ctypes.c_double), _ptr(state.pw, ctypes.c_double),
+            _ptr(state.warm, ctypes.c_int), _ptr(state.rho, ctypes.c_double),
+            _ptr(state.mom, ctypes.c_double), _ptr(state.t, ctypes.c_double),
+            _ptr(state.status, ctypes.c_int), _ptr(state.steps, ctypes.c_longlong),
+            int(n_steps), lcp, lfp, lzp, lsp, rcp, rfp, rsp, int(threads))
+    rec = None
+    if trace is None:
+        rc = L.oracle_run(*args)
+    else:
+        tp, tstep, tk = (int(x) for x in trace)
+        cap = 8 + 4 * 32 + (params.lmax + 2) * (2 * 32 + 1) + 64
+        buf = np.zeros(cap)
+        n = ctypes.c_int(0)
+        rc = L.oracle_run_trace(*args, tp, tstep, tk, _ptr(buf, ctypes.c_double), cap,
+                                ctypes.byref(n))
+        assert n.value <= cap
+        rec = trace_record(buf[:n.value])
     if rc != 0:
         raise ValueError(f"oracle_run rejected the parameters (rc={rc})")
+    out = ()
     if log == "full":
-        return lc[:, :nif], lf[:, :nif], lz[:, :nif], ls
-    if log:
-        return lc[:, :nif], lf[:, :nif], lz[:, :nif]
-    return None
+        out = (lc[:, :nif], lf[:, :nif], lz[:, :nif], ls)
+    elif log:
+        out = (lc[:, :nif], lf[:, :nif], lz[:, :nif])
+    if trace is not None:
+        return out + (rec,)
+    return out if log else None
+
+
+def trace_record(buf):
+    """Decodes one zone-solve record of oracle_run_trace: the zone's active
+    cells (m), its tiny cell, the cell left of the phase boundary, dt, the
+    dual time count and whether it stopped at lmax; per cell theta, h^n, the
+    predicted end length and its motion (+1, -1, 0); the iterates W[l]
+    (l = 0 .. count, shape [count+1, m, 2]) and the phase-boundary speed w[l]
+    of the interface solve on W[l].  None if no zone was recorded."""
+    if len(buf) == 0:
+        return None
+    m, tiny, ic = int(buf[0]), int(buf[1]), int(buf[2])
+    dt, count, lmax_hit, nrec = float(buf[3]), int(buf[4]), bool(buf[5]), int(buf[6])
+    cells = buf[8:8 + 4 * m].reshape(m, 4)
+    it = buf[8 + 4 * m:8 + 4 * m + nrec * (2 * m + 1)].reshape(nrec, 2 * m + 1)
+    return {"m": m, "tiny": tiny, "ic": ic, "dt": dt, "count": count, "lmax": lmax_hit,
+            "theta": cells[:, 0].copy(), "hn": cells[:, 1].copy(), "hh": cells[:, 2].copy(),
+            "mov": cells[:, 3].copy(), "W": it[:, :2 * m].reshape(nrec, m, 2).copy(),
+            "w": it[:, 2 * m].copy()}
 
 
 # objective of the adjoint: cx * sum of interface positions + mass in [wa, wb]

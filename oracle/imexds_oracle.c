@@ -48,6 +48,26 @@
  * run (pseudo-iteration counts, merges, crossings, CFL cell) and then
  * repeats them instead of testing; central finite differences of the loss
  * with decisions frozen use it.
+ *
+ * Plain-arithmetic build (-DOR_PLAIN, C only).  The default build fixes the
+ * rounding of every operation: its own fixed-order logarithm, reciprocals
+ * multiplied in, the stop test of Sec. 4 evaluated without its division, a
+ * squared merit in the Armijo test and a shortcut after a small full Newton
+ * step.  Compiled with OR_PLAIN the same source instead uses the C library's
+ * log and writes every formula as the paper prints it: divisions by a^2,
+ * rho_sat, det and h^{n,l+1}, the pressure-form shock wave
+ * sqrt((p* - p_K)(1/rho_K - 1/rho*)), the rarefaction a ln(rho* / rho_K), the
+ * update of Sec. 3.4 with its ratios h^n/h^{n,l+1} and dt/h^{n,l+1}, the
+ * residual res_i with its division by dtau_i max(|U|,1), Kelley's Armijo test
+ * on the unsquared merit, and Newton run until its step is below rtol.  It is
+ * the check that the default build's rounding choices change nothing beyond
+ * round-off (tests run both, the plain one with the default one's decisions
+ * replayed).
+ *
+ * Trace.  oracle_run_trace records, for one interface of one problem at one
+ * step, the zone's pseudo-step fractions and every dual time iterate W^l
+ * with the phase-boundary speed used to advance it, so that tests can
+ * evaluate the paper's residual on them independently.
  */
 #include <math.h>
 #include <stdint.h>
@@ -119,7 +139,11 @@ static real or_pres(const or_material *M, int ph, real rho) {
 
 /* inverse pressure law (used inside the interface solve), reciprocal form */
 static real or_rho_of_p(const or_material *M, int ph, real p) {
+#ifdef OR_PLAIN
+  return ph == OR_VAP ? p / M->a2v : M->rhol0 + (p - M->p0) / M->a2l;
+#else
   return ph == OR_VAP ? p * (1.0 / M->a2v) : M->rhol0 + (p - M->p0) * (1.0 / M->a2l);
+#endif
 }
 
 /* Natural logarithm of a positive finite double.  Argument reduction
@@ -165,8 +189,10 @@ OR_API double oracle_log(double x) {
   return de * 0x1.62e42feep-1 + (de * 0x1.a39ef35793c76p-33 + r);
 }
 
-#ifdef OR_TANGENT
+#if defined(OR_TANGENT)
 static real or_log(real x) { return or_dual(oracle_log(x.v), x.d / x.v); }
+#elif defined(OR_PLAIN)
+static real or_log(real x) { return log(x); }
 #else
 static real or_log(real x) { return oracle_log(x); }
 #endif
@@ -236,6 +262,7 @@ typedef struct {
   int ph;
   real r, u, p, LK;
   real a, a2, ia, ia2, hia, irs;
+  real rsat; /* saturation density of the side's phase */
 } or_side;
 
 static void or_side_init(const or_material *M, int ph, real r, real m, or_side *S) {
@@ -248,8 +275,13 @@ static void or_side_init(const or_material *M, int ph, real r, real m, or_side *
   S->ia = 1.0 / S->a;
   S->ia2 = 1.0 / S->a2;
   S->hia = 0.5 * S->ia;
-  S->irs = ph == OR_VAP ? 1.0 / (M->p0 / M->a2v) : 1.0 / M->rhol0;
+  S->rsat = ph == OR_VAP ? M->p0 / M->a2v : M->rhol0;
+  S->irs = 1.0 / S->rsat;
+#ifdef OR_PLAIN
+  S->LK = or_log(r / S->rsat);
+#else
   S->LK = or_log(r * S->irs);
+#endif
 }
 
 typedef struct {
@@ -264,6 +296,25 @@ static int or_wave(const or_material *M, const or_side *S, real ps, or_seval *E)
   real r = or_rho_of_p(M, S->ph, ps);
   if (!(r > 0.0) || !isfinite(r)) return 0;
   real v = 1.0 / r;
+#ifdef OR_PLAIN
+  /* as printed: shock sqrt(-[[p]][[v]]) = sqrt((p_s - p_K)(v_K - v_s)), whose
+   * derivative is ((v_K - v_s) + (p_s - p_K) v_s^2 / a^2) / (2 f) (v_s falls
+   * as p_s grows: dv_s / dp_s = -v_s^2 / a^2), continued by its limit
+   * v_s / a at f = 0; rarefaction: the integral of v/a over the pressure,
+   * a ln(rho_s / rho_K) */
+  E->rs = r;
+  E->v = v;
+  E->g = S->a2 * or_log(r / S->rsat);
+  if (ps > S->p) {
+    real dv = 1.0 / S->r - v;
+    E->f = sqrt((ps - S->p) * dv);
+    E->df = E->f > 0.0 ? (dv + (ps - S->p) * (v * v / S->a2)) / (2.0 * E->f) : v / S->a;
+  } else {
+    E->f = S->a * or_log(r / S->r);
+    E->df = v / S->a;
+  }
+  return 1;
+#else
   real L = or_log(r * S->irs);
   E->rs = r;
   E->v = v;
@@ -277,12 +328,14 @@ static int or_wave(const or_material *M, const or_side *S, real ps, or_seval *E)
     E->df = v * S->ia;
   }
   return 1;
+#endif
 }
 
 typedef struct {
   int phl, phr;
   or_side L, R;
   real izref; /* 1 / max(rho_l a_l, rho_r a_r) */
+  real zref;  /* max(rho_l a_l, rho_r a_r) */
 } or_rp;
 
 typedef struct {
@@ -311,6 +364,37 @@ static int or_eval_G(const or_material *M, const or_rp *R, real psl, real psr, o
   real sD = sqrt(D);
   real isD = 1.0 / sD;
   real z = 2.0 * C / (1.0 + sD);
+#ifdef OR_PLAIN
+  {
+    /* derivatives as printed in eq. jacobian:ex_sys, (v* / a*)^2 with its
+     * division; dz/dp = (dA/dp z^2 + dC/dp) / sqrt(D) */
+    real a2l = R->L.a2, a2r = R->R.a2;
+    real dAl = q * (vl * vl * vl / a2l), dAr = -(q * (vr * vr * vr / a2r));
+    real dCl = -(q * vl), dCr = q * vr;
+    if (R->phl == OR_VAP) {
+      dAl += M->tau * jv2 / 2.0;
+      dCl += M->tau * jg;
+    } else {
+      dAr += M->tau * jv2 / 2.0;
+      dCr += M->tau * jg;
+    }
+    real dzl = (dAl * z * z + dCl) / sD, dzr = (dAr * z * z + dCr) / sD;
+    real jv = vr - vl;
+    real el = (vl / R->L.a) * (vl / R->L.a), er = (vr / R->R.a) * (vr / R->R.a);
+    E->z = z;
+    E->G1 = (psr - psl) + z * z * jv;
+    E->G2 = (E->l.f + E->r.f) + z * jv + (R->R.u - R->L.u);
+    E->J11 = -1.0 + 2.0 * z * dzl * jv + z * z * el;
+    E->J12 = 1.0 + 2.0 * z * dzr * jv - z * z * er;
+    E->J21 = E->l.df + dzl * jv + z * el;
+    E->J22 = E->r.df + dzr * jv - z * er;
+    if (!isfinite(E->G1) || !isfinite(E->G2)) return 0;
+    real g1 = E->G1 / R->zref;
+    E->m2 = sqrt(g1 * g1 + E->G2 * E->G2); /* unsquared merit */
+    (void)isD;
+    return 1;
+  }
+#endif
   /* d(v^2)/dp = -2 v^3 / a^2, dg/dp = v */
   real dAl = q * ((vl * vl * vl) * R->L.ia2);
   real dAr = -(q * ((vr * vr * vr) * R->R.ia2));
@@ -385,9 +469,14 @@ static int or_newton(const or_material *M, const or_rp *R, real xl, real xr, int
   for (it = 0; it < maxit; ++it) {
     real det = E.J11 * E.J22 - E.J12 * E.J21;
     if (!(det != 0.0) || !isfinite(det)) return 0;
+#ifdef OR_PLAIN
+    real dl = (-E.G1 * E.J22 + E.G2 * E.J12) / det;
+    real dr = (-E.G2 * E.J11 + E.G1 * E.J21) / det;
+#else
     real idet = 1.0 / det;
     real dl = (-E.G1 * E.J22 + E.G2 * E.J12) * idet;
     real dr = (-E.G2 * E.J11 + E.G1 * E.J21) * idet;
+#endif
     real sc = fabs(xl) > fabs(xr) ? fabs(xl) : fabs(xr);
     if (M->p0 > sc) sc = M->p0;
     real st = fabs(dl) > fabs(dr) ? fabs(dl) : fabs(dr);
@@ -410,7 +499,11 @@ static int or_newton(const or_material *M, const or_rp *R, real xl, real xr, int
     for (k = 0; k <= 20; ++k) {
       real tl = xl + lam * dl, tr = xr + lam * dr;
       real c = 1.0 - 1e-4 * lam;
+#ifdef OR_PLAIN
+      if (or_eval_G(M, R, tl, tr, &Et) && Et.m2 <= c * E.m2) {
+#else
       if (or_eval_G(M, R, tl, tr, &Et) && Et.m2 <= (c * c) * E.m2) {
+#endif
         xl = tl;
         xr = tr;
         E = Et;
@@ -429,7 +522,12 @@ static int or_newton(const or_material *M, const or_rp *R, real xl, real xr, int
       }
       return 0;
     }
+#ifdef OR_PLAIN
+    (void)qtol;
+    if (0) {
+#else
     if (k == 0 && st <= qtol * sc) {
+#endif
       *ol = xl;
       *orr = xr;
       *Eo = E;
@@ -454,7 +552,8 @@ static int or_iface_solve(const or_material *M, int phl, real rl, real ml, int p
   or_side_init(M, phl, rl, ml, &R.L);
   or_side_init(M, phr, rr, mr, &R.R);
   real zl = rl * R.L.a, zr = rr * R.R.a;
-  R.izref = 1.0 / (zl > zr ? zl : zr);
+  R.zref = zl > zr ? zl : zr;
+  R.izref = 1.0 / R.zref;
   real xl = 0.0, xr = 0.0;
   or_geval E;
   int iters = 0, conv = 0, attempt;
@@ -518,7 +617,8 @@ int oracle_iface_G(const or_material *M, int phl, real rl, real ml, int phr, rea
   or_side_init(M, phl, rl, ml, &R.L);
   or_side_init(M, phr, rr, mr, &R.R);
   real zl = rl * R.L.a, zr = rr * R.R.a;
-  R.izref = 1.0 / (zl > zr ? zl : zr);
+  R.zref = zl > zr ? zl : zr;
+  R.izref = 1.0 / R.zref;
   if (!or_eval_G(M, &R, psl, psr, &E)) return 0;
   out6[0] = E.G1;
   out6[1] = E.G2;
@@ -810,7 +910,27 @@ typedef struct {
   const int *rp_count; /* [nif] pseudo-iteration counts */
   const int *rp_flags; /* [nif] event flags (merge, crossings) */
   int rp_cfl;          /* slot whose |u| + a set the time step (-1: take the max) */
+  /* trace of one zone's dual time iterates (NULL: none) */
+  struct or_trace *tr; /* where to record */
+  int tr_k;            /* which interface */
+  int tr_on;           /* set for the step to record */
 } or_prob;
+
+/* Trace record of one zone solve (oracle_run_trace): a header of 8 doubles
+ * (m, tiny cell, cell left of the phase boundary, dt, count, lmax hit,
+ * records, 0), per active cell (theta, h^n, predicted h^{n+1}, mov), then
+ * for l = 0 .. count the iterate W^l (m x 2) and the phase-boundary speed of
+ * the interface solve on W^l (the one that moves the lengths of W^{l+1}, or
+ * of Part 2 for l = count).  A redo after a collapse restarts the record. */
+typedef struct or_trace {
+  double *buf;
+  int cap, len;
+} or_trace;
+
+static void or_tr_put(or_trace *t, double x) {
+  if (t && t->len < t->cap) t->buf[t->len] = x;
+  if (t) t->len++;
+}
 
 typedef struct {
   int m;
@@ -978,7 +1098,7 @@ static int or_state_ok(real r, real m) { return r > 0.0 && isfinite(r) && isfini
  * the others); in relative mode |W^{l+1} - W^l| < tol_rel max(|W^l|, 1). */
 static int or_zone_dts(const or_material *M, const or_params *P, const or_zone *Z, real dt,
                        real *pw, real U1[][2], real *wstar, int *count, int *lmax_hit,
-                       int *shrink_cell, int force_count) {
+                       int *shrink_cell, int force_count, or_trace *tr) {
   real W[OR_MAXC][2], Wn[OR_MAXC][2], F[OR_MAXC + 1][2], hnew[OR_MAXC], ih[OR_MAXC];
   int c, l, m = Z->m;
   real w = 0.0;
@@ -988,11 +1108,45 @@ static int or_zone_dts(const or_material *M, const or_params *P, const or_zone *
     W[c][0] = Z->U0[c][0];
     W[c][1] = Z->U0[c][1];
   }
+#ifdef OR_TANGENT
+  (void)tr;
+#define OR_TRACE_ITER()
+#else
+  if (tr) {
+    tr->len = 0;
+    or_tr_put(tr, m);
+    or_tr_put(tr, Z->tiny);
+    or_tr_put(tr, Z->ic);
+    or_tr_put(tr, dt);
+    or_tr_put(tr, 0.0);
+    or_tr_put(tr, 0.0);
+    or_tr_put(tr, 0.0);
+    or_tr_put(tr, 0.0);
+    for (c = 0; c < m; ++c) {
+      or_tr_put(tr, Z->th[c]);
+      or_tr_put(tr, Z->hn[c]);
+      or_tr_put(tr, Z->hh[c]);
+      or_tr_put(tr, Z->mov[c]);
+    }
+  }
+#define OR_TRACE_ITER()                      \
+  do {                                       \
+    if (tr) {                                \
+      int c_;                                \
+      for (c_ = 0; c_ < m; ++c_) {           \
+        or_tr_put(tr, W[c_][0]);             \
+        or_tr_put(tr, W[c_][1]);             \
+      }                                      \
+      or_tr_put(tr, w);                      \
+    }                                        \
+  } while (0)
+#endif
   int cnt = 0, stop = 0;
   /* Part 1: pseudo-time iterations (exactly force_count of them in a replay) */
   int lmax = force_count > 0 ? force_count : P->lmax;
   for (l = 0; l < lmax; ++l) {
     if (!or_zone_fluxes(M, P, Z, W, F, pw, &w)) return OR_ST_NEWTON;
+    OR_TRACE_ITER();
     for (c = 0; c < m; ++c) {
       hnew[c] = Z->hn[c] + ((double)Z->mov[c] * w) * dt;
       ih[c] = 1.0 / hnew[c];
@@ -1006,11 +1160,26 @@ static int or_zone_dts(const or_material *M, const or_params *P, const or_zone *
       real th = Z->th[c], opt = 1.0 + th;
       int q;
       for (q = 0; q < 2; ++q) {
+#ifdef OR_PLAIN
+        /* Algorithm 2 update with the moving lengths of Sec. 3.4, as printed:
+         * W^{l+1} = W^l/(1+r) + r/(1+r) ((h^n/h^{n,l+1}) U^n
+         *           - (dt/h^{n,l+1}) (F_{i+1/2} - F_{i-1/2})),  r = dtau/dt = theta;
+         * residual res_i = |(1 + dtau/dt)(W^{l+1} - W^l)| / (dtau max(|W^l|,1)) */
+        real dtau = th * dt;
+        real rhs = (Z->hn[c] / hnew[c]) * Z->U0[c][q] - (dt / hnew[c]) * (F[c + 1][q] - F[c][q]);
+        Wn[c][q] = W[c][q] / (1.0 + th) + (th / (1.0 + th)) * rhs;
+        real d = Wn[c][q] - W[c][q];
+        real sc = fabs(W[c][q]) > 1.0 ? fabs(W[c][q]) : 1.0;
+        real tol = c == Z->tiny ? P->tol_tiny : P->tol_nb;
+        int ok = (P->tol_mode == 0) ? (fabs(opt * d) / (dtau * sc) < tol)
+                                    : (fabs(d) < P->tol_rel * sc);
+#else
         real rhs = (Z->hn[c] * Z->U0[c][q] - dt * (F[c + 1][q] - F[c][q])) * ih[c];
         Wn[c][q] = (W[c][q] + th * rhs) * Z->i1t[c];
         real d = Wn[c][q] - W[c][q];
         real sc = fabs(W[c][q]) > 1.0 ? fabs(W[c][q]) : 1.0;
         int ok = (P->tol_mode == 0) ? (fabs(opt * d) < Z->thr[c] * sc) : (fabs(d) < P->tol_rel * sc);
+#endif
         conv = conv && ok;
       }
       if (!or_state_ok(Wn[c][0], Wn[c][1])) return OR_ST_NONPHYS;
@@ -1027,6 +1196,15 @@ static int or_zone_dts(const or_material *M, const or_params *P, const or_zone *
   *count = cnt;
   /* Part 2: fluxes from the accepted iterate, conservative update */
   if (!or_zone_fluxes(M, P, Z, W, F, pw, &w)) return OR_ST_NEWTON;
+  OR_TRACE_ITER();
+#ifndef OR_TANGENT
+  if (tr && tr->cap >= 8) {
+    tr->buf[4] = cnt;
+    tr->buf[5] = !stop;
+    tr->buf[6] = cnt + 1;
+  }
+#endif
+#undef OR_TRACE_ITER
   for (c = 0; c < m; ++c) {
     hnew[c] = Z->hn[c] + ((double)Z->mov[c] * w) * dt;
     ih[c] = 1.0 / hnew[c];
@@ -1038,7 +1216,11 @@ static int or_zone_dts(const or_material *M, const or_params *P, const or_zone *
   for (c = 0; c < m; ++c) {
     int q;
     for (q = 0; q < 2; ++q)
+#ifdef OR_PLAIN
+      U1[c][q] = (Z->hn[c] / hnew[c]) * Z->U0[c][q] - (dt / hnew[c]) * (F[c + 1][q] - F[c][q]);
+#else
       U1[c][q] = (Z->hn[c] * Z->U0[c][q] - dt * (F[c + 1][q] - F[c][q])) * ih[c];
+#endif
     if (!or_state_ok(U1[c][0], U1[c][1])) return OR_ST_NONPHYS;
   }
   *wstar = w;
@@ -1272,9 +1454,10 @@ static int or_zone_step(const or_material *M, const or_params *P, or_prob *pb, i
 #ifndef OR_TANGENT
     int st = P->zone_solver == 1
                  ? or_zone_newton(M, P, &Z, dt, pw, U1, &wstar, &count, &lmax_hit, &sc)
-                 : or_zone_dts(M, P, &Z, dt, pw, U1, &wstar, &count, &lmax_hit, &sc, force);
+                 : or_zone_dts(M, P, &Z, dt, pw, U1, &wstar, &count, &lmax_hit, &sc, force,
+                               (pb->tr_on && k == pb->tr_k) ? pb->tr : NULL);
 #else
-    int st = or_zone_dts(M, P, &Z, dt, pw, U1, &wstar, &count, &lmax_hit, &sc, force);
+    int st = or_zone_dts(M, P, &Z, dt, pw, U1, &wstar, &count, &lmax_hit, &sc, force, NULL);
 #endif
     if (st == OR_ST_MESH && !merge && sc == Z.tiny) {
       merge = 1;
@@ -1472,7 +1655,7 @@ static real or_objective(const or_prob *pb, double x_left, double cx, double wa,
 static void or_run_problem(const or_material *M, const or_params *Pp, or_prob *pb, int n_steps,
                            int nif_tot, int k0, int P, int p, int *log_count, int *log_flags,
                            int *log_zlo, int *log_cfl, const int *rp_count, const int *rp_flags,
-                           const int *rp_cfl) {
+                           const int *rp_cfl, int tr_step) {
   int ns = pb->n + pb->nif;
   int *ph = (int *)malloc(sizeof(int) * ns);
   int *zm = (int *)malloc(sizeof(int) * ns);
@@ -1486,6 +1669,7 @@ static void or_run_problem(const or_material *M, const or_params *Pp, or_prob *p
     pb->rp_count = rp_count ? rp_count + (size_t)n * nif_tot + k0 : NULL;
     pb->rp_flags = rp_count ? rp_flags + (size_t)n * nif_tot + k0 : NULL;
     pb->rp_cfl = rp_cfl ? rp_cfl[(size_t)n * P + p] : -1;
+    pb->tr_on = pb->tr != NULL && n == tr_step;
     or_step(M, Pp, pb, ph, F, rn, mn, zm, lg, &cs);
     if (log_count) {
       for (k = 0; k < pb->nif; ++k) {
@@ -1511,18 +1695,24 @@ static void or_run_problem(const or_material *M, const or_params *Pp, or_prob *p
  * arrays with iface_off[P+1].  Logs (optional) are [n_steps][n_iface]
  * (counts, flags, zone start) and [n_steps][P] (CFL slot); rp_* (optional)
  * replay a previous run's logs. */
-int oracle_run(const or_material *M, const or_params *Pp, int P, const int *n_cells,
-               const double *h, const int *phase_first, const int *iface_off,
-               const long long *slot_off, int *home, double *hl, double *pw, int *warm,
-               double *rho, double *mom, double *t, int *status, long long *steps, int n_steps,
-               int *log_count, int *log_flags, int *log_zlo, int *log_cfl, const int *rp_count,
-               const int *rp_flags, const int *rp_cfl, int n_threads) {
+static int or_run_batch(const or_material *M, const or_params *Pp, int P, const int *n_cells,
+                        const double *h, const int *phase_first, const int *iface_off,
+                        const long long *slot_off, int *home, double *hl, double *pw, int *warm,
+                        double *rho, double *mom, double *t, int *status, long long *steps,
+                        int n_steps, int *log_count, int *log_flags, int *log_zlo, int *log_cfl,
+                        const int *rp_count, const int *rp_flags, const int *rp_cfl,
+                        int n_threads, int tr_p, int tr_step, int tr_k, or_trace *tr) {
   int nif_tot = iface_off[P];
   int p;
   if (Pp->zone_half < 1 || 2 * Pp->zone_half + 1 > OR_MAXC) return -1;
 #pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads > 0 ? n_threads : 1)
   for (p = 0; p < P; ++p) {
     or_prob pb;
+    memset(&pb, 0, sizeof(pb));
+    if (p == tr_p) {
+      pb.tr = tr;
+      pb.tr_k = tr_k;
+    }
     int k0 = iface_off[p];
     pb.n = n_cells[p];
     pb.nif = iface_off[p + 1] - k0;
@@ -1538,9 +1728,39 @@ int oracle_run(const or_material *M, const or_params *Pp, int P, const int *n_ce
     pb.status = status + p;
     pb.steps = steps + p;
     or_run_problem(M, Pp, &pb, n_steps, nif_tot, k0, P, p, log_count, log_flags, log_zlo,
-                   log_cfl, rp_count, rp_flags, rp_cfl);
+                   log_cfl, rp_count, rp_flags, rp_cfl, tr_step);
   }
   return 0;
+}
+
+int oracle_run(const or_material *M, const or_params *Pp, int P, const int *n_cells,
+               const double *h, const int *phase_first, const int *iface_off,
+               const long long *slot_off, int *home, double *hl, double *pw, int *warm,
+               double *rho, double *mom, double *t, int *status, long long *steps, int n_steps,
+               int *log_count, int *log_flags, int *log_zlo, int *log_cfl, const int *rp_count,
+               const int *rp_flags, const int *rp_cfl, int n_threads) {
+  return or_run_batch(M, Pp, P, n_cells, h, phase_first, iface_off, slot_off, home, hl, pw, warm,
+                      rho, mom, t, status, steps, n_steps, log_count, log_flags, log_zlo, log_cfl,
+                      rp_count, rp_flags, rp_cfl, n_threads, -1, -1, -1, NULL);
+}
+
+/* As oracle_run, and records the dual time iterates of interface tr_k
+ * (local to problem tr_p) at step tr_step of this call (layout: or_trace)
+ * into buf[cap]; *len receives the record's length (larger than cap if it
+ * did not fit; 0 if that zone was not solved at that step). */
+int oracle_run_trace(const or_material *M, const or_params *Pp, int P, const int *n_cells,
+                     const double *h, const int *phase_first, const int *iface_off,
+                     const long long *slot_off, int *home, double *hl, double *pw, int *warm,
+                     double *rho, double *mom, double *t, int *status, long long *steps,
+                     int n_steps, int *log_count, int *log_flags, int *log_zlo, int *log_cfl,
+                     const int *rp_count, const int *rp_flags, const int *rp_cfl, int n_threads,
+                     int tr_p, int tr_step, int tr_k, double *buf, int cap, int *len) {
+  or_trace tr = {buf, cap, 0};
+  int rc = or_run_batch(M, Pp, P, n_cells, h, phase_first, iface_off, slot_off, home, hl, pw,
+                        warm, rho, mom, t, status, steps, n_steps, log_count, log_flags, log_zlo,
+                        log_cfl, rp_count, rp_flags, rp_cfl, n_threads, tr_p, tr_step, tr_k, &tr);
+  *len = tr.len;
+  return rc;
 }
 
 /* objective (see or_objective) of every problem at the given state */
@@ -1610,8 +1830,11 @@ OR_API int oracle_tan_run(const double *mat, const double *dmat, const or_params
     pb.t = tp;
     pb.status = status + p;
     pb.steps = steps + p;
+    pb.tr = NULL;
+    pb.tr_k = -1;
+    pb.tr_on = 0;
     or_run_problem(&Md, Pp, &pb, n_steps, nif_tot, k0, P, p, NULL, NULL, NULL, NULL, NULL, NULL,
-                   NULL);
+                   NULL, -1);
     real L = or_objective(&pb, x_left[p], cx, wa, wb);
     obj[p] = L.v;
     dobj[p] = L.d;
@@ -1704,6 +1927,7 @@ int oracle_zone_fixed_point(const or_material *M, const or_params *Pp, int n_cel
   double t = 0.0;
   int status = 0;
   long long steps = 0;
+  memset(&pb, 0, sizeof(pb));
   pb.n = n_cells;
   pb.nif = nif;
   pb.h = h;
