@@ -8,9 +8,12 @@ seeded synthetic problems resident in HBM before timing starts.
 
 Prints one JSON line with the FP64 cell-update rate of the batched launch
 (HIP-graph replays), the per-problem launch form on the same state for
-comparison, the bulk kernel's HBM roofline fraction (HIP events around each
-bulk launch), and the CPU oracle timed on a bounded sample of the same
-problems (whose results are also compared with the GPU's).
+comparison, the HBM roofline fraction of the step as bounded by the zone
+kernel (the step's 32 B per cell update over the zone kernel's own launch
+duration, HIP events around each zone launch), the bulk kernel's roofline
+(HIP events around each bulk launch), and the CPU oracle timed on a bounded
+sample of the same problems (whose results are also compared with the
+GPU's).
 """
 import argparse
 import dataclasses
@@ -135,6 +138,31 @@ def slot_lengths(b, home, hl):
     return out
 
 
+def host_info():
+    """The host the oracle baseline runs on: logical CPUs, the ones this
+    process may use, and the CPU model (lscpu / /proc/cpuinfo)."""
+    model = None
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except Exception:
+        pass
+    if model is None and os.path.exists("/proc/cpuinfo"):
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except Exception:
+        usable = None
+    return {"nproc": os.cpu_count(), "usable_cpus": usable, "cpu_model": model}
+
+
 def cpu_baseline_leg(b, P, material, steps, gpu_rho, gpu_mom, gpu_home, gpu_hl, seconds):
     """Times the CPU oracle on chunks of the same problems for the same number
     of steps until about `seconds` of wall time, and compares its results with
@@ -173,6 +201,7 @@ def cpu_baseline_leg(b, P, material, steps, gpu_rho, gpu_mom, gpu_home, gpu_hl, 
     return {"value": cu / wall, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(done)} of {b.n_problems} problems ({int(np.sum(np.diff(b.slot_off)[done]))} slots) "
                       f"x {steps} steps, OpenMP over problems, {wall:.1f} s",
+            "host": host_info(),
             "parity_max_rel_l1": worst}
 
 
@@ -643,7 +672,8 @@ def main():
         tc, zp, zg, zn, ms = s.autotune(10)
         tune = {"tile_cells": tc, "zones_per_group": zp, "zone_groups": zg, "zone_lanes": zn,
                 "ms_per_step": ms}
-    s.set_launch(tune["tile_cells"], tune["zones_per_group"], tune["zone_groups"], 10,
+    graph_steps = 10
+    s.set_launch(tune["tile_cells"], tune["zones_per_group"], tune["zone_groups"], graph_steps,
                  tune["zone_lanes"])
 
     # warm-up on the initial state, then reload it so the timed steps are the first K steps
@@ -668,19 +698,30 @@ def main():
     g_home, g_hl, _ = s.interfaces()
     _, g_status, g_steps = s.problems()
 
-    # bulk-kernel roofline: same state, each bulk launch alone between two
-    # HIP events on its stream (zones follow it instead of overlapping it)
+    # kernel rooflines: the same K steps from the initial state again, each
+    # bulk launch and each zone launch alone between two HIP events on the
+    # main stream (the zones follow the sweep instead of overlapping it)
     NIF = b.n_iface
     zone_slots = int(round(NIF * (2 * P.zone_half + 1)))
     bulk_bytes = BYTES_PER_CELL_UPDATE * (b.n_slots - zone_slots)
-    bulk_ms = achieved = None
+    step_bytes = cell_updates / args.steps * BYTES_PER_CELL_UPDATE
+    bulk_ms = achieved = zone_ms = zone_achieved = None
+    zone_kernel = "k_zone8" if tune["zone_lanes"] == 8 else "k_zone"
+    if args.roofline_steps > 0:
+        s.set_state(rho0, mom0)
+        s.time_bulk(True)
+        s.step(args.steps)
+        torch.cuda.synchronize()
+        _, zone_ms, n_timed = s.kernel_timing()
+        s.time_bulk(False)
+        zone_achieved = step_bytes / (zone_ms * 1e-3) / 1e9
     # a plain copy moving the same bytes per launch (read + write), the
     # practical ceiling at this transfer size
     copy_same_gbs = (measure_copy_bandwidth(mib=max(1, int(round(bulk_bytes / 2 / (1 << 20)))))
                      if args.copy_bw else None)
     roof_tile = 1024  # the bulk sweep's own best tile class (the step's may differ)
     if args.roofline_steps > 0:
-        s.set_launch(roof_tile, tune["zones_per_group"], tune["zone_groups"], 10,
+        s.set_launch(roof_tile, tune["zones_per_group"], tune["zone_groups"], graph_steps,
                      tune["zone_lanes"])
         s.time_bulk(True)
         s.step(args.roofline_steps)
@@ -752,13 +793,28 @@ def main():
         "dtype": "f64",
         "data": "synthetic (seeded), inputs resident in HBM",
         "config": {"workload": desc, "problems": b.n_problems, "slots": b.n_slots,
-                   "interfaces": b.n_iface, "launch": "hipGraph replay, 10 steps per graph",
+                   "interfaces": b.n_iface,
+                   "launch": f"hipGraph replay, {graph_steps} steps per graph",
                    "launch_tuning": tune},
         "wall_s": wall,
         "failed_problems": int(np.sum(g_status != 0)),
         "pseudo_iters_per_zone_step": (st1["pseudo_iters"] - st0["pseudo_iters"]) / max(1, NIF * args.steps),
         "per_problem": pp,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "roofline": {"bound": "hbm", "kernel": zone_kernel, "achieved": zone_achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (zone_achieved / HBM_PEAK_GBS) if zone_achieved else None,
+                     "traffic": None,
+                     "zone_ms_per_launch": zone_ms,
+                     "zone_launches_timed": args.steps if zone_ms else 0,
+                     "algorithmic_bytes_per_launch": step_bytes,
+                     "note": "the step's algorithmic bytes (32 B per cell update: rho, rho u "
+                             "read and written, every slot) over the duration of the zone "
+                             "kernel, the step's longest kernel (launched alone, HIP events on "
+                             "its stream, same steps as the headline).  The zone kernel itself "
+                             "moves about 0.2 KB per zone: it is bound by its dependent FP64 "
+                             "chain (dual time iterations of the slowest zone), not by HBM; "
+                             "traffic is not reported for it"},
+        "bulk_roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                      "traffic": measured_traffic(args.workload, roof_tile),
                      "tile_cells": roof_tile,

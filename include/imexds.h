@@ -67,9 +67,16 @@ extern "C" {
 #define IMEXDS_FL_FAIL 64      /* the zone failed this step (status set) */
 #define IMEXDS_FL_INACTIVE 128 /* problem frozen or finished: nothing done */
 
-/* dual-time stopping rules */
-#define IMEXDS_TOL_PAPER 0 /* Sec. 4: max(res_{k-1},res_{k+1}) < tol_nb and res_k < tol_tiny */
-#define IMEXDS_TOL_REL 1   /* max |W^{l+1}-W^l| / max(|W^l|,1) < tol_rel over the zone */
+/* dual-time stopping rules (Algorithm 2, "Stopping criterium"):
+ * IMEXDS_TOL_PAPER: the residual of Sec. 4 (Numerical results),
+ *   res_i = |(1 + dtau_i/dt)(W_i^{l+1} - W_i^l)| / (dtau_i max(|W_i^l|, 1)),
+ *   dtau_i = theta_i dt, largest over the two components, must be below
+ *   tol_tiny on the tiny cell and below tol_nb on every other cell of the
+ *   (2Z+1)-cell zone (the paper's k-1, k+1 for Z = 1; the zone's outer cells
+ *   too for Z > 1);
+ * IMEXDS_TOL_REL: max |W^{l+1}-W^l| / max(|W^l|,1) < tol_rel over the zone. */
+#define IMEXDS_TOL_PAPER 0
+#define IMEXDS_TOL_REL 1
 
 #define IMEXDS_BC_WALL 0
 #define IMEXDS_BC_TRANSMISSIVE 1
@@ -125,18 +132,31 @@ typedef struct {
   const double *hl;         /* [n_iface] */
 } imexds_batch;
 
+/* Counters since the last imexds_set_state (imexds_get_stats). */
 typedef struct {
   int64_t steps;          /* physical steps completed, summed over problems */
   int64_t cell_updates;   /* sum over problems of slots x steps completed */
-  int64_t pseudo_iters;   /* dual-time iterations, summed over zones and steps */
-  int64_t merges;         /* merge events */
+  int64_t pseudo_iters;   /* dual-time iterations (Algorithm 2, Part 1), summed over
+                             zones and steps; Newton steps with IMEXDS_ZONE_NEWTON */
+  int64_t merges;         /* merges of vanishing cut pieces (Sec. 3.4) */
   int64_t lmax_hits;      /* zone steps that stopped at lmax */
   int32_t n_failed;       /* problems with a nonzero status */
   int32_t n_active;       /* problems still advancing (status 0, t < t_end) */
+  int64_t newton_iters;   /* evaluations of G (Appendix A, eq. "2p_RP:ex_sys") in the
+                             interface Newton-Armijo solves: Newton steps and Armijo
+                             trials (dual time zone solver; 0 with IMEXDS_ZONE_NEWTON) */
+  int64_t iface_solves;   /* interface solves those evaluations belong to */
+  int64_t events;         /* mesh events: merges, redone zone solves, interfaces
+                             moved into a neighbouring background cell */
+  double gpu_ms;          /* device time of the imexds_step / imexds_run /
+                             imexds_step_per_problem calls (HIP events) */
 } imexds_stats;
 
-/* Creates a context on the current HIP device for the given material,
- * parameters and batch layout.  Validates the inputs (IMEXDS_ERR_INVALID_ARG
+/* Creates a context on the current HIP device for the problem statement of
+ * Sec. 2 (Problem Formulation): the phase pressure laws and kinetic
+ * coefficient of Sec. 4 (eqs. "eos:isoT_idgas", "eos:isoT_lintait",
+ * "isoT:kin_rel1"), the grid-aligned interfaces of Sec. 2.3 and the
+ * parameters of Algorithms 1 and 2.  Validates the inputs (IMEXDS_ERR_INVALID_ARG
  * on bad sizes, interfaces outside their problem or out of order, more than
  * 64 interfaces in a problem, parameters out of range), allocates the device
  * buffers
@@ -146,50 +166,65 @@ typedef struct {
 int imexds_create(imexds_ctx **out, const imexds_material *mat, const imexds_params *par,
                   const imexds_batch *batch, void *hip_stream);
 
-/* Loads the cell averages (rho, rho u) of every slot (device pointers,
- * n_slots doubles each, flat layout above), resets t = 0, statuses, step
- * counts, interface positions (to the batch's home/hl), Newton warm starts
- * and statistics, and computes the first time step (CFL over all slots). */
+/* Loads the cell averages U = (rho, rho u) of the isothermal Euler system
+ * (Sec. 2.1) of every slot (device pointers, n_slots doubles each, flat
+ * layout above; read before the call returns, not kept), resets t = 0,
+ * statuses, step counts, interface positions (to the batch's home/hl),
+ * Newton warm starts and statistics, and computes the first time step
+ * dt = C h / max(|u| + a) over all slots (eq. "cfl_cond:unif"). */
 int imexds_set_state(imexds_ctx *ctx, const double *rho, const double *mom);
 
-/* Enqueues n_steps physical steps of every problem (async).  Problems that
- * reached t_end or failed are left unchanged. */
+/* Enqueues n_steps physical steps of every problem (async): each is
+ * Algorithm 1 (explicit update of the bulk, eq. "update expl time") with
+ * Algorithm 2 on every implicit zone (eq. "dual time tau diff", Part 2 with
+ * the moving lengths of eq. "godunov_meth:nonunif"), then the next CFL time
+ * step.  Problems that reached t_end or failed are left unchanged. */
 int imexds_step(imexds_ctx *ctx, int32_t n_steps);
 
-/* Steps until every problem has t >= t_end or is frozen, or max_steps steps
- * were enqueued; checks progress every check_every steps (synchronizes).
+/* The steps of imexds_step (Algorithm 1) until every problem has t >= t_end
+ * or is frozen, or max_steps steps were enqueued; checks progress every
+ * check_every steps (synchronizes).
  * *steps_done (host, may be NULL) receives the number of steps enqueued. */
 int imexds_run(imexds_ctx *ctx, int32_t max_steps, int32_t check_every, int32_t *steps_done);
 
-/* Baseline launch form: the same kernels, launched problem by problem on the
- * context's stream (n_steps steps of every problem, async). */
+/* Baseline launch form of the steps of imexds_step (Algorithm 1): the same
+ * kernels, launched problem by problem on the context's stream (n_steps
+ * steps of every problem, async).  Results are bit for bit those of
+ * imexds_step. */
 int imexds_step_per_problem(imexds_ctx *ctx, int32_t n_steps);
 
-/* Copies the current cell averages to device pointers (n_slots each, async). */
+/* Copies the current cell averages U = (rho, rho u) (Sec. 2.1) to device
+ * pointers (n_slots each, async). */
 int imexds_get_state(imexds_ctx *ctx, double *rho, double *mom);
 
-/* Host copies of the per-interface mesh state (n_iface each; any may be NULL):
- * background cell, offset in it, and position x_left + home*h + hl.
+/* Host copies of the per-interface mesh state of the grid alignment
+ * (Sec. 2.3) (n_iface each; any may be NULL): background cell, offset in
+ * it, and position x_left + home*h + hl.
  * Synchronizes. */
 int imexds_get_interfaces(imexds_ctx *ctx, int32_t *home, double *hl, double *x_iface);
 
-/* Host copies of per-problem time, status bits and completed steps
- * (n_problems each; any may be NULL).  Synchronizes. */
+/* Host copies of per-problem time (advanced by the CFL steps of eq.
+ * "cfl_cond:unif"), status bits and completed steps (n_problems each; any
+ * may be NULL).  Synchronizes. */
 int imexds_get_problems(imexds_ctx *ctx, double *t, int32_t *status, int64_t *steps);
 
-/* Enables per-step logging of the next max_steps steps (0 disables):
- * pseudo-iteration count, IMEXDS_FL_* flags and first zone slot (local to
- * the problem) of every interface.  Logging restarts at row 0. */
+/* Enables per-step logging of the next max_steps steps (0 disables): the
+ * dual time iteration count of Algorithm 2, the IMEXDS_FL_* flags (mesh
+ * events of Sec. 3.4) and the first zone slot (local to the problem) of
+ * every interface.  Logging restarts at row 0. */
 int imexds_enable_log(imexds_ctx *ctx, int32_t max_steps);
 
 /* Host copies of the logged rows, [rows][n_iface] each (any may be NULL);
  * *rows receives the number of rows written.  Synchronizes. */
 int imexds_get_log(imexds_ctx *ctx, int32_t *count, int32_t *flags, int32_t *zlo, int32_t *rows);
 
-/* Statistics since the last imexds_set_state.  Synchronizes. */
+/* Statistics since the last imexds_set_state (imexds_stats: counts of
+ * Algorithm 2's iterations, the interface solves of Appendix A, the mesh
+ * events of Sec. 3.4, device time).  Synchronizes. */
 int imexds_get_stats(imexds_ctx *ctx, imexds_stats *out);
 
-/* Launch configuration: bulk tile class (256, 512, 1024, 2048: R = class/256
+/* Launch configuration of the batched step (no counterpart in the paper,
+ * which steps one problem at a time): bulk tile class (256, 512, 1024, 2048: R = class/256
  * rows of 62 cells per wave, four waves per tile), zone lanes per 64-lane
  * workgroup (1..64, with one lane per zone), number of zone workgroups (0 =
  * enough for all zones at once; otherwise that many workgroups whose zone
@@ -228,7 +263,8 @@ int imexds_set_launch(imexds_ctx *ctx, int32_t tile_cells, int32_t zones_per_gro
 #define IMEXDS_ZONE_NEWTON 1
 int imexds_set_zone_solver(imexds_ctx *ctx, int32_t solver, int32_t maxit, double rtol);
 
-/* Times launch configurations on the current state for steps_per_trial
+/* Launch autotuner (no counterpart in the paper): times launch
+ * configurations on the current state for steps_per_trial
  * steps each (zone launch shapes first, then tile classes), restores the
  * state afterwards and keeps the fastest configuration.  Results (host, may
  * be NULL): chosen tile class, zone lanes per group, zone groups, lanes per
@@ -237,7 +273,7 @@ int imexds_autotune(imexds_ctx *ctx, int32_t steps_per_trial, int32_t *tile_cell
                     int32_t *zones_per_group, int32_t *zone_groups, int32_t *zone_lanes,
                     double *ms_per_step);
 
-/* Sizes of the batch (host, any may be NULL). */
+/* Sizes of the batch of imexds_create (host, any may be NULL). */
 int imexds_get_sizes(imexds_ctx *ctx, int32_t *n_problems, int32_t *n_iface, int64_t *n_slots);
 
 /* Device-time of the most recent imexds_step / imexds_step_per_problem /
@@ -246,11 +282,19 @@ int imexds_get_sizes(imexds_ctx *ctx, int32_t *n_problems, int32_t *n_iface, int
  * duration of one bulk-sweep launch inside it (ms, host).  Synchronizes. */
 int imexds_last_timing(imexds_ctx *ctx, double *total_ms, double *bulk_ms_per_launch);
 
-/* Enables HIP-event timing of the bulk-sweep kernel inside imexds_step:
- * kernels are launched directly (no graphs), each bulk launch is bracketed by
- * events and runs alone (the zones follow it on the same stream instead of
- * overlapping it).  Results are unchanged. */
+/* Enables HIP-event timing of the bulk-sweep kernel (Algorithm 1, Step 1)
+ * and the zone kernel (Algorithm 2) inside imexds_step: kernels are launched
+ * directly (no graphs), each bulk launch and each zone launch is bracketed
+ * by events on the main stream and runs alone (the zones follow the bulk
+ * sweep on the same stream instead of overlapping it).  Results are
+ * unchanged. */
 int imexds_time_bulk(imexds_ctx *ctx, int32_t on);
+
+/* Average device time of one bulk-sweep launch and of one zone launch in the
+ * most recent imexds_step made with imexds_time_bulk on (ms, host; any may
+ * be NULL), and the number of launches of each.  IMEXDS_ERR_NO_STATE if no
+ * step was timed.  Synchronizes. */
+int imexds_kernel_timing(imexds_ctx *ctx, double *bulk_ms, double *zone_ms, int32_t *launches);
 
 /* Replaces the kinetic coefficient tau of the kinetic relation (Sec. 2.1,
  * eq. "isoT:kin_rel1") for later steps (tau >= 0, finite).  Synchronizes;
@@ -293,7 +337,11 @@ int imexds_adjoint(imexds_ctx *ctx, const double *gL_rho, const double *gL_mom,
                    const double *gL_hl, double *g_rho0, double *g_mom0, double *g_hl0,
                    double *g_tau);
 
+/* Frees the context and every device buffer it owns (after synchronizing its
+ * streams); NULL is ignored. */
 void imexds_destroy(imexds_ctx *ctx);
+/* Static text naming an IMEXDS_ERR_* code (the last HIP error's text for
+ * IMEXDS_ERR_HIP, on the calling thread). */
 const char *imexds_strerror(int code);
 
 #ifdef __cplusplus

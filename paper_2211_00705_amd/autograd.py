@@ -23,6 +23,7 @@ class _Evolve(torch.autograd.Function):
         solver.set_tau(float(tau.item()))
         solver.set_state(rho0.detach().contiguous(), mom0.detach().contiguous())
         solver.forward_ckpt(n_steps, ckpt_every)
+        ctx.generation = solver.generation
         rho, mom = solver.state()
         home, hl, _ = solver.interfaces()
         ctx.solver = solver
@@ -33,6 +34,11 @@ class _Evolve(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g_rho, g_mom, g_hl):
         s = ctx.solver
+        if s.generation != ctx.generation:
+            raise RuntimeError("evolve: the solver has run again since this forward (another "
+                               "evolve, step or set_state); its adjoint would belong to that "
+                               "run.  Call backward before reusing the solver, or use one "
+                               "solver per graph.")
         S = s.n_slots
         dev = "cuda"
         if g_rho is None:

@@ -21,10 +21,16 @@ _creation.argtypes = [ctypes.POINTER(_base.imexds_material), c_i32, c_vp, c_vp, 
 EXPORTED = ["imexds_creation_rp"]
 
 
-def _dev(x, dtype):
+def _dev(x, dtype, n):
+    """Device address of a contiguous GPU tensor of that dtype and exactly n
+    elements (the library reads or writes that many through it)."""
     import torch
-    if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype != dtype or not x.is_contiguous():
-        raise ValueError(f"expected a contiguous {dtype} tensor on the GPU")
+    if not isinstance(x, torch.Tensor) or x.dtype != dtype or not x.is_contiguous():
+        raise ValueError(f"expected a contiguous {dtype} tensor")
+    if x.numel() != n:
+        raise ValueError(f"expected {n} elements, got {x.numel()}")
+    if not x.is_cuda:
+        raise ValueError("expected a tensor on the GPU")
     return c_vp(x.data_ptr())
 
 
@@ -41,8 +47,10 @@ def imexds_creation_rp(material, phase, rho_l, mom_l, rho_r, mom_r, p_min, p_til
                               material.tau)
     s = stream if stream is not None else torch.cuda.current_stream()
     d = torch.float64
-    _base._check(_creation(ctypes.byref(m), n, _dev(phase, torch.int32), _dev(rho_l, d),
-                           _dev(mom_l, d), _dev(rho_r, d), _dev(mom_r, d), float(p_min),
-                           float(p_tilde), int(maxit), float(rtol), _dev(status, torch.int32),
-                           _dev(out, d), c_vp(s.cuda_stream)), "imexds_creation_rp")
+    nf = n * len(FIELDS)
+    _base._check(_creation(ctypes.byref(m), n, _dev(phase, torch.int32, n), _dev(rho_l, d, n),
+                           _dev(mom_l, d, n), _dev(rho_r, d, n), _dev(mom_r, d, n),
+                           float(p_min), float(p_tilde), int(maxit), float(rtol),
+                           _dev(status, torch.int32, n), _dev(out, d, nf),
+                           c_vp(s.cuda_stream)), "imexds_creation_rp")
     return status, out

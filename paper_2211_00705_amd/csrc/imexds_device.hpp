@@ -191,6 +191,7 @@ struct GEval {
 
 struct IfaceOut {
   double pl, pr, rl, rr, ul, ur, z, w, F0, F1;
+  int nev;  // evaluations of G (Newton steps and Armijo trials, all starts)
 };
 
 __device__ __forceinline__ void d_side(const Mat& M, int ph, double r, double m, Side& S) {
@@ -397,9 +398,11 @@ __device__ __forceinline__ bool d_iface_solve_t(const Mat& M, int maxit, double 
          vr = 0.0, fr = 0.0;
   double dl = 0.0, dr = 0.0, st = 0.0, sc = 0.0, lam = 1.0;
   int k = 0, it = 0, mode = 0;  // 0: start point, 1: Armijo trial, 2: final step
+  int nev = 0;
   for (;;) {
     GEval Et;
     const bool valid = d_eval_G_t<PAIR>(M, R, tl, tr, side, partner, Et);
+    ++nev;
     bool done = false, take = false, next = false, acc = false;
     if (mode == 0) {
       if (!valid) {
@@ -503,6 +506,7 @@ __device__ __forceinline__ bool d_iface_solve_t(const Mat& M, int maxit, double 
   out.w = uV + z * vV;
   out.F0 = -z;
   out.F1 = -z * uV + pV;
+  out.nev = nev;
   return true;
 }
 

@@ -220,6 +220,7 @@ __global__ __launch_bounds__(64) void k_zone(StepArgs A, int if_begin, int if_en
 #pragma unroll
   for (int i = 0; i < MC; ++i) Ur[i] = Um[i] = W0[i] = W1[i] = 0.0;
   int stage = S_FETCH;
+  unsigned nsolve = 0, nev = 0;  // interface solves of this zone step, evaluations of G
   // first zone: the lane's own index in the grid; then the counter
   const int g_self = (int)blockIdx.x * A.zones_per_group + (int)threadIdx.x;
   const int g_all = (int)gridDim.x * A.zones_per_group;
@@ -300,6 +301,8 @@ __global__ __launch_bounds__(64) void k_zone(StepArgs A, int if_begin, int if_en
         d_hll(M, phe, r0[zhi], m0[zhi], r0[zhi + 1], m0[zhi + 1], FR0, FR1);
       merge = false;
       redo = false;
+      nsolve = 0;
+      nev = 0;
       stage = S_PRED;
     }
     if (stage == S_EXIT) break;
@@ -329,6 +332,10 @@ __global__ __launch_bounds__(64) void k_zone(StepArgs A, int if_begin, int if_en
     IfaceOut o;
     const bool ok = d_iface_solve(M, P.newton_maxit, P.newton_rtol, phl, ql0, ql1, phr, qr0, qr1,
                                   hg, g0, g1, o);
+    if (ok) {
+      ++nsolve;
+      nev += (unsigned)o.nev;
+    }
 
     // ---------------- stage-specific work ----------------
     int status = 0;
@@ -608,6 +615,13 @@ __global__ __launch_bounds__(64) void k_zone(StepArgs A, int if_begin, int if_en
       A.rec_pw1[2 * k + 1] = rpw1;
       A.rec_warm1[k] = warm;
       atomicOr(A.fail_acc + p, status);
+    }
+    if (A.st_newton) {
+      atomicAdd(A.st_newton, (unsigned long long)nev);
+      atomicAdd(A.st_solves, (unsigned long long)nsolve);
+      const int ev = ((flags & FL_MERGED) ? 1 : 0) + ((flags & FL_REDO) ? 1 : 0) +
+                     ((flags & (FL_CROSS_L | FL_CROSS_R)) ? 1 : 0);
+      if (ev) atomicAdd(A.st_events, (unsigned long long)ev);
     }
     A.rec_home1[k] = nhome;
     A.rec_hl1[k] = nhl;

@@ -52,6 +52,9 @@ struct StepArgs {
   unsigned long long* st_pseudo;
   unsigned long long* st_merges;
   unsigned long long* st_lmax;
+  unsigned long long* st_newton;  // evaluations of G in the interface solves
+  unsigned long long* st_solves;  // interface solves
+  unsigned long long* st_events;  // merges, redos and re-homings of interfaces
   int* zone_ctr;  // zones handed out so far in this step (reset by k_finalize)
   int zones_per_group;
   // zone tape of this step (nullptr: none).  Per interface, tape_stride

@@ -26,6 +26,10 @@ using imexds::StepArgs;
 
 namespace {
 
+// device counters of the zone kernels (imexds_stats): dual time iterations,
+// merges, lmax hits, evaluations of G, interface solves, mesh events
+constexpr int N_STATS = 6;
+
 template <class T>
 struct DBuf {
   T* p = nullptr;
@@ -51,6 +55,12 @@ struct imexds_ctx {
   std::vector<hipEvent_t> fork_ev, join_ev;
   hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
   std::vector<hipEvent_t> bulk_ev;  // pairs around bulk launches when timing
+  std::vector<hipEvent_t> zone_ev;  // pairs around zone launches when timing
+  // begin / end events of the stepping calls since the last statistics
+  // read-out, and the device time they have accounted for so far
+  std::vector<hipEvent_t> call_ev;
+  int n_call_ev = 0;
+  double acc_gpu_ms = 0.0;
   imexds::Mat mat{};
   imexds::Par par{};
   int P = 0, NIF = 0;
@@ -77,7 +87,7 @@ struct imexds_ctx {
   int *d_status = nullptr, *d_clipped = nullptr, *d_fail = nullptr;
   long long* d_steps = nullptr;
   unsigned long long* d_S = nullptr;
-  unsigned long long* d_stats = nullptr;  // pseudo, merges, lmax
+  unsigned long long* d_stats = nullptr;  // pseudo, merges, lmax, G evaluations, solves, events
   int* d_zone_ctr = nullptr;
   int *d_log_count = nullptr, *d_log_flags = nullptr, *d_log_zlo = nullptr, *d_log_row = nullptr;
   int log_max = 0;
@@ -201,6 +211,9 @@ StepArgs make_args(imexds_ctx* c, int parity, bool init) {
   A.st_pseudo = c->d_stats;
   A.st_merges = c->d_stats + 1;
   A.st_lmax = c->d_stats + 2;
+  A.st_newton = c->d_stats + 3;
+  A.st_solves = c->d_stats + 4;
+  A.st_events = c->d_stats + 5;
   A.zone_ctr = c->d_zone_ctr;
   A.zones_per_group = c->zones_per_group;
   return A;
@@ -271,8 +284,15 @@ int enqueue_step(imexds_ctx* c, int ev_slot) {
     CK(hipEventRecord(c->bulk_ev[2 * c->bulk_launches], c->ms));
     CK(imexds::launch_bulk(A, c->tile_cells, 0, c->n_tiles, c->ms));
     CK(hipEventRecord(c->bulk_ev[2 * c->bulk_launches + 1], c->ms));
-    c->bulk_launches++;
+    while (c->zone_ev.size() < need) {
+      hipEvent_t e;
+      CK(hipEventCreate(&e));
+      c->zone_ev.push_back(e);
+    }
+    CK(hipEventRecord(c->zone_ev[2 * c->bulk_launches], c->ms));
     if (c->NIF > 0) CK(launch_zones(c, A, 0, c->NIF, c->zone_groups, c->ms));
+    CK(hipEventRecord(c->zone_ev[2 * c->bulk_launches + 1], c->ms));
+    c->bulk_launches++;
     CK(imexds::launch_finalize(A, 0, c->P, 0, 1, c->ms));
     c->parity ^= 1;
     return 0;
@@ -345,6 +365,51 @@ int end_call(imexds_ctx* c) {
   return 0;
 }
 
+// Device time of the stepping calls: each call records a pair of events;
+// completed pairs are folded into acc_gpu_ms (all of them, waiting, when
+// `wait`; else those already done, and the oldest ones once many are
+// pending, so that the event list stays bounded).
+int fold_call_events(imexds_ctx* c, bool wait) {
+  int done = 0;
+  for (; done < c->n_call_ev; ++done) {
+    hipEvent_t e0 = c->call_ev[2 * done], e1 = c->call_ev[2 * done + 1];
+    if (wait || c->n_call_ev - done > 256) {
+      CK(hipEventSynchronize(e1));
+    } else {
+      hipError_t q = hipEventQuery(e1);
+      if (q == hipErrorNotReady) break;
+      if (q != hipSuccess) return hip_fail(q, "hipEventQuery");
+    }
+    float ms = 0.f;
+    CK(hipEventElapsedTime(&ms, e0, e1));
+    c->acc_gpu_ms += ms;
+  }
+  if (done > 0) {  // keep the pending pairs at the front, recycle the folded ones
+    std::rotate(c->call_ev.begin(), c->call_ev.begin() + 2 * done,
+                c->call_ev.begin() + 2 * c->n_call_ev);
+    c->n_call_ev -= done;
+  }
+  return 0;
+}
+
+int call_begin(imexds_ctx* c) {
+  int r = fold_call_events(c, false);
+  if (r) return r;
+  while (c->call_ev.size() < 2 * (size_t)(c->n_call_ev + 1)) {
+    hipEvent_t e;
+    CK(hipEventCreate(&e));
+    c->call_ev.push_back(e);
+  }
+  CK(hipEventRecord(c->call_ev[2 * c->n_call_ev], c->ms));
+  return 0;
+}
+
+int call_end(imexds_ctx* c) {
+  CK(hipEventRecord(c->call_ev[2 * c->n_call_ev + 1], c->ms));
+  c->n_call_ev++;
+  return 0;
+}
+
 int init_dt(imexds_ctx* c) {
   StepArgs A = make_args(c, c->parity, true);
   CK(imexds::launch_cfl(A, 0, c->n_tiles, c->ms));
@@ -366,7 +431,7 @@ int snap_take(imexds_ctx* c, Snapshot& s) {
   CK(hipMalloc((void**)&s.status, P * 4));
   CK(hipMalloc((void**)&s.clipped, P * 4));
   CK(hipMalloc((void**)&s.steps, P * 8));
-  CK(hipMalloc((void**)&s.stats, 3 * 8));
+  CK(hipMalloc((void**)&s.stats, N_STATS * 8));
   int a = c->parity;
   s.parity = a;
   hipStream_t m = c->ms;
@@ -383,7 +448,7 @@ int snap_take(imexds_ctx* c, Snapshot& s) {
   CK(hipMemcpyAsync(s.status, c->d_status, P * 4, hipMemcpyDeviceToDevice, m));
   CK(hipMemcpyAsync(s.clipped, c->d_clipped, P * 4, hipMemcpyDeviceToDevice, m));
   CK(hipMemcpyAsync(s.steps, c->d_steps, P * 8, hipMemcpyDeviceToDevice, m));
-  CK(hipMemcpyAsync(s.stats, c->d_stats, 3 * 8, hipMemcpyDeviceToDevice, m));
+  CK(hipMemcpyAsync(s.stats, c->d_stats, N_STATS * 8, hipMemcpyDeviceToDevice, m));
   return 0;
 }
 
@@ -406,7 +471,7 @@ int snap_restore(imexds_ctx* c, Snapshot& s) {
   CK(hipMemcpyAsync(c->d_status, s.status, P * 4, hipMemcpyDeviceToDevice, m));
   CK(hipMemcpyAsync(c->d_clipped, s.clipped, P * 4, hipMemcpyDeviceToDevice, m));
   CK(hipMemcpyAsync(c->d_steps, s.steps, P * 8, hipMemcpyDeviceToDevice, m));
-  CK(hipMemcpyAsync(c->d_stats, s.stats, 3 * 8, hipMemcpyDeviceToDevice, m));
+  CK(hipMemcpyAsync(c->d_stats, s.stats, N_STATS * 8, hipMemcpyDeviceToDevice, m));
   CK(hipStreamSynchronize(m));
   return 0;
 }
@@ -571,6 +636,7 @@ int record_segment(imexds_ctx* c, int len) {
     A.log_count = A.log_flags = A.log_zlo = A.log_row = nullptr;
     A.log_max = 0;
     A.st_pseudo = A.st_merges = A.st_lmax = nullptr;
+    A.st_newton = A.st_solves = A.st_events = nullptr;
     A.tape = c->tZone + (size_t)j * N * (size_t)c->tape_stride;
     A.tape_stride = c->tape_stride;
     if (N) CK(launch_zones(c, A, 0, c->NIF, c->zone_groups, m));
@@ -649,6 +715,8 @@ void imexds_destroy(imexds_ctx* c) {
   for (auto e : c->fork_ev) (void)hipEventDestroy(e);
   for (auto e : c->join_ev) (void)hipEventDestroy(e);
   for (auto e : c->bulk_ev) (void)hipEventDestroy(e);
+  for (auto e : c->zone_ev) (void)hipEventDestroy(e);
+  for (auto e : c->call_ev) (void)hipEventDestroy(e);
   hipEvent_t es[] = {c->ev_in, c->ev_out, c->ev_t0, c->ev_t1};
   for (auto e : es)
     if (e) (void)hipEventDestroy(e);
@@ -777,7 +845,7 @@ static int create_impl(imexds_ctx* c, const imexds_material* mat, const imexds_p
   AL(c->d_fail, Pn);
   AL(c->d_steps, Pn);
   AL(c->d_S, Pn);
-  AL(c->d_stats, 3);
+  AL(c->d_stats, N_STATS);
   AL(c->d_log_row, 1);
   AL(c->d_zone_ctr, 1);
   CK(hipMemcpy(c->d_slot_off, c->h_slot_off.data(), (Pn + 1) * 8, hipMemcpyHostToDevice));
@@ -838,7 +906,9 @@ int imexds_set_state(imexds_ctx* c, const double* rho, const double* mom) {
     CK(hipMemsetAsync(c->d_steps, 0, P * 8, m));
     CK(hipMemsetAsync(c->d_S, 0, P * 8, m));
   }
-  CK(hipMemsetAsync(c->d_stats, 0, 3 * 8, m));
+  CK(hipMemsetAsync(c->d_stats, 0, N_STATS * 8, m));
+  c->n_call_ev = 0;
+  c->acc_gpu_ms = 0.0;
   CK(hipMemsetAsync(c->d_log_row, 0, 4, m));
   CK(hipMemsetAsync(c->d_zone_ctr, 0, 4, m));
   // host->device copies above read pageable host memory: finish them here
@@ -859,9 +929,11 @@ int imexds_step(imexds_ctx* c, int32_t n_steps) {
   if (r) return r;
   c->adj_ready = false;
   c->bulk_launches = 0;
+  if ((r = call_begin(c))) return r;
   CK(hipEventRecord(c->ev_t0, c->ms));
   if (c->P > 0 && (r = steps_impl(c, n_steps))) return r;
   CK(hipEventRecord(c->ev_t1, c->ms));
+  if ((r = call_end(c))) return r;
   c->timed = true;
   return end_call(c);
 }
@@ -873,6 +945,7 @@ int imexds_step_per_problem(imexds_ctx* c, int32_t n_steps) {
   if (r) return r;
   c->adj_ready = false;
   c->bulk_launches = 0;
+  if ((r = call_begin(c))) return r;
   CK(hipEventRecord(c->ev_t0, c->ms));
   for (int n = 0; n < n_steps; ++n) {
     StepArgs A = make_args(c, c->parity, false);
@@ -886,6 +959,7 @@ int imexds_step_per_problem(imexds_ctx* c, int32_t n_steps) {
     c->parity ^= 1;
   }
   CK(hipEventRecord(c->ev_t1, c->ms));
+  if ((r = call_end(c))) return r;
   c->timed = true;
   return end_call(c);
 }
@@ -898,6 +972,7 @@ int imexds_run(imexds_ctx* c, int32_t max_steps, int32_t check_every, int32_t* s
   c->adj_ready = false;
   int done = 0;
   std::vector<double> dt(c->P);
+  if ((r = call_begin(c))) return r;
   CK(hipEventRecord(c->ev_t0, c->ms));
   while (done < max_steps && c->P > 0) {
     CK(hipMemcpyAsync(dt.data(), c->d_dt, sizeof(double) * c->P, hipMemcpyDeviceToHost, c->ms));
@@ -910,6 +985,7 @@ int imexds_run(imexds_ctx* c, int32_t max_steps, int32_t check_every, int32_t* s
     done += n;
   }
   CK(hipEventRecord(c->ev_t1, c->ms));
+  if ((r = call_end(c))) return r;
   c->timed = true;
   if (steps_done) *steps_done = done;
   return end_call(c);
@@ -1008,8 +1084,8 @@ int imexds_get_stats(imexds_ctx* c, imexds_stats* out) {
   if (!c || !out) return IMEXDS_ERR_INVALID_ARG;
   CK(hipSetDevice(c->device));
   memset(out, 0, sizeof(*out));
-  unsigned long long st[3] = {0, 0, 0};
-  CK(hipMemcpyAsync(st, c->d_stats, 24, hipMemcpyDeviceToHost, c->ms));
+  unsigned long long st[N_STATS] = {0, 0, 0, 0, 0, 0};
+  CK(hipMemcpyAsync(st, c->d_stats, N_STATS * 8, hipMemcpyDeviceToHost, c->ms));
   size_t P = (size_t)c->P;
   std::vector<long long> steps(P);
   std::vector<int> status(P);
@@ -1029,6 +1105,12 @@ int imexds_get_stats(imexds_ctx* c, imexds_stats* out) {
   out->pseudo_iters = (int64_t)st[0];
   out->merges = (int64_t)st[1];
   out->lmax_hits = (int64_t)st[2];
+  out->newton_iters = (int64_t)st[3];
+  out->iface_solves = (int64_t)st[4];
+  out->events = (int64_t)st[5];
+  int r = fold_call_events(c, true);
+  if (r) return r;
+  out->gpu_ms = c->acc_gpu_ms;
   return 0;
 }
 
@@ -1182,6 +1264,26 @@ int imexds_last_timing(imexds_ctx* c, double* total_ms, double* bulk_ms_per_laun
 int imexds_time_bulk(imexds_ctx* c, int32_t on) {
   if (!c) return IMEXDS_ERR_INVALID_ARG;
   c->time_bulk = on != 0;
+  return 0;
+}
+
+int imexds_kernel_timing(imexds_ctx* c, double* bulk_ms, double* zone_ms, int32_t* launches) {
+  if (!c) return IMEXDS_ERR_INVALID_ARG;
+  CK(hipSetDevice(c->device));
+  if (!c->timed) return IMEXDS_ERR_NO_STATE;
+  CK(hipEventSynchronize(c->ev_t1));
+  const int n = c->bulk_launches;
+  double sb = 0.0, sz = 0.0;
+  for (int i = 0; i < n; ++i) {
+    float b = 0.f, z = 0.f;
+    CK(hipEventElapsedTime(&b, c->bulk_ev[2 * i], c->bulk_ev[2 * i + 1]));
+    CK(hipEventElapsedTime(&z, c->zone_ev[2 * i], c->zone_ev[2 * i + 1]));
+    sb += b;
+    sz += z;
+  }
+  if (bulk_ms) *bulk_ms = n ? sb / n : 0.0;
+  if (zone_ms) *zone_ms = n ? sz / n : 0.0;
+  if (launches) *launches = n;
   return 0;
 }
 

@@ -549,6 +549,11 @@ __global__ __launch_bounds__(64) void k_zone_nt(StepArgs A, int if_begin, int if
     A.rec_warm1[k] = warm;
     atomicOr(A.fail_acc + p, status);
   }
+  if (A.st_events) {
+    const int ev = ((flags & FL_MERGED) ? 1 : 0) + ((flags & FL_REDO) ? 1 : 0) +
+                   ((flags & (FL_CROSS_L | FL_CROSS_R)) ? 1 : 0);
+    if (ev) atomicAdd(A.st_events, (unsigned long long)ev);
+  }
   A.rec_home1[k] = nhome;
   A.rec_hl1[k] = nhl;
   const int nsL = nhome + kk;

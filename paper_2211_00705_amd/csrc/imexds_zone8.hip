@@ -104,6 +104,9 @@ __global__ __launch_bounds__(64) void k_zone8(StepArgs A, int if_begin, int if_e
   double tol = 0.0;
   int ph = 0;
   int stage = S_FETCH;
+  // per lane: interface solves this lane led (side 0) in the current zone
+  // step and their evaluations of G (summed over the group at write-back)
+  unsigned nsolve = 0, nev = 0;
   // the first zone of a group is its own index in the grid, further ones come
   // from the counter: 4096 groups pulling from one address at once would
   // queue behind each other for tens of microseconds
@@ -196,6 +199,8 @@ __global__ __launch_bounds__(64) void k_zone8(StepArgs A, int if_begin, int if_e
       merge = false;
       redo = false;
       pos = -1;
+      nsolve = 0;
+      nev = 0;
       stage = S_PRED;
     }
     if (stage == S_EXIT) break;
@@ -214,6 +219,7 @@ __global__ __launch_bounds__(64) void k_zone8(StepArgs A, int if_begin, int if_e
     if (c == a0 + 1) side = 1;
     IfaceOut o;
     o.pl = o.pr = o.rl = o.rr = o.ul = o.ur = o.z = o.w = o.F0 = o.F1 = 0.0;
+    o.nev = 0;
     int okl = 0;
     if (side >= 0) {
       const double x0 = pred ? Ur : W0, x1 = pred ? Um : W1;
@@ -224,6 +230,10 @@ __global__ __launch_bounds__(64) void k_zone8(StepArgs A, int if_begin, int if_e
                                   g0, g1, side, partner, o)
                 ? 1
                 : 0;
+      if (side == 0 && okl) {
+        ++nsolve;
+        nev += (unsigned)o.nev;
+      }
     }
     const bool ok = z8_geti(okl, gb, a0) != 0;
     const double opl = z8_get(o.pl, gb, a0), opr = z8_get(o.pr, gb, a0);
@@ -518,6 +528,18 @@ __global__ __launch_bounds__(64) void k_zone8(StepArgs A, int if_begin, int if_e
       }
     }
     vmax = z8_max_u64(vmax);
+    if (A.st_newton) {
+      unsigned long long sv = ((unsigned long long)nsolve << 32) | nev;
+#pragma unroll
+      for (int off = 4; off > 0; off >>= 1) sv += __shfl_xor(sv, off, 8);
+      if (c == 0) {
+        atomicAdd(A.st_newton, sv & 0xffffffffull);
+        atomicAdd(A.st_solves, sv >> 32);
+        const int ev = ((flags & FL_MERGED) ? 1 : 0) + ((flags & FL_REDO) ? 1 : 0) +
+                       ((flags & (FL_CROSS_L | FL_CROSS_R)) ? 1 : 0);
+        if (ev) atomicAdd(A.st_events, (unsigned long long)ev);
+      }
+    }
     if (c == 0) {
       A.rec_home1[k] = nhome;
       A.rec_hl1[k] = nhl;

@@ -83,7 +83,8 @@ def imexds_ct_create(batch, stream=None):
 
 
 def imexds_ct_set_state(ctx, rho, mom):
-    _check(_set_state(c_vp(ctx), _dev_ptr(rho), _dev_ptr(mom)), "imexds_ct_set_state")
+    _, n = imexds_ct_get_sizes(ctx)
+    _check(_set_state(c_vp(ctx), _dev_ptr(rho, n), _dev_ptr(mom, n)), "imexds_ct_set_state")
 
 
 def imexds_ct_step(ctx, n_steps):
@@ -102,7 +103,8 @@ def imexds_ct_run(ctx, max_steps, check_every=64):
 
 
 def imexds_ct_get_state(ctx, rho, mom):
-    _check(_get_state(c_vp(ctx), _dev_ptr(rho), _dev_ptr(mom)), "imexds_ct_get_state")
+    _, n = imexds_ct_get_sizes(ctx)
+    _check(_get_state(c_vp(ctx), _dev_ptr(rho, n), _dev_ptr(mom, n)), "imexds_ct_get_state")
 
 
 def imexds_ct_get_sizes(ctx):

@@ -79,7 +79,8 @@ def imexds_eu_create(batch, stream=None):
 
 
 def imexds_eu_set_state(ctx, rho, mom, ene):
-    _check(_set_state(c_vp(ctx), _dev_ptr(rho), _dev_ptr(mom), _dev_ptr(ene)),
+    _, n = imexds_eu_get_sizes(ctx)
+    _check(_set_state(c_vp(ctx), _dev_ptr(rho, n), _dev_ptr(mom, n), _dev_ptr(ene, n)),
            "imexds_eu_set_state")
 
 
@@ -99,7 +100,8 @@ def imexds_eu_run(ctx, max_steps, check_every=64):
 
 
 def imexds_eu_get_state(ctx, rho, mom, ene):
-    _check(_get_state(c_vp(ctx), _dev_ptr(rho), _dev_ptr(mom), _dev_ptr(ene)),
+    _, n = imexds_eu_get_sizes(ctx)
+    _check(_get_state(c_vp(ctx), _dev_ptr(rho, n), _dev_ptr(mom, n), _dev_ptr(ene, n)),
            "imexds_eu_get_state")
 
 

@@ -52,7 +52,9 @@ class imexds_batch(ctypes.Structure):
 
 class imexds_stats(ctypes.Structure):
     _fields_ = [("steps", c_i64), ("cell_updates", c_i64), ("pseudo_iters", c_i64),
-                ("merges", c_i64), ("lmax_hits", c_i64), ("n_failed", c_i32), ("n_active", c_i32)]
+                ("merges", c_i64), ("lmax_hits", c_i64), ("n_failed", c_i32), ("n_active", c_i32),
+                ("newton_iters", c_i64), ("iface_solves", c_i64), ("events", c_i64),
+                ("gpu_ms", c_dbl)]
 
 
 def _sig(name, *args):
@@ -81,6 +83,7 @@ _autotune = _sig("imexds_autotune", c_vp, c_i32, P_i32, P_i32, P_i32, P_i32, P_d
 _get_sizes = _sig("imexds_get_sizes", c_vp, P_i32, P_i32, P_i64)
 _last_timing = _sig("imexds_last_timing", c_vp, P_dbl, P_dbl)
 _time_bulk = _sig("imexds_time_bulk", c_vp, c_i32)
+_kernel_timing = _sig("imexds_kernel_timing", c_vp, P_dbl, P_dbl, P_i32)
 _set_tau = _sig("imexds_set_tau", c_vp, c_dbl)
 _forward_ckpt = _sig("imexds_forward_ckpt", c_vp, c_i32, c_i32)
 _adjoint = _sig("imexds_adjoint", c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp)
@@ -93,7 +96,7 @@ EXPORTED = ["imexds_create", "imexds_set_state", "imexds_step", "imexds_run",
             "imexds_step_per_problem", "imexds_get_state", "imexds_get_interfaces",
             "imexds_get_problems", "imexds_enable_log", "imexds_get_log", "imexds_get_stats",
             "imexds_set_launch", "imexds_set_zone_solver", "imexds_autotune", "imexds_get_sizes",
-            "imexds_last_timing",
+            "imexds_last_timing", "imexds_kernel_timing",
             "imexds_time_bulk", "imexds_set_tau", "imexds_forward_ckpt", "imexds_adjoint",
             "imexds_destroy", "imexds_strerror"]
 
@@ -121,11 +124,16 @@ def _p(a, t):
     return a.ctypes.data_as(ctypes.POINTER(t))
 
 
-def _dev_ptr(x):
+def _dev_ptr(x, n=None):
+    """Device address of a contiguous float64 GPU tensor of exactly n
+    elements (the library reads or writes that many through it)."""
     import torch
-    if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype != torch.float64 \
-            or not x.is_contiguous():
-        raise ValueError("expected a contiguous float64 tensor on the GPU")
+    if not isinstance(x, torch.Tensor) or x.dtype != torch.float64 or not x.is_contiguous():
+        raise ValueError("expected a contiguous float64 tensor")
+    if n is not None and x.numel() != n:
+        raise ValueError(f"expected {n} elements, got {x.numel()}")
+    if not x.is_cuda:
+        raise ValueError("expected a tensor on the GPU")
     return ctypes.c_void_p(x.data_ptr())
 
 
@@ -155,7 +163,8 @@ def imexds_create(material, params, batch, stream=None):
 
 
 def imexds_set_state(ctx, rho, mom):
-    _check(_set_state(c_vp(ctx), _dev_ptr(rho), _dev_ptr(mom)), "imexds_set_state")
+    _, _, S = imexds_get_sizes(ctx)
+    _check(_set_state(c_vp(ctx), _dev_ptr(rho, S), _dev_ptr(mom, S)), "imexds_set_state")
 
 
 def imexds_step(ctx, n_steps):
@@ -173,7 +182,8 @@ def imexds_step_per_problem(ctx, n_steps):
 
 
 def imexds_get_state(ctx, rho, mom):
-    _check(_get_state(c_vp(ctx), _dev_ptr(rho), _dev_ptr(mom)), "imexds_get_state")
+    _, _, S = imexds_get_sizes(ctx)
+    _check(_get_state(c_vp(ctx), _dev_ptr(rho, S), _dev_ptr(mom, S)), "imexds_get_state")
 
 
 def imexds_get_sizes(ctx):
@@ -256,6 +266,15 @@ def imexds_time_bulk(ctx, on):
     _check(_time_bulk(c_vp(ctx), int(bool(on))), "imexds_time_bulk")
 
 
+def imexds_kernel_timing(ctx):
+    """(bulk ms, zone ms) per launch and the number of launches of the last
+    step call made with imexds_time_bulk on."""
+    b, z, n = c_dbl(), c_dbl(), c_i32()
+    _check(_kernel_timing(c_vp(ctx), ctypes.byref(b), ctypes.byref(z), ctypes.byref(n)),
+           "imexds_kernel_timing")
+    return b.value, z.value, n.value
+
+
 def imexds_set_tau(ctx, tau):
     _check(_set_tau(c_vp(ctx), float(tau)), "imexds_set_tau")
 
@@ -265,10 +284,14 @@ def imexds_forward_ckpt(ctx, n_steps, ckpt_every):
 
 
 def imexds_adjoint(ctx, gL_rho, gL_mom, gL_hl, g_rho0, g_mom0, g_hl0, g_tau):
-    """All arguments are FP64 cuda tensors (gL_hl and g_hl0 may be None)."""
-    opt = (lambda x: _dev_ptr(x) if x is not None else c_vp(None))
-    _check(_adjoint(c_vp(ctx), _dev_ptr(gL_rho), _dev_ptr(gL_mom), opt(gL_hl), _dev_ptr(g_rho0),
-                    _dev_ptr(g_mom0), opt(g_hl0), _dev_ptr(g_tau)), "imexds_adjoint")
+    """All arguments are FP64 cuda tensors (gL_hl and g_hl0 may be None):
+    n_slots elements for the state gradients, n_iface for the interface
+    ones, one for g_tau."""
+    _, N, S = imexds_get_sizes(ctx)
+    opt = (lambda x: _dev_ptr(x, N) if x is not None else c_vp(None))
+    _check(_adjoint(c_vp(ctx), _dev_ptr(gL_rho, S), _dev_ptr(gL_mom, S), opt(gL_hl),
+                    _dev_ptr(g_rho0, S), _dev_ptr(g_mom0, S), opt(g_hl0), _dev_ptr(g_tau, 1)),
+           "imexds_adjoint")
 
 
 def imexds_destroy(ctx):
@@ -287,6 +310,9 @@ class IMEXDS:
         self.ctx = imexds_create(material, params, batch, stream)
         self.n_slots = batch.n_slots
         self._torch = torch
+        # bumped by every call that replaces what a checkpointed forward
+        # recorded, so that a backward can tell whether it still has its own
+        self.generation = 0
 
     def set_state(self, rho=None, mom=None):
         torch = self._torch
@@ -294,15 +320,19 @@ class IMEXDS:
             rho = torch.from_numpy(np.ascontiguousarray(self.batch.rho, np.float64)).cuda()
             mom = torch.from_numpy(np.ascontiguousarray(self.batch.mom, np.float64)).cuda()
         imexds_set_state(self.ctx, rho, mom)
+        self.generation += 1
 
     def step(self, n):
         imexds_step(self.ctx, n)
+        self.generation += 1
 
     def run(self, max_steps, check_every=256):
+        self.generation += 1
         return imexds_run(self.ctx, max_steps, check_every)
 
     def step_per_problem(self, n):
         imexds_step_per_problem(self.ctx, n)
+        self.generation += 1
 
     def state(self):
         torch = self._torch
@@ -349,11 +379,16 @@ class IMEXDS:
     def time_bulk(self, on=True):
         imexds_time_bulk(self.ctx, on)
 
+    def kernel_timing(self):
+        return imexds_kernel_timing(self.ctx)
+
     def set_tau(self, tau):
         imexds_set_tau(self.ctx, tau)
+        self.generation += 1
 
     def forward_ckpt(self, n_steps, ckpt_every):
         imexds_forward_ckpt(self.ctx, n_steps, ckpt_every)
+        self.generation += 1
 
     def adjoint(self, g_rho, g_mom, g_hl=None):
         """dL/d(rho0, mom0, hl0, tau) of the last forward_ckpt, given dL/d of

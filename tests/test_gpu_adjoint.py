@@ -258,3 +258,29 @@ def test_adjoint_api_errors(material):
             s.forward_ckpt(5, 0)
     finally:
         s.close()
+
+
+def test_autograd_backward_belongs_to_its_own_forward(material):
+    """Two evolve() calls on one solver: the first graph's backward would
+    differentiate the second run, so it is refused; the second one works, and
+    a wrong-length gradient tensor is refused before it reaches the device."""
+    import torch
+    from paper_2211_00705_amd.imexds import IMEXDS
+    from paper_2211_00705_amd.autograd import evolve
+    b = W.random_batch(seed=4, n_problems=3, nmax=300)
+    s = IMEXDS(b, material, W.random_batch_params())
+    try:
+        rho0 = torch.tensor(b.rho, dtype=torch.float64, device="cuda", requires_grad=True)
+        mom0 = torch.tensor(b.mom, dtype=torch.float64, device="cuda", requires_grad=True)
+        tau = torch.tensor([material.tau], dtype=torch.float64, device="cuda", requires_grad=True)
+        r1, _, _ = evolve(s, rho0, mom0, tau, 8, 4)
+        r2, _, _ = evolve(s, rho0, mom0, tau, 6, 4)
+        with pytest.raises(RuntimeError, match="run again"):
+            r1.sum().backward()
+        r2.sum().backward()
+        assert rho0.grad is not None and torch.isfinite(rho0.grad).all()
+        short = torch.zeros(b.n_slots - 1, dtype=torch.float64, device="cuda")
+        with pytest.raises(ValueError, match="elements"):
+            s.adjoint(short, short)
+    finally:
+        s.close()
