@@ -50,6 +50,7 @@ extern "C" {
 #define IMEXDS_ERR_HIP (-3)
 #define IMEXDS_ERR_NO_STATE (-4)
 #define IMEXDS_ERR_UNSUPPORTED (-5)
+#define IMEXDS_ERR_TOO_LARGE (-6) /* size above an entry point's fixed maximum */
 
 /* per-problem status bits (sticky; a problem with any bit set is frozen) */
 #define IMEXDS_ST_NEWTON_FAIL 1  /* interface Newton-Armijo did not converge */

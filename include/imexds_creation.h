@@ -87,6 +87,26 @@ int imexds_creation_rp(const imexds_material *mat, int32_t n, const int32_t *pha
                        const double *mom_r, double p_min, double p_tilde, int32_t maxit,
                        double rtol, int32_t *status, double *out, void *hip_stream);
 
+/* Largest n that imexds_creation_rp_noalloc accepts. */
+#define IMEXDS_CR_NOALLOC_MAX (1 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same solve as
+ * imexds_creation_rp, with the same arguments, outputs and error codes, but
+ * its scratch (queue counters and queues, 8 n + 16 bytes) is a fixed array in
+ * the library's device memory, 8 MiB + 16 B on each device the library runs
+ * on, held until the process ends.  No allocation or release of any memory is
+ * made.  n must be at most IMEXDS_CR_NOALLOC_MAX, else IMEXDS_ERR_TOO_LARGE.
+ * The counters are cleared by a kernel at the start of every call.  Every
+ * call on one device uses that device's one array: calls that overlap on one
+ * device (on different streams, or from different host threads without
+ * ordering) race and give wrong results; calls ordered on one stream are
+ * safe.  IMEXDS_ERR_HIP if the array's device address cannot be obtained. */
+int imexds_creation_rp_noalloc(const imexds_material *mat, int32_t n, const int32_t *phase,
+                               const double *rho_l, const double *mom_l, const double *rho_r,
+                               const double *mom_r, double p_min, double p_tilde, int32_t maxit,
+                               double rtol, int32_t *status, double *out, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

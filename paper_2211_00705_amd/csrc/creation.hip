@@ -16,9 +16,18 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "../../include/imexds_creation.h"
 #include "creation_device.hpp"
+
+// Fixed scratch of imexds_creation_rp_noalloc: the four queue counters and
+// both queues for up to IMEXDS_CR_NOALLOC_MAX problems (8 MiB + 16 B).  Every
+// device the library runs on holds one copy for the life of the process.
+// Host code never passes this name to a kernel (on the host it only stands
+// for the symbol): it uses the device address that hipGetSymbolAddress
+// returns, looked up once per device.
+static __device__ __align__(256) int scratch[4 + 2 * IMEXDS_CR_NOALLOC_MAX];
 
 namespace imexds {
 namespace {
@@ -154,24 +163,16 @@ __global__ __launch_bounds__(256) void k_cr_solve(Mat M, int n, const int* __res
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
-}  // namespace
-}  // namespace imexds
-
-extern "C" int imexds_creation_rp(const imexds_material* mat, int32_t n, const int32_t* phase,
-                                  const double* rho_l, const double* mom_l, const double* rho_r,
-                                  const double* mom_r, double p_min, double p_tilde, int32_t maxit,
-                                  double rtol, int32_t* status, double* out, void* hip_stream) {
-  using namespace imexds;
-  if (!mat || n < 0 || maxit < 1 || !finite_pos(rtol)) return IMEXDS_ERR_INVALID_ARG;
+// Material constants as the time-stepping context derives them; false if the
+// arguments are invalid.
+bool cr_prepare(const imexds_material* mat, int32_t n, int32_t maxit, double rtol, double p_min,
+                double p_tilde, Mat& M) {
+  if (!mat || n < 0 || maxit < 1 || !finite_pos(rtol)) return false;
   if (!finite_pos(mat->a2_vap) || !finite_pos(mat->a2_liq) || !finite_pos(mat->p_sat) ||
       !finite_pos(mat->rho_liq_sat) || !finite_pos(mat->tau) || !std::isfinite(p_min) ||
       !std::isfinite(p_tilde))
-    return IMEXDS_ERR_INVALID_ARG;
-  if (n == 0) return IMEXDS_OK;
-  if (!phase || !rho_l || !mom_l || !rho_r || !mom_r || !status || !out)
-    return IMEXDS_ERR_INVALID_ARG;
-  // the same derived constants as the time-stepping context
-  Mat M{};
+    return false;
+  M = Mat{};
   M.a2v = mat->a2_vap;
   M.a2l = mat->a2_liq;
   M.p0 = mat->p_sat;
@@ -186,14 +187,19 @@ extern "C" int imexds_creation_rp(const imexds_material* mat, int32_t n, const i
   M.ial = 1.0 / M.al;
   M.irv0 = 1.0 / M.rhov0;
   M.irl0 = 1.0 / M.rhol0;
-  // scratch: four queue counters and two queues of n problem indices,
-  // stream-ordered, released after the solve pass
-  hipStream_t s = (hipStream_t)hip_stream;
-  int* scratch = nullptr;
-  const size_t bytes = sizeof(int) * (2 * (size_t)n + 4);
-  if (hipMallocAsync((void**)&scratch, bytes, s) != hipSuccess) return IMEXDS_ERR_OOM;
-  int* ctr = scratch;
-  int* qa = scratch + 4;
+  return true;
+}
+
+// The three passes on stream s over n > 0 problems, with buf = four queue
+// counters followed by two queues of n problem indices (device memory of
+// 4 (2 n + 4) bytes).  The counters are cleared by a kernel (k_cr_init), not
+// by a memset, so the sequence may be captured in a graph.
+void cr_launch(const Mat& M, int32_t n, const int32_t* phase, const double* rho_l,
+               const double* mom_l, const double* rho_r, const double* mom_r, double p_min,
+               double p_tilde, int32_t maxit, double rtol, int32_t* status, double* out,
+               int* buf, hipStream_t s) {
+  int* ctr = buf;
+  int* qa = buf + 4;
   int* q = qa + n;
   const int blocks = (int)(((long long)n + 255) / 256);
   const int qblocks = (int)(((long long)n + CR_BLOCK - 1) / CR_BLOCK);
@@ -203,8 +209,71 @@ extern "C" int imexds_creation_rp(const imexds_material* mat, int32_t n, const i
                                            p_tilde, status, out, ctr, qa, q);
   k_cr_solve<<<blocks, 256, 0, s>>>(M, n, phase, rho_l, mom_l, rho_r, mom_r, maxit, rtol, status,
                                     out, ctr, q);
+}
+
+constexpr int CR_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+int* g_scratch_ptr[CR_MAX_DEVICES] = {};
+
+// Device address of this device's scratch (looked up once per device, with
+// that device current); nullptr on failure.
+int* cr_scratch_ptr(int dev) {
+  if (dev < 0 || dev >= CR_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    g_scratch_ptr[dev] = (int*)ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
+}  // namespace
+}  // namespace imexds
+
+extern "C" int imexds_creation_rp(const imexds_material* mat, int32_t n, const int32_t* phase,
+                                  const double* rho_l, const double* mom_l, const double* rho_r,
+                                  const double* mom_r, double p_min, double p_tilde, int32_t maxit,
+                                  double rtol, int32_t* status, double* out, void* hip_stream) {
+  using namespace imexds;
+  Mat M;
+  if (!cr_prepare(mat, n, maxit, rtol, p_min, p_tilde, M)) return IMEXDS_ERR_INVALID_ARG;
+  if (n == 0) return IMEXDS_OK;
+  if (!phase || !rho_l || !mom_l || !rho_r || !mom_r || !status || !out)
+    return IMEXDS_ERR_INVALID_ARG;
+  // scratch: four queue counters and two queues of n problem indices,
+  // stream-ordered, released after the solve pass
+  hipStream_t s = (hipStream_t)hip_stream;
+  int* buf = nullptr;
+  const size_t bytes = sizeof(int) * (2 * (size_t)n + 4);
+  if (hipMallocAsync((void**)&buf, bytes, s) != hipSuccess) return IMEXDS_ERR_OOM;
+  cr_launch(M, n, phase, rho_l, mom_l, rho_r, mom_r, p_min, p_tilde, maxit, rtol, status, out,
+            buf, s);
   const hipError_t le = hipGetLastError();
-  const hipError_t fe = hipFreeAsync(scratch, s);
+  const hipError_t fe = hipFreeAsync(buf, s);
   if (le != hipSuccess || fe != hipSuccess) return IMEXDS_ERR_HIP;
+  return IMEXDS_OK;
+}
+
+extern "C" int imexds_creation_rp_noalloc(const imexds_material* mat, int32_t n,
+                                          const int32_t* phase, const double* rho_l,
+                                          const double* mom_l, const double* rho_r,
+                                          const double* mom_r, double p_min, double p_tilde,
+                                          int32_t maxit, double rtol, int32_t* status,
+                                          double* out, void* hip_stream) {
+  using namespace imexds;
+  Mat M;
+  if (!cr_prepare(mat, n, maxit, rtol, p_min, p_tilde, M)) return IMEXDS_ERR_INVALID_ARG;
+  if (n > IMEXDS_CR_NOALLOC_MAX) return IMEXDS_ERR_TOO_LARGE;
+  if (n == 0) return IMEXDS_OK;
+  if (!phase || !rho_l || !mom_l || !rho_r || !mom_r || !status || !out)
+    return IMEXDS_ERR_INVALID_ARG;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return IMEXDS_ERR_HIP;
+  int* scratch_dev = cr_scratch_ptr(dev);
+  if (!scratch_dev) return IMEXDS_ERR_HIP;
+  cr_launch(M, n, phase, rho_l, mom_l, rho_r, mom_r, p_min, p_tilde, maxit, rtol, status, out,
+            scratch_dev, (hipStream_t)hip_stream);
+  if (hipGetLastError() != hipSuccess) return IMEXDS_ERR_HIP;
   return IMEXDS_OK;
 }

@@ -693,6 +693,7 @@ const char* imexds_strerror(int code) {
     case IMEXDS_ERR_HIP: return g_err[0] ? g_err : "HIP runtime error";
     case IMEXDS_ERR_NO_STATE: return "no state loaded (call imexds_set_state first)";
     case IMEXDS_ERR_UNSUPPORTED: return "unsupported configuration";
+    case IMEXDS_ERR_TOO_LARGE: return "size above the entry point's fixed maximum";
     default: return "unknown error";
   }
 }

@@ -29,7 +29,7 @@ def test_header_declares_the_entry_points():
                  "imexds_eu_get_state", "imexds_eu_get_problems", "imexds_eu_destroy"):
         assert name in d
     assert not set(d) & set(declared())
-    assert declared(HDR_CR) == ["imexds_creation_rp"]
+    assert declared(HDR_CR) == ["imexds_creation_rp", "imexds_creation_rp_noalloc"]
     d = declared(HDR_CT)
     for name in ("imexds_ct_create", "imexds_ct_set_state", "imexds_ct_step", "imexds_ct_run",
                  "imexds_ct_get_state", "imexds_ct_get_problems", "imexds_ct_destroy"):
