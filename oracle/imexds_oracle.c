@@ -1086,6 +1086,48 @@ static int or_zone_fluxes(const or_material *M, const or_params *P, const or_zon
 
 static int or_state_ok(real r, real m) { return r > 0.0 && isfinite(r) && isfinite(m); }
 
+#ifdef OR_TANGENT
+#define OR_VAL(x) ((x).v)
+#else
+#define OR_VAL(x) (x)
+#endif
+
+/* Start of the interface solve of a dual time pass.  The paper fixes the
+ * solver (Newton-Armijo to a tolerance, Appendix A), not where it starts
+ * inside the dual time loop; the root it returns is the same to round-off.
+ * hist[0..2] hold the roots of the three previous passes, newest first
+ * (nh of them recorded).  With fewer than three the start is the previous
+ * root (pw).  From the fourth pass on the roots settle geometrically with
+ * the pseudo iterates, and each unknown is extrapolated one pass ahead:
+ * a + (d1 / d0) d1 with a the newest root, d1 = a - (the one before),
+ * d0 = (the one before) - (the one before that), when |d1| < |d0| (the
+ * differences contract); otherwise that unknown starts at a.  The ratio is
+ * taken from values only, so in the tangent build the start is a fixed
+ * linear combination of earlier roots. */
+static void or_dts_start(const real *pw, real hist[3][2], int nh, real *g) {
+  int j;
+  for (j = 0; j < 2; ++j) {
+    g[j] = pw[j];
+    if (nh >= 3) {
+      real a = hist[0][j], d1 = hist[0][j] - hist[1][j], d0 = hist[1][j] - hist[2][j];
+      if (fabs(OR_VAL(d1)) < fabs(OR_VAL(d0))) {
+        double q = OR_VAL(d1) / OR_VAL(d0);
+        g[j] = a + (real)q * d1;
+      }
+    }
+  }
+}
+
+static void or_dts_record(real hist[3][2], int *nh, const real *root) {
+  int j;
+  for (j = 0; j < 2; ++j) {
+    hist[2][j] = hist[1][j];
+    hist[1][j] = hist[0][j];
+    hist[0][j] = root[j];
+  }
+  if (*nh < 3) ++*nh;
+}
+
 /* Algorithm 2 on one zone. Returns 0 on success, or a status bit.
  * *shrink_cell is set when a moving cell fell below half of its predicted
  * end-of-step length (the length its pseudo step was sized for).
@@ -1142,10 +1184,16 @@ static int or_zone_dts(const or_material *M, const or_params *P, const or_zone *
   } while (0)
 #endif
   int cnt = 0, stop = 0;
+  real hist[3][2], g[2];
+  int nh = 0;
   /* Part 1: pseudo-time iterations (exactly force_count of them in a replay) */
   int lmax = force_count > 0 ? force_count : P->lmax;
   for (l = 0; l < lmax; ++l) {
-    if (!or_zone_fluxes(M, P, Z, W, F, pw, &w)) return OR_ST_NEWTON;
+    or_dts_start(pw, hist, nh, g);
+    if (!or_zone_fluxes(M, P, Z, W, F, g, &w)) return OR_ST_NEWTON;
+    pw[0] = g[0];
+    pw[1] = g[1];
+    or_dts_record(hist, &nh, g);
     OR_TRACE_ITER();
     for (c = 0; c < m; ++c) {
       hnew[c] = Z->hn[c] + ((double)Z->mov[c] * w) * dt;
@@ -1195,7 +1243,10 @@ static int or_zone_dts(const or_material *M, const or_params *P, const or_zone *
   if (!stop) *lmax_hit = 1;
   *count = cnt;
   /* Part 2: fluxes from the accepted iterate, conservative update */
-  if (!or_zone_fluxes(M, P, Z, W, F, pw, &w)) return OR_ST_NEWTON;
+  or_dts_start(pw, hist, nh, g);
+  if (!or_zone_fluxes(M, P, Z, W, F, g, &w)) return OR_ST_NEWTON;
+  pw[0] = g[0];
+  pw[1] = g[1];
   OR_TRACE_ITER();
 #ifndef OR_TANGENT
   if (tr && tr->cap >= 8) {

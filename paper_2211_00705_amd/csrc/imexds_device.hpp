@@ -518,4 +518,39 @@ __device__ __forceinline__ bool d_iface_solve(const Mat& M, int maxit, double rt
                                 0, out);
 }
 
+// Start of the interface solve of the next dual time pass.  The solver's
+// root does not depend on where it starts (to round-off); the start only
+// decides how many Newton steps it takes.  The roots of the last three passes
+// (r0 newest, then r1, r2; nh of them recorded since the zone was set up)
+// settle geometrically with the pseudo iterates: with fewer than three the
+// start is the newest root, else each unknown is extrapolated one pass ahead,
+// r0 + (d1 / d0) d1 with d1 = r0 - r1, d0 = r1 - r2, when |d1| < |d0|, and
+// starts at r0 otherwise.
+struct DtsRoots {
+  double r0l, r0r, r1l, r1r, r2l, r2r;
+  int nh;
+};
+
+__device__ __forceinline__ void d_dts_reset(DtsRoots& H) { H.nh = 0; }
+
+// Records the newest root and returns the start of the next pass.
+__device__ __forceinline__ void d_dts_record(DtsRoots& H, double pl, double pr, double& gl,
+                                             double& gr) {
+  H.r2l = H.r1l;
+  H.r2r = H.r1r;
+  H.r1l = H.r0l;
+  H.r1r = H.r0r;
+  H.r0l = pl;
+  H.r0r = pr;
+  if (H.nh < 3) ++H.nh;
+  gl = pl;
+  gr = pr;
+  if (H.nh >= 3) {
+    const double d1l = H.r0l - H.r1l, d0l = H.r1l - H.r2l;
+    const double d1r = H.r0r - H.r1r, d0r = H.r1r - H.r2r;
+    if (fabs(d1l) < fabs(d0l)) gl = H.r0l + (d1l / d0l) * d1l;
+    if (fabs(d1r) < fabs(d0r)) gr = H.r0r + (d1r / d0r) * d1r;
+  }
+}
+
 }  // namespace imexds

@@ -214,6 +214,10 @@ __global__ __launch_bounds__(64) void k_zone(StepArgs A, int if_begin, int if_en
   double th_f = 0.0, it_f = 0.0;  // theta and 1/(1+theta) of a fixed full cell
   double W0[MC], W1[MC];
   double pw0 = 0.0, pw1 = 0.0;
+  // start of the next pass's interface solve and the roots it comes from
+  double gn0 = 0.0, gn1 = 0.0;
+  DtsRoots H;
+  d_dts_reset(H);
   int l = 0, cnt = 0;
   bool stop = false;
   int row = -1;
@@ -326,8 +330,8 @@ __global__ __launch_bounds__(64) void k_zone(StepArgs A, int if_begin, int if_en
         }
       }
       hg = pred ? warm != 0 : true;
-      g0 = pred ? rpw0 : pw0;
-      g1 = pred ? rpw1 : pw1;
+      g0 = pred ? rpw0 : gn0;
+      g1 = pred ? rpw1 : gn1;
     }
     IfaceOut o;
     const bool ok = d_iface_solve(M, P.newton_maxit, P.newton_rtol, phl, ql0, ql1, phr, qr0, qr1,
@@ -366,6 +370,7 @@ __global__ __launch_bounds__(64) void k_zone(StepArgs A, int if_begin, int if_en
       const bool part2 = stop || (l == P.lmax);
       pw0 = o.pl;
       pw1 = o.pr;
+      d_dts_record(H, pw0, pw1, gn0, gn1);
       const double w = o.w;
       if (A.tape) {  // W^l and its interface root
         double* e = A.tape + k * A.tape_stride + TAPE_HDR + (long long)l * (2 * MC + 2);
@@ -537,6 +542,9 @@ __global__ __launch_bounds__(64) void k_zone(StepArgs A, int if_begin, int if_en
         if (bad) status = ST_MESH;
         pw0 = Ipl;
         pw1 = Ipr;
+        gn0 = Ipl;
+        gn1 = Ipr;
+        d_dts_reset(H);
         l = 0;
         cnt = 0;
         stop = false;

@@ -97,6 +97,11 @@ __global__ __launch_bounds__(64) void k_zone8(StepArgs A, int if_begin, int if_e
   int skip = -1, into = -1, ic = 0, tiny = 0, l = 0, cnt = 0;
   double FL0 = 0.0, FL1 = 0.0, FR0 = 0.0, FR1 = 0.0, Ipl = 0.0, Ipr = 0.0, wp = 0.0;
   double pw0 = 0.0, pw1 = 0.0, hh_l = 0.0, hh_r = 0.0;
+  // start of the next pass's interface solve and the roots it comes from
+  // (identical on the group's lanes)
+  double gn0 = 0.0, gn1 = 0.0;
+  DtsRoots H;
+  d_dts_reset(H);
   // per lane: U^n of zone position c, and the active cell c
   double Ur = 1.0, Um = 0.0;
   int pos = -1;  // zone position of active cell c (-1: lane idle)
@@ -224,7 +229,7 @@ __global__ __launch_bounds__(64) void k_zone8(StepArgs A, int if_begin, int if_e
     if (side >= 0) {
       const double x0 = pred ? Ur : W0, x1 = pred ? Um : W1;
       const bool hg = pred ? warm != 0 : true;
-      const double g0 = pred ? rpw0 : pw0, g1 = pred ? rpw1 : pw1;
+      const double g0 = pred ? rpw0 : gn0, g1 = pred ? rpw1 : gn1;
       const int partner = gb + (side == 0 ? a0 + 1 : a0);
       okl = d_iface_solve_t<true>(M, P.newton_maxit, P.newton_rtol, phl, x0, x1, phr, x0, x1, hg,
                                   g0, g1, side, partner, o)
@@ -269,6 +274,7 @@ __global__ __launch_bounds__(64) void k_zone8(StepArgs A, int if_begin, int if_e
       const bool part2 = stop || (l == P.lmax);
       pw0 = opl;
       pw1 = opr;
+      d_dts_record(H, pw0, pw1, gn0, gn1);
       const double w = ow;
       if (A.tape) {  // W^l (by zone position) and its interface root
         double* e = A.tape + k * A.tape_stride + TAPE_HDR + (long long)l * (2 * MC + 2);
@@ -442,6 +448,9 @@ __global__ __launch_bounds__(64) void k_zone8(StepArgs A, int if_begin, int if_e
         if (bad) status = ST_MESH;
         pw0 = Ipl;
         pw1 = Ipr;
+        gn0 = Ipl;
+        gn1 = Ipr;
+        d_dts_reset(H);
         l = 0;
         cnt = 0;
         stop = false;
