@@ -24,7 +24,7 @@
  *   0 on success, a negative IMEXDS_ERR_* code otherwise (imexds_strerror
  *   names it).  Nothing aborts; no C++ exception crosses the ABI.  A failure
  *   of one problem (Newton not converging, non-physical state, mesh failure,
- *   overlapping zones) does not fail the call: that problem is frozen and its
+ *   overlapping zones, a vanishing phase) does not fail the call: that problem is frozen and its
  *   IMEXDS_ST_* bits show in its status word (imexds_get_problems).
  * Pointers: "device" pointers are HIP device memory on the context's device
  *   (e.g. torch tensors on cuda), "host" pointers are ordinary memory.  The
@@ -56,7 +56,10 @@ extern "C" {
 #define IMEXDS_ST_NEWTON_FAIL 1  /* interface Newton-Armijo did not converge */
 #define IMEXDS_ST_NONPHYSICAL 2  /* rho <= 0 or non-finite state */
 #define IMEXDS_ST_MESH_FAIL 4    /* a cut piece collapsed / could not merge */
-#define IMEXDS_ST_ZONE_OVERLAP 8 /* two implicit zones would overlap */
+#define IMEXDS_ST_ZONE_OVERLAP 8 /* implicit zones overlap outside a pair (three in a row,
+                                    or any overlap under IMEXDS_ZONE_NEWTON) */
+#define IMEXDS_ST_PHASE_VANISH 16 /* a merge would leave the phase between two phase
+                                     boundaries as one cell bounded by both */
 
 /* per-step, per-interface log flags (imexds_get_log) */
 #define IMEXDS_FL_TINY_RIGHT 1 /* the smaller cut piece is right of the interface */
@@ -67,6 +70,7 @@ extern "C" {
 #define IMEXDS_FL_CROSS_R 32   /* interface moved into the right neighbour cell */
 #define IMEXDS_FL_FAIL 64      /* the zone failed this step (status set) */
 #define IMEXDS_FL_INACTIVE 128 /* problem frozen or finished: nothing done */
+#define IMEXDS_FL_PAIR 256     /* solved in one zone with the neighbouring interface */
 
 /* dual-time stopping rules (Algorithm 2, "Stopping criterium"):
  * IMEXDS_TOL_PAPER: the residual of Sec. 4 (Numerical results),
@@ -120,8 +124,13 @@ typedef struct {
  * slots of the flat state arrays, problems in order.  phase_first[p] is the
  * phase of the problem's first slot (0 liquid, 1 vapour); phases alternate
  * across interfaces; home cells of one problem must increase strictly, at
- * most 64 interfaces per problem.  Implicit zones that overlap do not fail
- * the call: the problem gets IMEXDS_ST_ZONE_OVERLAP and stays frozen. */
+ * most 64 interfaces per problem.  With Algorithm 2, two neighbouring
+ * interfaces whose implicit zones overlap are solved in one zone holding both
+ * phase boundaries (log flag IMEXDS_FL_PAIR); a merge there that would leave
+ * the phase between them as a single cell freezes the problem with
+ * IMEXDS_ST_PHASE_VANISH.  Any other overlap (three zones in a row, or the
+ * Newton zone solver) freezes it with IMEXDS_ST_ZONE_OVERLAP.  Neither fails
+ * the call. */
 typedef struct {
   int32_t n_problems;
   const int32_t *n_cells;
@@ -151,6 +160,8 @@ typedef struct {
                              moved into a neighbouring background cell */
   double gpu_ms;          /* device time of the imexds_step / imexds_run /
                              imexds_step_per_problem calls (HIP events) */
+  int64_t pair_zones;     /* zone steps solved as one zone holding the two phase
+                             boundaries of neighbouring interfaces */
 } imexds_stats;
 
 /* Creates a context on the current HIP device for the problem statement of

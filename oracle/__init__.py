@@ -23,9 +23,9 @@ LIB_TAN = os.path.join(_HERE, "liboracle_imexds_tan.so")
 # library's log (OR_PLAIN; see the source's header)
 LIB_PLAIN = os.path.join(_HERE, "liboracle_imexds_plain.so")
 
-ST_NEWTON, ST_NONPHYS, ST_MESH, ST_OVERLAP = 1, 2, 4, 8
+ST_NEWTON, ST_NONPHYS, ST_MESH, ST_OVERLAP, ST_VANISH = 1, 2, 4, 8, 16
 FL_TINY_RIGHT, FL_MERGED, FL_REDO, FL_LMAX = 1, 2, 4, 8
-FL_CROSS_L, FL_CROSS_R, FL_FAIL, FL_INACTIVE = 16, 32, 64, 128
+FL_CROSS_L, FL_CROSS_R, FL_FAIL, FL_INACTIVE, FL_PAIR = 16, 32, 64, 128, 256
 
 
 def build():

@@ -90,6 +90,7 @@ typedef double real;
 #define OR_ST_NONPHYS 2
 #define OR_ST_MESH 4
 #define OR_ST_OVERLAP 8
+#define OR_ST_VANISH 16
 
 #define OR_FL_TINY_RIGHT 1
 #define OR_FL_MERGED 2
@@ -99,6 +100,7 @@ typedef double real;
 #define OR_FL_CROSS_R 32
 #define OR_FL_FAIL 64
 #define OR_FL_INACTIVE 128
+#define OR_FL_PAIR 256
 
 #define OR_MAXC 32
 
@@ -946,6 +948,13 @@ typedef struct {
   int ic;   /* phase boundary lies between active cells ic and ic+1 */
   int tiny; /* active index of the tiny (or merged) cell */
   real FL[2], FR[2];
+  /* phase boundaries in the zone (one, or two when the zones of two
+   * neighbouring interfaces overlap): per boundary its cells and tiny cell
+   * (icb[0], tinyb[0] are ic, tiny); per active cell the boundary that moves
+   * it (bnd, -1 for a cell that does not move) */
+  int nb;
+  int icb[2], tinyb[2];
+  int bnd[OR_MAXC];
 } or_zone;
 
 typedef struct {
@@ -980,30 +989,54 @@ static void or_zone_range(const or_params *P, const or_prob *pb, int k, int *zlo
   *tiny_right = tr;
 }
 
-/* zone set-up: active cells, lengths, merge, pseudo-step fractions */
-static int or_zone_build(const or_material *M, const or_params *P, const or_prob *pb, int k,
-                         const int *ph, int zlo, int zhi, int tiny_right, int merge, real w,
-                         real dt, or_zone *Z) {
+/* zone set-up: active cells, lengths, merge, pseudo-step fractions, for a
+ * zone with nb phase boundaries (interfaces kb[0..nb-1], left to right),
+ * each with its tiny side (trb), merge decision (mergeb) and predicted speed
+ * (wb).  Returns 1, or 0 if the zone cannot be built; *vanish is set when
+ * a merge of a two-boundary zone would leave the phase between the two
+ * boundaries as a single cell bounded by both (the tiny piece would merge
+ * into a piece of the other boundary's cut cell, or both tiny pieces into
+ * the same cell): that phase is about to vanish. */
+static int or_zone_build_n(const or_material *M, const or_params *P, const or_prob *pb, int nb,
+                           const int *kb, const int *ph, int zlo, int zhi, const int *trb,
+                           const int *mergeb, const real *wb, real dt, or_zone *Z, int *vanish) {
   int ns = pb->n + pb->nif;
-  int sL = pb->home[k] + k, sR = sL + 1;
   real h = pb->h;
-  real hL = pb->hl[k], hR = h - hL;
-  int skip = -1, into = -1;
-  if (merge) {
-    if (!tiny_right) {
-      skip = sL;
-      into = sL - 1;
-    } else {
-      skip = sR;
-      into = sR + 1;
+  int sL[2], sR[2], skip[2] = {-1, -1}, into[2] = {-1, -1};
+  real hL[2], hR[2];
+  int b;
+  *vanish = 0;
+  for (b = 0; b < nb; ++b) {
+    sL[b] = pb->home[kb[b]] + kb[b];
+    sR[b] = sL[b] + 1;
+    hL[b] = pb->hl[kb[b]];
+    hR[b] = h - hL[b];
+    if (mergeb[b]) {
+      if (!trb[b]) {
+        skip[b] = sL[b];
+        into[b] = sL[b] - 1;
+      } else {
+        skip[b] = sR[b];
+        into[b] = sR[b] + 1;
+      }
+      if (into[b] < zlo || into[b] > zhi || into[b] < 0 || into[b] >= ns) return 0;
     }
-    if (into < zlo || into > zhi || into < 0 || into >= ns) return 0;
+  }
+  if (nb == 2) {
+    if (sR[0] >= sL[1]) *vanish = 1; /* two boundaries in one background cell */
+    for (b = 0; b < 2; ++b)
+      if (into[b] >= 0 && (into[b] == sL[1 - b] || into[b] == sR[1 - b])) *vanish = 1;
+    if (into[0] >= 0 && into[0] == into[1]) *vanish = 1;
+    if (*vanish) return 0;
   }
   int m = 0, s;
-  Z->ic = -1;
-  Z->tiny = -1;
+  Z->nb = nb;
+  for (b = 0; b < 2; ++b) {
+    Z->icb[b] = -1;
+    Z->tinyb[b] = -1;
+  }
   for (s = zlo; s <= zhi; ++s) {
-    if (s == skip) continue;
+    if (s == skip[0] || s == skip[1]) continue;
     if (m >= OR_MAXC) return 0;
     Z->slot[m] = s;
     Z->ph[m] = ph[s];
@@ -1011,38 +1044,54 @@ static int or_zone_build(const or_material *M, const or_params *P, const or_prob
     Z->U0[m][1] = pb->mom[s];
     Z->hn[m] = h;
     Z->mov[m] = 0;
-    if (s == sL) {
-      Z->hn[m] = hL;
-      Z->mov[m] = 1;
-    } else if (s == sR) {
-      Z->hn[m] = hR;
-      Z->mov[m] = -1;
+    Z->bnd[m] = -1;
+    for (b = 0; b < nb; ++b) {
+      if (s == sL[b]) {
+        Z->hn[m] = hL[b];
+        Z->mov[m] = 1;
+        Z->bnd[m] = b;
+      } else if (s == sR[b]) {
+        Z->hn[m] = hR[b];
+        Z->mov[m] = -1;
+        Z->bnd[m] = b;
+      }
     }
-    if (s == into) {
-      real ht = tiny_right ? hR : hL;
-      real hm = h + ht;
-      Z->U0[m][0] = (h * pb->rho[s] + ht * pb->rho[skip]) / hm;
-      Z->U0[m][1] = (h * pb->mom[s] + ht * pb->mom[skip]) / hm;
-      Z->hn[m] = hm;
-      Z->mov[m] = tiny_right ? -1 : 1;
+    for (b = 0; b < nb; ++b) {
+      if (s == into[b]) {
+        real ht = trb[b] ? hR[b] : hL[b];
+        real hm = h + ht;
+        Z->U0[m][0] = (h * pb->rho[s] + ht * pb->rho[skip[b]]) / hm;
+        Z->U0[m][1] = (h * pb->mom[s] + ht * pb->mom[skip[b]]) / hm;
+        Z->hn[m] = hm;
+        Z->mov[m] = trb[b] ? -1 : 1;
+        Z->bnd[m] = b;
+      }
     }
     ++m;
   }
   Z->m = m;
   for (s = 0; s < m; ++s) {
-    if (Z->mov[s] == 1) Z->ic = s;
-    int is_t = merge ? (Z->slot[s] == into) : (Z->slot[s] == (tiny_right ? sR : sL));
-    if (is_t) Z->tiny = s;
+    for (b = 0; b < nb; ++b) {
+      if (Z->mov[s] == 1 && Z->bnd[s] == b) Z->icb[b] = s;
+      int is_t = mergeb[b] ? (Z->slot[s] == into[b]) : (Z->slot[s] == (trb[b] ? sR[b] : sL[b]));
+      if (is_t) Z->tinyb[b] = s;
+    }
   }
-  if (Z->ic < 0 || Z->ic + 1 >= m || Z->tiny < 0) return 0;
+  for (b = 0; b < nb; ++b)
+    if (Z->icb[b] < 0 || Z->icb[b] + 1 >= m || Z->tinyb[b] < 0) return 0;
+  Z->ic = Z->icb[0];
+  Z->tiny = Z->tinyb[0];
   for (s = 0; s < m; ++s) {
-    real hh = Z->hn[s] + ((double)Z->mov[s] * w) * dt;
+    real wv = wb[Z->bnd[s] >= 0 ? Z->bnd[s] : 0];
+    real hh = Z->hn[s] + ((double)Z->mov[s] * wv) * dt;
     real th = hh / h;
     if (th > P->theta_nb) th = P->theta_nb;
     Z->hh[s] = hh;
     Z->th[s] = th;
     Z->i1t[s] = 1.0 / (1.0 + th);
-    Z->thr[s] = (s == Z->tiny ? P->tol_tiny : P->tol_nb) * (th * dt);
+    int is_tiny = 0;
+    for (b = 0; b < nb; ++b) is_tiny = is_tiny || s == Z->tinyb[b];
+    Z->thr[s] = (is_tiny ? P->tol_tiny : P->tol_nb) * (th * dt);
     if (!(th > 0.0)) return 0;
   }
   /* bounding fluxes from U^n (Algorithm 1, Step 1: F_left / F_right) */
@@ -1057,8 +1106,18 @@ static int or_zone_build(const or_material *M, const or_params *P, const or_prob
   return 1;
 }
 
-/* face fluxes of a zone iterate W; the phase-boundary face uses the
- * interface Riemann solver, all other inner faces HLL. */
+/* the zone of one interface */
+static int or_zone_build(const or_material *M, const or_params *P, const or_prob *pb, int k,
+                         const int *ph, int zlo, int zhi, int tiny_right, int merge, real w,
+                         real dt, or_zone *Z) {
+  int vanish = 0;
+  return or_zone_build_n(M, P, pb, 1, &k, ph, zlo, zhi, &tiny_right, &merge, &w, dt, Z, &vanish);
+}
+
+/* face fluxes of a zone iterate W; each phase-boundary face uses the
+ * interface Riemann solver (boundary b starts from pw[2b], pw[2b+1] and
+ * leaves its root there and its speed in wout[b]), all other inner faces
+ * HLL. */
 static int or_zone_fluxes(const or_material *M, const or_params *P, const or_zone *Z,
                           real W[][2], real F[][2], real *pw, real *wout) {
   int c;
@@ -1067,14 +1126,16 @@ static int or_zone_fluxes(const or_material *M, const or_params *P, const or_zon
   F[Z->m][0] = Z->FR[0];
   F[Z->m][1] = Z->FR[1];
   for (c = 0; c + 1 < Z->m; ++c) {
-    if (c == Z->ic) {
+    int b = c == Z->icb[0] ? 0 : ((Z->nb == 2 && c == Z->icb[1]) ? 1 : -1);
+    if (b >= 0) {
       or_iface I;
       if (!or_iface_solve(M, Z->ph[c], W[c][0], W[c][1], Z->ph[c + 1], W[c + 1][0],
-                              W[c + 1][1], 1, pw[0], pw[1], P->newton_maxit, P->newton_rtol, &I))
+                              W[c + 1][1], 1, pw[2 * b], pw[2 * b + 1], P->newton_maxit,
+                              P->newton_rtol, &I))
         return 0;
-      pw[0] = I.pl;
-      pw[1] = I.pr;
-      *wout = I.w;
+      pw[2 * b] = I.pl;
+      pw[2 * b + 1] = I.pr;
+      wout[b] = I.w;
       F[c + 1][0] = I.F0;
       F[c + 1][1] = I.F1;
     } else {
@@ -1142,8 +1203,8 @@ static int or_zone_dts(const or_material *M, const or_params *P, const or_zone *
                        real *pw, real U1[][2], real *wstar, int *count, int *lmax_hit,
                        int *shrink_cell, int force_count, or_trace *tr) {
   real W[OR_MAXC][2], Wn[OR_MAXC][2], F[OR_MAXC + 1][2], hnew[OR_MAXC], ih[OR_MAXC];
-  int c, l, m = Z->m;
-  real w = 0.0;
+  int c, l, m = Z->m, b;
+  real w[2] = {0.0, 0.0};
   *shrink_cell = -1;
   *lmax_hit = 0;
   for (c = 0; c < m; ++c) {
@@ -1179,24 +1240,27 @@ static int or_zone_dts(const or_material *M, const or_params *P, const or_zone *
         or_tr_put(tr, W[c_][0]);             \
         or_tr_put(tr, W[c_][1]);             \
       }                                      \
-      or_tr_put(tr, w);                      \
+      or_tr_put(tr, w[0]);                   \
     }                                        \
   } while (0)
 #endif
   int cnt = 0, stop = 0;
-  real hist[3][2], g[2];
-  int nh = 0;
+  /* per boundary: the roots of the last passes and the next start */
+  real hist[2][3][2], g[4];
+  int nh[2] = {0, 0};
   /* Part 1: pseudo-time iterations (exactly force_count of them in a replay) */
   int lmax = force_count > 0 ? force_count : P->lmax;
   for (l = 0; l < lmax; ++l) {
-    or_dts_start(pw, hist, nh, g);
-    if (!or_zone_fluxes(M, P, Z, W, F, g, &w)) return OR_ST_NEWTON;
-    pw[0] = g[0];
-    pw[1] = g[1];
-    or_dts_record(hist, &nh, g);
+    for (b = 0; b < Z->nb; ++b) or_dts_start(pw + 2 * b, hist[b], nh[b], g + 2 * b);
+    if (!or_zone_fluxes(M, P, Z, W, F, g, w)) return OR_ST_NEWTON;
+    for (b = 0; b < Z->nb; ++b) {
+      pw[2 * b] = g[2 * b];
+      pw[2 * b + 1] = g[2 * b + 1];
+      or_dts_record(hist[b], &nh[b], g + 2 * b);
+    }
     OR_TRACE_ITER();
     for (c = 0; c < m; ++c) {
-      hnew[c] = Z->hn[c] + ((double)Z->mov[c] * w) * dt;
+      hnew[c] = Z->hn[c] + ((double)Z->mov[c] * w[Z->bnd[c] >= 0 ? Z->bnd[c] : 0]) * dt;
       ih[c] = 1.0 / hnew[c];
       if (Z->mov[c] != 0 && !(hnew[c] >= 0.5 * Z->hh[c])) {
         *shrink_cell = c;
@@ -1243,10 +1307,12 @@ static int or_zone_dts(const or_material *M, const or_params *P, const or_zone *
   if (!stop) *lmax_hit = 1;
   *count = cnt;
   /* Part 2: fluxes from the accepted iterate, conservative update */
-  or_dts_start(pw, hist, nh, g);
-  if (!or_zone_fluxes(M, P, Z, W, F, g, &w)) return OR_ST_NEWTON;
-  pw[0] = g[0];
-  pw[1] = g[1];
+  for (b = 0; b < Z->nb; ++b) or_dts_start(pw + 2 * b, hist[b], nh[b], g + 2 * b);
+  if (!or_zone_fluxes(M, P, Z, W, F, g, w)) return OR_ST_NEWTON;
+  for (b = 0; b < Z->nb; ++b) {
+    pw[2 * b] = g[2 * b];
+    pw[2 * b + 1] = g[2 * b + 1];
+  }
   OR_TRACE_ITER();
 #ifndef OR_TANGENT
   if (tr && tr->cap >= 8) {
@@ -1257,7 +1323,7 @@ static int or_zone_dts(const or_material *M, const or_params *P, const or_zone *
 #endif
 #undef OR_TRACE_ITER
   for (c = 0; c < m; ++c) {
-    hnew[c] = Z->hn[c] + ((double)Z->mov[c] * w) * dt;
+    hnew[c] = Z->hn[c] + ((double)Z->mov[c] * w[Z->bnd[c] >= 0 ? Z->bnd[c] : 0]) * dt;
     ih[c] = 1.0 / hnew[c];
     if (Z->mov[c] != 0 && !(hnew[c] >= 0.5 * Z->hh[c])) {
       *shrink_cell = c;
@@ -1274,7 +1340,7 @@ static int or_zone_dts(const or_material *M, const or_params *P, const or_zone *
 #endif
     if (!or_state_ok(U1[c][0], U1[c][1])) return OR_ST_NONPHYS;
   }
-  *wstar = w;
+  for (b = 0; b < Z->nb; ++b) wstar[b] = w[b];
   return 0;
 }
 
@@ -1464,60 +1530,84 @@ static int or_zone_newton(const or_material *M, const or_params *P, const or_zon
 }
 #endif
 
-/* Predict, merge, solve and re-align one interface zone. Writes the zone's
- * new cell values into (rn, mn). Returns 0 or a status bit. */
-static int or_zone_step(const or_material *M, const or_params *P, or_prob *pb, int k,
-                        const int *ph, real dt, real *rn, real *mn, or_zlog *lg) {
-  int ns = pb->n + pb->nif;
-  int sL = pb->home[k] + k, sR = sL + 1;
+/* Predict, merge, solve and re-align one zone: the zone of interface kb[0]
+ * (nb = 1), or the zone of the two neighbouring interfaces kb[0], kb[1]
+ * whose zones overlap (nb = 2: their union, zlo..zhi, solved as one, with
+ * both phase boundaries).  Writes the zone's new cell values into (rn, mn)
+ * and each interface's log into lg[0..nb-1].  Returns 0 or a status bit. */
+static int or_zone_step(const or_material *M, const or_params *P, or_prob *pb, int nb,
+                        const int *kb, const int *ph, int zlo, int zhi, real dt, real *rn,
+                        real *mn, or_zlog *lg) {
   real h = pb->h;
-  int zlo, zhi, tr;
-  or_zone_range(P, pb, k, &zlo, &zhi, &tr);
-  lg->zlo = zlo;
-  lg->flags = tr ? OR_FL_TINY_RIGHT : 0;
-  lg->count = 0;
-  /* explicit prediction of the phase-boundary speed from U^n */
-  or_iface I;
-  if (!or_iface_solve(M, ph[sL], pb->rho[sL], pb->mom[sL], ph[sR], pb->rho[sR], pb->mom[sR],
-                          pb->warm[k], pb->pw[2 * k], pb->pw[2 * k + 1], P->newton_maxit,
-                          P->newton_rtol, &I))
-    return OR_ST_NEWTON;
-  real wp = I.w;
-  real ht = tr ? h - pb->hl[k] : pb->hl[k];
-  real rate = tr ? -wp : wp;
-  real hfl = P->alpha_floor * h;
-  int merge = (ht < hfl) || (ht + (P->merge_safety * rate) * dt < hfl);
-  int force = 0, rflags = 0;
-  if (pb->rp_count) {
-    force = pb->rp_count[k];
-    rflags = pb->rp_flags[k];
-    merge = (rflags & OR_FL_MERGED) != 0;
+  int b, sL[2], sR[2], tr[2], merge[2] = {0, 0};
+  real wp[2] = {0.0, 0.0};
+  or_iface I[2];
+  int force = 0, rflags[2] = {0, 0};
+  for (b = 0; b < nb; ++b) {
+    int lo, hi;
+    sL[b] = pb->home[kb[b]] + kb[b];
+    sR[b] = sL[b] + 1;
+    or_zone_range(P, pb, kb[b], &lo, &hi, &tr[b]);
+    lg[b].zlo = zlo;
+    lg[b].flags = (tr[b] ? OR_FL_TINY_RIGHT : 0) | (nb == 2 ? OR_FL_PAIR : 0);
+    lg[b].count = 0;
+  }
+  for (b = 0; b < nb; ++b) {
+    int k = kb[b];
+    /* explicit prediction of the phase-boundary speed from U^n */
+    if (!or_iface_solve(M, ph[sL[b]], pb->rho[sL[b]], pb->mom[sL[b]], ph[sR[b]], pb->rho[sR[b]],
+                        pb->mom[sR[b]], pb->warm[k], pb->pw[2 * k], pb->pw[2 * k + 1],
+                        P->newton_maxit, P->newton_rtol, &I[b]))
+      return OR_ST_NEWTON;
+    wp[b] = I[b].w;
+    real ht = tr[b] ? h - pb->hl[k] : pb->hl[k];
+    real rate = tr[b] ? -wp[b] : wp[b];
+    real hfl = P->alpha_floor * h;
+    merge[b] = (ht < hfl) || (ht + (P->merge_safety * rate) * dt < hfl);
+    if (pb->rp_count) {
+      force = pb->rp_count[k];
+      rflags[b] = pb->rp_flags[k];
+      merge[b] = (rflags[b] & OR_FL_MERGED) != 0;
+    }
   }
   int redo = 0;
   real U1[OR_MAXC][2];
-  real wstar = 0.0;
+  real wstar[2] = {0.0, 0.0};
   int count = 0, lmax_hit = 0;
   or_zone Z;
   for (;;) {
-    real pw[2] = {I.pl, I.pr};
-    if (!or_zone_build(M, P, pb, k, ph, zlo, zhi, tr, merge, wp, dt, &Z)) return OR_ST_MESH;
+    real pw[4] = {I[0].pl, I[0].pr, I[1].pl, I[1].pr};
+    int vanish = 0;
+    if (!or_zone_build_n(M, P, pb, nb, kb, ph, zlo, zhi, tr, merge, wp, dt, &Z, &vanish))
+      return vanish ? OR_ST_VANISH : OR_ST_MESH;
     int sc;
 #ifndef OR_TANGENT
     int st = P->zone_solver == 1
-                 ? or_zone_newton(M, P, &Z, dt, pw, U1, &wstar, &count, &lmax_hit, &sc)
-                 : or_zone_dts(M, P, &Z, dt, pw, U1, &wstar, &count, &lmax_hit, &sc, force,
-                               (pb->tr_on && k == pb->tr_k) ? pb->tr : NULL);
+                 ? or_zone_newton(M, P, &Z, dt, pw, U1, wstar, &count, &lmax_hit, &sc)
+                 : or_zone_dts(M, P, &Z, dt, pw, U1, wstar, &count, &lmax_hit, &sc, force,
+                               (pb->tr_on && kb[0] == pb->tr_k) ? pb->tr : NULL);
 #else
-    int st = or_zone_dts(M, P, &Z, dt, pw, U1, &wstar, &count, &lmax_hit, &sc, force, NULL);
+    int st = or_zone_dts(M, P, &Z, dt, pw, U1, wstar, &count, &lmax_hit, &sc, force, NULL);
 #endif
-    if (st == OR_ST_MESH && !merge && sc == Z.tiny) {
-      merge = 1;
-      redo = 1;
-      continue;
+    if (st == OR_ST_MESH) {
+      /* a tiny cell fell below half its predicted length: solve again with
+       * it merged (once per boundary) */
+      int again = 0;
+      for (b = 0; b < nb; ++b)
+        if (!merge[b] && sc == Z.tinyb[b]) {
+          merge[b] = 1;
+          again = 1;
+        }
+      if (again) {
+        redo = 1;
+        continue;
+      }
     }
     if (st) return st;
-    pb->pw[2 * k] = pw[0];
-    pb->pw[2 * k + 1] = pw[1];
+    for (b = 0; b < nb; ++b) {
+      pb->pw[2 * kb[b]] = pw[2 * b];
+      pb->pw[2 * kb[b] + 1] = pw[2 * b + 1];
+    }
     break;
   }
   int c;
@@ -1525,44 +1615,46 @@ static int or_zone_step(const or_material *M, const or_params *P, or_prob *pb, i
     rn[Z.slot[c]] = U1[c][0];
     mn[Z.slot[c]] = U1[c][1];
   }
-  real hln = pb->hl[k] + wstar * dt;
-  int fl = lg->flags;
-  if (merge) {
-    fl |= OR_FL_MERGED;
-    if (!tr) {
-      if (pb->rp_count ? (rflags & OR_FL_CROSS_L) != 0 : hln < 0.0) {
-        pb->home[k] -= 1;
-        pb->hl[k] = hln + h;
-        rn[sL] = rn[sR];
-        mn[sL] = mn[sR];
-        fl |= OR_FL_CROSS_L;
+  for (b = 0; b < nb; ++b) {
+    int k = kb[b];
+    real hln = pb->hl[k] + wstar[b] * dt;
+    int fl = lg[b].flags;
+    if (merge[b]) {
+      fl |= OR_FL_MERGED;
+      if (!tr[b]) {
+        if (pb->rp_count ? (rflags[b] & OR_FL_CROSS_L) != 0 : hln < 0.0) {
+          pb->home[k] -= 1;
+          pb->hl[k] = hln + h;
+          rn[sL[b]] = rn[sR[b]];
+          mn[sL[b]] = mn[sR[b]];
+          fl |= OR_FL_CROSS_L;
+        } else {
+          rn[sL[b]] = rn[sL[b] - 1];
+          mn[sL[b]] = mn[sL[b] - 1];
+          pb->hl[k] = hln;
+        }
       } else {
-        rn[sL] = rn[sL - 1];
-        mn[sL] = mn[sL - 1];
-        pb->hl[k] = hln;
+        if (pb->rp_count ? (rflags[b] & OR_FL_CROSS_R) != 0 : hln > h) {
+          pb->home[k] += 1;
+          pb->hl[k] = hln - h;
+          rn[sR[b]] = rn[sL[b]];
+          mn[sR[b]] = mn[sL[b]];
+          fl |= OR_FL_CROSS_R;
+        } else {
+          rn[sR[b]] = rn[sR[b] + 1];
+          mn[sR[b]] = mn[sR[b] + 1];
+          pb->hl[k] = hln;
+        }
       }
     } else {
-      if (pb->rp_count ? (rflags & OR_FL_CROSS_R) != 0 : hln > h) {
-        pb->home[k] += 1;
-        pb->hl[k] = hln - h;
-        rn[sR] = rn[sL];
-        mn[sR] = mn[sL];
-        fl |= OR_FL_CROSS_R;
-      } else {
-        rn[sR] = rn[sR + 1];
-        mn[sR] = mn[sR + 1];
-        pb->hl[k] = hln;
-      }
+      pb->hl[k] = hln;
     }
-  } else {
-    pb->hl[k] = hln;
+    pb->warm[k] = 1;
+    if (redo) fl |= OR_FL_REDO;
+    if (lmax_hit) fl |= OR_FL_LMAX;
+    lg[b].flags = fl;
+    lg[b].count = count;
   }
-  (void)ns;
-  pb->warm[k] = 1;
-  if (redo) fl |= OR_FL_REDO;
-  if (lmax_hit) fl |= OR_FL_LMAX;
-  lg->flags = fl;
-  lg->count = count;
   return 0;
 }
 
@@ -1612,18 +1704,30 @@ static void or_step(const or_material *M, const or_params *P, or_prob *pb, int *
     dt = rem;
     clipped = 1;
   }
-  /* zones: smaller cut piece +- Z slots; they must be disjoint */
+  /* zones: smaller cut piece +- Z slots.  With Algorithm 2, the zones of two
+   * neighbouring interfaces that overlap are solved as one zone (their
+   * union, both phase boundaries in it); any other overlap freezes the
+   * problem.  zmark: the first interface of the zone holding a slot. */
   for (s = 0; s < ns; ++s) zmark[s] = -1;
   int prev_hi = -1;
-  for (k = 0; k < pb->nif; ++k) {
-    int zlo, zhi, tr;
+  for (k = 0; k < pb->nif;) {
+    int zlo, zhi, tr, nbk = 1;
     or_zone_range(P, pb, k, &zlo, &zhi, &tr);
     if (zlo <= prev_hi) {
       *pb->status |= OR_ST_OVERLAP;
       return;
     }
+    if (k + 1 < pb->nif && P->zone_solver == 0) {
+      int zlo1, zhi1, tr1;
+      or_zone_range(P, pb, k + 1, &zlo1, &zhi1, &tr1);
+      if (zlo1 <= zhi) {
+        nbk = 2;
+        zhi = zhi1;
+      }
+    }
     prev_hi = zhi;
     for (s = zlo; s <= zhi; ++s) zmark[s] = k;
+    k += nbk;
   }
   /* Algorithm 1, Step 1: explicit update of every cell outside the zones */
   real lam = dt / pb->h;
@@ -1646,22 +1750,37 @@ static void or_step(const or_material *M, const or_params *P, or_prob *pb, int *
   }
   /* Algorithm 1, Step 2: each zone by Algorithm 2 */
   int fail = 0;
-  for (k = 0; k < pb->nif; ++k) {
-    int homek = pb->home[k];
-    real hlk = pb->hl[k];
-    int st = or_zone_step(M, P, pb, k, ph, dt, rn, mn, &lg[k]);
-    if (st) {
-      pb->home[k] = homek;
-      pb->hl[k] = hlk;
-      int zlo, zhi, tr;
-      or_zone_range(P, pb, k, &zlo, &zhi, &tr);
-      for (s = zlo; s <= zhi; ++s) {
-        rn[s] = pb->rho[s];
-        mn[s] = pb->mom[s];
+  for (k = 0; k < pb->nif;) {
+    int zlo, zhi, tr, b, nbk = 1;
+    or_zone_range(P, pb, k, &zlo, &zhi, &tr);
+    if (k + 1 < pb->nif && P->zone_solver == 0) {
+      int zlo1, zhi1, tr1;
+      or_zone_range(P, pb, k + 1, &zlo1, &zhi1, &tr1);
+      if (zlo1 <= zhi) {
+        nbk = 2;
+        zhi = zhi1;
       }
-      lg[k].flags |= OR_FL_FAIL;
+    }
+    int kb[2] = {k, k + 1}, homes[2], i;
+    real hls[2];
+    for (b = 0; b < nbk; ++b) {
+      homes[b] = pb->home[kb[b]];
+      hls[b] = pb->hl[kb[b]];
+    }
+    int st = or_zone_step(M, P, pb, nbk, kb, ph, zlo, zhi, dt, rn, mn, &lg[k]);
+    if (st) {
+      for (b = 0; b < nbk; ++b) {
+        pb->home[kb[b]] = homes[b];
+        pb->hl[kb[b]] = hls[b];
+        lg[kb[b]].flags |= OR_FL_FAIL;
+      }
+      for (i = zlo; i <= zhi; ++i) {
+        rn[i] = pb->rho[i];
+        mn[i] = pb->mom[i];
+      }
       fail |= st;
     }
+    k += nbk;
   }
   memcpy(pb->rho, rn, sizeof(real) * ns);
   memcpy(pb->mom, mn, sizeof(real) * ns);

@@ -6,6 +6,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libimexds.so")
 SOURCES = [os.path.join(HERE, "csrc", "imexds_kernels.hip"),
            os.path.join(HERE, "csrc", "imexds_zone8.hip"),
+           os.path.join(HERE, "csrc", "imexds_zpair.hip"),
            os.path.join(HERE, "csrc", "imexds_znewton.hip"),
            os.path.join(HERE, "csrc", "imexds_adjoint.hip"),
            os.path.join(HERE, "csrc", "imexds_runtime.hip"),

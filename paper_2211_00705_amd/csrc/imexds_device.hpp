@@ -24,6 +24,7 @@ constexpr int ST_NEWTON = 1;
 constexpr int ST_NONPHYS = 2;
 constexpr int ST_MESH = 4;
 constexpr int ST_OVERLAP = 8;
+constexpr int ST_VANISH = 16;
 
 constexpr int FL_TINY_RIGHT = 1;
 constexpr int FL_MERGED = 2;
@@ -33,6 +34,7 @@ constexpr int FL_CROSS_L = 16;
 constexpr int FL_CROSS_R = 32;
 constexpr int FL_FAIL = 64;
 constexpr int FL_INACTIVE = 128;
+constexpr int FL_PAIR = 256;
 
 // Material: the five physical constants and derived ones, each computed once
 // on the host with one correctly rounded operation (sqrt or division) from

@@ -273,6 +273,13 @@ __global__ __launch_bounds__(64) void k_zone(StepArgs A, int if_begin, int if_en
         continue;
       }
       h = A.h[p];
+      {
+        // an interface whose zone overlaps a neighbour's is solved with it
+        // in one zone by k_zone_pair
+        const int nif = A.iface_off[p + 1] - A.iface_off[p];
+        if (d_pair_lead(A, k - 1, kk - 1, nif, ns, h) || d_pair_lead(A, k, kk, nif, ns, h))
+          continue;
+      }
       phl = A.phase_first[p] ^ (kk & 1);
       phr = phl ^ 1;
       int zhi;
@@ -697,8 +704,10 @@ __global__ void k_finalize(StepArgs A, int p_begin, int p_end, int init, int bum
       const int ns = (int)(A.slot_off[p + 1] - so);
       const int i0 = A.iface_off[p], nif = A.iface_off[p + 1] - i0;
       const double h = A.h[p];
+      // zones must be disjoint, except that with Algorithm 2 the zones of
+      // two neighbouring interfaces may overlap (solved as one zone)
       int prev_hi = -1;
-      for (int j = 0; j < nif; ++j) {
+      for (int j = 0; j < nif;) {
         int zlo, zhi;
         bool tr;
         d_zone_range(A.rec_home1[i0 + j] + j, A.rec_hl1[i0 + j], h, P.zone_half, ns, zlo, zhi, tr);
@@ -706,7 +715,19 @@ __global__ void k_finalize(StepArgs A, int p_begin, int p_end, int init, int bum
           st |= ST_OVERLAP;
           break;
         }
+        int nb = 1;
+        if (j + 1 < nif && P.zone_solver == 0) {
+          int zlo1, zhi1;
+          bool tr1;
+          d_zone_range(A.rec_home1[i0 + j + 1] + j + 1, A.rec_hl1[i0 + j + 1], h, P.zone_half, ns,
+                       zlo1, zhi1, tr1);
+          if (zlo1 <= zhi) {
+            nb = 2;
+            zhi = zhi1;
+          }
+        }
         prev_hi = zhi;
+        j += nb;
       }
       if (st == 0) {
         ndt = (P.cfl * h) / S;

@@ -55,6 +55,8 @@ struct StepArgs {
   unsigned long long* st_newton;  // evaluations of G in the interface solves
   unsigned long long* st_solves;  // interface solves
   unsigned long long* st_events;  // merges, redos and re-homings of interfaces
+  unsigned long long* st_pairs;   // zone steps with two phase boundaries
+  int* pair_seen;                 // set to 1 when a zone with two boundaries is solved
   int* zone_ctr;  // zones handed out so far in this step (reset by k_finalize)
   int zones_per_group;
   // zone tape of this step (nullptr: none).  Per interface, tape_stride
@@ -106,6 +108,27 @@ hipError_t launch_zone(const StepArgs& A, int if_begin, int if_end, int groups, 
 // the same zones with eight lanes per zone, eight zones per wave; groups <= 0:
 // enough waves for all zones, else that many waves pulling zones
 hipError_t launch_zone8(const StepArgs& A, int if_begin, int if_end, int groups, hipStream_t s);
+// zones holding the two phase boundaries of neighbouring interfaces whose
+// zones overlap (Algorithm 2 only; every interface of [if_begin, if_end) is
+// a candidate)
+hipError_t launch_zone_pair(const StepArgs& A, int if_begin, int if_end, hipStream_t s);
+
+// Whether interface k (local index kk of the nif of its problem; ns slots,
+// background width h) and interface k + 1 have overlapping zones (records of
+// the step's start).  With Algorithm 2 such a pair is one zone; the
+// single-boundary zone kernels leave both interfaces to k_zone_pair.
+__device__ __forceinline__ bool d_pair_lead(const StepArgs& A, int k, int kk, int nif, int ns,
+                                            double h) {
+  if (kk < 0 || kk + 1 >= nif) return false;
+  const int s0 = A.rec_home0[k] + kk, s1 = A.rec_home0[k + 1] + kk + 1;
+  if (s0 < 0 || s1 < s0 + 2 || s1 + 1 >= ns) return false;  // records outside their problem
+  int zlo0, zhi0, zlo1, zhi1;
+  bool t0, t1;
+  d_zone_range(A.rec_home0[k] + kk, A.rec_hl0[k], h, A.par.zone_half, ns, zlo0, zhi0, t0);
+  d_zone_range(A.rec_home0[k + 1] + kk + 1, A.rec_hl0[k + 1], h, A.par.zone_half, ns, zlo1,
+               zhi1, t1);
+  return zlo1 <= zhi0;
+}
 hipError_t launch_finalize(const StepArgs& A, int p_begin, int p_end, int init, int bump_row,
                            hipStream_t s);
 // the zones solved by Newton on their implicit step (zone_half 1 or 2):

@@ -27,8 +27,9 @@ using imexds::StepArgs;
 namespace {
 
 // device counters of the zone kernels (imexds_stats): dual time iterations,
-// merges, lmax hits, evaluations of G, interface solves, mesh events
-constexpr int N_STATS = 6;
+// merges, lmax hits, evaluations of G, interface solves, mesh events, zone
+// steps with two phase boundaries
+constexpr int N_STATS = 7;
 
 template <class T>
 struct DBuf {
@@ -52,7 +53,8 @@ struct imexds_ctx {
   hipStream_t user = nullptr;  // the caller's stream
   hipStream_t ms = nullptr;    // main stream of the context
   hipStream_t zs = nullptr;    // zone stream of the context
-  std::vector<hipEvent_t> fork_ev, join_ev;
+  hipStream_t ps = nullptr;    // stream of the zones with two phase boundaries
+  std::vector<hipEvent_t> fork_ev, join_ev, join2_ev;
   hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
   std::vector<hipEvent_t> bulk_ev;  // pairs around bulk launches when timing
   std::vector<hipEvent_t> zone_ev;  // pairs around zone launches when timing
@@ -87,7 +89,11 @@ struct imexds_ctx {
   int *d_status = nullptr, *d_clipped = nullptr, *d_fail = nullptr;
   long long* d_steps = nullptr;
   unsigned long long* d_S = nullptr;
-  unsigned long long* d_stats = nullptr;  // pseudo, merges, lmax, G evaluations, solves, events
+  unsigned long long* d_stats = nullptr;  // pseudo, merges, lmax, G evaluations, solves, events,
+                                          // zone steps with two boundaries
+  int* d_pair_seen = nullptr;  // a zone with two boundaries was solved (adjoint refuses)
+  int max_nif = 0;             // most interfaces in one problem
+  bool adj_pairs = false;      // the last checkpointed forward solved such a zone
   int* d_zone_ctr = nullptr;
   int *d_log_count = nullptr, *d_log_flags = nullptr, *d_log_zlo = nullptr, *d_log_row = nullptr;
   int log_max = 0;
@@ -214,6 +220,8 @@ StepArgs make_args(imexds_ctx* c, int parity, bool init) {
   A.st_newton = c->d_stats + 3;
   A.st_solves = c->d_stats + 4;
   A.st_events = c->d_stats + 5;
+  A.st_pairs = c->d_stats + 6;
+  A.pair_seen = c->d_pair_seen;
   A.zone_ctr = c->d_zone_ctr;
   A.zones_per_group = c->zones_per_group;
   return A;
@@ -260,12 +268,22 @@ int build_tiles(imexds_ctx* c, int tile_cells) {
   return 0;
 }
 
+// zones with two phase boundaries can occur (Algorithm 2, a problem with
+// more than one interface)
+bool pairs_possible(const imexds_ctx* c) {
+  return c->par.zone_solver == IMEXDS_ZONE_DTS && c->max_nif >= 2;
+}
+
+// The zone kernels of interfaces [k0, k1) on stream s; with pairs, also the
+// zones holding two phase boundaries (after the others, same stream).
 hipError_t launch_zones(imexds_ctx* c, const StepArgs& A, int k0, int k1, int groups,
-                        hipStream_t s) {
+                        hipStream_t s, bool pairs = true) {
   if (c->par.zone_solver == IMEXDS_ZONE_NEWTON)
     return imexds::launch_zone_newton(A, k0, k1, c->zone_lanes, s);
-  if (c->zone_lanes == 8) return imexds::launch_zone8(A, k0, k1, groups, s);
-  return imexds::launch_zone(A, k0, k1, groups, s);
+  const hipError_t e = c->zone_lanes == 8 ? imexds::launch_zone8(A, k0, k1, groups, s)
+                                          : imexds::launch_zone(A, k0, k1, groups, s);
+  if (e != hipSuccess || !pairs || !pairs_possible(c)) return e;
+  return imexds::launch_zone_pair(A, k0, k1, s);
 }
 
 // One physical step of every problem, enqueued on c->ms (zones on c->zs).
@@ -297,15 +315,25 @@ int enqueue_step(imexds_ctx* c, int ev_slot) {
     c->parity ^= 1;
     return 0;
   }
+  // zones with one boundary on zs, those with two on ps, beside the bulk
+  const bool pairs = c->NIF > 0 && pairs_possible(c);
   if (c->NIF > 0) {
     CK(hipEventRecord(ef, c->ms));
     CK(hipStreamWaitEvent(c->zs, ef, 0));
-    CK(launch_zones(c, A, 0, c->NIF, c->zone_groups, c->zs));
+    CK(launch_zones(c, A, 0, c->NIF, c->zone_groups, c->zs, false));
+    if (pairs) {
+      CK(hipStreamWaitEvent(c->ps, ef, 0));
+      CK(imexds::launch_zone_pair(A, 0, c->NIF, c->ps));
+    }
   }
   CK(imexds::launch_bulk(A, c->tile_cells, 0, c->n_tiles, c->ms));
   if (c->NIF > 0) {
     CK(hipEventRecord(ej, c->zs));
     CK(hipStreamWaitEvent(c->ms, ej, 0));
+    if (pairs) {
+      CK(hipEventRecord(c->join2_ev[ev_slot], c->ps));
+      CK(hipStreamWaitEvent(c->ms, c->join2_ev[ev_slot], 0));
+    }
   }
   CK(imexds::launch_finalize(A, 0, c->P, 0, 1, c->ms));
   c->parity ^= 1;
@@ -314,11 +342,13 @@ int enqueue_step(imexds_ctx* c, int ev_slot) {
 
 int ensure_events(imexds_ctx* c, size_t n) {
   while (c->fork_ev.size() < n) {
-    hipEvent_t a, b;
+    hipEvent_t a, b, d;
     CK(hipEventCreateWithFlags(&a, hipEventDisableTiming));
     CK(hipEventCreateWithFlags(&b, hipEventDisableTiming));
+    CK(hipEventCreateWithFlags(&d, hipEventDisableTiming));
     c->fork_ev.push_back(a);
     c->join_ev.push_back(b);
+    c->join2_ev.push_back(d);
   }
   return 0;
 }
@@ -636,7 +666,7 @@ int record_segment(imexds_ctx* c, int len) {
     A.log_count = A.log_flags = A.log_zlo = A.log_row = nullptr;
     A.log_max = 0;
     A.st_pseudo = A.st_merges = A.st_lmax = nullptr;
-    A.st_newton = A.st_solves = A.st_events = nullptr;
+    A.st_newton = A.st_solves = A.st_events = A.st_pairs = nullptr;
     A.tape = c->tZone + (size_t)j * N * (size_t)c->tape_stride;
     A.tape_stride = c->tape_stride;
     if (N) CK(launch_zones(c, A, 0, c->NIF, c->zone_groups, m));
@@ -703,6 +733,7 @@ void imexds_destroy(imexds_ctx* c) {
   (void)hipSetDevice(c->device);
   if (c->ms) (void)hipStreamSynchronize(c->ms);
   if (c->zs) (void)hipStreamSynchronize(c->zs);
+  if (c->ps) (void)hipStreamSynchronize(c->ps);
   drop_graph(c);
   for (void* p : c->allocs) (void)hipFree(p);
   if (c->d_tile_prob) (void)hipFree(c->d_tile_prob);
@@ -715,6 +746,7 @@ void imexds_destroy(imexds_ctx* c) {
   if (c->d_log_zlo) (void)hipFree(c->d_log_zlo);
   for (auto e : c->fork_ev) (void)hipEventDestroy(e);
   for (auto e : c->join_ev) (void)hipEventDestroy(e);
+  for (auto e : c->join2_ev) (void)hipEventDestroy(e);
   for (auto e : c->bulk_ev) (void)hipEventDestroy(e);
   for (auto e : c->zone_ev) (void)hipEventDestroy(e);
   for (auto e : c->call_ev) (void)hipEventDestroy(e);
@@ -723,6 +755,7 @@ void imexds_destroy(imexds_ctx* c) {
     if (e) (void)hipEventDestroy(e);
   if (c->ms) (void)hipStreamDestroy(c->ms);
   if (c->zs) (void)hipStreamDestroy(c->zs);
+  if (c->ps) (void)hipStreamDestroy(c->ps);
   delete c;
 }
 
@@ -761,6 +794,7 @@ static int create_impl(imexds_ctx* c, const imexds_material* mat, const imexds_p
     c->h_phase_first[p] = b->phase_first[p];
     c->h_iface_off[p + 1] = b->iface_off[p + 1];
     c->h_slot_off[p + 1] = c->h_slot_off[p] + n + nif;
+    if (nif > c->max_nif) c->max_nif = nif;
   }
   c->NIF = P > 0 ? b->iface_off[P] : 0;
   c->S = c->h_slot_off[P];
@@ -817,6 +851,7 @@ static int create_impl(imexds_ctx* c, const imexds_material* mat, const imexds_p
   CK(hipGetDevice(&c->device));
   CK(hipStreamCreateWithFlags(&c->ms, hipStreamNonBlocking));
   CK(hipStreamCreateWithFlags(&c->zs, hipStreamNonBlocking));
+  CK(hipStreamCreateWithFlags(&c->ps, hipStreamNonBlocking));
   CK(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
   CK(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
   CK(hipEventCreate(&c->ev_t0));
@@ -847,6 +882,7 @@ static int create_impl(imexds_ctx* c, const imexds_material* mat, const imexds_p
   AL(c->d_steps, Pn);
   AL(c->d_S, Pn);
   AL(c->d_stats, N_STATS);
+  AL(c->d_pair_seen, 1);
   AL(c->d_log_row, 1);
   AL(c->d_zone_ctr, 1);
   CK(hipMemcpy(c->d_slot_off, c->h_slot_off.data(), (Pn + 1) * 8, hipMemcpyHostToDevice));
@@ -1085,7 +1121,7 @@ int imexds_get_stats(imexds_ctx* c, imexds_stats* out) {
   if (!c || !out) return IMEXDS_ERR_INVALID_ARG;
   CK(hipSetDevice(c->device));
   memset(out, 0, sizeof(*out));
-  unsigned long long st[N_STATS] = {0, 0, 0, 0, 0, 0};
+  unsigned long long st[N_STATS] = {};
   CK(hipMemcpyAsync(st, c->d_stats, N_STATS * 8, hipMemcpyDeviceToHost, c->ms));
   size_t P = (size_t)c->P;
   std::vector<long long> steps(P);
@@ -1109,6 +1145,7 @@ int imexds_get_stats(imexds_ctx* c, imexds_stats* out) {
   out->newton_iters = (int64_t)st[3];
   out->iface_solves = (int64_t)st[4];
   out->events = (int64_t)st[5];
+  out->pair_zones = (int64_t)st[6];
   int r = fold_call_events(c, true);
   if (r) return r;
   out->gpu_ms = c->acc_gpu_ms;
@@ -1142,6 +1179,7 @@ int imexds_set_zone_solver(imexds_ctx* c, int32_t solver, int32_t maxit, double 
   CK(hipSetDevice(c->device));
   CK(hipStreamSynchronize(c->ms));
   CK(hipStreamSynchronize(c->zs));
+  CK(hipStreamSynchronize(c->ps));
   c->par.zone_solver = solver;
   c->par.zn_maxit = maxit;
   c->par.zn_rtol = rtol;
@@ -1310,6 +1348,7 @@ int imexds_forward_ckpt(imexds_ctx* c, int32_t n_steps, int32_t ckpt_every) {
   CK(hipStreamSynchronize(c->ms));
   free_checkpoints(c);
   c->bulk_launches = 0;
+  CK(hipMemsetAsync(c->d_pair_seen, 0, 4, c->ms));
   CK(hipEventRecord(c->ev_t0, c->ms));
   const int nck = (n_steps + ckpt_every - 1) / ckpt_every;
   c->ck.resize(nck);
@@ -1332,6 +1371,10 @@ int imexds_forward_ckpt(imexds_ctx* c, int32_t n_steps, int32_t ckpt_every) {
   if ((r = snap_take(c, c->ck_end))) return r;
   c->ck_end_valid = true;
   CK(hipEventRecord(c->ev_t1, c->ms));
+  int seen = 0;
+  CK(hipMemcpyAsync(&seen, c->d_pair_seen, 4, hipMemcpyDeviceToHost, c->ms));
+  CK(hipStreamSynchronize(c->ms));
+  c->adj_pairs = seen != 0;
   c->timed = true;
   c->adj_steps = n_steps;
   c->adj_every = ckpt_every;
@@ -1347,6 +1390,12 @@ int imexds_adjoint(imexds_ctx* c, const double* gL_rho, const double* gL_mom,
   if (!c->adj_ready) {
     snprintf(g_err, sizeof(g_err), "imexds_adjoint needs a preceding imexds_forward_ckpt");
     return IMEXDS_ERR_NO_STATE;
+  }
+  if (c->adj_pairs) {
+    snprintf(g_err, sizeof(g_err),
+             "the adjoint does not cover zones holding two phase boundaries, which the "
+             "recorded forward solved");
+    return IMEXDS_ERR_UNSUPPORTED;
   }
   int r = begin_call(c);
   if (r) return r;

@@ -165,6 +165,13 @@ __global__ __launch_bounds__(64) void k_zone8(StepArgs A, int if_begin, int if_e
         continue;
       }
       h = A.h[p];
+      {
+        // an interface whose zone overlaps a neighbour's is solved with it
+        // in one zone by k_zone_pair
+        const int nif = A.iface_off[p + 1] - A.iface_off[p];
+        if (d_pair_lead(A, k - 1, kk - 1, nif, ns, h) || d_pair_lead(A, k, kk, nif, ns, h))
+          continue;
+      }
       phl = A.phase_first[p] ^ (kk & 1);
       phr = phl ^ 1;
       int zhi;

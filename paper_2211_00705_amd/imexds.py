@@ -23,9 +23,9 @@ if not os.path.exists(LIB_PATH):
 _L = ctypes.CDLL(LIB_PATH)
 
 OK, ERR_INVALID_ARG, ERR_OOM, ERR_HIP, ERR_NO_STATE, ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
-ST_NEWTON_FAIL, ST_NONPHYSICAL, ST_MESH_FAIL, ST_ZONE_OVERLAP = 1, 2, 4, 8
+ST_NEWTON_FAIL, ST_NONPHYSICAL, ST_MESH_FAIL, ST_ZONE_OVERLAP, ST_PHASE_VANISH = 1, 2, 4, 8, 16
 FL_TINY_RIGHT, FL_MERGED, FL_REDO, FL_LMAX = 1, 2, 4, 8
-FL_CROSS_L, FL_CROSS_R, FL_FAIL, FL_INACTIVE = 16, 32, 64, 128
+FL_CROSS_L, FL_CROSS_R, FL_FAIL, FL_INACTIVE, FL_PAIR = 16, 32, 64, 128, 256
 TOL_PAPER, TOL_REL = 0, 1
 
 c_i32, c_i64, c_dbl, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
@@ -54,7 +54,7 @@ class imexds_stats(ctypes.Structure):
     _fields_ = [("steps", c_i64), ("cell_updates", c_i64), ("pseudo_iters", c_i64),
                 ("merges", c_i64), ("lmax_hits", c_i64), ("n_failed", c_i32), ("n_active", c_i32),
                 ("newton_iters", c_i64), ("iface_solves", c_i64), ("events", c_i64),
-                ("gpu_ms", c_dbl)]
+                ("gpu_ms", c_dbl), ("pair_zones", c_i64)]
 
 
 def _sig(name, *args):
