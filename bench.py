@@ -799,6 +799,11 @@ def main():
         "wall_s": wall,
         "failed_problems": int(np.sum(g_status != 0)),
         "pseudo_iters_per_zone_step": (st1["pseudo_iters"] - st0["pseudo_iters"]) / max(1, NIF * args.steps),
+        "interface_solves": {
+            "per_zone_step": (st1["iface_solves"] - st0["iface_solves"]) / max(1, NIF * args.steps),
+            "evaluations_of_G_per_solve": (st1["newton_iters"] - st0["newton_iters"])
+            / max(1, st1["iface_solves"] - st0["iface_solves"]),
+            "lmax_hits_per_step": (st1["lmax_hits"] - st0["lmax_hits"]) / max(1, args.steps)},
         "per_problem": pp,
         "roofline": {"bound": "hbm", "kernel": zone_kernel, "achieved": zone_achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",

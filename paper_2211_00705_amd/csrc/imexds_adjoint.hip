@@ -39,7 +39,8 @@ __device__ __forceinline__ void d_flux_jt(double a2, double u, double b0, double
 }
 
 // Reverse of d_hll: adds (dF/dU_l)^T b and (dF/dU_r)^T b, with the branch
-// and the min / max choices of the forward.
+// and the min / max choices of the forward, to (grl, gml) and (grr, gmr),
+// which the caller passes in at zero.
 __device__ __forceinline__ void d_hll_adj(const Mat& M, int ph, double rl, double ml, double rr,
                                           double mr, double b0, double b1, double& grl,
                                           double& gml, double& grr, double& gmr) {
@@ -47,12 +48,19 @@ __device__ __forceinline__ void d_hll_adj(const Mat& M, int ph, double rl, doubl
   const double ul = ml / rl, ur = mr / rr;
   const double sl = (ul < ur ? ul : ur) - a;
   const double sr = (ul > ur ? ul : ur) + a;
-  if (sl >= 0.0) {
-    d_flux_jt(a2, ul, b0, b1, grl, gml);
-    return;
-  }
-  if (sr <= 0.0) {
-    d_flux_jt(a2, ur, b0, b1, grr, gmr);
+  if (sl >= 0.0 || sr <= 0.0) {
+    // one-sided: the flux is the physical flux of the upwind side.  Both
+    // sides' outputs are updated with selected values (updating one side
+    // chosen at run time makes the compiler keep the caller's accumulators
+    // in scratch memory); every caller passes them in at zero, so adding a
+    // zero leaves the other side unchanged.
+    const bool left = sl >= 0.0;
+    double tr = 0.0, tm = 0.0;
+    d_flux_jt(a2, left ? ul : ur, b0, b1, tr, tm);
+    grl += left ? tr : 0.0;
+    gml += left ? tm : 0.0;
+    grr += left ? 0.0 : tr;
+    gmr += left ? 0.0 : tm;
     return;
   }
   const double pl = d_pres(M, ph, rl), pr = d_pres(M, ph, rr);
