@@ -331,11 +331,11 @@ def other_configs_leg(material, cpu):
 EU_ZONE_FLOP_PER_TUBE_ITER = 8989.0  # k_eu_zone: per tube and dual time iteration
 EU_BULK_FLOP_PER_FACE = 1343.0       # k_eu_bulk: per face of a tube still running
 CR_FLOP_PER_PROBLEM = 2460.0         # k_cr_detect + k_cr_solve per problem of creation_batch
-# k_ct_zone: executed FP64 lane operations (64 per wave instruction; at 2 tubes
-# per wave and 4 lanes per tube 8 of the 64 lanes are busy) per tube and dual
-# time iteration, from the rocprofv3 PMC counts of the leg's 10 steps of
-# ctube_batch
-CT_ZONE_FLOP_PER_TUBE_ITER = 47456.0
+# k_ct_zone: FP64 operations of the busy lanes per tube and dual time
+# iteration, from the rocprofv3 PMC counts of the leg's 10 steps of
+# ctube_batch: 47456 executed lane operations (64 per wave instruction), of
+# which the 8 lanes a wave keeps busy (2 tubes of 4 lanes) do 8/64
+CT_ZONE_FLOP_PER_TUBE_ITER = 47456.0 * 8.0 / 64.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 
@@ -533,7 +533,8 @@ def ctube_leg(args, cpu):
                            "per_unit": f"{CT_ZONE_FLOP_PER_TUBE_ITER:.0f} FP64 ops per tube and "
                                        "dual time iteration",
                            "units_per_launch": tube_iters / max(1, n),
-                           "note": "the nucleating tubes' dependent chains (tens of thousands "
+                           "note": "operations of the busy lanes only (8 of a wave's 64); "
+                                   "the nucleating tubes' dependent chains (tens of thousands "
                                    "of dual time iterations per step) bound it: latency"}
     # the Newton zone solver (zone +- 1) on the whole run to t_end
     s = CreationTubes(b)

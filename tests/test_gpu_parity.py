@@ -167,21 +167,38 @@ def test_edge_cases(material, lanes):
     assert_parity(b, g, o)
 
 
-def test_full_size_batch_sampled(material):
+def _sampled_logs(b, g, idx):
+    """The per-step logs of the interfaces of problems idx (in order)."""
+    io = b.iface_off
+    cols = np.concatenate([np.arange(io[p], io[p + 1]) for p in idx]).astype(np.int64)
+    return {k: g[k][:, cols] for k in ("count", "flags", "zlo")}
+
+
+@pytest.mark.parametrize("launch", [(1024, 8, 0, 10, 8), (1024, 16, 64, 10, 1)])
+def test_full_size_batch_sampled(material, launch):
     """The benchmarked batch at full size (4096 problems, about 1.6e7 cells,
-    1000 steps) in the autotuned launch form; 6 sampled problems recomputed by
-    the oracle on their own."""
+    1000 steps) in the launch form bench.py times (eight lanes per zone, eight
+    zones per wave, all zones at once) and in a persistent one-lane form; 16
+    sampled problems, including the 8 with the most dual time iterations,
+    recomputed by the oracle on their own, logs (every step's dual time
+    count, flags and zone) included."""
     b = W.random_batch()
     P = W.random_batch_params()
-    g = run_gpu(b, material, P, 1000, launch=(1024, 16, 64, 10), log=False)
+    g = run_gpu(b, material, P, 1000, launch=launch, log=True)
     rng = np.random.default_rng(1)
-    idx = sorted(rng.choice(b.n_problems, size=6, replace=False).tolist())
+    heavy = np.argsort(-g["count"].sum(axis=0))[:8]
+    idx = sorted(set(rng.choice(b.n_problems, size=8, replace=False).tolist())
+                 | set(heavy.tolist()))
     sub = b.subset(idx)
     o = run_oracle(sub, material, P, 1000)
-    gs = {k: take_problems(b, v, k, idx) for k, v in g.items() if k != "stats"}
-    assert_parity(sub, gs, o, logs=False)
+    gs = {k: take_problems(b, v, k, idx) for k, v in g.items()
+          if k not in ("stats", "count", "flags", "zlo")}
+    gs.update(_sampled_logs(b, g, idx))
+    assert (o["flags"] & 8).any()  # the sample holds zones stopped at l_max
+    assert_parity(sub, gs, o, logs=True)
     assert np.all(g["steps"] == 1000)
     assert g["stats"]["cell_updates"] == 1000 * b.n_slots
+    assert g["stats"]["pseudo_iters"] == int(g["count"].sum())
 
 
 def test_single_cut_run_to_end_time(material):
@@ -214,9 +231,12 @@ def test_bubble_batch_full_size_sampled(material):
     b = W.bubble_batch()
     P = W.bubble_batch_params()
     n = 2000
-    g = run_gpu(b, material, P, n, log=False, lanes=8)
+    g = run_gpu(b, material, P, n, log=True, lanes=8)
     rng = np.random.default_rng(4)
     idx = set(rng.choice(b.n_problems, size=6, replace=False).tolist())
+    # problems whose two zones were joined at some step
+    paired = np.nonzero(((g["flags"] & 256) != 0).any(axis=0))[0] // 2
+    idx |= set(paired[:3].tolist())
     # In this configuration some bubbles close: compressed liquid condenses
     # the vapour, the two zones join into one, and the problem is frozen when
     # the vapour vanishes (PHASE_VANISH); one reaches a non-physical state.
@@ -231,5 +251,7 @@ def test_bubble_batch_full_size_sampled(material):
     idx = sorted(idx)
     sub = b.subset(idx)
     o = run_oracle(sub, material, P, n)
-    gs = {k: take_problems(b, v, k, idx) for k, v in g.items() if k != "stats"}
-    assert_parity(sub, gs, o, logs=False)
+    gs = {k: take_problems(b, v, k, idx) for k, v in g.items()
+          if k not in ("stats", "count", "flags", "zlo")}
+    gs.update(_sampled_logs(b, g, idx))
+    assert_parity(sub, gs, o, logs=True)

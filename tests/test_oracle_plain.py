@@ -46,6 +46,11 @@ CASES = {
     "random_batch": (lambda: W.random_batch(seed=7, n_problems=48, nmin=256, nmax=2048),
                      W.random_batch_params, 300),
     "bubble_batch": (lambda: W.bubble_batch(n_problems=24, n=1024), W.bubble_batch_params, 300),
+    # bubbles that close: 216 zone steps of joint zones (two phase boundaries)
+    # before the first problem is frozen (a frozen step's log does not carry
+    # the decisions that led to it, so a replay stops short of it)
+    "bubble_pairs": (lambda: W.bubble_batch(seed=7, n_problems=48, n=512), W.bubble_batch_params,
+                     355),
     "adjoint_batch": (lambda: W.adjoint_batch(n_problems=24, nmin=256, nmax=2048),
                       W.adjoint_batch_params, 200),
 }
@@ -83,7 +88,12 @@ def test_plain_arithmetic_build_takes_the_same_decisions(material, name):
     pc, pf, _, _ = oracle.run(pl, material, P, n, log="full", plain=True, threads=4)
     active = lc > 0
     flips = int(np.sum(lc != pc))
-    assert flips <= max(2, 0.002 * int(active.sum())), flips
+    # In the joint zones of closing bubbles the vapour cells squeezed between
+    # two boundaries sit near their tolerance step after step, so a flipped
+    # stop keeps flipping later ones in that zone (measured: 114 of 34,080
+    # zone-step logs, all in the two joint zones, states within 1.2e-13)
+    frac = 0.005 if name == "bubble_pairs" else 0.002
+    assert flips <= max(2, frac * int(active.sum())), flips
     assert np.array_equal(lf & ~oracle.FL_LMAX, pf & ~oracle.FL_LMAX)
     assert np.array_equal(pl.status, ref.status)
     assert _rel_l1(b, pl, ref) <= 1e-10
