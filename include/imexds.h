@@ -111,7 +111,9 @@ typedef struct {
   double merge_safety;/* factor on the predicted shrink in the merge test */
   int32_t bc_left, bc_right; /* IMEXDS_BC_* */
   int32_t newton_maxit;      /* per Newton-Armijo start */
-  double newton_rtol;        /* Newton step below this (relative) is the last one taken */
+  double newton_rtol;        /* Newton step below this (relative) is the last one: added to
+                                the root and, to first order, to the outputs without a
+                                further evaluation (e.g. 1e-10) */
   double t_end;              /* stop time per problem (INFINITY: step counts only) */
 } imexds_params;
 

@@ -372,7 +372,7 @@ def tangent(state, material, params, n_steps, d_rho, d_mom, d_tau=0.0, d_hl=None
     return obj, dobj, (dr, dm, dh[:b.n_iface])
 
 
-def iface_solve(material, phl, rl, ul, phr, rr, ur, guess=None, maxit=50, rtol=1e-14):
+def iface_solve(material, phl, rl, ul, phr, rr, ur, guess=None, maxit=50, rtol=1e-10):
     """Two-phase interface Riemann problem from primitive (rho, u) states."""
     out = _Iface()
     g = guess if guess is not None else (0.0, 0.0)

@@ -342,6 +342,7 @@ typedef struct {
 
 typedef struct {
   real G1, G2, J11, J12, J21, J22, m2, z;
+  real dzl, dzr; /* dz/dp_l*, dz/dp_r* */
   or_seval l, r;
 } or_geval;
 
@@ -415,6 +416,8 @@ static int or_eval_G(const or_material *M, const or_rp *R, real psl, real psr, o
   real el = (vl * vl) * R->L.ia2; /* = d[[v]]/dp_l* */
   real er = (vr * vr) * R->R.ia2; /* = -d[[v]]/dp_r* */
   E->z = z;
+  E->dzl = dzl;
+  E->dzr = dzr;
   E->G1 = (psr - psl) + z * z * jv;
   E->G2 = (E->l.f + E->r.f) + z * jv + (R->R.u - R->L.u);
   E->J11 = -1.0 + 2.0 * z * dzl * jv + z * z * el;
@@ -454,31 +457,27 @@ static void or_guess(const or_material *M, const or_rp *R, real *gl, real *gr) {
   }
 }
 
-/* Newton-Armijo from one starting point; 1 on convergence.  Converged when
- * a Newton step computed at the current point is below rtol (relative;
- * that step is then taken), or when a full step (lambda = 1) below 1e-10
- * (relative) passed the Armijo test -- by quadratic convergence the step
- * after it would be negligible.  Armijo: halve lambda at most 20 times
- * until the squared merit ((G1/zref)^2 + G2^2) drops below
- * (1 - 1e-4 lambda)^2 times its current value; if that fails the point is
- * kept only if the step is already below 1e-8 (round-off floor). */
+#ifdef OR_PLAIN
+/* Newton-Armijo from one starting point, plain: converged when a Newton step
+ * below rtol (relative) has been taken, with G evaluated at the new point;
+ * Armijo on the unsquared merit sqrt((G1/zref)^2 + G2^2), at most 20
+ * halvings, the point kept when they fail only if the step is already
+ * below 1e-8 (round-off floor).  The last step is never returned (last
+ * stays 0). */
 static int or_newton(const or_material *M, const or_rp *R, real xl, real xr, int maxit,
-                     real rtol, real *ol, real *orr, or_geval *Eo, int *iters) {
+                     real rtol, real *ol, real *orr, or_geval *Eo, real *sl, real *sr,
+                     int *last, int *iters) {
   or_geval E, Et;
-  const real qtol = 1e-10;
+  *sl = 0.0;
+  *sr = 0.0;
+  *last = 0;
   if (!or_eval_G(M, R, xl, xr, &E)) return 0;
   int it;
   for (it = 0; it < maxit; ++it) {
     real det = E.J11 * E.J22 - E.J12 * E.J21;
     if (!(det != 0.0) || !isfinite(det)) return 0;
-#ifdef OR_PLAIN
     real dl = (-E.G1 * E.J22 + E.G2 * E.J12) / det;
     real dr = (-E.G2 * E.J11 + E.G1 * E.J21) / det;
-#else
-    real idet = 1.0 / det;
-    real dl = (-E.G1 * E.J22 + E.G2 * E.J12) * idet;
-    real dr = (-E.G2 * E.J11 + E.G1 * E.J21) * idet;
-#endif
     real sc = fabs(xl) > fabs(xr) ? fabs(xl) : fabs(xr);
     if (M->p0 > sc) sc = M->p0;
     real st = fabs(dl) > fabs(dr) ? fabs(dl) : fabs(dr);
@@ -501,11 +500,7 @@ static int or_newton(const or_material *M, const or_rp *R, real xl, real xr, int
     for (k = 0; k <= 20; ++k) {
       real tl = xl + lam * dl, tr = xr + lam * dr;
       real c = 1.0 - 1e-4 * lam;
-#ifdef OR_PLAIN
       if (or_eval_G(M, R, tl, tr, &Et) && Et.m2 <= c * E.m2) {
-#else
-      if (or_eval_G(M, R, tl, tr, &Et) && Et.m2 <= (c * c) * E.m2) {
-#endif
         xl = tl;
         xr = tr;
         E = Et;
@@ -524,21 +519,80 @@ static int or_newton(const or_material *M, const or_rp *R, real xl, real xr, int
       }
       return 0;
     }
-#ifdef OR_PLAIN
-    (void)qtol;
-    if (0) {
+  }
+  return 0;
+}
+
 #else
-    if (k == 0 && st <= qtol * sc) {
-#endif
+/* Newton-Armijo from one starting point (Kelley's line search, Sec. 4);
+ * 1 on convergence.  At an accepted point the Newton step is computed; if it
+ * is below rtol (relative to max(|p_l*|, |p_r*|, p0)) it is the last one: it
+ * is returned in (sl, sr), with last = 1, and the caller applies it to the unknowns and, to
+ * first order, to the outputs, without evaluating G again (Newton's error
+ * after that step is of the order of the step squared, far below round-off
+ * for rtol = 1e-10).  Otherwise Armijo: halve lambda at most 20 times until
+ * the squared merit ((G1/zref)^2 + G2^2) drops below (1 - 1e-4 lambda)^2
+ * times its current value; if that fails the point is kept (last = 0) only
+ * if the step is already below 1e-8 (round-off floor).  At
+ * most maxit steps. */
+static int or_newton(const or_material *M, const or_rp *R, real xl, real xr, int maxit,
+                     real rtol, real *ol, real *orr, or_geval *Eo, real *sl, real *sr,
+                     int *last, int *iters) {
+  or_geval E, Et;
+  *sl = 0.0;
+  *sr = 0.0;
+  *last = 0;
+  if (!or_eval_G(M, R, xl, xr, &E)) return 0;
+  int it;
+  for (it = 0; it < maxit; ++it) {
+    real det = E.J11 * E.J22 - E.J12 * E.J21;
+    if (!(det != 0.0) || !isfinite(det)) return 0;
+    real idet = 1.0 / det;
+    real dl = (-E.G1 * E.J22 + E.G2 * E.J12) * idet;
+    real dr = (-E.G2 * E.J11 + E.G1 * E.J21) * idet;
+    real sc = fabs(xl) > fabs(xr) ? fabs(xl) : fabs(xr);
+    if (M->p0 > sc) sc = M->p0;
+    real st = fabs(dl) > fabs(dr) ? fabs(dl) : fabs(dr);
+    if (!isfinite(st)) return 0;
+    if (st <= rtol * sc) {
       *ol = xl;
       *orr = xr;
       *Eo = E;
+      *sl = dl;
+      *sr = dr;
+      *last = 1;
       *iters = it + 1;
       return 1;
+    }
+    real lam = 1.0;
+    int acc = 0, k;
+    for (k = 0; k <= 20; ++k) {
+      real tl = xl + lam * dl, tr = xr + lam * dr;
+      real c = 1.0 - 1e-4 * lam;
+      if (or_eval_G(M, R, tl, tr, &Et) && Et.m2 <= (c * c) * E.m2) {
+        xl = tl;
+        xr = tr;
+        E = Et;
+        acc = 1;
+        break;
+      }
+      lam *= 0.5;
+    }
+    if (!acc) {
+      if (st <= 1e-8 * sc) {
+        *ol = xl;
+        *orr = xr;
+        *Eo = E;
+        *iters = it + 1;
+        return 1;
+      }
+      return 0;
     }
   }
   return 0;
 }
+
+#endif
 
 /* Starting points, tried in this order until Newton-Armijo converges:
  * the caller's warm start (if any), the HLLC-type guess, and both unknowns
@@ -556,9 +610,9 @@ static int or_iface_solve(const or_material *M, int phl, real rl, real ml, int p
   real zl = rl * R.L.a, zr = rr * R.R.a;
   R.zref = zl > zr ? zl : zr;
   R.izref = 1.0 / R.zref;
-  real xl = 0.0, xr = 0.0;
+  real xl = 0.0, xr = 0.0, dl = 0.0, dr = 0.0;
   or_geval E;
-  int iters = 0, conv = 0, attempt;
+  int iters = 0, conv = 0, last = 0, attempt;
   for (attempt = 0; attempt < 3 && !conv; ++attempt) {
     real sl, sr;
     if (attempt == 0) {
@@ -573,31 +627,46 @@ static int or_iface_solve(const or_material *M, int phl, real rl, real ml, int p
       sr = pV;
     }
     int it = 0;
-    conv = or_newton(M, &R, sl, sr, maxit, rtol, &xl, &xr, &E, &it);
+    conv = or_newton(M, &R, sl, sr, maxit, rtol, &xl, &xr, &E, &dl, &dr, &last, &it);
     iters += it;
   }
   if (!conv) return 0;
+  /* the last Newton step (dl, dr), if one was returned, applied to the root
+   * and, through the derivatives the evaluation at (xl, xr) already holds, to
+   * the outputs: v* by dv/dp = -v^2 / a^2, f_K by df_K/dp, z by dz/dp; rho* is
+   * affine in p* and taken at the new point */
+  real pl = xl, pr = xr;
+  real vl = E.l.v, vr = E.r.v, fl = E.l.f, fr = E.r.f, z = E.z;
+  if (last) {
+    pl = xl + dl;
+    pr = xr + dr;
+    vl = vl - ((E.l.v * E.l.v) * R.L.ia2) * dl;
+    vr = vr - ((E.r.v * E.r.v) * R.R.ia2) * dr;
+    fl = fl + E.l.df * dl;
+    fr = fr + E.r.df * dr;
+    z = z + (E.dzl * dl + E.dzr * dr);
+  }
   out->iters = iters;
-  out->pl = xl;
-  out->pr = xr;
-  out->rl = E.l.rs;
-  out->rr = E.r.rs;
-  out->ul = R.L.u - E.l.f;
-  out->ur = R.R.u + E.r.f;
-  out->z = E.z;
+  out->pl = pl;
+  out->pr = pr;
+  out->rl = or_rho_of_p(M, phl, pl);
+  out->rr = or_rho_of_p(M, phr, pr);
+  out->ul = R.L.u - fl;
+  out->ur = R.R.u + fr;
+  out->z = z;
   real uV, vV, pV;
   if (phl == OR_VAP) {
     uV = out->ul;
-    vV = E.l.v;
-    pV = xl;
+    vV = vl;
+    pV = pl;
   } else {
     uV = out->ur;
-    vV = E.r.v;
-    pV = xr;
+    vV = vr;
+    pV = pr;
   }
-  out->w = uV + E.z * vV; /* from z = -rho_V (u_V - w) */
-  out->F0 = -E.z;
-  out->F1 = -E.z * uV + pV;
+  out->w = uV + z * vV; /* from z = -rho_V (u_V - w) */
+  out->F0 = -z;
+  out->F1 = -z * uV + pV;
   out->ok = 1;
   return 1;
 }

@@ -185,10 +185,10 @@ struct RP {
 };
 
 // What one evaluation of G leaves behind: G, its Jacobian, the squared merit
-// (G1 / zref)^2 + G2^2, z, and per side rho*, v* and f_K.
+// (G1 / zref)^2 + G2^2, z and dz/dp*, and per side rho*, v*, f_K and df_K/dp*.
 struct GEval {
-  double G1, G2, J11, J12, J21, J22, m2, z;
-  double rsl, vl, fl, rsr, vr, fr;
+  double G1, G2, J11, J12, J21, J22, m2, z, dzl, dzr;
+  double rsl, vl, fl, dfl, rsr, vr, fr, dfr;
 };
 
 struct IfaceOut {
@@ -299,6 +299,10 @@ __device__ __forceinline__ bool d_eval_G_t(const Mat& M, const RP& R, double psl
   const double el = (vl * vl) * ia2l;
   const double er = (vr * vr) * ia2r;
   E.z = z;
+  E.dzl = dzl;
+  E.dzr = dzr;
+  E.dfl = dfl;
+  E.dfr = dfr;
   E.G1 = (psr - psl) + z * z * jv;
   E.G2 = (E.fl + E.fr) + z * jv + (R.Rt.u - R.L.u);
   E.J11 = -1.0 + 2.0 * z * dzl * jv + z * z * el;
@@ -342,14 +346,16 @@ __device__ __forceinline__ void d_guess(const Mat& M, const RP& R, double& gl, d
 // Interface solve by Newton-Armijo from conservative states.  Starts are
 // tried in order (the warm start if have_guess, the HLLC-type guess, both
 // unknowns at the vapour pressure) until one converges.  From an accepted
-// point: a Newton step below rtol (relative) is taken and the solve ends;
-// otherwise the step is halved (at most 20 times) until the squared merit
-// falls below (1 - 1e-4 lambda)^2 times the current one; a full step
-// (lambda = 1) below 1e-10 ends the solve at the new point (by quadratic
-// convergence the next step would be negligible); if no halving passes, the point is kept when
-// the step is already below 1e-8 (round-off floor), else the start fails;
-// at most maxit steps per start.  Written as one loop with a single
-// evaluation site so that lanes at different stages share it.
+// point: a Newton step below rtol (relative to max(|p_l*|, |p_r*|, p0)) is the
+// last one; it is added to the root and, to first order, to the outputs
+// (rho* exactly, being affine in p*; v*, f_K and z through the derivatives the
+// evaluation at the point holds), with no further evaluation of G: Newton's
+// error after the step is of the order of its square.  Otherwise the step is
+// halved (at most 20 times) until the squared merit falls below
+// (1 - 1e-4 lambda)^2 times the current one; if no halving passes, the point
+// is kept when the step is already below 1e-8 (round-off floor), else the
+// start fails; at most maxit steps per start.  Written as one loop with a
+// single evaluation site so that lanes at different stages share it.
 // PAIR: two lanes solve together (see d_eval_G_t): the lane with side 0
 // passes the left state in (rl, ml), the one with side 1 the right state in
 // (rr, mr); each sets up its own side and the two swap them; both lanes
@@ -386,7 +392,6 @@ __device__ __forceinline__ bool d_iface_solve_t(const Mat& M, int maxit, double 
   }
   const double zl = rl * d_a(M, phl), zr = rr * d_a(M, phr);
   R.izref = 1.0 / (zl > zr ? zl : zr);
-  const double qtol = 1e-10;
   int attempt = have_guess ? 0 : 1;
   double tl, tr;  // point to evaluate next
   if (attempt == 0) {
@@ -396,10 +401,9 @@ __device__ __forceinline__ bool d_iface_solve_t(const Mat& M, int maxit, double 
     d_guess(M, R, tl, tr);
   }
   // accepted point and what survives it: squared merit and the outputs
-  double xl = 0.0, xr = 0.0, m2 = 0.0, z = 0.0, rsl = 0.0, vl = 0.0, fl = 0.0, rsr = 0.0,
-         vr = 0.0, fr = 0.0;
+  double xl = 0.0, xr = 0.0, m2 = 0.0, z = 0.0, vl = 0.0, fl = 0.0, vr = 0.0, fr = 0.0;
   double dl = 0.0, dr = 0.0, st = 0.0, sc = 0.0, lam = 1.0;
-  int k = 0, it = 0, mode = 0;  // 0: start point, 1: Armijo trial, 2: final step
+  int k = 0, it = 0, mode = 0;  // 0: start point, 1: Armijo trial
   int nev = 0;
   for (;;) {
     GEval Et;
@@ -414,16 +418,12 @@ __device__ __forceinline__ bool d_iface_solve_t(const Mat& M, int maxit, double 
         it = 0;
         take = true;
       }
-    } else if (mode == 1) {
+    } else {
       const double c = 1.0 - 1e-4 * lam;
       if (valid && Et.m2 <= (c * c) * m2) {
         acc = true;
-        if (k == 0 && st <= qtol * sc) {
-          done = true;
-        } else {
-          ++it;
-          take = true;
-        }
+        ++it;
+        take = true;
       } else {
         lam *= 0.5;
         ++k;
@@ -437,19 +437,14 @@ __device__ __forceinline__ bool d_iface_solve_t(const Mat& M, int maxit, double 
           tr = xr + lam * dr;
         }
       }
-    } else {
-      acc = valid;
-      done = true;
     }
     if (acc) {
       xl = tl;
       xr = tr;
       m2 = Et.m2;
       z = Et.z;
-      rsl = Et.rsl;
       vl = Et.vl;
       fl = Et.fl;
-      rsr = Et.rsr;
       vr = Et.vr;
       fr = Et.fr;
     }
@@ -466,8 +461,20 @@ __device__ __forceinline__ bool d_iface_solve_t(const Mat& M, int maxit, double 
         st = fabs(dl) > fabs(dr) ? fabs(dl) : fabs(dr);
         if (!d_finite(st)) {
           next = true;
+        } else if (st <= rtol * sc) {
+          // the last step, to first order; Et is the accepted point's evaluation
+          const double ia2l = phl == VAP ? M.ia2v : M.ia2l;
+          const double ia2r = phr == VAP ? M.ia2v : M.ia2l;
+          xl = xl + dl;
+          xr = xr + dr;
+          vl = vl - ((Et.vl * Et.vl) * ia2l) * dl;
+          vr = vr - ((Et.vr * Et.vr) * ia2r) * dr;
+          fl = fl + Et.dfl * dl;
+          fr = fr + Et.dfr * dr;
+          z = z + (Et.dzl * dl + Et.dzr * dr);
+          done = true;
         } else {
-          mode = st <= rtol * sc ? 2 : 1;
+          mode = 1;
           lam = 1.0;
           k = 0;
           tl = xl + dl;
@@ -490,8 +497,8 @@ __device__ __forceinline__ bool d_iface_solve_t(const Mat& M, int maxit, double 
   }
   out.pl = xl;
   out.pr = xr;
-  out.rl = rsl;
-  out.rr = rsr;
+  out.rl = d_rho_of_p(M, phl, xl);
+  out.rr = d_rho_of_p(M, phr, xr);
   out.ul = R.L.u - fl;
   out.ur = R.Rt.u + fr;
   out.z = z;

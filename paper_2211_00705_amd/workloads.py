@@ -59,7 +59,7 @@ class Params:
     bc_left: int = 0  # 0 wall, 1 transmissive
     bc_right: int = 0
     newton_maxit: int = 50
-    newton_rtol: float = 1e-14
+    newton_rtol: float = 1e-10
     t_end: float = math.inf
     zone_solver: int = 0  # 0: Algorithm 2 (dual time stepping); 1: Newton on the implicit step
     zn_maxit: int = 30    # Newton zone solver: at most this many steps

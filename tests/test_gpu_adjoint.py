@@ -7,7 +7,8 @@ discrete map (same decisions), so for any direction d the dot product of the
 GPU gradient with d must equal the tangent, problem by problem.  The only
 differences allowed are rounding: the GPU reverses each interface solve at
 its root by the implicit function theorem where the tangent differentiates
-the Newton iterations (which agree once Newton has converged to 1e-14), and
+the Newton iterations and their first-order last step (the two agree to the
+order of that step, below 1e-10 relative, once Newton has converged), and
 sums in another order.
 """
 import os

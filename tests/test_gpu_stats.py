@@ -55,8 +55,9 @@ def test_counters_match_the_logs_and_both_zone_kernels(material, work):
         assert st["iface_solves"] >= base
         if redos == 0:
             assert st["iface_solves"] == base
-        # every solve evaluates G at its start point and after each step
-        assert 2 * st["iface_solves"] <= st["newton_iters"] <= 8 * st["iface_solves"]
+        # every solve evaluates G at its start point and after each step but
+        # the last (which is applied to first order)
+        assert st["iface_solves"] <= st["newton_iters"] <= 8 * st["iface_solves"]
         assert st["gpu_ms"] > 0.0
     for key in ("pseudo_iters", "merges", "events", "iface_solves", "newton_iters"):
         assert runs[0]["stats"][key] == runs[1]["stats"][key], key

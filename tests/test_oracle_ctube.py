@@ -73,14 +73,19 @@ def test_nucleation_test_reproduces_printed_implicit_row():
     star cells sit where the printed implicit row does (70382.992468 /
     70383.072633 / 70382.992468 Pa, 0.465933 / ~1e-10 / -0.465933 m/s),
     about 0.03 Pa below the exact solution (70383.024449 / 70383.115685):
-    the scheme's own error, reproduced to 5e-4 Pa.  The liquid cell is
-    2.03e-7 m at t_end."""
+    the scheme's own error, reproduced to 5e-4 Pa in the vapour cells.  The
+    created liquid cell's pressure is fixed only to within the dual time
+    stop rule: with a_L^2 = 2.2e6 m^2/s^2 a density change of 5e-12
+    (relative), far inside the stop tolerance, is 0.01 Pa, and changing the
+    initial speeds by 1 to 7 ulp moves it between -0.01 and +0.03 Pa of the
+    printed value; it is pinned to that band (0.035 Pa, still short of the
+    exact value 0.043 Pa above).  The liquid cell is 2.03e-7 m at t_end."""
     b = CW.nucleation_tube()
     st = run(b)
     assert st.status[0] == 0 and st.t[0] == 5e-4 and st.face[0] == 200
     (pl, ul), (pv, uv), (pr, ur) = star_cells(st, b)
     assert abs(pl - 70382.992468) < 1e-3 and abs(pr - 70382.992468) < 1e-3
-    assert abs(pv - 70383.072633) < 1e-3
+    assert abs(pv - 70383.072633) < 0.035
     assert abs(pl - 70383.024449) > 0.02  # not the exact solution
     assert abs(ul - 0.465933) < 1e-6 and abs(ur + 0.465933) < 1e-6
     assert abs(uv) < 1e-9
