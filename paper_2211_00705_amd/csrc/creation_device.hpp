@@ -24,7 +24,11 @@ __device__ int c_single_rp(const Mat& M, const Side& L, const Side& R, double& p
   double p = 0.5 * (L.p + R.p);
   for (int it = 0; it < 100; ++it) {
     double rl, vl, gl, fl, dfl, rr, vr, gr, fr, dfr;
-    if (!d_wave(M, L, p, rl, vl, gl, fl, dfl) || !d_wave(M, R, p, rr, vr, gr, fr, dfr)) return 1;
+    // taken branches: selecting here makes the compiler address the
+    // material constants through a stack copy
+    const bool okl = d_wave<false>(M, L, p, rl, vl, gl, fl, dfl);
+    const bool okr = d_wave<false>(M, R, p, rr, vr, gr, fr, dfr);
+    if (!okl || !okr) return 1;
     double dp = -(fl + fr + du) / (dfl + dfr);
     if (!d_finite(dp)) return 1;
     double pn = p + dp;
@@ -244,15 +248,24 @@ __device__ int c_solve(const Mat& M, int ph, double rl, double ml, double rr, do
 // step (i) and its decision alone: 1 if the problem creates a layer of the
 // other phase (p* < p_min for a liquid, p* > p_tilde for a vapour, or no
 // root), 0 if not; p1 gets the star pressure (0 without a root)
-__device__ __forceinline__ int c_creates(const Mat& M, int ph, double rl, double ml, double rr,
-                                         double mr, double p_min, double p_tilde, double& p1) {
+template <int PH>
+__device__ __forceinline__ int c_creates_t(const Mat& M, double rl, double ml, double rr, double mr,
+                                           double p_min, double p_tilde, double& p1) {
   Side L, R;
-  d_side(M, ph, rl, ml, L);
-  d_side(M, ph, rr, mr, R);
+  d_side(M, PH, rl, ml, L);
+  d_side(M, PH, rr, mr, R);
   p1 = 0.0;
   const int none = c_single_rp(M, L, R, p1);
   if (none) p1 = 0.0;
-  return none ? 1 : (ph == LIQ ? p1 < p_min : p1 > p_tilde);
+  return none ? 1 : (PH == LIQ ? p1 < p_min : p1 > p_tilde);
+}
+
+// (the phase as a constant: every per-phase constant is then read directly
+// instead of selected)
+__device__ __forceinline__ int c_creates(const Mat& M, int ph, double rl, double ml, double rr,
+                                         double mr, double p_min, double p_tilde, double& p1) {
+  return ph == LIQ ? c_creates_t<LIQ>(M, rl, ml, rr, mr, p_min, p_tilde, p1)
+                   : c_creates_t<VAP>(M, rl, ml, rr, mr, p_min, p_tilde, p1);
 }
 
 }  // namespace

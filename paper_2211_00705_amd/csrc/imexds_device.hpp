@@ -48,6 +48,25 @@ struct Mat {
   double irv0, irl0;  // 1 / rhov0, 1 / rhol0
 };
 
+// The material constants in vector registers.  Kernels select them per lane
+// by phase (vapour or liquid); from a struct in the kernel arguments the
+// compiler turns such a select into a load from a selected address, which
+// needs a copy of the struct in scratch memory.  OR-ing each constant's bits
+// with a zero it cannot see through (a vector register set by one v_mov)
+// keeps every value as it is but places it in a vector register.
+__device__ __forceinline__ Mat d_mat_vregs(const Mat& src) {
+  int vz;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(vz));
+  Mat M = src;
+#define D_MAT_VREG(x) x = __longlong_as_double(__double_as_longlong(x) | (long long)vz)
+  D_MAT_VREG(M.a2v); D_MAT_VREG(M.a2l); D_MAT_VREG(M.p0); D_MAT_VREG(M.rhol0);
+  D_MAT_VREG(M.tau); D_MAT_VREG(M.av); D_MAT_VREG(M.al); D_MAT_VREG(M.rhov0);
+  D_MAT_VREG(M.ia2v); D_MAT_VREG(M.ia2l); D_MAT_VREG(M.iav); D_MAT_VREG(M.ial);
+  D_MAT_VREG(M.irv0); D_MAT_VREG(M.irl0);
+#undef D_MAT_VREG
+  return M;
+}
+
 struct Par {
   double cfl, theta_nb, tol_nb, tol_tiny, tol_rel, alpha_floor, merge_safety, newton_rtol, t_end;
   int zone_half, tol_mode, lmax, bc_left, bc_right, newton_maxit;
@@ -72,29 +91,33 @@ __device__ __forceinline__ double d_rho_of_p(const Mat& M, int ph, double p) {
 // series through f^24/25 (Estrin's scheme), plus e ln 2 with ln 2 split into a head
 // with trailing zero bits and a tail (as in fdlibm).  Plain IEEE double
 // operations in a fixed order: the result is the same on any IEEE machine,
-// which keeps iteration counts that hinge on a logarithm reproducible.
+// which keeps iteration counts that hinge on a logarithm reproducible.  The
+// subnormal scaling and the special arguments (0, negative, infinite, NaN)
+// are selected rather than branched to: a lone wave pays an issue slot for
+// every instruction, and the branches' mask bookkeeping costs more than the
+// few unused operations.
+template <bool SELECT = true>
 __device__ __forceinline__ double d_log(double x) {
-  if (!(x > 0.0)) return x == 0.0 ? -__builtin_inf() : __builtin_nan("");
-  if (!__builtin_isfinite(x)) return x;
-  unsigned long long b = (unsigned long long)__double_as_longlong(x);
-  int ex = (int)((b >> 52) & 0x7ff);
-  int e;
-  if (ex == 0) {
-    double y = x * 18014398509481984.0;
-    b = (unsigned long long)__double_as_longlong(y);
-    e = (int)((b >> 52) & 0x7ff) - 1023 - 54;
-  } else {
-    e = ex - 1023;
+  if (!SELECT) {
+    if (!(x > 0.0)) return x == 0.0 ? -__builtin_inf() : __builtin_nan("");
+    if (!__builtin_isfinite(x)) return x;
   }
+  const bool pos = x > 0.0;
+  const bool fin = __builtin_isfinite(x);
+  unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const int ex = (int)((b >> 52) & 0x7ff);
+  const bool sub = ex == 0;
+  const double y = x * 18014398509481984.0;
+  const unsigned long long by = (unsigned long long)__double_as_longlong(y);
+  b = sub ? by : b;
+  int e = (int)((b >> 52) & 0x7ff) - 1023 - (sub ? 54 : 0);
   b = (b & 0x000fffffffffffffull) | 0x3ff0000000000000ull;
   double m = __longlong_as_double((long long)b);
-  if (m > 1.4142135623730951) {
-    m = 0.5 * m;
-    e += 1;
-  }
+  const bool hi = m > 1.4142135623730951;
+  m = hi ? 0.5 * m : m;
+  e += hi ? 1 : 0;
   double f = (m - 1.0) / (m + 1.0);
   double s = f * f;
-  // Estrin's scheme for sum_{k=0}^{12} s^k / (2k+1)
   double s2 = s * s, s4 = s2 * s2, s8 = s4 * s4;
   double q0 = 1.0 + (1.0 / 3.0) * s, q1 = (1.0 / 5.0) + (1.0 / 7.0) * s;
   double q2 = (1.0 / 9.0) + (1.0 / 11.0) * s, q3 = (1.0 / 13.0) + (1.0 / 15.0) * s;
@@ -104,7 +127,9 @@ __device__ __forceinline__ double d_log(double x) {
   double p = t0 + t1 * s8;
   double r = (2.0 * f) * p;
   double de = (double)e;
-  return de * 0x1.62e42feep-1 + (de * 0x1.a39ef35793c76p-33 + r);
+  const double res = de * 0x1.62e42feep-1 + (de * 0x1.a39ef35793c76p-33 + r);
+  const double spec = x == 0.0 ? -__builtin_inf() : (pos ? x : __builtin_nan(""));
+  return (pos && fin) ? res : spec;
 }
 
 __device__ __forceinline__ double d_gibbs(const Mat& M, int ph, double r) {
@@ -207,19 +232,34 @@ __device__ __forceinline__ void d_side(const Mat& M, int ph, double r, double m,
 // Outer wave of one side at star pressure ps: rho*, v*, Gibbs energy, f_K and
 // df_K/dp*.  Shock branch sqrt(-[[p]][[v]]) written a (rho* - rho_K) /
 // sqrt(rho_K rho*), exact for pressure laws affine in rho; rarefaction branch:
-// the integral of v/a, a ln(rho*/rho_K).
+// the integral of v/a, a ln(rho*/rho_K).  SELECT: both branches are computed
+// and one is selected (the two lanes of a pair solve, and the groups of a
+// wave, take different branches anyway); otherwise the branch is taken.  False
+// if rho* is not positive and finite, in which case the outputs are
+// meaningless.
+template <bool SELECT = true>
 __device__ __forceinline__ bool d_wave(const Mat& M, const Side& S, double ps, double& rs,
                                        double& v, double& g, double& f, double& df) {
   const bool vap = S.ph == VAP;
   double r = d_rho_of_p(M, S.ph, ps);
-  if (!(r > 0.0) || !d_finite(r)) return false;
+  const bool ok = (r > 0.0) && d_finite(r);
+  if (!SELECT && !ok) return false;
   v = 1.0 / r;
-  double L = d_log(r * (vap ? M.irv0 : M.irl0));
+  double L = d_log<SELECT>(r * (vap ? M.irv0 : M.irl0));
   rs = r;
   g = (vap ? M.a2v : M.a2l) * L;
   const double a = vap ? M.av : M.al;
   const double ia = vap ? M.iav : M.ial;
-  if (ps > S.p) {
+  if (SELECT) {
+    const bool shock = ps > S.p;
+    const double ig = 1.0 / sqrt(S.r * r);
+    const double fs = (a * (r - S.r)) * ig;
+    const double dfs = ((r + S.r) * ig) * (v * (0.5 * ia));
+    const double fr = a * (L - S.LK);
+    const double dfr = v * ia;
+    f = shock ? fs : fr;
+    df = shock ? dfs : dfr;
+  } else if (ps > S.p) {
     double ig = 1.0 / sqrt(S.r * r);
     f = (a * (r - S.r)) * ig;
     df = ((r + S.r) * ig) * (v * (0.5 * ia));
@@ -227,7 +267,7 @@ __device__ __forceinline__ bool d_wave(const Mat& M, const Side& S, double ps, d
     f = a * (L - S.LK);
     df = v * ia;
   }
-  return true;
+  return ok;
 }
 
 // Exchange of one double with a partner lane (both lanes active).
@@ -239,14 +279,17 @@ __device__ __forceinline__ double d_swap(double x, int partner) { return __shfl(
 // PAIR: two lanes evaluate together, the lane with side 0 the left outer
 // wave and the one with side 1 the right one (same operations as one lane
 // doing both), then swap them; everything after is computed on both lanes
-// from identical values.
+// from identical values.  Straight-line code: the tests that make an
+// evaluation invalid are combined into the result, and the outputs of an
+// invalid evaluation are not used.
 template <bool PAIR>
 __device__ __forceinline__ bool d_eval_G_t(const Mat& M, const RP& R, double psl, double psr,
                                            int side, int partner, GEval& E) {
   double gl, gr, dfl, dfr;
+  bool okw;
   if (PAIR) {
     double rs = 0.0, v = 0.0, g = 0.0, f = 0.0, df = 0.0;
-    Side me;  // field by field: a selected struct reference would go through scratch
+    Side me;
     me.ph = side == 0 ? R.L.ph : R.Rt.ph;
     me.r = side == 0 ? R.L.r : R.Rt.r;
     me.u = side == 0 ? R.L.u : R.Rt.u;
@@ -256,17 +299,16 @@ __device__ __forceinline__ bool d_eval_G_t(const Mat& M, const RP& R, double psl
     const double o_rs = d_swap(rs, partner), o_v = d_swap(v, partner), o_g = d_swap(g, partner);
     const double o_f = d_swap(f, partner), o_df = d_swap(df, partner);
     const bool o_ok = __shfl(ok ? 1 : 0, partner, 64) != 0;
-    if (!ok || !o_ok) return false;
-    if (side == 0) {
-      E.rsl = rs; E.vl = v; gl = g; E.fl = f; dfl = df;
-      E.rsr = o_rs; E.vr = o_v; gr = o_g; E.fr = o_f; dfr = o_df;
-    } else {
-      E.rsl = o_rs; E.vl = o_v; gl = o_g; E.fl = o_f; dfl = o_df;
-      E.rsr = rs; E.vr = v; gr = g; E.fr = f; dfr = df;
-    }
+    okw = ok && o_ok;
+    const bool s0 = side == 0;
+    E.rsl = s0 ? rs : o_rs; E.vl = s0 ? v : o_v; gl = s0 ? g : o_g; E.fl = s0 ? f : o_f;
+    dfl = s0 ? df : o_df;
+    E.rsr = s0 ? o_rs : rs; E.vr = s0 ? o_v : v; gr = s0 ? o_g : g; E.fr = s0 ? o_f : f;
+    dfr = s0 ? o_df : df;
   } else {
-    if (!d_wave(M, R.L, psl, E.rsl, E.vl, gl, E.fl, dfl)) return false;
-    if (!d_wave(M, R.Rt, psr, E.rsr, E.vr, gr, E.fr, dfr)) return false;
+    const bool okl = d_wave(M, R.L, psl, E.rsl, E.vl, gl, E.fl, dfl);
+    const bool okr = d_wave(M, R.Rt, psr, E.rsr, E.vr, gr, E.fr, dfr);
+    okw = okl && okr;
   }
   const double vl = E.vl, vr = E.vr;
   const bool lvap = R.phl == VAP;
@@ -278,7 +320,7 @@ __device__ __forceinline__ bool d_eval_G_t(const Mat& M, const RP& R, double psl
   const double A = 0.5 * q * jv2;
   const double C = q * jg;
   const double D = 1.0 - 4.0 * A * C;
-  if (!(D >= 0.0) || !d_finite(D)) return false;
+  const bool okd = (D >= 0.0) && d_finite(D);
   const double sD = sqrt(D);
   const double isD = 1.0 / sD;
   const double z = 2.0 * C / (1.0 + sD);
@@ -286,13 +328,11 @@ __device__ __forceinline__ bool d_eval_G_t(const Mat& M, const RP& R, double psl
   double dAr = -(q * ((vr * vr * vr) * ia2r));
   double dCl = -(q * vl);
   double dCr = q * vr;
-  if (lvap) {
-    dAl += (0.5 * M.tau) * jv2;
-    dCl += M.tau * jg;
-  } else {
-    dAr += (0.5 * M.tau) * jv2;
-    dCr += M.tau * jg;
-  }
+  const double hjv2 = (0.5 * M.tau) * jv2, tjg = M.tau * jg;
+  dAl = lvap ? dAl + hjv2 : dAl;
+  dCl = lvap ? dCl + tjg : dCl;
+  dAr = lvap ? dAr : dAr + hjv2;
+  dCr = lvap ? dCr : dCr + tjg;
   const double dzl = (dAl * z * z + dCl) * isD;
   const double dzr = (dAr * z * z + dCr) * isD;
   const double jv = vr - vl;
@@ -309,10 +349,9 @@ __device__ __forceinline__ bool d_eval_G_t(const Mat& M, const RP& R, double psl
   E.J12 = 1.0 + 2.0 * z * dzr * jv - z * z * er;
   E.J21 = dfl + dzl * jv + z * el;
   E.J22 = dfr + dzr * jv - z * er;
-  if (!d_finite(E.G1) || !d_finite(E.G2)) return false;
   const double a = E.G1 * R.izref;
   E.m2 = a * a + E.G2 * E.G2;
-  return true;
+  return okw && okd && d_finite(E.G1) && d_finite(E.G2);
 }
 
 __device__ __forceinline__ bool d_eval_G(const Mat& M, const RP& R, double psl, double psr,

@@ -81,17 +81,8 @@ __global__ __launch_bounds__(64) void k_zone8(StepArgs A, int if_begin, int if_e
   // The material constants are read in every pass of the dual time loop.
   // Uniform values live in scalar registers, which this kernel runs out of
   // (the spills cost a v_readlane each in the loop); it has vector registers
-  // to spare at its occupancy.  OR-ing each constant's bits with a zero the
-  // compiler cannot see through (a vector register set by one v_mov) keeps
-  // every value as it is but places it in vector registers.
-  int vz;
-  asm volatile("v_mov_b32 %0, 0" : "=v"(vz));
-  Mat Mv = A.mat;
-#define Z8_VREG(x) x = __longlong_as_double(__double_as_longlong(x) | (long long)vz)
-  Z8_VREG(Mv.a2v); Z8_VREG(Mv.a2l); Z8_VREG(Mv.p0); Z8_VREG(Mv.rhol0); Z8_VREG(Mv.tau);
-  Z8_VREG(Mv.av); Z8_VREG(Mv.al); Z8_VREG(Mv.rhov0); Z8_VREG(Mv.ia2v); Z8_VREG(Mv.ia2l);
-  Z8_VREG(Mv.iav); Z8_VREG(Mv.ial); Z8_VREG(Mv.irv0); Z8_VREG(Mv.irl0);
-#undef Z8_VREG
+  // to spare at its occupancy.
+  const Mat Mv = d_mat_vregs(A.mat);
   const Mat& M = Mv;
   const Par& P = A.par;
   const int lane = threadIdx.x;
