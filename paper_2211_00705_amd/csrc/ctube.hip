@@ -399,7 +399,7 @@ __global__ __launch_bounds__(64) void k_ct_zone(Args A) {
                                            lf ? W[Z - 1][0] : W[Z][0], lf ? W[Z - 1][1] : W[Z][1],
                                            lf ? phn : ph, lf ? W[Z][0] : W[Z + 1][0],
                                            lf ? W[Z][1] : W[Z + 1][1], true, lf ? pl0 : pr0,
-                                           lf ? pl1 : pr1, half, lane ^ 1, I)) {
+                                           lf ? pl1 : pr1, half, I)) {
         ec = 1;
       } else if (lf) {
         wl = I.w;
@@ -679,8 +679,7 @@ __global__ __launch_bounds__(64) void k_ct_newton(Args A) {
       if (!imexds::d_iface_solve_t<L == 4>(M, A.newton_maxit, A.newton_rtol, lf ? ph : phn,
                                            lf ? X[Z - 1][0] : X[Z][0], lf ? X[Z - 1][1] : X[Z][1],
                                            lf ? phn : ph, lf ? X[Z][0] : X[Z + 1][0],
-                                           lf ? X[Z][1] : X[Z + 1][1], true, g0, g1, half,
-                                           lane ^ 1, I)) {
+                                           lf ? X[Z][1] : X[Z + 1][1], true, g0, g1, half, I)) {
         ec = 1;
       } else if (lf) {
         ewl = I.w;

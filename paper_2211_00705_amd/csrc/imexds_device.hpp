@@ -270,8 +270,19 @@ __device__ __forceinline__ bool d_wave(const Mat& M, const Side& S, double ps, d
   return ok;
 }
 
-// Exchange of one double with a partner lane (both lanes active).
-__device__ __forceinline__ double d_swap(double x, int partner) { return __shfl(x, partner, 64); }
+// Exchange with the pair's other lane.  The two lanes of a pair solve are an
+// even lane and the odd one after it (lane and lane ^ 1), both active, so the
+// exchange is one DPP quad permutation [1,0,3,2] per 32 bits: a VALU move
+// that waits no longer than any other, where a lane permute goes through the
+// LDS crossbar (about 70 cycles).
+__device__ __forceinline__ int d_swap_i(int x) {
+  return __builtin_amdgcn_update_dpp(x, x, 0xB1, 0xF, 0xF, false);
+}
+__device__ __forceinline__ double d_swap(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = d_swap_i((int)b), hi = d_swap_i((int)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
 
 // G(p_l*, p_r*) and its Jacobian.  z solves A z^2 - z + C = 0 with
 // A = tau p_V [[v^2]] / 2, C = tau p_V [[g]] (root continuous at A = 0);
@@ -284,7 +295,7 @@ __device__ __forceinline__ double d_swap(double x, int partner) { return __shfl(
 // invalid evaluation are not used.
 template <bool PAIR>
 __device__ __forceinline__ bool d_eval_G_t(const Mat& M, const RP& R, double psl, double psr,
-                                           int side, int partner, GEval& E) {
+                                           int side, GEval& E) {
   double gl, gr, dfl, dfr;
   bool okw;
   if (PAIR) {
@@ -296,9 +307,9 @@ __device__ __forceinline__ bool d_eval_G_t(const Mat& M, const RP& R, double psl
     me.p = side == 0 ? R.L.p : R.Rt.p;
     me.LK = side == 0 ? R.L.LK : R.Rt.LK;
     const bool ok = d_wave(M, me, side == 0 ? psl : psr, rs, v, g, f, df);
-    const double o_rs = d_swap(rs, partner), o_v = d_swap(v, partner), o_g = d_swap(g, partner);
-    const double o_f = d_swap(f, partner), o_df = d_swap(df, partner);
-    const bool o_ok = __shfl(ok ? 1 : 0, partner, 64) != 0;
+    const double o_rs = d_swap(rs), o_v = d_swap(v), o_g = d_swap(g);
+    const double o_f = d_swap(f), o_df = d_swap(df);
+    const bool o_ok = d_swap_i(ok ? 1 : 0) != 0;
     okw = ok && o_ok;
     const bool s0 = side == 0;
     E.rsl = s0 ? rs : o_rs; E.vl = s0 ? v : o_v; gl = s0 ? g : o_g; E.fl = s0 ? f : o_f;
@@ -356,7 +367,7 @@ __device__ __forceinline__ bool d_eval_G_t(const Mat& M, const RP& R, double psl
 
 __device__ __forceinline__ bool d_eval_G(const Mat& M, const RP& R, double psl, double psr,
                                          GEval& E) {
-  return d_eval_G_t<false>(M, R, psl, psr, 0, 0, E);
+  return d_eval_G_t<false>(M, R, psl, psr, 0, E);
 }
 
 // HLLC-type start (eq. HLLC:2p_nopt, mirrored when the liquid is on the left):
@@ -395,22 +406,22 @@ __device__ __forceinline__ void d_guess(const Mat& M, const RP& R, double& gl, d
 // is kept when the step is already below 1e-8 (round-off floor), else the
 // start fails; at most maxit steps per start.  Written as one loop with a
 // single evaluation site so that lanes at different stages share it.
-// PAIR: two lanes solve together (see d_eval_G_t): the lane with side 0
-// passes the left state in (rl, ml), the one with side 1 the right state in
-// (rr, mr); each sets up its own side and the two swap them; both lanes
-// return the same result.
+// PAIR: two lanes solve together (see d_eval_G_t): the lane with side 0, an
+// even lane, passes the left state in (rl, ml), the one with side 1, the odd
+// lane after it, the right state in (rr, mr); each sets up its own side and
+// the two swap them (d_swap); both lanes return the same result.
 template <bool PAIR>
 __device__ __forceinline__ bool d_iface_solve_t(const Mat& M, int maxit, double rtol, int phl,
                                                 double rl, double ml, int phr, double rr,
                                                 double mr, bool have_guess, double gl, double gr,
-                                                int side, int partner, IfaceOut& out) {
+                                                int side, IfaceOut& out) {
   RP R;
   R.phl = phl;
   if (PAIR) {
     Side own;
     d_side(M, side == 0 ? phl : phr, side == 0 ? rl : rr, side == 0 ? ml : mr, own);
-    const double o_r = d_swap(own.r, partner), o_u = d_swap(own.u, partner);
-    const double o_p = d_swap(own.p, partner), o_LK = d_swap(own.LK, partner);
+    const double o_r = d_swap(own.r), o_u = d_swap(own.u);
+    const double o_p = d_swap(own.p), o_LK = d_swap(own.LK);
     R.L.ph = phl;
     R.Rt.ph = phr;
     R.L.r = side == 0 ? own.r : o_r;
@@ -446,7 +457,7 @@ __device__ __forceinline__ bool d_iface_solve_t(const Mat& M, int maxit, double 
   int nev = 0;
   for (;;) {
     GEval Et;
-    const bool valid = d_eval_G_t<PAIR>(M, R, tl, tr, side, partner, Et);
+    const bool valid = d_eval_G_t<PAIR>(M, R, tl, tr, side, Et);
     ++nev;
     bool done = false, take = false, next = false, acc = false;
     if (mode == 0) {
@@ -563,7 +574,7 @@ __device__ __forceinline__ bool d_iface_solve(const Mat& M, int maxit, double rt
                                               bool have_guess, double gl, double gr,
                                               IfaceOut& out) {
   return d_iface_solve_t<false>(M, maxit, rtol, phl, rl, ml, phr, rr, mr, have_guess, gl, gr, 0,
-                                0, out);
+                                out);
 }
 
 // Start of the interface solve of the next dual time pass.  The solver's

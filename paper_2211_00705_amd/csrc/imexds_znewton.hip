@@ -233,7 +233,7 @@ __global__ __launch_bounds__(64) void k_zone_nt(StepArgs A, int if_begin, int if
     const double g1 = pred ? rpw1 : (fd ? gw1 : pw1);
     IfaceOut o;
     const bool okl = d_iface_solve_t<LG == 2>(M, P.newton_maxit, P.newton_rtol, phl, ql0, ql1,
-                                              phr, qr0, qr1, hg, g0, g1, half, lane ^ 1, o);
+                                              phr, qr0, qr1, hg, g0, g1, half, o);
     const unsigned long long failm = __ballot(!okl);
     const unsigned long long zm = ((1ull << TL) - 1ull) << lane0;
     if (failm & zm) {

@@ -108,8 +108,8 @@ __global__ __launch_bounds__(64) void k_zone8(StepArgs A, int if_begin, int if_e
   double gn0 = 0.0, gn1 = 0.0;
   DtsRoots H;
   d_dts_reset(H);
-  // per lane: U^n of zone position c, and the active cell c
-  double Ur = 1.0, Um = 0.0;
+  // per lane: U^n of zone position c (and of position c + 1), and the active cell c
+  double Ur = 1.0, Um = 0.0, nUr = 1.0, nUm = 0.0;
   int pos = -1;  // zone position of active cell c (-1: lane idle)
   double W0 = 1.0, W1 = 0.0, U00 = 1.0, U01 = 0.0, hn = 0.0, th = 0.0, it1 = 0.0, mv = 0.0;
   double tol = 0.0;
@@ -193,6 +193,8 @@ __global__ __launch_bounds__(64) void k_zone8(StepArgs A, int if_begin, int if_e
         Ur = r0[zlo + c];
         Um = m0[zlo + c];
       }
+      nUr = z8_from_next(Ur);
+      nUm = z8_from_next(Um);
       // bounding fluxes from U^n: F_left on lane 0, F_right on lane 1
       {
         double f0 = 0.0, f1 = 0.0;
@@ -230,22 +232,28 @@ __global__ __launch_bounds__(64) void k_zone8(StepArgs A, int if_begin, int if_e
     // ---------------- one interface solve (two lanes of the group) ----------------
     const bool pred = stage == S_PRED;
     // prediction: zone positions iL, iR hold the two sides; iteration:
-    // active cells ic, ic + 1
+    // active cells ic, ic + 1.  The pair solve runs on an even lane and the
+    // odd one after it (its exchanges are DPP quad permutations): on a0, a0 + 1
+    // for an even a0, else on a0 - 1, a0, which take their states from the
+    // right neighbour's values (U^n of the next zone position, the next
+    // active cell's iterate).
     const int a0 = pred ? iL : ic;
+    const int p0 = a0 & ~1;
+    const bool shifted = (a0 & 1) != 0;
     int side = -1;
-    if (c == a0) side = 0;
-    if (c == a0 + 1) side = 1;
+    if (c == p0) side = 0;
+    if (c == p0 + 1) side = 1;
     IfaceOut o;
     o.pl = o.pr = o.rl = o.rr = o.ul = o.ur = o.z = o.w = o.F0 = o.F1 = 0.0;
     o.nev = 0;
     int okl = 0;
     if (side >= 0) {
-      const double x0 = pred ? Ur : W0, x1 = pred ? Um : W1;
+      const double x0 = pred ? (shifted ? nUr : Ur) : (shifted ? nW0 : W0);
+      const double x1 = pred ? (shifted ? nUm : Um) : (shifted ? nW1 : W1);
       const bool hg = pred ? warm != 0 : true;
       const double g0 = pred ? rpw0 : gn0, g1 = pred ? rpw1 : gn1;
-      const int partner = gb + (side == 0 ? a0 + 1 : a0);
       okl = d_iface_solve_t<true>(M, P.newton_maxit, P.newton_rtol, phl, x0, x1, phr, x0, x1, hg,
-                                  g0, g1, side, partner, o)
+                                  g0, g1, side, o)
                 ? 1
                 : 0;
       if (side == 0 && okl) {
