@@ -236,6 +236,58 @@ def test_iface_solves_random_configuration_states(material):
         assert fl == pytest.approx(fv, rel=1e-9)
 
 
+def _outputs_at_root(M, phl, rl, ul, phr, rr, ur, pl, pr):
+    """The interface outputs at given star pressures, from the definitions:
+    the outer waves (shock sqrt((p* - p_K)(v_K - v*)), rarefaction
+    a_K ln(rho*/rho_K)), the Gibbs energies a^2 ln(rho/rho_sat) and the
+    kinetic relation z = tau p_V ([[g]] + z^2 [[v^2]]/2) (its root that stays
+    finite as [[v^2]] -> 0); then w from z = -rho_V (u_V* - w)."""
+    def side(ph, r, p_star):
+        a2 = M.a2v if ph == W.VAP else M.a2l
+        rsat = M.p0 / M.a2v if ph == W.VAP else M.rhol0
+        p = M.a2v * r if ph == W.VAP else M.p0 + M.a2l * (r - M.rhol0)
+        rs = rho_of_p(M, ph, p_star)
+        if p_star > p:
+            f = math.sqrt((p_star - p) * (1.0 / r - 1.0 / rs))
+        else:
+            f = math.sqrt(a2) * math.log(rs / r)
+        return rs, 1.0 / rs, a2 * math.log(rs / rsat), f
+    rsl, vl, gl, fl = side(phl, rl, pl)
+    rsr, vr, gr, fr = side(phr, rr, pr)
+    pV = pl if phl == W.VAP else pr
+    q = M.tau * pV
+    A, C = 0.5 * q * (vr * vr - vl * vl), q * (gr - gl)
+    z = 2.0 * C / (1.0 + math.sqrt(1.0 - 4.0 * A * C))
+    usl, usr = ul - fl, ur + fr
+    uV, vV = (usl, vl) if phl == W.VAP else (usr, vr)
+    return dict(rl=rsl, rr=rsr, ul=usl, ur=usr, z=z, w=uV + z * vV)
+
+
+def test_iface_outputs_are_those_of_the_returned_root(material):
+    """The solve ends with a Newton step below 1e-10 (relative) applied to
+    the root and, to first order, to the outputs.  Recomputed from the
+    definitions at the returned root, the outputs agree to round-off: the
+    first-order finish leaves an error of the order of the step squared."""
+    rng = np.random.default_rng(19)
+    for i in range(300):
+        rl, ul = rng.uniform(900, 1000), rng.uniform(-1, 1)
+        rv, uv = rng.uniform(0.01, 0.1), rng.uniform(-1, 1)
+        if i % 2:
+            args = (W.LIQ, rl, ul, W.VAP, rv, uv)
+        else:
+            args = (W.VAP, rv, uv, W.LIQ, rl, ul)
+        r = oracle.iface_solve(material, *args)
+        assert r["ok"]
+        e = _outputs_at_root(material, *args, r["pl"], r["pr"])
+        U = max(abs(r["ul"]), abs(r["ur"]), abs(r["w"]), 1.0)
+        for k in ("rl", "rr"):
+            assert r[k] == pytest.approx(e[k], rel=1e-14)
+        for k in ("ul", "ur", "w"):
+            assert abs(r[k] - e[k]) <= 1e-12 * U, (i, k, r[k], e[k])
+        # z: a mass flux of size rho_L |u* - w|
+        assert abs(r["z"] - e["z"]) <= 1e-12 * max(abs(e["z"]), 1e-6 * rl * U), (i, r["z"], e["z"])
+
+
 # ---------------------------------------------------------------------------
 # bulk scheme
 # ---------------------------------------------------------------------------
