@@ -136,19 +136,22 @@ __device__ __forceinline__ void d_wave_lin(const Mat& M, int ph, double rK, doub
   }
 }
 
-__device__ __forceinline__ void d_iface_lin(const Mat& M, int phl, double rl, double ml,
-                                            double rr, double mr, double psl, double psr,
-                                            IfaceLin& Q) {
-  const int phr = phl ^ 1;
+// The linearisation from the two outer waves (d_wave_lin of each side).
+__device__ __forceinline__ void d_iface_lin_w(const Mat& M, int phl, double rl, double ml,
+                                              double rr, double mr, double psl, double psr,
+                                              double vl, double gl, double fl, double dfl,
+                                              double dfl_r, double vr, double gr, double fr,
+                                              double dfr, double dfr_r, IfaceLin& Q) {
   const bool lvap = phl == VAP;
   Q.lvap = lvap;
   Q.rl = rl;
   Q.rr = rr;
   Q.ul = ml / rl;
   Q.ur = mr / rr;
-  double vl, gl, fl, vr, gr, fr;
-  d_wave_lin(M, phl, rl, psl, vl, gl, fl, Q.dfl, Q.dfl_r);
-  d_wave_lin(M, phr, rr, psr, vr, gr, fr, Q.dfr, Q.dfr_r);
+  Q.dfl = dfl;
+  Q.dfl_r = dfl_r;
+  Q.dfr = dfr;
+  Q.dfr_r = dfr_r;
   const double ia2l = lvap ? M.ia2v : M.ia2l, ia2r = lvap ? M.ia2l : M.ia2v;
   const double pV = lvap ? psl : psr;
   const double q = M.tau * pV;
@@ -194,6 +197,16 @@ __device__ __forceinline__ void d_iface_lin(const Mat& M, int phl, double rl, do
   Q.w = Q.uVs + z * Q.vV;
   Q.F0 = -z;
   Q.F1 = -z * Q.uVs + pV;
+}
+
+__device__ __forceinline__ void d_iface_lin(const Mat& M, int phl, double rl, double ml,
+                                            double rr, double mr, double psl, double psr,
+                                            IfaceLin& Q) {
+  double vl, gl, fl, dfl, dfl_r, vr, gr, fr, dfr, dfr_r;
+  d_wave_lin(M, phl, rl, psl, vl, gl, fl, dfl, dfl_r);
+  d_wave_lin(M, phl ^ 1, rr, psr, vr, gr, fr, dfr, dfr_r);
+  d_iface_lin_w(M, phl, rl, ml, rr, mr, psl, psr, vl, gl, fl, dfl, dfl_r, vr, gr, fr, dfr, dfr_r,
+                Q);
 }
 
 // Reverse of one interface solve: adjoints (b0, b1, bw) of (F0, F1, w) to the
@@ -708,14 +721,31 @@ __device__ __forceinline__ void a8_pass_rev(const Mat& M, ZoneRev8& Z, bool part
                                             double W1, double rpl, double rpr, double N0,
                                             double N1, double gO0, double gO1, double gwx,
                                             double& gW0, double& gW1) {
-  const int c = Z.c, gb = Z.gb;
-  const int cn = c < 7 ? c + 1 : 7;
-  const double nW0 = a8_get(W0, gb, cn), nW1 = a8_get(W1, gb, cn);
+  // Neighbour values come by DPP row shifts: the 8-lane groups sit inside the
+  // 16-lane rows, and the lanes whose shift would cross a group boundary
+  // (lane 7 from the next group, lane 0 from the previous) do not use them.
+  const int c = Z.c;
+  const double nW0 = d_lane_next(W0), nW1 = d_lane_next(W1);
   IfaceLin Q;
   Q.F0 = Q.F1 = Q.w = 0.0;
-  if (c == Z.ic) d_iface_lin(M, Z.phl, W0, W1, nW0, nW1, rpl, rpr, Q);
-  const double F0pb = a8_get(Q.F0, gb, Z.ic), F1pb = a8_get(Q.F1, gb, Z.ic);
-  const double w = a8_get(Q.w, gb, Z.ic);
+  // the two outer waves side by side: lane ic the left one (its own cell),
+  // lane ic + 1 the right one; lane ic then takes the right one's results
+  double wv = 0.0, wg = 0.0, wf = 0.0, wdf = 0.0, wdr = 0.0;
+  if (c == Z.ic || c == Z.ic + 1) {
+    const bool lft = c == Z.ic;
+    d_wave_lin(M, lft ? Z.phl : Z.phl ^ 1, W0, lft ? rpl : rpr, wv, wg, wf, wdf, wdr);
+  }
+  const double ov = d_lane_next(wv), og = d_lane_next(wg), of = d_lane_next(wf);
+  const double odf = d_lane_next(wdf), odr = d_lane_next(wdr);
+  if (c == Z.ic)
+    d_iface_lin_w(M, Z.phl, W0, W1, nW0, nW1, rpl, rpr, wv, wg, wf, wdf, wdr, ov, og, of, odf, odr,
+                  Q);
+  // the boundary's flux is used on lane ic, which holds it; its speed on
+  // the two moving cells ic and ic + 1 (every other cell has mv = 0 and
+  // keeps its length whatever the speed)
+  const double F0pb = Q.F0, F1pb = Q.F1;
+  const double wprev = d_lane_prev(Q.w);
+  const double w = c == Z.ic ? Q.w : (c == Z.ic + 1 ? wprev : 0.0);
   const bool act = c < Z.m;
   double Fr0 = 0.0, Fr1 = 0.0;
   if (act) {
@@ -729,8 +759,7 @@ __device__ __forceinline__ void a8_pass_rev(const Mat& M, ZoneRev8& Z, bool part
       d_hll(M, Z.ph, W0, W1, nW0, nW1, Fr0, Fr1);
     }
   }
-  const int cp = c > 0 ? c - 1 : 0;
-  double Fl0 = a8_get(Fr0, gb, cp), Fl1 = a8_get(Fr1, gb, cp);
+  double Fl0 = d_lane_prev(Fr0), Fl1 = d_lane_prev(Fr1);
   if (c == 0) {
     Fl0 = Z.FL0;
     Fl1 = Z.FL1;
@@ -769,7 +798,7 @@ __device__ __forceinline__ void a8_pass_rev(const Mat& M, ZoneRev8& Z, bool part
   }
   // adjoint of the flux on the right face of c: own part plus the left-face
   // part of cell c + 1
-  double gF0 = gfr0 + a8_get(gfl0, gb, cn), gF1 = gfr1 + a8_get(gfl1, gb, cn);
+  double gF0 = gfr0 + d_lane_next(gfl0), gF1 = gfr1 + d_lane_next(gfl1);
   if (c == 0) {
     Z.gFL0 += gfl0;
     Z.gFL1 += gfl1;
@@ -778,7 +807,9 @@ __device__ __forceinline__ void a8_pass_rev(const Mat& M, ZoneRev8& Z, bool part
     Z.gFR0 += gfr0;
     Z.gFR1 += gfr1;
   }
-  const double gw = a8_sum(gwl) + gwx;
+  // only the moving cells ic and ic + 1 carry a speed adjoint; it is needed
+  // on lane ic
+  const double gw = (gwl + d_lane_next(gwl)) + gwx;
   double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;  // own / right neighbour
   if (act && c < Z.m - 1) {
     if (c == Z.ic)
@@ -786,8 +817,8 @@ __device__ __forceinline__ void a8_pass_rev(const Mat& M, ZoneRev8& Z, bool part
     else
       d_hll_adj(M, Z.ph, W0, W1, nW0, nW1, gF0, gF1, a0, a1, b0, b1);
   }
-  gW0 += a0 + a8_get(b0, gb, cp) * (c > 0 ? 1.0 : 0.0);
-  gW1 += a1 + a8_get(b1, gb, cp) * (c > 0 ? 1.0 : 0.0);
+  gW0 += a0 + d_lane_prev(b0) * (c > 0 ? 1.0 : 0.0);
+  gW1 += a1 + d_lane_prev(b1) * (c > 0 ? 1.0 : 0.0);
 }
 
 }  // namespace

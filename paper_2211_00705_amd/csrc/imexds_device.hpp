@@ -270,6 +270,23 @@ __device__ __forceinline__ bool d_wave(const Mat& M, const Side& S, double ps, d
   return ok;
 }
 
+// Value of the next / previous lane in the 16-lane row (a DPP row shift, a
+// VALU move; a lane permute goes through the LDS crossbar, about 70 cycles).
+// A lane whose source lies outside its row keeps its own value; the source
+// lane must be active.
+__device__ __forceinline__ double d_lane_next(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, 0x101, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), 0x101, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ double d_lane_prev(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, 0x111, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), 0x111, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
 // Exchange with the pair's other lane.  The two lanes of a pair solve are an
 // even lane and the odd one after it (lane and lane ^ 1), both active, so the
 // exchange is one DPP quad permutation [1,0,3,2] per 32 bits: a VALU move

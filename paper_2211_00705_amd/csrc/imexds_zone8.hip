@@ -37,21 +37,6 @@ __device__ __forceinline__ unsigned long long z8_speed_bits(const Mat& M, int ph
 __device__ __forceinline__ double z8_get(double x, int gb, int c) { return __shfl(x, gb + c, 64); }
 __device__ __forceinline__ int z8_geti(int x, int gb, int c) { return __shfl(x, gb + c, 64); }
 
-// value of the next / previous lane in the 16-lane row (DPP row shift); a
-// lane whose source lies outside the row keeps its own value
-__device__ __forceinline__ double z8_from_next(double x) {
-  const long long b = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, 0x101, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), 0x101, 0xF, 0xF, false);
-  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
-}
-__device__ __forceinline__ double z8_from_prev(double x) {
-  const long long b = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, 0x111, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), 0x111, 0xF, 0xF, false);
-  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
-}
-
 // group-wide AND / OR of a per-lane flag (lanes of the group only)
 __device__ __forceinline__ bool z8_all(bool v, int gb) {
   const unsigned long long b = __ballot(v ? 1 : 0);
@@ -193,8 +178,8 @@ __global__ __launch_bounds__(64) void k_zone8(StepArgs A, int if_begin, int if_e
         Ur = r0[zlo + c];
         Um = m0[zlo + c];
       }
-      nUr = z8_from_next(Ur);
-      nUm = z8_from_next(Um);
+      nUr = d_lane_next(Ur);
+      nUm = d_lane_next(Um);
       // bounding fluxes from U^n: F_left on lane 0, F_right on lane 1
       {
         double f0 = 0.0, f1 = 0.0;
@@ -226,8 +211,8 @@ __global__ __launch_bounds__(64) void k_zone8(StepArgs A, int if_begin, int if_e
     if (stage == S_EXIT) break;
     // the right neighbour's iterate for this pass's HLL flux, read ahead of the
     // interface solve (which leaves it unchanged) so the exchange overlaps it
-    const double nW0 = z8_from_next(W0);
-    const double nW1 = z8_from_next(W1);
+    const double nW0 = d_lane_next(W0);
+    const double nW1 = d_lane_next(W1);
 
     // ---------------- one interface solve (two lanes of the group) ----------------
     const bool pred = stage == S_PRED;
@@ -321,8 +306,8 @@ __global__ __launch_bounds__(64) void k_zone8(StepArgs A, int if_begin, int if_e
           d_hll(M, ph, W0, W1, nW0, nW1, Fr0, Fr1);
         }
       }
-      double Fl0 = z8_from_prev(Fr0);
-      double Fl1 = z8_from_prev(Fr1);
+      double Fl0 = d_lane_prev(Fr0);
+      double Fl1 = d_lane_prev(Fr1);
       if (c == 0) {
         Fl0 = FL0;
         Fl1 = FL1;
