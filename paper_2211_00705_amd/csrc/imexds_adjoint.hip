@@ -971,14 +971,31 @@ __global__ __launch_bounds__(64) void k_zone_adj8(StepArgs A, AdjArgs B) {
   double gW0 = 0.0, gW1 = 0.0;
   a8_pass_rev(M, Z, true, W0, W1, e[2 * MC], e[2 * MC + 1], W0, W1, gO0, gO1,
               (c == Z.ic) ? ghl1 * dt : 0.0, gW0, gW1);
+  // each pass's iterate and root are read from the tape one pass ahead, so
+  // that the loads overlap the pass before
+  double tW0 = 0.0, tW1 = 0.0, tpl = 0.0, tpr = 0.0;
+  if (cnt > 0) {
+    const double* el = T + TAPE_HDR + (long long)(cnt - 1) * E;
+    tW0 = el[ep];
+    tW1 = el[MC + ep];
+    tpl = el[2 * MC];
+    tpr = el[2 * MC + 1];
+  }
   for (int l = cnt - 1; l >= 0; --l) {
-    const double* el = T + TAPE_HDR + (long long)l * E;
     const double N0 = W0, N1 = W1;
-    W0 = el[ep];
-    W1 = el[MC + ep];
+    W0 = tW0;
+    W1 = tW1;
+    const double rpl = tpl, rpr = tpr;
+    if (l > 0) {
+      const double* en = T + TAPE_HDR + (long long)(l - 1) * E;
+      tW0 = en[ep];
+      tW1 = en[MC + ep];
+      tpl = en[2 * MC];
+      tpr = en[2 * MC + 1];
+    }
     const double o0 = gW0, o1 = gW1;
     gW0 = gW1 = 0.0;
-    a8_pass_rev(M, Z, false, W0, W1, el[2 * MC], el[2 * MC + 1], N0, N1, o0, o1, 0.0, gW0, gW1);
+    a8_pass_rev(M, Z, false, W0, W1, rpl, rpr, N0, N1, o0, o1, 0.0, gW0, gW1);
   }
   // W^0 = U0
   Z.gU00 += gW0;
