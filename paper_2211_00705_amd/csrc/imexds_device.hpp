@@ -221,10 +221,12 @@ struct IfaceOut {
   int nev;  // evaluations of G (Newton steps and Armijo trials, all starts)
 };
 
-__device__ __forceinline__ void d_side(const Mat& M, int ph, double r, double m, Side& S) {
+// u: the side's velocity m / r when the caller already has it (has_u)
+__device__ __forceinline__ void d_side(const Mat& M, int ph, double r, double m, Side& S,
+                                       bool has_u = false, double u = 0.0) {
   S.ph = ph;
   S.r = r;
-  S.u = m / r;
+  S.u = has_u ? u : m / r;
   S.p = d_pres(M, ph, r);
   S.LK = d_log(r * (ph == VAP ? M.irv0 : M.irl0));
 }
@@ -426,17 +428,19 @@ __device__ __forceinline__ void d_guess(const Mat& M, const RP& R, double& gl, d
 // PAIR: two lanes solve together (see d_eval_G_t): the lane with side 0, an
 // even lane, passes the left state in (rl, ml), the one with side 1, the odd
 // lane after it, the right state in (rr, mr); each sets up its own side and
-// the two swap them (d_swap); both lanes return the same result.
+// the two swap them (d_swap); both lanes return the same result.  has_u: the
+// caller passes its side's velocity m / r in u_own (PAIR only).
 template <bool PAIR>
 __device__ __forceinline__ bool d_iface_solve_t(const Mat& M, int maxit, double rtol, int phl,
                                                 double rl, double ml, int phr, double rr,
                                                 double mr, bool have_guess, double gl, double gr,
-                                                int side, IfaceOut& out) {
+                                                int side, IfaceOut& out, bool has_u = false,
+                                                double u_own = 0.0) {
   RP R;
   R.phl = phl;
   if (PAIR) {
     Side own;
-    d_side(M, side == 0 ? phl : phr, side == 0 ? rl : rr, side == 0 ? ml : mr, own);
+    d_side(M, side == 0 ? phl : phr, side == 0 ? rl : rr, side == 0 ? ml : mr, own, has_u, u_own);
     const double o_r = d_swap(own.r), o_u = d_swap(own.u);
     const double o_p = d_swap(own.p), o_LK = d_swap(own.LK);
     R.L.ph = phl;

@@ -94,7 +94,7 @@ __global__ __launch_bounds__(64) void k_zone8(StepArgs A, int if_begin, int if_e
   DtsRoots H;
   d_dts_reset(H);
   // per lane: U^n of zone position c (and of position c + 1), and the active cell c
-  double Ur = 1.0, Um = 0.0, nUr = 1.0, nUm = 0.0;
+  double Ur = 1.0, Um = 0.0, nUr = 1.0, nUm = 0.0, Uu = 0.0, nUu = 0.0;
   int pos = -1;  // zone position of active cell c (-1: lane idle)
   double W0 = 1.0, W1 = 0.0, U00 = 1.0, U01 = 0.0, hn = 0.0, th = 0.0, it1 = 0.0, mv = 0.0;
   double tol = 0.0;
@@ -180,6 +180,8 @@ __global__ __launch_bounds__(64) void k_zone8(StepArgs A, int if_begin, int if_e
       }
       nUr = d_lane_next(Ur);
       nUm = d_lane_next(Um);
+      Uu = Um / Ur;
+      nUu = d_lane_next(Uu);
       // bounding fluxes from U^n: F_left on lane 0, F_right on lane 1
       {
         double f0 = 0.0, f1 = 0.0;
@@ -213,6 +215,10 @@ __global__ __launch_bounds__(64) void k_zone8(StepArgs A, int if_begin, int if_e
     // interface solve (which leaves it unchanged) so the exchange overlaps it
     const double nW0 = d_lane_next(W0);
     const double nW1 = d_lane_next(W1);
+    // the lane's velocity and its right neighbour's, for the HLL flux and the
+    // interface solve's set-up
+    const double uo = W1 / W0;
+    const double nu = d_lane_next(uo);
 
     // ---------------- one interface solve (two lanes of the group) ----------------
     const bool pred = stage == S_PRED;
@@ -235,10 +241,11 @@ __global__ __launch_bounds__(64) void k_zone8(StepArgs A, int if_begin, int if_e
     if (side >= 0) {
       const double x0 = pred ? (shifted ? nUr : Ur) : (shifted ? nW0 : W0);
       const double x1 = pred ? (shifted ? nUm : Um) : (shifted ? nW1 : W1);
+      const double xu = pred ? (shifted ? nUu : Uu) : (shifted ? nu : uo);
       const bool hg = pred ? warm != 0 : true;
       const double g0 = pred ? rpw0 : gn0, g1 = pred ? rpw1 : gn1;
       okl = d_iface_solve_t<true>(M, P.newton_maxit, P.newton_rtol, phl, x0, x1, phr, x0, x1, hg,
-                                  g0, g1, side, o)
+                                  g0, g1, side, o, true, xu)
                 ? 1
                 : 0;
       if (side == 0 && okl) {
@@ -303,7 +310,8 @@ __global__ __launch_bounds__(64) void k_zone8(StepArgs A, int if_begin, int if_e
           Fr0 = oF0;
           Fr1 = oF1;
         } else {
-          d_hll(M, ph, W0, W1, nW0, nW1, Fr0, Fr1);
+          d_hll_prim(d_a(M, ph), W0, W1, uo, d_pres(M, ph, W0), nW0, nW1, nu, d_pres(M, ph, nW0),
+                     Fr0, Fr1);
         }
       }
       double Fl0 = d_lane_prev(Fr0);
