@@ -712,34 +712,61 @@ struct ZoneRev8 {
   double gU00, gU01, ghn, gth, gdt, gtau, gFL0, gFL1, gFR0, gFR1;
 };
 
+// The interface linearisations of up to four passes at once: pair j of the
+// group (lanes 2j, 2j + 1) takes pass l_hi - j, the even lane the left outer
+// wave (active cell ic, tape position pic), the odd one the right (ic + 1,
+// pic1); they exchange them by DPP quad permutation and the even lane
+// completes the linearisation and stores it in slots[pass & 3] (A8_LIN
+// doubles).  Lanes without a pass of their own (j >= nb) repeat pass l_hi
+// and store nothing.  Every lane of the group must be active.
+constexpr int A8_LIN = 23;
+
+__device__ __forceinline__ void a8_lin_batch(const Mat& M, const ZoneRev8& Z, const double* T,
+                                             int E, int MC, int l_hi, int nb, int pic, int pic1,
+                                             double (*slots)[A8_LIN]) {
+  const int j = Z.c >> 1, side = Z.c & 1;
+  const int lp = j < nb ? l_hi - j : l_hi;
+  const double* el = T + TAPE_HDR + (long long)lp * E;
+  const int pc = side ? pic1 : pic;
+  const double Wr = el[pc], Wm = el[MC + pc];
+  const double rpl = el[2 * MC], rpr = el[2 * MC + 1];
+  double v, g, f, df, dr;
+  d_wave_lin(M, side ? Z.phr : Z.phl, Wr, side ? rpr : rpl, v, g, f, df, dr);
+  const double oWr = d_swap(Wr), oWm = d_swap(Wm), ov = d_swap(v), og = d_swap(g);
+  const double of = d_swap(f), odf = d_swap(df), odr = d_swap(dr);
+  if (side == 0 && j < nb) {
+    IfaceLin Q;
+    d_iface_lin_w(M, Z.phl, Wr, Wm, oWr, oWm, rpl, rpr, v, g, f, df, dr, ov, og, of, odf, odr, Q);
+    double* q = slots[lp & 3];
+    q[0] = Q.F0; q[1] = Q.F1; q[2] = Q.w; q[3] = Q.z; q[4] = Q.zt; q[5] = Q.dzl; q[6] = Q.dzr;
+    q[7] = Q.J11; q[8] = Q.J12; q[9] = Q.J21; q[10] = Q.J22; q[11] = Q.jv; q[12] = Q.ul;
+    q[13] = Q.ur; q[14] = Q.rl; q[15] = Q.rr; q[16] = Q.dfl; q[17] = Q.dfr; q[18] = Q.dfl_r;
+    q[19] = Q.dfr_r; q[20] = Q.uVs; q[21] = Q.vV; q[22] = Q.dvV;
+  }
+}
+
+__device__ __forceinline__ void a8_lin_load(const double* q, int phl, IfaceLin& Q) {
+  Q.F0 = q[0]; Q.F1 = q[1]; Q.w = q[2]; Q.z = q[3]; Q.zt = q[4]; Q.dzl = q[5]; Q.dzr = q[6];
+  Q.J11 = q[7]; Q.J12 = q[8]; Q.J21 = q[9]; Q.J22 = q[10]; Q.jv = q[11]; Q.ul = q[12];
+  Q.ur = q[13]; Q.rl = q[14]; Q.rr = q[15]; Q.dfl = q[16]; Q.dfr = q[17]; Q.dfl_r = q[18];
+  Q.dfr_r = q[19]; Q.uVs = q[20]; Q.vV = q[21]; Q.dvV = q[22];
+  Q.lvap = phl == VAP;
+}
+
 // One pass of the zone (a pseudo iteration, or Part 2) reversed: own iterate
 // (W0, W1), next iterate (N0, N1), adjoint of this lane's output (gO0, gO1);
 // gwx is the adjoint of the boundary speed from outside the pass (Part 2:
-// the interface advance; counted once).  Adds the adjoint of the own iterate
-// to (gW0, gW1).
+// the interface advance; counted once); Q the pass's interface linearisation
+// (read on lane ic).  Adds the adjoint of the own iterate to (gW0, gW1).
 __device__ __forceinline__ void a8_pass_rev(const Mat& M, ZoneRev8& Z, bool part2, double W0,
-                                            double W1, double rpl, double rpr, double N0,
-                                            double N1, double gO0, double gO1, double gwx,
-                                            double& gW0, double& gW1) {
+                                            double W1, const IfaceLin& Q, double N0, double N1,
+                                            double gO0, double gO1, double gwx, double& gW0,
+                                            double& gW1) {
   // Neighbour values come by DPP row shifts: the 8-lane groups sit inside the
   // 16-lane rows, and the lanes whose shift would cross a group boundary
   // (lane 7 from the next group, lane 0 from the previous) do not use them.
   const int c = Z.c;
   const double nW0 = d_lane_next(W0), nW1 = d_lane_next(W1);
-  IfaceLin Q;
-  Q.F0 = Q.F1 = Q.w = 0.0;
-  // the two outer waves side by side: lane ic the left one (its own cell),
-  // lane ic + 1 the right one; lane ic then takes the right one's results
-  double wv = 0.0, wg = 0.0, wf = 0.0, wdf = 0.0, wdr = 0.0;
-  if (c == Z.ic || c == Z.ic + 1) {
-    const bool lft = c == Z.ic;
-    d_wave_lin(M, lft ? Z.phl : Z.phl ^ 1, W0, lft ? rpl : rpr, wv, wg, wf, wdf, wdr);
-  }
-  const double ov = d_lane_next(wv), og = d_lane_next(wg), of = d_lane_next(wf);
-  const double odf = d_lane_next(wdf), odr = d_lane_next(wdr);
-  if (c == Z.ic)
-    d_iface_lin_w(M, Z.phl, W0, W1, nW0, nW1, rpl, rpr, wv, wg, wf, wdf, wdr, ov, og, of, odf, odr,
-                  Q);
   // the boundary's flux is used on lane ic, which holds it; its speed on
   // the two moving cells ic and ic + 1 (every other cell has mv = 0 and
   // keeps its length whatever the speed)
@@ -828,6 +855,8 @@ __global__ __launch_bounds__(64) void k_zone_adj8(StepArgs A, AdjArgs B) {
   constexpr int MC = 2 * ZH + 1;
   constexpr int E = 2 * MC + 2;
   static_assert(MC <= 8, "a zone must fit an 8-lane group");
+  // the interface linearisations of four passes per group (a8_lin_batch)
+  __shared__ double s_lin[8][4][A8_LIN];
   const int c = threadIdx.x & 7, gb = threadIdx.x & ~7;
   const int k = (blockIdx.x * 64 + threadIdx.x) >> 3;
   if (k >= A.n_iface) return;  // uniform over the group
@@ -964,38 +993,48 @@ __global__ __launch_bounds__(64) void k_zone_adj8(StepArgs A, AdjArgs B) {
   double ghl = ghl1;
   Z.gdt += (c == 0) ? ghl1 * wstar : 0.0;
 
-  // Part 2 at W^count, then the pseudo iterations in reverse
-  const double* e = T + TAPE_HDR + (long long)cnt * E;
+  // Part 2 at W^count, then the pseudo iterations in reverse.  The interface
+  // linearisations at the tape's roots do not depend on the adjoints: they
+  // are computed four passes at a time by the group's four lane pairs
+  // (a8_lin_batch, every fourth pass; the pass counter is common to the
+  // groups of the wave, so they batch together) and each pass's lane ic
+  // reads its own from LDS.  Each pass's iterate is read from the tape one
+  // pass ahead, so that the loads overlap the pass before.
+  const int gi = (int)threadIdx.x >> 3;
+  const int pic = (skip >= 0 && Z.ic >= skip) ? Z.ic + 1 : Z.ic;
+  const int pic1 = (skip >= 0 && Z.ic + 1 >= skip) ? Z.ic + 2 : Z.ic + 1;
   const int ep = pos >= 0 ? pos : 0;
+  const double* e = T + TAPE_HDR + (long long)cnt * E;
   double W0 = e[ep], W1 = e[MC + ep];
   double gW0 = 0.0, gW1 = 0.0;
-  a8_pass_rev(M, Z, true, W0, W1, e[2 * MC], e[2 * MC + 1], W0, W1, gO0, gO1,
-              (c == Z.ic) ? ghl1 * dt : 0.0, gW0, gW1);
-  // each pass's iterate and root are read from the tape one pass ahead, so
-  // that the loads overlap the pass before
-  double tW0 = 0.0, tW1 = 0.0, tpl = 0.0, tpr = 0.0;
+  double tW0 = 0.0, tW1 = 0.0;
   if (cnt > 0) {
     const double* el = T + TAPE_HDR + (long long)(cnt - 1) * E;
     tW0 = el[ep];
     tW1 = el[MC + ep];
-    tpl = el[2 * MC];
-    tpr = el[2 * MC + 1];
   }
-  for (int l = cnt - 1; l >= 0; --l) {
-    const double N0 = W0, N1 = W1;
-    W0 = tW0;
-    W1 = tW1;
-    const double rpl = tpl, rpr = tpr;
-    if (l > 0) {
-      const double* en = T + TAPE_HDR + (long long)(l - 1) * E;
-      tW0 = en[ep];
-      tW1 = en[MC + ep];
-      tpl = en[2 * MC];
-      tpr = en[2 * MC + 1];
+  for (int i = 0; i <= cnt; ++i) {
+    const int l = cnt - i;
+    if ((i & 3) == 0) a8_lin_batch(M, Z, T, E, MC, l, l + 1 < 4 ? l + 1 : 4, pic, pic1, s_lin[gi]);
+    IfaceLin Q;
+    Q.F0 = Q.F1 = Q.w = 0.0;
+    if (c == Z.ic) a8_lin_load(s_lin[gi][l & 3], phl, Q);
+    if (i == 0) {
+      a8_pass_rev(M, Z, true, W0, W1, Q, W0, W1, gO0, gO1, (c == Z.ic) ? ghl1 * dt : 0.0, gW0,
+                  gW1);
+    } else {
+      const double N0 = W0, N1 = W1;
+      W0 = tW0;
+      W1 = tW1;
+      if (l > 0) {
+        const double* en = T + TAPE_HDR + (long long)(l - 1) * E;
+        tW0 = en[ep];
+        tW1 = en[MC + ep];
+      }
+      const double o0 = gW0, o1 = gW1;
+      gW0 = gW1 = 0.0;
+      a8_pass_rev(M, Z, false, W0, W1, Q, N0, N1, o0, o1, 0.0, gW0, gW1);
     }
-    const double o0 = gW0, o1 = gW1;
-    gW0 = gW1 = 0.0;
-    a8_pass_rev(M, Z, false, W0, W1, rpl, rpr, N0, N1, o0, o1, 0.0, gW0, gW1);
   }
   // W^0 = U0
   Z.gU00 += gW0;
