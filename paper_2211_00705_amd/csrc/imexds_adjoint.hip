@@ -1231,17 +1231,17 @@ __global__ __launch_bounds__(256) void k_bulk_adj(StepArgs A, AdjArgs B) {
     const double rho = rr[r], mom = mm[r];
     const double u = mom / rho;
     const double pr = d_pres(M, ph, rho);
-    const double rhoR = __shfl_down(rho, 1, 64);
-    const double momR = __shfl_down(mom, 1, 64);
-    const double uR = __shfl_down(u, 1, 64);
-    const double prR = __shfl_down(pr, 1, 64);
-    const double bR0 = __shfl_down(br[r], 1, 64);
-    const double bR1 = __shfl_down(bm[r], 1, 64);
-    const int bulkR = __shfl_down(bulk ? 1 : 0, 1, 64);
+    const double rhoR = d_wave_next(rho);
+    const double momR = d_wave_next(mom);
+    const double uR = d_wave_next(u);
+    const double prR = d_wave_next(pr);
+    const double bR0 = d_wave_next(br[r]);
+    const double bR1 = d_wave_next(bm[r]);
+    const int bulkR = d_wave_next_i(bulk ? 1 : 0);
     double F0, F1;  // forward flux on the face s | s+1
     d_hll_prim(d_a(M, ph), rho, mom, u, pr, rhoR, momR, uR, prR, F0, F1);
-    const double Fl0 = __shfl_up(F0, 1, 64);
-    const double Fl1 = __shfl_up(F1, 1, 64);
+    const double Fl0 = d_wave_prev(F0);
+    const double Fl1 = d_wave_prev(F1);
     // adjoint of the face flux
     double gf0 = gzl0, gf1 = gzl1;
     if (bulkR) {
@@ -1263,8 +1263,8 @@ __global__ __launch_bounds__(256) void k_bulk_adj(StepArgs A, AdjArgs B) {
       cl_r += cr_r;
       cl_m += (bcR == 0) ? -cr_m : cr_m;
     }
-    const double from_r = __shfl_up(cr_r, 1, 64);
-    const double from_m = __shfl_up(cr_m, 1, 64);
+    const double from_r = d_wave_prev(cr_r);
+    const double from_m = d_wave_prev(cr_m);
     if (lane >= 1 && lane <= OUT && s < tend && in) {
       double base_r, base_m;
       if (bulk) {

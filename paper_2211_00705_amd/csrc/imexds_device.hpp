@@ -289,6 +289,26 @@ __device__ __forceinline__ double d_lane_prev(double x) {
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
+// Value of lane + 1 / lane - 1 across the whole wave (DPP wave shift); the
+// last / first lane keeps its own value, as __shfl_down / __shfl_up by one
+// do.  Every lane must be active.
+__device__ __forceinline__ int d_wave_next_i(int x) {
+  return __builtin_amdgcn_update_dpp(x, x, 0x130, 0xF, 0xF, false);
+}
+__device__ __forceinline__ int d_wave_prev_i(int x) {
+  return __builtin_amdgcn_update_dpp(x, x, 0x138, 0xF, 0xF, false);
+}
+__device__ __forceinline__ double d_wave_next(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = d_wave_next_i((int)b), hi = d_wave_next_i((int)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ double d_wave_prev(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = d_wave_prev_i((int)b), hi = d_wave_prev_i((int)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
 // Exchange with the pair's other lane.  The two lanes of a pair solve are an
 // even lane and the odd one after it (lane and lane ^ 1), both active, so the
 // exchange is one DPP quad permutation [1,0,3,2] per 32 bits: a VALU move

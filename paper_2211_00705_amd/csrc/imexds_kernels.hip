@@ -128,14 +128,14 @@ __global__ __launch_bounds__(256) void k_bulk(StepArgs A, int tile_begin) {
     const double rho = rr[r], mom = mm[r];
     const double u = mom / rho;
     const double pr = d_pres(M, ph, rho);
-    const double rhoR = __shfl_down(rho, 1, 64);
-    const double momR = __shfl_down(mom, 1, 64);
-    const double uR = __shfl_down(u, 1, 64);
-    const double prR = __shfl_down(pr, 1, 64);
+    const double rhoR = d_wave_next(rho);
+    const double momR = d_wave_next(mom);
+    const double uR = d_wave_next(u);
+    const double prR = d_wave_next(pr);
     double F0, F1;  // flux on the face between s and s+1 (phase of s)
     d_hll_prim(d_a(M, ph), rho, mom, u, pr, rhoR, momR, uR, prR, F0, F1);
-    const double G0 = __shfl_up(F0, 1, 64);
-    const double G1 = __shfl_up(F1, 1, 64);
+    const double G0 = d_wave_prev(F0);
+    const double G1 = d_wave_prev(F1);
     if (lane >= 1 && lane <= OUT && s < tend && !zone) {
       double rn = rho - lam * (F0 - G0);
       double mn = mom - lam * (F1 - G1);
