@@ -644,17 +644,23 @@ int ensure_adjoint_buffers(imexds_ctx* c, int C) {
 }
 
 // Re-runs `len` steps from the restored checkpoint, keeping for each step
-// its input state, records, dt and the zone tape.
+// its input state, records, dt and the zone tape.  Step j reads its state
+// from tape slot j and writes the next one straight into slot j + 1 (the
+// last step into the live state buffer, which the segment's caller reads).
+// The zones and the bulk sweep run one after the other on ms: the recording
+// zone kernel bounds the step, and cross-stream waits between launches made
+// one by one cost more than the overlap saved (a graph-captured replay of the
+// segment with the overlap measured no faster either).
 int record_segment(imexds_ctx* c, int len) {
   const size_t S = (size_t)c->S, N = (size_t)c->NIF, P = (size_t)c->P;
   hipStream_t m = c->ms;
+  if (len < 0 || len > c->tape_steps) return IMEXDS_ERR_INVALID_ARG;
+  if (S && len > 0) {
+    CK(hipMemcpyAsync(c->tU, c->d_rho[c->parity], S * 8, hipMemcpyDeviceToDevice, m));
+    CK(hipMemcpyAsync(c->tU + S, c->d_mom[c->parity], S * 8, hipMemcpyDeviceToDevice, m));
+  }
   for (int j = 0; j < len; ++j) {
     const int a = c->parity;
-    double* u = c->tU + (size_t)j * 2 * S;
-    if (S) {
-      CK(hipMemcpyAsync(u, c->d_rho[a], S * 8, hipMemcpyDeviceToDevice, m));
-      CK(hipMemcpyAsync(u + S, c->d_mom[a], S * 8, hipMemcpyDeviceToDevice, m));
-    }
     if (N) {
       CK(hipMemcpyAsync(c->tHome + j * N, c->d_home[a], N * 4, hipMemcpyDeviceToDevice, m));
       CK(hipMemcpyAsync(c->tHl + j * N, c->d_hl[a], N * 8, hipMemcpyDeviceToDevice, m));
@@ -663,6 +669,12 @@ int record_segment(imexds_ctx* c, int len) {
     CK(hipMemcpyAsync(c->tClip + j * P, c->d_clipped, P * 4, hipMemcpyDeviceToDevice, m));
     CK(hipMemcpyAsync(c->tSteps + j * P, c->d_steps, P * 8, hipMemcpyDeviceToDevice, m));
     StepArgs A = make_args(c, a, false);
+    A.rho0 = c->tU + (size_t)j * 2 * S;
+    A.mom0 = A.rho0 + S;
+    if (j + 1 < len) {
+      A.rho1 = c->tU + (size_t)(j + 1) * 2 * S;
+      A.mom1 = A.rho1 + S;
+    }
     A.log_count = A.log_flags = A.log_zlo = A.log_row = nullptr;
     A.log_max = 0;
     A.st_pseudo = A.st_merges = A.st_lmax = nullptr;
