@@ -1184,11 +1184,11 @@ static int or_zone_build(const or_material *M, const or_params *P, const or_prob
 }
 
 /* face fluxes of a zone iterate W; each phase-boundary face uses the
- * interface Riemann solver (boundary b starts from pw[2b], pw[2b+1] and
- * leaves its root there and its speed in wout[b]), all other inner faces
- * HLL. */
-static int or_zone_fluxes(const or_material *M, const or_params *P, const or_zone *Z,
-                          real W[][2], real F[][2], real *pw, real *wout) {
+ * interface Riemann solver (boundary b starts from pw[2b], pw[2b+1], a guess
+ * it takes when have is NULL or have[b] is set, and leaves its root there and
+ * its speed in wout[b]), all other inner faces HLL. */
+static int or_zone_fluxes_g(const or_material *M, const or_params *P, const or_zone *Z,
+                            real W[][2], real F[][2], real *pw, const int *have, real *wout) {
   int c;
   F[0][0] = Z->FL[0];
   F[0][1] = Z->FL[1];
@@ -1199,8 +1199,8 @@ static int or_zone_fluxes(const or_material *M, const or_params *P, const or_zon
     if (b >= 0) {
       or_iface I;
       if (!or_iface_solve(M, Z->ph[c], W[c][0], W[c][1], Z->ph[c + 1], W[c + 1][0],
-                              W[c + 1][1], 1, pw[2 * b], pw[2 * b + 1], P->newton_maxit,
-                              P->newton_rtol, &I))
+                              W[c + 1][1], have ? have[b] : 1, pw[2 * b], pw[2 * b + 1],
+                              P->newton_maxit, P->newton_rtol, &I))
         return 0;
       pw[2 * b] = I.pl;
       pw[2 * b + 1] = I.pr;
@@ -1212,6 +1212,11 @@ static int or_zone_fluxes(const or_material *M, const or_params *P, const or_zon
     }
   }
   return 1;
+}
+
+static int or_zone_fluxes(const or_material *M, const or_params *P, const or_zone *Z,
+                          real W[][2], real F[][2], real *pw, real *wout) {
+  return or_zone_fluxes_g(M, P, Z, W, F, pw, NULL, wout);
 }
 
 static int or_state_ok(real r, real m) { return r > 0.0 && isfinite(r) && isfinite(m); }
@@ -1418,16 +1423,22 @@ static int or_zone_dts(const or_material *M, const or_params *P, const or_zone *
  * paper's outlook), the alternative to or_zone_dts: unknowns the zone
  * iterates W, equations
  *   R_c(W) = (h_c(W) / h_c^n) W_c - U_c^n + (dt / h_c^n)(F_{c+1/2}(W) - F_{c-1/2}(W)),
- * h_c(W) = h_c^n + mov_c w(W) dt, the zone's outer faces from U^n; from
- * W = U^n a forward-difference Jacobian (step 1e-7 max(|W_j|, 1), the
- * interface solve warm-started from the base point's), full steps;
- * converged when every step component is below zn_rtol max(|W_j|, 1); at
- * most zn_maxit steps.  R_c depends on W_{c-1}, W_c and W_{c+1} only (each
- * face flux on the two cells beside it, the moving lengths on the interface
- * face, whose cells are neighbours), so the Jacobian is block tridiagonal in
- * 2x2 blocks: the Newton system takes the difference quotients of those
- * blocks and is solved by or_block_tri.  Shrink and state checks, Part 2 and
- * the return codes as in or_zone_dts (the shrink check on every base point). */
+ * h_c(W) = h_c^n + mov_c w(W) dt, the zone's outer faces from U^n.  From
+ * W = U^n, each Newton step evaluates R at the base point W_k and at the
+ * points moved along each unknown (forward differences, step
+ * 1e-7 max(|W_j|, 1)); every interface solve of the step starts from the
+ * same point, the previous base point's root (in the first step the recorded
+ * root, or the solver's own guess without one, as the prediction), so that
+ * no evaluation of a step waits for another.  The step dx solves J dx = -R;
+ * it is the last when every component is below zn_rtol max(|W_j|, 1) or it
+ * is the zn_maxit-th, otherwise W_{k+1} = W_k + dx.  Part 2 then takes the
+ * fluxes and the boundary speed of that last base point.  R_c depends on
+ * W_{c-1}, W_c and W_{c+1} only (each face flux on the two cells beside it,
+ * the moving lengths on the interface face, whose cells are neighbours), so
+ * the Jacobian is block tridiagonal in 2x2 blocks: the Newton system takes
+ * the difference quotients of those blocks and is solved by or_block_tri.
+ * Shrink and state checks and the return codes as in or_zone_dts (the
+ * shrink check on every base point). */
 
 /* inverse of a 2x2 matrix by its adjugate; 0 if 1/det is not finite */
 static int or_inv2(const double A[2][2], double I[2][2]) {
@@ -1506,13 +1517,12 @@ int oracle_block_tri(int m, const double *D, const double *L, const double *U, c
 }
 
 static int or_zone_resid(const or_material *M, const or_params *P, const or_zone *Z, double dt,
-                         double W[][2], double *pw, double *R, double *w, int check,
-                         int *shrink_cell) {
-  double F[OR_MAXC + 1][2];
+                         double W[][2], double *pw, const int *have, double *R,
+                         double F[][2], double *w, int check, int *shrink_cell) {
   int c, q;
-  if (!or_zone_fluxes(M, P, Z, W, F, pw, w)) return OR_ST_NEWTON;
+  if (!or_zone_fluxes_g(M, P, Z, W, F, pw, have, w)) return OR_ST_NEWTON;
   for (c = 0; c < Z->m; ++c) {
-    double hk = Z->hn[c] + ((double)Z->mov[c] * *w) * dt;
+    double hk = Z->hn[c] + ((double)Z->mov[c] * w[0]) * dt;
     if (check && Z->mov[c] != 0 && !(hk >= 0.5 * Z->hh[c])) {
       *shrink_cell = c;
       return OR_ST_MESH;
@@ -1524,13 +1534,16 @@ static int or_zone_resid(const or_material *M, const or_params *P, const or_zone
   return 0;
 }
 
+/* rec_have, rec_pw: the recorded start of the boundary's interface solve
+ * (the prediction's); pw: in, the prediction's root, out the last base
+ * point's */
 static int or_zone_newton(const or_material *M, const or_params *P, const or_zone *Z, double dt,
-                          double *pw, double U1[][2], double *wstar, int *count, int *lmax_hit,
-                          int *shrink_cell) {
+                          int rec_have, const double *rec_pw, double *pw, double U1[][2],
+                          double *wstar, int *count, int *lmax_hit, int *shrink_cell) {
   int m = Z->m, n = 2 * m, c, q, j, it, conv = 0;
   double W[OR_MAXC][2], R[2 * OR_MAXC], Rp[2 * OR_MAXC], J[2 * OR_MAXC][2 * OR_MAXC];
   double Db[OR_MAXC][2][2], Lb[OR_MAXC][2][2], Ub[OR_MAXC][2][2], rb[OR_MAXC][2], d[OR_MAXC][2];
-  double w = 0.0;
+  double F[OR_MAXC + 1][2], Fp[OR_MAXC + 1][2], w[2] = {0.0, 0.0};
   *shrink_cell = -1;
   *lmax_hit = 0;
   *count = 0;
@@ -1538,16 +1551,21 @@ static int or_zone_newton(const or_material *M, const or_params *P, const or_zon
     W[c][0] = Z->U0[c][0];
     W[c][1] = Z->U0[c][1];
   }
-  for (it = 0; it < P->zn_maxit && !conv; ++it) {
-    int st = or_zone_resid(M, P, Z, dt, W, pw, R, &w, 1, shrink_cell);
+  for (it = 0;; ++it) {
+    /* the start of every interface solve of this step */
+    const int have[1] = {it == 0 ? rec_have : 1};
+    const double g0[2] = {it == 0 ? rec_pw[0] : pw[0], it == 0 ? rec_pw[1] : pw[1]};
+    pw[0] = g0[0];
+    pw[1] = g0[1];
+    int st = or_zone_resid(M, P, Z, dt, W, pw, have, R, F, w, 1, shrink_cell);
     if (st) return st;
     for (j = 0; j < n; ++j) {
       int cj = j / 2, qj = j % 2, dummy;
       double xj = W[cj][qj];
       double e = 1e-7 * (fabs(xj) > 1.0 ? fabs(xj) : 1.0);
-      double g[2] = {pw[0], pw[1]}, a;
+      double g[2] = {g0[0], g0[1]}, a[2];
       W[cj][qj] = xj + e;
-      st = or_zone_resid(M, P, Z, dt, W, g, Rp, &a, 0, &dummy);
+      st = or_zone_resid(M, P, Z, dt, W, g, have, Rp, Fp, a, 0, &dummy);
       W[cj][qj] = xj;
       if (st) return st;
       for (q = 0; q < n; ++q) J[q][j] = (Rp[q] - R[q]) / e;
@@ -1570,19 +1588,19 @@ static int or_zone_newton(const or_material *M, const or_params *P, const or_zon
       double sc = fabs(xj) > 1.0 ? fabs(xj) : 1.0;
       conv = conv && (fabs(d[j / 2][j % 2]) <= P->zn_rtol * sc);
     }
+    *count = it + 1;
+    if (conv || it + 1 >= P->zn_maxit) break;
     for (c = 0; c < m; ++c) {
       W[c][0] = W[c][0] + d[c][0];
       W[c][1] = W[c][1] + d[c][1];
       if (!or_state_ok(W[c][0], W[c][1])) return OR_ST_NONPHYS;
     }
-    *count = it + 1;
   }
   if (!conv) *lmax_hit = 1;
-  /* Part 2 */
-  double F[OR_MAXC + 1][2], ih[OR_MAXC];
-  if (!or_zone_fluxes(M, P, Z, W, F, pw, &w)) return OR_ST_NEWTON;
+  /* Part 2 with the last base point's fluxes and boundary speed */
+  double ih[OR_MAXC];
   for (c = 0; c < m; ++c) {
-    double hk = Z->hn[c] + ((double)Z->mov[c] * w) * dt;
+    double hk = Z->hn[c] + ((double)Z->mov[c] * w[0]) * dt;
     ih[c] = 1.0 / hk;
     if (Z->mov[c] != 0 && !(hk >= 0.5 * Z->hh[c])) {
       *shrink_cell = c;
@@ -1594,7 +1612,7 @@ static int or_zone_newton(const or_material *M, const or_params *P, const or_zon
       U1[c][q] = (Z->hn[c] * Z->U0[c][q] - dt * (F[c + 1][q] - F[c][q])) * ih[c];
     if (!or_state_ok(U1[c][0], U1[c][1])) return OR_ST_NONPHYS;
   }
-  *wstar = w;
+  *wstar = w[0];
   return 0;
 }
 #endif
@@ -1652,7 +1670,8 @@ static int or_zone_step(const or_material *M, const or_params *P, or_prob *pb, i
     int sc;
 #ifndef OR_TANGENT
     int st = P->zone_solver == 1
-                 ? or_zone_newton(M, P, &Z, dt, pw, U1, wstar, &count, &lmax_hit, &sc)
+                 ? or_zone_newton(M, P, &Z, dt, pb->warm[kb[0]], pb->pw + 2 * kb[0], pw, U1,
+                                  wstar, &count, &lmax_hit, &sc)
                  : or_zone_dts(M, P, &Z, dt, pw, U1, wstar, &count, &lmax_hit, &sc, force,
                                (pb->tr_on && kb[0] == pb->tr_k) ? pb->tr : NULL);
 #else

@@ -9,24 +9,29 @@
 //
 // The solve: unknowns the zone cells' values W (2 per cell), residual
 //   R_i(W) = (h_i(W) / h_i^n) W_i - U_i^n + (dt / h_i^n)(F_{i+1/2}(W) - F_{i-1/2}(W)),
-// h_i(W) = h_i^n + mov_i w(W) dt, the zone's outer faces from U^n; a
-// forward-difference Jacobian (step 1e-7 max(|W_j|, 1), the interface solve
-// warm-started from the base point's) of which the 2x2 blocks next to the
-// diagonal are kept (R_i depends on W_{i-1}, W_i, W_{i+1} only), solved by
-// the block Thomas algorithm; full steps from W = U^n, converged when every
-// step component is below zn_rtol max(|W_j|, 1), at most zn_maxit steps (then
-// flagged like l_max).  The kernel works on 2 Z + 1 cells; cells past the
+// h_i(W) = h_i^n + mov_i w(W) dt, the zone's outer faces from U^n.  From
+// W = U^n each Newton step evaluates R at the base point and at the points
+// moved along each unknown (forward differences, step 1e-7 max(|W_j|, 1));
+// every interface solve of a step starts from the previous base point's root
+// (in a zone's first step from the recorded root, as the prediction).  Of the
+// difference Jacobian the 2x2 blocks next to the diagonal are kept (R_i
+// depends on W_{i-1}, W_i, W_{i+1} only), solved by the block Thomas
+// algorithm.  The step is the last when every component is below
+// zn_rtol max(|W_j|, 1) or it is the zn_maxit-th (then flagged like l_max);
+// else W moves by the full step.  Part 2 takes the last base point's fluxes
+// and boundary speed.  The kernel works on 2 Z + 1 cells; cells past the
 // zone (the folded piece's position is left out) are identity rows with
 // zero right-hand sides, which leave the zone cells' results as in the
 // compact system.
 //
 // A zone has G = 1 + 2 MC groups of one lane, or of two lanes (the pair form
-// of the interface solver: one lane per side of the interface problem).  Every
-// group evaluates the prediction and each base point with identical inputs
-// (identical results, no exchange); group g >= 1 then evaluates the point
-// moved along unknown g - 1, so the difference columns run side by side;
-// every lane gathers the three blocks of each cell's row and runs the same
-// block solve.
+// of the interface solver: one lane per side of the interface problem).  In
+// a round group 0 evaluates the base point and group g >= 1 the point moved
+// along unknown g - 1, all side by side; the base point's residual, root and
+// boundary speed are then read from group 0, and every lane gathers the three
+// blocks of each cell's row and runs the same block solve.  The first round
+// is also the prediction (the base point is U^n); unless the prediction
+// merges the tiny piece, it is the first Newton step too.
 #include "imexds_device.hpp"
 #include "imexds_kernels.hpp"
 
@@ -117,102 +122,98 @@ __global__ __launch_bounds__(64) void k_zone_nt(StepArgs A, int if_begin, int if
   bool merge = false, redo = false;
   int skip = -1, into = -1, ic = 0, icr = 1, tiny = 0;
   double Mr = 0.0, Mm = 0.0, hn_l = 0.0, hn_r = 0.0, hh_l = 0.0, hh_r = 0.0;
-  double Ipl = 0.0, Ipr = 0.0, wp = 0.0;
+  double wp = 0.0;
   double W0[MC], W1[MC];
 #pragma unroll
   for (int i = 0; i < MC; ++i) {
     W0[i] = Ur[i];
     W1[i] = Um[i];
   }
-  double pw0 = 0.0, pw1 = 0.0, gw0 = 0.0, gw1 = 0.0, w = 0.0;
-  double R[NV], Jc[NV];
-#pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    R[i] = 0.0;
-    Jc[i] = 0.0;
-  }
+  double pw0 = 0.0, pw1 = 0.0, w = 0.0;
   const int colj = grp - 1;
-  int status = 0, it = 0, phase = -2;  // -2: prediction, -1: base point, 0: columns
-  double ecol = 0.0;
-  bool final_pass = false, conv = false, finished = false, setup = false;
+  int status = 0, it = 0;
+  bool pred = true, conv = false, finished = false;
   double wstar = 0.0;
+  // (re)builds the zone after the prediction or a redo: the folded piece and
+  // its merged content, the interface cells, the lengths; false (status set)
+  // when the zone cannot be built
+  auto build_zone = [&]() -> bool {
+    skip = -1;
+    into = -1;
+    if (merge) {
+      skip = tr ? iR : iL;
+      into = tr ? iR + 1 : iL - 1;
+      if (into < 0 || into >= nr) status = ST_MESH;
+    }
+    if (status) return false;
+    double rskip = 0.0, mskip = 0.0, rin = 0.0, min_ = 0.0;
+#pragma unroll
+    for (int i = 0; i < MC; ++i) {
+      if (i == skip) {
+        rskip = Ur[i];
+        mskip = Um[i];
+      }
+      if (i == into) {
+        rin = Ur[i];
+        min_ = Um[i];
+      }
+    }
+    const double hLp = hl, hRp = h - hl;
+    const double ht = tr ? hRp : hLp;
+    const double hm = h + ht;
+    if (merge) {
+      Mr = (h * rin + ht * rskip) / hm;
+      Mm = (h * min_ + ht * mskip) / hm;
+    }
+    ic = (merge && !tr) ? into : iL;
+    icr = (merge && tr) ? into : iR;
+    tiny = merge ? into : (tr ? iR : iL);
+    hn_l = (merge && !tr) ? hm : hLp;
+    hn_r = (merge && tr) ? hm : hRp;
+    hh_l = hn_l + (1.0 * wp) * dt;
+    hh_r = hn_r + (-1.0 * wp) * dt;
+    const double hh_f = h + (0.0 * wp) * dt;
+    double th_l = hh_l / h, th_r = hh_r / h, th_f = hh_f / h;
+    if (th_l > P.theta_nb) th_l = P.theta_nb;
+    if (th_r > P.theta_nb) th_r = P.theta_nb;
+    if (th_f > P.theta_nb) th_f = P.theta_nb;
+    if (!(th_l > 0.0) || !(th_r > 0.0) || !(th_f > 0.0)) {
+      status = ST_MESH;
+      return false;
+    }
+#pragma unroll
+    for (int i = 0; i < MC; ++i) {
+      W0[i] = (i == into) ? Mr : Ur[i];
+      W1[i] = (i == into) ? Mm : Um[i];
+    }
+    it = 0;
+    conv = false;
+    return true;
+  };
 #pragma unroll 1
   for (;;) {
-    // ---------------- (re)build the zone after the prediction or a redo ----------------
-    if (setup) {
-      setup = false;
-      skip = -1;
-      into = -1;
-      if (merge) {
-        skip = tr ? iR : iL;
-        into = tr ? iR + 1 : iL - 1;
-        if (into < 0 || into >= nr) status = ST_MESH;
-      }
-      if (status) break;
-      double rskip = 0.0, mskip = 0.0, rin = 0.0, min_ = 0.0;
-#pragma unroll
-      for (int i = 0; i < MC; ++i) {
-        if (i == skip) {
-          rskip = Ur[i];
-          mskip = Um[i];
-        }
-        if (i == into) {
-          rin = Ur[i];
-          min_ = Um[i];
-        }
-      }
-      const double hLp = hl, hRp = h - hl;
-      const double ht = tr ? hRp : hLp;
-      const double hm = h + ht;
-      if (merge) {
-        Mr = (h * rin + ht * rskip) / hm;
-        Mm = (h * min_ + ht * mskip) / hm;
-      }
-      ic = (merge && !tr) ? into : iL;
-      icr = (merge && tr) ? into : iR;
-      tiny = merge ? into : (tr ? iR : iL);
-      hn_l = (merge && !tr) ? hm : hLp;
-      hn_r = (merge && tr) ? hm : hRp;
-      hh_l = hn_l + (1.0 * wp) * dt;
-      hh_r = hn_r + (-1.0 * wp) * dt;
-      const double hh_f = h + (0.0 * wp) * dt;
-      double th_l = hh_l / h, th_r = hh_r / h, th_f = hh_f / h;
-      if (th_l > P.theta_nb) th_l = P.theta_nb;
-      if (th_r > P.theta_nb) th_r = P.theta_nb;
-      if (th_f > P.theta_nb) th_f = P.theta_nb;
-      if (!(th_l > 0.0) || !(th_r > 0.0) || !(th_f > 0.0)) {
-        status = ST_MESH;
-        break;
-      }
-#pragma unroll
-      for (int i = 0; i < MC; ++i) {
-        W0[i] = (i == into) ? Mr : Ur[i];
-        W1[i] = (i == into) ? Mm : Um[i];
-      }
-      pw0 = Ipl;
-      pw1 = Ipr;
-      it = 0;
-      conv = false;
-      final_pass = false;
-      phase = -1;
-    }
-    const bool pred = phase == -2;
-    const bool fd = phase == 0;
-    // the point: W (or U^n for the prediction), moved along colj by groups
-    // >= 1 in the column pass when that unknown belongs to the zone
-    // unknown colj is component ccmp of zone cell ccell (zone cells in slot
-    // order, the folded piece left out), at position cpos
+    // One Newton step: group 0 evaluates the base point W, group g >= 1 the
+    // point moved along unknown colj = g - 1 when that unknown belongs to the
+    // zone (component ccmp of zone cell ccell, zone cells in slot order and
+    // the folded piece left out, at position cpos).  The first round is also
+    // the prediction (group 0's point is U^n at the cut); without a merge it
+    // is the first Newton step as well, since W = U^n there.
     const int mm = skip >= 0 ? nr - 1 : nr;
     const int ccell = colj >> 1, ccmp = colj & 1;
     const int cpos = ccell + ((skip >= 0 && ccell >= skip) ? 1 : 0);
-    const bool cact = colj >= 0 && ccell < mm;
-    const bool moved = fd && cact;
+    const bool moved = colj >= 0 && ccell < mm;
+    double xj = 0.0;
+#pragma unroll
+    for (int i = 0; i < MC; ++i) {
+      if (cpos == i && ccmp == 0) xj = W0[i];
+      if (cpos == i && ccmp == 1) xj = W1[i];
+    }
+    const double ecol = 1e-7 * (fabs(xj) > 1.0 ? fabs(xj) : 1.0);
     double X0[MC], X1[MC];
 #pragma unroll
     for (int i = 0; i < MC; ++i) {
-      const double a0 = pred ? Ur[i] : W0[i], a1 = pred ? Um[i] : W1[i];
-      X0[i] = (moved && cpos == i && ccmp == 0) ? a0 + ecol : a0;
-      X1[i] = (moved && cpos == i && ccmp == 1) ? a1 + ecol : a1;
+      X0[i] = (moved && cpos == i && ccmp == 0) ? W0[i] + ecol : W0[i];
+      X1[i] = (moved && cpos == i && ccmp == 1) ? W1[i] + ecol : W1[i];
     }
     // the interface problem: positions iL, iR (prediction) or ic, icr
     const int a = pred ? iL : ic, b = pred ? iR : icr;
@@ -228,33 +229,38 @@ __global__ __launch_bounds__(64) void k_zone_nt(StepArgs A, int if_begin, int if
         qr1 = X1[i];
       }
     }
-    const bool hg = pred ? warm != 0 : true;
-    const double g0 = pred ? rpw0 : (fd ? gw0 : pw0);
-    const double g1 = pred ? rpw1 : (fd ? gw1 : pw1);
+    // every solve of a step starts from the previous base point's root; in
+    // the first step of a (re)built zone, as the prediction, from the
+    // recorded root (or the solver's guess without one)
+    const bool rs = it == 0;
+    const bool hg = rs ? warm != 0 : true;
+    const double g0 = rs ? rpw0 : pw0;
+    const double g1 = rs ? rpw1 : pw1;
     IfaceOut o;
     const bool okl = d_iface_solve_t<LG == 2>(M, P.newton_maxit, P.newton_rtol, phl, ql0, ql1,
                                               phr, qr0, qr1, hg, g0, g1, half, o);
-    const unsigned long long failm = __ballot(!okl);
     const unsigned long long zm = ((1ull << TL) - 1ull) << lane0;
-    if (failm & zm) {
+    const unsigned long long failm = __ballot(!okl) & zm;
+    // the base point's solve first (group 0); a moved point's failure counts
+    // after the base point's shrink test
+    const unsigned long long bm = ((1ull << LG) - 1ull) << lane0;
+    if (failm & bm) {
       status = ST_NEWTON;
       break;
     }
+    // the base point's boundary speed and root, from group 0
+    const double bw = __shfl(o.w, lane0, 64);
+    const double bpl = __shfl(o.pl, lane0, 64);
+    const double bpr = __shfl(o.pr, lane0, 64);
     if (pred) {
-      Ipl = o.pl;
-      Ipr = o.pr;
-      wp = o.w;
+      pred = false;
+      wp = bw;
       const double ht = tr ? h - hl : hl;
       const double rate = tr ? -wp : wp;
       const double hfl = P.alpha_floor * h;
       merge = (ht < hfl) || (ht + (P.merge_safety * rate) * dt < hfl);
-      setup = true;
-      continue;
-    }
-    if (!fd) {
-      pw0 = o.pl;
-      pw1 = o.pr;
-      w = o.w;
+      if (!build_zone()) break;
+      if (merge) continue;  // the zone changed: this round's points are not its own
     }
     const double we = o.w;
     // right face of each zone position at the point
@@ -278,8 +284,10 @@ __global__ __launch_bounds__(64) void k_zone_nt(StepArgs A, int if_begin, int if
     const double hk_l = hn_l + (1.0 * we) * dt;
     const double hk_r = hn_r + (-1.0 * we) * dt;
     const double hk_f = h + (0.0 * we) * dt;
-    if (!fd) {
-      const bool bl = !(hk_l >= 0.5 * hh_l), br = !(hk_r >= 0.5 * hh_r);
+    {  // shrink test at the base point
+      const double bk_l = hn_l + (1.0 * bw) * dt;
+      const double bk_r = hn_r + (-1.0 * bw) * dt;
+      const bool bl = !(bk_l >= 0.5 * hh_l), br = !(bk_r >= 0.5 * hh_r);
       int shrink = -1;
       if (bl && br)
         shrink = ic < icr ? ic : icr;
@@ -291,16 +299,22 @@ __global__ __launch_bounds__(64) void k_zone_nt(StepArgs A, int if_begin, int if
         if (!merge && shrink == tiny) {
           merge = true;
           redo = true;
-          setup = true;
+          if (!build_zone()) break;
           continue;
         }
         status = ST_MESH;
         break;
       }
     }
-    // residual (or Part 2) of every zone position
+    if (failm) {
+      status = ST_NEWTON;
+      break;
+    }
+    pw0 = bpl;
+    pw1 = bpr;
+    w = bw;
+    // residual of every zone position at the point
     double RX[NV];
-    bool okw = true;
 #pragma unroll
     for (int i = 0; i < MC; ++i) {
       RX[2 * i] = 0.0;
@@ -321,45 +335,18 @@ __global__ __launch_bounds__(64) void k_zone_nt(StepArgs A, int if_begin, int if
       const double u0m = (i == into) ? Mm : Um[i];
       const double hni = (i == ic) ? hn_l : ((i == icr) ? hn_r : h);
       const double hki = (i == ic) ? hk_l : ((i == icr) ? hk_r : hk_f);
-      if (final_pass) {
-        const double ih = 1.0 / hki;
-        const double n0 = (hni * u0r - dt * (FR_0[i] - fl0)) * ih;
-        const double n1 = (hni * u0m - dt * (FR_1[i] - fl1)) * ih;
-        if (!d_state_ok(n0, n1)) okw = false;
-        W0[i] = n0;
-        W1[i] = n1;
-      } else {
-        const double ihn = 1.0 / hni;
-        RX[2 * i] = (hki * ihn) * X0[i] - u0r + (dt * ihn) * (FR_0[i] - fl0);
-        RX[2 * i + 1] = (hki * ihn) * X1[i] - u0m + (dt * ihn) * (FR_1[i] - fl1);
-      }
+      const double ihn = 1.0 / hni;
+      RX[2 * i] = (hki * ihn) * X0[i] - u0r + (dt * ihn) * (FR_0[i] - fl0);
+      RX[2 * i + 1] = (hki * ihn) * X1[i] - u0m + (dt * ihn) * (FR_1[i] - fl1);
     }
-    if (final_pass) {
-      if (!okw) {
-        status = ST_NONPHYS;
-      } else {
-        wstar = w;
-        finished = true;
-      }
-      break;
+    // the base point's residual, from group 0, and this group's difference
+    // column (group 0's is not used)
+    double R[NV], Jc[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      R[i] = __shfl(RX[i], lane0, 64);
+      Jc[i] = (RX[i] - R[i]) / ecol;
     }
-    if (!fd) {
-#pragma unroll
-      for (int i = 0; i < NV; ++i) R[i] = RX[i];
-      gw0 = pw0;
-      gw1 = pw1;
-      double xj = 0.0;
-#pragma unroll
-      for (int i = 0; i < MC; ++i) {
-        if (cpos == i && ccmp == 0) xj = W0[i];
-        if (cpos == i && ccmp == 1) xj = W1[i];
-      }
-      ecol = 1e-7 * (fabs(xj) > 1.0 ? fabs(xj) : 1.0);
-      phase = 0;
-      continue;
-    }
-#pragma unroll
-    for (int i = 0; i < NV; ++i) Jc[i] = (RX[i] - R[i]) / ecol;
     // rows in zone-cell order (the folded piece's position left out)
     double Jk[NV], Rk[NV];
 #pragma unroll
@@ -461,6 +448,44 @@ __global__ __launch_bounds__(64) void k_zone_nt(StepArgs A, int if_begin, int if
       const double s1 = fabs(W1[i]) > 1.0 ? fabs(W1[i]) : 1.0;
       conv = conv && (fabs(e0[i]) <= P.zn_rtol * s0) && (fabs(e1[i]) <= P.zn_rtol * s1);
     }
+    it += 1;
+    if (conv || it >= P.zn_maxit) {
+      // Part 2 with the base point's fluxes and boundary speed (group 0's;
+      // the write-back is lane 0's)
+      bool okw = true;
+#pragma unroll
+      for (int i = 0; i < MC; ++i) {
+        if (i >= nr || i == skip) continue;
+        double fl0, fl1;
+        if (i == 0) {
+          fl0 = FL0;
+          fl1 = FL1;
+        } else if (i >= 2 && skip == i - 1) {
+          fl0 = FR_0[i >= 2 ? i - 2 : 0];
+          fl1 = FR_1[i >= 2 ? i - 2 : 0];
+        } else {
+          fl0 = FR_0[i - 1];
+          fl1 = FR_1[i - 1];
+        }
+        const double u0r = (i == into) ? Mr : Ur[i];
+        const double u0m = (i == into) ? Mm : Um[i];
+        const double hni = (i == ic) ? hn_l : ((i == icr) ? hn_r : h);
+        const double hki = (i == ic) ? hk_l : ((i == icr) ? hk_r : hk_f);
+        const double ih = 1.0 / hki;
+        const double n0 = (hni * u0r - dt * (FR_0[i] - fl0)) * ih;
+        const double n1 = (hni * u0m - dt * (FR_1[i] - fl1)) * ih;
+        if (!d_state_ok(n0, n1)) okw = false;
+        W0[i] = n0;
+        W1[i] = n1;
+      }
+      if (!okw) {
+        status = ST_NONPHYS;
+      } else {
+        wstar = w;
+        finished = true;
+      }
+      break;
+    }
     bool okst = true;
 #pragma unroll
     for (int i = 0; i < MC; ++i) {
@@ -473,9 +498,6 @@ __global__ __launch_bounds__(64) void k_zone_nt(StepArgs A, int if_begin, int if
       status = ST_NONPHYS;
       break;
     }
-    it += 1;
-    final_pass = conv || it == P.zn_maxit;
-    phase = -1;
   }
   if (!writer) return;
 
