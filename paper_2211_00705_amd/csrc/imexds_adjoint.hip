@@ -227,14 +227,19 @@ __device__ __forceinline__ void d_iface_adj(const IfaceLin& Q, double b0, double
   const double idet = 1.0 / (Q.J11 * Q.J22 - Q.J12 * Q.J21);
   const double mu1 = (Q.J22 * gpl - Q.J21 * gpr) * idet;
   const double mu2 = (Q.J11 * gpr - Q.J12 * gpl) * idet;
-  // direct dependence at fixed p*
+  // direct dependence at fixed p*: u_V* through the vapour side's velocity
+  // (selected, not branched: a conditional update of one of two accumulators
+  // put them in scratch memory)
   gtau += gz * Q.zt;
-  if (Q.lvap) {
-    grl += guV * (-(Q.ul / Q.rl) - Q.dfl_r);
-    gml += guV / Q.rl;
-  } else {
-    grr += guV * (-(Q.ur / Q.rr) + Q.dfr_r);
-    gmr += guV / Q.rr;
+  {
+    const double rV = Q.lvap ? Q.rl : Q.rr, uV = Q.lvap ? Q.ul : Q.ur;
+    const double dV = Q.lvap ? -Q.dfl_r : Q.dfr_r;
+    const double gr = guV * (-(uV / rV) + dV), gm = guV / rV;
+    const double grl1 = grl + gr, gml1 = gml + gm, grr1 = grr + gr, gmr1 = gmr + gm;
+    grl = Q.lvap ? grl1 : grl;
+    gml = Q.lvap ? gml1 : gml;
+    grr = Q.lvap ? grr : grr1;
+    gmr = Q.lvap ? gmr : gmr1;
   }
   // minus dG/dx^T mu: G1 = (p_r* - p_l*) + z^2 [[v]],
   // G2 = f_l + f_r + z [[v]] + (u_r - u_l)

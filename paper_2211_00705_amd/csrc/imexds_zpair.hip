@@ -147,8 +147,11 @@ __global__ __launch_bounds__(64) void k_zone_pair(StepArgs A, int if_begin, int 
     const bool pred = stage == S_PRED;
     double ql0 = 0.0, ql1 = 0.0, qr0 = 0.0, qr1 = 0.0;
     {
-      const int a = pred ? iL[me] : ic[me];
-      const int c = pred ? iL[me] + 1 : icr[me];
+      // this lane's boundary, selected (an array indexed by the lane would
+      // live in scratch memory)
+      const int iLm = me ? iL[1] : iL[0];
+      const int a = pred ? iLm : (me ? ic[1] : ic[0]);
+      const int c = pred ? iLm + 1 : (me ? icr[1] : icr[0]);
 #pragma unroll
       for (int i = 0; i < MP; ++i) {
         const double x0 = pred ? Ur[i] : W0[i], x1 = pred ? Um[i] : W1[i];
@@ -163,8 +166,9 @@ __global__ __launch_bounds__(64) void k_zone_pair(StepArgs A, int if_begin, int 
       }
     }
     const int phl_me = me == 0 ? phl0 : (phl0 ^ 1);
-    const bool hg = pred ? warm[me] != 0 : true;
-    const double g0 = pred ? rpw0[me] : gn0[me], g1 = pred ? rpw1[me] : gn1[me];
+    const bool hg = pred ? (me ? warm[1] : warm[0]) != 0 : true;
+    const double g0 = pred ? (me ? rpw0[1] : rpw0[0]) : (me ? gn0[1] : gn0[0]);
+    const double g1 = pred ? (me ? rpw1[1] : rpw1[0]) : (me ? gn1[1] : gn1[0]);
     IfaceOut o;
     const bool ok_me = d_iface_solve(M, P.newton_maxit, P.newton_rtol, phl_me, ql0, ql1,
                                      phl_me ^ 1, qr0, qr1, hg, g0, g1, o);
