@@ -3,8 +3,8 @@
 // The step is the discrete map U^n -> U^{n+1} of the forward kernels with all
 // of its decisions frozen (pseudo-iteration count, merge and crossing events,
 // HLL branches, the cell that set the CFL time step), as recorded on the
-// forward's tape.  Its adjoint runs in three launches per step, in this
-// order:
+// forward's tape.  Its adjoint runs in three launches per step; the first
+// two touch disjoint cells and may run at the same time:
 //   k_zone_adj  (one lane per zone): reverse of the interface advance and
 //               re-split, of Part 2 and of every pseudo iteration of Part 1
 //               (Algorithm 2) in reverse order from the stored iterates, of
@@ -14,15 +14,17 @@
 //               its root by the implicit function theorem: with G(p*; x) = 0
 //               (Appendix A, eq. 2p_RP:ex_sys), the adjoint of the inputs x
 //               is dO/dx^T b - dG/dx^T mu with J^T mu = dO/dp*^T b, J the
-//               Jacobian of eq. jacobian:ex_sys.
+//               Jacobian of eq. jacobian:ex_sys.  It leaves the adjoints of
+//               the zone's edge fluxes F_left / F_right.
 //   k_bulk_adj  (tiles of cells): transposed three-point stencil of the
-//               explicit HLL update (Algorithm 1 Step 1), including the zone
-//               edge fluxes F_left / F_right handed over by the zone pass and
-//               the dependence of the update on dt; per tile it also leaves
-//               the maximum of |u| + a and the first slot attaining it.
-//   k_fin_adj   (one lane per problem): adjoint of dt = C h / max(|u| + a)
-//               (eq. cfl_cond:unif) through that slot, or of a clipped last
-//               step through t.
+//               explicit HLL update (Algorithm 1 Step 1) on the faces between
+//               bulk cells, and the dependence of the update on dt; per tile
+//               it also leaves the maximum of |u| + a and the first slot
+//               attaining it.
+//   k_fin_adj   (one lane per problem): the faces next to zone cells (the
+//               stencil's terms there plus the edge-flux adjoints), then the
+//               adjoint of dt = C h / max(|u| + a) (eq. cfl_cond:unif)
+//               through that slot, or of a clipped last step through t.
 // Everything is FP64; sums run in a fixed order (no atomics), so the adjoint
 // is reproducible run to run.
 #include "imexds_device.hpp"
@@ -1133,12 +1135,14 @@ __device__ __forceinline__ double d_wave_sum(double v) {
 //        + gF_left of a zone starting at s+1 + gF_right of a zone ending at s,
 // sent through the HLL Jacobians to s (own lane) and s+1 (shuffled up).
 // Cells outside the domain are the wall / transmissive ghosts of the
-// boundary cells, so their adjoints fold back onto those.
+// boundary cells, so their adjoints fold back onto those.  The faces with a
+// zone cell on either side need the zone pass's results, so they are left to
+// the per-problem pass (d_edge_faces) and zone cells are not written: the
+// zone pass can run at the same time.
 template <int R>
 __global__ __launch_bounds__(256) void k_bulk_adj(StepArgs A, AdjArgs B) {
   constexpr int OUT = 62;
   __shared__ int s_zlo[MAX_IF_PER_PROB], s_zhi[MAX_IF_PER_PROB], s_sR[MAX_IF_PER_PROB];
-  __shared__ double s_gz[MAX_IF_PER_PROB][4];
   __shared__ double s_red[4];
   __shared__ unsigned long long s_mx[4];
   __shared__ int s_ix[4];
@@ -1185,11 +1189,6 @@ __global__ __launch_bounds__(256) void k_bulk_adj(StepArgs A, AdjArgs B) {
     s_zlo[tid] = zlo;
     s_zhi[tid] = zhi;
     s_sR[tid] = sL + 1;
-    const double* zg = B.zadj + 5 * (long long)(i0 + tid);
-    s_gz[tid][0] = zg[0];
-    s_gz[tid][1] = zg[1];
-    s_gz[tid][2] = zg[2];
-    s_gz[tid][3] = zg[3];
   }
   __syncthreads();
 
@@ -1219,20 +1218,15 @@ __global__ __launch_bounds__(256) void k_bulk_adj(StepArgs A, AdjArgs B) {
     const int se = s < 0 ? 0 : (s > ns - 1 ? ns - 1 : s);
     int ph = pf;
     bool zone = false;
-    double gzl0 = 0.0, gzl1 = 0.0;  // zone edge adjoints on the face s | s+1
     for (int j = 0; j < nif; ++j) {
       ph ^= (s_sR[j] <= se) ? 1 : 0;
       zone = zone || (s >= s_zlo[j] && s <= s_zhi[j]);
-      if (s_zlo[j] == s + 1) {
-        gzl0 += s_gz[j][0];
-        gzl1 += s_gz[j][1];
-      }
-      if (s_zhi[j] == s) {
-        gzl0 += s_gz[j][2];
-        gzl1 += s_gz[j][3];
-      }
     }
     const bool bulk = in && !zone;
+    // a face with a zone cell on either side is the per-problem pass's (the
+    // shift runs on every lane: a lane masked off would not provide its value)
+    const int zoneR = d_wave_next_i(zone ? 1 : 0);
+    const bool edge = zone || zoneR != 0;
     const double rho = rr[r], mom = mm[r];
     const double u = mom / rho;
     const double pr = d_pres(M, ph, rho);
@@ -1248,12 +1242,12 @@ __global__ __launch_bounds__(256) void k_bulk_adj(StepArgs A, AdjArgs B) {
     const double Fl0 = d_wave_prev(F0);
     const double Fl1 = d_wave_prev(F1);
     // adjoint of the face flux
-    double gf0 = gzl0, gf1 = gzl1;
-    if (bulkR) {
+    double gf0 = 0.0, gf1 = 0.0;
+    if (bulkR && !edge) {
       gf0 += lam * bR0;
       gf1 += lam * bR1;
     }
-    if (bulk) {
+    if (bulk && !edge) {
       gf0 -= lam * br[r];
       gf1 -= lam * bm[r];
     }
@@ -1271,17 +1265,11 @@ __global__ __launch_bounds__(256) void k_bulk_adj(StepArgs A, AdjArgs B) {
     const double from_r = d_wave_prev(cr_r);
     const double from_m = d_wave_prev(cr_m);
     if (lane >= 1 && lane <= OUT && s < tend && in) {
-      double base_r, base_m;
-      if (bulk) {
-        base_r = br[r];
-        base_m = bm[r];
+      if (bulk) {  // zone cells: the zone pass's
         gdt -= ((F0 - Fl0) * br[r] + (F1 - Fl1) * bm[r]) / h;
-      } else {  // zone cell: partial adjoint of the zone pass
-        base_r = g0r[s];
-        base_m = g0m[s];
+        g0r[s] = br[r] + cl_r + from_r;
+        g0m[s] = bm[r] + cl_m + from_m;
       }
-      g0r[s] = base_r + cl_r + from_r;
-      g0m[s] = base_m + cl_m + from_m;
       const unsigned long long b =
           (unsigned long long)__double_as_longlong(fabs(mom / rho) + d_a(M, ph));
       if (b > vmax || (b == vmax && s < vidx)) {
@@ -1326,11 +1314,102 @@ __global__ __launch_bounds__(256) void k_bulk_adj(StepArgs A, AdjArgs B) {
 // ---------------------------------------------------------------------------
 // per-problem pass: dt and t
 // ---------------------------------------------------------------------------
+// The faces that k_bulk_adj left out, those with a zone cell on
+// either side (each zone's two bounding faces, a face between two adjacent
+// zones once), of problem p: the face adjoint as k_bulk_adj forms it, sent
+// through the HLL Jacobians to both cells (ghosts folded back), added to
+// their adjoints.  One thread per problem, after the zone and bulk passes.
+__device__ void d_edge_faces(const StepArgs& A, const AdjArgs& B, int p, double dt) {
+  const Mat& M = A.mat;
+  const Par& P = A.par;
+  const long long so = A.slot_off[p];
+  const int ns = (int)(A.slot_off[p + 1] - so);
+  const double h = A.h[p];
+  const double lam = dt / h;
+  const int i0 = A.iface_off[p];
+  const int nif = A.iface_off[p + 1] - i0;
+  const int pf = A.phase_first[p];
+  const int bcL = P.bc_left, bcR = P.bc_right;
+  const double* r0 = A.rho0 + so;
+  const double* m0 = A.mom0 + so;
+  const double* g1r = B.gr1 + so;
+  const double* g1m = B.gm1 + so;
+  double* g0r = B.gr0 + so;
+  double* g0m = B.gm0 + so;
+  auto zone_of = [&](int j, int& lo, int& hi) {
+    bool tr;
+    d_zone_range(A.rec_home0[i0 + j] + j, A.rec_hl0[i0 + j], h, P.zone_half, ns, lo, hi, tr);
+  };
+  // the face between slots a and a + 1 (a = -1, ns - 1: a ghost on one side)
+  auto face = [&](int a) {
+    const int se = a < 0 ? 0 : a, seR = a + 1 > ns - 1 ? ns - 1 : a + 1;
+    int ph = pf;
+    bool zl = false, zr = false;
+    double gf0 = 0.0, gf1 = 0.0;
+    for (int j = 0; j < nif; ++j) {
+      int lo, hi;
+      zone_of(j, lo, hi);
+      ph ^= (A.rec_home0[i0 + j] + j + 1 <= se) ? 1 : 0;
+      zl = zl || (a >= lo && a <= hi);
+      zr = zr || (a + 1 >= lo && a + 1 <= hi);
+      const double* zg = B.zadj + 5 * (long long)(i0 + j);
+      if (lo == a + 1) {
+        gf0 += zg[0];
+        gf1 += zg[1];
+      }
+      if (hi == a) {
+        gf0 += zg[2];
+        gf1 += zg[3];
+      }
+    }
+    const bool bulkL = a >= 0 && !zl, bulkR = a + 1 < ns && !zr;
+    if (bulkR) {
+      gf0 += lam * g1r[a + 1];
+      gf1 += lam * g1m[a + 1];
+    }
+    if (bulkL) {
+      gf0 -= lam * g1r[a];
+      gf1 -= lam * g1m[a];
+    }
+    if (gf0 == 0.0 && gf1 == 0.0) return;
+    double rl = r0[se], ml = m0[se], rr = r0[seR], mr = m0[seR];
+    if (a < 0 && bcL == 0) ml = -ml;
+    if (a + 1 >= ns && bcR == 0) mr = -mr;
+    double cl_r = 0.0, cl_m = 0.0, cr_r = 0.0, cr_m = 0.0;
+    d_hll_adj(M, ph, rl, ml, rr, mr, gf0, gf1, cl_r, cl_m, cr_r, cr_m);
+    if (a == -1) {
+      cr_r += cl_r;
+      cr_m += (bcL == 0) ? -cl_m : cl_m;
+    }
+    if (a == ns - 1) {
+      cl_r += cr_r;
+      cl_m += (bcR == 0) ? -cr_m : cr_m;
+    }
+    if (a >= 0) {
+      g0r[a] += cl_r;
+      g0m[a] += cl_m;
+    }
+    if (a + 1 < ns) {
+      g0r[a + 1] += cr_r;
+      g0m[a + 1] += cr_m;
+    }
+  };
+  int last = -2;
+  for (int j = 0; j < nif; ++j) {
+    int lo, hi;
+    zone_of(j, lo, hi);
+    if (lo - 1 != last) face(lo - 1);
+    face(hi);
+    last = hi;
+  }
+}
+
 __global__ void k_fin_adj(StepArgs A, AdjArgs B, int P) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= P) return;
   const double dt = A.dt[p];
   if (dt == 0.0) return;
+  d_edge_faces(A, B, p, dt);
   double gdt = 0.0;
   unsigned long long mx = 0;
   int ix = 0x7fffffff;

@@ -82,11 +82,11 @@ inline long long tape_stride(int zone_half, int lmax) {
 struct AdjArgs {
   const double* gr1;  // [S] adjoint of rho^{n+1}
   const double* gm1;  // [S] adjoint of (rho u)^{n+1}
-  double* gr0;        // [S] out: adjoint of rho^n (zone cells: partial from the zone pass)
+  double* gr0;        // [S] out: adjoint of rho^n
   double* gm0;
   double* hl_bar;     // [NIF] in: adjoint of hl^{n+1}; out: of hl^n
   double* tau_bar;    // [NIF] accumulated adjoint of tau per zone
-  double* zadj;       // [NIF * 5] zone pass -> bulk pass: adjoints of F_left, F_right, dt
+  double* zadj;       // [NIF * 5] zone pass -> per-problem pass: adjoints of F_left, F_right, dt
   double* tile_gdt;   // [tiles] bulk cells' part of the adjoint of dt
   unsigned long long* tile_smax;  // [tiles] max |u| + a (bit pattern) over the tile
   int* tile_sidx;     // [tiles] first slot attaining it

@@ -100,6 +100,10 @@ struct imexds_ctx {
   int parity = 0;
   bool has_state = false;
   hipGraphExec_t gexec = nullptr;
+  // reverse sweeps of a recorded segment, by the adjoint buffer they start
+  // from (index bit 0) and full or shorter last segment (bit 1)
+  hipGraphExec_t rev_gexec[4] = {nullptr, nullptr, nullptr, nullptr};
+  int rev_len[4] = {0, 0, 0, 0};
   bool time_bulk = false;
   int bulk_launches = 0;
   double last_total_ms = 0.0, last_bulk_ms = 0.0;
@@ -165,11 +169,26 @@ int dalloc(imexds_ctx* c, T** p, size_t n) {
     if (r_) return r_;                      \
   } while (0)
 
-void drop_graph(imexds_ctx* c) {
+void drop_step_graph(imexds_ctx* c) {
   if (c->gexec) {
     (void)hipGraphExecDestroy(c->gexec);
     c->gexec = nullptr;
   }
+}
+
+void drop_reverse_graphs(imexds_ctx* c) {
+  for (int a = 0; a < 4; ++a) {
+    if (c->rev_gexec[a]) (void)hipGraphExecDestroy(c->rev_gexec[a]);
+    c->rev_gexec[a] = nullptr;
+    c->rev_len[a] = 0;
+  }
+}
+
+// Captured graphs hold the launch arguments (material, parameters, buffers)
+// by value: any change of them drops the graphs.
+void drop_graph(imexds_ctx* c) {
+  drop_step_graph(c);
+  drop_reverse_graphs(c);
 }
 
 StepArgs make_args(imexds_ctx* c, int parity, bool init) {
@@ -354,7 +373,7 @@ int ensure_events(imexds_ctx* c, size_t n) {
 }
 
 int capture_graph(imexds_ctx* c) {
-  drop_graph(c);
+  drop_step_graph(c);
   int G = c->graph_steps;
   int r = ensure_events(c, (size_t)G);
   if (r) return r;
@@ -546,6 +565,7 @@ int steps_impl(imexds_ctx* c, int n) {
 }
 
 void free_tape(imexds_ctx* c) {
+  drop_reverse_graphs(c);
   void* ps[] = {c->tU, c->tHome, c->tHl, c->tDt, c->tClip, c->tSteps, c->tZone};
   for (void* p : ps)
     if (p) (void)hipFree(p);
@@ -628,6 +648,7 @@ int ensure_adjoint_buffers(imexds_ctx* c, int C) {
     HA(c->d_tbar, P);
   }
   if (c->adj_tiles != c->n_tiles) {
+    drop_reverse_graphs(c);
     if (c->d_tgdt) (void)hipFree(c->d_tgdt);
     if (c->d_tsmax) (void)hipFree(c->d_tsmax);
     if (c->d_tsidx) (void)hipFree(c->d_tsidx);
@@ -691,6 +712,10 @@ int record_segment(imexds_ctx* c, int len) {
 }
 
 // Reverse of step j of the recorded segment: adjoint buffers cur -> cur ^ 1.
+// The bulk pass leaves the faces next to zone cells to the per-problem pass,
+// so it does not wait for the zone pass, which runs on zs beside it (the
+// steps are captured into a graph: launched one by one, the cross-stream
+// waits would cost more than the overlap saves).
 int reverse_step(imexds_ctx* c, int j, int cur) {
   const size_t S = (size_t)c->S, N = (size_t)c->NIF, P = (size_t)c->P;
   StepArgs A = make_args(c, 0, false);
@@ -717,9 +742,54 @@ int reverse_step(imexds_ctx* c, int j, int cur) {
   B.steps0 = c->tSteps + (size_t)j * P;
   B.steps1 = c->tSteps + (size_t)(j + 1) * P;
   B.t_bar = c->d_tbar;
-  if (N) CK(imexds::launch_zone_adj(A, B, c->zone_lanes, c->ms));
+  if (N) {
+    CK(hipEventRecord(c->fork_ev[j], c->ms));
+    CK(hipStreamWaitEvent(c->zs, c->fork_ev[j], 0));
+    CK(imexds::launch_zone_adj(A, B, c->zone_lanes, c->zs));
+  }
   CK(imexds::launch_bulk_adj(A, B, c->tile_cells, c->n_tiles, c->ms));
+  if (N) {
+    CK(hipEventRecord(c->join_ev[j], c->zs));
+    CK(hipStreamWaitEvent(c->ms, c->join_ev[j], 0));
+  }
   CK(imexds::launch_finalize_adj(A, B, c->P, c->ms));
+  return 0;
+}
+
+// Reverse sweep of the recorded segment (steps len - 1 .. 0) from adjoint
+// buffer cur, captured into a graph and replayed.  The graph is kept per
+// start buffer and segment kind (`last`: the shorter last segment) for the
+// next sweep of the same length: every full checkpointed segment is one.
+int reverse_segment(imexds_ctx* c, int len, int cur, bool last) {
+  if (len <= 0 || c->P <= 0) return 0;
+  const int slot = cur + (last ? 2 : 0);
+  if (!c->rev_gexec[slot] || c->rev_len[slot] != len) {
+    if (c->rev_gexec[slot]) (void)hipGraphExecDestroy(c->rev_gexec[slot]);
+    c->rev_gexec[slot] = nullptr;
+    c->rev_len[slot] = 0;
+    int r = ensure_events(c, (size_t)len);
+    if (r) return r;
+    CK(hipStreamBeginCapture(c->ms, hipStreamCaptureModeThreadLocal));
+    int b = cur;
+    for (int j = len - 1; j >= 0 && !r; --j) {
+      r = reverse_step(c, j, b);
+      b ^= 1;
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t ee = hipStreamEndCapture(c->ms, &g);
+    if (r || ee != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return r ? r : hip_fail(ee, "hipStreamEndCapture");
+    }
+    const hipError_t e = hipGraphInstantiate(&c->rev_gexec[slot], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      c->rev_gexec[slot] = nullptr;
+      return hip_fail(e, "hipGraphInstantiate");
+    }
+    c->rev_len[slot] = len;
+  }
+  CK(hipGraphLaunch(c->rev_gexec[slot], c->ms));
   return 0;
 }
 
@@ -1436,10 +1506,8 @@ int imexds_adjoint(imexds_ctx* c, const double* gL_rho, const double* gL_mom,
       if ((r = record_segment(c, len))) return r;
       c->tape_seg = seg;
     }
-    for (int j = len - 1; j >= 0; --j) {
-      if ((r = reverse_step(c, j, cur))) return r;
-      cur ^= 1;
-    }
+    if ((r = reverse_segment(c, len, cur, len != C))) return r;
+    cur ^= len & 1;
   }
   if (S) {
     CK(hipMemcpyAsync(g_rho0, c->d_gr[cur], S * 8, hipMemcpyDeviceToDevice, m));

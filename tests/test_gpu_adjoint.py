@@ -154,6 +154,36 @@ def test_adjoint_is_reproducible_and_repeatable(material):
         s.close()
 
 
+def test_adjoint_same_for_every_checkpoint_interval(material):
+    """The recomputed forward is bitwise the forward, so the gradient does
+    not depend on the checkpoint interval: one segment of 40 steps (one
+    captured reverse sweep), and 4 or 8 segments of 10 or 5 steps (one sweep
+    captured and replayed per segment, with the eager checkpoint restores and
+    recomputations between the replays) give bitwise the same gradient, also
+    when the adjoint is called again on the same recording (the graphs
+    replayed once more)."""
+    import torch
+    from paper_2211_00705_amd.imexds import IMEXDS
+    b = W.random_batch(seed=5, n_problems=48, nmax=900)
+    s = IMEXDS(b, material, W.random_batch_params())
+    try:
+        s.set_launch(zone_lanes=8)
+        s.set_state()
+        s.forward_ckpt(40, 40)
+        rho, mom = s.state()
+        g = (torch.rand_like(rho), torch.rand_like(mom))
+        ref = [x.cpu().numpy() for x in s.adjoint(*g)]
+        for C in (10, 5):
+            s.set_state()
+            s.forward_ckpt(40, C)
+            for _ in range(2):
+                got = [x.cpu().numpy() for x in s.adjoint(*g)]
+                for x, y in zip(ref, got):
+                    assert np.array_equal(x, y), C
+    finally:
+        s.close()
+
+
 def test_autograd_function_gradients(material):
     """torch.autograd through evolve(): gradients of the window objective in
     rho0, rho u 0 and tau agree with the direct adjoint call."""
