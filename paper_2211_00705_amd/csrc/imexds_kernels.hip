@@ -785,6 +785,34 @@ hipError_t launch_zone(const StepArgs& A, int if_begin, int if_end, int groups, 
   return hipGetLastError();
 }
 
+// The per-step records of a recorded step copied into its tape slot: the
+// interface cells and cut lengths (N each), dt, the clip flag and the step
+// counter (P each).  One launch instead of five copies.
+__global__ void k_tape_copy(const int* home, const double* hl, const double* dt, const int* clip,
+                            const long long* steps, int* t_home, double* t_hl, double* t_dt,
+                            int* t_clip, long long* t_steps, int N, int P) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) {
+    t_home[i] = home[i];
+    t_hl[i] = hl[i];
+  }
+  if (i < P) {
+    t_dt[i] = dt[i];
+    t_clip[i] = clip[i];
+    t_steps[i] = steps[i];
+  }
+}
+
+hipError_t launch_tape_copy(const int* home, const double* hl, const double* dt, const int* clip,
+                            const long long* steps, int* t_home, double* t_hl, double* t_dt,
+                            int* t_clip, long long* t_steps, int N, int P, hipStream_t s) {
+  const int n = N > P ? N : P;
+  if (n <= 0) return hipSuccess;
+  k_tape_copy<<<(n + 255) / 256, 256, 0, s>>>(home, hl, dt, clip, steps, t_home, t_hl, t_dt,
+                                              t_clip, t_steps, N, P);
+  return hipGetLastError();
+}
+
 hipError_t launch_finalize(const StepArgs& A, int p_begin, int p_end, int init, int bump_row,
                            hipStream_t s) {
   int n = p_end - p_begin;

@@ -129,6 +129,11 @@ __device__ __forceinline__ bool d_pair_lead(const StepArgs& A, int k, int kk, in
                zhi1, t1);
   return zlo1 <= zhi0;
 }
+// copies one step's records (N interface cells and cut lengths; P of dt,
+// clip flags, step counters) into a tape slot
+hipError_t launch_tape_copy(const int* home, const double* hl, const double* dt, const int* clip,
+                            const long long* steps, int* t_home, double* t_hl, double* t_dt,
+                            int* t_clip, long long* t_steps, int N, int P, hipStream_t s);
 hipError_t launch_finalize(const StepArgs& A, int p_begin, int p_end, int init, int bump_row,
                            hipStream_t s);
 // the zones solved by Newton on their implicit step (zone_half 1 or 2):

@@ -101,9 +101,12 @@ struct imexds_ctx {
   bool has_state = false;
   hipGraphExec_t gexec = nullptr;
   // reverse sweeps of a recorded segment, by the adjoint buffer they start
-  // from (index bit 0) and full or shorter last segment (bit 1)
+  // from (index bit 0) and full or shorter last segment (bit 1); recorded
+  // segments, by the state parity they start at (bit 0) and length (bit 1)
   hipGraphExec_t rev_gexec[4] = {nullptr, nullptr, nullptr, nullptr};
   int rev_len[4] = {0, 0, 0, 0};
+  hipGraphExec_t rec_gexec[4] = {nullptr, nullptr, nullptr, nullptr};
+  int rec_len[4] = {0, 0, 0, 0};
   bool time_bulk = false;
   int bulk_launches = 0;
   double last_total_ms = 0.0, last_bulk_ms = 0.0;
@@ -176,11 +179,14 @@ void drop_step_graph(imexds_ctx* c) {
   }
 }
 
-void drop_reverse_graphs(imexds_ctx* c) {
+void drop_adjoint_graphs(imexds_ctx* c) {
   for (int a = 0; a < 4; ++a) {
     if (c->rev_gexec[a]) (void)hipGraphExecDestroy(c->rev_gexec[a]);
     c->rev_gexec[a] = nullptr;
     c->rev_len[a] = 0;
+    if (c->rec_gexec[a]) (void)hipGraphExecDestroy(c->rec_gexec[a]);
+    c->rec_gexec[a] = nullptr;
+    c->rec_len[a] = 0;
   }
 }
 
@@ -188,7 +194,7 @@ void drop_reverse_graphs(imexds_ctx* c) {
 // by value: any change of them drops the graphs.
 void drop_graph(imexds_ctx* c) {
   drop_step_graph(c);
-  drop_reverse_graphs(c);
+  drop_adjoint_graphs(c);
 }
 
 StepArgs make_args(imexds_ctx* c, int parity, bool init) {
@@ -565,7 +571,7 @@ int steps_impl(imexds_ctx* c, int n) {
 }
 
 void free_tape(imexds_ctx* c) {
-  drop_reverse_graphs(c);
+  drop_adjoint_graphs(c);
   void* ps[] = {c->tU, c->tHome, c->tHl, c->tDt, c->tClip, c->tSteps, c->tZone};
   for (void* p : ps)
     if (p) (void)hipFree(p);
@@ -648,7 +654,7 @@ int ensure_adjoint_buffers(imexds_ctx* c, int C) {
     HA(c->d_tbar, P);
   }
   if (c->adj_tiles != c->n_tiles) {
-    drop_reverse_graphs(c);
+    drop_adjoint_graphs(c);
     if (c->d_tgdt) (void)hipFree(c->d_tgdt);
     if (c->d_tsmax) (void)hipFree(c->d_tsmax);
     if (c->d_tsidx) (void)hipFree(c->d_tsidx);
@@ -664,31 +670,23 @@ int ensure_adjoint_buffers(imexds_ctx* c, int C) {
   return 0;
 }
 
-// Re-runs `len` steps from the restored checkpoint, keeping for each step
+// Enqueues `len` steps from the restored checkpoint, keeping for each step
 // its input state, records, dt and the zone tape.  Step j reads its state
 // from tape slot j and writes the next one straight into slot j + 1 (the
-// last step into the live state buffer, which the segment's caller reads).
-// The zones and the bulk sweep run one after the other on ms: the recording
-// zone kernel bounds the step, and cross-stream waits between launches made
-// one by one cost more than the overlap saved (a graph-captured replay of the
-// segment with the overlap measured no faster either).
-int record_segment(imexds_ctx* c, int len) {
+// last step into the live state buffer, which the segment's caller reads);
+// the zones run on zs beside the bulk sweep, as in a plain step.
+int enqueue_record(imexds_ctx* c, int len) {
   const size_t S = (size_t)c->S, N = (size_t)c->NIF, P = (size_t)c->P;
   hipStream_t m = c->ms;
-  if (len < 0 || len > c->tape_steps) return IMEXDS_ERR_INVALID_ARG;
   if (S && len > 0) {
     CK(hipMemcpyAsync(c->tU, c->d_rho[c->parity], S * 8, hipMemcpyDeviceToDevice, m));
     CK(hipMemcpyAsync(c->tU + S, c->d_mom[c->parity], S * 8, hipMemcpyDeviceToDevice, m));
   }
   for (int j = 0; j < len; ++j) {
     const int a = c->parity;
-    if (N) {
-      CK(hipMemcpyAsync(c->tHome + j * N, c->d_home[a], N * 4, hipMemcpyDeviceToDevice, m));
-      CK(hipMemcpyAsync(c->tHl + j * N, c->d_hl[a], N * 8, hipMemcpyDeviceToDevice, m));
-    }
-    CK(hipMemcpyAsync(c->tDt + j * P, c->d_dt, P * 8, hipMemcpyDeviceToDevice, m));
-    CK(hipMemcpyAsync(c->tClip + j * P, c->d_clipped, P * 4, hipMemcpyDeviceToDevice, m));
-    CK(hipMemcpyAsync(c->tSteps + j * P, c->d_steps, P * 8, hipMemcpyDeviceToDevice, m));
+    CK(imexds::launch_tape_copy(c->d_home[a], c->d_hl[a], c->d_dt, c->d_clipped, c->d_steps,
+                                c->tHome + j * N, c->tHl + j * N, c->tDt + j * P,
+                                c->tClip + j * P, c->tSteps + j * P, (int)N, (int)P, m));
     StepArgs A = make_args(c, a, false);
     A.rho0 = c->tU + (size_t)j * 2 * S;
     A.mom0 = A.rho0 + S;
@@ -702,12 +700,58 @@ int record_segment(imexds_ctx* c, int len) {
     A.st_newton = A.st_solves = A.st_events = A.st_pairs = nullptr;
     A.tape = c->tZone + (size_t)j * N * (size_t)c->tape_stride;
     A.tape_stride = c->tape_stride;
-    if (N) CK(launch_zones(c, A, 0, c->NIF, c->zone_groups, m));
+    if (N) {
+      CK(hipEventRecord(c->fork_ev[j], m));
+      CK(hipStreamWaitEvent(c->zs, c->fork_ev[j], 0));
+      CK(launch_zones(c, A, 0, c->NIF, c->zone_groups, c->zs));
+    }
     CK(imexds::launch_bulk(A, c->tile_cells, 0, c->n_tiles, m));
+    if (N) {
+      CK(hipEventRecord(c->join_ev[j], c->zs));
+      CK(hipStreamWaitEvent(m, c->join_ev[j], 0));
+    }
     CK(imexds::launch_finalize(A, 0, c->P, 0, 0, m));
     c->parity ^= 1;
   }
   CK(hipMemcpyAsync(c->tSteps + (size_t)len * P, c->d_steps, P * 8, hipMemcpyDeviceToDevice, m));
+  return 0;
+}
+
+// Records a segment of `len` steps, captured into a graph (kept per start
+// parity and segment kind for the next segment of the same shape: the
+// reverse sweep records every checkpointed segment again) and replayed.
+// Launched one by one, the cross-stream waits of the zone/bulk overlap
+// would cost more than the overlap saves.
+int record_segment(imexds_ctx* c, int len) {
+  if (len < 0 || len > c->tape_steps) return IMEXDS_ERR_INVALID_ARG;
+  if (len == 0 || c->P <= 0) return enqueue_record(c, len);
+  const int p0 = c->parity;
+  const int slot = p0 + (len != c->tape_steps ? 2 : 0);
+  if (!c->rec_gexec[slot] || c->rec_len[slot] != len) {
+    if (c->rec_gexec[slot]) (void)hipGraphExecDestroy(c->rec_gexec[slot]);
+    c->rec_gexec[slot] = nullptr;
+    c->rec_len[slot] = 0;
+    int r = ensure_events(c, (size_t)len);
+    if (r) return r;
+    CK(hipStreamBeginCapture(c->ms, hipStreamCaptureModeThreadLocal));
+    r = enqueue_record(c, len);
+    hipGraph_t g = nullptr;
+    const hipError_t ee = hipStreamEndCapture(c->ms, &g);
+    c->parity = p0;
+    if (r || ee != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return r ? r : hip_fail(ee, "hipStreamEndCapture");
+    }
+    const hipError_t e = hipGraphInstantiate(&c->rec_gexec[slot], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      c->rec_gexec[slot] = nullptr;
+      return hip_fail(e, "hipGraphInstantiate");
+    }
+    c->rec_len[slot] = len;
+  }
+  CK(hipGraphLaunch(c->rec_gexec[slot], c->ms));
+  c->parity = p0 ^ (len & 1);
   return 0;
 }
 
