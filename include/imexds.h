@@ -339,9 +339,12 @@ int imexds_set_tau(imexds_ctx *ctx, double tau);
  * zero).  Outputs (device): dL/drho and dL/d(rho u) of the start state
  * ([n_slots]), dL/dhl of the start offsets ([n_iface], may be NULL) and
  * dL/dtau (one double).  Each segment of ckpt_every steps is run again from
- * its checkpoint while its per-step states and zone iterates are kept
- * (about ckpt_every x (16 B per slot + 8 B x (2 Z + 2) x (l_max + 1) per
- * interface)), then reversed step by step.  Sums are taken in a fixed
+ * its checkpoint while its per-step states and zone iterates are kept in a
+ * tape (about ckpt_every x (16 B per slot + 8 B x (2 Z + 2) x (l_max + 1)
+ * per interface)), then reversed step by step.  With more than one segment
+ * a second tape is allocated if device memory allows, and each segment is
+ * run again while the one after it is reversed; without it the two
+ * alternate.  Sums are taken in a fixed
  * order, so results are reproducible.  Async; the end state of the forward
  * is in place again afterwards, and the call may be repeated with other
  * end-state derivatives.  Returns IMEXDS_ERR_NO_STATE unless the last call

@@ -48,6 +48,18 @@ struct Snapshot {
 
 }  // namespace
 
+// The recorded steps of one checkpoint segment.
+struct Tape {
+  double* U = nullptr;          // [C][2][S] rho^n, (rho u)^n
+  int* home = nullptr;          // [C][NIF]
+  double* hl = nullptr;         // [C][NIF]
+  double* dt = nullptr;         // [C][P]
+  int* clip = nullptr;          // [C][P]
+  long long* steps = nullptr;   // [C+1][P]
+  double* zone = nullptr;       // [C][NIF][stride]
+  int seg = -1;                 // checkpoint segment recorded in it (-1: none)
+};
+
 struct imexds_ctx {
   int device = 0;
   hipStream_t user = nullptr;  // the caller's stream
@@ -100,13 +112,15 @@ struct imexds_ctx {
   int parity = 0;
   bool has_state = false;
   hipGraphExec_t gexec = nullptr;
+  hipEvent_t ev_rev = nullptr, ev_rec = nullptr;  // the adjoint's two streams
   // reverse sweeps of a recorded segment, by the adjoint buffer they start
-  // from (index bit 0) and full or shorter last segment (bit 1); recorded
-  // segments, by the state parity they start at (bit 0) and length (bit 1)
-  hipGraphExec_t rev_gexec[4] = {nullptr, nullptr, nullptr, nullptr};
-  int rev_len[4] = {0, 0, 0, 0};
-  hipGraphExec_t rec_gexec[4] = {nullptr, nullptr, nullptr, nullptr};
-  int rec_len[4] = {0, 0, 0, 0};
+  // from (index bit 0), full or shorter last segment (bit 1) and tape (bit
+  // 2); recorded segments, by the state parity they start at (bit 0), length
+  // (bit 1) and tape (bit 2)
+  hipGraphExec_t rev_gexec[8] = {};
+  int rev_len[8] = {};
+  hipGraphExec_t rec_gexec[8] = {};
+  int rec_len[8] = {};
   bool time_bulk = false;
   int bulk_launches = 0;
   double last_total_ms = 0.0, last_bulk_ms = 0.0;
@@ -119,15 +133,12 @@ struct imexds_ctx {
   int adj_steps = 0, adj_every = 0;
   bool adj_ready = false;
   int tape_steps = 0;      // segment length the tape buffers hold
-  int tape_seg = -1;       // checkpoint segment whose tape is recorded (-1: none)
   long long tape_stride = 0;
-  double* tU = nullptr;    // [C][2][S] rho^n, (rho u)^n
-  int* tHome = nullptr;    // [C][NIF]
-  double* tHl = nullptr;   // [C][NIF]
-  double* tDt = nullptr;   // [C][P]
-  int* tClip = nullptr;    // [C][P]
-  long long* tSteps = nullptr;  // [C+1][P]
-  double* tZone = nullptr;      // [C][NIF][stride]
+  // Two tapes: while the reverse sweep reads one segment's tape, the
+  // segment before it is recomputed into the other (tape[1] allocated by the
+  // adjoint when there is more than one segment and memory allows)
+  Tape tape[2];
+  int n_tapes = 0;
   double *d_gr[2] = {nullptr, nullptr}, *d_gm[2] = {nullptr, nullptr};
   double *d_hlbar = nullptr, *d_taubar = nullptr, *d_zadj = nullptr, *d_tbar = nullptr;
   double* d_tgdt = nullptr;
@@ -180,7 +191,7 @@ void drop_step_graph(imexds_ctx* c) {
 }
 
 void drop_adjoint_graphs(imexds_ctx* c) {
-  for (int a = 0; a < 4; ++a) {
+  for (int a = 0; a < 8; ++a) {
     if (c->rev_gexec[a]) (void)hipGraphExecDestroy(c->rev_gexec[a]);
     c->rev_gexec[a] = nullptr;
     c->rev_len[a] = 0;
@@ -507,12 +518,14 @@ int snap_take(imexds_ctx* c, Snapshot& s) {
   return 0;
 }
 
-int snap_restore(imexds_ctx* c, Snapshot& s) {
+// Copies the snapshot back into the live state on stream m (the main stream
+// by default) and, with `sync`, waits for it.
+int snap_restore(imexds_ctx* c, Snapshot& s, hipStream_t m = nullptr, bool sync = true) {
   size_t S = (size_t)std::max<long long>(c->S, 1), N = (size_t)std::max(c->NIF, 1),
          P = (size_t)std::max(c->P, 1);
   int a = s.parity;
   c->parity = a;
-  hipStream_t m = c->ms;
+  if (!m) m = c->ms;
   CK(hipMemcpyAsync(c->d_rho[a], s.rho, S * 8, hipMemcpyDeviceToDevice, m));
   CK(hipMemcpyAsync(c->d_mom[a], s.mom, S * 8, hipMemcpyDeviceToDevice, m));
   if (c->NIF > 0) {
@@ -527,7 +540,7 @@ int snap_restore(imexds_ctx* c, Snapshot& s) {
   CK(hipMemcpyAsync(c->d_clipped, s.clipped, P * 4, hipMemcpyDeviceToDevice, m));
   CK(hipMemcpyAsync(c->d_steps, s.steps, P * 8, hipMemcpyDeviceToDevice, m));
   CK(hipMemcpyAsync(c->d_stats, s.stats, N_STATS * 8, hipMemcpyDeviceToDevice, m));
-  CK(hipStreamSynchronize(m));
+  if (sync) CK(hipStreamSynchronize(m));
   return 0;
 }
 
@@ -570,24 +583,23 @@ int steps_impl(imexds_ctx* c, int n) {
   return 0;
 }
 
-void free_tape(imexds_ctx* c) {
-  drop_adjoint_graphs(c);
-  void* ps[] = {c->tU, c->tHome, c->tHl, c->tDt, c->tClip, c->tSteps, c->tZone};
+void free_one_tape(Tape& T) {
+  void* ps[] = {T.U, T.home, T.hl, T.dt, T.clip, T.steps, T.zone};
   for (void* p : ps)
     if (p) (void)hipFree(p);
-  c->tape_seg = -1;
-  c->tU = nullptr;
-  c->tHome = nullptr;
-  c->tHl = nullptr;
-  c->tDt = nullptr;
-  c->tClip = nullptr;
-  c->tSteps = nullptr;
-  c->tZone = nullptr;
+  T = Tape();
+}
+
+void free_tape(imexds_ctx* c) {
+  drop_adjoint_graphs(c);
+  free_one_tape(c->tape[0]);
+  free_one_tape(c->tape[1]);
+  c->n_tapes = 0;
   c->tape_steps = 0;
 }
 
 void free_checkpoints(imexds_ctx* c) {
-  c->tape_seg = -1;
+  c->tape[0].seg = c->tape[1].seg = -1;
   for (Snapshot& s : c->ck) snap_free(s);
   c->ck.clear();
   if (c->ck_end_valid) snap_free(c->ck_end);
@@ -627,21 +639,47 @@ int halloc(T** p, size_t n) {
     if (r_) return r_;                      \
   } while (0)
 
+int alloc_tape(imexds_ctx* c, Tape& T) {
+  const size_t S = (size_t)c->S, N = (size_t)c->NIF, P = (size_t)c->P;
+  const size_t C = (size_t)c->tape_steps;
+  HA(T.U, C * 2 * S);
+  HA(T.home, C * N);
+  HA(T.hl, C * N);
+  HA(T.dt, C * P);
+  HA(T.clip, C * P);
+  HA(T.steps, (C + 1) * P);
+  HA(T.zone, C * N * (size_t)c->tape_stride);
+  T.seg = -1;
+  return 0;
+}
+
+// The second tape, for recomputing a segment while the one after it is
+// reversed; false (and one tape) when it does not fit in device memory.
+bool ensure_second_tape(imexds_ctx* c) {
+  if (c->n_tapes >= 2) return true;
+  if (alloc_tape(c, c->tape[1])) {
+    free_one_tape(c->tape[1]);
+    (void)hipGetLastError();
+    return false;
+  }
+  c->n_tapes = 2;
+  return true;
+}
+
 // Tape of one segment of C steps and the adjoint work arrays.
 int ensure_adjoint_buffers(imexds_ctx* c, int C) {
   const size_t S = (size_t)c->S, N = (size_t)c->NIF, P = (size_t)c->P;
   const long long stride = imexds::tape_stride(c->par.zone_half, c->par.lmax);
   if (c->tape_steps != C || c->tape_stride != stride) {
     free_tape(c);
-    HA(c->tU, (size_t)C * 2 * S);
-    HA(c->tHome, (size_t)C * N);
-    HA(c->tHl, (size_t)C * N);
-    HA(c->tDt, (size_t)C * P);
-    HA(c->tClip, (size_t)C * P);
-    HA(c->tSteps, (size_t)(C + 1) * P);
-    HA(c->tZone, (size_t)C * N * (size_t)stride);
     c->tape_steps = C;
     c->tape_stride = stride;
+    int r = alloc_tape(c, c->tape[0]);
+    if (r) {
+      free_tape(c);
+      return r;
+    }
+    c->n_tapes = 1;
   }
   if (!c->d_gr[0]) {
     for (int a = 0; a < 2; ++a) {
@@ -675,30 +713,29 @@ int ensure_adjoint_buffers(imexds_ctx* c, int C) {
 // from tape slot j and writes the next one straight into slot j + 1 (the
 // last step into the live state buffer, which the segment's caller reads);
 // the zones run on zs beside the bulk sweep, as in a plain step.
-int enqueue_record(imexds_ctx* c, int len) {
+int enqueue_record(imexds_ctx* c, Tape& T, int len, hipStream_t m) {
   const size_t S = (size_t)c->S, N = (size_t)c->NIF, P = (size_t)c->P;
-  hipStream_t m = c->ms;
   if (S && len > 0) {
-    CK(hipMemcpyAsync(c->tU, c->d_rho[c->parity], S * 8, hipMemcpyDeviceToDevice, m));
-    CK(hipMemcpyAsync(c->tU + S, c->d_mom[c->parity], S * 8, hipMemcpyDeviceToDevice, m));
+    CK(hipMemcpyAsync(T.U, c->d_rho[c->parity], S * 8, hipMemcpyDeviceToDevice, m));
+    CK(hipMemcpyAsync(T.U + S, c->d_mom[c->parity], S * 8, hipMemcpyDeviceToDevice, m));
   }
   for (int j = 0; j < len; ++j) {
     const int a = c->parity;
     CK(imexds::launch_tape_copy(c->d_home[a], c->d_hl[a], c->d_dt, c->d_clipped, c->d_steps,
-                                c->tHome + j * N, c->tHl + j * N, c->tDt + j * P,
-                                c->tClip + j * P, c->tSteps + j * P, (int)N, (int)P, m));
+                                T.home + j * N, T.hl + j * N, T.dt + j * P, T.clip + j * P,
+                                T.steps + j * P, (int)N, (int)P, m));
     StepArgs A = make_args(c, a, false);
-    A.rho0 = c->tU + (size_t)j * 2 * S;
+    A.rho0 = T.U + (size_t)j * 2 * S;
     A.mom0 = A.rho0 + S;
     if (j + 1 < len) {
-      A.rho1 = c->tU + (size_t)(j + 1) * 2 * S;
+      A.rho1 = T.U + (size_t)(j + 1) * 2 * S;
       A.mom1 = A.rho1 + S;
     }
     A.log_count = A.log_flags = A.log_zlo = A.log_row = nullptr;
     A.log_max = 0;
     A.st_pseudo = A.st_merges = A.st_lmax = nullptr;
     A.st_newton = A.st_solves = A.st_events = A.st_pairs = nullptr;
-    A.tape = c->tZone + (size_t)j * N * (size_t)c->tape_stride;
+    A.tape = T.zone + (size_t)j * N * (size_t)c->tape_stride;
     A.tape_stride = c->tape_stride;
     if (N) {
       CK(hipEventRecord(c->fork_ev[j], m));
@@ -713,7 +750,7 @@ int enqueue_record(imexds_ctx* c, int len) {
     CK(imexds::launch_finalize(A, 0, c->P, 0, 0, m));
     c->parity ^= 1;
   }
-  CK(hipMemcpyAsync(c->tSteps + (size_t)len * P, c->d_steps, P * 8, hipMemcpyDeviceToDevice, m));
+  CK(hipMemcpyAsync(T.steps + (size_t)len * P, c->d_steps, P * 8, hipMemcpyDeviceToDevice, m));
   return 0;
 }
 
@@ -722,21 +759,22 @@ int enqueue_record(imexds_ctx* c, int len) {
 // reverse sweep records every checkpointed segment again) and replayed.
 // Launched one by one, the cross-stream waits of the zone/bulk overlap
 // would cost more than the overlap saves.
-int record_segment(imexds_ctx* c, int len) {
-  if (len < 0 || len > c->tape_steps) return IMEXDS_ERR_INVALID_ARG;
-  if (len == 0 || c->P <= 0) return enqueue_record(c, len);
+int record_segment(imexds_ctx* c, int t, int len, hipStream_t m) {
+  if (len < 0 || len > c->tape_steps || t < 0 || t >= c->n_tapes) return IMEXDS_ERR_INVALID_ARG;
+  Tape& T = c->tape[t];
+  if (len == 0 || c->P <= 0) return enqueue_record(c, T, len, m);
   const int p0 = c->parity;
-  const int slot = p0 + (len != c->tape_steps ? 2 : 0);
+  const int slot = p0 + (len != c->tape_steps ? 2 : 0) + 4 * t;
   if (!c->rec_gexec[slot] || c->rec_len[slot] != len) {
     if (c->rec_gexec[slot]) (void)hipGraphExecDestroy(c->rec_gexec[slot]);
     c->rec_gexec[slot] = nullptr;
     c->rec_len[slot] = 0;
     int r = ensure_events(c, (size_t)len);
     if (r) return r;
-    CK(hipStreamBeginCapture(c->ms, hipStreamCaptureModeThreadLocal));
-    r = enqueue_record(c, len);
+    CK(hipStreamBeginCapture(m, hipStreamCaptureModeThreadLocal));
+    r = enqueue_record(c, T, len, m);
     hipGraph_t g = nullptr;
-    const hipError_t ee = hipStreamEndCapture(c->ms, &g);
+    const hipError_t ee = hipStreamEndCapture(m, &g);
     c->parity = p0;
     if (r || ee != hipSuccess) {
       if (g) (void)hipGraphDestroy(g);
@@ -750,7 +788,7 @@ int record_segment(imexds_ctx* c, int len) {
     }
     c->rec_len[slot] = len;
   }
-  CK(hipGraphLaunch(c->rec_gexec[slot], c->ms));
+  CK(hipGraphLaunch(c->rec_gexec[slot], m));
   c->parity = p0 ^ (len & 1);
   return 0;
 }
@@ -760,16 +798,16 @@ int record_segment(imexds_ctx* c, int len) {
 // so it does not wait for the zone pass, which runs on zs beside it (the
 // steps are captured into a graph: launched one by one, the cross-stream
 // waits would cost more than the overlap saves).
-int reverse_step(imexds_ctx* c, int j, int cur) {
+int reverse_step(imexds_ctx* c, const Tape& T, int j, int cur) {
   const size_t S = (size_t)c->S, N = (size_t)c->NIF, P = (size_t)c->P;
   StepArgs A = make_args(c, 0, false);
-  A.rho0 = c->tU + (size_t)j * 2 * S;
+  A.rho0 = T.U + (size_t)j * 2 * S;
   A.mom0 = A.rho0 + S;
-  A.rec_home0 = c->tHome + (size_t)j * N;
-  A.rec_hl0 = c->tHl + (size_t)j * N;
-  A.dt = c->tDt + (size_t)j * P;
-  A.clipped = c->tClip + (size_t)j * P;
-  A.tape = c->tZone + (size_t)j * N * (size_t)c->tape_stride;
+  A.rec_home0 = T.home + (size_t)j * N;
+  A.rec_hl0 = T.hl + (size_t)j * N;
+  A.dt = T.dt + (size_t)j * P;
+  A.clipped = T.clip + (size_t)j * P;
+  A.tape = T.zone + (size_t)j * N * (size_t)c->tape_stride;
   A.tape_stride = c->tape_stride;
   imexds::AdjArgs B;
   B.gr1 = c->d_gr[cur];
@@ -783,8 +821,8 @@ int reverse_step(imexds_ctx* c, int j, int cur) {
   B.tile_smax = c->d_tsmax;
   B.tile_sidx = c->d_tsidx;
   B.tile_off = c->d_tile_off;
-  B.steps0 = c->tSteps + (size_t)j * P;
-  B.steps1 = c->tSteps + (size_t)(j + 1) * P;
+  B.steps0 = T.steps + (size_t)j * P;
+  B.steps1 = T.steps + (size_t)(j + 1) * P;
   B.t_bar = c->d_tbar;
   if (N) {
     CK(hipEventRecord(c->fork_ev[j], c->ms));
@@ -804,9 +842,10 @@ int reverse_step(imexds_ctx* c, int j, int cur) {
 // buffer cur, captured into a graph and replayed.  The graph is kept per
 // start buffer and segment kind (`last`: the shorter last segment) for the
 // next sweep of the same length: every full checkpointed segment is one.
-int reverse_segment(imexds_ctx* c, int len, int cur, bool last) {
+int reverse_segment(imexds_ctx* c, int t, int len, int cur, bool last) {
   if (len <= 0 || c->P <= 0) return 0;
-  const int slot = cur + (last ? 2 : 0);
+  const Tape& T = c->tape[t];
+  const int slot = cur + (last ? 2 : 0) + 4 * t;
   if (!c->rev_gexec[slot] || c->rev_len[slot] != len) {
     if (c->rev_gexec[slot]) (void)hipGraphExecDestroy(c->rev_gexec[slot]);
     c->rev_gexec[slot] = nullptr;
@@ -816,7 +855,7 @@ int reverse_segment(imexds_ctx* c, int len, int cur, bool last) {
     CK(hipStreamBeginCapture(c->ms, hipStreamCaptureModeThreadLocal));
     int b = cur;
     for (int j = len - 1; j >= 0 && !r; --j) {
-      r = reverse_step(c, j, b);
+      r = reverse_step(c, T, j, b);
       b ^= 1;
     }
     hipGraph_t g = nullptr;
@@ -876,7 +915,7 @@ void imexds_destroy(imexds_ctx* c) {
   for (auto e : c->bulk_ev) (void)hipEventDestroy(e);
   for (auto e : c->zone_ev) (void)hipEventDestroy(e);
   for (auto e : c->call_ev) (void)hipEventDestroy(e);
-  hipEvent_t es[] = {c->ev_in, c->ev_out, c->ev_t0, c->ev_t1};
+  hipEvent_t es[] = {c->ev_in, c->ev_out, c->ev_t0, c->ev_t1, c->ev_rev, c->ev_rec};
   for (auto e : es)
     if (e) (void)hipEventDestroy(e);
   if (c->ms) (void)hipStreamDestroy(c->ms);
@@ -982,6 +1021,8 @@ static int create_impl(imexds_ctx* c, const imexds_material* mat, const imexds_p
   CK(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
   CK(hipEventCreate(&c->ev_t0));
   CK(hipEventCreate(&c->ev_t1));
+  CK(hipEventCreateWithFlags(&c->ev_rev, hipEventDisableTiming));
+  CK(hipEventCreateWithFlags(&c->ev_rec, hipEventDisableTiming));
   int r = ensure_events(c, 1);
   if (r) return r;
 
@@ -1487,8 +1528,8 @@ int imexds_forward_ckpt(imexds_ctx* c, int32_t n_steps, int32_t ckpt_every) {
     const int len = std::min(ckpt_every, n_steps - j * ckpt_every);
     if (c->P > 0) {
       if (j == nck - 1) {
-        if ((r = record_segment(c, len))) return r;
-        c->tape_seg = j;
+        if ((r = record_segment(c, 0, len, c->ms))) return r;
+        c->tape[0].seg = j;
       } else if ((r = steps_impl(c, len))) {
         return r;
       }
@@ -1543,15 +1584,38 @@ int imexds_adjoint(imexds_ctx* c, const double* gL_rho, const double* gL_mom,
   }
   if (P) CK(hipMemsetAsync(c->d_tbar, 0, P * 8, m));
   int cur = 0;
-  for (int seg = (int)c->ck.size() - 1; seg >= 0; --seg) {
+  const int nck = (int)c->ck.size();
+  // the tape that holds the last segment (imexds_forward_ckpt recorded it)
+  int t = (c->n_tapes > 1 && c->tape[1].seg == nck - 1) ? 1 : 0;
+  // With two tapes, while segment seg is reversed on ms the segment before
+  // it is recomputed into the other tape on ps, after the reverse sweep that
+  // last read that tape: each reads only its own tape, checkpoint and
+  // buffers.  With one tape, each segment is recomputed and then reversed.
+  const bool two = nck > 1 && ensure_second_tape(c);
+  hipStream_t q = c->ps;
+  for (int seg = nck - 1; seg >= 0; --seg) {
     const int len = std::min(C, n - seg * C);
-    if (c->tape_seg != seg) {
+    if (c->tape[t].seg != seg) {
       if ((r = snap_restore(c, c->ck[seg]))) return r;
-      if ((r = record_segment(c, len))) return r;
-      c->tape_seg = seg;
+      if ((r = record_segment(c, t, len, m))) return r;
+      c->tape[t].seg = seg;
     }
-    if ((r = reverse_segment(c, len, cur, len != C))) return r;
+    const bool ahead = two && seg > 0;
+    if (ahead) {
+      const int u = t ^ 1;
+      CK(hipEventRecord(c->ev_rev, m));
+      CK(hipStreamWaitEvent(q, c->ev_rev, 0));
+      if ((r = snap_restore(c, c->ck[seg - 1], q, false))) return r;
+      if ((r = record_segment(c, u, std::min(C, n - (seg - 1) * C), q))) return r;
+      c->tape[u].seg = seg - 1;
+      CK(hipEventRecord(c->ev_rec, q));
+    }
+    if ((r = reverse_segment(c, t, len, cur, len != C))) return r;
     cur ^= len & 1;
+    if (ahead) {
+      CK(hipStreamWaitEvent(m, c->ev_rec, 0));
+      t ^= 1;
+    }
   }
   if (S) {
     CK(hipMemcpyAsync(g_rho0, c->d_gr[cur], S * 8, hipMemcpyDeviceToDevice, m));
