@@ -661,8 +661,6 @@ def main():
         print(json.dumps({"creation_tubes": ctube_leg(args, not args.no_cpu)}))
         return
 
-    # practical HBM ceiling (after the copy the traffic calibration counts on)
-    copy_gbs = measure_copy_bandwidth() if args.copy_bw else None
     b, P, desc = make_workload(args)
     s = I.IMEXDS(b, material, P)
     rho0 = torch.from_numpy(np.ascontiguousarray(b.rho)).cuda()
@@ -718,8 +716,7 @@ def main():
         zone_achieved = step_bytes / (zone_ms * 1e-3) / 1e9
     # a plain copy moving the same bytes per launch (read + write), the
     # practical ceiling at this transfer size
-    copy_same_gbs = (measure_copy_bandwidth(mib=max(1, int(round(bulk_bytes / 2 / (1 << 20)))))
-                     if args.copy_bw else None)
+    copy_mib_same = max(1, int(round(bulk_bytes / 2 / (1 << 20))))
     roof_tile = 1024  # the bulk sweep's own best tile class (the step's may differ)
     if args.roofline_steps > 0:
         s.set_launch(roof_tile, tune["zones_per_group"], tune["zone_groups"], graph_steps,
@@ -828,11 +825,8 @@ def main():
                      "kernel": "k_bulk", "bulk_ms_per_launch": bulk_ms,
                      "bulk_launches_timed": args.roofline_steps,
                      "algorithmic_bytes_per_launch": bulk_bytes,
-                     "copy_GBs_measured": copy_gbs,
-                     "frac_of_copy": (achieved / copy_gbs) if (achieved and copy_gbs) else None,
-                     "copy_same_bytes_GBs": copy_same_gbs,
-                     "frac_of_same_bytes_copy": (achieved / copy_same_gbs)
-                     if (achieved and copy_same_gbs) else None},
+                     "copy_GBs_measured": None, "frac_of_copy": None,
+                     "copy_same_bytes_GBs": None, "frac_of_same_bytes_copy": None},
         "step_roofline_frac": value / (HBM_PEAK_GBS * 1e9 / BYTES_PER_CELL_UPDATE),
         "newton_zone_solver": nz,
     }
@@ -848,6 +842,16 @@ def main():
         out["phase_creation"] = creation_leg(args, not args.no_cpu)
     if args.ctube_problems > 0:
         out["creation_tubes"] = ctube_leg(args, not args.no_cpu)
+    if args.copy_bw:
+        # the plain-copy ceilings, after every GPU leg: measured before them,
+        # these copies made the adjoint leg's two-stream overlap slower
+        br = out["bulk_roofline"]
+        copy_gbs = measure_copy_bandwidth()
+        copy_same_gbs = measure_copy_bandwidth(mib=copy_mib_same)
+        br["copy_GBs_measured"] = copy_gbs
+        br["frac_of_copy"] = (achieved / copy_gbs) if (achieved and copy_gbs) else None
+        br["copy_same_bytes_GBs"] = copy_same_gbs
+        br["frac_of_same_bytes_copy"] = (achieved / copy_same_gbs) if (achieved and copy_same_gbs) else None
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline_leg(b, P, material, args.steps, g_rho, g_mom, g_home,
                                                g_hl, args.cpu_seconds)
